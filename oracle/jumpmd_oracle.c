@@ -1,0 +1,999 @@
+/*
+ * jumpmd_oracle.c — plain CPU FP64 oracle of the JUMP integrator.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark; never by the GPU library. It shares no
+ * code with the GPU path. Everything here is written for being checked by eye
+ * against the paper, not for speed: all pair sums are brute force over every
+ * pair of atoms (minimum image), candidate rows are built by brute force and
+ * sorted with qsort, every jump chain is a sequential loop.
+ *
+ * Paper: Gouraud, Lagardere, Adjoua, Ple, Monmarche, Piquemal,
+ * "Velocity Jumps for Molecular Dynamics", arXiv 2412.15073.
+ *
+ * Readings of the paper that this file adopts (the supporting information
+ * that would fix them is not part of the paper text):
+ *  - switching function chi: C2 quintic smoothstep, chi = 1 for r <= r_s - w,
+ *    chi = 0 for r >= r_s (Sec. 3.1 only says it goes smoothly from 1 to 0);
+ *  - F_ij is a gradient (Sec. 2.1: grad U = sum F_i; Sec. 3.1: F_ij = grad_{x_i}
+ *    of the long part), so the force on atom i is -F_ij;
+ *  - jump candidates of atom i are the entries of a neighbour row built with a
+ *    skin (Remark in Sec. 3.1.1) rather than all N atoms (Alg. 4, Alg. 5);
+ *    candidates whose long-range gradient is exactly zero have rate zero;
+ *  - thinning uses the exponential clock of Alg. 1/2 for the J step as well
+ *    (equivalent in law to the Poisson count of Alg. 3/5, Sec. 2.4);
+ *  - in Alg. 1/2/4 the overflow branch ends the half step;
+ *  - adaptive eps: eps = eps0 |F_ij| (Sec. 2.2) inserted in Eqs.
+ *    (tauxsaut),(majvitesse), per-candidate bound beta*B_v*l_j + sqrt(beta/(2 pi m))/eps0;
+ *  - Z = eta + G~ is drawn by exact rejection from the density
+ *    z exp(-(z-eta)^2/2) on z > 0 with the regimes of Sec. 2.4
+ *    (Gamma(2) for eta < -1, Rayleigh for -1 <= eta <= 0, mixed
+ *    Rayleigh-Gaussian for eta > 0).
+ */
+#include "jumpmd_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PI 3.14159265358979323846
+#define ZS_MAXIT 64
+#define MAX_PROPOSALS (1ll << 22) /* per chain and half step */
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of a
+ * multiply-based bijection keyed by a Weyl sequence. */
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo) {
+  unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+  *hi = (uint64_t)(p >> 64);
+  *lo = (uint64_t)p;
+}
+
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; r++) {
+    if (r > 0) {
+      k0 += 0x9E3779B97F4A7C15ULL;
+      k1 += 0xBB67AE8584CAA73BULL;
+    }
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(0xD2E7470EE14C6C93ULL, c0, &hi0, &lo0);
+    mulhilo64(0xCA5A826395121157ULL, c2, &hi1, &lo1);
+    uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* uniform in the open interval (0,1): (top 52 bits + 1/2) / 2^52, exact */
+double orc_u01(uint64_t w) {
+  return ((double)(w >> 12) + 0.5) * (1.0 / 4503599627370496.0);
+}
+
+static void draw4(uint64_t seed, uint64_t replica, int64_t step, int64_t atom,
+                  uint64_t tag, int64_t k, double u[4]) {
+  uint64_t ctr[4] = {(uint64_t)step, (uint64_t)atom, tag, (uint64_t)k};
+  uint64_t key[2] = {seed, replica};
+  uint64_t w[4];
+  orc_philox4x64(ctr, key, w);
+  for (int q = 0; q < 4; q++) u[q] = orc_u01(w[q]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Theta(eta) = E[(eta + G)_+], G ~ N(0,1)  (Sec. 2.2, Eq. (tauxsaut)).
+ * Closed form eta*Phi(eta) + phi(eta). */
+double orc_theta(double eta) {
+  double Phi = 0.5 * erfc(-eta / sqrt(2.0));
+  double phi = exp(-0.5 * eta * eta) / sqrt(2.0 * PI);
+  return eta * Phi + phi;
+}
+
+/* Z = eta + G~ where G~ has density (eta+y)_+ exp(-y^2/2) / (Theta sqrt(2 pi))
+ * (Sec. 2.2, Eq. (majvitesse)); rejection sampling as in Sec. 2.4.
+ * Iteration r draws one Philox block with counter word 2 = phase | (r+1)<<24. */
+double orc_zsample(double eta, uint64_t seed, uint64_t replica, int64_t step,
+                   int64_t atom, int32_t phase, int64_t k, int32_t *iters) {
+  for (int r = 0; r < ZS_MAXIT; r++) {
+    double u[4];
+    uint64_t tag = (uint64_t)(uint32_t)phase | ((uint64_t)(r + 1) << 24);
+    draw4(seed, replica, step, atom, tag, k, u);
+    if (iters) *iters = r + 1;
+    if (eta > 0.0) {
+      /* proposal density on y: eta*exp(-y^2/2) (Gaussian part, mass eta*sqrt(2 pi))
+       * plus y_+ exp(-y^2/2) (Rayleigh part, mass 1) */
+      double p_ray = 1.0 / (1.0 + eta * sqrt(2.0 * PI));
+      double y;
+      if (u[0] < p_ray) {
+        y = sqrt(-2.0 * log(u[1]));
+      } else {
+        y = sqrt(-2.0 * log(u[1])) * cos(2.0 * PI * u[2]);
+      }
+      double z = eta + y;
+      if (y >= 0.0) return z;          /* target/proposal ratio 1 */
+      if (z <= 0.0) continue;          /* ratio 0 */
+      if (u[3] <= z / eta) return z;   /* ratio (eta+y)/eta */
+    } else if (eta >= -1.0) {
+      /* Rayleigh proposal z exp(-z^2/2); ratio exp(eta z) <= 1 */
+      double z = sqrt(-2.0 * log(u[0]));
+      if (u[1] <= exp(eta * z)) return z;
+    } else {
+      /* Gamma(2, rate |eta|) proposal z exp(-|eta| z); ratio exp(-z^2/2) */
+      double z = -(log(u[0]) + log(u[1])) / (-eta);
+      if (u[2] <= exp(-0.5 * z * z)) return z;
+    }
+  }
+  if (iters) *iters = -1;
+  return 0.5 * (eta + sqrt(eta * eta + 4.0)); /* mode; only after ZS_MAXIT rejections */
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair potential pieces (Sec. 3.1 direct electrostatics, Sec. 3.2 LJ):
+ *  LJ truncated and energy-shifted at r_c: 4 eps [(s/r)^12 - (s/r)^6] - (same at r_c)
+ *  damped shifted-force Coulomb (Fennell-Gezelter) with damping alpha, cut at r_c
+ *  switch chi(r) on [r_s - w, r_s].
+ * out = {U_lj, dU_lj/dr, U_c, dU_c/dr, chi, dchi/dr} */
+static void lj_terms(double r, double eps, double sig, double rc, double *U, double *dU) {
+  *U = 0.0; *dU = 0.0;
+  if (eps == 0.0 || r >= rc) return;
+  double sr6 = pow(sig / r, 6.0);
+  double sc6 = pow(sig / rc, 6.0);
+  *U = 4.0 * eps * (sr6 * sr6 - sr6) - 4.0 * eps * (sc6 * sc6 - sc6);
+  *dU = 4.0 * eps * (-12.0 * sr6 * sr6 + 6.0 * sr6) / r;
+}
+
+static void dsf_terms(double r, double qq, double ke, double alpha, double rc, double *U, double *dU) {
+  *U = 0.0; *dU = 0.0;
+  if (qq == 0.0 || r >= rc) return;
+  double two_a_sqpi = 2.0 * alpha / sqrt(PI);
+  double erfc_rc = erfc(alpha * rc);
+  double fc = erfc_rc / (rc * rc) + two_a_sqpi * exp(-alpha * alpha * rc * rc) / rc;
+  double erfc_r = erfc(alpha * r);
+  *U = ke * qq * (erfc_r / r - erfc_rc / rc + fc * (r - rc));
+  *dU = ke * qq * (-(erfc_r / (r * r) + two_a_sqpi * exp(-alpha * alpha * r * r) / r) + fc);
+}
+
+static void switch_terms(double r, double rs, double w, double *chi, double *dchi) {
+  double rlo = rs - w;
+  if (r <= rlo) { *chi = 1.0; *dchi = 0.0; return; }
+  if (r >= rs) { *chi = 0.0; *dchi = 0.0; return; }
+  double t = (r - rlo) / w;
+  *chi = 1.0 - t * t * t * (10.0 - 15.0 * t + 6.0 * t * t);
+  *dchi = -30.0 * t * t * (1.0 - t) * (1.0 - t) / w;
+}
+
+void orc_pair_terms(double r, double eps, double sigma, double qq, double coulomb_k,
+                    double alpha, double r_s, double w, double r_c, double out[6]) {
+  lj_terms(r, eps, sigma, r_c, &out[0], &out[1]);
+  dsf_terms(r, qq, coulomb_k, alpha, r_c, &out[2], &out[3]);
+  switch_terms(r, r_s, w, &out[4], &out[5]);
+}
+
+/* ------------------------------------------------------------------------ */
+typedef struct { int32_t seg, j; } cand_t;
+
+struct orc_sim {
+  int n, nt;
+  double *x, *v, *mass, *me, *q;
+  int32_t *type;
+  double *eps, *sig;
+  double L[3];
+  int nb; int32_t *bij; double *bk, *br0;
+  int na; int32_t *aijk; double *ak, *at0;
+  int32_t *xptr, *xj;
+  double ke_c, accel, kB;
+  double rs, rc, w, skin, alpha, rlo; int nr; double rw;
+  double dt, gamma, kT, beta; uint64_t seed, replica;
+  int jlj, jc; double eps0; int respa_inner, rebuild_every, log_events;
+  /* state */
+  int64_t step;
+  double *xref;
+  int64_t steps_since_build;
+  double *fnb, *fb;   /* forces (-grad) */
+  int fkind;          /* -1: stale, ORC_F_SHORT or ORC_F_FULL */
+  int fb_valid;
+  /* candidate rows */
+  int S;
+  int64_t *cptr; cand_t *cand; int32_t *segst;
+  int lists_valid;
+  /* bounds */
+  double *ell_lj, *ell_cu, *qmax;
+  double bound_scale;  /* test knob: every bound multiplied by this (1 by default) */
+  /* statistics */
+  int64_t *nprop, *nacc, *nviol; uint64_t *hash;
+  int64_t n_rebuilds, n_zs_overflow, n_list_err;
+  int64_t nev, evcap; int64_t *ev;
+};
+
+static void *xmalloc(size_t n) { void *p = calloc(1, n ? n : 1); return p; }
+
+static double min_image(double d, double L) { return d - L * rint(d / L); }
+
+static double pair_vec(const orc_sim *s, int i, int j, double d[3]) {
+  for (int c = 0; c < 3; c++) d[c] = min_image(s->x[3 * i + c] - s->x[3 * j + c], s->L[c]);
+  return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+}
+
+static int excluded(const orc_sim *s, int i, int j) {
+  if (!s->xptr) return 0;
+  for (int e = s->xptr[i]; e < s->xptr[i + 1]; e++)
+    if (s->xj[e] == j) return 1;
+  return 0;
+}
+
+/* ---------------------------------------------------------------- bounds */
+/* Analytic bounds on |F_ij| (Sec. 3.1 end, Sec. 3.1.1 ring technique).
+ * For r >= r_a >= r_s - w, |U| and |U'| of both LJ (r_a >= 1.25 sigma) and DSF
+ * are non-increasing, so sup |(1-chi) U' - chi' U| <= |U'(r_a)| + max|chi'| |U(r_a)|
+ * with max|chi'| = 15/(8w); the chi' term vanishes when r_a >= r_s. Ring k holds
+ * candidates whose build-time distance is in [e_k, e_k + ring_width), e_k =
+ * r_s - w - skin + k*ring_width; their current distance is at least e_k - skin. */
+static double ring_ra(const orc_sim *s, int k) {
+  double ek = (s->rlo - s->skin) + k * s->rw;
+  double ra = ek - s->skin;
+  return ra > s->rlo ? ra : s->rlo;
+}
+
+static void compute_bounds(orc_sim *s) {
+  int nt = s->nt, nr = s->nr;
+  for (int a = 0; a < nt; a++)
+    for (int b = 0; b < nt; b++)
+      for (int k = 0; k < nr; k++) {
+        double ra = ring_ra(s, k);
+        double Ul, dUl, Uc, dUc;
+        double lj = 0.0, cu = 0.0;
+        if (ra < s->rc) {
+          lj_terms(ra, s->eps[a * nt + b], s->sig[a * nt + b], s->rc, &Ul, &dUl);
+          dsf_terms(ra, 1.0, s->ke_c, s->alpha, s->rc, &Uc, &dUc);
+          lj = fabs(dUl);
+          cu = fabs(dUc);
+          if (ra < s->rs) {
+            lj += 15.0 / (8.0 * s->w) * fabs(Ul);
+            cu += 15.0 / (8.0 * s->w) * fabs(Uc);
+          }
+        }
+        s->ell_lj[(a * nt + b) * nr + k] = lj;
+        s->ell_cu[(a * nt + b) * nr + k] = cu;
+      }
+  for (int t = 0; t < nt; t++) s->qmax[t] = 0.0;
+  for (int i = 0; i < s->n; i++)
+    if (fabs(s->q[i]) > s->qmax[s->type[i]]) s->qmax[s->type[i]] = fabs(s->q[i]);
+}
+
+/* bound of candidates of atom i in segment sg (class = type of j, ring) */
+static double seg_bound(const orc_sim *s, int i, int sg, int coulomb) {
+  int b = sg / s->nr, k = sg % s->nr, a = s->type[i];
+  int idx = (a * s->nt + b) * s->nr + k;
+  double ell = coulomb ? (fabs(s->q[i]) * s->qmax[b]) * s->ell_cu[idx] : s->ell_lj[idx];
+  return s->bound_scale == 1.0 ? ell : ell * s->bound_scale;
+}
+
+/* thinning is exact for any valid bound: larger bounds only add rejected
+ * proposals (Sec. 2.4); tests use this to check that the law is unchanged */
+void orc_set_bound_scale(orc_sim *s, double scale) { s->bound_scale = scale; }
+
+/* ----------------------------------------------------------------- lists */
+static int cand_cmp(const void *pa, const void *pb) {
+  const cand_t *a = (const cand_t *)pa, *b = (const cand_t *)pb;
+  if (a->seg != b->seg) return a->seg < b->seg ? -1 : 1;
+  if (a->j != b->j) return a->j < b->j ? -1 : 1;
+  return 0;
+}
+
+/* Candidate rows (Remark of Sec. 3.1.1): for each i, every j != i, not
+ * excluded, with r_s - w - skin <= r < r_c + skin at the build positions,
+ * keyed by (type of j, ring) and sorted by (segment, j). */
+void orc_build_lists(orc_sim *s) {
+  int n = s->n;
+  int64_t total = 0;
+  double rin = s->rlo - s->skin, rout = s->rc + s->skin;
+  /* count */
+  for (int i = 0; i < n; i++) {
+    int64_t c = 0;
+    for (int j = 0; j < n; j++) {
+      if (j == i || excluded(s, i, j)) continue;
+      double d[3], r = pair_vec(s, i, j, d);
+      if (r >= rin && r < rout) c++;
+    }
+    s->cptr[i + 1] = s->cptr[i] + c;
+    total += c;
+  }
+  free(s->cand);
+  s->cand = (cand_t *)xmalloc(sizeof(cand_t) * (size_t)total);
+  for (int i = 0; i < n; i++) {
+    int64_t p = s->cptr[i];
+    for (int j = 0; j < n; j++) {
+      if (j == i || excluded(s, i, j)) continue;
+      double d[3], r = pair_vec(s, i, j, d);
+      if (r >= rin && r < rout) {
+        int k = (int)floor((r - rin) / s->rw);
+        if (k < 0) k = 0;
+        if (k > s->nr - 1) k = s->nr - 1;
+        s->cand[p].seg = s->type[j] * s->nr + k;
+        s->cand[p].j = j;
+        p++;
+      }
+    }
+    qsort(s->cand + s->cptr[i], (size_t)(s->cptr[i + 1] - s->cptr[i]), sizeof(cand_t), cand_cmp);
+    /* segment starts, relative to the row start */
+    int64_t len = s->cptr[i + 1] - s->cptr[i];
+    int64_t e = 0;
+    for (int sg = 0; sg <= s->S; sg++) {
+      while (e < len && s->cand[s->cptr[i] + e].seg < sg) e++;
+      s->segst[(int64_t)i * (s->S + 1) + sg] = (int32_t)e;
+    }
+  }
+  memcpy(s->xref, s->x, sizeof(double) * 3 * (size_t)n);
+  s->steps_since_build = 0;
+  s->lists_valid = 1;
+}
+
+/* Rebuild when some atom moved more than skin/2 since the last build
+ * (or on the fixed period; then a larger displacement is a list error). */
+static void maybe_rebuild(orc_sim *s) {
+  double maxd2 = 0.0;
+  for (int i = 0; i < s->n; i++) {
+    double d2 = 0.0;
+    for (int c = 0; c < 3; c++) {
+      double d = s->x[3 * i + c] - s->xref[3 * i + c];
+      d2 += d * d;
+    }
+    if (d2 > maxd2) maxd2 = d2;
+  }
+  double half = 0.5 * s->skin;
+  int exceed = maxd2 > half * half;
+  s->steps_since_build++;
+  if (s->rebuild_every > 0) {
+    if (s->steps_since_build >= s->rebuild_every) {
+      orc_build_lists(s); s->n_rebuilds++;
+    } else if (exceed) {
+      s->n_list_err++;
+    }
+  } else if (exceed) {
+    orc_build_lists(s); s->n_rebuilds++;
+  }
+}
+
+/* ---------------------------------------------------------------- forces */
+/* Non-bonded forces by brute force over all pairs (minimum image).
+ * kind SHORT: U_short = chi U for r < r_s; kind FULL: U for r < r_c. */
+static void nb_forces(const orc_sim *s, int kind, double *f, double *pe_s, double *pe_l) {
+  int n = s->n;
+  memset(f, 0, sizeof(double) * 3 * (size_t)n);
+  double es = 0.0, el = 0.0;
+  for (int i = 0; i < n; i++)
+    for (int j = i + 1; j < n; j++) {
+      if (excluded(s, i, j)) continue;
+      double d[3], r = pair_vec(s, i, j, d);
+      if (r >= s->rc) continue;
+      int a = s->type[i], b = s->type[j];
+      double Ul, dUl, Uc, dUc, chi, dchi;
+      lj_terms(r, s->eps[a * s->nt + b], s->sig[a * s->nt + b], s->rc, &Ul, &dUl);
+      dsf_terms(r, s->q[i] * s->q[j], s->ke_c, s->alpha, s->rc, &Uc, &dUc);
+      switch_terms(r, s->rs, s->w, &chi, &dchi);
+      double U = Ul + Uc, dU = dUl + dUc;
+      es += chi * U;
+      el += (1.0 - chi) * U;
+      double g;
+      if (kind == ORC_F_SHORT) {
+        if (r >= s->rs) continue;
+        g = chi * dU + dchi * U;
+      } else {
+        g = dU;
+      }
+      for (int c = 0; c < 3; c++) {
+        double fc = -g * d[c] / r;
+        f[3 * i + c] += fc;
+        f[3 * j + c] -= fc;
+      }
+    }
+  if (pe_s) *pe_s = es;
+  if (pe_l) *pe_l = el;
+}
+
+/* Harmonic bonds (k/2)(b-b0)^2 and angles (k/2)(theta-theta0)^2 */
+static double bonded_forces(const orc_sim *s, double *f) {
+  memset(f, 0, sizeof(double) * 3 * (size_t)s->n);
+  double e = 0.0;
+  for (int t = 0; t < s->nb; t++) {
+    int i = s->bij[2 * t], j = s->bij[2 * t + 1];
+    double d[3], b = pair_vec(s, i, j, d);
+    double db = b - s->br0[t];
+    e += 0.5 * s->bk[t] * db * db;
+    for (int c = 0; c < 3; c++) {
+      double fc = -s->bk[t] * db * d[c] / b;
+      f[3 * i + c] += fc;
+      f[3 * j + c] -= fc;
+    }
+  }
+  for (int t = 0; t < s->na; t++) {
+    int i = s->aijk[3 * t], j = s->aijk[3 * t + 1], k = s->aijk[3 * t + 2];
+    double u[3], w[3];
+    double ru = pair_vec(s, i, j, u), rw = pair_vec(s, k, j, w);
+    double cs = (u[0] * w[0] + u[1] * w[1] + u[2] * w[2]) / (ru * rw);
+    if (cs > 1.0) cs = 1.0;
+    if (cs < -1.0) cs = -1.0;
+    double th = acos(cs), sn = sqrt(1.0 - cs * cs);
+    double dth = th - s->at0[t];
+    e += 0.5 * s->ak[t] * dth * dth;
+    double dUdth = s->ak[t] * dth;
+    /* d theta / d x_i = -(1/sin) d cos / d x_i ; d cos/d x_i = w/(ru rw) - cos u/ru^2 */
+    for (int c = 0; c < 3; c++) {
+      double dci = w[c] / (ru * rw) - cs * u[c] / (ru * ru);
+      double dck = u[c] / (ru * rw) - cs * w[c] / (rw * rw);
+      double fi = dUdth * dci / sn;  /* -dU/dx_i = dU/dth * dcos/dx_i / sin */
+      double fk = dUdth * dck / sn;
+      f[3 * i + c] += fi;
+      f[3 * k + c] += fk;
+      f[3 * j + c] -= fi + fk;
+    }
+  }
+  return e;
+}
+
+static void ensure_forces(orc_sim *s, int kind) {
+  if (s->fkind != kind) {
+    nb_forces(s, kind, s->fnb, NULL, NULL);
+    s->fkind = kind;
+  }
+  if (!s->fb_valid) {
+    bonded_forces(s, s->fb);
+    s->fb_valid = 1;
+  }
+}
+
+static void positions_moved(orc_sim *s) { s->fkind = -1; s->fb_valid = 0; }
+
+/* Long-range gradient F_ij = grad_{x_i} (1 - chi) U_ij (Sec. 3.1, Sec. 3.2);
+ * coulomb selects the DSF part, otherwise the LJ part. Zero when r <= r_s - w
+ * or r >= r_c. */
+static double long_grad(const orc_sim *s, int i, int j, int coulomb, double F[3]) {
+  double d[3], r = pair_vec(s, i, j, d);
+  int a = s->type[i], b = s->type[j];
+  double U, dU, chi, dchi;
+  if (coulomb) dsf_terms(r, s->q[i] * s->q[j], s->ke_c, s->alpha, s->rc, &U, &dU);
+  else lj_terms(r, s->eps[a * s->nt + b], s->sig[a * s->nt + b], s->rc, &U, &dU);
+  switch_terms(r, s->rs, s->w, &chi, &dchi);
+  double g = (1.0 - chi) * dU - dchi * U;
+  for (int c = 0; c < 3; c++) F[c] = g * d[c] / r;
+  return F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
+}
+
+/* ------------------------------------------------------------ event log */
+static uint64_t fnv1a_bytes(uint64_t h, const void *p, size_t n) {
+  const unsigned char *b = (const unsigned char *)p;
+  for (size_t q = 0; q < n; q++) {
+    h ^= (uint64_t)b[q];
+    h *= 0x100000001b3ULL;
+  }
+  return h;
+}
+
+static void log_event(orc_sim *s, int32_t phase, int i, int j, int64_t k) {
+  uint64_t st = (uint64_t)s->step;
+  uint32_t ph = (uint32_t)phase, jj = (uint32_t)j;
+  uint64_t h = s->hash[i];
+  h = fnv1a_bytes(h, &st, 8);
+  h = fnv1a_bytes(h, &ph, 4);
+  h = fnv1a_bytes(h, &jj, 4);
+  s->hash[i] = h;
+  s->nacc[i]++;
+  if (!s->log_events) return;
+  if (s->nev == s->evcap) {
+    s->evcap = s->evcap ? 2 * s->evcap : 1024;
+    s->ev = (int64_t *)realloc(s->ev, sizeof(int64_t) * 5 * (size_t)s->evcap);
+  }
+  int64_t *e = s->ev + 5 * s->nev++;
+  e[0] = s->step; e[1] = phase; e[2] = i; e[3] = j; e[4] = k;
+}
+
+/* categorical draw: first index with target < running sum of w; if rounding
+ * leaves none, the last index with positive weight */
+static int pick(const double *w, int n, double target) {
+  double acc = 0.0;
+  int last = -1;
+  for (int q = 0; q < n; q++) {
+    acc += w[q];
+    if (w[q] > 0.0) last = q;
+    if (target < acc && w[q] > 0.0) return q;
+  }
+  return last;
+}
+
+/* ------------------------------------------------------------- J step */
+/* Step (J) with BPS jumps for the LJ long part (Sec. 3.2, Alg. 5), one
+ * independent chain per atom (Sec. 3.1, per-atom independence), in the
+ * exponential-clock form of Alg. 2. Bound per candidate in segment s:
+ * beta |v_i| l_s (constant over the half step, |v_i| is preserved). */
+static void jstep_atom(orc_sim *s, int i, int32_t phase, double h) {
+  double *v = s->v + 3 * i;
+  int S = s->S;
+  const int32_t *st = s->segst + (int64_t)i * (S + 1);
+  double nl[64];
+  double W = 0.0;
+  for (int sg = 0; sg < S; sg++) {
+    nl[sg] = (double)(st[sg + 1] - st[sg]) * seg_bound(s, i, sg, 0);
+    W += nl[sg];
+  }
+  double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  double Lam = s->beta * vn * W;
+  if (!(Lam > 0.0)) return;
+  double t = 0.0;
+  if (!isfinite(Lam)) return;
+  for (int64_t k = 0; k < MAX_PROPOSALS; k++) {
+    double u[4];
+    draw4(s->seed, s->replica, s->step, i, (uint64_t)phase, k, u);
+    double T = -log(u[0]) / Lam;
+    if (t + T > h) break;
+    t += T;
+    int sg = pick(nl, S, u[1] * W);
+    int64_t ns = st[sg + 1] - st[sg];
+    int64_t idx = (int64_t)floor(u[2] * (double)ns);
+    if (idx > ns - 1) idx = ns - 1;
+    int j = s->cand[s->cptr[i] + st[sg] + idx].j;
+    double F[3];
+    double F2 = long_grad(s, i, j, 0, F);
+    s->nprop[i]++;
+    double vF = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
+    double p = (vF > 0.0 ? vF : 0.0) / (vn * seg_bound(s, i, sg, 0));
+    if (p > 1.0) s->nviol[i]++;
+    if (p > 0.0 && u[3] <= p) {
+      /* reflection R_ij (Sec. 3.2): v - 2 (v.F)/|F|^2 F */
+      double c = 2.0 * vF / F2;
+      for (int q = 0; q < 3; q++) v[q] -= c * F[q];
+      log_event(s, phase, i, j, k);
+    }
+  }
+}
+
+/* ------------------------------------------------------------- C step */
+/* Step (C) (Sec. 2.3, Alg. 1, Alg. 4): constant acceleration a_i between
+ * proposals plus MRZ jumps for the Coulomb long part. Bound on |v_i| over the
+ * rest of the half step: B_v = sqrt(|v|^2 + tau^2 |a|^2 + 2 tau (v.a)_+),
+ * tau = h - t (Alg. 4). Per-candidate rate bound c_j:
+ *   adaptive eps:  beta B_v l_s + f,   f = sqrt(beta/(2 pi m_i))/eps0 (if l_s > 0)
+ *   constant eps:  l_s (beta B_v + sqrt(beta/(2 pi m_i))/eps)
+ * A proposal picks (component, segment) with probability proportional to the
+ * summed bounds, then j uniformly inside the segment. */
+static void cstep_atom(orc_sim *s, int i, int32_t phase, double h, const double a[3]) {
+  double *v = s->v + 3 * i;
+  int S = s->S;
+  const int32_t *st = s->segst + (int64_t)i * (S + 1);
+  double me = s->me[i], beta = s->beta, eps0 = s->eps0;
+  int adaptive = (s->jc == ORC_JUMP_MRZ_ADAPTIVE);
+  double nl[64], w[128];
+  double W = 0.0;
+  int64_t nf = 0;
+  for (int sg = 0; sg < S; sg++) {
+    int64_t ns = st[sg + 1] - st[sg];
+    double ell = seg_bound(s, i, sg, 1);
+    nl[sg] = (double)ns * ell;
+    W += nl[sg];
+    if (ell > 0.0) nf += ns;
+  }
+  double f = sqrt(beta / (2.0 * PI * me)) / eps0;
+  double aa = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+  double t = 0.0;
+  for (int64_t k = 0; k < MAX_PROPOSALS; k++) {
+    double tau = h - t;
+    double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double va = v[0] * a[0] + v[1] * a[1] + v[2] * a[2];
+    double Bv = sqrt(vv + tau * tau * aa + 2.0 * tau * (va > 0.0 ? va : 0.0));
+    double bBv = beta * Bv;
+    double Lam = adaptive ? bBv * W + f * (double)nf : (bBv + f) * W;
+    double u[4];
+    if (!isfinite(Lam)) break;
+    if (Lam > 0.0) draw4(s->seed, s->replica, s->step, i, (uint64_t)phase, k, u);
+    double T = Lam > 0.0 ? -log(u[0]) / Lam : 2.0 * h + 1.0;
+    if (!(Lam > 0.0) || t + T > h) {
+      for (int q = 0; q < 3; q++) v[q] += tau * a[q];
+      break;
+    }
+    t += T;
+    for (int q = 0; q < 3; q++) v[q] += T * a[q];
+    int sg;
+    if (adaptive) {
+      for (int q = 0; q < S; q++) {
+        int64_t ns = st[q + 1] - st[q];
+        w[q] = bBv * nl[q];
+        w[S + q] = seg_bound(s, i, q, 1) > 0.0 ? f * (double)ns : 0.0;
+      }
+      sg = pick(w, 2 * S, u[1] * Lam);
+      if (sg >= S) sg -= S;
+    } else {
+      sg = pick(nl, S, u[1] * W);
+    }
+    int64_t ns = st[sg + 1] - st[sg];
+    int64_t idx = (int64_t)floor(u[2] * (double)ns);
+    if (idx > ns - 1) idx = ns - 1;
+    int j = s->cand[s->cptr[i] + st[sg] + idx].j;
+    double F[3];
+    double F2 = long_grad(s, i, j, 1, F);
+    s->nprop[i]++;
+    double ell = seg_bound(s, i, sg, 1);
+    double c = adaptive ? bBv * ell + f : ell * (bBv + f);
+    double lam = 0.0, eta = 0.0;
+    double vF = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
+    if (F2 > 0.0) {
+      if (adaptive) {
+        /* eps = eps0 |F|: lambda = sqrt(beta/m)/eps0 Theta(eps0 sqrt(beta m) v.F) */
+        eta = eps0 * sqrt(beta * me) * vF;
+        lam = sqrt(beta / me) / eps0 * orc_theta(eta);
+      } else {
+        double Fn = sqrt(F2);
+        eta = eps0 * sqrt(beta * me) * vF / Fn;
+        lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * orc_theta(eta);
+      }
+    }
+    double p = lam / c;
+    if (p > 1.0) s->nviol[i]++;
+    if (p > 0.0 && u[3] <= p) {
+      int32_t it;
+      double Z = orc_zsample(eta, s->seed, s->replica, s->step, i, phase, k, &it);
+      if (it < 0) s->n_zs_overflow++;
+      /* Eq. (majvitesse) restricted to atom i (Sec. 3.1) */
+      double coef;
+      if (adaptive) coef = 2.0 * eps0 * Z / ((1.0 + eps0 * eps0 * F2) * sqrt(beta * me));
+      else coef = 2.0 * eps0 * Z / ((1.0 + eps0 * eps0) * sqrt(beta * me) * sqrt(F2));
+      for (int q = 0; q < 3; q++) v[q] -= coef * F[q];
+      log_event(s, phase, i, j, k);
+    }
+  }
+}
+
+/* ------------------------------------------------------------- B, A, O */
+static void kick(orc_sim *s, double h, int with_nb, int with_b) {
+  for (int i = 0; i < s->n; i++)
+    for (int c = 0; c < 3; c++) {
+      double fc = (with_nb ? s->fnb[3 * i + c] : 0.0) + (with_b ? s->fb[3 * i + c] : 0.0);
+      s->v[3 * i + c] += h * fc / s->me[i];
+    }
+}
+
+static void drift(orc_sim *s, double h) {
+  for (int i = 0; i < 3 * s->n; i++) s->x[i] += h * s->v[i];
+  positions_moved(s);
+}
+
+/* (O): v <- e^{-gamma dt} v + sqrt((1 - e^{-2 gamma dt}) kT/m) G  (Sec. 2.3).
+ * Normals by Box-Muller from one Philox block per atom. */
+void orc_phase_o(orc_sim *s, double h, int32_t substep) {
+  double c1 = exp(-s->gamma * h);
+  double c2 = sqrt(1.0 - c1 * c1);
+  uint64_t tag = (uint64_t)ORC_PH_O | ((uint64_t)(uint32_t)substep << 8);
+  for (int i = 0; i < s->n; i++) {
+    double u[4];
+    draw4(s->seed, s->replica, s->step, i, tag, 0, u);
+    double r1 = sqrt(-2.0 * log(u[0])), r2 = sqrt(-2.0 * log(u[2]));
+    double g[3] = {r1 * cos(2.0 * PI * u[1]), r1 * sin(2.0 * PI * u[1]), r2 * cos(2.0 * PI * u[3])};
+    double sd = sqrt(s->kT / s->me[i]);
+    for (int c = 0; c < 3; c++) s->v[3 * i + c] = c1 * s->v[3 * i + c] + c2 * sd * g[c];
+  }
+}
+
+void orc_phase_j(orc_sim *s, int32_t phase, double h) {
+  if (!s->lists_valid) orc_build_lists(s);
+  for (int i = 0; i < s->n; i++) jstep_atom(s, i, phase, h);
+}
+
+/* a_kind 0: acceleration from short non-bonded + bonded, 1: short non-bonded */
+void orc_phase_c(orc_sim *s, int32_t phase, double h, int a_kind) {
+  if (!s->lists_valid) orc_build_lists(s);
+  ensure_forces(s, ORC_F_SHORT);
+  for (int i = 0; i < s->n; i++) {
+    double a[3];
+    for (int c = 0; c < 3; c++) {
+      double fc = s->fnb[3 * i + c] + (a_kind == 0 ? s->fb[3 * i + c] : 0.0);
+      a[c] = fc / s->me[i];
+    }
+    cstep_atom(s, i, phase, h, a);
+  }
+}
+
+/* (C') or plain (B) depending on whether Coulomb jumps are on */
+static void c_or_b(orc_sim *s, int32_t phase, double h, int a_kind) {
+  if (s->jc != ORC_JUMP_NONE) orc_phase_c(s, phase, h, a_kind);
+  else kick(s, h, 1, a_kind == 0);
+}
+
+/* ------------------------------------------------------------- schemes */
+/* BAOAB with full-range forces (Sec. 2.3 without J). */
+int orc_step_baoab(orc_sim *s, int64_t n) {
+  double h = 0.5 * s->dt;
+  ensure_forces(s, ORC_F_FULL);
+  for (int64_t it = 0; it < n; it++) {
+    kick(s, h, 1, 1);
+    drift(s, h);
+    orc_phase_o(s, s->dt, 0);
+    drift(s, h);
+    maybe_rebuild(s);
+    ensure_forces(s, ORC_F_FULL);
+    kick(s, h, 1, 1);
+    s->step++;
+  }
+  return 0;
+}
+
+/* JUMP: B J A O A J B, or C' J' A O A J' C' (Sec. 2.3, Sec. 3.3). */
+int orc_step_jump(orc_sim *s, int64_t n) {
+  double h = 0.5 * s->dt;
+  if (!s->lists_valid) orc_build_lists(s);
+  ensure_forces(s, ORC_F_SHORT);
+  for (int64_t it = 0; it < n; it++) {
+    c_or_b(s, ORC_PH_C1, h, 0);
+    if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J1, h);
+    drift(s, h);
+    orc_phase_o(s, s->dt, 0);
+    drift(s, h);
+    maybe_rebuild(s);
+    ensure_forces(s, ORC_F_SHORT);
+    if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J2, h);
+    c_or_b(s, ORC_PH_C2, h, 0);
+    s->step++;
+  }
+  return 0;
+}
+
+/* JUMP-RESPA (Sec. 2.3.2 and Sec. 3.3): bonded forces at the inner step dt,
+ * short non-bonded forces and all jumps at the outer step n*dt. Inner steps
+ * are B_b A O A B_b; the O draw carries the inner index. */
+int orc_step_jump_respa(orc_sim *s, int64_t n_outer) {
+  int m = s->respa_inner > 0 ? s->respa_inner : 1;
+  double H = 0.5 * s->dt * m, h = 0.5 * s->dt;
+  if (!s->lists_valid) orc_build_lists(s);
+  ensure_forces(s, ORC_F_SHORT);
+  for (int64_t it = 0; it < n_outer; it++) {
+    c_or_b(s, ORC_PH_C1, H, 1);
+    if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J1, H);
+    for (int sub = 0; sub < m; sub++) {
+      kick(s, h, 0, 1);
+      drift(s, h);
+      orc_phase_o(s, s->dt, sub);
+      drift(s, h);
+      bonded_forces(s, s->fb);
+      s->fb_valid = 1;
+      kick(s, h, 0, 1);
+    }
+    maybe_rebuild(s);
+    ensure_forces(s, ORC_F_SHORT);
+    if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J2, H);
+    c_or_b(s, ORC_PH_C2, H, 1);
+    s->step++;
+  }
+  return 0;
+}
+
+/* BAOAB-RESPA comparator: full-range non-bonded kick at the outer step. */
+int orc_step_baoab_respa(orc_sim *s, int64_t n_outer) {
+  int m = s->respa_inner > 0 ? s->respa_inner : 1;
+  double H = 0.5 * s->dt * m, h = 0.5 * s->dt;
+  ensure_forces(s, ORC_F_FULL);
+  for (int64_t it = 0; it < n_outer; it++) {
+    kick(s, H, 1, 0);
+    for (int sub = 0; sub < m; sub++) {
+      kick(s, h, 0, 1);
+      drift(s, h);
+      orc_phase_o(s, s->dt, sub);
+      drift(s, h);
+      bonded_forces(s, s->fb);
+      s->fb_valid = 1;
+      kick(s, h, 0, 1);
+    }
+    maybe_rebuild(s);
+    ensure_forces(s, ORC_F_FULL);
+    kick(s, H, 1, 0);
+    s->step++;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------ create */
+orc_sim *orc_create(const orc_system *sy, const orc_split *sp, const orc_params *pa,
+                    char *err, int errlen) {
+#define FAIL(msg) do { if (err) snprintf(err, (size_t)errlen, "%s", msg); orc_destroy(s); return NULL; } while (0)
+  orc_sim *s = (orc_sim *)xmalloc(sizeof(orc_sim));
+  int n = sy->n_atoms, nt = sy->n_types;
+  s->n = n; s->nt = nt;
+  if (n <= 0 || nt <= 0) FAIL("n_atoms and n_types must be positive");
+  s->x = (double *)xmalloc(sizeof(double) * 3 * (size_t)n);
+  s->v = (double *)xmalloc(sizeof(double) * 3 * (size_t)n);
+  s->xref = (double *)xmalloc(sizeof(double) * 3 * (size_t)n);
+  s->fnb = (double *)xmalloc(sizeof(double) * 3 * (size_t)n);
+  s->fb = (double *)xmalloc(sizeof(double) * 3 * (size_t)n);
+  s->mass = (double *)xmalloc(sizeof(double) * (size_t)n);
+  s->me = (double *)xmalloc(sizeof(double) * (size_t)n);
+  s->q = (double *)xmalloc(sizeof(double) * (size_t)n);
+  s->type = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)n);
+  s->eps = (double *)xmalloc(sizeof(double) * (size_t)(nt * nt));
+  s->sig = (double *)xmalloc(sizeof(double) * (size_t)(nt * nt));
+  memcpy(s->x, sy->pos, sizeof(double) * 3 * (size_t)n);
+  memcpy(s->v, sy->vel, sizeof(double) * 3 * (size_t)n);
+  memcpy(s->mass, sy->mass, sizeof(double) * (size_t)n);
+  for (int i = 0; i < n; i++) s->q[i] = sy->charge ? sy->charge[i] : 0.0;
+  memcpy(s->type, sy->type, sizeof(int32_t) * (size_t)n);
+  memcpy(s->eps, sy->lj_eps, sizeof(double) * (size_t)(nt * nt));
+  memcpy(s->sig, sy->lj_sigma, sizeof(double) * (size_t)(nt * nt));
+  for (int c = 0; c < 3; c++) s->L[c] = sy->box[c];
+  s->nb = sy->n_bonds; s->na = sy->n_angles;
+  s->bij = (int32_t *)xmalloc(sizeof(int32_t) * 2 * (size_t)s->nb);
+  s->bk = (double *)xmalloc(sizeof(double) * (size_t)s->nb);
+  s->br0 = (double *)xmalloc(sizeof(double) * (size_t)s->nb);
+  if (s->nb) {
+    memcpy(s->bij, sy->bond_ij, sizeof(int32_t) * 2 * (size_t)s->nb);
+    memcpy(s->bk, sy->bond_k, sizeof(double) * (size_t)s->nb);
+    memcpy(s->br0, sy->bond_r0, sizeof(double) * (size_t)s->nb);
+  }
+  s->aijk = (int32_t *)xmalloc(sizeof(int32_t) * 3 * (size_t)s->na);
+  s->ak = (double *)xmalloc(sizeof(double) * (size_t)s->na);
+  s->at0 = (double *)xmalloc(sizeof(double) * (size_t)s->na);
+  if (s->na) {
+    memcpy(s->aijk, sy->angle_ijk, sizeof(int32_t) * 3 * (size_t)s->na);
+    memcpy(s->ak, sy->angle_k, sizeof(double) * (size_t)s->na);
+    memcpy(s->at0, sy->angle_t0, sizeof(double) * (size_t)s->na);
+  }
+  if (sy->excl_ptr) {
+    s->xptr = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n + 1));
+    memcpy(s->xptr, sy->excl_ptr, sizeof(int32_t) * (size_t)(n + 1));
+    s->xj = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)s->xptr[n]);
+    memcpy(s->xj, sy->excl_j, sizeof(int32_t) * (size_t)s->xptr[n]);
+  }
+  s->ke_c = sy->coulomb_k; s->accel = sy->accel_factor; s->kB = sy->kB;
+  for (int i = 0; i < n; i++) s->me[i] = s->mass[i] / s->accel;
+  s->rs = sp->r_s; s->rc = sp->r_c; s->w = sp->switch_width; s->skin = sp->skin;
+  s->alpha = sp->coulomb_alpha; s->nr = sp->n_rings > 0 ? sp->n_rings : 1;
+  s->rw = sp->ring_width;
+  s->rlo = s->rs - s->w;
+  if (s->nr == 1) s->rw = (s->rc + s->skin) - (s->rlo - s->skin);
+  if (!(s->w > 0.0) || !(s->rs <= s->rc) || s->skin < 0.0 || !(s->rw > 0.0)) FAIL("bad split");
+  for (int c = 0; c < 3; c++)
+    if (!(s->rc < 0.5 * s->L[c])) FAIL("r_c must be below half the box edge");
+  s->dt = pa->dt; s->gamma = pa->gamma; s->kT = pa->kT; s->beta = 1.0 / pa->kT;
+  s->seed = pa->seed; s->replica = pa->replica;
+  s->jlj = pa->jump_lj; s->jc = pa->jump_coul; s->eps0 = pa->eps;
+  s->respa_inner = pa->respa_inner; s->rebuild_every = pa->rebuild_every;
+  s->log_events = pa->log_events;
+  if (s->jlj != ORC_JUMP_NONE && s->jlj != ORC_JUMP_BPS) FAIL("LJ jumps: NONE or BPS");
+  if (s->jc != ORC_JUMP_NONE && s->jc != ORC_JUMP_MRZ_CONST && s->jc != ORC_JUMP_MRZ_ADAPTIVE)
+    FAIL("Coulomb jumps: NONE, MRZ_CONST or MRZ_ADAPTIVE");
+  if (s->jc != ORC_JUMP_NONE && !(s->eps0 > 0.0)) FAIL("eps must be positive");
+  /* the LJ bound needs |U|, |U'| non-increasing beyond r_s - w */
+  for (int ab = 0; ab < nt * nt; ab++)
+    if (s->eps[ab] != 0.0 && s->rlo < 1.25 * s->sig[ab]) FAIL("r_s - w must be >= 1.25 sigma");
+  s->S = nt * s->nr;
+  if (2 * s->S > 128) FAIL("too many segments");
+  s->cptr = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)(n + 1));
+  s->segst = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)n * (size_t)(s->S + 1));
+  s->ell_lj = (double *)xmalloc(sizeof(double) * (size_t)(nt * nt * s->nr));
+  s->ell_cu = (double *)xmalloc(sizeof(double) * (size_t)(nt * nt * s->nr));
+  s->qmax = (double *)xmalloc(sizeof(double) * (size_t)nt);
+  s->nprop = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)n);
+  s->nacc = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)n);
+  s->nviol = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)n);
+  s->hash = (uint64_t *)xmalloc(sizeof(uint64_t) * (size_t)n);
+  for (int i = 0; i < n; i++) s->hash[i] = 0xcbf29ce484222325ULL;
+  compute_bounds(s);
+  s->bound_scale = 1.0;
+  s->fkind = -1;
+  s->fb_valid = 0;
+  s->lists_valid = 0;
+  memcpy(s->xref, s->x, sizeof(double) * 3 * (size_t)n);
+  return s;
+#undef FAIL
+}
+
+void orc_destroy(orc_sim *s) {
+  if (!s) return;
+  free(s->x); free(s->v); free(s->xref); free(s->fnb); free(s->fb); free(s->mass);
+  free(s->me); free(s->q); free(s->type); free(s->eps); free(s->sig); free(s->bij);
+  free(s->bk); free(s->br0); free(s->aijk); free(s->ak); free(s->at0); free(s->xptr);
+  free(s->xj); free(s->cptr); free(s->cand); free(s->segst); free(s->ell_lj);
+  free(s->ell_cu); free(s->qmax); free(s->nprop); free(s->nacc); free(s->nviol);
+  free(s->hash); free(s->ev); free(s);
+}
+
+/* ------------------------------------------------------------ accessors */
+void orc_get_state(const orc_sim *s, double *pos, double *vel) {
+  if (pos) memcpy(pos, s->x, sizeof(double) * 3 * (size_t)s->n);
+  if (vel) memcpy(vel, s->v, sizeof(double) * 3 * (size_t)s->n);
+}
+
+void orc_set_state(orc_sim *s, const double *pos, const double *vel, int64_t step) {
+  if (pos) { memcpy(s->x, pos, sizeof(double) * 3 * (size_t)s->n); positions_moved(s); s->lists_valid = 0; }
+  if (vel) memcpy(s->v, vel, sizeof(double) * 3 * (size_t)s->n);
+  if (step >= 0) s->step = step;
+}
+
+int64_t orc_step_index(const orc_sim *s) { return s->step; }
+int64_t orc_n_rebuilds(const orc_sim *s) { return s->n_rebuilds; }
+int64_t orc_n_zsampler_overflow(const orc_sim *s) { return s->n_zs_overflow; }
+int64_t orc_n_list_errors(const orc_sim *s) { return s->n_list_err; }
+
+void orc_atom_stats(const orc_sim *s, int64_t *nprop, int64_t *nacc, int64_t *nviol, uint64_t *hash) {
+  size_t n = (size_t)s->n;
+  if (nprop) memcpy(nprop, s->nprop, 8 * n);
+  if (nacc) memcpy(nacc, s->nacc, 8 * n);
+  if (nviol) memcpy(nviol, s->nviol, 8 * n);
+  if (hash) memcpy(hash, s->hash, 8 * n);
+}
+
+/* run hash: FNV-1a over the per-atom hashes in atom order */
+uint64_t orc_event_hash(const orc_sim *s) {
+  uint64_t h = 0xcbf29ce484222325ULL;
+  for (int i = 0; i < s->n; i++) h = fnv1a_bytes(h, &s->hash[i], 8);
+  return h;
+}
+
+int64_t orc_n_events(const orc_sim *s) { return s->nev; }
+void orc_get_events(const orc_sim *s, int64_t *buf) {
+  memcpy(buf, s->ev, sizeof(int64_t) * 5 * (size_t)s->nev);
+}
+
+void orc_energies(const orc_sim *s, double out[6]) {
+  double ke = 0.0;
+  for (int i = 0; i < s->n; i++)
+    for (int c = 0; c < 3; c++) ke += 0.5 * s->me[i] * s->v[3 * i + c] * s->v[3 * i + c];
+  double *tmp = (double *)xmalloc(sizeof(double) * 3 * (size_t)s->n);
+  double es, el;
+  nb_forces(s, ORC_F_FULL, tmp, &es, &el);
+  double eb = bonded_forces(s, tmp);
+  free(tmp);
+  out[0] = ke;
+  out[1] = 2.0 * ke / (3.0 * s->n * s->kB);
+  out[2] = es; out[3] = el; out[4] = eb; out[5] = es + el + eb;
+}
+
+void orc_accel(const orc_sim *s, int kind, double *acc) {
+  double *f = (double *)xmalloc(sizeof(double) * 3 * (size_t)s->n);
+  if (kind == ORC_F_BONDED) bonded_forces(s, f);
+  else nb_forces(s, kind, f, NULL, NULL);
+  for (int i = 0; i < s->n; i++)
+    for (int c = 0; c < 3; c++) acc[3 * i + c] = f[3 * i + c] / s->me[i];
+  free(f);
+}
+
+/* pair-count histogram of (ta, tb) pairs (unordered if ta == tb) with r < r_max */
+void orc_rdf(const orc_sim *s, int ta, int tb, double r_max, int n_bins, double *hist) {
+  for (int b = 0; b < n_bins; b++) hist[b] = 0.0;
+  double dr = r_max / n_bins;
+  for (int i = 0; i < s->n; i++)
+    for (int j = i + 1; j < s->n; j++) {
+      int a = s->type[i], b = s->type[j];
+      if (!((a == ta && b == tb) || (a == tb && b == ta))) continue;
+      double d[3], r = pair_vec(s, i, j, d);
+      if (r >= r_max) continue;
+      int bin = (int)(r / dr);
+      if (bin < n_bins) hist[bin] += 1.0;
+    }
+}
+
+int32_t orc_n_segments(const orc_sim *s) { return s->S; }
+int64_t orc_cand_count(const orc_sim *s, int32_t i) { return s->cptr[i + 1] - s->cptr[i]; }
+void orc_cand_row(const orc_sim *s, int32_t i, int32_t *j) {
+  for (int64_t p = s->cptr[i]; p < s->cptr[i + 1]; p++) j[p - s->cptr[i]] = s->cand[p].j;
+}
+void orc_seg_start(const orc_sim *s, int32_t i, int32_t *starts) {
+  memcpy(starts, s->segst + (int64_t)i * (s->S + 1), sizeof(int32_t) * (size_t)(s->S + 1));
+}
+
+/* unordered non-excluded pairs (i<j) with r < rcut at the current positions */
+int64_t orc_pairs_within(const orc_sim *s, double rcut, int32_t *ij, int64_t cap) {
+  int64_t c = 0;
+  for (int i = 0; i < s->n; i++)
+    for (int j = i + 1; j < s->n; j++) {
+      if (excluded(s, i, j)) continue;
+      double d[3], r = pair_vec(s, i, j, d);
+      if (r < rcut) {
+        if (c < cap) { ij[2 * c] = i; ij[2 * c + 1] = j; }
+        c++;
+      }
+    }
+  return c;
+}
+
+void orc_bounds(const orc_sim *s, double *ell_lj, double *ell_coul_unit, double *qmax) {
+  size_t m = (size_t)(s->nt * s->nt * s->nr);
+  if (ell_lj) memcpy(ell_lj, s->ell_lj, sizeof(double) * m);
+  if (ell_coul_unit) memcpy(ell_coul_unit, s->ell_cu, sizeof(double) * m);
+  if (qmax) memcpy(qmax, s->qmax, sizeof(double) * (size_t)s->nt);
+}
