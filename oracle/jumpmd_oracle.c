@@ -22,6 +22,8 @@
  *    candidates whose long-range gradient is exactly zero have rate zero;
  *  - thinning uses the exponential clock of Alg. 1/2 for the J step as well
  *    (equivalent in law to the Poisson count of Alg. 3/5, Sec. 2.4);
+ *  - in the C step the local rate bound is re-evaluated after each accepted
+ *    jump (Sec. 2.4) rather than after each proposal (Alg. 4); both are exact;
  *  - in Alg. 1/2/4 the overflow branch ends the half step;
  *  - adaptive eps: eps = eps0 |F_ij| (Sec. 2.2) inserted in Eqs.
  *    (tauxsaut),(majvitesse), per-candidate bound beta*B_v*l_j + sqrt(beta/(2 pi m))/eps0;
@@ -488,55 +490,97 @@ static void log_event(orc_sim *s, int32_t phase, int i, int j, int64_t k) {
   e[0] = s->step; e[1] = phase; e[2] = i; e[3] = j; e[4] = k;
 }
 
-/* categorical draw: first index with target < running sum of w; if rounding
- * leaves none, the last index with positive weight */
-static int pick(const double *w, int n, double target) {
-  double acc = 0.0;
-  int last = -1;
-  for (int q = 0; q < n; q++) {
-    acc += w[q];
-    if (w[q] > 0.0) last = q;
-    if (target < acc && w[q] > 0.0) return q;
+/* Segment tables of atom i for one jump component: counts n_s, bounds l_s,
+ * cumulative weights cumW_s = sum_{q<=s} n_q l_q and cumulative counts of the
+ * segments with a nonzero bound cumN_s (the candidates whose rate can be > 0). */
+typedef struct {
+  int S;
+  int64_t n[64], st[64];
+  double ell[64], cumW[64], cumN[64];
+  double W, nf;
+} segtab_t;
+
+static void seg_table(const orc_sim *s, int i, int coulomb, segtab_t *T) {
+  const int32_t *st = s->segst + (int64_t)i * (s->S + 1);
+  T->S = s->S;
+  double cw = 0.0, cn = 0.0;
+  for (int q = 0; q < s->S; q++) {
+    T->st[q] = st[q];
+    T->n[q] = st[q + 1] - st[q];
+    T->ell[q] = seg_bound(s, i, q, coulomb);
+    cw += (double)T->n[q] * T->ell[q];
+    if (T->ell[q] > 0.0) cn += (double)T->n[q];
+    T->cumW[q] = cw;
+    T->cumN[q] = cn;
   }
-  return last;
+  T->W = cw;
+  T->nf = cn;
+}
+
+/* Candidate drawn with probability proportional to the bound (ring technique,
+ * Sec. 3.1.1: choose the ring/segment in proportion to N l, then j uniformly
+ * inside it). u picks the segment; its residual inside the segment picks j. */
+static int64_t pick_by_bound(const segtab_t *T, double u, int *seg) {
+  double target = u * T->W;
+  int s = -1, last = -1;
+  for (int q = 0; q < T->S; q++) {
+    if (T->n[q] > 0 && T->ell[q] > 0.0) last = q;
+    if (target < T->cumW[q] && T->n[q] > 0 && T->ell[q] > 0.0) { s = q; break; }
+  }
+  if (s < 0) s = last;
+  double below = s > 0 ? T->cumW[s - 1] : 0.0;
+  int64_t idx = (int64_t)floor((target - below) / T->ell[s]);
+  if (idx < 0) idx = 0;
+  if (idx > T->n[s] - 1) idx = T->n[s] - 1;
+  *seg = s;
+  return T->st[s] + idx;
+}
+
+/* Candidate drawn uniformly among the candidates of segments with l > 0. */
+static int64_t pick_uniform(const segtab_t *T, double u, int *seg) {
+  double target = u * T->nf;
+  int s = -1, last = -1;
+  for (int q = 0; q < T->S; q++) {
+    if (T->n[q] > 0 && T->ell[q] > 0.0) last = q;
+    if (target < T->cumN[q] && T->n[q] > 0 && T->ell[q] > 0.0) { s = q; break; }
+  }
+  if (s < 0) s = last;
+  double below = s > 0 ? T->cumN[s - 1] : 0.0;
+  int64_t idx = (int64_t)floor(target - below);
+  if (idx < 0) idx = 0;
+  if (idx > T->n[s] - 1) idx = T->n[s] - 1;
+  *seg = s;
+  return T->st[s] + idx;
 }
 
 /* ------------------------------------------------------------- J step */
 /* Step (J) with BPS jumps for the LJ long part (Sec. 3.2, Alg. 5), one
- * independent chain per atom (Sec. 3.1, per-atom independence), in the
- * exponential-clock form of Alg. 2. Bound per candidate in segment s:
- * beta |v_i| l_s (constant over the half step, |v_i| is preserved). */
+ * independent chain per atom (Sec. 3.1), in the exponential-clock form of
+ * Alg. 2. The bound beta |v_i| l_s per candidate is constant over the half
+ * step (|v_i| is preserved), so proposal k happens at (E_0 + ... + E_k)/Lambda.
+ * Proposal k uses Philox block (step, i, phase, k): u0 -> E_k, u2 -> candidate,
+ * u3 -> acceptance (u1 unused). */
 static void jstep_atom(orc_sim *s, int i, int32_t phase, double h) {
   double *v = s->v + 3 * i;
-  int S = s->S;
-  const int32_t *st = s->segst + (int64_t)i * (S + 1);
-  double nl[64];
-  double W = 0.0;
-  for (int sg = 0; sg < S; sg++) {
-    nl[sg] = (double)(st[sg + 1] - st[sg]) * seg_bound(s, i, sg, 0);
-    W += nl[sg];
-  }
+  segtab_t T;
+  seg_table(s, i, 0, &T);
   double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-  double Lam = s->beta * vn * W;
-  if (!(Lam > 0.0)) return;
-  double t = 0.0;
-  if (!isfinite(Lam)) return;
+  double Lam = s->beta * vn * T.W;
+  if (!(Lam > 0.0) || !isfinite(Lam)) return;
+  double sumE = 0.0;
   for (int64_t k = 0; k < MAX_PROPOSALS; k++) {
     double u[4];
     draw4(s->seed, s->replica, s->step, i, (uint64_t)phase, k, u);
-    double T = -log(u[0]) / Lam;
-    if (t + T > h) break;
-    t += T;
-    int sg = pick(nl, S, u[1] * W);
-    int64_t ns = st[sg + 1] - st[sg];
-    int64_t idx = (int64_t)floor(u[2] * (double)ns);
-    if (idx > ns - 1) idx = ns - 1;
-    int j = s->cand[s->cptr[i] + st[sg] + idx].j;
+    sumE += -log(u[0]);
+    if (sumE / Lam > h) break;
+    int sg;
+    int64_t pos = pick_by_bound(&T, u[2], &sg);
+    int j = s->cand[s->cptr[i] + pos].j;
     double F[3];
     double F2 = long_grad(s, i, j, 0, F);
     s->nprop[i]++;
     double vF = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
-    double p = (vF > 0.0 ? vF : 0.0) / (vn * seg_bound(s, i, sg, 0));
+    double p = (vF > 0.0 ? vF : 0.0) / (vn * T.ell[sg]);
     if (p > 1.0) s->nviol[i]++;
     if (p > 0.0 && u[3] <= p) {
       /* reflection R_ij (Sec. 3.2): v - 2 (v.F)/|F|^2 F */
@@ -549,95 +593,96 @@ static void jstep_atom(orc_sim *s, int i, int32_t phase, double h) {
 
 /* ------------------------------------------------------------- C step */
 /* Step (C) (Sec. 2.3, Alg. 1, Alg. 4): constant acceleration a_i between
- * proposals plus MRZ jumps for the Coulomb long part. Bound on |v_i| over the
- * rest of the half step: B_v = sqrt(|v|^2 + tau^2 |a|^2 + 2 tau (v.a)_+),
- * tau = h - t (Alg. 4). Per-candidate rate bound c_j:
- *   adaptive eps:  beta B_v l_s + f,   f = sqrt(beta/(2 pi m_i))/eps0 (if l_s > 0)
- *   constant eps:  l_s (beta B_v + sqrt(beta/(2 pi m_i))/eps)
- * A proposal picks (component, segment) with probability proportional to the
- * summed bounds, then j uniformly inside the segment. */
+ * jumps plus MRZ jumps for the Coulomb long part. The rate bound is local and
+ * re-evaluated after each jump (Sec. 2.4): from a jump (or the start) at
+ * time t_e with velocity v_e, v(t) = v_e + (t - t_e) a_i and
+ *   B_v = sqrt(|v_e|^2 + tau^2 |a|^2 + 2 tau (v_e.a)_+),  tau = h - t_e
+ * bounds |v(t)| up to the end of the half step (Alg. 4). Per-candidate bound
+ *   adaptive eps:  c_j = beta B_v l_s + f,   f = sqrt(beta/(2 pi m_i))/eps0
+ *   constant eps:  c_j = l_s (beta B_v + sqrt(beta/(2 pi m_i))/eps)
+ * and Lambda = sum_j c_j. Proposal k (Philox block (step, i, phase, k)):
+ * u0 -> E_k (time t_e + (E_first + ... + E_k)/Lambda), u1 -> which part of
+ * c_j proposes (the beta B_v l part or the f part, adaptive only), u2 -> the
+ * candidate (by bound, or uniform over candidates with l > 0), u3 ->
+ * acceptance lambda_ij / c_j. */
 static void cstep_atom(orc_sim *s, int i, int32_t phase, double h, const double a[3]) {
   double *v = s->v + 3 * i;
-  int S = s->S;
-  const int32_t *st = s->segst + (int64_t)i * (S + 1);
+  segtab_t T;
+  seg_table(s, i, 1, &T);
   double me = s->me[i], beta = s->beta, eps0 = s->eps0;
   int adaptive = (s->jc == ORC_JUMP_MRZ_ADAPTIVE);
-  double nl[64], w[128];
-  double W = 0.0;
-  int64_t nf = 0;
-  for (int sg = 0; sg < S; sg++) {
-    int64_t ns = st[sg + 1] - st[sg];
-    double ell = seg_bound(s, i, sg, 1);
-    nl[sg] = (double)ns * ell;
-    W += nl[sg];
-    if (ell > 0.0) nf += ns;
-  }
   double f = sqrt(beta / (2.0 * PI * me)) / eps0;
   double aa = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
-  double t = 0.0;
-  for (int64_t k = 0; k < MAX_PROPOSALS; k++) {
-    double tau = h - t;
-    double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    double va = v[0] * a[0] + v[1] * a[1] + v[2] * a[2];
+  double ve[3] = {v[0], v[1], v[2]};
+  double te = 0.0;
+  int64_t k = 0;
+  int done = 0;
+  while (!done) {
+    /* epoch: bound from (t_e, v_e) */
+    double tau = h - te;
+    double vv = ve[0] * ve[0] + ve[1] * ve[1] + ve[2] * ve[2];
+    double va = ve[0] * a[0] + ve[1] * a[1] + ve[2] * a[2];
     double Bv = sqrt(vv + tau * tau * aa + 2.0 * tau * (va > 0.0 ? va : 0.0));
     double bBv = beta * Bv;
-    double Lam = adaptive ? bBv * W + f * (double)nf : (bBv + f) * W;
-    double u[4];
-    if (!isfinite(Lam)) break;
-    if (Lam > 0.0) draw4(s->seed, s->replica, s->step, i, (uint64_t)phase, k, u);
-    double T = Lam > 0.0 ? -log(u[0]) / Lam : 2.0 * h + 1.0;
-    if (!(Lam > 0.0) || t + T > h) {
-      for (int q = 0; q < 3; q++) v[q] += tau * a[q];
+    double Wb = bBv * T.W;
+    double Lam = adaptive ? Wb + f * T.nf : (bBv + f) * T.W;
+    if (!(Lam > 0.0) || !isfinite(Lam)) {
+      for (int q = 0; q < 3; q++) v[q] = ve[q] + tau * a[q];
       break;
     }
-    t += T;
-    for (int q = 0; q < 3; q++) v[q] += T * a[q];
-    int sg;
-    if (adaptive) {
-      for (int q = 0; q < S; q++) {
-        int64_t ns = st[q + 1] - st[q];
-        w[q] = bBv * nl[q];
-        w[S + q] = seg_bound(s, i, q, 1) > 0.0 ? f * (double)ns : 0.0;
+    double sumE = 0.0;
+    for (;; k++) {
+      if (k >= MAX_PROPOSALS) { done = 1; for (int q = 0; q < 3; q++) v[q] = ve[q] + tau * a[q]; break; }
+      double u[4];
+      draw4(s->seed, s->replica, s->step, i, (uint64_t)phase, k, u);
+      sumE += -log(u[0]);
+      double tk = te + sumE / Lam;
+      if (tk > h) {
+        for (int q = 0; q < 3; q++) v[q] = ve[q] + tau * a[q];
+        done = 1;
+        break;
       }
-      sg = pick(w, 2 * S, u[1] * Lam);
-      if (sg >= S) sg -= S;
-    } else {
-      sg = pick(nl, S, u[1] * W);
-    }
-    int64_t ns = st[sg + 1] - st[sg];
-    int64_t idx = (int64_t)floor(u[2] * (double)ns);
-    if (idx > ns - 1) idx = ns - 1;
-    int j = s->cand[s->cptr[i] + st[sg] + idx].j;
-    double F[3];
-    double F2 = long_grad(s, i, j, 1, F);
-    s->nprop[i]++;
-    double ell = seg_bound(s, i, sg, 1);
-    double c = adaptive ? bBv * ell + f : ell * (bBv + f);
-    double lam = 0.0, eta = 0.0;
-    double vF = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
-    if (F2 > 0.0) {
-      if (adaptive) {
-        /* eps = eps0 |F|: lambda = sqrt(beta/m)/eps0 Theta(eps0 sqrt(beta m) v.F) */
-        eta = eps0 * sqrt(beta * me) * vF;
-        lam = sqrt(beta / me) / eps0 * orc_theta(eta);
-      } else {
-        double Fn = sqrt(F2);
-        eta = eps0 * sqrt(beta * me) * vF / Fn;
-        lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * orc_theta(eta);
+      double vk[3];
+      for (int q = 0; q < 3; q++) vk[q] = ve[q] + (tk - te) * a[q];
+      int sg;
+      int64_t pos;
+      if (adaptive && !(u[1] * Lam < Wb)) pos = pick_uniform(&T, u[2], &sg);
+      else pos = pick_by_bound(&T, u[2], &sg);
+      int j = s->cand[s->cptr[i] + pos].j;
+      double F[3];
+      double F2 = long_grad(s, i, j, 1, F);
+      s->nprop[i]++;
+      double ell = T.ell[sg];
+      double c = adaptive ? bBv * ell + f : ell * (bBv + f);
+      double lam = 0.0, eta = 0.0;
+      double vF = vk[0] * F[0] + vk[1] * F[1] + vk[2] * F[2];
+      if (F2 > 0.0) {
+        if (adaptive) {
+          /* eps = eps0 |F|: lambda = sqrt(beta/m)/eps0 Theta(eps0 sqrt(beta m) v.F) */
+          eta = eps0 * sqrt(beta * me) * vF;
+          lam = sqrt(beta / me) / eps0 * orc_theta(eta);
+        } else {
+          double Fn = sqrt(F2);
+          eta = eps0 * sqrt(beta * me) * vF / Fn;
+          lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * orc_theta(eta);
+        }
       }
-    }
-    double p = lam / c;
-    if (p > 1.0) s->nviol[i]++;
-    if (p > 0.0 && u[3] <= p) {
-      int32_t it;
-      double Z = orc_zsample(eta, s->seed, s->replica, s->step, i, phase, k, &it);
-      if (it < 0) s->n_zs_overflow++;
-      /* Eq. (majvitesse) restricted to atom i (Sec. 3.1) */
-      double coef;
-      if (adaptive) coef = 2.0 * eps0 * Z / ((1.0 + eps0 * eps0 * F2) * sqrt(beta * me));
-      else coef = 2.0 * eps0 * Z / ((1.0 + eps0 * eps0) * sqrt(beta * me) * sqrt(F2));
-      for (int q = 0; q < 3; q++) v[q] -= coef * F[q];
-      log_event(s, phase, i, j, k);
+      double p = lam / c;
+      if (p > 1.0) s->nviol[i]++;
+      if (p > 0.0 && u[3] <= p) {
+        int32_t it;
+        double Z = orc_zsample(eta, s->seed, s->replica, s->step, i, phase, k, &it);
+        if (it < 0) s->n_zs_overflow++;
+        /* Eq. (majvitesse) restricted to atom i (Sec. 3.1) */
+        double coef;
+        if (adaptive) coef = 2.0 * eps0 * Z / ((1.0 + eps0 * eps0 * F2) * sqrt(beta * me));
+        else coef = 2.0 * eps0 * Z / ((1.0 + eps0 * eps0) * sqrt(beta * me) * sqrt(F2));
+        for (int q = 0; q < 3; q++) ve[q] = vk[q] - coef * F[q];
+        te = tk;
+        log_event(s, phase, i, j, k);
+        k++;
+        break; /* new epoch */
+      }
     }
   }
 }
@@ -861,7 +906,7 @@ orc_sim *orc_create(const orc_system *sy, const orc_split *sp, const orc_params 
   for (int ab = 0; ab < nt * nt; ab++)
     if (s->eps[ab] != 0.0 && s->rlo < 1.25 * s->sig[ab]) FAIL("r_s - w must be >= 1.25 sigma");
   s->S = nt * s->nr;
-  if (2 * s->S > 128) FAIL("too many segments");
+  if (s->S > 64) FAIL("too many segments (n_types * n_rings > 64)");
   s->cptr = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)(n + 1));
   s->segst = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)n * (size_t)(s->S + 1));
   s->ell_lj = (double *)xmalloc(sizeof(double) * (size_t)(nt * nt * s->nr));

@@ -242,11 +242,13 @@ class OracleSim:
         return lib().orc_event_hash(self._h)
 
     def events(self):
+        """Accepted jumps (step, phase, i, j, k), sorted by (step, phase, i, k)."""
         n = lib().orc_n_events(self._h)
         buf = np.zeros(5 * n, np.int64)
         if n:
             lib().orc_get_events(self._h, _ptr(buf, _lp))
-        return buf.reshape(-1, 5)
+        ev = buf.reshape(-1, 5)
+        return ev[np.lexsort((ev[:, 4], ev[:, 2], ev[:, 1], ev[:, 0]))]
 
     def energies(self):
         out = np.zeros(6)

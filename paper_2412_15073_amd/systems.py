@@ -142,10 +142,13 @@ def _random_rotations(rng, n):
     ], 1)
 
 
-def water_box(n_mol: int, density: float = 0.0334, T: float = 300.0, seed: int = 1) -> System:
+def water_box(n_mol: int, density: float = 0.0334, T: float = 300.0, seed: int = 1,
+              jitter: float = 0.0) -> System:
     """n_mol flexible 3-site waters (O,H,H per molecule) in a cubic box of
     n_mol/density A^3; O on the sites of an n_side^3 cubic lattice (random
-    vacancies if n_mol < n_side^3), random orientations."""
+    vacancies if n_mol < n_side^3), random orientations. jitter > 0 displaces
+    every atom by a seeded uniform offset in [-jitter, jitter]^3 A (bonds and
+    angles off their minimum)."""
     p = WATER
     L = (n_mol / density) ** (1.0 / 3.0)
     n_side = int(np.ceil(n_mol ** (1.0 / 3.0) - 1e-9))
@@ -174,6 +177,8 @@ def water_box(n_mol: int, density: float = 0.0334, T: float = 300.0, seed: int =
                    np.stack([base, base + 1], 1)], 1).reshape(-1).astype(np.int32)
     kT = KB_KJ * T
     vel = _mb_velocities(rng, mass, kT, ACCEL_KJ)
+    if jitter > 0.0:
+        pos = pos + rng.uniform(-jitter, jitter, size=pos.shape)
     return System(n_atoms=n, n_types=2, pos=pos, vel=vel, mass=mass, charge=charge, type=typ,
                   lj_eps=np.array([p["eps_o"], 0.0, 0.0, 0.0]),
                   lj_sigma=np.array([p["sigma_o"], 1.0, 1.0, 1.0]),
@@ -239,3 +244,34 @@ def two_charges(L: float = 10.0776, r0: float = 3.5, q: float = 1.0, coulomb_k: 
                   box=np.array([L, L, L]), bond_ij=z2, bond_k=np.zeros(0), bond_r0=np.zeros(0),
                   angle_ijk=z3, angle_k=np.zeros(0), angle_t0=np.zeros(0), excl_ptr=None, excl_j=None,
                   coulomb_k=coulomb_k, accel_factor=1.0, kB=1.0, name="two_charges")
+
+
+def ion_lattice(n_side: int = 4, spacing: float = 3.3, q: float = 1.0, coulomb_k: float = 13.0,
+                lj_eps: float = 0.0, lj_sigma: float = 1.0, jitter: float = 0.1, kT: float = 1.0,
+                seed: int = 1, neutral_every: int = 0) -> System:
+    """n_side^3 particles on a simple cubic lattice (reduced units) with
+    alternating charges +q/-q (two types), optional LJ between all pairs and a
+    seeded jitter; with spacing - 2*jitter above r_s no pair is inside the
+    short range, so all forces come from the long part. neutral_every = m > 0
+    makes every m-th site a neutral third type."""
+    rng = np.random.default_rng(seed)
+    g = np.stack(np.meshgrid(*[np.arange(n_side)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    n = len(g)
+    pos = (g + 0.5) * spacing + rng.uniform(-jitter, jitter, size=(n, 3))
+    typ = (g.sum(1) % 2).astype(np.int32)
+    charge = np.where(typ == 0, q, -q).astype(np.float64)
+    nt = 2
+    if neutral_every > 0:
+        typ[::neutral_every] = 2
+        charge[::neutral_every] = 0.0
+        nt = 3
+    mass = np.ones(n)
+    vel = _mb_velocities(rng, mass, kT, 1.0)
+    L = n_side * spacing
+    z2 = np.zeros((0, 2), np.int32)
+    z3 = np.zeros((0, 3), np.int32)
+    return System(n_atoms=n, n_types=nt, pos=pos, vel=vel, mass=mass, charge=charge, type=typ,
+                  lj_eps=np.full(nt * nt, lj_eps), lj_sigma=np.full(nt * nt, lj_sigma), box=np.array([L, L, L]),
+                  bond_ij=z2, bond_k=np.zeros(0), bond_r0=np.zeros(0), angle_ijk=z3, angle_k=np.zeros(0),
+                  angle_t0=np.zeros(0), excl_ptr=None, excl_j=None, coulomb_k=coulomb_k, accel_factor=1.0,
+                  kB=1.0, name=f"ion_lattice_{n}")

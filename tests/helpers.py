@@ -16,9 +16,10 @@ def lj_c1(seed=1, n_rings=1):
     return S.lj_fcc(6, seed=seed), sp
 
 
-def water_small(n_mol=125, seed=3, n_rings=3, skin=0.5):
-    """125 flexible waters (box 15.5 A); split 5 / 7 A, switch 1 A."""
-    return S.water_box(n_mol, seed=seed), S.water_split(r_s=5.0, r_c=7.0, w=1.0, skin=skin, n_rings=n_rings)
+def water_small(n_mol=125, seed=3, n_rings=3, skin=0.5, jitter=0.05):
+    """125 flexible waters (box 15.5 A), geometry jittered by 0.05 A; split 5 / 7 A, switch 1 A."""
+    return (S.water_box(n_mol, seed=seed, jitter=jitter),
+            S.water_split(r_s=5.0, r_c=7.0, w=1.0, skin=skin, n_rings=n_rings))
 
 
 def rel_err(a, b):

@@ -447,6 +447,57 @@ def test_c_step_bound_holds_under_strong_acceleration(kind):
     assert st_["n_viol"].sum() == 0
 
 
+def _moment_check(o, phase_fn, h, K, kT, seed=11):
+    """Mean velocity change over K independent half steps started from
+    Maxwell-Boltzmann velocities, against h * a_full (here the short force is
+    exactly zero, so the jumps alone must supply -grad U_long / m on average:
+    the rate/kernel pair reproduces the missing force in the generator,
+    Sec. 2.1-2.2, up to O(h^2)). Returns (chi2 of the mismatch, chi2 of the
+    signal against zero, degrees of freedom)."""
+    x0, v0 = o.state()
+    expected = h * o.accel(O.F_FULL)
+    assert np.abs(o.accel(O.F_SHORT)).max() == 0.0
+    rng = np.random.default_rng(seed)
+    dv = []
+    for k in range(K):
+        v = rng.standard_normal(v0.shape) * np.sqrt(kT)
+        o.set_state(vel=v, step=k)
+        phase_fn(h)
+        dv.append(o.state()[1] - v)
+    dv = np.array(dv)
+    m, se = dv.mean(0), dv.std(0, ddof=1) / np.sqrt(K)
+    still = se == 0.0                            # atoms that never jump (neutral): no drift either
+    assert np.all(m[still] == 0.0) and np.all(np.abs(expected[still]) < 1e-15)
+    z, z0 = (m - expected)[~still] / se[~still], m[~still] / se[~still]
+    return float((z * z).sum()), float((z0 * z0).sum()), int(z.size)
+
+
+def test_c_step_mean_kick_equals_long_force():
+    """Ions on a jittered lattice (+/- charges and neutral sites, 3 rings, all
+    pairs beyond r_s): averaged over Maxwell-Boltzmann velocities, the adaptive-MRZ C step
+    changes v by -h grad U_long / m. Detects a biased choice of proposal part,
+    segment or index, a wrong floor count, jump size or sign."""
+    sy = S.ion_lattice(4, 3.3, jitter=0.1, neutral_every=5)   # neutral third type: segments with l = 0
+    sp = S.Split(r_s=3.0, r_c=5.0, switch_width=1.0, skin=0.3, coulomb_alpha=0.2, n_rings=3,
+                 ring_width=(5.3 - 1.7) / 3)
+    pa = S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_coul=O.JUMP_MRZ_ADAPTIVE, eps=0.3)
+    o = _oracle(sy, sp, pa)
+    chi2, signal, dof = _moment_check(o, lambda h: o.phase_c(O.PH_C1, h), 0.05, 20000, pa.kT)
+    assert signal > 10 * dof                      # the drift is resolved
+    assert st.chi2.sf(chi2, dof) > 1e-3, chi2
+
+
+def test_j_step_mean_kick_equals_long_lj_force():
+    """Same identity for the BPS J step on the LJ long part (Sec. 3.2)."""
+    sy = S.ion_lattice(4, 3.7, q=0.0, lj_eps=5.0, lj_sigma=2.0, jitter=0.1)
+    sp = S.Split(r_s=3.5, r_c=6.0, switch_width=1.0, skin=0.3, n_rings=3, ring_width=(6.3 - 2.2) / 3)
+    pa = S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_lj=O.JUMP_BPS)
+    o = _oracle(sy, sp, pa)
+    chi2, signal, dof = _moment_check(o, lambda h: o.phase_j(O.PH_J1, h), 0.1, 10000, pa.kT)
+    assert signal > 4 * dof
+    assert st.chi2.sf(chi2, dof) > 1e-3, chi2
+
+
 # ------------------------------------------------------------ Gibbs marginal
 def _gibbs_reference(sy, sp, kT, edges):
     def u(r):
