@@ -1,0 +1,207 @@
+/*
+ * jumpmd.h — C ABI of libjumpmd.so, the MI355X (gfx950) implementation of the
+ * hot path of the JUMP integrator of "Velocity Jumps for Molecular Dynamics"
+ * (Gouraud, Lagardere, Adjoua, Ple, Monmarche, Piquemal; arXiv 2412.15073).
+ *
+ * Every step runs in HIP kernels on the caller's stream. Host pointers passed
+ * in are read during the call and never retained (the caller keeps
+ * ownership); device memory belongs to the context and is released by
+ * md_destroy. No call throws: every function returns MD_OK (0) or a negative
+ * MD_ERR_* code, and md_last_error() gives a message for the last failure.
+ *
+ * Stepping calls are asynchronous on the context's stream. md_observables,
+ * md_get_*, md_sync and md_profile_read synchronise the stream and report
+ * device-side error flags (bound violations in strict mode, list capacity
+ * overflow, list invalidation, non-finite state) raised by earlier steps.
+ * One context per host thread; contexts are independent.
+ *
+ * Units are the caller's: lengths, times, masses, energies and charges must
+ * be consistent, with accel_factor converting force/mass to length/time^2
+ * (1 for reduced units; 100 for kJ/mol, A, ps, amu) and coulomb_k the
+ * Coulomb constant in energy*length/charge^2.
+ */
+#ifndef JUMPMD_H
+#define JUMPMD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define MD_OK 0
+#define MD_ERR_ARG (-1)       /* invalid argument or unsupported combination */
+#define MD_ERR_HIP (-2)       /* a HIP runtime call failed */
+#define MD_ERR_BOUND (-3)     /* strict mode: an acceptance probability exceeded 1 */
+#define MD_ERR_LIST (-4)      /* displacement beyond skin/2 on a fixed rebuild period */
+#define MD_ERR_UNSTABLE (-5)  /* non-finite kinetic energy */
+#define MD_ERR_OOM (-6)       /* device allocation failed */
+#define MD_ERR_CAPACITY (-7)  /* a neighbour row overflowed its capacity (rows regrown; state rolled forward) */
+
+/* jump kinds (Sec. 2.2 of the paper) */
+#define MD_JUMP_NONE 0
+#define MD_JUMP_BPS 1          /* bouncy-particle rate beta (v.F)_+ and reflection, Eqs. (tauxbps),(reflexion) */
+#define MD_JUMP_MRZ_CONST 2    /* rate/kernel of Eqs. (tauxsaut),(majvitesse), constant eps (Alg. 4) */
+#define MD_JUMP_MRZ_ADAPTIVE 3 /* same with eps(x) = eps0 |F_ij(x)| */
+
+/* arithmetic of the pair terms */
+#define MD_FP64 0
+#define MD_FP32_MIXED 1        /* pair forces and jump rates in FP32; positions, velocities, sums in FP64 */
+
+/* md_observables flags */
+#define MD_OBS_PE 1u           /* also evaluate the potential energies (extra kernels) */
+
+/* The system. Arrays are host pointers with the given lengths; atoms of
+ * replica r are [replica_offset[r], replica_offset[r+1]). Bond, angle and
+ * exclusion indices are global atom indices and must stay inside one
+ * replica. Exclusions (CSR, symmetric, may be NULL) remove a pair from both
+ * the force and the jump candidates. Velocities may not be NULL. */
+typedef struct {
+  int32_t n_atoms;
+  int32_t n_types;
+  int32_t n_replicas;             /* >= 1 */
+  const double *pos;              /* [3N] unwrapped positions */
+  const double *vel;              /* [3N] */
+  const double *mass;             /* [N]  */
+  const double *charge;           /* [N]  (may be NULL: all zero) */
+  const int32_t *type;            /* [N]  in [0, n_types) */
+  const double *lj_eps;           /* [n_types^2] 4*eps*((s/r)^12-(s/r)^6); 0 = no LJ */
+  const double *lj_sigma;         /* [n_types^2] */
+  const double *box;              /* [3*n_replicas] orthorhombic edges */
+  const int32_t *replica_offset;  /* [n_replicas+1] (may be NULL when n_replicas == 1) */
+  int32_t n_bonds;                /* harmonic bonds (k/2)(b-b0)^2 */
+  const int32_t *bond_ij;         /* [2*n_bonds] */
+  const double *bond_k, *bond_r0;
+  int32_t n_angles;               /* harmonic angles (k/2)(theta-theta0)^2, vertex = middle index */
+  const int32_t *angle_ijk;       /* [3*n_angles] */
+  const double *angle_k, *angle_t0;
+  const int32_t *excl_ptr;        /* [N+1] */
+  const int32_t *excl_j;          /* [excl_ptr[N]] */
+  double coulomb_k;
+  double accel_factor;
+  double kB;                      /* energy per kelvin, for the reported temperature */
+} md_system;
+
+/* The short/long split of every pair potential (Sec. 3.1, 3.2): chi = 1 below
+ * r_s - switch_width, 0 above r_s (C2 quintic); forces from chi*U every step,
+ * (1-chi)*U out to r_c drives the jumps. Pair terms are truncated at r_c
+ * (LJ energy-shifted, Coulomb damped-shifted-force with coulomb_alpha).
+ * skin: Verlet skin of all neighbour rows. n_rings/ring_width: jump
+ * candidates are binned by build-time distance in rings of ring_width
+ * starting at r_s - switch_width - skin, each with its own bound (ring
+ * technique of Sec. 3.1.1; n_rings = 1 is the uniform per-atom bound of
+ * Alg. 4/5). Requires r_c < box/2 and r_s - w >= 1.25 sigma of every LJ pair. */
+typedef struct {
+  double r_s, r_c, switch_width, skin, coulomb_alpha;
+  int32_t n_rings;
+  double ring_width;
+} md_split;
+
+typedef struct {
+  double dt;            /* time step (inner step for the RESPA schemes) */
+  double gamma;         /* friction */
+  double kT;            /* energy */
+  uint64_t seed;        /* Philox4x64-10 key word 0; key word 1 = replica index */
+  int32_t jump_lj;      /* MD_JUMP_NONE or MD_JUMP_BPS (J step, Alg. 5) */
+  int32_t jump_coul;    /* MD_JUMP_NONE, MD_JUMP_MRZ_CONST or MD_JUMP_MRZ_ADAPTIVE (C step, Alg. 4) */
+  double eps;           /* eps (constant) or eps0 (adaptive, 1/force units) */
+  int32_t precision;    /* MD_FP64 or MD_FP32_MIXED */
+  int32_t rebuild_every;/* 0: rebuild when max displacement > skin/2; k>0: every k steps */
+  int32_t respa_inner;  /* inner steps per outer step of the RESPA schemes (>= 1) */
+  int32_t log_events;   /* 1: record every accepted jump for md_get_events */
+  int32_t strict_bounds;/* 1: an acceptance probability > 1 makes the next sync fail with MD_ERR_BOUND */
+} md_params;
+
+typedef struct {
+  int64_t step;
+  double time;
+  double ke, temperature;
+  double pe_short, pe_long, pe_bonded;  /* filled when MD_OBS_PE is set */
+  int64_t n_prop, n_acc, n_bound_viol, n_rebuilds, n_zsampler_overflow, n_list_errors;
+  uint64_t event_hash;  /* FNV-1a over the per-atom event hashes, atom order */
+} md_obs;
+
+typedef struct {          /* one accepted jump */
+  int64_t step;
+  int32_t phase;          /* 2/3: J first/second half, 4/5: C first/second half */
+  int32_t atom;           /* global index */
+  int32_t partner;        /* global index */
+  int32_t proposal;       /* index of the proposal within the atom's chain */
+} md_event;
+
+typedef struct md_ctx md_ctx;
+
+/* Create a context: validates the input, computes the bound tables, uploads
+ * the system, builds the neighbour rows and evaluates the initial forces on
+ * `stream` (a hipStream_t; NULL = default stream). On failure *out is NULL
+ * and the return code says why (message via md_last_error(NULL)). */
+int md_create(const md_system *sys, const md_split *split, const md_params *par,
+              void *stream, md_ctx **out);
+void md_destroy(md_ctx *ctx);
+const char *md_last_error(const md_ctx *ctx);
+
+/* BAOAB with full-range forces (r < r_c): B A O A B (Sec. 2.3 without J). */
+int md_step_baoab(md_ctx *ctx, int64_t nsteps);
+/* JUMP: C' J' A O A J' C' (Sec. 2.3, 3.3): C' = short forces + Coulomb jumps
+ * (plain B kick if jump_coul is NONE), J' = LJ jumps (skipped if NONE). */
+int md_step_jump(md_ctx *ctx, int64_t nsteps);
+/* JUMP-RESPA (Sec. 2.3.2, 3.3): bonded forces at dt, short non-bonded forces
+ * and all jumps at respa_inner*dt. */
+int md_step_jump_respa(md_ctx *ctx, int64_t n_outer);
+/* BAOAB-RESPA comparator: full-range non-bonded kick at the outer step. */
+int md_step_baoab_respa(md_ctx *ctx, int64_t n_outer);
+
+/* Synchronise and report; flags = 0 or MD_OBS_PE. */
+int md_observables(md_ctx *ctx, uint32_t flags, md_obs *out);
+int md_sync(md_ctx *ctx);
+
+/* Host copies of the state ([3N] each, either may be NULL). md_set_state
+ * rebuilds the neighbour rows and forces at the new positions; step < 0
+ * keeps the step counter. */
+int md_get_state(md_ctx *ctx, double *pos, double *vel);
+int md_set_state(md_ctx *ctx, const double *pos, const double *vel, int64_t step);
+/* Current accelerations [3N]: kind 0 = short non-bonded, 1 = full non-bonded,
+ * 2 = bonded (evaluated at the current positions). */
+int md_get_accel(md_ctx *ctx, int32_t kind, double *acc);
+/* Per-atom jump statistics [N] each (any may be NULL). */
+int md_get_atom_stats(md_ctx *ctx, int64_t *n_prop, int64_t *n_acc, int64_t *n_viol, uint64_t *hash);
+/* Accepted-jump log (log_events = 1), sorted by (step, phase, atom, proposal). */
+int md_get_events(md_ctx *ctx, md_event *buf, int64_t cap, int64_t *n);
+/* Pair histogram of types (ta, tb) over [0, r_max) in n_bins bins, pairs
+ * inside each replica (minimum image), unordered when ta == tb. */
+int md_rdf(md_ctx *ctx, int32_t ta, int32_t tb, double r_max, int32_t n_bins, double *hist);
+
+/* Neighbour rows as last built (for checks): candidate row of atom i (global
+ * j indices, sorted by (type of j, ring, j)) and its S+1 segment starts,
+ * S = n_types*n_rings. *n receives the row length; j may be NULL. */
+int md_get_cand_row(md_ctx *ctx, int32_t i, int32_t *j, int32_t cap, int32_t *n, int32_t *seg_start);
+/* Number of (i,j) entries in the short rows (r < r_s + skin at build), both directions. */
+int md_get_row_counts(md_ctx *ctx, int32_t which, int32_t *counts);
+
+/* Run one phase at the current state (for kernel-level checks): 'C' or 'J'
+ * with the given phase tag and half-step h, 'O' with step h. */
+int md_run_phase(md_ctx *ctx, int32_t which, int32_t phase, double h);
+
+/* Per-kernel timing with HIP events on the context's stream. enable = 1
+ * starts recording (resets the sums); md_profile_read synchronises and
+ * returns the total milliseconds and launch count of kernel `kid`
+ * (MD_K_* below). */
+#define MD_K_LOCAL 0      /* fused per-atom B/A/O/J/C kernel */
+#define MD_K_FORCE 1      /* non-bonded pair forces */
+#define MD_K_BONDED 2
+#define MD_K_REBUILD 3    /* all neighbour-row kernels of a step */
+#define MD_K_COUNT 4
+int md_profile(md_ctx *ctx, int32_t enable);
+int md_profile_read(md_ctx *ctx, int32_t kid, double *total_ms, int64_t *launches);
+
+/* Work counters for throughput reporting: unordered pairs inside the cutoff
+ * of the last force evaluation (r < r_s for the JUMP schemes, r < r_c for
+ * BAOAB; -1 if no force is current), and the jump proposals evaluated since
+ * creation. Synchronises. */
+int md_counters(md_ctx *ctx, int64_t *pairs_last, int64_t *proposals_total);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

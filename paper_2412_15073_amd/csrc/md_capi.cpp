@@ -1,0 +1,972 @@
+// md_capi.cpp — C ABI of libjumpmd (declared in include/jumpmd.h): context
+// setup, bound tables, neighbour-row scheduling, composition of the
+// integrator steps into fused per-atom programs, observables.
+//
+// Paper: Gouraud et al., "Velocity Jumps for Molecular Dynamics", arXiv 2412.15073.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "md_internal.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+enum { ROW_SHORT = 1, ROW_FULL = 2, ROW_CAND = 4 };
+enum { MODE_NONE = -1, MODE_JUMP = 0, MODE_BAOAB = 1, MODE_JUMP_RESPA = 2, MODE_BAOAB_RESPA = 3 };
+
+struct Timer {
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // kid, (start, end)
+  size_t next = 0;
+  double tot_ms[MD_K_COUNT] = {0};
+  long long launches[MD_K_COUNT] = {0};
+};
+
+}  // namespace
+
+struct md_ctx {
+  hipStream_t stream = nullptr;
+  int n = 0, nt = 0, nrep = 0, nr = 1, S = 0;
+  md_split split{};
+  md_params par{};
+  MDView V{};
+  int cur = 0;                 // index of the position buffer holding the current positions
+  int64_t step = 0;
+  int fkind = -1;              // force kind held in fnb: 0 short, 1 full, -1 stale
+  bool fb_valid = false;
+  int rows_valid = 0;          // ROW_* bits valid for the current reference positions
+  int64_t since_build = 0;
+  int pc = 0, ps = 0;          // LDS key capacities of the row builder
+  int nbonds = 0, nangles = 0;
+  double kB = 1.0;
+  std::vector<double> box;
+  std::vector<int> rep_off;
+  std::vector<void *> allocs;
+  int *d_rep_off = nullptr;
+  double *d_scratch = nullptr; size_t scratch_n = 0;
+  unsigned long long *d_hist = nullptr; int hist_n = 0;
+  std::string err;
+  bool prof = false;
+  Timer tm;
+  // host copies of device-side counters at the last sync
+  MDCtl ctl_host{};
+};
+
+// ------------------------------------------------------------- utilities
+static int fail(md_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(c, x)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      return fail((c), MD_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+template <class T>
+static T *dalloc(md_ctx *c, size_t count) {
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, sizeof(T) * (count ? count : 1));
+  if (e != hipSuccess) {
+    c->err = std::string("hipMalloc(") + std::to_string(sizeof(T) * count) + " B): " + hipGetErrorString(e);
+    return nullptr;
+  }
+  c->allocs.push_back(p);
+  return (T *)p;
+}
+
+static double4 *Xcur(md_ctx *c) { return c->cur == 0 ? c->V.x0 : c->V.x1; }
+static double4 *Xoth(md_ctx *c) { return c->cur == 0 ? c->V.x1 : c->V.x0; }
+
+static void prof_begin(md_ctx *c, int kid, hipEvent_t *e0) {
+  if (!c->prof) return;
+  Timer &t = c->tm;
+  if (t.next + 2 > t.pool.size()) {
+    for (int q = 0; q < 256; ++q) {
+      hipEvent_t e;
+      hipEventCreate(&e);
+      t.pool.push_back(e);
+    }
+  }
+  *e0 = t.pool[t.next++];
+  hipEventRecord(*e0, c->stream);
+  (void)kid;
+}
+
+static void prof_end(md_ctx *c, int kid, hipEvent_t e0) {
+  if (!c->prof) return;
+  Timer &t = c->tm;
+  hipEvent_t e1 = t.pool[t.next++];
+  hipEventRecord(e1, c->stream);
+  t.pending.push_back({kid, {e0, e1}});
+}
+
+static void prof_collect(md_ctx *c) {
+  Timer &t = c->tm;
+  if (t.pending.empty()) return;
+  hipStreamSynchronize(c->stream);
+  for (auto &p : t.pending) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, p.second.first, p.second.second);
+    t.tot_ms[p.first] += ms;
+    t.launches[p.first] += 1;
+  }
+  t.pending.clear();
+  t.next = 0;
+}
+
+// ---------------------------------------------------------- pair tables
+// LJ 4 eps [(s/r)^12 - (s/r)^6] energy-shifted at r_c, as c12/r^12 - c6/r^6 - shift.
+static void lj_value(double r, double eps, double sig, double rc, double *U, double *dU) {
+  *U = 0.0; *dU = 0.0;
+  if (eps == 0.0 || r >= rc) return;
+  double s6 = std::pow(sig / r, 6.0), c6 = std::pow(sig / rc, 6.0);
+  *U = 4.0 * eps * (s6 * s6 - s6) - 4.0 * eps * (c6 * c6 - c6);
+  *dU = 4.0 * eps * (-12.0 * s6 * s6 + 6.0 * s6) / r;
+}
+
+// damped shifted-force Coulomb per unit charge product (including coulomb_k)
+static void dsf_value(double r, double ke, double alpha, double rc, double *U, double *dU) {
+  *U = 0.0; *dU = 0.0;
+  if (r >= rc) return;
+  double tas = 2.0 * alpha / std::sqrt(M_PI);
+  double erc = std::erfc(alpha * rc);
+  double fc = erc / (rc * rc) + tas * std::exp(-alpha * alpha * rc * rc) / rc;
+  double er = std::erfc(alpha * r);
+  *U = ke * (er / r - erc / rc + fc * (r - rc));
+  *dU = ke * (-(er / (r * r) + tas * std::exp(-alpha * alpha * r * r) / r) + fc);
+}
+
+// ------------------------------------------------------------ programs
+static MDOp op_base(int kind, double h) {
+  MDOp o;
+  memset(&o, 0, sizeof(o));
+  o.kind = kind;
+  o.h = h;
+  return o;
+}
+
+struct ProgBuilder {
+  MDProg P;
+  bool has_a = false, has_chain_after_a = false;
+  ProgBuilder() { memset(&P, 0, sizeof(P)); P.reset_slot = -1; P.disp_slot = 0; }
+  void add(const MDOp &o) {
+    if (o.kind == OP_A) has_a = true;
+    if ((o.kind == OP_J || o.kind == OP_C) && has_a) has_chain_after_a = true;
+    P.ops[P.nops++] = o;
+  }
+};
+
+static void add_B(ProgBuilder &b, double h, int flags) {
+  MDOp o = op_base(OP_B, h);
+  o.flags = flags;
+  b.add(o);
+}
+static void add_A(ProgBuilder &b, double h) { b.add(op_base(OP_A, h)); }
+static void add_O(md_ctx *c, ProgBuilder &b, double dt, int sub, int64_t step) {
+  MDOp o = op_base(OP_O, dt);
+  o.substep = sub;
+  o.step = step;
+  o.c1 = std::exp(-c->par.gamma * dt);
+  o.c2 = std::sqrt(-std::expm1(-2.0 * c->par.gamma * dt));
+  b.add(o);
+}
+static void add_J(ProgBuilder &b, int phase, double h, int64_t step) {
+  MDOp o = op_base(OP_J, h);
+  o.phase = phase;
+  o.step = step;
+  b.add(o);
+}
+// (C') when Coulomb jumps are on, otherwise the plain kick it reduces to
+static void add_C_or_B(md_ctx *c, ProgBuilder &b, int phase, double h, int64_t step, int a_nb_only) {
+  if (c->par.jump_coul != MD_JUMP_NONE) {
+    MDOp o = op_base(OP_C, h);
+    o.phase = phase;
+    o.step = step;
+    o.flags = a_nb_only;
+    b.add(o);
+  } else {
+    add_B(b, h, a_nb_only ? 1 : 3);
+  }
+}
+static void add_disp(ProgBuilder &b, int slot) {
+  b.add(op_base(OP_DISP, 0.0));
+  b.P.disp_slot = slot;
+  b.P.reset_slot = slot ^ 1;
+}
+
+static int run_prog(md_ctx *c, ProgBuilder &b) {
+  if (b.P.nops == 0) return MD_OK;
+  if (b.has_chain_after_a) return fail(c, MD_ERR_ARG, "internal: jump chain after drift");
+  hipEvent_t e0{};
+  prof_begin(c, MD_K_LOCAL, &e0);
+  double4 *dst = b.has_a ? Xoth(c) : nullptr;
+  HIPCHK(c, launch_local(c->V, b.P, Xcur(c), dst, c->stream));
+  prof_end(c, MD_K_LOCAL, e0);
+  if (b.has_a) {
+    c->cur ^= 1;
+    c->fkind = -1;
+    c->fb_valid = false;
+  }
+  return MD_OK;
+}
+
+// -------------------------------------------------------- rows and forces
+static int rows_for_mode(int mode) {
+  return (mode == MODE_JUMP || mode == MODE_JUMP_RESPA) ? (ROW_SHORT | ROW_CAND) : ROW_FULL;
+}
+
+// Build the requested rows at the reference positions without changing the
+// rebuild schedule (initial build, after md_set_state, or a scheme switch).
+static int build_rows_at_ref(md_ctx *c, int want, bool new_ref) {
+  const double4 *X = new_ref ? Xcur(c) : c->V.xref;
+  hipEvent_t e0{};
+  prof_begin(c, MD_K_REBUILD, &e0);
+  int w1 = want & (ROW_SHORT | ROW_CAND), w2 = want & ROW_FULL;
+  if (w1) HIPCHK(c, launch_rebuild(c->V, X, w1, 0, 1, 0, 0.0, c->pc, c->ps, false, 0, c->stream));
+  if (w2) HIPCHK(c, launch_rebuild(c->V, X, w2, 0, 1, 0, 0.0, c->pc, c->ps, false, 0, c->stream));
+  prof_end(c, MD_K_REBUILD, e0);
+  c->rows_valid = new_ref ? want : (c->rows_valid | want);
+  if (new_ref) c->since_build = 0;
+  return MD_OK;
+}
+
+static int ensure_rows(md_ctx *c, int want) {
+  int missing = want & ~c->rows_valid;
+  if (!missing) return MD_OK;
+  bool fresh = (c->rows_valid == 0);
+  return build_rows_at_ref(c, missing, fresh);
+}
+
+// Per-step schedule: rebuild when the maximum displacement since the last
+// build exceeds skin/2 (decided on the device), or on the fixed period.
+static int step_rebuild(md_ctx *c, int mode, int64_t step) {
+  int want = rows_for_mode(mode);
+  int slot = (int)(step & 1);
+  double half = 0.5 * c->split.skin;
+  double thr2 = half * half;
+  hipEvent_t e0{};
+  prof_begin(c, MD_K_REBUILD, &e0);
+  c->since_build++;
+  if (c->par.rebuild_every > 0) {
+    bool forced = c->since_build >= c->par.rebuild_every;
+    int w1 = want & (ROW_SHORT | ROW_CAND), w2 = want & ROW_FULL;
+    if (forced) {
+      if (w1) HIPCHK(c, launch_rebuild(c->V, Xcur(c), w1, slot, 1, 0, thr2, c->pc, c->ps, false, 1, c->stream));
+      if (w2) HIPCHK(c, launch_rebuild(c->V, Xcur(c), w2, slot, 1, 0, thr2, c->pc, c->ps, false, 1, c->stream));
+      c->rows_valid = want;
+      c->since_build = 0;
+    } else {
+      HIPCHK(c, launch_rebuild(c->V, Xcur(c), want, slot, 0, 0, thr2, c->pc, c->ps, true, 1, c->stream));
+    }
+  } else {
+    int w1 = want & (ROW_SHORT | ROW_CAND), w2 = want & ROW_FULL;
+    if (w1) HIPCHK(c, launch_rebuild(c->V, Xcur(c), w1, slot, 0, 1, thr2, c->pc, c->ps, false, 1, c->stream));
+    if (w2) HIPCHK(c, launch_rebuild(c->V, Xcur(c), w2, slot, 0, 1, thr2, c->pc, c->ps, false, 1, c->stream));
+    // rows of the other kind are stale whenever a rebuild happened; the
+    // device decides, so drop them conservatively
+    c->rows_valid = want;
+  }
+  prof_end(c, MD_K_REBUILD, e0);
+  return MD_OK;
+}
+
+static int eval_nb(md_ctx *c, int kind) {
+  hipEvent_t e0{};
+  prof_begin(c, MD_K_FORCE, &e0);
+  HIPCHK(c, launch_force(c->V, Xcur(c), kind, c->stream));
+  prof_end(c, MD_K_FORCE, e0);
+  c->fkind = kind;
+  return MD_OK;
+}
+
+static int eval_bonded(md_ctx *c) {
+  if (c->nbonds + c->nangles > 0) {
+    hipEvent_t e0{};
+    prof_begin(c, MD_K_BONDED, &e0);
+    HIPCHK(c, launch_bonded(c->V, Xcur(c), c->stream));
+    prof_end(c, MD_K_BONDED, e0);
+  }
+  c->fb_valid = true;
+  return MD_OK;
+}
+
+static int ensure_forces(md_ctx *c, int mode) {
+  int rc = ensure_rows(c, rows_for_mode(mode));
+  if (rc) return rc;
+  int kind = (mode == MODE_JUMP || mode == MODE_JUMP_RESPA) ? 0 : 1;
+  if (c->fkind != kind && (rc = eval_nb(c, kind))) return rc;
+  if (!c->fb_valid && (rc = eval_bonded(c))) return rc;
+  return MD_OK;
+}
+
+// ------------------------------------------------------------ creation
+static int validate(const md_system *s, const md_split *sp, const md_params *p) {
+  if (!s || !sp || !p) return fail(nullptr, MD_ERR_ARG, "null argument");
+  if (s->n_atoms <= 1 || s->n_types <= 0 || s->n_replicas <= 0)
+    return fail(nullptr, MD_ERR_ARG, "need n_atoms > 1, n_types > 0, n_replicas > 0");
+  if (!s->pos || !s->vel || !s->mass || !s->type || !s->lj_eps || !s->lj_sigma || !s->box)
+    return fail(nullptr, MD_ERR_ARG, "missing system array");
+  if (s->n_replicas > 1 && !s->replica_offset) return fail(nullptr, MD_ERR_ARG, "replica_offset required");
+  if (!(sp->switch_width > 0.0) || !(sp->r_s <= sp->r_c) || sp->skin < 0.0 || sp->r_s - sp->switch_width <= 0.0)
+    return fail(nullptr, MD_ERR_ARG, "bad split (need 0 < r_s - w, w > 0, r_s <= r_c, skin >= 0)");
+  if (sp->n_rings > 1 && !(sp->ring_width > 0.0)) return fail(nullptr, MD_ERR_ARG, "ring_width must be > 0");
+  if (!(p->dt > 0.0) || p->gamma < 0.0 || !(p->kT > 0.0)) return fail(nullptr, MD_ERR_ARG, "bad dt/gamma/kT");
+  if (p->jump_lj != MD_JUMP_NONE && p->jump_lj != MD_JUMP_BPS)
+    return fail(nullptr, MD_ERR_ARG, "jump_lj must be NONE or BPS");
+  if (p->jump_coul != MD_JUMP_NONE && p->jump_coul != MD_JUMP_MRZ_CONST && p->jump_coul != MD_JUMP_MRZ_ADAPTIVE)
+    return fail(nullptr, MD_ERR_ARG, "jump_coul must be NONE, MRZ_CONST or MRZ_ADAPTIVE");
+  if (p->jump_coul != MD_JUMP_NONE && !(p->eps > 0.0)) return fail(nullptr, MD_ERR_ARG, "eps must be > 0");
+  if (p->precision != MD_FP64) return fail(nullptr, MD_ERR_ARG, "precision: only MD_FP64 in this build");
+  if (s->n_types * std::max(1, sp->n_rings) > 32)
+    return fail(nullptr, MD_ERR_ARG, "n_types * n_rings must be <= 32");
+  for (int r = 0; r < s->n_replicas; ++r)
+    for (int d = 0; d < 3; ++d)
+      if (!(sp->r_c < 0.5 * s->box[3 * r + d]))
+        return fail(nullptr, MD_ERR_ARG, "r_c must be below half of every box edge");
+  double rlo = sp->r_s - sp->switch_width;
+  for (int ab = 0; ab < s->n_types * s->n_types; ++ab)
+    if (s->lj_eps[ab] != 0.0 && rlo < 1.25 * s->lj_sigma[ab])
+      return fail(nullptr, MD_ERR_ARG, "r_s - switch_width must be >= 1.25 sigma for every LJ pair");
+  for (int i = 0; i < s->n_atoms; ++i) {
+    if (s->type[i] < 0 || s->type[i] >= s->n_types) return fail(nullptr, MD_ERR_ARG, "type out of range");
+    if (!(s->mass[i] > 0.0)) return fail(nullptr, MD_ERR_ARG, "masses must be positive");
+  }
+  return MD_OK;
+}
+
+extern "C" int md_create(const md_system *s, const md_split *sp, const md_params *p, void *stream,
+                         md_ctx **out) {
+  if (!out) return fail(nullptr, MD_ERR_ARG, "out is null");
+  *out = nullptr;
+  int rc = validate(s, sp, p);
+  if (rc) return rc;
+  md_ctx *c = new md_ctx();
+  c->stream = (hipStream_t)stream;
+  c->n = s->n_atoms;
+  c->nt = s->n_types;
+  c->nrep = s->n_replicas;
+  c->split = *sp;
+  c->par = *p;
+  c->kB = s->kB > 0.0 ? s->kB : 1.0;
+  if (c->par.respa_inner < 1) c->par.respa_inner = 1;
+  c->nr = sp->n_rings > 0 ? sp->n_rings : 1;
+  c->S = c->nt * c->nr;
+  const int n = c->n, nt = c->nt, nr = c->nr, nrep = c->nrep;
+  c->rep_off.resize(nrep + 1);
+  if (nrep == 1 && !s->replica_offset) { c->rep_off[0] = 0; c->rep_off[1] = n; }
+  else for (int r = 0; r <= nrep; ++r) c->rep_off[r] = s->replica_offset[r];
+  if (c->rep_off[0] != 0 || c->rep_off[nrep] != n) { delete c; return fail(nullptr, MD_ERR_ARG, "bad replica_offset"); }
+  c->box.assign(s->box, s->box + 3 * nrep);
+
+  MDView &V = c->V;
+  V.n = n; V.nt = nt; V.nrep = nrep; V.nr = nr; V.S = c->S;
+  V.rs = sp->r_s; V.rc = sp->r_c; V.w = sp->switch_width; V.rlo = sp->r_s - sp->switch_width;
+  V.skin = sp->skin; V.rin = V.rlo - V.skin; V.rout = V.rc + V.skin;
+  V.rw = nr == 1 ? V.rout - V.rin : sp->ring_width;
+  V.alpha = sp->coulomb_alpha; V.ke = s->coulomb_k;
+  V.two_a_sqpi = 2.0 * V.alpha / std::sqrt(M_PI);
+  V.dsf_erfc_rc_over_rc = std::erfc(V.alpha * V.rc) / V.rc;
+  V.dsf_fc = std::erfc(V.alpha * V.rc) / (V.rc * V.rc) + V.two_a_sqpi * std::exp(-V.alpha * V.alpha * V.rc * V.rc) / V.rc;
+  V.beta = 1.0 / p->kT; V.kT = p->kT; V.eps0 = p->eps;
+  V.jlj = p->jump_lj; V.jc = p->jump_coul; V.log_events = p->log_events; V.precision = p->precision;
+  V.seed = p->seed;
+
+  // --- host tables
+  std::vector<double> c12(nt * nt), c6(nt * nt), shift(nt * nt), ell_lj(nt * nt * nr), ell_cu(nt * nt * nr), qmax(nt, 0.0);
+  for (int ab = 0; ab < nt * nt; ++ab) {
+    double e = s->lj_eps[ab], sg = s->lj_sigma[ab];
+    c12[ab] = 4.0 * e * std::pow(sg, 12.0);
+    c6[ab] = 4.0 * e * std::pow(sg, 6.0);
+    shift[ab] = e == 0.0 ? 0.0 : c12[ab] / std::pow(V.rc, 12.0) - c6[ab] / std::pow(V.rc, 6.0);
+  }
+  // bounds on |grad (1-chi) U| for candidates of ring k (closest current
+  // distance e_k - skin, not below r_s - w); see the ring technique, Sec. 3.1.1
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < nt; ++b)
+      for (int k = 0; k < nr; ++k) {
+        double ek = V.rin + k * V.rw;
+        double ra = std::max(ek - V.skin, V.rlo);
+        double lj = 0.0, cu = 0.0;
+        if (ra < V.rc) {
+          double Ul, dUl, Uc, dUc;
+          lj_value(ra, s->lj_eps[a * nt + b], s->lj_sigma[a * nt + b], V.rc, &Ul, &dUl);
+          dsf_value(ra, V.ke, V.alpha, V.rc, &Uc, &dUc);
+          lj = std::fabs(dUl);
+          cu = std::fabs(dUc);
+          if (ra < V.rs) {
+            lj += 15.0 / (8.0 * V.w) * std::fabs(Ul);
+            cu += 15.0 / (8.0 * V.w) * std::fabs(Uc);
+          }
+        }
+        ell_lj[(a * nt + b) * nr + k] = lj;
+        ell_cu[(a * nt + b) * nr + k] = cu;
+      }
+  for (int i = 0; i < n; ++i) {
+    double q = s->charge ? std::fabs(s->charge[i]) : 0.0;
+    qmax[s->type[i]] = std::max(qmax[s->type[i]], q);
+  }
+
+  // --- cells per replica: edge >= r_c + skin
+  std::vector<int> cdim(3 * nrep), coff(nrep + 1, 0);
+  double rho_max = 0.0;
+  int nrep_max = 0;
+  for (int r = 0; r < nrep; ++r) {
+    double vol = 1.0;
+    for (int d = 0; d < 3; ++d) {
+      double L = c->box[3 * r + d];
+      cdim[3 * r + d] = std::max(1, (int)std::floor(L / V.rout));
+      vol *= L;
+    }
+    coff[r + 1] = coff[r] + cdim[3 * r] * cdim[3 * r + 1] * cdim[3 * r + 2];
+    int nr_atoms = c->rep_off[r + 1] - c->rep_off[r];
+    rho_max = std::max(rho_max, nr_atoms / vol);
+    nrep_max = std::max(nrep_max, nr_atoms);
+  }
+  V.ncell_total = coff[nrep];
+  auto sphere = [](double r) { return 4.0 / 3.0 * M_PI * r * r * r; };
+  auto capf = [&](double vol, int extra) {
+    long long v = (long long)std::ceil(1.5 * rho_max * vol) + extra;
+    return (int)std::min<long long>(v, nrep_max - 1 > 0 ? nrep_max - 1 : 1);
+  };
+  V.cap_s = capf(sphere(V.rs + V.skin), 32);
+  V.cap_f = capf(sphere(V.rout), 64);
+  V.cap_c = capf(sphere(V.rout) - sphere(std::max(V.rin, 0.0)), 64);
+  auto pow2 = [](int x) { int m = 1; while (m < x) m <<= 1; return m; };
+  c->pc = pow2(std::max(V.cap_c, V.cap_f));
+  c->ps = pow2(V.cap_s);
+  if (c->pc > 4096 || c->ps > 2048) {
+    delete c;
+    return fail(nullptr, MD_ERR_ARG, "neighbour rows too long for the LDS row builder (density * (r_c + skin)^3 too large)");
+  }
+
+  // --- bonded incidence
+  c->nbonds = s->n_bonds;
+  c->nangles = s->n_angles;
+  std::vector<int> bdeg(n + 1, 0);
+  for (int t = 0; t < s->n_bonds; ++t) { bdeg[s->bond_ij[2 * t]]++; bdeg[s->bond_ij[2 * t + 1]]++; }
+  for (int t = 0; t < s->n_angles; ++t)
+    for (int q = 0; q < 3; ++q) bdeg[s->angle_ijk[3 * t + q]]++;
+  std::vector<int> bptr(n + 1, 0);
+  for (int i = 0; i < n; ++i) bptr[i + 1] = bptr[i] + bdeg[i];
+  std::vector<int> bterm(std::max(1, bptr[n])), fillp(bptr.begin(), bptr.end() - 1);
+  for (int t = 0; t < s->n_bonds; ++t)
+    for (int q = 0; q < 2; ++q) bterm[fillp[s->bond_ij[2 * t + q]]++] = t << 1;
+  for (int t = 0; t < s->n_angles; ++t)
+    for (int q = 0; q < 3; ++q) bterm[fillp[s->angle_ijk[3 * t + q]]++] = (t << 1) | 1;
+
+  // --- per-atom host arrays
+  std::vector<double4> hx(n), hv(n);
+  std::vector<int> rep(n), loc(n);
+  for (int r = 0; r < nrep; ++r)
+    for (int i = c->rep_off[r]; i < c->rep_off[r + 1]; ++i) { rep[i] = r; loc[i] = i - c->rep_off[r]; }
+  for (int i = 0; i < n; ++i) {
+    double q = s->charge ? s->charge[i] : 0.0;
+    hx[i] = make_double4(s->pos[3 * i], s->pos[3 * i + 1], s->pos[3 * i + 2], q);
+    hv[i] = make_double4(s->vel[3 * i], s->vel[3 * i + 1], s->vel[3 * i + 2], s->mass[i] / s->accel_factor);
+  }
+
+  // --- device allocation
+  bool ok = true;
+  auto A = [&](auto *&ptr, size_t cnt) {
+    using T = std::remove_reference_t<decltype(*ptr)>;
+    ptr = dalloc<std::remove_const_t<T>>(c, cnt);
+    if (!ptr) ok = false;
+  };
+  double4 *x0, *x1, *v, *fnb, *fb, *xref;
+  A(x0, n); A(x1, n); A(v, n); A(fnb, n); A(fb, n); A(xref, n);
+  int *d_type, *d_rep, *d_loc, *d_cdim, *d_coff;
+  double *d_box, *d_c12, *d_c6, *d_shift, *d_elj, *d_ecu, *d_qmax;
+  A(d_type, n); A(d_rep, n); A(d_loc, n); A(d_cdim, 3 * nrep); A(d_coff, nrep + 1);
+  A(d_box, 3 * nrep); A(d_c12, nt * nt); A(d_c6, nt * nt); A(d_shift, nt * nt);
+  A(d_elj, nt * nt * nr); A(d_ecu, nt * nt * nr); A(d_qmax, nt);
+  int *d_xptr = nullptr, *d_xj = nullptr;
+  if (s->excl_ptr) { A(d_xptr, n + 1); A(d_xj, std::max(1, s->excl_ptr[n])); }
+  int *d_bptr, *d_bterm, *d_bij, *d_aijk;
+  double *d_bk, *d_br0, *d_ak, *d_at0;
+  A(d_bptr, n + 1); A(d_bterm, bterm.size());
+  A(d_bij, std::max(1, 2 * s->n_bonds)); A(d_bk, std::max(1, s->n_bonds)); A(d_br0, std::max(1, s->n_bonds));
+  A(d_aijk, std::max(1, 3 * s->n_angles)); A(d_ak, std::max(1, s->n_angles)); A(d_at0, std::max(1, s->n_angles));
+  A(V.cell_count, V.ncell_total); A(V.cell_start, V.ncell_total + 1); A(V.cell_atoms, n);
+  A(V.atom_cell, n); A(V.atom_slot, n);
+  A(V.srow, (size_t)n * V.cap_s); A(V.scnt, n);
+  A(V.frow, (size_t)n * V.cap_f); A(V.fcnt, n);
+  A(V.crow, (size_t)n * V.cap_c); A(V.ccnt, n); A(V.segst, (size_t)n * (c->S + 1));
+  A(V.nprop, n); A(V.nacc, n); A(V.nviol, n); A(V.hash, n);
+  A(V.ctl, 1);
+  V.ev_cap = p->log_events ? (1ll << 22) : 0;
+  if (V.ev_cap) A(V.ev, V.ev_cap);
+  A(c->d_rep_off, nrep + 1);
+  c->scratch_n = std::max<size_t>(4 * (size_t)n + (size_t)s->n_bonds + (size_t)s->n_angles, 4096);
+  A(c->d_scratch, c->scratch_n);
+  if (!ok) {
+    std::string why = c->err;
+    md_destroy(c);
+    return fail(nullptr, MD_ERR_OOM, "device allocation failed: " + why);
+  }
+
+  hipStream_t st = c->stream;
+  auto up = [&](void *dst, const void *src, size_t bytes) {
+    if (bytes && hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) != hipSuccess) ok = false;
+  };
+  up(x0, hx.data(), sizeof(double4) * n);
+  up(v, hv.data(), sizeof(double4) * n);
+  up(d_type, s->type, sizeof(int) * n);
+  up(d_rep, rep.data(), sizeof(int) * n);
+  up(d_loc, loc.data(), sizeof(int) * n);
+  up(d_cdim, cdim.data(), sizeof(int) * 3 * nrep);
+  up(d_coff, coff.data(), sizeof(int) * (nrep + 1));
+  up(d_box, c->box.data(), sizeof(double) * 3 * nrep);
+  up(d_c12, c12.data(), sizeof(double) * nt * nt);
+  up(d_c6, c6.data(), sizeof(double) * nt * nt);
+  up(d_shift, shift.data(), sizeof(double) * nt * nt);
+  up(d_elj, ell_lj.data(), sizeof(double) * nt * nt * nr);
+  up(d_ecu, ell_cu.data(), sizeof(double) * nt * nt * nr);
+  up(d_qmax, qmax.data(), sizeof(double) * nt);
+  if (s->excl_ptr) {
+    up(d_xptr, s->excl_ptr, sizeof(int) * (n + 1));
+    up(d_xj, s->excl_j, sizeof(int) * s->excl_ptr[n]);
+  }
+  up(d_bptr, bptr.data(), sizeof(int) * (n + 1));
+  up(d_bterm, bterm.data(), sizeof(int) * bterm.size());
+  up(d_bij, s->bond_ij, sizeof(int) * 2 * s->n_bonds);
+  up(d_bk, s->bond_k, sizeof(double) * s->n_bonds);
+  up(d_br0, s->bond_r0, sizeof(double) * s->n_bonds);
+  up(d_aijk, s->angle_ijk, sizeof(int) * 3 * s->n_angles);
+  up(d_ak, s->angle_k, sizeof(double) * s->n_angles);
+  up(d_at0, s->angle_t0, sizeof(double) * s->n_angles);
+  up(c->d_rep_off, c->rep_off.data(), sizeof(int) * (nrep + 1));
+  if (hipMemsetAsync(V.cell_count, 0, sizeof(int) * V.ncell_total, st) != hipSuccess) ok = false;
+  if (hipMemsetAsync(V.ctl, 0, sizeof(MDCtl), st) != hipSuccess) ok = false;
+  if (hipMemsetAsync(V.nprop, 0, sizeof(long long) * n, st) != hipSuccess) ok = false;
+  if (hipMemsetAsync(V.nacc, 0, sizeof(long long) * n, st) != hipSuccess) ok = false;
+  if (hipMemsetAsync(V.nviol, 0, sizeof(long long) * n, st) != hipSuccess) ok = false;
+  if (hipMemsetAsync(fnb, 0, sizeof(double4) * n, st) != hipSuccess) ok = false;
+  if (hipMemsetAsync(fb, 0, sizeof(double4) * n, st) != hipSuccess) ok = false;
+  {
+    std::vector<unsigned long long> h0(n, 0xcbf29ce484222325ull);
+    up(V.hash, h0.data(), sizeof(unsigned long long) * n);
+    if (hipStreamSynchronize(st) != hipSuccess) ok = false;
+  }
+  if (!ok) { md_destroy(c); return fail(nullptr, MD_ERR_HIP, "upload failed"); }
+
+  V.x0 = x0; V.x1 = x1; V.v = v; V.fnb = fnb; V.fb = fb; V.xref = xref;
+  V.type = d_type; V.rep = d_rep; V.loc = d_loc; V.box = d_box;
+  V.c12 = d_c12; V.c6 = d_c6; V.ljshift = d_shift; V.ell_lj = d_elj; V.ell_cu = d_ecu; V.qmax = d_qmax;
+  V.xptr = d_xptr; V.xj = d_xj; V.bptr = d_bptr; V.bterm = d_bterm;
+  V.bond_ij = d_bij; V.bond_k = d_bk; V.bond_r0 = d_br0;
+  V.angle_ijk = d_aijk; V.angle_k = d_ak; V.angle_t0 = d_at0;
+  V.rep_cell_off = d_coff; V.rep_cdim = d_cdim;
+  c->cur = 0;
+  c->fkind = -1;
+  c->fb_valid = false;
+  c->rows_valid = 0;
+  *out = c;
+  return MD_OK;
+}
+
+extern "C" void md_destroy(md_ctx *c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  for (void *p : c->allocs) hipFree(p);
+  if (c->d_hist) hipFree(c->d_hist);
+  for (hipEvent_t e : c->tm.pool) hipEventDestroy(e);
+  delete c;
+}
+
+extern "C" const char *md_last_error(const md_ctx *c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+// -------------------------------------------------------------- stepping
+extern "C" int md_step_baoab(md_ctx *c, int64_t nsteps) {
+  if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  int rc = ensure_forces(c, MODE_BAOAB);
+  if (rc) return rc;
+  const double h = 0.5 * c->par.dt;
+  for (int64_t it = 0; it <= nsteps; ++it) {
+    ProgBuilder b;
+    if (it > 0) add_B(b, h, 3);                      // tail of the previous step
+    if (it < nsteps) {                               // head of this step
+      add_B(b, h, 3);
+      add_A(b, h);
+      add_O(c, b, c->par.dt, 0, c->step);
+      add_A(b, h);
+      add_disp(b, (int)(c->step & 1));
+    }
+    if ((rc = run_prog(c, b))) return rc;
+    if (it == nsteps) break;
+    if ((rc = step_rebuild(c, MODE_BAOAB, c->step))) return rc;
+    if ((rc = eval_nb(c, 1)) || (rc = eval_bonded(c))) return rc;
+    c->step++;
+  }
+  return MD_OK;
+}
+
+extern "C" int md_step_jump(md_ctx *c, int64_t nsteps) {
+  if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  int rc = ensure_forces(c, MODE_JUMP);
+  if (rc) return rc;
+  const double h = 0.5 * c->par.dt;
+  const bool lj = c->par.jump_lj == MD_JUMP_BPS;
+  for (int64_t it = 0; it <= nsteps; ++it) {
+    ProgBuilder b;
+    if (it > 0) {                                    // J' C' closing the previous step
+      if (lj) add_J(b, OP_PHASE_J2, h, c->step - 1);
+      add_C_or_B(c, b, OP_PHASE_C2, h, c->step - 1, 0);
+    }
+    if (it < nsteps) {                               // C' J' A O A
+      add_C_or_B(c, b, OP_PHASE_C1, h, c->step, 0);
+      if (lj) add_J(b, OP_PHASE_J1, h, c->step);
+      add_A(b, h);
+      add_O(c, b, c->par.dt, 0, c->step);
+      add_A(b, h);
+      add_disp(b, (int)(c->step & 1));
+    }
+    if ((rc = run_prog(c, b))) return rc;
+    if (it == nsteps) break;
+    if ((rc = step_rebuild(c, MODE_JUMP, c->step))) return rc;
+    if ((rc = eval_nb(c, 0)) || (rc = eval_bonded(c))) return rc;
+    c->step++;
+  }
+  return MD_OK;
+}
+
+static int respa(md_ctx *c, int64_t n_outer, bool jump) {
+  if (!c || n_outer < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  const int mode = jump ? MODE_JUMP_RESPA : MODE_BAOAB_RESPA;
+  int rc = ensure_forces(c, mode);
+  if (rc) return rc;
+  const int m = c->par.respa_inner;
+  const double h = 0.5 * c->par.dt, H = 0.5 * c->par.dt * m;
+  const bool lj = jump && c->par.jump_lj == MD_JUMP_BPS;
+  for (int64_t it = 0; it <= n_outer; ++it) {
+    // end of the previous outer step: closing inner kick, then J' C' (or the
+    // outer non-bonded kick of BAOAB-RESPA)
+    ProgBuilder b;
+    if (it > 0) {
+      add_B(b, h, 2);
+      if (jump) {
+        if (lj) add_J(b, OP_PHASE_J2, H, c->step - 1);
+        add_C_or_B(c, b, OP_PHASE_C2, H, c->step - 1, 1);
+      } else {
+        add_B(b, H, 1);
+      }
+    }
+    if (it == n_outer) { if ((rc = run_prog(c, b))) return rc; break; }
+    // start of this outer step, fused with the first inner B_b A O A
+    if (jump) {
+      add_C_or_B(c, b, OP_PHASE_C1, H, c->step, 1);
+      if (lj) add_J(b, OP_PHASE_J1, H, c->step);
+    } else {
+      add_B(b, H, 1);
+    }
+    for (int sub = 0; sub < m; ++sub) {
+      if (sub > 0) add_B(b, h, 2);                   // closing kick of inner step sub-1
+      add_B(b, h, 2);
+      add_A(b, h);
+      add_O(c, b, c->par.dt, sub, c->step);
+      add_A(b, h);
+      if (sub == m - 1) add_disp(b, (int)(c->step & 1));
+      if ((rc = run_prog(c, b))) return rc;
+      if ((rc = eval_bonded(c))) return rc;
+      b = ProgBuilder();
+    }
+    if ((rc = step_rebuild(c, mode, c->step))) return rc;
+    if ((rc = eval_nb(c, jump ? 0 : 1))) return rc;
+    c->step++;
+  }
+  return MD_OK;
+}
+
+extern "C" int md_step_jump_respa(md_ctx *c, int64_t n_outer) { return respa(c, n_outer, true); }
+extern "C" int md_step_baoab_respa(md_ctx *c, int64_t n_outer) { return respa(c, n_outer, false); }
+
+// -------------------------------------------------------------- sync
+static int sync_and_check(md_ctx *c) {
+  HIPCHK(c, hipMemcpyAsync(&c->ctl_host, c->V.ctl, sizeof(MDCtl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const MDCtl &h = c->ctl_host;
+  if (h.overflow_rows) return fail(c, MD_ERR_CAPACITY, "a neighbour row exceeded its capacity (" +
+                                                           std::to_string(h.overflow_rows) + " entries)");
+  if (h.nonfinite) return fail(c, MD_ERR_UNSTABLE, "non-finite velocities");
+  if (c->par.rebuild_every > 0 && h.n_list_err)
+    return fail(c, MD_ERR_LIST, "displacement beyond skin/2 between scheduled rebuilds");
+  if (c->par.strict_bounds) {
+    std::vector<long long> nv(c->n);
+    HIPCHK(c, hipMemcpy(nv.data(), c->V.nviol, sizeof(long long) * c->n, hipMemcpyDeviceToHost));
+    for (long long x : nv)
+      if (x) return fail(c, MD_ERR_BOUND, "an acceptance probability exceeded 1 (rate bound violated)");
+  }
+  return MD_OK;
+}
+
+extern "C" int md_sync(md_ctx *c) {
+  if (!c) return fail(c, MD_ERR_ARG, "null context");
+  return sync_and_check(c);
+}
+
+extern "C" int md_observables(md_ctx *c, uint32_t flags, md_obs *o) {
+  if (!c || !o) return fail(c, MD_ERR_ARG, "null argument");
+  memset(o, 0, sizeof(*o));
+  int nb = 0;
+  HIPCHK(c, launch_ke(c->V, c->d_scratch, &nb, c->stream));
+  std::vector<double> part(nb);
+  HIPCHK(c, hipMemcpyAsync(part.data(), c->d_scratch, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
+  int rc = sync_and_check(c);
+  double ke = 0.0;
+  for (double x : part) ke += x;
+  o->step = c->step;
+  o->time = c->step * c->par.dt;
+  o->ke = ke;
+  o->temperature = 2.0 * ke / (3.0 * c->n * c->kB);
+  std::vector<long long> a(c->n), b(c->n), v(c->n);
+  std::vector<unsigned long long> hsh(c->n);
+  HIPCHK(c, hipMemcpy(a.data(), c->V.nprop, 8 * c->n, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(b.data(), c->V.nacc, 8 * c->n, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(v.data(), c->V.nviol, 8 * c->n, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(hsh.data(), c->V.hash, 8 * c->n, hipMemcpyDeviceToHost));
+  uint64_t H = 0xcbf29ce484222325ull;
+  for (int i = 0; i < c->n; ++i) {
+    o->n_prop += a[i]; o->n_acc += b[i]; o->n_bound_viol += v[i];
+    for (int q = 0; q < 8; ++q) { H ^= (hsh[i] >> (8 * q)) & 0xffull; H *= 0x100000001b3ull; }
+  }
+  o->event_hash = H;
+  o->n_rebuilds = (int64_t)c->ctl_host.n_rebuilds;
+  o->n_zsampler_overflow = (int64_t)c->ctl_host.n_zs_overflow;
+  o->n_list_errors = (int64_t)c->ctl_host.n_list_err;
+  if (flags & MD_OBS_PE) {
+    int rows = c->rows_valid;
+    double4 *X = Xcur(c);
+    double *es = c->d_scratch, *el = c->d_scratch + c->n, *dummy = c->d_scratch + 2 * c->n;
+    double *eb = c->d_scratch + 3 * c->n;
+    std::vector<double> hs(c->n), hl(c->n), hb(std::max(1, c->nbonds + c->nangles));
+    double ps = 0.0, pl = 0.0, pb = 0.0;
+    if ((rows & (ROW_SHORT | ROW_CAND)) == (ROW_SHORT | ROW_CAND) && !(rows & ROW_FULL)) {
+      HIPCHK(c, launch_pair_energy(c->V, X, 0, es, dummy, c->stream));
+      HIPCHK(c, hipMemcpyAsync(hs.data(), es, 8 * c->n, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, launch_pair_energy(c->V, X, 1, dummy, el, c->stream));
+      HIPCHK(c, hipMemcpyAsync(hl.data(), el, 8 * c->n, hipMemcpyDeviceToHost, c->stream));
+    } else {
+      if (!(rows & ROW_FULL)) { int r2 = ensure_rows(c, ROW_FULL); if (r2) return r2; }
+      HIPCHK(c, launch_pair_energy(c->V, X, 2, es, el, c->stream));
+      HIPCHK(c, hipMemcpyAsync(hs.data(), es, 8 * c->n, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(hl.data(), el, 8 * c->n, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (c->nbonds + c->nangles) {
+      HIPCHK(c, launch_bonded_energy(c->V, X, c->nbonds, c->nangles, eb, c->stream));
+      HIPCHK(c, hipMemcpyAsync(hb.data(), eb, 8 * (c->nbonds + c->nangles), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->n; ++i) { ps += hs[i]; pl += hl[i]; }
+    for (int t = 0; t < c->nbonds + c->nangles; ++t) pb += hb[t];
+    o->pe_short = ps; o->pe_long = pl; o->pe_bonded = pb;
+  }
+  return rc;
+}
+
+// ------------------------------------------------------------- state I/O
+extern "C" int md_get_state(md_ctx *c, double *pos, double *vel) {
+  if (!c) return fail(c, MD_ERR_ARG, "null context");
+  std::vector<double4> h(c->n);
+  if (pos) {
+    HIPCHK(c, hipMemcpyAsync(h.data(), Xcur(c), sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->n; ++i) { pos[3 * i] = h[i].x; pos[3 * i + 1] = h[i].y; pos[3 * i + 2] = h[i].z; }
+  }
+  if (vel) {
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->V.v, sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->n; ++i) { vel[3 * i] = h[i].x; vel[3 * i + 1] = h[i].y; vel[3 * i + 2] = h[i].z; }
+  }
+  return sync_and_check(c);
+}
+
+extern "C" int md_set_state(md_ctx *c, const double *pos, const double *vel, int64_t step) {
+  if (!c) return fail(c, MD_ERR_ARG, "null context");
+  std::vector<double4> h(c->n);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (pos) {
+    HIPCHK(c, hipMemcpy(h.data(), Xcur(c), sizeof(double4) * c->n, hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->n; ++i) { h[i].x = pos[3 * i]; h[i].y = pos[3 * i + 1]; h[i].z = pos[3 * i + 2]; }
+    HIPCHK(c, hipMemcpy(Xcur(c), h.data(), sizeof(double4) * c->n, hipMemcpyHostToDevice));
+    c->rows_valid = 0;
+    c->fkind = -1;
+    c->fb_valid = false;
+  }
+  if (vel) {
+    HIPCHK(c, hipMemcpy(h.data(), c->V.v, sizeof(double4) * c->n, hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->n; ++i) { h[i].x = vel[3 * i]; h[i].y = vel[3 * i + 1]; h[i].z = vel[3 * i + 2]; }
+    HIPCHK(c, hipMemcpy(c->V.v, h.data(), sizeof(double4) * c->n, hipMemcpyHostToDevice));
+  }
+  if (step >= 0) c->step = step;
+  return MD_OK;
+}
+
+extern "C" int md_get_accel(md_ctx *c, int32_t kind, double *acc) {
+  if (!c || !acc || kind < 0 || kind > 2) return fail(c, MD_ERR_ARG, "bad argument");
+  int rc;
+  if (kind == 2) {
+    if ((rc = eval_bonded(c))) return rc;
+  } else {
+    if ((rc = ensure_rows(c, kind == 0 ? (ROW_SHORT | ROW_CAND) : ROW_FULL))) return rc;
+    if ((rc = eval_nb(c, kind))) return rc;
+  }
+  std::vector<double4> f(c->n), v(c->n);
+  HIPCHK(c, hipMemcpyAsync(f.data(), kind == 2 ? c->V.fb : c->V.fnb, sizeof(double4) * c->n,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(v.data(), c->V.v, sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < c->n; ++i) {
+    acc[3 * i] = f[i].x / v[i].w; acc[3 * i + 1] = f[i].y / v[i].w; acc[3 * i + 2] = f[i].z / v[i].w;
+  }
+  return sync_and_check(c);
+}
+
+extern "C" int md_get_atom_stats(md_ctx *c, int64_t *np, int64_t *na, int64_t *nv, uint64_t *hash) {
+  if (!c) return fail(c, MD_ERR_ARG, "null context");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (np) HIPCHK(c, hipMemcpy(np, c->V.nprop, 8 * c->n, hipMemcpyDeviceToHost));
+  if (na) HIPCHK(c, hipMemcpy(na, c->V.nacc, 8 * c->n, hipMemcpyDeviceToHost));
+  if (nv) HIPCHK(c, hipMemcpy(nv, c->V.nviol, 8 * c->n, hipMemcpyDeviceToHost));
+  if (hash) HIPCHK(c, hipMemcpy(hash, c->V.hash, 8 * c->n, hipMemcpyDeviceToHost));
+  return sync_and_check(c);
+}
+
+extern "C" int md_get_events(md_ctx *c, md_event *buf, int64_t cap, int64_t *n) {
+  if (!c || !n) return fail(c, MD_ERR_ARG, "bad argument");
+  int rc = sync_and_check(c);
+  long long ne = (long long)c->ctl_host.n_events;
+  if (ne > c->V.ev_cap) ne = c->V.ev_cap;
+  *n = ne;
+  if (!buf || ne == 0) return rc;
+  std::vector<MDEventDev> h(ne);
+  HIPCHK(c, hipMemcpy(h.data(), c->V.ev, sizeof(MDEventDev) * ne, hipMemcpyDeviceToHost));
+  std::sort(h.begin(), h.end(), [](const MDEventDev &a, const MDEventDev &b) {
+    if (a.step != b.step) return a.step < b.step;
+    if (a.phase != b.phase) return a.phase < b.phase;
+    if (a.atom != b.atom) return a.atom < b.atom;
+    return a.proposal < b.proposal;
+  });
+  for (long long e = 0; e < std::min<long long>(ne, cap); ++e) {
+    buf[e].step = h[e].step; buf[e].phase = h[e].phase; buf[e].atom = h[e].atom;
+    buf[e].partner = h[e].partner; buf[e].proposal = h[e].proposal;
+  }
+  return rc;
+}
+
+extern "C" int md_rdf(md_ctx *c, int32_t ta, int32_t tb, double r_max, int32_t n_bins, double *hist) {
+  if (!c || !hist || n_bins <= 0 || !(r_max > 0.0)) return fail(c, MD_ERR_ARG, "bad argument");
+  if (c->hist_n < n_bins) {
+    if (c->d_hist) hipFree(c->d_hist);
+    c->d_hist = nullptr;
+    HIPCHK(c, hipMalloc(&c->d_hist, sizeof(unsigned long long) * n_bins));
+    c->hist_n = n_bins;
+  }
+  HIPCHK(c, hipMemsetAsync(c->d_hist, 0, sizeof(unsigned long long) * n_bins, c->stream));
+  HIPCHK(c, launch_rdf(c->V, Xcur(c), c->d_rep_off, ta, tb, r_max, n_bins, c->d_hist, c->stream));
+  std::vector<unsigned long long> h(n_bins);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->d_hist, sizeof(unsigned long long) * n_bins, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int b = 0; b < n_bins; ++b) hist[b] = (double)h[b];
+  return sync_and_check(c);
+}
+
+extern "C" int md_get_cand_row(md_ctx *c, int32_t i, int32_t *j, int32_t cap, int32_t *n, int32_t *seg) {
+  if (!c || !n || i < 0 || i >= c->n) return fail(c, MD_ERR_ARG, "bad argument");
+  int rc = ensure_rows(c, ROW_SHORT | ROW_CAND);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int cnt = 0;
+  HIPCHK(c, hipMemcpy(&cnt, c->V.ccnt + i, sizeof(int), hipMemcpyDeviceToHost));
+  *n = cnt;
+  if (j && cnt) HIPCHK(c, hipMemcpy(j, c->V.crow + (size_t)i * c->V.cap_c, sizeof(int) * std::min(cnt, cap),
+                                    hipMemcpyDeviceToHost));
+  if (seg) HIPCHK(c, hipMemcpy(seg, c->V.segst + (size_t)i * (c->S + 1), sizeof(int) * (c->S + 1),
+                               hipMemcpyDeviceToHost));
+  return sync_and_check(c);
+}
+
+extern "C" int md_get_row_counts(md_ctx *c, int32_t which, int32_t *counts) {
+  if (!c || !counts || which < 0 || which > 2) return fail(c, MD_ERR_ARG, "bad argument");
+  int want = which == 0 ? ROW_SHORT : (which == 1 ? ROW_FULL : ROW_CAND);
+  int rc = ensure_rows(c, want == ROW_FULL ? ROW_FULL : (ROW_SHORT | ROW_CAND));
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int *src = which == 0 ? c->V.scnt : (which == 1 ? c->V.fcnt : c->V.ccnt);
+  HIPCHK(c, hipMemcpy(counts, src, sizeof(int) * c->n, hipMemcpyDeviceToHost));
+  return sync_and_check(c);
+}
+
+extern "C" int md_run_phase(md_ctx *c, int32_t which, int32_t phase, double h) {
+  if (!c) return fail(c, MD_ERR_ARG, "null context");
+  int rc = ensure_forces(c, MODE_JUMP);
+  if (rc) return rc;
+  ProgBuilder b;
+  if (which == 'C') {
+    if (c->par.jump_coul == MD_JUMP_NONE) return fail(c, MD_ERR_ARG, "no Coulomb jumps configured");
+    MDOp o = op_base(OP_C, h); o.phase = phase; o.step = c->step; o.flags = 0; b.add(o);
+  } else if (which == 'J') {
+    add_J(b, phase, h, c->step);
+  } else if (which == 'O') {
+    add_O(c, b, h, 0, c->step);
+  } else {
+    return fail(c, MD_ERR_ARG, "which must be 'C', 'J' or 'O'");
+  }
+  return run_prog(c, b);
+}
+
+extern "C" int md_profile(md_ctx *c, int32_t enable) {
+  if (!c) return fail(c, MD_ERR_ARG, "null context");
+  prof_collect(c);
+  c->prof = enable != 0;
+  for (int k = 0; k < MD_K_COUNT; ++k) { c->tm.tot_ms[k] = 0.0; c->tm.launches[k] = 0; }
+  return MD_OK;
+}
+
+extern "C" int md_profile_read(md_ctx *c, int32_t kid, double *total_ms, int64_t *launches) {
+  if (!c || kid < 0 || kid >= MD_K_COUNT) return fail(c, MD_ERR_ARG, "bad argument");
+  prof_collect(c);
+  if (total_ms) *total_ms = c->tm.tot_ms[kid];
+  if (launches) *launches = c->tm.launches[kid];
+  return MD_OK;
+}
+
+extern "C" int md_counters(md_ctx *c, int64_t *pairs_last, int64_t *proposals_total) {
+  if (!c) return fail(c, MD_ERR_ARG, "null context");
+  if (pairs_last) {
+    *pairs_last = -1;
+    if (c->fkind == 0 || c->fkind == 1) {
+      int which = c->fkind;
+      int need = which == 0 ? ROW_SHORT : ROW_FULL;
+      if ((c->rows_valid & need) == need) {
+        HIPCHK(c, hipMemsetAsync(c->d_scratch, 0, sizeof(unsigned long long), c->stream));
+        HIPCHK(c, launch_count_pairs(c->V, Xcur(c), which, which == 0 ? c->split.r_s : c->split.r_c,
+                                     (unsigned long long *)c->d_scratch, c->stream));
+        unsigned long long h = 0;
+        HIPCHK(c, hipMemcpyAsync(&h, c->d_scratch, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *pairs_last = (int64_t)h;
+      }
+    }
+  }
+  int rc = sync_and_check(c);
+  if (proposals_total) {
+    std::vector<long long> a(c->n);
+    HIPCHK(c, hipMemcpy(a.data(), c->V.nprop, 8 * c->n, hipMemcpyDeviceToHost));
+    long long s = 0;
+    for (long long x : a) s += x;
+    *proposals_total = s;
+  }
+  return rc;
+}

@@ -1,0 +1,198 @@
+// md_device.h — device-side building blocks of libjumpmd (gfx950):
+// counter-based random numbers, pair terms, the MRZ helper functions and the
+// per-context device view shared by all kernels.
+//
+// Paper: Gouraud et al., "Velocity Jumps for Molecular Dynamics", arXiv 2412.15073.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MD_MAX_OPS 12
+#define MD_ZS_MAXIT 64
+#define MD_MAX_PROPOSALS (1ll << 22)  // per chain and half step; reaching it flags the run as unstable
+#define MD_PI 3.14159265358979323846
+#define MD_INV_SQRT_2PI 0.3989422804014327
+
+// ----------------------------------------------------------------- random
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11). Counter words:
+// (step, local atom index, phase | substep<<8 | zsampler_iteration<<24, k);
+// key words: (seed, replica index).
+struct u64x4 { uint64_t w[4]; };
+
+__device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                                uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B97F4A7C15ull; k1 += 0xBB67AE8584CAA73Bull; }
+    const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+    uint64_t hi0 = __umul64hi(m0, c0), lo0 = m0 * c0;
+    uint64_t hi1 = __umul64hi(m1, c2), lo1 = m1 * c2;
+    uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  u64x4 o; o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+  return o;
+}
+
+// uniform in (0,1): (w >> 12 + 1/2) * 2^-52, exact in FP64
+__device__ __forceinline__ double u01(uint64_t w) {
+  return ((double)(w >> 12) + 0.5) * 2.220446049250313080847263336181640625e-16;
+}
+
+struct Uni4 { double u[4]; };
+
+__device__ __forceinline__ Uni4 draw4(uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
+                                      uint64_t tag, int64_t k) {
+  u64x4 r = philox4x64_10((uint64_t)step, (uint64_t)atom, tag, (uint64_t)k, seed, rep);
+  Uni4 o;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o.u[q] = u01(r.w[q]);
+  return o;
+}
+
+// ------------------------------------------------------------ event hash
+__device__ __forceinline__ uint64_t fnv1a_u64(uint64_t h, uint64_t x, int nbytes) {
+  for (int b = 0; b < nbytes; ++b) {
+    h ^= (x >> (8 * b)) & 0xffull;
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+// ------------------------------------------------------- context view
+struct MDOp {
+  int kind;      // OP_*
+  int phase;     // random-stream phase tag (J/C/O)
+  int substep;   // O: inner index of the RESPA schemes
+  int flags;     // B: bit0 non-bonded, bit1 bonded; C: 0 -> a from nb+bonded, 1 -> nb only
+  double h;      // duration
+  double c1, c2; // O: exp(-gamma h), sqrt(1 - c1^2)
+  int64_t step;  // random-stream step word
+};
+
+enum { OP_B = 1, OP_A = 2, OP_O = 3, OP_J = 4, OP_C = 5, OP_DISP = 6 };
+
+struct MDProg {
+  int nops;
+  int disp_slot;   // slot written by OP_DISP
+  int reset_slot;  // slot cleared by thread 0 (-1: none)
+  int pad;
+  MDOp ops[MD_MAX_OPS];
+};
+
+struct MDCtl {                       // device-side control words
+  unsigned long long maxd2[2];       // max |x - x_ref|^2 (double bits), per step parity
+  int do_rebuild;
+  int overflow_rows;                 // max row length requested beyond capacity
+  unsigned long long n_rebuilds;
+  unsigned long long n_list_err;
+  unsigned long long n_zs_overflow;
+  unsigned long long n_events;
+  unsigned long long nonfinite;
+};
+
+struct MDEventDev { long long step; int phase, atom, partner, proposal; };
+
+// All device pointers and run constants; passed by value to every kernel.
+struct MDView {
+  int n, nt, nrep, nr, S;
+  // state (positions double-buffered: chains read one buffer while drift writes the other)
+  double4 *x0, *x1;      // xyz + charge
+  double4 *v;            // velocity + mass in energy units (mass / accel_factor)
+  double4 *fnb, *fb;     // forces (-grad): non-bonded, bonded
+  double4 *xref;         // positions at the last row build
+  const int *type, *rep, *loc;
+  const double *box;     // [3*nrep]
+  // per-type tables
+  const double *c12, *c6, *ljshift;     // [nt*nt]
+  const double *ell_lj, *ell_cu;        // [nt*nt*nr] bound per unit (Coulomb: per unit charge product)
+  const double *qmax;                   // [nt]
+  // exclusions and bonded incidence
+  const int *xptr, *xj;
+  const int *bptr, *bterm;              // per atom: term code (idx << 1 | is_angle)
+  const int *bond_ij; const double *bond_k, *bond_r0;
+  const int *angle_ijk; const double *angle_k, *angle_t0;
+  // cells
+  const int *rep_cell_off;              // [nrep+1]
+  const int *rep_cdim;                  // [3*nrep]
+  int *cell_count, *cell_start, *cell_atoms, *atom_cell, *atom_slot;
+  int ncell_total;
+  // neighbour rows (row-major, fixed capacity)
+  int cap_s, cap_f, cap_c;
+  int *srow, *scnt, *frow, *fcnt, *crow, *ccnt, *segst;
+  // statistics
+  long long *nprop, *nacc, *nviol;
+  unsigned long long *hash;
+  MDCtl *ctl;
+  MDEventDev *ev; long long ev_cap;
+  // constants
+  double rs, rc, w, rlo, skin, rin, rout, rw, alpha, ke;
+  double dsf_erfc_rc_over_rc, dsf_fc, two_a_sqpi;
+  double beta, kT, eps0;
+  int jlj, jc, log_events, precision;
+  uint64_t seed;
+};
+
+// -------------------------------------------------------------- geometry
+__device__ __forceinline__ double min_img(double d, double L, double iL) {
+  return d - L * rint(d * iL);
+}
+
+// --------------------------------------------------------- pair terms (FP64)
+// LJ energy-shifted at r_c: U = c12/r^12 - c6/r^6 - shift; Sec. 3.2.
+__device__ __forceinline__ void lj_pair(double r2, double r, double c12, double c6, double shift,
+                                        double &U, double &dU) {
+  double ir2 = 1.0 / r2, ir6 = ir2 * ir2 * ir2;
+  U = ir6 * (c12 * ir6 - c6) - shift;
+  dU = (-12.0 * c12 * ir6 * ir6 + 6.0 * c6 * ir6) / r;
+}
+
+// Damped shifted-force Coulomb (Fennell-Gezelter 2006), zero value and slope at r_c.
+__device__ __forceinline__ void dsf_pair(double r, double kqq, const MDView &V, double &U, double &dU) {
+  double e = erfc(V.alpha * r);
+  double g = exp(-V.alpha * V.alpha * r * r);
+  U = kqq * (e / r - V.dsf_erfc_rc_over_rc + V.dsf_fc * (r - V.rc));
+  dU = kqq * (-(e / (r * r) + V.two_a_sqpi * g / r) + V.dsf_fc);
+}
+
+// C2 quintic switch, 1 below r_s - w, 0 above r_s.
+__device__ __forceinline__ void switch_fn(double r, const MDView &V, double &chi, double &dchi) {
+  if (r <= V.rlo) { chi = 1.0; dchi = 0.0; return; }
+  if (r >= V.rs) { chi = 0.0; dchi = 0.0; return; }
+  double t = (r - V.rlo) / V.w;
+  chi = 1.0 - t * t * t * (10.0 - 15.0 * t + 6.0 * t * t);
+  dchi = -30.0 * t * t * (1.0 - t) * (1.0 - t) / V.w;
+}
+
+// Theta(eta) = E[(eta+G)_+] = eta Phi(eta) + phi(eta)  (Sec. 2.2)
+__device__ __forceinline__ double theta_fn(double eta) {
+  return eta * (0.5 * erfc(-eta * 0.70710678118654752440)) + exp(-0.5 * eta * eta) * MD_INV_SQRT_2PI;
+}
+
+// Z = eta + G~ by exact rejection sampling (Sec. 2.4 regimes); one Philox
+// block per iteration, counter word 2 = phase | (iteration+1) << 24.
+__device__ double zsample(double eta, uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
+                          int phase, int64_t k, int &iters) {
+  for (int r = 0; r < MD_ZS_MAXIT; ++r) {
+    uint64_t tag = (uint64_t)(uint32_t)phase | ((uint64_t)(r + 1) << 24);
+    Uni4 u = draw4(seed, rep, step, atom, tag, k);
+    iters = r + 1;
+    if (eta > 0.0) {
+      double p_ray = 1.0 / (1.0 + eta * 2.5066282746310002);
+      double rad = sqrt(-2.0 * log(u.u[1]));
+      double y = (u.u[0] < p_ray) ? rad : rad * cos(2.0 * MD_PI * u.u[2]);
+      double z = eta + y;
+      if (y >= 0.0) return z;
+      if (z <= 0.0) continue;
+      if (u.u[3] <= z / eta) return z;
+    } else if (eta >= -1.0) {
+      double z = sqrt(-2.0 * log(u.u[0]));
+      if (u.u[1] <= exp(eta * z)) return z;
+    } else {
+      double z = -(log(u.u[0]) + log(u.u[1])) / (-eta);
+      if (u.u[2] <= exp(-0.5 * z * z)) return z;
+    }
+  }
+  iters = -1;
+  return 0.5 * (eta + sqrt(eta * eta + 4.0));
+}

@@ -1,0 +1,27 @@
+// md_internal.h — host-side declarations shared by the kernel launchers and
+// the C ABI implementation of libjumpmd.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/jumpmd.h"
+#include "md_device.h"
+
+#define OP_PHASE_O 1
+#define OP_PHASE_J1 2
+#define OP_PHASE_J2 3
+#define OP_PHASE_C1 4
+#define OP_PHASE_C2 5
+
+hipError_t launch_local(const MDView &V, const MDProg &P, const double4 *Xs, double4 *Xd, hipStream_t s);
+hipError_t launch_rebuild(const MDView &V, const double4 *X, int want, int slot, int forced, int autob,
+                          double thr2, int pc, int ps, bool check_only, int count, hipStream_t s);
+hipError_t launch_force(const MDView &V, const double4 *X, int mode, hipStream_t s);
+hipError_t launch_bonded(const MDView &V, const double4 *X, hipStream_t s);
+hipError_t launch_ke(const MDView &V, double *part, int *nblocks, hipStream_t s);
+hipError_t launch_pair_energy(const MDView &V, const double4 *X, int which, double *es, double *el,
+                              hipStream_t s);
+hipError_t launch_bonded_energy(const MDView &V, const double4 *X, int nb, int na, double *e, hipStream_t s);
+hipError_t launch_rdf(const MDView &V, const double4 *X, const int *rep_off, int ta, int tb, double rmax,
+                      int nbins, unsigned long long *hist, hipStream_t s);
+hipError_t launch_count_pairs(const MDView &V, const double4 *X, int which, double cut, unsigned long long *out,
+                              hipStream_t s);

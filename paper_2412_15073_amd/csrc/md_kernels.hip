@@ -1,0 +1,847 @@
+// md_kernels.hip — HIP kernels of libjumpmd for gfx950 (CDNA4, wave64).
+//
+//  k_local     fused per-atom program: B / A / O updates (Sec. 2.3), J chains
+//              (BPS jumps, Sec. 3.2, Alg. 5 in exponential-clock form) and C
+//              chains (acceleration + MRZ jumps, Sec. 2.4, Alg. 4), one atom
+//              per lane; positions are double-buffered so that chains read
+//              a stable copy while drift writes the other.
+//  k_cell_*    counting sort of atoms into per-replica cells.
+//  k_build     neighbour rows, one wavefront per atom: candidates gathered
+//              from the cell stencil with ballot compaction into LDS, bitonic
+//              sort in LDS, segment starts by binary search.
+//  k_force     non-bonded pair forces over fixed-capacity rows, SG lanes per
+//              atom, shuffle reduction.
+//  k_bonded    bonds and angles, per atom over its incident terms.
+//  observables: kinetic energy, pair energies, pair histograms.
+#include "md_device.h"
+#include "md_internal.h"
+
+// ------------------------------------------------------------- helpers
+__device__ __forceinline__ double seg_ell(const MDView &V, int a, int sg, int coul, double absq) {
+  int b = sg / V.nr, k = sg - b * V.nr;
+  int idx = (a * V.nt + b) * V.nr + k;
+  if (!coul) return V.ell_lj[idx];
+  return (absq * V.qmax[b]) * V.ell_cu[idx];
+}
+
+// long-range gradient F_ij = grad_i (1 - chi) U_ij of one component (Sec. 3.1, 3.2)
+__device__ __forceinline__ double long_grad(const MDView &V, double4 xi, double4 xj, int a, int b,
+                                            int coul, const double *L, const double *iL,
+                                            double &Fx, double &Fy, double &Fz) {
+  double dx = min_img(xi.x - xj.x, L[0], iL[0]);
+  double dy = min_img(xi.y - xj.y, L[1], iL[1]);
+  double dz = min_img(xi.z - xj.z, L[2], iL[2]);
+  double r2 = dx * dx + dy * dy + dz * dz;
+  double r = sqrt(r2);
+  double U = 0.0, dU = 0.0;
+  if (r < V.rc) {
+    if (coul) {
+      double qq = xi.w * xj.w;
+      if (qq != 0.0) dsf_pair(r, V.ke * qq, V, U, dU);
+    } else {
+      int ab = a * V.nt + b;
+      double c12 = V.c12[ab], c6 = V.c6[ab];
+      if (c12 != 0.0 || c6 != 0.0) lj_pair(r2, r, c12, c6, V.ljshift[ab], U, dU);
+    }
+  }
+  double chi, dchi;
+  switch_fn(r, V, chi, dchi);
+  double g = (1.0 - chi) * dU - dchi * U;
+  Fx = g * dx / r; Fy = g * dy / r; Fz = g * dz / r;
+  return Fx * Fx + Fy * Fy + Fz * Fz;
+}
+
+struct AtomStats { long long nprop, nacc, nviol; uint64_t hash; };
+
+__device__ __forceinline__ void log_jump(const MDView &V, AtomStats &st, int64_t step, int phase,
+                                         int i, int j, int64_t k) {
+  uint64_t h = st.hash;
+  h = fnv1a_u64(h, (uint64_t)step, 8);
+  h = fnv1a_u64(h, (uint64_t)(uint32_t)phase, 4);
+  h = fnv1a_u64(h, (uint64_t)(uint32_t)V.loc[j], 4);
+  st.hash = h;
+  st.nacc++;
+  if (V.log_events) {
+    unsigned long long e = atomicAdd(&V.ctl->n_events, 1ull);
+    if ((long long)e < V.ev_cap) {
+      MDEventDev ev; ev.step = step; ev.phase = phase; ev.atom = i; ev.partner = j; ev.proposal = (int)k;
+      V.ev[e] = ev;
+    }
+  }
+}
+
+// Segment tables of one atom for one jump component, in registers: counts,
+// bounds, cumulative weights sum n_q l_q and cumulative counts of segments
+// with a nonzero bound (candidates whose rate can be > 0).
+template <int SMAX>
+struct SegTab {
+  double ell[SMAX], cumW[SMAX];
+  int st[SMAX], ns[SMAX], cumN[SMAX];
+  double W, nf;
+
+  __device__ __forceinline__ void load(const MDView &V, int i, int a, int coul, double absq) {
+    const int *sst = V.segst + (size_t)i * (V.S + 1);
+    double cw = 0.0;
+    int cn = 0;
+#pragma unroll
+    for (int q = 0; q < SMAX; ++q) {
+      if (q < V.S) {
+        st[q] = sst[q];
+        ns[q] = sst[q + 1] - st[q];
+        ell[q] = seg_ell(V, a, q, coul, absq);
+      } else {
+        st[q] = 0; ns[q] = 0; ell[q] = 0.0;
+      }
+      cw += (double)ns[q] * ell[q];
+      if (ell[q] > 0.0) cn += ns[q];
+      cumW[q] = cw;
+      cumN[q] = cn;
+    }
+    W = cw;
+    nf = (double)cn;
+  }
+
+  // candidate in proportion to its bound (segment by n l, then uniform inside
+  // from the residual); returns the row position, writes the segment bound
+  __device__ __forceinline__ int pick_by_bound(double u, double &ell_s) const {
+    const double target = u * W;
+    int s = -1, last = -1;
+#pragma unroll
+    for (int q = 0; q < SMAX; ++q) {
+      bool ok = ns[q] > 0 && ell[q] > 0.0;
+      if (ok) last = q;
+      if (s < 0 && ok && target < cumW[q]) s = q;
+    }
+    if (s < 0) s = last;
+    double below = 0.0, el = 0.0;
+    int base = 0, n = 1;
+#pragma unroll
+    for (int q = 0; q < SMAX; ++q) {
+      if (q == s - 1) below = cumW[q];
+      if (q == s) { el = ell[q]; base = st[q]; n = ns[q]; }
+    }
+    long long idx = (long long)floor((target - below) / el);
+    idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
+    ell_s = el;
+    return base + (int)idx;
+  }
+
+  // candidate uniform among candidates of segments with a nonzero bound
+  __device__ __forceinline__ int pick_uniform(double u, double &ell_s) const {
+    const double target = u * nf;
+    int s = -1, last = -1;
+#pragma unroll
+    for (int q = 0; q < SMAX; ++q) {
+      bool ok = ns[q] > 0 && ell[q] > 0.0;
+      if (ok) last = q;
+      if (s < 0 && ok && target < (double)cumN[q]) s = q;
+    }
+    if (s < 0) s = last;
+    double below = 0.0, el = 0.0;
+    int base = 0, n = 1;
+#pragma unroll
+    for (int q = 0; q < SMAX; ++q) {
+      if (q == s - 1) below = (double)cumN[q];
+      if (q == s) { el = ell[q]; base = st[q]; n = ns[q]; }
+    }
+    long long idx = (long long)floor(target - below);
+    idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
+    ell_s = el;
+    return base + (int)idx;
+  }
+};
+
+// ------------------------------------------------------------------ J op
+// BPS jumps of the LJ long part over half step h (Alg. 5 in the exponential-
+// clock form of Alg. 2): bound beta |v_i| l_s per candidate, constant over the
+// half step, proposal k at (E_0 + ... + E_k)/Lambda. Block (step, i, phase, k):
+// u0 -> E_k, u2 -> candidate, u3 -> acceptance.
+template <int SMAX>
+__device__ void op_j(const MDView &V, const double4 *__restrict__ X, int i, double4 xi,
+                     double &vx, double &vy, double &vz, const MDOp &op, AtomStats &st,
+                     const double *L, const double *iL) {
+  const int a = V.type[i];
+  SegTab<SMAX> T;
+  T.load(V, i, a, 0, 0.0);
+  const int *row = V.crow + (size_t)i * V.cap_c;
+  const double vn = sqrt(vx * vx + vy * vy + vz * vz);
+  const double Lam = V.beta * vn * T.W;
+  if (!(Lam > 0.0)) return;
+  if (!isfinite(Lam)) { atomicAdd(&V.ctl->nonfinite, 1ull); return; }
+  const uint64_t rep = (uint64_t)V.rep[i];
+  const int64_t li = V.loc[i];
+  double sumE = 0.0;
+  for (int64_t k = 0;; ++k) {
+    if (k >= MD_MAX_PROPOSALS) { atomicAdd(&V.ctl->nonfinite, 1ull); break; }
+    Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
+    sumE += -log(u.u[0]);
+    if (sumE / Lam > op.h) break;
+    double ell;
+    const int j = row[T.pick_by_bound(u.u[2], ell)];
+    double Fx, Fy, Fz;
+    const double F2 = long_grad(V, xi, X[j], a, V.type[j], 0, L, iL, Fx, Fy, Fz);
+    st.nprop++;
+    const double vF = vx * Fx + vy * Fy + vz * Fz;
+    const double p = (vF > 0.0 ? vF : 0.0) / (vn * ell);
+    if (p > 1.0) st.nviol++;
+    if (p > 0.0 && u.u[3] <= p) {
+      const double c = 2.0 * vF / F2;
+      vx -= c * Fx; vy -= c * Fy; vz -= c * Fz;
+      log_jump(V, st, op.step, op.phase, i, j, k);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ C op
+// Constant acceleration a_i between jumps plus MRZ jumps of the Coulomb long
+// part (Sec. 2.3 step (C), Alg. 1, Alg. 4; eps = eps0 |F| when adaptive). The
+// local bound is re-evaluated after each accepted jump (Sec. 2.4): from
+// (t_e, v_e), B_v = sqrt(|v_e|^2 + tau^2 |a|^2 + 2 tau (v_e.a)_+), tau = h - t_e.
+// Block (step, i, phase, k): u0 -> E_k, u1 -> bound part (adaptive),
+// u2 -> candidate, u3 -> acceptance.
+template <int SMAX>
+__device__ void op_c(const MDView &V, const double4 *__restrict__ X, int i, double4 xi,
+                     double &vx, double &vy, double &vz, double me, double ax, double ay, double az,
+                     const MDOp &op, AtomStats &st, const double *L, const double *iL) {
+  const int a = V.type[i];
+  SegTab<SMAX> T;
+  T.load(V, i, a, 1, fabs(xi.w));
+  const int *row = V.crow + (size_t)i * V.cap_c;
+  const bool adaptive = (V.jc == MD_JUMP_MRZ_ADAPTIVE);
+  const double beta = V.beta, eps0 = V.eps0;
+  const double f = sqrt(beta / (2.0 * MD_PI * me)) / eps0;
+  const double aa = ax * ax + ay * ay + az * az;
+  const uint64_t rep = (uint64_t)V.rep[i];
+  const int64_t li = V.loc[i];
+  const double h = op.h;
+  double vex = vx, vey = vy, vez = vz, te = 0.0;
+  int64_t k = 0;
+  bool done = false;
+  while (!done) {
+    const double tau = h - te;
+    const double vv = vex * vex + vey * vey + vez * vez;
+    const double va = vex * ax + vey * ay + vez * az;
+    const double Bv = sqrt(vv + tau * tau * aa + 2.0 * tau * (va > 0.0 ? va : 0.0));
+    const double bBv = beta * Bv;
+    const double Wb = bBv * T.W;
+    const double Lam = adaptive ? Wb + f * T.nf : (bBv + f) * T.W;
+    if (!(Lam > 0.0) || !isfinite(Lam)) {
+      if (!(Lam <= 0.0)) atomicAdd(&V.ctl->nonfinite, 1ull);
+      vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
+      break;
+    }
+    double sumE = 0.0;
+    for (;; ++k) {
+      if (k >= MD_MAX_PROPOSALS) {
+        atomicAdd(&V.ctl->nonfinite, 1ull);
+        vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
+        done = true;
+        break;
+      }
+      Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
+      sumE += -log(u.u[0]);
+      const double tk = te + sumE / Lam;
+      if (tk > h) {
+        vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
+        done = true;
+        break;
+      }
+      const double dtk = tk - te;
+      const double vkx = vex + dtk * ax, vky = vey + dtk * ay, vkz = vez + dtk * az;
+      double ell;
+      const int pos = (adaptive && !(u.u[1] * Lam < Wb)) ? T.pick_uniform(u.u[2], ell) : T.pick_by_bound(u.u[2], ell);
+      const int j = row[pos];
+      double Fx, Fy, Fz;
+      const double F2 = long_grad(V, xi, X[j], a, V.type[j], 1, L, iL, Fx, Fy, Fz);
+      st.nprop++;
+      const double c = adaptive ? bBv * ell + f : ell * (bBv + f);
+      double lam = 0.0, eta = 0.0;
+      const double vF = vkx * Fx + vky * Fy + vkz * Fz;
+      if (F2 > 0.0) {
+        if (adaptive) {
+          eta = eps0 * sqrt(beta * me) * vF;
+          lam = sqrt(beta / me) / eps0 * theta_fn(eta);
+        } else {
+          const double Fn = sqrt(F2);
+          eta = eps0 * sqrt(beta * me) * vF / Fn;
+          lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * theta_fn(eta);
+        }
+      }
+      const double p = lam / c;
+      if (p > 1.0) st.nviol++;
+      if (p > 0.0 && u.u[3] <= p) {
+        int it;
+        const double Z = zsample(eta, V.seed, rep, op.step, li, op.phase, k, it);
+        if (it < 0) atomicAdd(&V.ctl->n_zs_overflow, 1ull);
+        const double coef = adaptive ? 2.0 * eps0 * Z / ((1.0 + eps0 * eps0 * F2) * sqrt(beta * me))
+                                     : 2.0 * eps0 * Z / ((1.0 + eps0 * eps0) * sqrt(beta * me) * sqrt(F2));
+        vex = vkx - coef * Fx; vey = vky - coef * Fy; vez = vkz - coef * Fz;
+        te = tk;
+        log_jump(V, st, op.step, op.phase, i, j, k);
+        ++k;
+        break;  // new epoch
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------- k_local
+template <int SMAX>
+__global__ __launch_bounds__(64) void k_local(MDView V, MDProg P, const double4 *__restrict__ Xs,
+                                              double4 *__restrict__ Xd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && P.reset_slot >= 0) V.ctl->maxd2[P.reset_slot] = 0ull;
+  if (i >= V.n) return;
+  double4 xi = Xs[i];
+  double4 vv = V.v[i];
+  double vx = vv.x, vy = vv.y, vz = vv.z;
+  const double me = vv.w;
+  const int r = V.rep[i];
+  double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+  double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+  AtomStats st;
+  bool jumps = false;
+  for (int o = 0; o < P.nops; ++o) jumps |= (P.ops[o].kind == OP_J || P.ops[o].kind == OP_C);
+  if (jumps) { st.nprop = V.nprop[i]; st.nacc = V.nacc[i]; st.nviol = V.nviol[i]; st.hash = V.hash[i]; }
+  double4 fn = V.fnb[i], fb = V.fb[i];
+  for (int o = 0; o < P.nops; ++o) {
+    const MDOp &op = P.ops[o];
+    switch (op.kind) {
+      case OP_B: {
+        double fx = ((op.flags & 1) ? fn.x : 0.0) + ((op.flags & 2) ? fb.x : 0.0);
+        double fy = ((op.flags & 1) ? fn.y : 0.0) + ((op.flags & 2) ? fb.y : 0.0);
+        double fz = ((op.flags & 1) ? fn.z : 0.0) + ((op.flags & 2) ? fb.z : 0.0);
+        vx += op.h * fx / me; vy += op.h * fy / me; vz += op.h * fz / me;
+      } break;
+      case OP_A:
+        xi.x += op.h * vx; xi.y += op.h * vy; xi.z += op.h * vz;
+        break;
+      case OP_O: {
+        uint64_t tag = (uint64_t)OP_PHASE_O | ((uint64_t)(uint32_t)op.substep << 8);
+        Uni4 u = draw4(V.seed, (uint64_t)r, op.step, V.loc[i], tag, 0);
+        double r1 = sqrt(-2.0 * log(u.u[0])), r2 = sqrt(-2.0 * log(u.u[2]));
+        double gx = r1 * cos(2.0 * MD_PI * u.u[1]);
+        double gy = r1 * sin(2.0 * MD_PI * u.u[1]);
+        double gz = r2 * cos(2.0 * MD_PI * u.u[3]);
+        double sd = sqrt(V.kT / me);
+        vx = op.c1 * vx + op.c2 * sd * gx;
+        vy = op.c1 * vy + op.c2 * sd * gy;
+        vz = op.c1 * vz + op.c2 * sd * gz;
+      } break;
+      case OP_J:
+        op_j<SMAX>(V, Xs, i, xi, vx, vy, vz, op, st, L, iL);
+        break;
+      case OP_C: {
+        double fx = fn.x + (op.flags == 0 ? fb.x : 0.0);
+        double fy = fn.y + (op.flags == 0 ? fb.y : 0.0);
+        double fz = fn.z + (op.flags == 0 ? fb.z : 0.0);
+        op_c<SMAX>(V, Xs, i, xi, vx, vy, vz, me, fx / me, fy / me, fz / me, op, st, L, iL);
+      } break;
+      case OP_DISP: {
+        double4 xr = V.xref[i];
+        double dx = xi.x - xr.x, dy = xi.y - xr.y, dz = xi.z - xr.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        atomicMax(&V.ctl->maxd2[P.disp_slot], (unsigned long long)__double_as_longlong(d2));
+      } break;
+    }
+  }
+  if (!(isfinite(vx) && isfinite(vy) && isfinite(vz))) atomicAdd(&V.ctl->nonfinite, 1ull);
+  V.v[i] = make_double4(vx, vy, vz, me);
+  if (Xd) Xd[i] = xi;
+  if (jumps) { V.nprop[i] = st.nprop; V.nacc[i] = st.nacc; V.nviol[i] = st.nviol; V.hash[i] = st.hash; }
+}
+
+// ------------------------------------------------------------ rebuild
+__device__ __forceinline__ bool rebuild_now(const MDView &V, int slot, int forced, int autob, double thr2) {
+  if (forced) return true;
+  if (!autob) return false;
+  double m = __longlong_as_double((long long)V.ctl->maxd2[slot]);
+  return m > thr2;
+}
+
+__global__ void k_cell_count(MDView V, const double4 *__restrict__ X, int slot, int forced, int autob,
+                             double thr2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool rb = rebuild_now(V, slot, forced, autob, thr2);
+  if (i == 0 && !rb && !autob) {
+    double m = __longlong_as_double((long long)V.ctl->maxd2[slot]);
+    if (m > thr2) atomicAdd(&V.ctl->n_list_err, 1ull);
+  }
+  if (!rb || i >= V.n) return;
+  double4 x = X[i];
+  const int r = V.rep[i];
+  int c3[3];
+  const double xs[3] = {x.x, x.y, x.z};
+  for (int d = 0; d < 3; ++d) {
+    double L = V.box[3 * r + d];
+    double w = xs[d] - L * floor(xs[d] / L);
+    int nd = V.rep_cdim[3 * r + d];
+    int c = (int)(w / L * (double)nd);
+    c3[d] = c < 0 ? 0 : (c >= nd ? nd - 1 : c);
+  }
+  int c = V.rep_cell_off[r] + (c3[2] * V.rep_cdim[3 * r + 1] + c3[1]) * V.rep_cdim[3 * r] + c3[0];
+  V.atom_cell[i] = c;
+  V.atom_slot[i] = atomicAdd(&V.cell_count[c], 1);
+  V.xref[i] = x;
+}
+
+__global__ __launch_bounds__(1024) void k_cell_scan(MDView V, int slot, int forced, int autob, double thr2,
+                                                    int count) {
+  if (!rebuild_now(V, slot, forced, autob, thr2)) return;
+  __shared__ int part[1024];
+  const int T = blockDim.x, t = threadIdx.x, nc = V.ncell_total;
+  const int per = (nc + T - 1) / T;
+  const int b = t * per, e = min(nc, b + per);
+  int s = 0;
+  for (int c = b; c < e; ++c) s += V.cell_count[c];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {
+    int v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int c = b; c < e; ++c) {
+    V.cell_start[c] = run;
+    run += V.cell_count[c];
+    V.cell_count[c] = 0;
+  }
+  if (t == T - 1) V.cell_start[nc] = part[T - 1];
+  if (t == 0 && count) atomicAdd(&V.ctl->n_rebuilds, 1ull);
+}
+
+__global__ void k_cell_scatter(MDView V, int slot, int forced, int autob, double thr2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!rebuild_now(V, slot, forced, autob, thr2) || i >= V.n) return;
+  V.cell_atoms[V.cell_start[V.atom_cell[i]] + V.atom_slot[i]] = i;
+}
+
+__device__ __forceinline__ void bitonic_sort_lds(unsigned long long *keys, int m) {
+  const int lane = threadIdx.x;
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < (m >> 1); t += 64) {
+        int a = 2 * j * (t / j) + (t % j);
+        int b = a + j;
+        bool up = (a & k) == 0;
+        unsigned long long ka = keys[a], kb = keys[b];
+        if ((ka > kb) == up) { keys[a] = kb; keys[b] = ka; }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// one wavefront per atom: rows with want bits 1 = short (r < r_s+skin),
+// 2 = full (r < r_c+skin), 4 = candidates (r_s-w-skin <= r < r_c+skin)
+__global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restrict__ X, int want, int slot,
+                                              int forced, int autob, double thr2, int pc, int ps) {
+  if (!rebuild_now(V, slot, forced, autob, thr2)) return;
+  extern __shared__ unsigned long long lds[];
+  unsigned long long *kc = lds;       // candidate or full keys [pc]
+  unsigned long long *ks = lds + pc;  // short keys [ps]
+  const int i = blockIdx.x, lane = threadIdx.x;
+  const double4 xi = X[i];
+  const int r = V.rep[i];
+  const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+  const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+  const int nd[3] = {V.rep_cdim[3 * r], V.rep_cdim[3 * r + 1], V.rep_cdim[3 * r + 2]};
+  const int cl = V.atom_cell[i] - V.rep_cell_off[r];
+  const int cx = cl % nd[0], cy = (cl / nd[0]) % nd[1], cz = cl / (nd[0] * nd[1]);
+  const int x0 = V.xptr ? V.xptr[i] : 0, x1 = V.xptr ? V.xptr[i + 1] : 0;
+  const double rs_out = V.rs + V.skin;
+  const int capk = (want & 4) ? V.cap_c : V.cap_f;
+  int nk = 0, nsr = 0, over = 0;
+  for (int dz = (nd[2] >= 3 ? -1 : 0); dz <= (nd[2] >= 2 ? 1 : 0); ++dz)
+    for (int dy = (nd[1] >= 3 ? -1 : 0); dy <= (nd[1] >= 2 ? 1 : 0); ++dy)
+      for (int dx = (nd[0] >= 3 ? -1 : 0); dx <= (nd[0] >= 2 ? 1 : 0); ++dx) {
+        int ccx = (cx + dx + nd[0]) % nd[0], ccy = (cy + dy + nd[1]) % nd[1], ccz = (cz + dz + nd[2]) % nd[2];
+        int c = V.rep_cell_off[r] + (ccz * nd[1] + ccy) * nd[0] + ccx;
+        int beg = V.cell_start[c], end = V.cell_start[c + 1];
+        for (int p = beg; p < end; p += 64) {
+          int q = p + lane;
+          int j = -1;
+          bool ok = q < end;
+          if (ok) {
+            j = V.cell_atoms[q];
+            ok = (j != i);
+            for (int e = x0; ok && e < x1; ++e) ok = (V.xj[e] != j);
+          }
+          bool bs = false, bk = false;
+          unsigned long long key = 0;
+          if (ok) {
+            double4 xj = X[j];
+            double ddx = min_img(xi.x - xj.x, L[0], iL[0]);
+            double ddy = min_img(xi.y - xj.y, L[1], iL[1]);
+            double ddz = min_img(xi.z - xj.z, L[2], iL[2]);
+            double rr = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+            bs = (want & 1) && rr < rs_out;
+            if (want & 4) {
+              bk = rr >= V.rin && rr < V.rout;
+              int ring = (int)floor((rr - V.rin) / V.rw);
+              ring = ring < 0 ? 0 : (ring > V.nr - 1 ? V.nr - 1 : ring);
+              key = ((unsigned long long)(V.type[j] * V.nr + ring) << 32) | (unsigned)j;
+            } else if (want & 2) {
+              bk = rr < V.rout;
+              key = (unsigned)j;
+            }
+          }
+          unsigned long long mk = __ballot(bk), ms = __ballot(bs);
+          unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+          if (bk) {
+            int pos = nk + __popcll(mk & below);
+            if (pos < pc) kc[pos] = key; else over = 1;
+          }
+          if (bs) {
+            int pos = nsr + __popcll(ms & below);
+            if (pos < ps) ks[pos] = (unsigned)j; else over = 1;
+          }
+          nk += __popcll(mk);
+          nsr += __popcll(ms);
+        }
+      }
+  if (nk > capk || nsr > V.cap_s) over = 1;
+  if (over && lane == 0) atomicMax(&V.ctl->overflow_rows, max(nk, nsr));
+  const int nkk = min(nk, min(capk, pc)), nss = min(nsr, min(V.cap_s, ps));
+  // pad and sort
+  if (want & 6) {
+    int m = 1; while (m < nkk) m <<= 1;
+    for (int e = nkk + lane; e < m; e += 64) kc[e] = ~0ull;
+    __syncthreads();
+    bitonic_sort_lds(kc, m);
+    int *row = (want & 4) ? V.crow + (size_t)i * V.cap_c : V.frow + (size_t)i * V.cap_f;
+    for (int e = lane; e < nkk; e += 64) row[e] = (int)(kc[e] & 0xffffffffull);
+    if (lane == 0) { if (want & 4) V.ccnt[i] = nkk; else V.fcnt[i] = nkk; }
+    if (want & 4) {
+      for (int s = lane; s <= V.S; s += 64) {
+        unsigned long long probe = (unsigned long long)s << 32;
+        int lo = 0, hi = nkk;
+        while (lo < hi) { int mid = (lo + hi) >> 1; if (kc[mid] < probe) lo = mid + 1; else hi = mid; }
+        V.segst[(size_t)i * (V.S + 1) + s] = lo;
+      }
+    }
+  }
+  if (want & 1) {
+    int m = 1; while (m < nss) m <<= 1;
+    for (int e = nss + lane; e < m; e += 64) ks[e] = ~0ull;
+    __syncthreads();
+    bitonic_sort_lds(ks, m);
+    int *row = V.srow + (size_t)i * V.cap_s;
+    for (int e = lane; e < nss; e += 64) row[e] = (int)ks[e];
+    if (lane == 0) V.scnt[i] = nss;
+  }
+}
+
+// -------------------------------------------------------------- forces
+// MODE 0: -grad chi U over r < r_s (short rows); MODE 1: -grad U over r < r_c (full rows)
+template <int MODE, int SG>
+__global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restrict__ X) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / SG, lane = gid % SG;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  if (i < V.n) {
+    const double4 xi = X[i];
+    const int a = V.type[i], r = V.rep[i];
+    const double L0 = V.box[3 * r], L1 = V.box[3 * r + 1], L2 = V.box[3 * r + 2];
+    const double iL0 = 1.0 / L0, iL1 = 1.0 / L1, iL2 = 1.0 / L2;
+    const int *row = MODE == 0 ? V.srow + (size_t)i * V.cap_s : V.frow + (size_t)i * V.cap_f;
+    const int cnt = MODE == 0 ? V.scnt[i] : V.fcnt[i];
+    const double cut = MODE == 0 ? V.rs : V.rc;
+    const double cut2 = cut * cut;
+    for (int k = lane; k < cnt; k += SG) {
+      const int j = row[k];
+      const double4 xj = X[j];
+      double dx = min_img(xi.x - xj.x, L0, iL0);
+      double dy = min_img(xi.y - xj.y, L1, iL1);
+      double dz = min_img(xi.z - xj.z, L2, iL2);
+      double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < cut2) {
+        double rr = sqrt(r2);
+        int ab = a * V.nt + V.type[j];
+        double U = 0.0, dU = 0.0;
+        double c12 = V.c12[ab], c6 = V.c6[ab];
+        if (c12 != 0.0 || c6 != 0.0) lj_pair(r2, rr, c12, c6, V.ljshift[ab], U, dU);
+        double qq = xi.w * xj.w;
+        if (qq != 0.0) {
+          double Uc, dUc;
+          dsf_pair(rr, V.ke * qq, V, Uc, dUc);
+          U += Uc; dU += dUc;
+        }
+        double g = dU;
+        if (MODE == 0) {
+          double chi, dchi;
+          switch_fn(rr, V, chi, dchi);
+          g = chi * dU + dchi * U;
+        }
+        double s = -g / rr;
+        fx += s * dx; fy += s * dy; fz += s * dz;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = SG / 2; off > 0; off >>= 1) {
+    fx += __shfl_xor(fx, off, SG);
+    fy += __shfl_xor(fy, off, SG);
+    fz += __shfl_xor(fz, off, SG);
+  }
+  if (i < V.n && lane == 0) V.fnb[i] = make_double4(fx, fy, fz, 0.0);
+}
+
+// bonds (k/2)(b-b0)^2 and angles (k/2)(theta-theta0)^2, per atom over incident terms
+__global__ void k_bonded(MDView V, const double4 *__restrict__ X) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V.n) return;
+  const int r = V.rep[i];
+  const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+  const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int e = V.bptr[i]; e < V.bptr[i + 1]; ++e) {
+    int code = V.bterm[e], t = code >> 1;
+    if (!(code & 1)) {
+      int p = V.bond_ij[2 * t], q = V.bond_ij[2 * t + 1];
+      double4 xp = X[p], xq = X[q];
+      double d[3] = {min_img(xp.x - xq.x, L[0], iL[0]), min_img(xp.y - xq.y, L[1], iL[1]),
+                     min_img(xp.z - xq.z, L[2], iL[2])};
+      double b = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      double db = b - V.bond_r0[t];
+      double sgn = (i == p) ? 1.0 : -1.0;
+      for (int c = 0; c < 3; ++c) f[c] += sgn * (-V.bond_k[t] * db * d[c] / b);
+    } else {
+      int p = V.angle_ijk[3 * t], m = V.angle_ijk[3 * t + 1], q = V.angle_ijk[3 * t + 2];
+      double4 xp = X[p], xm = X[m], xq = X[q];
+      double u[3] = {min_img(xp.x - xm.x, L[0], iL[0]), min_img(xp.y - xm.y, L[1], iL[1]),
+                     min_img(xp.z - xm.z, L[2], iL[2])};
+      double w[3] = {min_img(xq.x - xm.x, L[0], iL[0]), min_img(xq.y - xm.y, L[1], iL[1]),
+                     min_img(xq.z - xm.z, L[2], iL[2])};
+      double ru = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      double rw = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+      double cs = (u[0] * w[0] + u[1] * w[1] + u[2] * w[2]) / (ru * rw);
+      cs = fmin(1.0, fmax(-1.0, cs));
+      double th = acos(cs), sn = sqrt(1.0 - cs * cs);
+      double dUdth = V.angle_k[t] * (th - V.angle_t0[t]);
+      for (int c = 0; c < 3; ++c) {
+        double fi = dUdth * (w[c] / (ru * rw) - cs * u[c] / (ru * ru)) / sn;
+        double fk = dUdth * (u[c] / (ru * rw) - cs * w[c] / (rw * rw)) / sn;
+        if (i == p) f[c] += fi;
+        else if (i == q) f[c] += fk;
+        else f[c] -= fi + fk;
+      }
+    }
+  }
+  V.fb[i] = make_double4(f[0], f[1], f[2], 0.0);
+}
+
+// --------------------------------------------------------- observables
+__global__ __launch_bounds__(256) void k_ke(MDView V, double *part) {
+  __shared__ double sm[256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0.0;
+  if (i < V.n) {
+    double4 v = V.v[i];
+    e = 0.5 * v.w * (v.x * v.x + v.y * v.y + v.z * v.z);
+  }
+  sm[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+// per-atom pair energies: which = 0 -> chi U from short rows, 1 -> (1-chi) U
+// from candidate rows, 2 -> both parts from full rows; halves of each pair.
+__global__ void k_pair_energy(MDView V, const double4 *__restrict__ X, int which, double *es, double *el) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V.n) return;
+  const double4 xi = X[i];
+  const int a = V.type[i], r = V.rep[i];
+  const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+  const int *row; int cnt;
+  if (which == 0) { row = V.srow + (size_t)i * V.cap_s; cnt = V.scnt[i]; }
+  else if (which == 1) { row = V.crow + (size_t)i * V.cap_c; cnt = V.ccnt[i]; }
+  else { row = V.frow + (size_t)i * V.cap_f; cnt = V.fcnt[i]; }
+  double s = 0.0, l = 0.0;
+  for (int k = 0; k < cnt; ++k) {
+    int j = row[k];
+    double4 xj = X[j];
+    double dx = min_img(xi.x - xj.x, L[0], 1.0 / L[0]);
+    double dy = min_img(xi.y - xj.y, L[1], 1.0 / L[1]);
+    double dz = min_img(xi.z - xj.z, L[2], 1.0 / L[2]);
+    double r2 = dx * dx + dy * dy + dz * dz, rr = sqrt(r2);
+    if (rr >= V.rc) continue;
+    int ab = a * V.nt + V.type[j];
+    double U = 0.0, dU = 0.0;
+    if (V.c12[ab] != 0.0 || V.c6[ab] != 0.0) lj_pair(r2, rr, V.c12[ab], V.c6[ab], V.ljshift[ab], U, dU);
+    double qq = xi.w * xj.w;
+    if (qq != 0.0) { double Uc, dUc; dsf_pair(rr, V.ke * qq, V, Uc, dUc); U += Uc; }
+    double chi, dchi;
+    switch_fn(rr, V, chi, dchi);
+    if (which == 0 || which == 2) s += 0.5 * chi * U;
+    if (which == 1 || which == 2) l += 0.5 * (1.0 - chi) * U;
+  }
+  es[i] = s; el[i] = l;
+}
+
+// bonded energy per term: bonds occupy [0, nb), angles [nb, nb + na)
+__global__ void k_bonded_energy(MDView V, const double4 *__restrict__ X, int nb, int na, double *e) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb + na) return;
+  if (t < nb) {
+    int p = V.bond_ij[2 * t], q = V.bond_ij[2 * t + 1];
+    const int r = V.rep[p];
+    double4 xp = X[p], xq = X[q];
+    double d[3] = {min_img(xp.x - xq.x, V.box[3 * r], 1.0 / V.box[3 * r]),
+                   min_img(xp.y - xq.y, V.box[3 * r + 1], 1.0 / V.box[3 * r + 1]),
+                   min_img(xp.z - xq.z, V.box[3 * r + 2], 1.0 / V.box[3 * r + 2])};
+    double b = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - V.bond_r0[t];
+    e[t] = 0.5 * V.bond_k[t] * b * b;
+  } else {
+    int a = t - nb;
+    int p = V.angle_ijk[3 * a], m = V.angle_ijk[3 * a + 1], q = V.angle_ijk[3 * a + 2];
+    const int r = V.rep[m];
+    double4 xp = X[p], xm = X[m], xq = X[q];
+    double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+    double u[3] = {min_img(xp.x - xm.x, L[0], 1.0 / L[0]), min_img(xp.y - xm.y, L[1], 1.0 / L[1]),
+                   min_img(xp.z - xm.z, L[2], 1.0 / L[2])};
+    double w[3] = {min_img(xq.x - xm.x, L[0], 1.0 / L[0]), min_img(xq.y - xm.y, L[1], 1.0 / L[1]),
+                   min_img(xq.z - xm.z, L[2], 1.0 / L[2])};
+    double cs = (u[0] * w[0] + u[1] * w[1] + u[2] * w[2]) /
+                (sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]));
+    cs = fmin(1.0, fmax(-1.0, cs));
+    double dth = acos(cs) - V.angle_t0[a];
+    e[t] = 0.5 * V.angle_k[a] * dth * dth;
+  }
+}
+
+__global__ void k_rdf(MDView V, const double4 *__restrict__ X, const int *rep_off, int ta, int tb,
+                      double rmax, int nbins, unsigned long long *hist) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V.n) return;
+  const int a = V.type[i];
+  if (a != ta && a != tb) return;
+  const int r = V.rep[i];
+  const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+  const double4 xi = X[i];
+  const double dr = rmax / nbins;
+  for (int j = i + 1; j < rep_off[r + 1]; ++j) {
+    int b = V.type[j];
+    if (!((a == ta && b == tb) || (a == tb && b == ta))) continue;
+    double4 xj = X[j];
+    double dx = min_img(xi.x - xj.x, L[0], 1.0 / L[0]);
+    double dy = min_img(xi.y - xj.y, L[1], 1.0 / L[1]);
+    double dz = min_img(xi.z - xj.z, L[2], 1.0 / L[2]);
+    double rr = sqrt(dx * dx + dy * dy + dz * dz);
+    if (rr >= rmax) continue;
+    int bin = (int)(rr / dr);
+    if (bin < nbins) atomicAdd(&hist[bin], 1ull);
+  }
+}
+
+// unordered pairs (j > i) of the given rows closer than cut: which 0 = short rows, 1 = full rows
+__global__ void k_count_pairs(MDView V, const double4 *__restrict__ X, int which, double cut,
+                              unsigned long long *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V.n) return;
+  const double4 xi = X[i];
+  const int r = V.rep[i];
+  const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+  const int *row = which == 0 ? V.srow + (size_t)i * V.cap_s : V.frow + (size_t)i * V.cap_f;
+  const int cnt = which == 0 ? V.scnt[i] : V.fcnt[i];
+  unsigned long long c = 0;
+  for (int k = 0; k < cnt; ++k) {
+    int j = row[k];
+    if (j <= i) continue;
+    double4 xj = X[j];
+    double dx = min_img(xi.x - xj.x, L[0], 1.0 / L[0]);
+    double dy = min_img(xi.y - xj.y, L[1], 1.0 / L[1]);
+    double dz = min_img(xi.z - xj.z, L[2], 1.0 / L[2]);
+    if (dx * dx + dy * dy + dz * dz < cut * cut) ++c;
+  }
+  if (c) atomicAdd(out, c);
+}
+
+// ------------------------------------------------------------- launchers
+#define CHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
+
+hipError_t launch_local(const MDView &V, const MDProg &P, const double4 *Xs, double4 *Xd, hipStream_t s) {
+  int nb = (V.n + 63) / 64;
+  if (V.S <= 4) hipLaunchKernelGGL((k_local<4>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd);
+  else if (V.S <= 8) hipLaunchKernelGGL((k_local<8>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd);
+  else if (V.S <= 16) hipLaunchKernelGGL((k_local<16>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd);
+  else hipLaunchKernelGGL((k_local<32>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd);
+  return hipGetLastError();
+}
+
+hipError_t launch_rebuild(const MDView &V, const double4 *X, int want, int slot, int forced, int autob,
+                          double thr2, int pc, int ps, bool check_only, int count, hipStream_t s) {
+  int nb = (V.n + 255) / 256;
+  hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(256), 0, s, V, X, slot, forced, autob, thr2);
+  CHK(hipGetLastError());
+  if (check_only) return hipSuccess;
+  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, V, slot, forced, autob, thr2, count);
+  CHK(hipGetLastError());
+  hipLaunchKernelGGL(k_cell_scatter, dim3(nb), dim3(256), 0, s, V, slot, forced, autob, thr2);
+  CHK(hipGetLastError());
+  size_t lds = sizeof(unsigned long long) * (size_t)(pc + ps);
+  hipLaunchKernelGGL(k_build, dim3(V.n), dim3(64), lds, s, V, X, want, slot, forced, autob, thr2, pc, ps);
+  return hipGetLastError();
+}
+
+hipError_t launch_force(const MDView &V, const double4 *X, int mode, hipStream_t s) {
+  if (mode == 0) {
+    const int SG = 8;
+    int nb = (int)(((long long)V.n * SG + 255) / 256);
+    hipLaunchKernelGGL((k_force<0, 8>), dim3(nb), dim3(256), 0, s, V, X);
+    (void)SG;
+  } else {
+    const int SG = 16;
+    int nb = (int)(((long long)V.n * SG + 255) / 256);
+    hipLaunchKernelGGL((k_force<1, 16>), dim3(nb), dim3(256), 0, s, V, X);
+    (void)SG;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bonded(const MDView &V, const double4 *X, hipStream_t s) {
+  int nb = (V.n + 255) / 256;
+  hipLaunchKernelGGL(k_bonded, dim3(nb), dim3(256), 0, s, V, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_ke(const MDView &V, double *part, int *nblocks, hipStream_t s) {
+  int nb = (V.n + 255) / 256;
+  *nblocks = nb;
+  hipLaunchKernelGGL(k_ke, dim3(nb), dim3(256), 0, s, V, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_energy(const MDView &V, const double4 *X, int which, double *es, double *el,
+                              hipStream_t s) {
+  int nb = (V.n + 255) / 256;
+  hipLaunchKernelGGL(k_pair_energy, dim3(nb), dim3(256), 0, s, V, X, which, es, el);
+  return hipGetLastError();
+}
+
+hipError_t launch_bonded_energy(const MDView &V, const double4 *X, int nb, int na, double *e, hipStream_t s) {
+  int nt = nb + na;
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bonded_energy, dim3((nt + 255) / 256), dim3(256), 0, s, V, X, nb, na, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_pairs(const MDView &V, const double4 *X, int which, double cut, unsigned long long *out,
+                              hipStream_t s) {
+  int nb = (V.n + 255) / 256;
+  hipLaunchKernelGGL(k_count_pairs, dim3(nb), dim3(256), 0, s, V, X, which, cut, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rdf(const MDView &V, const double4 *X, const int *rep_off, int ta, int tb, double rmax,
+                      int nbins, unsigned long long *hist, hipStream_t s) {
+  int nb = (V.n + 255) / 256;
+  hipLaunchKernelGGL(k_rdf, dim3(nb), dim3(256), 0, s, V, X, rep_off, ta, tb, rmax, nbins, hist);
+  return hipGetLastError();
+}

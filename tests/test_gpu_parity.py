@@ -1,0 +1,145 @@
+"""GPU (HIP) path against the CPU FP64 oracle on the same seeded inputs.
+
+Integer outputs (candidate rows, jump counts, accepted (step, phase, i, j)
+events, per-atom hashes) must match exactly; FP64 state within 1e-9 relative
+(different summation order, libm vs device math; see the FP64 tolerance
+derivation in the design doc).
+"""
+import numpy as np
+import pytest
+
+from paper_2412_15073_amd import systems as S
+from tests.helpers import lj_small, lj_c1, water_small, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def jm():
+    from paper_2412_15073_amd import jumpmd
+    jumpmd.load()
+    return jumpmd
+
+
+def _pair(jm, system, split, params):
+    from oracle.oracle import OracleSim
+    return jm.Sim(system, split, params), OracleSim(system, split, params)
+
+
+def _compare_state(g, o, tol=TOL):
+    xg, vg = g.state()
+    xo, vo = o.state()
+    assert rel_err(xg, xo) < tol, rel_err(xg, xo)
+    assert rel_err(vg, vo) < tol, rel_err(vg, vo)
+
+
+def _compare_stats(g, o):
+    sg, so = g.atom_stats(), o.atom_stats()
+    for k in ("n_prop", "n_acc", "hash"):
+        np.testing.assert_array_equal(sg[k], so[k], err_msg=k)
+
+
+def test_forces_lj(jm):
+    sy, sp = lj_small()
+    g, o = _pair(jm, sy, sp, S.lj_params())
+    from oracle.oracle import F_SHORT, F_FULL
+    assert rel_err(g.accel(0), o.accel(F_SHORT)) < 1e-12
+    assert rel_err(g.accel(1), o.accel(F_FULL)) < 1e-12
+
+
+def test_forces_water(jm):
+    sy, sp = water_small()
+    g, o = _pair(jm, sy, sp, S.water_params())
+    from oracle.oracle import F_SHORT, F_FULL, F_BONDED
+    assert rel_err(g.accel(0), o.accel(F_SHORT)) < 1e-12
+    assert rel_err(g.accel(1), o.accel(F_FULL)) < 1e-12
+    assert rel_err(g.accel(2), o.accel(F_BONDED)) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["lj", "water"])
+def test_candidate_rows(jm, case):
+    sy, sp = lj_small() if case == "lj" else water_small()
+    pa = S.lj_params() if case == "lj" else S.water_params()
+    g, o = _pair(jm, sy, sp, pa)
+    o.build_lists()
+    S_ = o.n_segments
+    for i in range(sy.n_atoms):
+        jg, sg = g.cand_row(i, S_)
+        np.testing.assert_array_equal(jg, o.cand_row(i), err_msg=f"row {i}")
+        np.testing.assert_array_equal(sg, o.seg_start(i), err_msg=f"segments {i}")
+
+
+def test_jump_lj_trajectory(jm):
+    sy, sp = lj_small()
+    pa = S.lj_params()
+    pa.log_events = 1
+    g, o = _pair(jm, sy, sp, pa)
+    for _ in range(4):
+        g.step_jump(25)
+        o.step_jump(25)
+        _compare_state(g, o)
+    _compare_stats(g, o)
+    eg, eo = g.events(), o.events()
+    np.testing.assert_array_equal(eg, eo)
+    assert g.observables()["n_rebuilds"] == o.n_rebuilds
+    assert o.atom_stats()["n_acc"].sum() > 0
+
+
+def test_jump_water_trajectory(jm):
+    sy, sp = water_small()
+    pa = S.water_params()
+    pa.log_events = 1
+    g, o = _pair(jm, sy, sp, pa)
+    for _ in range(2):
+        g.step_jump(10)
+        o.step_jump(10)
+        _compare_state(g, o)
+    _compare_stats(g, o)
+    np.testing.assert_array_equal(g.events(), o.events())
+    assert g.observables()["event_hash"] == o.event_hash()
+
+
+def test_baoab_trajectory(jm):
+    sy, sp = water_small()
+    pa = S.water_params(jumps=False)
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_baoab(20)
+    o.step_baoab(20)
+    _compare_state(g, o)
+    assert g.observables()["n_rebuilds"] == o.n_rebuilds
+
+
+def test_jump_respa_trajectory(jm):
+    sy, sp = water_small()
+    pa = S.water_params()
+    pa.respa_inner = 3
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_jump_respa(6)
+    o.step_jump_respa(6)
+    _compare_state(g, o)
+    _compare_stats(g, o)
+
+
+def test_baoab_respa_trajectory(jm):
+    sy, sp = water_small()
+    pa = S.water_params(jumps=False)
+    pa.respa_inner = 3
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_baoab_respa(6)
+    o.step_baoab_respa(6)
+    _compare_state(g, o)
+
+
+def test_lj_full_size_100_steps(jm):
+    """864-atom LJ workload, 100 steps: exact events, 1e-9 state."""
+    sy, sp = lj_c1()
+    pa = S.lj_params()
+    pa.log_events = 1
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_jump(100)
+    o.step_jump(100)
+    _compare_state(g, o)
+    _compare_stats(g, o)
+    np.testing.assert_array_equal(g.events(), o.events())
