@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-baoab", action="store_true")
+    ap.add_argument("--chain-lanes", type=int, default=0, help="lanes per atom in the jump chains (0 = auto)")
+    ap.add_argument("--graph-steps", type=int, default=0, help="steps per replayed HIP graph (0 = plain launches)")
     return ap.parse_args()
 
 
@@ -90,6 +92,8 @@ def main():
 
     # JUMP (C' J' A O A J' C'), FP64
     pj = S.water_params(eps0_per_kcal=a.eps0)
+    pj.chain_lanes = a.chain_lanes
+    pj.graph_steps = a.graph_steps
     js = jumpmd.Sim(sysm, split, pj)
     p0 = js.proposals_total()
     dt_j, prof_j = timed(js, js.step_jump, a.steps, a.warmup)
@@ -111,6 +115,7 @@ def main():
     prof_b = None
     if not a.no_baoab:
         pb = S.water_params(jumps=False)
+        pb.graph_steps = a.graph_steps
         bs = jumpmd.Sim(sysm, split, pb)
         dt_b, prof_b = timed(bs, bs.step_baoab, a.steps, a.warmup)
         jumpmd.load().md_counters(bs._h, C.byref(pl), C.byref(pt))
@@ -171,7 +176,8 @@ def main():
         "config": {"workload": f"water_{a.n_mol}mol_jump_fp64", "n_atoms": sysm.n_atoms,
                    "box_A": round(float(sysm.box[0]), 3), "r_s": 5.0, "r_c": 10.0, "switch": 1.0,
                    "skin": a.skin, "rings": a.rings, "dt_fs": 1.0, "gamma_per_ps": 1.0, "T_K": 300,
-                   "eps0_per_kcal_mol_A": a.eps0, "jumps": "LJ BPS + Coulomb adaptive MRZ"},
+                   "eps0_per_kcal_mol_A": a.eps0, "jumps": "LJ BPS + Coulomb adaptive MRZ",
+                   "chain_lanes": a.chain_lanes, "graph_steps": a.graph_steps},
         "baoab_full_ns_per_day": ns_day_b, "baoab_full_ms_per_step": ms_b,
         "jump_speedup_vs_baoab": (ns_day_j / ns_day_b) if ns_day_b else None,
         "pair_interactions_per_s": {

@@ -111,6 +111,11 @@ typedef struct {
   int32_t respa_inner;  /* inner steps per outer step of the RESPA schemes (>= 1) */
   int32_t log_events;   /* 1: record every accepted jump for md_get_events */
   int32_t strict_bounds;/* 1: an acceptance probability > 1 makes the next sync fail with MD_ERR_BOUND */
+  int32_t chain_lanes;  /* lanes per atom in the jump chains: 0 = automatic, or 1, 2, 4, 8, 16
+                           (results do not depend on it) */
+  int32_t graph_steps;  /* 0: launch kernels step by step; K > 0 (even): md_step_jump and
+                           md_step_baoab replay a captured HIP graph of K steps (needs
+                           rebuild_every == 0; results do not depend on it) */
 } md_params;
 
 typedef struct {

@@ -55,6 +55,11 @@ struct md_ctx {
   std::string err;
   bool prof = false;
   Timer tm;
+  bool own_stream = false;
+  // graph replay of K-step chunks (JUMP / BAOAB x current position buffer)
+  bool capturing = false;
+  int64_t step_rel0 = 0;
+  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
   // host copies of device-side counters at the last sync
   MDCtl ctl_host{};
 };
@@ -88,7 +93,7 @@ static double4 *Xcur(md_ctx *c) { return c->cur == 0 ? c->V.x0 : c->V.x1; }
 static double4 *Xoth(md_ctx *c) { return c->cur == 0 ? c->V.x1 : c->V.x0; }
 
 static void prof_begin(md_ctx *c, int kid, hipEvent_t *e0) {
-  if (!c->prof) return;
+  if (!c->prof || c->capturing) return;
   Timer &t = c->tm;
   if (t.next + 2 > t.pool.size()) {
     for (int q = 0; q < 256; ++q) {
@@ -103,7 +108,7 @@ static void prof_begin(md_ctx *c, int kid, hipEvent_t *e0) {
 }
 
 static void prof_end(md_ctx *c, int kid, hipEvent_t e0) {
-  if (!c->prof) return;
+  if (!c->prof || c->capturing) return;
   Timer &t = c->tm;
   hipEvent_t e1 = t.pool[t.next++];
   hipEventRecord(e1, c->stream);
@@ -207,6 +212,11 @@ static void add_disp(ProgBuilder &b, int slot) {
 static int run_prog(md_ctx *c, ProgBuilder &b) {
   if (b.P.nops == 0) return MD_OK;
   if (b.has_chain_after_a) return fail(c, MD_ERR_ARG, "internal: jump chain after drift");
+  if (c->capturing) {
+    // step words become offsets from the device-side base set before each replay
+    b.P.dev_step = 1;
+    for (int o = 0; o < b.P.nops; ++o) b.P.ops[o].step -= c->step_rel0;
+  }
   hipEvent_t e0{};
   prof_begin(c, MD_K_LOCAL, &e0);
   double4 *dst = b.has_a ? Xoth(c) : nullptr;
@@ -326,7 +336,8 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
   if (p->jump_coul != MD_JUMP_NONE && p->jump_coul != MD_JUMP_MRZ_CONST && p->jump_coul != MD_JUMP_MRZ_ADAPTIVE)
     return fail(nullptr, MD_ERR_ARG, "jump_coul must be NONE, MRZ_CONST or MRZ_ADAPTIVE");
   if (p->jump_coul != MD_JUMP_NONE && !(p->eps > 0.0)) return fail(nullptr, MD_ERR_ARG, "eps must be > 0");
-  if (p->precision != MD_FP64) return fail(nullptr, MD_ERR_ARG, "precision: only MD_FP64 in this build");
+  if (p->precision != MD_FP64 && p->precision != MD_FP32_MIXED)
+    return fail(nullptr, MD_ERR_ARG, "precision must be MD_FP64 or MD_FP32_MIXED");
   if (s->n_types * std::max(1, sp->n_rings) > 32)
     return fail(nullptr, MD_ERR_ARG, "n_types * n_rings must be <= 32");
   for (int r = 0; r < s->n_replicas; ++r)
@@ -350,8 +361,17 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   *out = nullptr;
   int rc = validate(s, sp, p);
   if (rc) return rc;
+  if (p->graph_steps < 0 || (p->graph_steps & 1)) return fail(nullptr, MD_ERR_ARG, "graph_steps must be 0 or even");
   md_ctx *c = new md_ctx();
   c->stream = (hipStream_t)stream;
+  if (!c->stream) {
+    // graphs cannot be captured on the legacy default stream: use a private one
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(nullptr, MD_ERR_HIP, "hipStreamCreateWithFlags failed");
+    }
+    c->own_stream = true;
+  }
   c->n = s->n_atoms;
   c->nt = s->n_types;
   c->nrep = s->n_replicas;
@@ -380,6 +400,16 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.beta = 1.0 / p->kT; V.kT = p->kT; V.eps0 = p->eps;
   V.jlj = p->jump_lj; V.jc = p->jump_coul; V.log_events = p->log_events; V.precision = p->precision;
   V.seed = p->seed;
+  {
+    // enough lanes to fill the device (~64k lanes in flight) when atoms are few
+    int g = p->chain_lanes;
+    if (g <= 0) {
+      g = 1;
+      while (g < 16 && (long long)n * g * 2 <= 65536) g *= 2;
+    }
+    if (g != 1 && g != 2 && g != 4 && g != 8 && g != 16) { delete c; return fail(nullptr, MD_ERR_ARG, "chain_lanes must be 0, 1, 2, 4, 8 or 16"); }
+    V.chain_lanes = g;
+  }
 
   // --- host tables
   std::vector<double> c12(nt * nt), c6(nt * nt), shift(nt * nt), ell_lj(nt * nt * nr), ell_cu(nt * nt * nr), qmax(nt, 0.0);
@@ -416,7 +446,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
     qmax[s->type[i]] = std::max(qmax[s->type[i]], q);
   }
 
-  // --- cells per replica: edge >= r_c + skin
+  // --- cells per replica: edge >= (r_c + skin)/2, searched with a 5x5x5 stencil
   std::vector<int> cdim(3 * nrep), coff(nrep + 1, 0);
   double rho_max = 0.0;
   int nrep_max = 0;
@@ -424,7 +454,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
     double vol = 1.0;
     for (int d = 0; d < 3; ++d) {
       double L = c->box[3 * r + d];
-      cdim[3 * r + d] = std::max(1, (int)std::floor(L / V.rout));
+      cdim[3 * r + d] = std::max(1, (int)std::floor(L / (0.5 * V.rout)));
       vol *= L;
     }
     coff[r + 1] = coff[r] + cdim[3 * r] * cdim[3 * r + 1] * cdim[3 * r + 2];
@@ -444,7 +474,11 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   auto pow2 = [](int x) { int m = 1; while (m < x) m <<= 1; return m; };
   c->pc = pow2(std::max(V.cap_c, V.cap_f));
   c->ps = pow2(V.cap_s);
-  if (c->pc > 4096 || c->ps > 2048) {
+  if (n >= (1 << 24)) {
+    delete c;
+    return fail(nullptr, MD_ERR_ARG, "at most 2^24 - 1 atoms (24-bit atom field of the row sort keys)");
+  }
+  if (c->pc > 8192 || c->ps > 4096) {
     delete c;
     return fail(nullptr, MD_ERR_ARG, "neighbour rows too long for the LDS row builder (density * (r_c + skin)^3 too large)");
   }
@@ -497,6 +531,9 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   A(d_bij, std::max(1, 2 * s->n_bonds)); A(d_bk, std::max(1, s->n_bonds)); A(d_br0, std::max(1, s->n_bonds));
   A(d_aijk, std::max(1, 3 * s->n_angles)); A(d_ak, std::max(1, s->n_angles)); A(d_at0, std::max(1, s->n_angles));
   A(V.cell_count, V.ncell_total); A(V.cell_start, V.ncell_total + 1); A(V.cell_atoms, n);
+  A(V.cell_tmp, V.ncell_total); A(V.rep_maxd2, 2 * nrep); A(V.xcell, n);
+  int *d_cell_rep;
+  A(d_cell_rep, V.ncell_total);
   A(V.atom_cell, n); A(V.atom_slot, n);
   A(V.srow, (size_t)n * V.cap_s); A(V.scnt, n);
   A(V.frow, (size_t)n * V.cap_f); A(V.fcnt, n);
@@ -545,6 +582,13 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   up(d_ak, s->angle_k, sizeof(double) * s->n_angles);
   up(d_at0, s->angle_t0, sizeof(double) * s->n_angles);
   up(c->d_rep_off, c->rep_off.data(), sizeof(int) * (nrep + 1));
+  {
+    std::vector<int> cr(V.ncell_total);
+    for (int r = 0; r < nrep; ++r)
+      for (int q = coff[r]; q < coff[r + 1]; ++q) cr[q] = r;
+    up(d_cell_rep, cr.data(), sizeof(int) * V.ncell_total);
+  }
+  if (hipMemsetAsync(V.rep_maxd2, 0, sizeof(unsigned long long) * 2 * nrep, st) != hipSuccess) ok = false;
   if (hipMemsetAsync(V.cell_count, 0, sizeof(int) * V.ncell_total, st) != hipSuccess) ok = false;
   if (hipMemsetAsync(V.ctl, 0, sizeof(MDCtl), st) != hipSuccess) ok = false;
   if (hipMemsetAsync(V.nprop, 0, sizeof(long long) * n, st) != hipSuccess) ok = false;
@@ -566,6 +610,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.bond_ij = d_bij; V.bond_k = d_bk; V.bond_r0 = d_br0;
   V.angle_ijk = d_aijk; V.angle_k = d_ak; V.angle_t0 = d_at0;
   V.rep_cell_off = d_coff; V.rep_cdim = d_cdim;
+  V.cell_rep = d_cell_rep; V.rep_off = c->d_rep_off;
   c->cur = 0;
   c->fkind = -1;
   c->fb_valid = false;
@@ -581,6 +626,8 @@ extern "C" void md_destroy(md_ctx *c) {
   for (void *p : c->allocs) hipFree(p);
   if (c->d_hist) hipFree(c->d_hist);
   for (hipEvent_t e : c->tm.pool) hipEventDestroy(e);
+  for (auto &g : c->gexec) if (g) hipGraphExecDestroy(g);
+  if (c->own_stream) hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -589,8 +636,7 @@ extern "C" const char *md_last_error(const md_ctx *c) {
 }
 
 // -------------------------------------------------------------- stepping
-extern "C" int md_step_baoab(md_ctx *c, int64_t nsteps) {
-  if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
+static int baoab_plain(md_ctx *c, int64_t nsteps) {
   int rc = ensure_forces(c, MODE_BAOAB);
   if (rc) return rc;
   const double h = 0.5 * c->par.dt;
@@ -613,8 +659,7 @@ extern "C" int md_step_baoab(md_ctx *c, int64_t nsteps) {
   return MD_OK;
 }
 
-extern "C" int md_step_jump(md_ctx *c, int64_t nsteps) {
-  if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
+static int jump_plain(md_ctx *c, int64_t nsteps) {
   int rc = ensure_forces(c, MODE_JUMP);
   if (rc) return rc;
   const double h = 0.5 * c->par.dt;
@@ -640,6 +685,64 @@ extern "C" int md_step_jump(md_ctx *c, int64_t nsteps) {
     c->step++;
   }
   return MD_OK;
+}
+
+// Replay whole K-step chunks from a captured graph (captured lazily per
+// scheme and position-buffer parity); the random-stream step base is set on
+// the device before each replay. Steps left over run kernel by kernel.
+static int graph_chunks(md_ctx *c, int mode, int64_t &n) {
+  const int K = c->par.graph_steps;
+  if (K <= 0 || c->par.rebuild_every > 0 || n < K) return MD_OK;
+  int (*plain)(md_ctx *, int64_t) = mode == MODE_JUMP ? jump_plain : baoab_plain;
+  int rc;
+  if (c->step & 1) {            // chunks start on even steps (displacement-slot parity)
+    if ((rc = plain(c, 1))) return rc;
+    n -= 1;
+    if (n < K) return MD_OK;
+  }
+  if ((rc = ensure_forces(c, mode))) return rc;
+  const int key = (mode == MODE_JUMP ? 0 : 2) + c->cur;
+  if (!c->gexec[key]) {
+    const int64_t step0 = c->step;
+    const int cur0 = c->cur, fk0 = c->fkind, rows0 = c->rows_valid;
+    const bool fb0 = c->fb_valid;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    c->step_rel0 = step0;
+    rc = plain(c, K);
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->step = step0; c->cur = cur0; c->fkind = fk0; c->rows_valid = rows0; c->fb_valid = fb0;
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(c, MD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->gexec[key], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { c->gexec[key] = nullptr; return fail(c, MD_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e)); }
+  }
+  while (n >= K) {
+    HIPCHK(c, launch_set_step(c->V.ctl, (long long)c->step, c->stream));
+    HIPCHK(c, hipGraphLaunch(c->gexec[key], c->stream));
+    c->step += K;
+    n -= K;
+  }
+  // a chunk ends with the forces and rows of this scheme current
+  c->fkind = mode == MODE_JUMP ? 0 : 1;
+  c->fb_valid = true;
+  c->rows_valid = rows_for_mode(mode);
+  return MD_OK;
+}
+
+extern "C" int md_step_baoab(md_ctx *c, int64_t nsteps) {
+  if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  int rc = graph_chunks(c, MODE_BAOAB, nsteps);
+  return rc ? rc : (nsteps > 0 ? baoab_plain(c, nsteps) : MD_OK);
+}
+
+extern "C" int md_step_jump(md_ctx *c, int64_t nsteps) {
+  if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  int rc = graph_chunks(c, MODE_JUMP, nsteps);
+  return rc ? rc : (nsteps > 0 ? jump_plain(c, nsteps) : MD_OK);
 }
 
 static int respa(md_ctx *c, int64_t n_outer, bool jump) {

@@ -76,12 +76,11 @@ struct MDProg {
   int nops;
   int disp_slot;   // slot written by OP_DISP
   int reset_slot;  // slot cleared by thread 0 (-1: none)
-  int pad;
+  int dev_step;    // 1: op.step is an offset from ctl->step_base (graph replays)
   MDOp ops[MD_MAX_OPS];
 };
 
 struct MDCtl {                       // device-side control words
-  unsigned long long maxd2[2];       // max |x - x_ref|^2 (double bits), per step parity
   int do_rebuild;
   int overflow_rows;                 // max row length requested beyond capacity
   unsigned long long n_rebuilds;
@@ -89,6 +88,7 @@ struct MDCtl {                       // device-side control words
   unsigned long long n_zs_overflow;
   unsigned long long n_events;
   unsigned long long nonfinite;
+  long long step_base;               // random-stream step of offset 0 in graph replays
 };
 
 struct MDEventDev { long long step; int phase, atom, partner, proposal; };
@@ -116,6 +116,11 @@ struct MDView {
   const int *rep_cell_off;              // [nrep+1]
   const int *rep_cdim;                  // [3*nrep]
   int *cell_count, *cell_start, *cell_atoms, *atom_cell, *atom_slot;
+  int *cell_tmp;                        // [ncell] scratch of the cell scan
+  double4 *xcell;                       // [n] build positions in cell order
+  const int *cell_rep;                  // [ncell] replica of each cell
+  const int *rep_off;                   // [nrep+1] first atom of each replica
+  unsigned long long *rep_maxd2;        // [2*nrep] max |x - x_ref|^2 (double bits) per step parity and replica
   int ncell_total;
   // neighbour rows (row-major, fixed capacity)
   int cap_s, cap_f, cap_c;
@@ -130,6 +135,7 @@ struct MDView {
   double dsf_erfc_rc_over_rc, dsf_fc, two_a_sqpi;
   double beta, kT, eps0;
   int jlj, jc, log_events, precision;
+  int chain_lanes;       // lanes cooperating on one atom's jump chain (1, 2, 4, 8, 16)
   uint64_t seed;
 };
 
@@ -162,6 +168,35 @@ __device__ __forceinline__ void switch_fn(double r, const MDView &V, double &chi
   double t = (r - V.rlo) / V.w;
   chi = 1.0 - t * t * t * (10.0 - 15.0 * t + 6.0 * t * t);
   dchi = -30.0 * t * t * (1.0 - t) * (1.0 - t) / V.w;
+}
+
+// FP32 variants (mixed-precision path): pair arithmetic in float, with the
+// constants of the run rounded once; accumulation stays in FP64.
+__device__ __forceinline__ void lj_pair_f(float r2, float r, float c12, float c6, float shift, float &U, float &dU) {
+  float ir2 = 1.0f / r2, ir6 = ir2 * ir2 * ir2;
+  U = ir6 * (c12 * ir6 - c6) - shift;
+  dU = (-12.0f * c12 * ir6 * ir6 + 6.0f * c6 * ir6) / r;
+}
+
+__device__ __forceinline__ void dsf_pair_f(float r, float kqq, const MDView &V, float &U, float &dU) {
+  const float alpha = (float)V.alpha;
+  float e = erfcf(alpha * r);
+  float g = __expf(-alpha * alpha * r * r);
+  U = kqq * (e / r - (float)V.dsf_erfc_rc_over_rc + (float)V.dsf_fc * (r - (float)V.rc));
+  dU = kqq * (-(e / (r * r) + (float)V.two_a_sqpi * g / r) + (float)V.dsf_fc);
+}
+
+__device__ __forceinline__ void switch_fn_f(float r, const MDView &V, float &chi, float &dchi) {
+  const float rlo = (float)V.rlo, rs = (float)V.rs, w = (float)V.w;
+  if (r <= rlo) { chi = 1.0f; dchi = 0.0f; return; }
+  if (r >= rs) { chi = 0.0f; dchi = 0.0f; return; }
+  float t = (r - rlo) / w;
+  chi = 1.0f - t * t * t * (10.0f - 15.0f * t + 6.0f * t * t);
+  dchi = -30.0f * t * t * (1.0f - t) * (1.0f - t) / w;
+}
+
+__device__ __forceinline__ float theta_fn_f(float eta) {
+  return eta * (0.5f * erfcf(-eta * 0.70710678f)) + __expf(-0.5f * eta * eta) * 0.39894228f;
 }
 
 // Theta(eta) = E[(eta+G)_+] = eta Phi(eta) + phi(eta)  (Sec. 2.2)

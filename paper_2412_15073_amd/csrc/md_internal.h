@@ -25,3 +25,4 @@ hipError_t launch_rdf(const MDView &V, const double4 *X, const int *rep_off, int
                       int nbins, unsigned long long *hist, hipStream_t s);
 hipError_t launch_count_pairs(const MDView &V, const double4 *X, int which, double cut, unsigned long long *out,
                               hipStream_t s);
+hipError_t launch_set_step(MDCtl *ctl, long long step, hipStream_t s);

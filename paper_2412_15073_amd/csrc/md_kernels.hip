@@ -24,8 +24,36 @@ __device__ __forceinline__ double seg_ell(const MDView &V, int a, int sg, int co
   return (absq * V.qmax[b]) * V.ell_cu[idx];
 }
 
+// long-range gradient in FP32 (mixed-precision path): displacement in FP64,
+// pair arithmetic in float, gradient returned in FP64
+__device__ __forceinline__ double long_grad_f(const MDView &V, double4 xi, double4 xj, int a, int b, int coul,
+                                              const double *L, const double *iL, double &Fx, double &Fy,
+                                              double &Fz) {
+  const float dx = (float)min_img(xi.x - xj.x, L[0], iL[0]);
+  const float dy = (float)min_img(xi.y - xj.y, L[1], iL[1]);
+  const float dz = (float)min_img(xi.z - xj.z, L[2], iL[2]);
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  const float r = sqrtf(r2);
+  float U = 0.0f, dU = 0.0f;
+  if (r < (float)V.rc) {
+    if (coul) {
+      const float qq = (float)(xi.w * xj.w);
+      if (qq != 0.0f) dsf_pair_f(r, (float)V.ke * qq, V, U, dU);
+    } else {
+      const int ab = a * V.nt + b;
+      const float c12 = (float)V.c12[ab], c6 = (float)V.c6[ab];
+      if (c12 != 0.0f || c6 != 0.0f) lj_pair_f(r2, r, c12, c6, (float)V.ljshift[ab], U, dU);
+    }
+  }
+  float chi, dchi;
+  switch_fn_f(r, V, chi, dchi);
+  const float g = ((1.0f - chi) * dU - dchi * U) / r;
+  Fx = (double)(g * dx); Fy = (double)(g * dy); Fz = (double)(g * dz);
+  return Fx * Fx + Fy * Fy + Fz * Fz;
+}
+
 // long-range gradient F_ij = grad_i (1 - chi) U_ij of one component (Sec. 3.1, 3.2)
-__device__ __forceinline__ double long_grad(const MDView &V, double4 xi, double4 xj, int a, int b,
+__device__ __forceinline__ double long_grad_d(const MDView &V, double4 xi, double4 xj, int a, int b,
                                             int coul, const double *L, const double *iL,
                                             double &Fx, double &Fy, double &Fz) {
   double dx = min_img(xi.x - xj.x, L[0], iL[0]);
@@ -51,6 +79,16 @@ __device__ __forceinline__ double long_grad(const MDView &V, double4 xi, double4
   return Fx * Fx + Fy * Fy + Fz * Fz;
 }
 
+__device__ __forceinline__ double long_grad(const MDView &V, double4 xi, double4 xj, int a, int b, int coul,
+                                            const double *L, const double *iL, double &Fx, double &Fy, double &Fz) {
+  if (V.precision == MD_FP32_MIXED) return long_grad_f(V, xi, xj, a, b, coul, L, iL, Fx, Fy, Fz);
+  return long_grad_d(V, xi, xj, a, b, coul, L, iL, Fx, Fy, Fz);
+}
+
+__device__ __forceinline__ double theta_p(const MDView &V, double eta) {
+  return V.precision == MD_FP32_MIXED ? (double)theta_fn_f((float)eta) : theta_fn(eta);
+}
+
 struct AtomStats { long long nprop, nacc, nviol; uint64_t hash; };
 
 __device__ __forceinline__ void log_jump(const MDView &V, AtomStats &st, int64_t step, int phase,
@@ -70,30 +108,37 @@ __device__ __forceinline__ void log_jump(const MDView &V, AtomStats &st, int64_t
   }
 }
 
+// the part of log_jump every lane of a group repeats (replicated statistics)
+__device__ __forceinline__ void log_jump_hash_only(const MDView &V, AtomStats &st, int64_t step, int phase, int j) {
+  uint64_t h = st.hash;
+  h = fnv1a_u64(h, (uint64_t)step, 8);
+  h = fnv1a_u64(h, (uint64_t)(uint32_t)phase, 4);
+  h = fnv1a_u64(h, (uint64_t)(uint32_t)V.loc[j], 4);
+  st.hash = h;
+  st.nacc++;
+}
+
 // Segment tables of one atom for one jump component, in registers: counts,
 // bounds, cumulative weights sum n_q l_q and cumulative counts of segments
 // with a nonzero bound (candidates whose rate can be > 0).
 template <int SMAX>
 struct SegTab {
   double ell[SMAX], cumW[SMAX];
-  int st[SMAX], ns[SMAX], cumN[SMAX];
+  int st[SMAX + 1], cumN[SMAX];
   double W, nf;
 
   __device__ __forceinline__ void load(const MDView &V, int i, int a, int coul, double absq) {
     const int *sst = V.segst + (size_t)i * (V.S + 1);
     double cw = 0.0;
     int cn = 0;
+    st[0] = sst[0];
 #pragma unroll
     for (int q = 0; q < SMAX; ++q) {
-      if (q < V.S) {
-        st[q] = sst[q];
-        ns[q] = sst[q + 1] - st[q];
-        ell[q] = seg_ell(V, a, q, coul, absq);
-      } else {
-        st[q] = 0; ns[q] = 0; ell[q] = 0.0;
-      }
-      cw += (double)ns[q] * ell[q];
-      if (ell[q] > 0.0) cn += ns[q];
+      st[q + 1] = (q < V.S) ? sst[q + 1] : st[q];
+      ell[q] = (q < V.S) ? seg_ell(V, a, q, coul, absq) : 0.0;
+      const int nq = st[q + 1] - st[q];
+      cw += (double)nq * ell[q];
+      if (ell[q] > 0.0) cn += nq;
       cumW[q] = cw;
       cumN[q] = cn;
     }
@@ -108,7 +153,7 @@ struct SegTab {
     int s = -1, last = -1;
 #pragma unroll
     for (int q = 0; q < SMAX; ++q) {
-      bool ok = ns[q] > 0 && ell[q] > 0.0;
+      const bool ok = st[q + 1] > st[q] && ell[q] > 0.0;
       if (ok) last = q;
       if (s < 0 && ok && target < cumW[q]) s = q;
     }
@@ -118,7 +163,7 @@ struct SegTab {
 #pragma unroll
     for (int q = 0; q < SMAX; ++q) {
       if (q == s - 1) below = cumW[q];
-      if (q == s) { el = ell[q]; base = st[q]; n = ns[q]; }
+      if (q == s) { el = ell[q]; base = st[q]; n = st[q + 1] - st[q]; }
     }
     long long idx = (long long)floor((target - below) / el);
     idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
@@ -132,7 +177,7 @@ struct SegTab {
     int s = -1, last = -1;
 #pragma unroll
     for (int q = 0; q < SMAX; ++q) {
-      bool ok = ns[q] > 0 && ell[q] > 0.0;
+      const bool ok = st[q + 1] > st[q] && ell[q] > 0.0;
       if (ok) last = q;
       if (s < 0 && ok && target < (double)cumN[q]) s = q;
     }
@@ -142,7 +187,7 @@ struct SegTab {
 #pragma unroll
     for (int q = 0; q < SMAX; ++q) {
       if (q == s - 1) below = (double)cumN[q];
-      if (q == s) { el = ell[q]; base = st[q]; n = ns[q]; }
+      if (q == s) { el = ell[q]; base = st[q]; n = st[q + 1] - st[q]; }
     }
     long long idx = (long long)floor(target - below);
     idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
@@ -260,11 +305,11 @@ __device__ void op_c(const MDView &V, const double4 *__restrict__ X, int i, doub
       if (F2 > 0.0) {
         if (adaptive) {
           eta = eps0 * sqrt(beta * me) * vF;
-          lam = sqrt(beta / me) / eps0 * theta_fn(eta);
+          lam = sqrt(beta / me) / eps0 * theta_p(V, eta);
         } else {
           const double Fn = sqrt(F2);
           eta = eps0 * sqrt(beta * me) * vF / Fn;
-          lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * theta_fn(eta);
+          lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * theta_p(V, eta);
         }
       }
       const double p = lam / c;
@@ -285,27 +330,287 @@ __device__ void op_c(const MDView &V, const double4 *__restrict__ X, int i, doub
   }
 }
 
-// -------------------------------------------------------------- k_local
+// --------------------------------------------------- lane-group chains
+// G lanes cooperate on one atom's chain. Lane r holds proposal kk (kk = r mod
+// G) of the window [w0, w0 + G): its velocity-independent part (Philox block,
+// candidate, gathered position, long-range gradient) is computed once; the
+// velocity-dependent part (time, acceptance) is evaluated for the whole
+// window assuming no jump inside it, and the first event (acceptance or end
+// of the half step, by proposal order) is found with a group minimum. Only
+// proposals after an accepted jump are re-evaluated. Proposal times are
+// prefix sums taken in proposal order, so every decision is the one the
+// sequential chain takes.
+template <int G>
+__device__ __forceinline__ int group_min(int x) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, G));
+  return x;
+}
+template <int G>
+__device__ __forceinline__ int group_sum(int x) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, G);
+  return x;
+}
+
+// Z by rejection with G iterations in parallel: lane r tries iteration
+// base + r; the first accepted iteration (in order) wins.
+template <int G>
+__device__ double zsample_grp(double eta, uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
+                              int phase, int64_t k, int r, int &overflow) {
+  overflow = 0;
+  for (int base = 0; base < MD_ZS_MAXIT; base += G) {
+    const int it = base + r;
+    double z = 0.0;
+    bool ok = false;
+    if (it < MD_ZS_MAXIT) {
+      uint64_t tag = (uint64_t)(uint32_t)phase | ((uint64_t)(it + 1) << 24);
+      Uni4 u = draw4(seed, rep, step, atom, tag, k);
+      if (eta > 0.0) {
+        double p_ray = 1.0 / (1.0 + eta * 2.5066282746310002);
+        double rad = sqrt(-2.0 * log(u.u[1]));
+        double y = (u.u[0] < p_ray) ? rad : rad * cos(2.0 * MD_PI * u.u[2]);
+        z = eta + y;
+        ok = (y >= 0.0) || (z > 0.0 && u.u[3] <= z / eta);
+      } else if (eta >= -1.0) {
+        z = sqrt(-2.0 * log(u.u[0]));
+        ok = u.u[1] <= exp(eta * z);
+      } else {
+        z = -(log(u.u[0]) + log(u.u[1])) / (-eta);
+        ok = u.u[2] <= exp(-0.5 * z * z);
+      }
+    }
+    const int first = group_min<G>(ok ? r : G);
+    if (first < G) return __shfl(z, first, G);
+  }
+  overflow = 1;
+  return 0.5 * (eta + sqrt(eta * eta + 4.0));
+}
+
+struct PropBranch { int j; double Fx, Fy, Fz, F2, ell; };
+
 template <int SMAX>
+__device__ __forceinline__ void fill_branch(const MDView &V, const double4 *__restrict__ X, const int *row,
+                                            const SegTab<SMAX> &T, bool uniform, double u2, double4 xi, int a,
+                                            int coul, const double *L, const double *iL, PropBranch &b) {
+  const int pos = uniform ? T.pick_uniform(u2, b.ell) : T.pick_by_bound(u2, b.ell);
+  b.j = row[pos];
+  b.F2 = long_grad(V, xi, X[b.j], a, V.type[b.j], coul, L, iL, b.Fx, b.Fy, b.Fz);
+}
+
+template <int SMAX, int G>
+__device__ void op_j_grp(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
+                         double &vx, double &vy, double &vz, const MDOp &op, AtomStats &st,
+                         const double *L, const double *iL) {
+  const int a = V.type[i];
+  SegTab<SMAX> T;
+  T.load(V, i, a, 0, 0.0);
+  const int *row = V.crow + (size_t)i * V.cap_c;
+  const double vn = sqrt(vx * vx + vy * vy + vz * vz);
+  const double Lam = V.beta * vn * T.W;
+  if (!(Lam > 0.0)) return;
+  if (!isfinite(Lam)) { if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull); return; }
+  const uint64_t rep = (uint64_t)V.rep[i];
+  const int64_t li = V.loc[i];
+  int64_t w0 = 0, kk = r;
+  double E = 0.0, u3 = 0.0;
+  PropBranch pb;
+  auto reload = [&]() {
+    Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, kk);
+    E = -log(u.u[0]);
+    u3 = u.u[3];
+    fill_branch<SMAX>(V, X, row, T, false, u.u[2], xi, a, 0, L, iL, pb);
+  };
+  reload();
+  double base = 0.0;  // sum of E over proposals before the window
+  for (;;) {
+    if (w0 >= MD_MAX_PROPOSALS) { if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull); break; }
+    const int rank = (int)(kk - w0);
+    double s = base, tot = base;
+#pragma unroll
+    for (int m = 0; m < G; ++m) {
+      const double Em = __shfl(E, (int)((w0 + m) % G), G);
+      tot += Em;
+      if (m <= rank) s = tot;
+    }
+    const bool out = s / Lam > op.h;
+    const double vF = vx * pb.Fx + vy * pb.Fy + vz * pb.Fz;
+    const double p = (vF > 0.0 ? vF : 0.0) / (vn * pb.ell);
+    const bool acc = !out && p > 0.0 && u3 <= p;
+    const int first = group_min<G>((out || acc) ? rank : G);
+    // proposals evaluated in this window: ranks < first, plus an accepted one
+    const bool counted = rank < first || (rank == first && acc);
+    const int nev = group_sum<G>(counted ? 1 : 0);
+    const int nvi = group_sum<G>((counted && p > 1.0) ? 1 : 0);
+    st.nprop += nev;
+    st.nviol += nvi;
+    if (first == G) { base = tot; w0 += G; kk += G; reload(); continue; }
+    const int src = (int)((w0 + first) % G);
+    const bool out_f = __shfl((int)out, src, G) != 0;
+    if (out_f) break;
+    const double Fx = __shfl(pb.Fx, src, G), Fy = __shfl(pb.Fy, src, G), Fz = __shfl(pb.Fz, src, G);
+    const double F2 = __shfl(pb.F2, src, G);
+    const int j = __shfl(pb.j, src, G);
+    const double vFs = vx * Fx + vy * Fy + vz * Fz;
+    const double c = 2.0 * vFs / F2;
+    vx -= c * Fx; vy -= c * Fy; vz -= c * Fz;
+    const int64_t kstar = w0 + first;
+    if (r == src) log_jump(V, st, op.step, op.phase, i, j, kstar);
+    else log_jump_hash_only(V, st, op.step, op.phase, j);
+    base = __shfl(s, src, G);
+    w0 = kstar + 1;
+    if (kk < w0) { kk += G; reload(); }
+  }
+}
+
+template <int SMAX, int G>
+__device__ void op_c_grp(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
+                         double &vx, double &vy, double &vz, double me, double ax, double ay, double az,
+                         const MDOp &op, AtomStats &st, const double *L, const double *iL) {
+  const int a = V.type[i];
+  SegTab<SMAX> T;
+  T.load(V, i, a, 1, fabs(xi.w));
+  const int *row = V.crow + (size_t)i * V.cap_c;
+  const bool adaptive = (V.jc == MD_JUMP_MRZ_ADAPTIVE);
+  const double beta = V.beta, eps0 = V.eps0;
+  const double f = sqrt(beta / (2.0 * MD_PI * me)) / eps0;
+  const double aa = ax * ax + ay * ay + az * az;
+  const uint64_t rep = (uint64_t)V.rep[i];
+  const int64_t li = V.loc[i];
+  const double h = op.h;
+  int64_t w0 = 0, kk = r;
+  double E = 0.0, u1 = 0.0, u3 = 0.0;
+  PropBranch pb, pf;
+  auto reload = [&]() {
+    Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, kk);
+    E = -log(u.u[0]);
+    u1 = u.u[1];
+    u3 = u.u[3];
+    fill_branch<SMAX>(V, X, row, T, false, u.u[2], xi, a, 1, L, iL, pb);
+    if (adaptive) fill_branch<SMAX>(V, X, row, T, true, u.u[2], xi, a, 1, L, iL, pf);
+  };
+  reload();
+  double vex = vx, vey = vy, vez = vz, te = 0.0;
+  for (;;) {
+    // epoch: bound from (t_e, v_e) over the rest of the half step
+    const double tau = h - te;
+    const double vv = vex * vex + vey * vey + vez * vez;
+    const double va = vex * ax + vey * ay + vez * az;
+    const double Bv = sqrt(vv + tau * tau * aa + 2.0 * tau * (va > 0.0 ? va : 0.0));
+    const double bBv = beta * Bv;
+    const double Wb = bBv * T.W;
+    const double Lam = adaptive ? Wb + f * T.nf : (bBv + f) * T.W;
+    if (!(Lam > 0.0) || !isfinite(Lam)) {
+      if (!(Lam <= 0.0) && r == 0) atomicAdd(&V.ctl->nonfinite, 1ull);
+      vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
+      return;
+    }
+    double base = 0.0;
+    bool jumped = false;
+    while (!jumped) {
+      if (w0 >= MD_MAX_PROPOSALS) {
+        if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull);
+        vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
+        return;
+      }
+      const int rank = (int)(kk - w0);
+      double s = base, tot = base;
+#pragma unroll
+      for (int m = 0; m < G; ++m) {
+        const double Em = __shfl(E, (int)((w0 + m) % G), G);
+        tot += Em;
+        if (m <= rank) s = tot;
+      }
+      const double tk = te + s / Lam;
+      const bool out = tk > h;
+      const double dtk = tk - te;
+      const double vkx = vex + dtk * ax, vky = vey + dtk * ay, vkz = vez + dtk * az;
+      const bool use_f = adaptive && !(u1 * Lam < Wb);
+      const PropBranch &b = use_f ? pf : pb;
+      const double c = adaptive ? bBv * b.ell + f : b.ell * (bBv + f);
+      double lam = 0.0, eta = 0.0;
+      const double vF = vkx * b.Fx + vky * b.Fy + vkz * b.Fz;
+      if (!out && b.F2 > 0.0) {
+        if (adaptive) {
+          eta = eps0 * sqrt(beta * me) * vF;
+          lam = sqrt(beta / me) / eps0 * theta_p(V, eta);
+        } else {
+          const double Fn = sqrt(b.F2);
+          eta = eps0 * sqrt(beta * me) * vF / Fn;
+          lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * theta_p(V, eta);
+        }
+      }
+      const double p = lam / c;
+      const bool acc = !out && p > 0.0 && u3 <= p;
+      const int first = group_min<G>((out || acc) ? rank : G);
+      const bool counted = rank < first || (rank == first && acc);
+      st.nprop += group_sum<G>(counted ? 1 : 0);
+      st.nviol += group_sum<G>((counted && p > 1.0) ? 1 : 0);
+      if (first == G) { base = tot; w0 += G; kk += G; reload(); continue; }
+      const int src = (int)((w0 + first) % G);
+      if (__shfl((int)out, src, G)) {
+        vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
+        return;
+      }
+      const double etas = __shfl(eta, src, G);
+      const double F2 = __shfl(b.F2, src, G);
+      const double Fx = __shfl(b.Fx, src, G), Fy = __shfl(b.Fy, src, G), Fz = __shfl(b.Fz, src, G);
+      const int j = __shfl(b.j, src, G);
+      const double tks = __shfl(tk, src, G);
+      const int64_t kstar = w0 + first;
+      int ovf;
+      const double Z = zsample_grp<G>(etas, V.seed, rep, op.step, li, op.phase, kstar, r, ovf);
+      if (ovf && r == 0) atomicAdd(&V.ctl->n_zs_overflow, 1ull);
+      const double coef = adaptive ? 2.0 * eps0 * Z / ((1.0 + eps0 * eps0 * F2) * sqrt(beta * me))
+                                   : 2.0 * eps0 * Z / ((1.0 + eps0 * eps0) * sqrt(beta * me) * sqrt(F2));
+      const double dts = tks - te;
+      vex = vex + dts * ax - coef * Fx;
+      vey = vey + dts * ay - coef * Fy;
+      vez = vez + dts * az - coef * Fz;
+      te = tks;
+      if (r == src) log_jump(V, st, op.step, op.phase, i, j, kstar);
+      else log_jump_hash_only(V, st, op.step, op.phase, j);
+      w0 = kstar + 1;
+      if (kk < w0) { kk += G; reload(); }
+      jumped = true;
+    }
+  }
+}
+
+// -------------------------------------------------------------- k_local
+// G lanes per atom (G = 1: one lane runs the whole chain). B/A/O ops are
+// repeated by every lane of the group; lane 0 writes the atom back.
+template <int SMAX, int G>
 __global__ __launch_bounds__(64) void k_local(MDView V, MDProg P, const double4 *__restrict__ Xs,
-                                              double4 *__restrict__ Xd) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && P.reset_slot >= 0) V.ctl->maxd2[P.reset_slot] = 0ull;
+                                               double4 *__restrict__ Xd) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / G, r = gid - (gid / G) * G;
+  // displacement maximum: per-block LDS max (blocks are single waves), then
+  // one global atomic per block; every lane on one shared word serialises
+  __shared__ unsigned long long s_d2;
+  const int rp_blk = V.rep[min(V.n - 1, (int)(blockIdx.x * blockDim.x) / G)];
+  if (threadIdx.x == 0) s_d2 = 0ull;
+  __syncthreads();
+  if (gid < V.nrep && P.reset_slot >= 0) V.rep_maxd2[P.reset_slot * V.nrep + gid] = 0ull;
   if (i >= V.n) return;
   double4 xi = Xs[i];
   double4 vv = V.v[i];
   double vx = vv.x, vy = vv.y, vz = vv.z;
   const double me = vv.w;
-  const int r = V.rep[i];
-  double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+  const int rp = V.rep[i];
+  double L[3] = {V.box[3 * rp], V.box[3 * rp + 1], V.box[3 * rp + 2]};
   double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
   AtomStats st;
   bool jumps = false;
   for (int o = 0; o < P.nops; ++o) jumps |= (P.ops[o].kind == OP_J || P.ops[o].kind == OP_C);
   if (jumps) { st.nprop = V.nprop[i]; st.nacc = V.nacc[i]; st.nviol = V.nviol[i]; st.hash = V.hash[i]; }
   double4 fn = V.fnb[i], fb = V.fb[i];
+  const int64_t sbase = P.dev_step ? (int64_t)V.ctl->step_base : 0;
+  double disp2 = 0.0;
+  bool has_disp = false;
   for (int o = 0; o < P.nops; ++o) {
-    const MDOp &op = P.ops[o];
+    MDOp op = P.ops[o];
+    op.step += sbase;
     switch (op.kind) {
       case OP_B: {
         double fx = ((op.flags & 1) ? fn.x : 0.0) + ((op.flags & 2) ? fb.x : 0.0);
@@ -318,7 +623,7 @@ __global__ __launch_bounds__(64) void k_local(MDView V, MDProg P, const double4 
         break;
       case OP_O: {
         uint64_t tag = (uint64_t)OP_PHASE_O | ((uint64_t)(uint32_t)op.substep << 8);
-        Uni4 u = draw4(V.seed, (uint64_t)r, op.step, V.loc[i], tag, 0);
+        Uni4 u = draw4(V.seed, (uint64_t)rp, op.step, V.loc[i], tag, 0);
         double r1 = sqrt(-2.0 * log(u.u[0])), r2 = sqrt(-2.0 * log(u.u[2]));
         double gx = r1 * cos(2.0 * MD_PI * u.u[1]);
         double gy = r1 * sin(2.0 * MD_PI * u.u[1]);
@@ -329,47 +634,64 @@ __global__ __launch_bounds__(64) void k_local(MDView V, MDProg P, const double4 
         vz = op.c1 * vz + op.c2 * sd * gz;
       } break;
       case OP_J:
-        op_j<SMAX>(V, Xs, i, xi, vx, vy, vz, op, st, L, iL);
+        if (G == 1) op_j<SMAX>(V, Xs, i, xi, vx, vy, vz, op, st, L, iL);
+        else op_j_grp<SMAX, G>(V, Xs, i, r, xi, vx, vy, vz, op, st, L, iL);
         break;
       case OP_C: {
         double fx = fn.x + (op.flags == 0 ? fb.x : 0.0);
         double fy = fn.y + (op.flags == 0 ? fb.y : 0.0);
         double fz = fn.z + (op.flags == 0 ? fb.z : 0.0);
-        op_c<SMAX>(V, Xs, i, xi, vx, vy, vz, me, fx / me, fy / me, fz / me, op, st, L, iL);
+        if (G == 1) op_c<SMAX>(V, Xs, i, xi, vx, vy, vz, me, fx / me, fy / me, fz / me, op, st, L, iL);
+        else op_c_grp<SMAX, G>(V, Xs, i, r, xi, vx, vy, vz, me, fx / me, fy / me, fz / me, op, st, L, iL);
       } break;
-      case OP_DISP: {
-        double4 xr = V.xref[i];
-        double dx = xi.x - xr.x, dy = xi.y - xr.y, dz = xi.z - xr.z;
-        double d2 = dx * dx + dy * dy + dz * dz;
-        atomicMax(&V.ctl->maxd2[P.disp_slot], (unsigned long long)__double_as_longlong(d2));
-      } break;
+      case OP_DISP:
+        disp2 = 0.0;
+        if (r == 0) {
+          double4 xr = V.xref[i];
+          double dx = xi.x - xr.x, dy = xi.y - xr.y, dz = xi.z - xr.z;
+          disp2 = dx * dx + dy * dy + dz * dz;
+        }
+        has_disp = true;
+        break;
     }
   }
-  if (!(isfinite(vx) && isfinite(vy) && isfinite(vz))) atomicAdd(&V.ctl->nonfinite, 1ull);
-  V.v[i] = make_double4(vx, vy, vz, me);
-  if (Xd) Xd[i] = xi;
-  if (jumps) { V.nprop[i] = st.nprop; V.nacc[i] = st.nacc; V.nviol[i] = st.nviol; V.hash[i] = st.hash; }
+  if (r == 0) {
+    if (!(isfinite(vx) && isfinite(vy) && isfinite(vz))) atomicAdd(&V.ctl->nonfinite, 1ull);
+    V.v[i] = make_double4(vx, vy, vz, me);
+    if (Xd) Xd[i] = xi;
+    if (jumps) { V.nprop[i] = st.nprop; V.nacc[i] = st.nacc; V.nviol[i] = st.nviol; V.hash[i] = st.hash; }
+  }
+  if (has_disp) {
+    const unsigned long long d = (unsigned long long)__double_as_longlong(disp2);
+    if (rp == rp_blk) atomicMax(&s_d2, d);
+    else atomicMax(&V.rep_maxd2[P.disp_slot * V.nrep + rp], d);   // block straddles two replicas
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(&V.rep_maxd2[P.disp_slot * V.nrep + rp_blk], s_d2);
+  }
 }
 
 // ------------------------------------------------------------ rebuild
-__device__ __forceinline__ bool rebuild_now(const MDView &V, int slot, int forced, int autob, double thr2) {
+// Every replica decides on its own: rebuild when its maximum displacement
+// since its last build exceeds skin/2 (or when forced).
+__device__ __forceinline__ bool rebuild_now(const MDView &V, int slot, int forced, int autob, double thr2, int r) {
   if (forced) return true;
   if (!autob) return false;
-  double m = __longlong_as_double((long long)V.ctl->maxd2[slot]);
+  double m = __longlong_as_double((long long)V.rep_maxd2[slot * V.nrep + r]);
   return m > thr2;
 }
 
 __global__ void k_cell_count(MDView V, const double4 *__restrict__ X, int slot, int forced, int autob,
                              double thr2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool rb = rebuild_now(V, slot, forced, autob, thr2);
-  if (i == 0 && !rb && !autob) {
-    double m = __longlong_as_double((long long)V.ctl->maxd2[slot]);
+  if (i >= V.n) return;
+  const int r = V.rep[i];
+  const bool rb = rebuild_now(V, slot, forced, autob, thr2, r);
+  if (i == V.rep_off[r] && !forced && !autob) {
+    double m = __longlong_as_double((long long)V.rep_maxd2[slot * V.nrep + r]);
     if (m > thr2) atomicAdd(&V.ctl->n_list_err, 1ull);
   }
-  if (!rb || i >= V.n) return;
+  if (!rb) return;
   double4 x = X[i];
-  const int r = V.rep[i];
   int c3[3];
   const double xs[3] = {x.x, x.y, x.z};
   for (int d = 0; d < 3; ++d) {
@@ -385,13 +707,15 @@ __global__ void k_cell_count(MDView V, const double4 *__restrict__ X, int slot, 
   V.xref[i] = x;
 }
 
+// One block: exclusive scan of the cell counts (replicas that do not rebuild
+// contribute zero), then per rebuilding replica cell starts offset to the
+// replica's own atom range; the other replicas' cells are left untouched.
 __global__ __launch_bounds__(1024) void k_cell_scan(MDView V, int slot, int forced, int autob, double thr2,
                                                     int count) {
-  if (!rebuild_now(V, slot, forced, autob, thr2)) return;
   __shared__ int part[1024];
   const int T = blockDim.x, t = threadIdx.x, nc = V.ncell_total;
   const int per = (nc + T - 1) / T;
-  const int b = t * per, e = min(nc, b + per);
+  const int b = min(nc, t * per), e = min(nc, b + per);
   int s = 0;
   for (int c = b; c < e; ++c) s += V.cell_count[c];
   part[t] = s;
@@ -404,29 +728,39 @@ __global__ __launch_bounds__(1024) void k_cell_scan(MDView V, int slot, int forc
   }
   int run = part[t] - s;
   for (int c = b; c < e; ++c) {
-    V.cell_start[c] = run;
+    V.cell_tmp[c] = run;
     run += V.cell_count[c];
+  }
+  __syncthreads();
+  for (int c = b; c < e; ++c) {
+    const int r = V.cell_rep[c];
+    if (!rebuild_now(V, slot, forced, autob, thr2, r)) continue;
+    V.cell_start[c] = V.rep_off[r] + V.cell_tmp[c] - V.cell_tmp[V.rep_cell_off[r]];
     V.cell_count[c] = 0;
   }
-  if (t == T - 1) V.cell_start[nc] = part[T - 1];
-  if (t == 0 && count) atomicAdd(&V.ctl->n_rebuilds, 1ull);
+  if (t == 0) V.cell_start[nc] = V.n;
+  if (count)
+    for (int r = t; r < V.nrep; r += T)
+      if (rebuild_now(V, slot, forced, autob, thr2, r)) atomicAdd(&V.ctl->n_rebuilds, 1ull);
 }
 
 __global__ void k_cell_scatter(MDView V, int slot, int forced, int autob, double thr2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (!rebuild_now(V, slot, forced, autob, thr2) || i >= V.n) return;
-  V.cell_atoms[V.cell_start[V.atom_cell[i]] + V.atom_slot[i]] = i;
+  if (i >= V.n || !rebuild_now(V, slot, forced, autob, thr2, V.rep[i])) return;
+  const int p = V.cell_start[V.atom_cell[i]] + V.atom_slot[i];
+  V.cell_atoms[p] = i;
+  V.xcell[p] = V.xref[i];   // positions in cell order: contiguous reads in the row builder
 }
 
-__device__ __forceinline__ void bitonic_sort_lds(unsigned long long *keys, int m) {
+__device__ __forceinline__ void bitonic_sort_lds(unsigned *keys, int m) {
   const int lane = threadIdx.x;
   for (int k = 2; k <= m; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int t = lane; t < (m >> 1); t += 64) {
-        int a = 2 * j * (t / j) + (t % j);
-        int b = a + j;
-        bool up = (a & k) == 0;
-        unsigned long long ka = keys[a], kb = keys[b];
+        const int a = 2 * j * (t / j) + (t % j);
+        const int b = a + j;
+        const bool up = (a & k) == 0;
+        const unsigned ka = keys[a], kb = keys[b];
         if ((ka > kb) == up) { keys[a] = kb; keys[b] = ka; }
       }
       __syncthreads();
@@ -434,98 +768,121 @@ __device__ __forceinline__ void bitonic_sort_lds(unsigned long long *keys, int m
   }
 }
 
-// one wavefront per atom: rows with want bits 1 = short (r < r_s+skin),
-// 2 = full (r < r_c+skin), 4 = candidates (r_s-w-skin <= r < r_c+skin)
+// cells of one stencil dimension: offsets -2..2 when the replica has at least
+// 5 cells along it (cell edge >= (r_c + skin)/2), otherwise every cell once
+__device__ __forceinline__ void stencil_range(int c, int nd, int &lo, int &hi) {
+  if (nd >= 5) { lo = c - 2; hi = c + 2; }
+  else { lo = 0; hi = nd - 1; }
+}
+
+// One wavefront per atom: rows with want bits 1 = short (r < r_s + skin),
+// 2 = full (r < r_c + skin), 4 = candidates (r_s - w - skin <= r < r_c + skin).
+// Candidates are read from the cell-ordered copy of positions along
+// contiguous x-runs of the 5x5x5 stencil, compacted into LDS with a ballot,
+// sorted (32-bit keys: segment << 24 | j, or j) and written out.
 __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restrict__ X, int want, int slot,
                                               int forced, int autob, double thr2, int pc, int ps) {
-  if (!rebuild_now(V, slot, forced, autob, thr2)) return;
-  extern __shared__ unsigned long long lds[];
-  unsigned long long *kc = lds;       // candidate or full keys [pc]
-  unsigned long long *ks = lds + pc;  // short keys [ps]
+  if (!rebuild_now(V, slot, forced, autob, thr2, V.rep[blockIdx.x])) return;
+  extern __shared__ unsigned lds[];
+  unsigned *kc = lds;       // candidate or full keys [pc]
+  unsigned *ks = lds + pc;  // short keys [ps]
   const int i = blockIdx.x, lane = threadIdx.x;
   const double4 xi = X[i];
   const int r = V.rep[i];
   const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
   const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
   const int nd[3] = {V.rep_cdim[3 * r], V.rep_cdim[3 * r + 1], V.rep_cdim[3 * r + 2]};
-  const int cl = V.atom_cell[i] - V.rep_cell_off[r];
+  const int coff = V.rep_cell_off[r];
+  const int cl = V.atom_cell[i] - coff;
   const int cx = cl % nd[0], cy = (cl / nd[0]) % nd[1], cz = cl / (nd[0] * nd[1]);
   const int x0 = V.xptr ? V.xptr[i] : 0, x1 = V.xptr ? V.xptr[i + 1] : 0;
   const double rs_out = V.rs + V.skin;
   const int capk = (want & 4) ? V.cap_c : V.cap_f;
   int nk = 0, nsr = 0, over = 0;
-  for (int dz = (nd[2] >= 3 ? -1 : 0); dz <= (nd[2] >= 2 ? 1 : 0); ++dz)
-    for (int dy = (nd[1] >= 3 ? -1 : 0); dy <= (nd[1] >= 2 ? 1 : 0); ++dy)
-      for (int dx = (nd[0] >= 3 ? -1 : 0); dx <= (nd[0] >= 2 ? 1 : 0); ++dx) {
-        int ccx = (cx + dx + nd[0]) % nd[0], ccy = (cy + dy + nd[1]) % nd[1], ccz = (cz + dz + nd[2]) % nd[2];
-        int c = V.rep_cell_off[r] + (ccz * nd[1] + ccy) * nd[0] + ccx;
-        int beg = V.cell_start[c], end = V.cell_start[c + 1];
+  int zlo, zhi, ylo, yhi, xlo, xhi;
+  stencil_range(cz, nd[2], zlo, zhi);
+  stencil_range(cy, nd[1], ylo, yhi);
+  stencil_range(cx, nd[0], xlo, xhi);
+  for (int zz = zlo; zz <= zhi; ++zz)
+    for (int yy = ylo; yy <= yhi; ++yy) {
+      const int ccz = (zz + nd[2]) % nd[2], ccy = (yy + nd[1]) % nd[1];
+      const int row0 = coff + (ccz * nd[1] + ccy) * nd[0];
+      // x-run as at most two contiguous spans of cells
+      int sp_lo[2], sp_hi[2], nsp = 1;
+      if (xlo >= 0 && xhi < nd[0]) { sp_lo[0] = xlo; sp_hi[0] = xhi; }
+      else if (xlo < 0) { sp_lo[0] = xlo + nd[0]; sp_hi[0] = nd[0] - 1; sp_lo[1] = 0; sp_hi[1] = xhi; nsp = 2; }
+      else { sp_lo[0] = xlo; sp_hi[0] = nd[0] - 1; sp_lo[1] = 0; sp_hi[1] = xhi - nd[0]; nsp = 2; }
+      for (int t = 0; t < nsp; ++t) {
+        const int beg = V.cell_start[row0 + sp_lo[t]], end = V.cell_start[row0 + sp_hi[t] + 1];
         for (int p = beg; p < end; p += 64) {
-          int q = p + lane;
+          const int q = p + lane;
           int j = -1;
           bool ok = q < end;
+          double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
           if (ok) {
             j = V.cell_atoms[q];
+            xj = V.xcell[q];
             ok = (j != i);
             for (int e = x0; ok && e < x1; ++e) ok = (V.xj[e] != j);
           }
           bool bs = false, bk = false;
-          unsigned long long key = 0;
+          unsigned key = 0;
           if (ok) {
-            double4 xj = X[j];
-            double ddx = min_img(xi.x - xj.x, L[0], iL[0]);
-            double ddy = min_img(xi.y - xj.y, L[1], iL[1]);
-            double ddz = min_img(xi.z - xj.z, L[2], iL[2]);
-            double rr = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+            const double ddx = min_img(xi.x - xj.x, L[0], iL[0]);
+            const double ddy = min_img(xi.y - xj.y, L[1], iL[1]);
+            const double ddz = min_img(xi.z - xj.z, L[2], iL[2]);
+            const double rr = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
             bs = (want & 1) && rr < rs_out;
             if (want & 4) {
               bk = rr >= V.rin && rr < V.rout;
               int ring = (int)floor((rr - V.rin) / V.rw);
               ring = ring < 0 ? 0 : (ring > V.nr - 1 ? V.nr - 1 : ring);
-              key = ((unsigned long long)(V.type[j] * V.nr + ring) << 32) | (unsigned)j;
+              key = ((unsigned)(V.type[j] * V.nr + ring) << 24) | (unsigned)j;
             } else if (want & 2) {
               bk = rr < V.rout;
               key = (unsigned)j;
             }
           }
-          unsigned long long mk = __ballot(bk), ms = __ballot(bs);
-          unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+          const unsigned long long mk = __ballot(bk), ms = __ballot(bs);
+          const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
           if (bk) {
-            int pos = nk + __popcll(mk & below);
+            const int pos = nk + __popcll(mk & below);
             if (pos < pc) kc[pos] = key; else over = 1;
           }
           if (bs) {
-            int pos = nsr + __popcll(ms & below);
+            const int pos = nsr + __popcll(ms & below);
             if (pos < ps) ks[pos] = (unsigned)j; else over = 1;
           }
           nk += __popcll(mk);
           nsr += __popcll(ms);
         }
       }
+    }
   if (nk > capk || nsr > V.cap_s) over = 1;
-  if (over && lane == 0) atomicMax(&V.ctl->overflow_rows, max(nk, nsr));
+  if (__any(over) && lane == 0) atomicMax(&V.ctl->overflow_rows, max(nk, nsr));
   const int nkk = min(nk, min(capk, pc)), nss = min(nsr, min(V.cap_s, ps));
-  // pad and sort
   if (want & 6) {
-    int m = 1; while (m < nkk) m <<= 1;
-    for (int e = nkk + lane; e < m; e += 64) kc[e] = ~0ull;
+    int m = 1;
+    while (m < nkk) m <<= 1;
+    for (int e = nkk + lane; e < m; e += 64) kc[e] = 0xffffffffu;
     __syncthreads();
     bitonic_sort_lds(kc, m);
     int *row = (want & 4) ? V.crow + (size_t)i * V.cap_c : V.frow + (size_t)i * V.cap_f;
-    for (int e = lane; e < nkk; e += 64) row[e] = (int)(kc[e] & 0xffffffffull);
+    for (int e = lane; e < nkk; e += 64) row[e] = (int)(kc[e] & 0xffffffu);
     if (lane == 0) { if (want & 4) V.ccnt[i] = nkk; else V.fcnt[i] = nkk; }
     if (want & 4) {
-      for (int s = lane; s <= V.S; s += 64) {
-        unsigned long long probe = (unsigned long long)s << 32;
+      for (int sg = lane; sg <= V.S; sg += 64) {
+        const unsigned probe = (unsigned)sg << 24;
         int lo = 0, hi = nkk;
         while (lo < hi) { int mid = (lo + hi) >> 1; if (kc[mid] < probe) lo = mid + 1; else hi = mid; }
-        V.segst[(size_t)i * (V.S + 1) + s] = lo;
+        V.segst[(size_t)i * (V.S + 1) + sg] = lo;
       }
     }
   }
   if (want & 1) {
-    int m = 1; while (m < nss) m <<= 1;
-    for (int e = nss + lane; e < m; e += 64) ks[e] = ~0ull;
+    int m = 1;
+    while (m < nss) m <<= 1;
+    for (int e = nss + lane; e < m; e += 64) ks[e] = 0xffffffffu;
     __syncthreads();
     bitonic_sort_lds(ks, m);
     int *row = V.srow + (size_t)i * V.cap_s;
@@ -536,6 +893,61 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
 
 // -------------------------------------------------------------- forces
 // MODE 0: -grad chi U over r < r_s (short rows); MODE 1: -grad U over r < r_c (full rows)
+// FP32 pair arithmetic with FP64 accumulation (mixed-precision path)
+template <int MODE, int SG>
+__global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__restrict__ X) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / SG, lane = gid % SG;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  if (i < V.n) {
+    const double4 xi = X[i];
+    const int a = V.type[i], r = V.rep[i];
+    const double L0 = V.box[3 * r], L1 = V.box[3 * r + 1], L2 = V.box[3 * r + 2];
+    const double iL0 = 1.0 / L0, iL1 = 1.0 / L1, iL2 = 1.0 / L2;
+    const int *row = MODE == 0 ? V.srow + (size_t)i * V.cap_s : V.frow + (size_t)i * V.cap_f;
+    const int cnt = MODE == 0 ? V.scnt[i] : V.fcnt[i];
+    const float cut = (float)(MODE == 0 ? V.rs : V.rc);
+    const float cut2 = cut * cut;
+    const float kq = (float)(V.ke * xi.w);
+    for (int k = lane; k < cnt; k += SG) {
+      const int j = row[k];
+      const double4 xj = X[j];
+      const float dx = (float)min_img(xi.x - xj.x, L0, iL0);
+      const float dy = (float)min_img(xi.y - xj.y, L1, iL1);
+      const float dz = (float)min_img(xi.z - xj.z, L2, iL2);
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < cut2) {
+        const float rr = sqrtf(r2);
+        const int ab = a * V.nt + V.type[j];
+        float U = 0.0f, dU = 0.0f;
+        const float c12 = (float)V.c12[ab], c6 = (float)V.c6[ab];
+        if (c12 != 0.0f || c6 != 0.0f) lj_pair_f(r2, rr, c12, c6, (float)V.ljshift[ab], U, dU);
+        const float kqq = kq * (float)xj.w;
+        if (kqq != 0.0f) {
+          float Uc, dUc;
+          dsf_pair_f(rr, kqq, V, Uc, dUc);
+          U += Uc; dU += dUc;
+        }
+        float g = dU;
+        if (MODE == 0) {
+          float chi, dchi;
+          switch_fn_f(rr, V, chi, dchi);
+          g = chi * dU + dchi * U;
+        }
+        const float sc = -g / rr;
+        fx += (double)(sc * dx); fy += (double)(sc * dy); fz += (double)(sc * dz);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = SG / 2; off > 0; off >>= 1) {
+    fx += __shfl_xor(fx, off, SG);
+    fy += __shfl_xor(fy, off, SG);
+    fz += __shfl_xor(fz, off, SG);
+  }
+  if (i < V.n && lane == 0) V.fnb[i] = make_double4(fx, fy, fz, 0.0);
+}
+
 template <int MODE, int SG>
 __global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restrict__ X) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -763,15 +1175,31 @@ __global__ void k_count_pairs(MDView V, const double4 *__restrict__ X, int which
   if (c) atomicAdd(out, c);
 }
 
+__global__ void k_set_step(MDCtl *ctl, long long step) { ctl->step_base = step; }
+
 // ------------------------------------------------------------- launchers
 #define CHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
+template <int SMAX>
+static void launch_local_s(const MDView &V, const MDProg &P, const double4 *Xs, double4 *Xd, hipStream_t s) {
+  const int G = V.chain_lanes;
+  const long long threads = (long long)V.n * G;
+  const int nb = (int)((threads + 63) / 64);   // wave-sized blocks spread the few long waves over all CUs
+  switch (G) {
+    case 1: hipLaunchKernelGGL((k_local<SMAX, 1>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd); break;
+    case 2: hipLaunchKernelGGL((k_local<SMAX, 2>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd); break;
+    case 4: hipLaunchKernelGGL((k_local<SMAX, 4>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd); break;
+    case 8: hipLaunchKernelGGL((k_local<SMAX, 8>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd); break;
+    default: hipLaunchKernelGGL((k_local<SMAX, 16>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd); break;
+  }
+}
+
 hipError_t launch_local(const MDView &V, const MDProg &P, const double4 *Xs, double4 *Xd, hipStream_t s) {
-  int nb = (V.n + 63) / 64;
-  if (V.S <= 4) hipLaunchKernelGGL((k_local<4>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd);
-  else if (V.S <= 8) hipLaunchKernelGGL((k_local<8>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd);
-  else if (V.S <= 16) hipLaunchKernelGGL((k_local<16>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd);
-  else hipLaunchKernelGGL((k_local<32>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd);
+  if (V.S <= 4) launch_local_s<4>(V, P, Xs, Xd, s);
+  else if (V.S <= 8) launch_local_s<8>(V, P, Xs, Xd, s);
+  else if (V.S <= 12) launch_local_s<12>(V, P, Xs, Xd, s);
+  else if (V.S <= 16) launch_local_s<16>(V, P, Xs, Xd, s);
+  else launch_local_s<32>(V, P, Xs, Xd, s);
   return hipGetLastError();
 }
 
@@ -785,22 +1213,21 @@ hipError_t launch_rebuild(const MDView &V, const double4 *X, int want, int slot,
   CHK(hipGetLastError());
   hipLaunchKernelGGL(k_cell_scatter, dim3(nb), dim3(256), 0, s, V, slot, forced, autob, thr2);
   CHK(hipGetLastError());
-  size_t lds = sizeof(unsigned long long) * (size_t)(pc + ps);
+  size_t lds = sizeof(unsigned) * (size_t)(pc + ps);
   hipLaunchKernelGGL(k_build, dim3(V.n), dim3(64), lds, s, V, X, want, slot, forced, autob, thr2, pc, ps);
   return hipGetLastError();
 }
 
 hipError_t launch_force(const MDView &V, const double4 *X, int mode, hipStream_t s) {
+  const bool f32 = V.precision == MD_FP32_MIXED;
   if (mode == 0) {
-    const int SG = 8;
-    int nb = (int)(((long long)V.n * SG + 255) / 256);
-    hipLaunchKernelGGL((k_force<0, 8>), dim3(nb), dim3(256), 0, s, V, X);
-    (void)SG;
+    int nb = (int)(((long long)V.n * 8 + 255) / 256);
+    if (f32) hipLaunchKernelGGL((k_force_f<0, 8>), dim3(nb), dim3(256), 0, s, V, X);
+    else hipLaunchKernelGGL((k_force<0, 8>), dim3(nb), dim3(256), 0, s, V, X);
   } else {
-    const int SG = 16;
-    int nb = (int)(((long long)V.n * SG + 255) / 256);
-    hipLaunchKernelGGL((k_force<1, 16>), dim3(nb), dim3(256), 0, s, V, X);
-    (void)SG;
+    int nb = (int)(((long long)V.n * 16 + 255) / 256);
+    if (f32) hipLaunchKernelGGL((k_force_f<1, 16>), dim3(nb), dim3(256), 0, s, V, X);
+    else hipLaunchKernelGGL((k_force<1, 16>), dim3(nb), dim3(256), 0, s, V, X);
   }
   return hipGetLastError();
 }
@@ -836,6 +1263,11 @@ hipError_t launch_count_pairs(const MDView &V, const double4 *X, int which, doub
                               hipStream_t s) {
   int nb = (V.n + 255) / 256;
   hipLaunchKernelGGL(k_count_pairs, dim3(nb), dim3(256), 0, s, V, X, which, cut, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_step(MDCtl *ctl, long long step, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, ctl, step);
   return hipGetLastError();
 }
 

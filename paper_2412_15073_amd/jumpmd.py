@@ -45,7 +45,8 @@ class MDParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("gamma", C.c_double), ("kT", C.c_double), ("seed", C.c_uint64),
                 ("jump_lj", C.c_int32), ("jump_coul", C.c_int32), ("eps", C.c_double),
                 ("precision", C.c_int32), ("rebuild_every", C.c_int32), ("respa_inner", C.c_int32),
-                ("log_events", C.c_int32), ("strict_bounds", C.c_int32)]
+                ("log_events", C.c_int32), ("strict_bounds", C.c_int32), ("chain_lanes", C.c_int32),
+                ("graph_steps", C.c_int32)]
 
 
 class MDObs(C.Structure):
@@ -189,7 +190,8 @@ class Sim:
                      split.n_rings, split.ring_width)
         pa = MDParams(params.dt, params.gamma, params.kT, params.seed, params.jump_lj, params.jump_coul,
                       params.eps, params.precision, params.rebuild_every, params.respa_inner,
-                      params.log_events, params.strict_bounds)
+                      params.log_events, params.strict_bounds, getattr(params, "chain_lanes", 0),
+                      getattr(params, "graph_steps", 0))
         self.stream = stream if stream is not None else _current_stream()
         h = C.c_void_p()
         rc = L.md_create(C.byref(sy), C.byref(sp), C.byref(pa), self.stream, C.byref(h))

@@ -79,6 +79,8 @@ class Params:
     log_events: int = 0
     precision: int = FP64
     strict_bounds: int = 0
+    chain_lanes: int = 0      # lanes per atom in the GPU jump chains (0 = automatic)
+    graph_steps: int = 0      # steps per replayed HIP graph chunk (0 = no graphs)
 
 
 @dataclass

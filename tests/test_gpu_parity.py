@@ -143,3 +143,54 @@ def test_lj_full_size_100_steps(jm):
     _compare_state(g, o)
     _compare_stats(g, o)
     np.testing.assert_array_equal(g.events(), o.events())
+
+
+@pytest.mark.parametrize("lanes", [2, 4, 8, 16])
+def test_chain_lanes_do_not_change_results(jm, lanes):
+    """The lane-group chains (speculative windows of proposals) take exactly
+    the decisions of the one-lane chain and of the oracle."""
+    sy, sp = water_small()
+    pa = S.water_params()
+    pa.log_events = 1
+    pa.chain_lanes = lanes
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_jump(8)
+    o.step_jump(8)
+    _compare_state(g, o)
+    _compare_stats(g, o)
+    np.testing.assert_array_equal(g.events(), o.events())
+
+
+@pytest.mark.parametrize("lanes", [1, 8])
+def test_lj_chain_lanes(jm, lanes):
+    sy, sp = lj_small()
+    pa = S.lj_params()
+    pa.log_events = 1
+    pa.chain_lanes = lanes
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_jump(40)
+    o.step_jump(40)
+    _compare_state(g, o)
+    _compare_stats(g, o)
+    np.testing.assert_array_equal(g.events(), o.events())
+
+
+@pytest.mark.parametrize("scheme", ["jump", "baoab"])
+def test_graph_replay_matches_oracle(jm, scheme):
+    """Replaying captured K-step HIP graphs (device-side random-stream base,
+    odd start step, leftover steps run kernel by kernel) changes nothing."""
+    sy, sp = water_small()
+    pa = S.water_params(jumps=(scheme == "jump"))
+    pa.log_events = 1
+    pa.graph_steps = 4
+    g, o = _pair(jm, sy, sp, pa)
+    step = g.step_jump if scheme == "jump" else g.step_baoab
+    ostep = o.step_jump if scheme == "jump" else o.step_baoab
+    for n in (3, 9, 8):          # 3: plain; 9: 1 plain + 2 chunks; 8: 2 chunks (other buffer parity)
+        step(n)
+        ostep(n)
+        _compare_state(g, o)
+    if scheme == "jump":
+        _compare_stats(g, o)
+        np.testing.assert_array_equal(g.events(), o.events())
+    assert g.observables()["n_rebuilds"] == o.n_rebuilds
