@@ -401,13 +401,32 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.jlj = p->jump_lj; V.jc = p->jump_coul; V.log_events = p->log_events; V.precision = p->precision;
   V.seed = p->seed;
   {
-    // enough lanes to fill the device (~64k lanes in flight) when atoms are few
+    // automatic: the most lanes per atom whose waves still fit the device in
+    // one round (LDS of the proposal rings and segment tables per block)
     int g = p->chain_lanes;
+    const int S = V.nt * V.nr;
     if (g <= 0) {
+      int dev = 0, ncu = 256, lds_cu = 160 * 1024;
+      if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess && v > 0)
+          lds_cu = v;
+      }
       g = 1;
-      while (g < 16 && (long long)n * g * 2 <= 65536) g *= 2;
+      for (int c = 2; c <= 16; c *= 2) {
+        const size_t b = chain_lds_bytes_host(c, S);
+        if (b > 65536) continue;
+        const long long slots = (long long)ncu * (long long)(lds_cu / (long long)b);
+        if ((long long)n * c / 64 <= slots) g = c;
+      }
+      if (chain_lds_bytes_host(g, S) > 65536) g = 2;
     }
     if (g != 1 && g != 2 && g != 4 && g != 8 && g != 16) { delete c; return fail(nullptr, MD_ERR_ARG, "chain_lanes must be 0, 1, 2, 4, 8 or 16"); }
+    if (chain_lds_bytes_host(g, S) > 65536) {
+      delete c;
+      return fail(nullptr, MD_ERR_ARG, "chain_lanes too small for this many segments (jump-chain LDS above 64 KiB per block)");
+    }
     V.chain_lanes = g;
   }
 

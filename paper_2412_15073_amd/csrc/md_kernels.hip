@@ -118,228 +118,33 @@ __device__ __forceinline__ void log_jump_hash_only(const MDView &V, AtomStats &s
   st.nacc++;
 }
 
-// Segment tables of one atom for one jump component, in registers: counts,
-// bounds, cumulative weights sum n_q l_q and cumulative counts of segments
-// with a nonzero bound (candidates whose rate can be > 0).
-template <int SMAX>
-struct SegTab {
-  double ell[SMAX], cumW[SMAX];
-  int st[SMAX + 1], cumN[SMAX];
-  double W, nf;
+// ------------------------------------------------------- jump chains
+// G lanes cooperate on one atom's chain. The velocity-independent part of
+// every proposal (Philox block, candidate of each branch, gathered position,
+// long-range gradient, the uniforms of the first Z iteration) is computed G
+// proposals at a time, one per lane, into a per-atom ring of M = 2G slots in
+// LDS. The sequential part then evaluates windows of G proposals: times are
+// left folds of the exponential clocks taken in proposal order, acceptance
+// uses the velocity at the proposal time, and the first event (acceptance or
+// end of the half step) is found with a group minimum. Every decision is the
+// one the one-proposal-at-a-time chain takes.
 
-  __device__ __forceinline__ void load(const MDView &V, int i, int a, int coul, double absq) {
-    const int *sst = V.segst + (size_t)i * (V.S + 1);
-    double cw = 0.0;
-    int cn = 0;
-    st[0] = sst[0];
-#pragma unroll
-    for (int q = 0; q < SMAX; ++q) {
-      st[q + 1] = (q < V.S) ? sst[q + 1] : st[q];
-      ell[q] = (q < V.S) ? seg_ell(V, a, q, coul, absq) : 0.0;
-      const int nq = st[q + 1] - st[q];
-      cw += (double)nq * ell[q];
-      if (ell[q] > 0.0) cn += nq;
-      cumW[q] = cw;
-      cumN[q] = cn;
-    }
-    W = cw;
-    nf = (double)cn;
-  }
+// ring fields (doubles, field-major: field f of slot s at f*M + s)
+enum { RF_E = 0, RF_U1, RF_U3, RF_BX, RF_BY, RF_BZ, RF_B2, RF_BL, RF_BJ,
+       RF_FX, RF_FY, RF_FZ, RF_F2, RF_FL, RF_FJ, RF_Z0, RF_Z1, RF_Z2, RF_Z3, RF_N };
 
-  // candidate in proportion to its bound (segment by n l, then uniform inside
-  // from the residual); returns the row position, writes the segment bound
-  __device__ __forceinline__ int pick_by_bound(double u, double &ell_s) const {
-    const double target = u * W;
-    int s = -1, last = -1;
-#pragma unroll
-    for (int q = 0; q < SMAX; ++q) {
-      const bool ok = st[q + 1] > st[q] && ell[q] > 0.0;
-      if (ok) last = q;
-      if (s < 0 && ok && target < cumW[q]) s = q;
-    }
-    if (s < 0) s = last;
-    double below = 0.0, el = 0.0;
-    int base = 0, n = 1;
-#pragma unroll
-    for (int q = 0; q < SMAX; ++q) {
-      if (q == s - 1) below = cumW[q];
-      if (q == s) { el = ell[q]; base = st[q]; n = st[q + 1] - st[q]; }
-    }
-    long long idx = (long long)floor((target - below) / el);
-    idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
-    ell_s = el;
-    return base + (int)idx;
-  }
+// LDS doubles per atom of the segment table for S segments: cumulative
+// weights (S), cumulative counts (S, plus one spare: last usable segment),
+// bounds (S) and starts (S + 1 ints)
+__host__ __device__ constexpr int seg_lds_doubles(int S) { return 3 * S + 1 + (S + 2) / 2; }
 
-  // candidate uniform among candidates of segments with a nonzero bound
-  __device__ __forceinline__ int pick_uniform(double u, double &ell_s) const {
-    const double target = u * nf;
-    int s = -1, last = -1;
-#pragma unroll
-    for (int q = 0; q < SMAX; ++q) {
-      const bool ok = st[q + 1] > st[q] && ell[q] > 0.0;
-      if (ok) last = q;
-      if (s < 0 && ok && target < (double)cumN[q]) s = q;
-    }
-    if (s < 0) s = last;
-    double below = 0.0, el = 0.0;
-    int base = 0, n = 1;
-#pragma unroll
-    for (int q = 0; q < SMAX; ++q) {
-      if (q == s - 1) below = (double)cumN[q];
-      if (q == s) { el = ell[q]; base = st[q]; n = st[q + 1] - st[q]; }
-    }
-    long long idx = (long long)floor(target - below);
-    idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
-    ell_s = el;
-    return base + (int)idx;
-  }
-};
-
-// ------------------------------------------------------------------ J op
-// BPS jumps of the LJ long part over half step h (Alg. 5 in the exponential-
-// clock form of Alg. 2): bound beta |v_i| l_s per candidate, constant over the
-// half step, proposal k at (E_0 + ... + E_k)/Lambda. Block (step, i, phase, k):
-// u0 -> E_k, u2 -> candidate, u3 -> acceptance.
-template <int SMAX>
-__device__ void op_j(const MDView &V, const double4 *__restrict__ X, int i, double4 xi,
-                     double &vx, double &vy, double &vz, const MDOp &op, AtomStats &st,
-                     const double *L, const double *iL) {
-  const int a = V.type[i];
-  SegTab<SMAX> T;
-  T.load(V, i, a, 0, 0.0);
-  const int *row = V.crow + (size_t)i * V.cap_c;
-  const double vn = sqrt(vx * vx + vy * vy + vz * vz);
-  const double Lam = V.beta * vn * T.W;
-  if (!(Lam > 0.0)) return;
-  if (!isfinite(Lam)) { atomicAdd(&V.ctl->nonfinite, 1ull); return; }
-  const uint64_t rep = (uint64_t)V.rep[i];
-  const int64_t li = V.loc[i];
-  double sumE = 0.0;
-  for (int64_t k = 0;; ++k) {
-    if (k >= MD_MAX_PROPOSALS) { atomicAdd(&V.ctl->nonfinite, 1ull); break; }
-    Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
-    sumE += -log(u.u[0]);
-    if (sumE / Lam > op.h) break;
-    double ell;
-    const int j = row[T.pick_by_bound(u.u[2], ell)];
-    double Fx, Fy, Fz;
-    const double F2 = long_grad(V, xi, X[j], a, V.type[j], 0, L, iL, Fx, Fy, Fz);
-    st.nprop++;
-    const double vF = vx * Fx + vy * Fy + vz * Fz;
-    const double p = (vF > 0.0 ? vF : 0.0) / (vn * ell);
-    if (p > 1.0) st.nviol++;
-    if (p > 0.0 && u.u[3] <= p) {
-      const double c = 2.0 * vF / F2;
-      vx -= c * Fx; vy -= c * Fy; vz -= c * Fz;
-      log_jump(V, st, op.step, op.phase, i, j, k);
-    }
-  }
+// wave-scope ordering of LDS writes by some lanes before reads by others
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// ------------------------------------------------------------------ C op
-// Constant acceleration a_i between jumps plus MRZ jumps of the Coulomb long
-// part (Sec. 2.3 step (C), Alg. 1, Alg. 4; eps = eps0 |F| when adaptive). The
-// local bound is re-evaluated after each accepted jump (Sec. 2.4): from
-// (t_e, v_e), B_v = sqrt(|v_e|^2 + tau^2 |a|^2 + 2 tau (v_e.a)_+), tau = h - t_e.
-// Block (step, i, phase, k): u0 -> E_k, u1 -> bound part (adaptive),
-// u2 -> candidate, u3 -> acceptance.
-template <int SMAX>
-__device__ void op_c(const MDView &V, const double4 *__restrict__ X, int i, double4 xi,
-                     double &vx, double &vy, double &vz, double me, double ax, double ay, double az,
-                     const MDOp &op, AtomStats &st, const double *L, const double *iL) {
-  const int a = V.type[i];
-  SegTab<SMAX> T;
-  T.load(V, i, a, 1, fabs(xi.w));
-  const int *row = V.crow + (size_t)i * V.cap_c;
-  const bool adaptive = (V.jc == MD_JUMP_MRZ_ADAPTIVE);
-  const double beta = V.beta, eps0 = V.eps0;
-  const double f = sqrt(beta / (2.0 * MD_PI * me)) / eps0;
-  const double aa = ax * ax + ay * ay + az * az;
-  const uint64_t rep = (uint64_t)V.rep[i];
-  const int64_t li = V.loc[i];
-  const double h = op.h;
-  double vex = vx, vey = vy, vez = vz, te = 0.0;
-  int64_t k = 0;
-  bool done = false;
-  while (!done) {
-    const double tau = h - te;
-    const double vv = vex * vex + vey * vey + vez * vez;
-    const double va = vex * ax + vey * ay + vez * az;
-    const double Bv = sqrt(vv + tau * tau * aa + 2.0 * tau * (va > 0.0 ? va : 0.0));
-    const double bBv = beta * Bv;
-    const double Wb = bBv * T.W;
-    const double Lam = adaptive ? Wb + f * T.nf : (bBv + f) * T.W;
-    if (!(Lam > 0.0) || !isfinite(Lam)) {
-      if (!(Lam <= 0.0)) atomicAdd(&V.ctl->nonfinite, 1ull);
-      vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
-      break;
-    }
-    double sumE = 0.0;
-    for (;; ++k) {
-      if (k >= MD_MAX_PROPOSALS) {
-        atomicAdd(&V.ctl->nonfinite, 1ull);
-        vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
-        done = true;
-        break;
-      }
-      Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
-      sumE += -log(u.u[0]);
-      const double tk = te + sumE / Lam;
-      if (tk > h) {
-        vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
-        done = true;
-        break;
-      }
-      const double dtk = tk - te;
-      const double vkx = vex + dtk * ax, vky = vey + dtk * ay, vkz = vez + dtk * az;
-      double ell;
-      const int pos = (adaptive && !(u.u[1] * Lam < Wb)) ? T.pick_uniform(u.u[2], ell) : T.pick_by_bound(u.u[2], ell);
-      const int j = row[pos];
-      double Fx, Fy, Fz;
-      const double F2 = long_grad(V, xi, X[j], a, V.type[j], 1, L, iL, Fx, Fy, Fz);
-      st.nprop++;
-      const double c = adaptive ? bBv * ell + f : ell * (bBv + f);
-      double lam = 0.0, eta = 0.0;
-      const double vF = vkx * Fx + vky * Fy + vkz * Fz;
-      if (F2 > 0.0) {
-        if (adaptive) {
-          eta = eps0 * sqrt(beta * me) * vF;
-          lam = sqrt(beta / me) / eps0 * theta_p(V, eta);
-        } else {
-          const double Fn = sqrt(F2);
-          eta = eps0 * sqrt(beta * me) * vF / Fn;
-          lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * theta_p(V, eta);
-        }
-      }
-      const double p = lam / c;
-      if (p > 1.0) st.nviol++;
-      if (p > 0.0 && u.u[3] <= p) {
-        int it;
-        const double Z = zsample(eta, V.seed, rep, op.step, li, op.phase, k, it);
-        if (it < 0) atomicAdd(&V.ctl->n_zs_overflow, 1ull);
-        const double coef = adaptive ? 2.0 * eps0 * Z / ((1.0 + eps0 * eps0 * F2) * sqrt(beta * me))
-                                     : 2.0 * eps0 * Z / ((1.0 + eps0 * eps0) * sqrt(beta * me) * sqrt(F2));
-        vex = vkx - coef * Fx; vey = vky - coef * Fy; vez = vkz - coef * Fz;
-        te = tk;
-        log_jump(V, st, op.step, op.phase, i, j, k);
-        ++k;
-        break;  // new epoch
-      }
-    }
-  }
-}
-
-// --------------------------------------------------- lane-group chains
-// G lanes cooperate on one atom's chain. Lane r holds proposal kk (kk = r mod
-// G) of the window [w0, w0 + G): its velocity-independent part (Philox block,
-// candidate, gathered position, long-range gradient) is computed once; the
-// velocity-dependent part (time, acceptance) is evaluated for the whole
-// window assuming no jump inside it, and the first event (acceptance or end
-// of the half step, by proposal order) is found with a group minimum. Only
-// proposals after an accepted jump are re-evaluated. Proposal times are
-// prefix sums taken in proposal order, so every decision is the one the
-// sequential chain takes.
 template <int G>
 __device__ __forceinline__ int group_min(int x) {
 #pragma unroll
@@ -353,32 +158,111 @@ __device__ __forceinline__ int group_sum(int x) {
   return x;
 }
 
-// Z by rejection with G iterations in parallel: lane r tries iteration
-// base + r; the first accepted iteration (in order) wins.
+// Segment table of one atom for one jump component: bound l_q per segment,
+// cumulative weights sum n_q l_q and cumulative counts of the candidates whose
+// bound is nonzero. The first segment whose cumulative value exceeds a target
+// always has n_q l_q > 0, so the searches need no validity test.
+struct SegL {
+  double *cw, *cn, *el;
+  int *st;
+  int S, last;
+  double W, nf;
+
+  __device__ __forceinline__ void attach(double *base, int S_) {
+    S = S_;
+    cw = base; cn = base + S; el = base + 2 * S + 1;
+    st = (int *)(base + 3 * S + 1);
+  }
+  // lane r == 0 of the group writes; every lane reads back the totals
+  __device__ __forceinline__ void build(const MDView &V, int i, int a, int coul, double absq, int r) {
+    wave_lds_sync();   // earlier reads of the table by the group are complete
+    if (r == 0) {
+      const int *sst = V.segst + (size_t)i * (S + 1);
+      double w = 0.0;
+      int c = 0, lst = -1;
+      int s0 = sst[0];
+      st[0] = s0;
+      for (int q = 0; q < S; ++q) {
+        const int s1 = sst[q + 1];
+        const double l = seg_ell(V, a, q, coul, absq);
+        const int nq = s1 - s0;
+        w += (double)nq * l;
+        if (l > 0.0) c += nq;
+        if (nq > 0 && l > 0.0) lst = q;
+        cw[q] = w; cn[q] = (double)c; el[q] = l; st[q + 1] = s1;
+        s0 = s1;
+      }
+      cn[S] = (double)lst;   // spare slot of the count array: last usable segment
+    }
+    wave_lds_sync();
+    W = cw[S - 1];
+    nf = cn[S - 1];
+    last = (int)cn[S];
+  }
+  __device__ __forceinline__ int first_above(const double *c, double target) const {
+    int lo = 0, hi = S;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (target < c[mid]) hi = mid; else lo = mid + 1;
+    }
+    return lo < S ? lo : last;
+  }
+  // candidate in proportion to its bound: segment by n_q l_q, then uniform
+  // inside from the residual
+  __device__ __forceinline__ int pick_by_bound(double u, double &ell_s) const {
+    const double target = u * W;
+    const int s = first_above(cw, target);
+    const double below = s > 0 ? cw[s - 1] : 0.0;
+    const double el_s = el[s];
+    const int base = st[s], n = st[s + 1] - base;
+    long long idx = (long long)floor((target - below) / el_s);
+    idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
+    ell_s = el_s;
+    return base + (int)idx;
+  }
+  // candidate uniform among those with a nonzero bound
+  __device__ __forceinline__ int pick_uniform(double u, double &ell_s) const {
+    const double target = u * nf;
+    const int s = first_above(cn, target);
+    const double below = s > 0 ? cn[s - 1] : 0.0;
+    const int base = st[s], n = st[s + 1] - base;
+    long long idx = (long long)floor(target - below);
+    idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
+    ell_s = el[s];
+    return base + (int)idx;
+  }
+};
+
+// One Z iteration (Sec. 2.4 regimes) from the block's four uniforms.
+__device__ __forceinline__ bool z_iteration(double eta, double u0, double u1, double u2, double u3, double &z) {
+  if (eta > 0.0) {
+    const double p_ray = 1.0 / (1.0 + eta * 2.5066282746310002);
+    const double rad = sqrt(-2.0 * log(u1));
+    const double y = (u0 < p_ray) ? rad : rad * cos(2.0 * MD_PI * u2);
+    z = eta + y;
+    return (y >= 0.0) || (z > 0.0 && u3 <= z / eta);
+  } else if (eta >= -1.0) {
+    z = sqrt(-2.0 * log(u0));
+    return u1 <= exp(eta * z);
+  }
+  z = -(log(u0) + log(u1)) / (-eta);
+  return u2 <= exp(-0.5 * z * z);
+}
+
+// Z iterations it0, it0 + 1, ... with G of them in parallel: lane r tries
+// it = base + r; the first accepted iteration (in order) wins.
 template <int G>
 __device__ double zsample_grp(double eta, uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
-                              int phase, int64_t k, int r, int &overflow) {
+                              int phase, int64_t k, int r, int it0, int &overflow) {
   overflow = 0;
-  for (int base = 0; base < MD_ZS_MAXIT; base += G) {
+  for (int base = it0; base < MD_ZS_MAXIT; base += G) {
     const int it = base + r;
     double z = 0.0;
     bool ok = false;
     if (it < MD_ZS_MAXIT) {
-      uint64_t tag = (uint64_t)(uint32_t)phase | ((uint64_t)(it + 1) << 24);
+      const uint64_t tag = (uint64_t)(uint32_t)phase | ((uint64_t)(it + 1) << 24);
       Uni4 u = draw4(seed, rep, step, atom, tag, k);
-      if (eta > 0.0) {
-        double p_ray = 1.0 / (1.0 + eta * 2.5066282746310002);
-        double rad = sqrt(-2.0 * log(u.u[1]));
-        double y = (u.u[0] < p_ray) ? rad : rad * cos(2.0 * MD_PI * u.u[2]);
-        z = eta + y;
-        ok = (y >= 0.0) || (z > 0.0 && u.u[3] <= z / eta);
-      } else if (eta >= -1.0) {
-        z = sqrt(-2.0 * log(u.u[0]));
-        ok = u.u[1] <= exp(eta * z);
-      } else {
-        z = -(log(u.u[0]) + log(u.u[1])) / (-eta);
-        ok = u.u[2] <= exp(-0.5 * z * z);
-      }
+      ok = z_iteration(eta, u.u[0], u.u[1], u.u[2], u.u[3], z);
     }
     const int first = group_min<G>(ok ? r : G);
     if (first < G) return __shfl(z, first, G);
@@ -387,24 +271,32 @@ __device__ double zsample_grp(double eta, uint64_t seed, uint64_t rep, int64_t s
   return 0.5 * (eta + sqrt(eta * eta + 4.0));
 }
 
-struct PropBranch { int j; double Fx, Fy, Fz, F2, ell; };
-
-template <int SMAX>
-__device__ __forceinline__ void fill_branch(const MDView &V, const double4 *__restrict__ X, const int *row,
-                                            const SegTab<SMAX> &T, bool uniform, double u2, double4 xi, int a,
-                                            int coul, const double *L, const double *iL, PropBranch &b) {
-  const int pos = uniform ? T.pick_uniform(u2, b.ell) : T.pick_by_bound(u2, b.ell);
-  b.j = row[pos];
-  b.F2 = long_grad(V, xi, X[b.j], a, V.type[b.j], coul, L, iL, b.Fx, b.Fy, b.Fz);
+// Left fold base + E_w0 + ... + E_(w0+r) over the window, in proposal order.
+template <int G>
+__device__ __forceinline__ double window_fold(const double *ringE, int64_t w0, int r, double base, double &tot) {
+  constexpr int M = 2 * G;
+  double s = base, t = base;
+#pragma unroll
+  for (int m = 0; m < G; ++m) {
+    t += ringE[(int)((w0 + m) & (M - 1))];
+    if (m == r) s = t;
+  }
+  tot = t;
+  return s;
 }
 
-template <int SMAX, int G>
-__device__ void op_j_grp(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
-                         double &vx, double &vy, double &vz, const MDOp &op, AtomStats &st,
-                         const double *L, const double *iL) {
+// ------------------------------------------------------------------ J op
+// BPS jumps of the LJ long part over half step h (Alg. 5 in the exponential-
+// clock form of Alg. 2): bound beta |v_i| l_s per candidate, constant over the
+// half step (a reflection keeps |v|), proposal k at (E_0 + ... + E_k)/Lambda.
+// Block (step, i, phase, k): u0 -> E_k, u2 -> candidate, u3 -> acceptance.
+template <int G>
+__device__ void op_j_ring(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
+                          double &vx, double &vy, double &vz, const MDOp &op, AtomStats &st,
+                          const double *L, const double *iL, double *ring, SegL &T) {
+  constexpr int M = 2 * G;
   const int a = V.type[i];
-  SegTab<SMAX> T;
-  T.load(V, i, a, 0, 0.0);
+  T.build(V, i, a, 0, 0.0, r);
   const int *row = V.crow + (size_t)i * V.cap_c;
   const double vn = sqrt(vx * vx + vy * vy + vz * vz);
   const double Lam = V.beta * vn * T.W;
@@ -412,64 +304,72 @@ __device__ void op_j_grp(const MDView &V, const double4 *__restrict__ X, int i, 
   if (!isfinite(Lam)) { if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull); return; }
   const uint64_t rep = (uint64_t)V.rep[i];
   const int64_t li = V.loc[i];
-  int64_t w0 = 0, kk = r;
-  double E = 0.0, u3 = 0.0;
-  PropBranch pb;
-  auto reload = [&]() {
-    Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, kk);
-    E = -log(u.u[0]);
-    u3 = u.u[3];
-    fill_branch<SMAX>(V, X, row, T, false, u.u[2], xi, a, 0, L, iL, pb);
-  };
-  reload();
-  double base = 0.0;  // sum of E over proposals before the window
+  int64_t w0 = 0, computed = 0;
+  double base = 0.0;  // fold of E over the proposals before the window
   for (;;) {
     if (w0 >= MD_MAX_PROPOSALS) { if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull); break; }
-    const int rank = (int)(kk - w0);
-    double s = base, tot = base;
-#pragma unroll
-    for (int m = 0; m < G; ++m) {
-      const double Em = __shfl(E, (int)((w0 + m) % G), G);
-      tot += Em;
-      if (m <= rank) s = tot;
+    if (computed < w0 + G) {
+      const int64_t k = computed + r;
+      const int sl = (int)(k & (M - 1));
+      wave_lds_sync();   // reads of the slots being replaced are complete
+      Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
+      double ell, Fx, Fy, Fz;
+      const int j = row[T.pick_by_bound(u.u[2], ell)];
+      const double F2 = long_grad(V, xi, X[j], a, V.type[j], 0, L, iL, Fx, Fy, Fz);
+      ring[RF_E * M + sl] = -log(u.u[0]);
+      ring[RF_U3 * M + sl] = u.u[3];
+      ring[RF_BX * M + sl] = Fx; ring[RF_BY * M + sl] = Fy; ring[RF_BZ * M + sl] = Fz;
+      ring[RF_B2 * M + sl] = F2; ring[RF_BL * M + sl] = ell;
+      ring[RF_BJ * M + sl] = (double)j;
+      computed += G;
+      wave_lds_sync();
     }
+    const int sl = (int)((w0 + r) & (M - 1));
+    double tot;
+    const double s = window_fold<G>(ring + RF_E * M, w0, r, base, tot);
     const bool out = s / Lam > op.h;
-    const double vF = vx * pb.Fx + vy * pb.Fy + vz * pb.Fz;
-    const double p = (vF > 0.0 ? vF : 0.0) / (vn * pb.ell);
-    const bool acc = !out && p > 0.0 && u3 <= p;
-    const int first = group_min<G>((out || acc) ? rank : G);
-    // proposals evaluated in this window: ranks < first, plus an accepted one
-    const bool counted = rank < first || (rank == first && acc);
-    const int nev = group_sum<G>(counted ? 1 : 0);
-    const int nvi = group_sum<G>((counted && p > 1.0) ? 1 : 0);
-    st.nprop += nev;
-    st.nviol += nvi;
-    if (first == G) { base = tot; w0 += G; kk += G; reload(); continue; }
-    const int src = (int)((w0 + first) % G);
-    const bool out_f = __shfl((int)out, src, G) != 0;
-    if (out_f) break;
-    const double Fx = __shfl(pb.Fx, src, G), Fy = __shfl(pb.Fy, src, G), Fz = __shfl(pb.Fz, src, G);
-    const double F2 = __shfl(pb.F2, src, G);
-    const int j = __shfl(pb.j, src, G);
-    const double vFs = vx * Fx + vy * Fy + vz * Fz;
+    const double Fx = ring[RF_BX * M + sl], Fy = ring[RF_BY * M + sl], Fz = ring[RF_BZ * M + sl];
+    const double ell = ring[RF_BL * M + sl];
+    const double vF = vx * Fx + vy * Fy + vz * Fz;
+    const double p = (vF > 0.0 ? vF : 0.0) / (vn * ell);
+    const bool acc = !out && p > 0.0 && ring[RF_U3 * M + sl] <= p;
+    const int first = group_min<G>((out || acc) ? r : G);
+    // proposals evaluated in this window: ranks before the event, plus an accepted one
+    const bool counted = r < first || (r == first && acc);
+    st.nprop += group_sum<G>(counted ? 1 : 0);
+    st.nviol += group_sum<G>((counted && p > 1.0) ? 1 : 0);
+    if (first == G) { base = tot; w0 += G; continue; }
+    if (__shfl((int)out, first, G)) break;
+    const int fs = (int)((w0 + first) & (M - 1));
+    const double Fxs = ring[RF_BX * M + fs], Fys = ring[RF_BY * M + fs], Fzs = ring[RF_BZ * M + fs];
+    const double F2 = ring[RF_B2 * M + fs];
+    const int j = (int)ring[RF_BJ * M + fs];
+    const double vFs = vx * Fxs + vy * Fys + vz * Fzs;
     const double c = 2.0 * vFs / F2;
-    vx -= c * Fx; vy -= c * Fy; vz -= c * Fz;
+    vx -= c * Fxs; vy -= c * Fys; vz -= c * Fzs;
     const int64_t kstar = w0 + first;
-    if (r == src) log_jump(V, st, op.step, op.phase, i, j, kstar);
+    if (r == first) log_jump(V, st, op.step, op.phase, i, j, kstar);
     else log_jump_hash_only(V, st, op.step, op.phase, j);
-    base = __shfl(s, src, G);
+    base = __shfl(s, first, G);
     w0 = kstar + 1;
-    if (kk < w0) { kk += G; reload(); }
   }
 }
 
-template <int SMAX, int G>
-__device__ void op_c_grp(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
-                         double &vx, double &vy, double &vz, double me, double ax, double ay, double az,
-                         const MDOp &op, AtomStats &st, const double *L, const double *iL) {
+// ------------------------------------------------------------------ C op
+// Constant acceleration a_i between jumps plus MRZ jumps of the Coulomb long
+// part (Sec. 2.3 step (C), Alg. 1, Alg. 4; eps = eps0 |F| when adaptive). The
+// local bound is re-evaluated after each accepted jump (Sec. 2.4): from
+// (t_e, v_e), B_v = sqrt(|v_e|^2 + tau^2 |a|^2 + 2 tau (v_e.a)_+), tau = h - t_e.
+// Block (step, i, phase, k): u0 -> E_k, u1 -> bound part (adaptive),
+// u2 -> candidate, u3 -> acceptance.
+template <int G>
+__device__ void op_c_ring(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
+                          double &vx, double &vy, double &vz, double me, double ax, double ay, double az,
+                          const MDOp &op, AtomStats &st, const double *L, const double *iL, double *ring,
+                          SegL &T) {
+  constexpr int M = 2 * G;
   const int a = V.type[i];
-  SegTab<SMAX> T;
-  T.load(V, i, a, 1, fabs(xi.w));
+  T.build(V, i, a, 1, fabs(xi.w), r);
   const int *row = V.crow + (size_t)i * V.cap_c;
   const bool adaptive = (V.jc == MD_JUMP_MRZ_ADAPTIVE);
   const double beta = V.beta, eps0 = V.eps0;
@@ -478,18 +378,7 @@ __device__ void op_c_grp(const MDView &V, const double4 *__restrict__ X, int i, 
   const uint64_t rep = (uint64_t)V.rep[i];
   const int64_t li = V.loc[i];
   const double h = op.h;
-  int64_t w0 = 0, kk = r;
-  double E = 0.0, u1 = 0.0, u3 = 0.0;
-  PropBranch pb, pf;
-  auto reload = [&]() {
-    Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, kk);
-    E = -log(u.u[0]);
-    u1 = u.u[1];
-    u3 = u.u[3];
-    fill_branch<SMAX>(V, X, row, T, false, u.u[2], xi, a, 1, L, iL, pb);
-    if (adaptive) fill_branch<SMAX>(V, X, row, T, true, u.u[2], xi, a, 1, L, iL, pf);
-  };
-  reload();
+  int64_t w0 = 0, computed = 0;
   double vex = vx, vey = vy, vez = vz, te = 0.0;
   for (;;) {
     // epoch: bound from (t_e, v_e) over the rest of the half step
@@ -506,83 +395,111 @@ __device__ void op_c_grp(const MDView &V, const double4 *__restrict__ X, int i, 
       return;
     }
     double base = 0.0;
-    bool jumped = false;
-    while (!jumped) {
+    for (;;) {
       if (w0 >= MD_MAX_PROPOSALS) {
         if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull);
         vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
         return;
       }
-      const int rank = (int)(kk - w0);
-      double s = base, tot = base;
-#pragma unroll
-      for (int m = 0; m < G; ++m) {
-        const double Em = __shfl(E, (int)((w0 + m) % G), G);
-        tot += Em;
-        if (m <= rank) s = tot;
+      if (computed < w0 + G) {
+        const int64_t k = computed + r;
+        const int sl = (int)(k & (M - 1));
+        wave_lds_sync();   // reads of the slots being replaced are complete
+        Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
+        double ell, Fx, Fy, Fz;
+        int j = row[T.pick_by_bound(u.u[2], ell)];
+        double F2 = long_grad(V, xi, X[j], a, V.type[j], 1, L, iL, Fx, Fy, Fz);
+        ring[RF_E * M + sl] = -log(u.u[0]);
+        ring[RF_U1 * M + sl] = u.u[1];
+        ring[RF_U3 * M + sl] = u.u[3];
+        ring[RF_BX * M + sl] = Fx; ring[RF_BY * M + sl] = Fy; ring[RF_BZ * M + sl] = Fz;
+        ring[RF_B2 * M + sl] = F2; ring[RF_BL * M + sl] = ell; ring[RF_BJ * M + sl] = (double)j;
+        if (adaptive) {
+          j = row[T.pick_uniform(u.u[2], ell)];
+          F2 = long_grad(V, xi, X[j], a, V.type[j], 1, L, iL, Fx, Fy, Fz);
+          ring[RF_FX * M + sl] = Fx; ring[RF_FY * M + sl] = Fy; ring[RF_FZ * M + sl] = Fz;
+          ring[RF_F2 * M + sl] = F2; ring[RF_FL * M + sl] = ell; ring[RF_FJ * M + sl] = (double)j;
+        }
+        Uni4 z = draw4(V.seed, rep, op.step, li, (uint64_t)(uint32_t)op.phase | (1ull << 24), k);
+        ring[RF_Z0 * M + sl] = z.u[0]; ring[RF_Z1 * M + sl] = z.u[1];
+        ring[RF_Z2 * M + sl] = z.u[2]; ring[RF_Z3 * M + sl] = z.u[3];
+        computed += G;
+        wave_lds_sync();
       }
+      const int sl = (int)((w0 + r) & (M - 1));
+      double tot;
+      const double s = window_fold<G>(ring + RF_E * M, w0, r, base, tot);
       const double tk = te + s / Lam;
       const bool out = tk > h;
       const double dtk = tk - te;
       const double vkx = vex + dtk * ax, vky = vey + dtk * ay, vkz = vez + dtk * az;
-      const bool use_f = adaptive && !(u1 * Lam < Wb);
-      const PropBranch &b = use_f ? pf : pb;
-      const double c = adaptive ? bBv * b.ell + f : b.ell * (bBv + f);
+      const bool use_f = adaptive && !(ring[RF_U1 * M + sl] * Lam < Wb);
+      const int fb = use_f ? (RF_FX - RF_BX) * M : 0;
+      const double Fx = ring[fb + RF_BX * M + sl], Fy = ring[fb + RF_BY * M + sl], Fz = ring[fb + RF_BZ * M + sl];
+      const double F2 = ring[fb + RF_B2 * M + sl], ell = ring[fb + RF_BL * M + sl];
+      const double c = adaptive ? bBv * ell + f : ell * (bBv + f);
       double lam = 0.0, eta = 0.0;
-      const double vF = vkx * b.Fx + vky * b.Fy + vkz * b.Fz;
-      if (!out && b.F2 > 0.0) {
+      const double vF = vkx * Fx + vky * Fy + vkz * Fz;
+      if (!out && F2 > 0.0) {
         if (adaptive) {
           eta = eps0 * sqrt(beta * me) * vF;
           lam = sqrt(beta / me) / eps0 * theta_p(V, eta);
         } else {
-          const double Fn = sqrt(b.F2);
+          const double Fn = sqrt(F2);
           eta = eps0 * sqrt(beta * me) * vF / Fn;
           lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * theta_p(V, eta);
         }
       }
       const double p = lam / c;
-      const bool acc = !out && p > 0.0 && u3 <= p;
-      const int first = group_min<G>((out || acc) ? rank : G);
-      const bool counted = rank < first || (rank == first && acc);
+      const bool acc = !out && p > 0.0 && ring[RF_U3 * M + sl] <= p;
+      const int first = group_min<G>((out || acc) ? r : G);
+      const bool counted = r < first || (r == first && acc);
       st.nprop += group_sum<G>(counted ? 1 : 0);
       st.nviol += group_sum<G>((counted && p > 1.0) ? 1 : 0);
-      if (first == G) { base = tot; w0 += G; kk += G; reload(); continue; }
-      const int src = (int)((w0 + first) % G);
-      if (__shfl((int)out, src, G)) {
+      if (first == G) { base = tot; w0 += G; continue; }
+      if (__shfl((int)out, first, G)) {
         vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
         return;
       }
-      const double etas = __shfl(eta, src, G);
-      const double F2 = __shfl(b.F2, src, G);
-      const double Fx = __shfl(b.Fx, src, G), Fy = __shfl(b.Fy, src, G), Fz = __shfl(b.Fz, src, G);
-      const int j = __shfl(b.j, src, G);
-      const double tks = __shfl(tk, src, G);
+      const double etas = __shfl(eta, first, G);
+      const double tks = __shfl(tk, first, G);
+      const double F2s = __shfl(F2, first, G);
+      const double Fxs = __shfl(Fx, first, G), Fys = __shfl(Fy, first, G), Fzs = __shfl(Fz, first, G);
+      const int fbs = __shfl(fb, first, G);
+      const int fs = (int)((w0 + first) & (M - 1));
+      const int j = (int)ring[fbs + RF_BJ * M + fs];
       const int64_t kstar = w0 + first;
-      int ovf;
-      const double Z = zsample_grp<G>(etas, V.seed, rep, op.step, li, op.phase, kstar, r, ovf);
-      if (ovf && r == 0) atomicAdd(&V.ctl->n_zs_overflow, 1ull);
-      const double coef = adaptive ? 2.0 * eps0 * Z / ((1.0 + eps0 * eps0 * F2) * sqrt(beta * me))
-                                   : 2.0 * eps0 * Z / ((1.0 + eps0 * eps0) * sqrt(beta * me) * sqrt(F2));
+      double Z;
+      if (!z_iteration(etas, ring[RF_Z0 * M + fs], ring[RF_Z1 * M + fs], ring[RF_Z2 * M + fs],
+                       ring[RF_Z3 * M + fs], Z)) {
+        int ovf;
+        Z = zsample_grp<G>(etas, V.seed, rep, op.step, li, op.phase, kstar, r, 1, ovf);
+        if (ovf && r == 0) atomicAdd(&V.ctl->n_zs_overflow, 1ull);
+      }
+      const double coef = adaptive ? 2.0 * eps0 * Z / ((1.0 + eps0 * eps0 * F2s) * sqrt(beta * me))
+                                   : 2.0 * eps0 * Z / ((1.0 + eps0 * eps0) * sqrt(beta * me) * sqrt(F2s));
       const double dts = tks - te;
-      vex = vex + dts * ax - coef * Fx;
-      vey = vey + dts * ay - coef * Fy;
-      vez = vez + dts * az - coef * Fz;
+      vex = vex + dts * ax - coef * Fxs;
+      vey = vey + dts * ay - coef * Fys;
+      vez = vez + dts * az - coef * Fzs;
       te = tks;
-      if (r == src) log_jump(V, st, op.step, op.phase, i, j, kstar);
+      if (r == first) log_jump(V, st, op.step, op.phase, i, j, kstar);
       else log_jump_hash_only(V, st, op.step, op.phase, j);
       w0 = kstar + 1;
-      if (kk < w0) { kk += G; reload(); }
-      jumped = true;
+      break;  // new epoch
     }
   }
 }
 
 // -------------------------------------------------------------- k_local
 // G lanes per atom (G = 1: one lane runs the whole chain). B/A/O ops are
-// repeated by every lane of the group; lane 0 writes the atom back.
-template <int SMAX, int G>
+// repeated by every lane of the group; lane 0 writes the atom back. Dynamic
+// LDS (programs with jumps): the proposal rings of the block's 64/G atoms,
+// then their segment tables.
+template <int G>
 __global__ __launch_bounds__(64) void k_local(MDView V, MDProg P, const double4 *__restrict__ Xs,
                                                double4 *__restrict__ Xd) {
+  extern __shared__ double lds_chain[];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid / G, r = gid - (gid / G) * G;
   // displacement maximum: per-block LDS max (blocks are single waves), then
@@ -605,6 +522,11 @@ __global__ __launch_bounds__(64) void k_local(MDView V, MDProg P, const double4 
   for (int o = 0; o < P.nops; ++o) jumps |= (P.ops[o].kind == OP_J || P.ops[o].kind == OP_C);
   if (jumps) { st.nprop = V.nprop[i]; st.nacc = V.nacc[i]; st.nviol = V.nviol[i]; st.hash = V.hash[i]; }
   double4 fn = V.fnb[i], fb = V.fb[i];
+  constexpr int APB = 64 / G;   // atoms per block
+  const int ab = (int)threadIdx.x / G;
+  double *ring = lds_chain + ab * (RF_N * 2 * G);
+  SegL T;
+  T.attach(lds_chain + APB * (RF_N * 2 * G) + ab * seg_lds_doubles(V.S), V.S);
   const int64_t sbase = P.dev_step ? (int64_t)V.ctl->step_base : 0;
   double disp2 = 0.0;
   bool has_disp = false;
@@ -634,15 +556,13 @@ __global__ __launch_bounds__(64) void k_local(MDView V, MDProg P, const double4 
         vz = op.c1 * vz + op.c2 * sd * gz;
       } break;
       case OP_J:
-        if (G == 1) op_j<SMAX>(V, Xs, i, xi, vx, vy, vz, op, st, L, iL);
-        else op_j_grp<SMAX, G>(V, Xs, i, r, xi, vx, vy, vz, op, st, L, iL);
+        op_j_ring<G>(V, Xs, i, r, xi, vx, vy, vz, op, st, L, iL, ring, T);
         break;
       case OP_C: {
         double fx = fn.x + (op.flags == 0 ? fb.x : 0.0);
         double fy = fn.y + (op.flags == 0 ? fb.y : 0.0);
         double fz = fn.z + (op.flags == 0 ? fb.z : 0.0);
-        if (G == 1) op_c<SMAX>(V, Xs, i, xi, vx, vy, vz, me, fx / me, fy / me, fz / me, op, st, L, iL);
-        else op_c_grp<SMAX, G>(V, Xs, i, r, xi, vx, vy, vz, me, fx / me, fy / me, fz / me, op, st, L, iL);
+        op_c_ring<G>(V, Xs, i, r, xi, vx, vy, vz, me, fx / me, fy / me, fz / me, op, st, L, iL, ring, T);
       } break;
       case OP_DISP:
         disp2 = 0.0;
@@ -1180,28 +1100,29 @@ __global__ void k_set_step(MDCtl *ctl, long long step) { ctl->step_base = step; 
 // ------------------------------------------------------------- launchers
 #define CHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
-template <int SMAX>
-static void launch_local_s(const MDView &V, const MDProg &P, const double4 *Xs, double4 *Xd, hipStream_t s) {
-  const int G = V.chain_lanes;
-  const long long threads = (long long)V.n * G;
-  const int nb = (int)((threads + 63) / 64);   // wave-sized blocks spread the few long waves over all CUs
-  switch (G) {
-    case 1: hipLaunchKernelGGL((k_local<SMAX, 1>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd); break;
-    case 2: hipLaunchKernelGGL((k_local<SMAX, 2>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd); break;
-    case 4: hipLaunchKernelGGL((k_local<SMAX, 4>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd); break;
-    case 8: hipLaunchKernelGGL((k_local<SMAX, 8>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd); break;
-    default: hipLaunchKernelGGL((k_local<SMAX, 16>), dim3(nb), dim3(64), 0, s, V, P, Xs, Xd); break;
-  }
+// LDS bytes of one k_local block with G lanes per atom
+static size_t chain_lds_bytes(int G, int S) {
+  return sizeof(double) * (size_t)(64 / G) * (size_t)(RF_N * 2 * G + seg_lds_doubles(S));
 }
 
 hipError_t launch_local(const MDView &V, const MDProg &P, const double4 *Xs, double4 *Xd, hipStream_t s) {
-  if (V.S <= 4) launch_local_s<4>(V, P, Xs, Xd, s);
-  else if (V.S <= 8) launch_local_s<8>(V, P, Xs, Xd, s);
-  else if (V.S <= 12) launch_local_s<12>(V, P, Xs, Xd, s);
-  else if (V.S <= 16) launch_local_s<16>(V, P, Xs, Xd, s);
-  else launch_local_s<32>(V, P, Xs, Xd, s);
+  const int G = V.chain_lanes;
+  const long long threads = (long long)V.n * G;
+  const int nb = (int)((threads + 63) / 64);   // wave-sized blocks spread the few long waves over all CUs
+  bool jumps = false;
+  for (int o = 0; o < P.nops; ++o) jumps |= (P.ops[o].kind == OP_J || P.ops[o].kind == OP_C);
+  const size_t lds = jumps ? chain_lds_bytes(G, V.S) : 0;
+  switch (G) {
+    case 1: hipLaunchKernelGGL((k_local<1>), dim3(nb), dim3(64), lds, s, V, P, Xs, Xd); break;
+    case 2: hipLaunchKernelGGL((k_local<2>), dim3(nb), dim3(64), lds, s, V, P, Xs, Xd); break;
+    case 4: hipLaunchKernelGGL((k_local<4>), dim3(nb), dim3(64), lds, s, V, P, Xs, Xd); break;
+    case 8: hipLaunchKernelGGL((k_local<8>), dim3(nb), dim3(64), lds, s, V, P, Xs, Xd); break;
+    default: hipLaunchKernelGGL((k_local<16>), dim3(nb), dim3(64), lds, s, V, P, Xs, Xd); break;
+  }
   return hipGetLastError();
 }
+
+size_t chain_lds_bytes_host(int G, int S) { return chain_lds_bytes(G, S); }
 
 hipError_t launch_rebuild(const MDView &V, const double4 *X, int want, int slot, int forced, int autob,
                           double thr2, int pc, int ps, bool check_only, int count, hipStream_t s) {
