@@ -59,7 +59,7 @@ def timed(sim, fn, steps, warmup):
     sim.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = {k: sim.profile_read(k) for k in range(4)}
+    prof = {k: sim.profile_read(k) for k in range(5)}
     sim.profile(False)
     return t1 - t0, prof
 
@@ -128,7 +128,8 @@ def main():
               f"{pairs_full} pairs", flush=True)
 
     # dominant kernel of the JUMP step and its roofline
-    names = {0: "k_local (B/A/O + J/C jump chains)", 1: "k_force (short pairs)", 2: "k_bonded", 3: "row rebuild"}
+    names = {0: "k_local (B/A/O updates)", 1: "k_force (short pairs)", 2: "k_bonded", 3: "row rebuild",
+             4: "k_chain (J/C jump chains)"}
     dom = max(prof_j, key=lambda k: prof_j[k][0])
     tot_ms, launches = prof_j[dom]
     avg_s = tot_ms * 1e-3 / max(launches, 1)
@@ -136,8 +137,8 @@ def main():
         work = pairs_short * FLOP_PER_SHORT_PAIR
         roof = {"kernel": names[dom], "bound": "alu", "achieved": work / avg_s / 1e12,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
-    elif dom == 0:
-        # per launch: one step's per-atom programs; work = proposals x pair-gradient flops
+    elif dom == 4:
+        # per launch: one step's chains; work = proposals x pair-gradient flops
         work = props * FLOP_PER_SHORT_PAIR
         roof = {"kernel": names[dom], "bound": "alu", "achieved": work / avg_s / 1e12,
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}

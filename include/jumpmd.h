@@ -192,11 +192,12 @@ int md_run_phase(md_ctx *ctx, int32_t which, int32_t phase, double h);
  * starts recording (resets the sums); md_profile_read synchronises and
  * returns the total milliseconds and launch count of kernel `kid`
  * (MD_K_* below). */
-#define MD_K_LOCAL 0      /* fused per-atom B/A/O/J/C kernel */
+#define MD_K_LOCAL 0      /* per-atom B/A/O updates and displacement check */
 #define MD_K_FORCE 1      /* non-bonded pair forces */
 #define MD_K_BONDED 2
 #define MD_K_REBUILD 3    /* all neighbour-row kernels of a step */
-#define MD_K_COUNT 4
+#define MD_K_CHAIN 4      /* jump chains (J and C ops, with the kicks between them) */
+#define MD_K_COUNT 5
 int md_profile(md_ctx *ctx, int32_t enable);
 int md_profile_read(md_ctx *ctx, int32_t kid, double *total_ms, int64_t *launches);
 

@@ -209,6 +209,8 @@ static void add_disp(ProgBuilder &b, int slot) {
   b.P.reset_slot = slot ^ 1;
 }
 
+// A step program runs as at most two launches: the position-preserving
+// prefix that holds the jump chains (k_chain), then the rest (k_local).
 static int run_prog(md_ctx *c, ProgBuilder &b) {
   if (b.P.nops == 0) return MD_OK;
   if (b.has_chain_after_a) return fail(c, MD_ERR_ARG, "internal: jump chain after drift");
@@ -217,11 +219,33 @@ static int run_prog(md_ctx *c, ProgBuilder &b) {
     b.P.dev_step = 1;
     for (int o = 0; o < b.P.nops; ++o) b.P.ops[o].step -= c->step_rel0;
   }
-  hipEvent_t e0{};
-  prof_begin(c, MD_K_LOCAL, &e0);
-  double4 *dst = b.has_a ? Xoth(c) : nullptr;
-  HIPCHK(c, launch_local(c->V, b.P, Xcur(c), dst, c->stream));
-  prof_end(c, MD_K_LOCAL, e0);
+  int cut = 0;
+  bool chain = false;
+  while (cut < b.P.nops && (b.P.ops[cut].kind == OP_B || b.P.ops[cut].kind == OP_J || b.P.ops[cut].kind == OP_C)) {
+    chain |= (b.P.ops[cut].kind != OP_B);
+    ++cut;
+  }
+  for (int o = cut; o < b.P.nops; ++o)
+    if (b.P.ops[o].kind == OP_J || b.P.ops[o].kind == OP_C) return fail(c, MD_ERR_ARG, "internal: jump chain after drift");
+  MDProg rest = b.P;
+  if (chain) {
+    MDProg pre = b.P;
+    pre.nops = cut;
+    pre.reset_slot = -1;
+    hipEvent_t e0{};
+    prof_begin(c, MD_K_CHAIN, &e0);
+    HIPCHK(c, launch_chain(c->V, pre, Xcur(c), c->stream));
+    prof_end(c, MD_K_CHAIN, e0);
+    rest.nops = b.P.nops - cut;
+    for (int o = 0; o < rest.nops; ++o) rest.ops[o] = b.P.ops[cut + o];
+  }
+  if (rest.nops > 0) {
+    hipEvent_t e0{};
+    prof_begin(c, MD_K_LOCAL, &e0);
+    double4 *dst = b.has_a ? Xoth(c) : nullptr;
+    HIPCHK(c, launch_local(c->V, rest, Xcur(c), dst, c->stream));
+    prof_end(c, MD_K_LOCAL, e0);
+  }
   if (b.has_a) {
     c->cur ^= 1;
     c->fkind = -1;
@@ -402,23 +426,18 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.seed = p->seed;
   {
     // automatic: the most lanes per atom whose waves still fit the device in
-    // one round (LDS of the proposal rings and segment tables per block)
+    // one round (resident blocks per CU from the kernel's registers and LDS)
     int g = p->chain_lanes;
     const int S = V.nt * V.nr;
     if (g <= 0) {
-      int dev = 0, ncu = 256, lds_cu = 160 * 1024;
-      if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess && v > 0)
-          lds_cu = v;
-      }
+      int dev = 0, ncu = 256;
+      if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
       g = 1;
-      for (int c = 2; c <= 16; c *= 2) {
-        const size_t b = chain_lds_bytes_host(c, S);
-        if (b > 65536) continue;
-        const long long slots = (long long)ncu * (long long)(lds_cu / (long long)b);
-        if ((long long)n * c / 64 <= slots) g = c;
+      for (int cand = 2; cand <= 16; cand *= 2) {
+        if (chain_lds_bytes_host(cand, S) > 65536) continue;
+        int bpc = chain_blocks_per_cu(cand, S);
+        if (bpc <= 0) bpc = 4;
+        if ((long long)n * cand / 64 <= (long long)ncu * bpc) g = cand;
       }
       if (chain_lds_bytes_host(g, S) > 65536) g = 2;
     }

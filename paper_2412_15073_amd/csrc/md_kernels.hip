@@ -119,24 +119,30 @@ __device__ __forceinline__ void log_jump_hash_only(const MDView &V, AtomStats &s
 }
 
 // ------------------------------------------------------- jump chains
-// G lanes cooperate on one atom's chain. The velocity-independent part of
-// every proposal (Philox block, candidate of each branch, gathered position,
-// long-range gradient, the uniforms of the first Z iteration) is computed G
-// proposals at a time, one per lane, into a per-atom ring of M = 2G slots in
-// LDS. The sequential part then evaluates windows of G proposals: times are
-// left folds of the exponential clocks taken in proposal order, acceptance
-// uses the velocity at the proposal time, and the first event (acceptance or
-// end of the half step) is found with a group minimum. Every decision is the
-// one the one-proposal-at-a-time chain takes.
+// G lanes cooperate on one atom's chain; a wave holds 64/G atoms. The
+// velocity-independent part of every proposal (Philox block, candidate of
+// each branch, gathered position, long-range gradient, the uniforms of the
+// first Z iteration) is computed into a per-atom ring of M slots in LDS, one
+// proposal per lane. Refills are wave-synchronous: when any atom of the wave
+// runs low, every atom with room takes G more proposals in the same pass, so
+// the wave pays for one refill where desynchronised atoms would pay for each.
+// The sequential part evaluates windows of G proposals: proposal times are
+// left folds of the exponential clocks in proposal order, acceptance uses the
+// velocity at the proposal time, and the first event (acceptance or end of
+// the half step) is found with a group minimum. Every decision is the one the
+// one-proposal-at-a-time chain takes.
 
-// ring fields (doubles, field-major: field f of slot s at f*M + s)
-enum { RF_E = 0, RF_U1, RF_U3, RF_BX, RF_BY, RF_BZ, RF_B2, RF_BL, RF_BJ,
-       RF_FX, RF_FY, RF_FZ, RF_F2, RF_FL, RF_FJ, RF_Z0, RF_Z1, RF_Z2, RF_Z3, RF_N };
+// ring fields (doubles, field-major: field f of slot s at f*M + s); RF_J holds
+// the two candidates (by-bound, uniform) as a pair of ints
+enum { RF_E = 0, RF_U1, RF_U3, RF_BX, RF_BY, RF_BZ, RF_BL, RF_FX, RF_FY, RF_FZ, RF_FL, RF_J,
+       RF_Z0, RF_Z1, RF_Z2, RF_Z3, RF_N };
+
+__host__ __device__ constexpr int ring_slots(int G) { return G == 1 ? 3 : (5 * G) / 2; }
 
 // LDS doubles per atom of the segment table for S segments: cumulative
-// weights (S), cumulative counts (S, plus one spare: last usable segment),
-// bounds (S) and starts (S + 1 ints)
-__host__ __device__ constexpr int seg_lds_doubles(int S) { return 3 * S + 1 + (S + 2) / 2; }
+// weights (S), cumulative counts (S, plus one spare: last usable segment)
+// and starts (S + 1 ints)
+__host__ __device__ constexpr int seg_lds_doubles(int S) { return 2 * S + 1 + (S + 2) / 2; }
 
 // wave-scope ordering of LDS writes by some lanes before reads by others
 __device__ __forceinline__ void wave_lds_sync() {
@@ -158,23 +164,30 @@ __device__ __forceinline__ int group_sum(int x) {
   return x;
 }
 
-// Segment table of one atom for one jump component: bound l_q per segment,
-// cumulative weights sum n_q l_q and cumulative counts of the candidates whose
-// bound is nonzero. The first segment whose cumulative value exceeds a target
-// always has n_q l_q > 0, so the searches need no validity test.
+// |F|^2 evaluated the same way wherever it is needed
+__device__ __forceinline__ double norm2_nc(double x, double y, double z) {
+#pragma clang fp contract(off)
+  return x * x + y * y + z * z;
+}
+
+// Segment table of one atom for one jump component: cumulative weights
+// sum n_q l_q and cumulative counts of the candidates whose bound is nonzero.
+// The first segment whose cumulative value exceeds a target always has
+// n_q l_q > 0, so the searches need no validity test.
 struct SegL {
-  double *cw, *cn, *el;
+  double *cw, *cn;
   int *st;
-  int S, last;
-  double W, nf;
+  int S, last, a, coul;
+  double W, nf, absq;
 
   __device__ __forceinline__ void attach(double *base, int S_) {
     S = S_;
-    cw = base; cn = base + S; el = base + 2 * S + 1;
-    st = (int *)(base + 3 * S + 1);
+    cw = base; cn = base + S;
+    st = (int *)(base + 2 * S + 1);
   }
   // lane r == 0 of the group writes; every lane reads back the totals
-  __device__ __forceinline__ void build(const MDView &V, int i, int a, int coul, double absq, int r) {
+  __device__ __forceinline__ void build(const MDView &V, int i, int a_, int coul_, double absq_, int r) {
+    a = a_; coul = coul_; absq = absq_;
     wave_lds_sync();   // earlier reads of the table by the group are complete
     if (r == 0) {
       const int *sst = V.segst + (size_t)i * (S + 1);
@@ -189,10 +202,10 @@ struct SegL {
         w += (double)nq * l;
         if (l > 0.0) c += nq;
         if (nq > 0 && l > 0.0) lst = q;
-        cw[q] = w; cn[q] = (double)c; el[q] = l; st[q + 1] = s1;
+        cw[q] = w; cn[q] = (double)c; st[q + 1] = s1;
         s0 = s1;
       }
-      cn[S] = (double)lst;   // spare slot of the count array: last usable segment
+      cn[S] = (double)lst;   // spare slot: last usable segment
     }
     wave_lds_sync();
     W = cw[S - 1];
@@ -209,11 +222,11 @@ struct SegL {
   }
   // candidate in proportion to its bound: segment by n_q l_q, then uniform
   // inside from the residual
-  __device__ __forceinline__ int pick_by_bound(double u, double &ell_s) const {
+  __device__ __forceinline__ int pick_by_bound(const MDView &V, double u, double &ell_s) const {
     const double target = u * W;
     const int s = first_above(cw, target);
     const double below = s > 0 ? cw[s - 1] : 0.0;
-    const double el_s = el[s];
+    const double el_s = seg_ell(V, a, s, coul, absq);
     const int base = st[s], n = st[s + 1] - base;
     long long idx = (long long)floor((target - below) / el_s);
     idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
@@ -221,14 +234,14 @@ struct SegL {
     return base + (int)idx;
   }
   // candidate uniform among those with a nonzero bound
-  __device__ __forceinline__ int pick_uniform(double u, double &ell_s) const {
+  __device__ __forceinline__ int pick_uniform(const MDView &V, double u, double &ell_s) const {
     const double target = u * nf;
     const int s = first_above(cn, target);
     const double below = s > 0 ? cn[s - 1] : 0.0;
     const int base = st[s], n = st[s + 1] - base;
     long long idx = (long long)floor(target - below);
     idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
-    ell_s = el[s];
+    ell_s = seg_ell(V, a, s, coul, absq);
     return base + (int)idx;
   }
 };
@@ -252,8 +265,8 @@ __device__ __forceinline__ bool z_iteration(double eta, double u0, double u1, do
 // Z iterations it0, it0 + 1, ... with G of them in parallel: lane r tries
 // it = base + r; the first accepted iteration (in order) wins.
 template <int G>
-__device__ double zsample_grp(double eta, uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
-                              int phase, int64_t k, int r, int it0, int &overflow) {
+__device__ __noinline__ double zsample_grp(double eta, uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
+                                           int phase, int64_t k, int r, int it0, int &overflow) {
   overflow = 0;
   for (int base = it0; base < MD_ZS_MAXIT; base += G) {
     const int it = base + r;
@@ -271,174 +284,134 @@ __device__ double zsample_grp(double eta, uint64_t seed, uint64_t rep, int64_t s
   return 0.5 * (eta + sqrt(eta * eta + 4.0));
 }
 
-// Left fold base + E_w0 + ... + E_(w0+r) over the window, in proposal order.
-template <int G>
-__device__ __forceinline__ double window_fold(const double *ringE, int64_t w0, int r, double base, double &tot) {
-  constexpr int M = 2 * G;
-  double s = base, t = base;
-#pragma unroll
-  for (int m = 0; m < G; ++m) {
-    t += ringE[(int)((w0 + m) & (M - 1))];
-    if (m == r) s = t;
-  }
-  tot = t;
-  return s;
+__device__ __forceinline__ int ring_add(int s, int d, int M) {
+  s += d;
+  return s >= M ? s - M : s;
 }
 
-// ------------------------------------------------------------------ J op
-// BPS jumps of the LJ long part over half step h (Alg. 5 in the exponential-
-// clock form of Alg. 2): bound beta |v_i| l_s per candidate, constant over the
-// half step (a reflection keeps |v|), proposal k at (E_0 + ... + E_k)/Lambda.
-// Block (step, i, phase, k): u0 -> E_k, u2 -> candidate, u3 -> acceptance.
+// One chain op over duration h for the atom of this group (wave-synchronous
+// loop; groups that have finished stay masked until the wave is done).
+//  J (BPS jumps of the LJ long part, Alg. 5 in the exponential-clock form of
+//    Alg. 2): bound beta |v| l_s per candidate, constant over the op since a
+//    reflection keeps |v|; proposal k at (E_0 + ... + E_k)/Lambda.
+//  C (Sec. 2.3 step (C), Alg. 1, Alg. 4; eps = eps0 |F| when adaptive):
+//    constant acceleration a between jumps plus MRZ jumps of the Coulomb long
+//    part; the bound is re-evaluated after each accepted jump (Sec. 2.4): from
+//    (t_e, v_e), B_v = sqrt(|v_e|^2 + tau^2 |a|^2 + 2 tau (v_e.a)_+), tau = h - t_e.
+// Block (step, i, phase, k): u0 -> E_k, u1 -> bound part (adaptive C),
+// u2 -> candidate, u3 -> acceptance; block (step, i, phase | 1 << 24, k) ->
+// first Z iteration.
 template <int G>
-__device__ void op_j_ring(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
-                          double &vx, double &vy, double &vz, const MDOp &op, AtomStats &st,
-                          const double *L, const double *iL, double *ring, SegL &T) {
-  constexpr int M = 2 * G;
+__device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
+                         double &vx, double &vy, double &vz, double me, double ax, double ay, double az,
+                         const MDOp &op, AtomStats &st, const double *L, const double *iL, double *ring,
+                         SegL &T) {
+  constexpr int M = ring_slots(G);
+  const bool isC = op.kind == OP_C;
   const int a = V.type[i];
-  T.build(V, i, a, 0, 0.0, r);
+  T.build(V, i, a, isC ? 1 : 0, isC ? fabs(xi.w) : 0.0, r);
   const int *row = V.crow + (size_t)i * V.cap_c;
-  const double vn = sqrt(vx * vx + vy * vy + vz * vz);
-  const double Lam = V.beta * vn * T.W;
-  if (!(Lam > 0.0)) return;
-  if (!isfinite(Lam)) { if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull); return; }
-  const uint64_t rep = (uint64_t)V.rep[i];
-  const int64_t li = V.loc[i];
-  int64_t w0 = 0, computed = 0;
-  double base = 0.0;  // fold of E over the proposals before the window
-  for (;;) {
-    if (w0 >= MD_MAX_PROPOSALS) { if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull); break; }
-    if (computed < w0 + G) {
-      const int64_t k = computed + r;
-      const int sl = (int)(k & (M - 1));
-      wave_lds_sync();   // reads of the slots being replaced are complete
-      Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
-      double ell, Fx, Fy, Fz;
-      const int j = row[T.pick_by_bound(u.u[2], ell)];
-      const double F2 = long_grad(V, xi, X[j], a, V.type[j], 0, L, iL, Fx, Fy, Fz);
-      ring[RF_E * M + sl] = -log(u.u[0]);
-      ring[RF_U3 * M + sl] = u.u[3];
-      ring[RF_BX * M + sl] = Fx; ring[RF_BY * M + sl] = Fy; ring[RF_BZ * M + sl] = Fz;
-      ring[RF_B2 * M + sl] = F2; ring[RF_BL * M + sl] = ell;
-      ring[RF_BJ * M + sl] = (double)j;
-      computed += G;
-      wave_lds_sync();
-    }
-    const int sl = (int)((w0 + r) & (M - 1));
-    double tot;
-    const double s = window_fold<G>(ring + RF_E * M, w0, r, base, tot);
-    const bool out = s / Lam > op.h;
-    const double Fx = ring[RF_BX * M + sl], Fy = ring[RF_BY * M + sl], Fz = ring[RF_BZ * M + sl];
-    const double ell = ring[RF_BL * M + sl];
-    const double vF = vx * Fx + vy * Fy + vz * Fz;
-    const double p = (vF > 0.0 ? vF : 0.0) / (vn * ell);
-    const bool acc = !out && p > 0.0 && ring[RF_U3 * M + sl] <= p;
-    const int first = group_min<G>((out || acc) ? r : G);
-    // proposals evaluated in this window: ranks before the event, plus an accepted one
-    const bool counted = r < first || (r == first && acc);
-    st.nprop += group_sum<G>(counted ? 1 : 0);
-    st.nviol += group_sum<G>((counted && p > 1.0) ? 1 : 0);
-    if (first == G) { base = tot; w0 += G; continue; }
-    if (__shfl((int)out, first, G)) break;
-    const int fs = (int)((w0 + first) & (M - 1));
-    const double Fxs = ring[RF_BX * M + fs], Fys = ring[RF_BY * M + fs], Fzs = ring[RF_BZ * M + fs];
-    const double F2 = ring[RF_B2 * M + fs];
-    const int j = (int)ring[RF_BJ * M + fs];
-    const double vFs = vx * Fxs + vy * Fys + vz * Fzs;
-    const double c = 2.0 * vFs / F2;
-    vx -= c * Fxs; vy -= c * Fys; vz -= c * Fzs;
-    const int64_t kstar = w0 + first;
-    if (r == first) log_jump(V, st, op.step, op.phase, i, j, kstar);
-    else log_jump_hash_only(V, st, op.step, op.phase, j);
-    base = __shfl(s, first, G);
-    w0 = kstar + 1;
-  }
-}
-
-// ------------------------------------------------------------------ C op
-// Constant acceleration a_i between jumps plus MRZ jumps of the Coulomb long
-// part (Sec. 2.3 step (C), Alg. 1, Alg. 4; eps = eps0 |F| when adaptive). The
-// local bound is re-evaluated after each accepted jump (Sec. 2.4): from
-// (t_e, v_e), B_v = sqrt(|v_e|^2 + tau^2 |a|^2 + 2 tau (v_e.a)_+), tau = h - t_e.
-// Block (step, i, phase, k): u0 -> E_k, u1 -> bound part (adaptive),
-// u2 -> candidate, u3 -> acceptance.
-template <int G>
-__device__ void op_c_ring(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
-                          double &vx, double &vy, double &vz, double me, double ax, double ay, double az,
-                          const MDOp &op, AtomStats &st, const double *L, const double *iL, double *ring,
-                          SegL &T) {
-  constexpr int M = 2 * G;
-  const int a = V.type[i];
-  T.build(V, i, a, 1, fabs(xi.w), r);
-  const int *row = V.crow + (size_t)i * V.cap_c;
-  const bool adaptive = (V.jc == MD_JUMP_MRZ_ADAPTIVE);
+  const bool adaptive = isC && (V.jc == MD_JUMP_MRZ_ADAPTIVE);
   const double beta = V.beta, eps0 = V.eps0;
   const double f = sqrt(beta / (2.0 * MD_PI * me)) / eps0;
   const double aa = ax * ax + ay * ay + az * az;
   const uint64_t rep = (uint64_t)V.rep[i];
   const int64_t li = V.loc[i];
   const double h = op.h;
+  const double vn = sqrt(vx * vx + vy * vy + vz * vz);   // J: |v| for the whole op
   int64_t w0 = 0, computed = 0;
-  double vex = vx, vey = vy, vez = vz, te = 0.0;
-  for (;;) {
-    // epoch: bound from (t_e, v_e) over the rest of the half step
-    const double tau = h - te;
-    const double vv = vex * vex + vey * vey + vez * vez;
-    const double va = vex * ax + vey * ay + vez * az;
-    const double Bv = sqrt(vv + tau * tau * aa + 2.0 * tau * (va > 0.0 ? va : 0.0));
-    const double bBv = beta * Bv;
-    const double Wb = bBv * T.W;
-    const double Lam = adaptive ? Wb + f * T.nf : (bBv + f) * T.W;
-    if (!(Lam > 0.0) || !isfinite(Lam)) {
-      if (!(Lam <= 0.0) && r == 0) atomicAdd(&V.ctl->nonfinite, 1ull);
-      vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
-      return;
-    }
-    double base = 0.0;
-    for (;;) {
-      if (w0 >= MD_MAX_PROPOSALS) {
-        if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull);
-        vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
-        return;
+  int ws = 0, cs = 0;   // ring slots of w0 and of computed
+  double vex = vx, vey = vy, vez = vz, te = 0.0, base = 0.0;
+  double tau = h, bBv = 0.0, Wb = 0.0, Lam = 0.0;
+  bool live = true, epoch = true;
+  auto finish = [&]() {
+    if (isC) { vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az; }
+    live = false;
+  };
+  while (__any(live)) {
+    if (live && epoch) {
+      epoch = false;
+      if (isC) {
+        tau = h - te;
+        const double vv = vex * vex + vey * vey + vez * vez;
+        const double va = vex * ax + vey * ay + vez * az;
+        const double Bv = sqrt(vv + tau * tau * aa + 2.0 * tau * (va > 0.0 ? va : 0.0));
+        bBv = beta * Bv;
+        Wb = bBv * T.W;
+        Lam = adaptive ? Wb + f * T.nf : (bBv + f) * T.W;
+        base = 0.0;
+        if (!(Lam > 0.0) || !isfinite(Lam)) {
+          if (!(Lam <= 0.0) && r == 0) atomicAdd(&V.ctl->nonfinite, 1ull);
+          finish();
+        }
+      } else {
+        Lam = V.beta * vn * T.W;
+        if (!(Lam > 0.0)) finish();
+        else if (!isfinite(Lam)) { if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull); finish(); }
       }
-      if (computed < w0 + G) {
+    }
+    if (live && w0 >= MD_MAX_PROPOSALS) {
+      if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull);
+      finish();
+    }
+    // wave-synchronous refill: every atom with room for G more proposals
+    if (__any(live && computed - w0 < G)) {
+      wave_lds_sync();   // reads of the slots being replaced are complete
+      if (live && (int)(computed - w0) <= M - G) {
         const int64_t k = computed + r;
-        const int sl = (int)(k & (M - 1));
-        wave_lds_sync();   // reads of the slots being replaced are complete
+        const int sl = ring_add(cs, r, M);
         Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
         double ell, Fx, Fy, Fz;
-        int j = row[T.pick_by_bound(u.u[2], ell)];
-        double F2 = long_grad(V, xi, X[j], a, V.type[j], 1, L, iL, Fx, Fy, Fz);
+        const int jb = row[T.pick_by_bound(V, u.u[2], ell)];
+        long_grad(V, xi, X[jb], a, V.type[jb], isC ? 1 : 0, L, iL, Fx, Fy, Fz);
         ring[RF_E * M + sl] = -log(u.u[0]);
         ring[RF_U1 * M + sl] = u.u[1];
         ring[RF_U3 * M + sl] = u.u[3];
         ring[RF_BX * M + sl] = Fx; ring[RF_BY * M + sl] = Fy; ring[RF_BZ * M + sl] = Fz;
-        ring[RF_B2 * M + sl] = F2; ring[RF_BL * M + sl] = ell; ring[RF_BJ * M + sl] = (double)j;
+        ring[RF_BL * M + sl] = ell;
+        int jf = jb;
         if (adaptive) {
-          j = row[T.pick_uniform(u.u[2], ell)];
-          F2 = long_grad(V, xi, X[j], a, V.type[j], 1, L, iL, Fx, Fy, Fz);
+          jf = row[T.pick_uniform(V, u.u[2], ell)];
+          long_grad(V, xi, X[jf], a, V.type[jf], 1, L, iL, Fx, Fy, Fz);
           ring[RF_FX * M + sl] = Fx; ring[RF_FY * M + sl] = Fy; ring[RF_FZ * M + sl] = Fz;
-          ring[RF_F2 * M + sl] = F2; ring[RF_FL * M + sl] = ell; ring[RF_FJ * M + sl] = (double)j;
+          ring[RF_FL * M + sl] = ell;
         }
-        Uni4 z = draw4(V.seed, rep, op.step, li, (uint64_t)(uint32_t)op.phase | (1ull << 24), k);
-        ring[RF_Z0 * M + sl] = z.u[0]; ring[RF_Z1 * M + sl] = z.u[1];
-        ring[RF_Z2 * M + sl] = z.u[2]; ring[RF_Z3 * M + sl] = z.u[3];
+        int2 *jp = (int2 *)(ring + RF_J * M);
+        jp[sl] = make_int2(jb, jf);
+        if (isC) {
+          Uni4 z = draw4(V.seed, rep, op.step, li, (uint64_t)(uint32_t)op.phase | (1ull << 24), k);
+          ring[RF_Z0 * M + sl] = z.u[0]; ring[RF_Z1 * M + sl] = z.u[1];
+          ring[RF_Z2 * M + sl] = z.u[2]; ring[RF_Z3 * M + sl] = z.u[3];
+        }
         computed += G;
-        wave_lds_sync();
+        cs = ring_add(cs, G, M);
       }
-      const int sl = (int)((w0 + r) & (M - 1));
-      double tot;
-      const double s = window_fold<G>(ring + RF_E * M, w0, r, base, tot);
-      const double tk = te + s / Lam;
-      const bool out = tk > h;
+      wave_lds_sync();
+    }
+    if (!live) continue;
+    // window [w0, w0 + G): lane r holds proposal w0 + r
+    const int sl = ring_add(ws, r, M);
+    double s = base, tot = base;
+#pragma unroll
+    for (int m = 0; m < G; ++m) {
+      tot += ring[RF_E * M + ring_add(ws, m, M)];
+      if (m == r) s = tot;
+    }
+    const bool use_f = adaptive && !(ring[RF_U1 * M + sl] * Lam < Wb);
+    const int fo = use_f ? (RF_FX - RF_BX) * M : 0;
+    const double Fx = ring[fo + RF_BX * M + sl], Fy = ring[fo + RF_BY * M + sl], Fz = ring[fo + RF_BZ * M + sl];
+    const double ell = ring[fo + RF_BL * M + sl];
+    const double F2 = norm2_nc(Fx, Fy, Fz);
+    const double u3 = ring[RF_U3 * M + sl];
+    bool out, acc;
+    double p, eta = 0.0, tk = 0.0;
+    if (isC) {
+      tk = te + s / Lam;
+      out = tk > h;
       const double dtk = tk - te;
       const double vkx = vex + dtk * ax, vky = vey + dtk * ay, vkz = vez + dtk * az;
-      const bool use_f = adaptive && !(ring[RF_U1 * M + sl] * Lam < Wb);
-      const int fb = use_f ? (RF_FX - RF_BX) * M : 0;
-      const double Fx = ring[fb + RF_BX * M + sl], Fy = ring[fb + RF_BY * M + sl], Fz = ring[fb + RF_BZ * M + sl];
-      const double F2 = ring[fb + RF_B2 * M + sl], ell = ring[fb + RF_BL * M + sl];
       const double c = adaptive ? bBv * ell + f : ell * (bBv + f);
-      double lam = 0.0, eta = 0.0;
+      double lam = 0.0;
       const double vF = vkx * Fx + vky * Fy + vkz * Fz;
       if (!out && F2 > 0.0) {
         if (adaptive) {
@@ -450,25 +423,29 @@ __device__ void op_c_ring(const MDView &V, const double4 *__restrict__ X, int i,
           lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * theta_p(V, eta);
         }
       }
-      const double p = lam / c;
-      const bool acc = !out && p > 0.0 && ring[RF_U3 * M + sl] <= p;
-      const int first = group_min<G>((out || acc) ? r : G);
-      const bool counted = r < first || (r == first && acc);
-      st.nprop += group_sum<G>(counted ? 1 : 0);
-      st.nviol += group_sum<G>((counted && p > 1.0) ? 1 : 0);
-      if (first == G) { base = tot; w0 += G; continue; }
-      if (__shfl((int)out, first, G)) {
-        vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az;
-        return;
-      }
+      p = lam / c;
+    } else {
+      out = s / Lam > h;
+      const double vF = vx * Fx + vy * Fy + vz * Fz;
+      p = (vF > 0.0 ? vF : 0.0) / (vn * ell);
+    }
+    acc = !out && p > 0.0 && u3 <= p;
+    const int first = group_min<G>((out || acc) ? r : G);
+    // proposals evaluated in this window: ranks before the event, plus an accepted one
+    const bool counted = r < first || (r == first && acc);
+    st.nprop += group_sum<G>(counted ? 1 : 0);
+    st.nviol += group_sum<G>((counted && p > 1.0) ? 1 : 0);
+    if (first == G) { base = tot; w0 += G; ws = ring_add(ws, G, M); continue; }
+    if (__shfl((int)out, first, G)) { finish(); continue; }
+    const double Fxs = __shfl(Fx, first, G), Fys = __shfl(Fy, first, G), Fzs = __shfl(Fz, first, G);
+    const double F2s = __shfl(F2, first, G);
+    const int fs = ring_add(ws, first, M);
+    const int2 jj = ((const int2 *)(ring + RF_J * M))[fs];
+    const int j = __shfl((int)use_f, first, G) ? jj.y : jj.x;
+    const int64_t kstar = w0 + first;
+    if (isC) {
       const double etas = __shfl(eta, first, G);
       const double tks = __shfl(tk, first, G);
-      const double F2s = __shfl(F2, first, G);
-      const double Fxs = __shfl(Fx, first, G), Fys = __shfl(Fy, first, G), Fzs = __shfl(Fz, first, G);
-      const int fbs = __shfl(fb, first, G);
-      const int fs = (int)((w0 + first) & (M - 1));
-      const int j = (int)ring[fbs + RF_BJ * M + fs];
-      const int64_t kstar = w0 + first;
       double Z;
       if (!z_iteration(etas, ring[RF_Z0 * M + fs], ring[RF_Z1 * M + fs], ring[RF_Z2 * M + fs],
                        ring[RF_Z3 * M + fs], Z)) {
@@ -483,50 +460,96 @@ __device__ void op_c_ring(const MDView &V, const double4 *__restrict__ X, int i,
       vey = vey + dts * ay - coef * Fys;
       vez = vez + dts * az - coef * Fzs;
       te = tks;
-      if (r == first) log_jump(V, st, op.step, op.phase, i, j, kstar);
-      else log_jump_hash_only(V, st, op.step, op.phase, j);
-      w0 = kstar + 1;
-      break;  // new epoch
+      epoch = true;   // new bound from (t_e, v_e)
+    } else {
+      const double vFs = vx * Fxs + vy * Fys + vz * Fzs;
+      const double c = 2.0 * vFs / F2s;
+      vx -= c * Fxs; vy -= c * Fys; vz -= c * Fzs;
+      base = __shfl(s, first, G);
     }
+    if (r == first) log_jump(V, st, op.step, op.phase, i, j, kstar);
+    else log_jump_hash_only(V, st, op.step, op.phase, j);
+    w0 = kstar + 1;
+    ws = ring_add(ws, first + 1, M);
+  }
+}
+
+// Chain kernel: the position-preserving prefix of a step program (B kicks,
+// J and C chains) for every atom; G lanes per atom, one wave per block.
+// Dynamic LDS: the proposal rings of the block's 64/G atoms, then their
+// segment tables.
+#ifndef MD_CHAIN_WAVES_PER_SIMD
+#define MD_CHAIN_WAVES_PER_SIMD 1   // register budget of the chain kernel: 512 / this per lane
+#endif
+template <int G>
+__global__ __launch_bounds__(64, MD_CHAIN_WAVES_PER_SIMD) void k_chain(MDView V, MDProg P,
+                                                                      const double4 *__restrict__ X) {
+  extern __shared__ double lds_chain[];
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid / G, r = gid - (gid / G) * G;
+  if (i >= V.n) return;
+  const double4 xi = X[i];
+  const double4 vv = V.v[i];
+  double vx = vv.x, vy = vv.y, vz = vv.z;
+  const double me = vv.w;
+  const int rp = V.rep[i];
+  const double L[3] = {V.box[3 * rp], V.box[3 * rp + 1], V.box[3 * rp + 2]};
+  const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+  AtomStats st;
+  st.nprop = V.nprop[i]; st.nacc = V.nacc[i]; st.nviol = V.nviol[i]; st.hash = V.hash[i];
+  const double4 fn = V.fnb[i], fb = V.fb[i];
+  constexpr int M = ring_slots(G);
+  constexpr int APB = 64 / G;
+  const int ab = (int)threadIdx.x / G;
+  double *ring = lds_chain + ab * (RF_N * M);
+  SegL T;
+  T.attach(lds_chain + APB * (RF_N * M) + ab * seg_lds_doubles(V.S), V.S);
+  const int64_t sbase = P.dev_step ? (int64_t)V.ctl->step_base : 0;
+  for (int o = 0; o < P.nops; ++o) {
+    MDOp op = P.ops[o];
+    op.step += sbase;
+    if (op.kind == OP_B) {
+      const double fx = ((op.flags & 1) ? fn.x : 0.0) + ((op.flags & 2) ? fb.x : 0.0);
+      const double fy = ((op.flags & 1) ? fn.y : 0.0) + ((op.flags & 2) ? fb.y : 0.0);
+      const double fz = ((op.flags & 1) ? fn.z : 0.0) + ((op.flags & 2) ? fb.z : 0.0);
+      vx += op.h * fx / me; vy += op.h * fy / me; vz += op.h * fz / me;
+    } else {
+      double ax = 0.0, ay = 0.0, az = 0.0;
+      if (op.kind == OP_C) {
+        ax = (fn.x + (op.flags == 0 ? fb.x : 0.0)) / me;
+        ay = (fn.y + (op.flags == 0 ? fb.y : 0.0)) / me;
+        az = (fn.z + (op.flags == 0 ? fb.z : 0.0)) / me;
+      }
+      chain_op<G>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, T);
+    }
+  }
+  if (r == 0) {
+    if (!(isfinite(vx) && isfinite(vy) && isfinite(vz))) atomicAdd(&V.ctl->nonfinite, 1ull);
+    V.v[i] = make_double4(vx, vy, vz, me);
+    V.nprop[i] = st.nprop; V.nacc[i] = st.nacc; V.nviol[i] = st.nviol; V.hash[i] = st.hash;
   }
 }
 
 // -------------------------------------------------------------- k_local
-// G lanes per atom (G = 1: one lane runs the whole chain). B/A/O ops are
-// repeated by every lane of the group; lane 0 writes the atom back. Dynamic
-// LDS (programs with jumps): the proposal rings of the block's 64/G atoms,
-// then their segment tables.
-template <int G>
-__global__ __launch_bounds__(64) void k_local(MDView V, MDProg P, const double4 *__restrict__ Xs,
-                                               double4 *__restrict__ Xd) {
-  extern __shared__ double lds_chain[];
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = gid / G, r = gid - (gid / G) * G;
-  // displacement maximum: per-block LDS max (blocks are single waves), then
-  // one global atomic per block; every lane on one shared word serialises
+// One lane per atom: B / A / O updates and the displacement check of a step
+// program without jump chains. Positions are double-buffered (read Xs, write Xd).
+__global__ __launch_bounds__(256) void k_local(MDView V, MDProg P, const double4 *__restrict__ Xs,
+                                                double4 *__restrict__ Xd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // displacement maximum: per-block LDS max, one global atomic per block
   __shared__ unsigned long long s_d2;
-  const int rp_blk = V.rep[min(V.n - 1, (int)(blockIdx.x * blockDim.x) / G)];
+  const int rp_blk = V.rep[min(V.n - 1, (int)(blockIdx.x * blockDim.x))];
   if (threadIdx.x == 0) s_d2 = 0ull;
   __syncthreads();
-  if (gid < V.nrep && P.reset_slot >= 0) V.rep_maxd2[P.reset_slot * V.nrep + gid] = 0ull;
-  if (i >= V.n) return;
-  double4 xi = Xs[i];
-  double4 vv = V.v[i];
+  if (i < V.nrep && P.reset_slot >= 0) V.rep_maxd2[P.reset_slot * V.nrep + i] = 0ull;
+  const bool valid = i < V.n;
+  const int ii = valid ? i : V.n - 1;
+  double4 xi = Xs[ii];
+  const double4 vv = V.v[ii];
   double vx = vv.x, vy = vv.y, vz = vv.z;
   const double me = vv.w;
-  const int rp = V.rep[i];
-  double L[3] = {V.box[3 * rp], V.box[3 * rp + 1], V.box[3 * rp + 2]};
-  double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
-  AtomStats st;
-  bool jumps = false;
-  for (int o = 0; o < P.nops; ++o) jumps |= (P.ops[o].kind == OP_J || P.ops[o].kind == OP_C);
-  if (jumps) { st.nprop = V.nprop[i]; st.nacc = V.nacc[i]; st.nviol = V.nviol[i]; st.hash = V.hash[i]; }
-  double4 fn = V.fnb[i], fb = V.fb[i];
-  constexpr int APB = 64 / G;   // atoms per block
-  const int ab = (int)threadIdx.x / G;
-  double *ring = lds_chain + ab * (RF_N * 2 * G);
-  SegL T;
-  T.attach(lds_chain + APB * (RF_N * 2 * G) + ab * seg_lds_doubles(V.S), V.S);
+  const int rp = V.rep[ii];
+  const double4 fn = V.fnb[ii], fb = V.fb[ii];
   const int64_t sbase = P.dev_step ? (int64_t)V.ctl->step_base : 0;
   double disp2 = 0.0;
   bool has_disp = false;
@@ -535,56 +558,43 @@ __global__ __launch_bounds__(64) void k_local(MDView V, MDProg P, const double4 
     op.step += sbase;
     switch (op.kind) {
       case OP_B: {
-        double fx = ((op.flags & 1) ? fn.x : 0.0) + ((op.flags & 2) ? fb.x : 0.0);
-        double fy = ((op.flags & 1) ? fn.y : 0.0) + ((op.flags & 2) ? fb.y : 0.0);
-        double fz = ((op.flags & 1) ? fn.z : 0.0) + ((op.flags & 2) ? fb.z : 0.0);
+        const double fx = ((op.flags & 1) ? fn.x : 0.0) + ((op.flags & 2) ? fb.x : 0.0);
+        const double fy = ((op.flags & 1) ? fn.y : 0.0) + ((op.flags & 2) ? fb.y : 0.0);
+        const double fz = ((op.flags & 1) ? fn.z : 0.0) + ((op.flags & 2) ? fb.z : 0.0);
         vx += op.h * fx / me; vy += op.h * fy / me; vz += op.h * fz / me;
       } break;
       case OP_A:
         xi.x += op.h * vx; xi.y += op.h * vy; xi.z += op.h * vz;
         break;
       case OP_O: {
-        uint64_t tag = (uint64_t)OP_PHASE_O | ((uint64_t)(uint32_t)op.substep << 8);
-        Uni4 u = draw4(V.seed, (uint64_t)rp, op.step, V.loc[i], tag, 0);
-        double r1 = sqrt(-2.0 * log(u.u[0])), r2 = sqrt(-2.0 * log(u.u[2]));
-        double gx = r1 * cos(2.0 * MD_PI * u.u[1]);
-        double gy = r1 * sin(2.0 * MD_PI * u.u[1]);
-        double gz = r2 * cos(2.0 * MD_PI * u.u[3]);
-        double sd = sqrt(V.kT / me);
+        const uint64_t tag = (uint64_t)OP_PHASE_O | ((uint64_t)(uint32_t)op.substep << 8);
+        Uni4 u = draw4(V.seed, (uint64_t)rp, op.step, V.loc[ii], tag, 0);
+        const double r1 = sqrt(-2.0 * log(u.u[0])), r2 = sqrt(-2.0 * log(u.u[2]));
+        const double gx = r1 * cos(2.0 * MD_PI * u.u[1]);
+        const double gy = r1 * sin(2.0 * MD_PI * u.u[1]);
+        const double gz = r2 * cos(2.0 * MD_PI * u.u[3]);
+        const double sd = sqrt(V.kT / me);
         vx = op.c1 * vx + op.c2 * sd * gx;
         vy = op.c1 * vy + op.c2 * sd * gy;
         vz = op.c1 * vz + op.c2 * sd * gz;
       } break;
-      case OP_J:
-        op_j_ring<G>(V, Xs, i, r, xi, vx, vy, vz, op, st, L, iL, ring, T);
-        break;
-      case OP_C: {
-        double fx = fn.x + (op.flags == 0 ? fb.x : 0.0);
-        double fy = fn.y + (op.flags == 0 ? fb.y : 0.0);
-        double fz = fn.z + (op.flags == 0 ? fb.z : 0.0);
-        op_c_ring<G>(V, Xs, i, r, xi, vx, vy, vz, me, fx / me, fy / me, fz / me, op, st, L, iL, ring, T);
-      } break;
-      case OP_DISP:
-        disp2 = 0.0;
-        if (r == 0) {
-          double4 xr = V.xref[i];
-          double dx = xi.x - xr.x, dy = xi.y - xr.y, dz = xi.z - xr.z;
-          disp2 = dx * dx + dy * dy + dz * dz;
-        }
+      case OP_DISP: {
+        const double4 xr = V.xref[ii];
+        const double dx = xi.x - xr.x, dy = xi.y - xr.y, dz = xi.z - xr.z;
+        disp2 = valid ? dx * dx + dy * dy + dz * dz : 0.0;
         has_disp = true;
-        break;
+      } break;
     }
   }
-  if (r == 0) {
+  if (valid) {
     if (!(isfinite(vx) && isfinite(vy) && isfinite(vz))) atomicAdd(&V.ctl->nonfinite, 1ull);
     V.v[i] = make_double4(vx, vy, vz, me);
     if (Xd) Xd[i] = xi;
-    if (jumps) { V.nprop[i] = st.nprop; V.nacc[i] = st.nacc; V.nviol[i] = st.nviol; V.hash[i] = st.hash; }
   }
   if (has_disp) {
     const unsigned long long d = (unsigned long long)__double_as_longlong(disp2);
-    if (rp == rp_blk) atomicMax(&s_d2, d);
-    else atomicMax(&V.rep_maxd2[P.disp_slot * V.nrep + rp], d);   // block straddles two replicas
+    if (!valid || rp == rp_blk) atomicMax(&s_d2, d);
+    else atomicMax(&V.rep_maxd2[P.disp_slot * V.nrep + rp], d);   // block straddles replicas
     __syncthreads();
     if (threadIdx.x == 0) atomicMax(&V.rep_maxd2[P.disp_slot * V.nrep + rp_blk], s_d2);
   }
@@ -1100,29 +1110,47 @@ __global__ void k_set_step(MDCtl *ctl, long long step) { ctl->step_base = step; 
 // ------------------------------------------------------------- launchers
 #define CHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
-// LDS bytes of one k_local block with G lanes per atom
+// LDS bytes of one k_chain block with G lanes per atom
 static size_t chain_lds_bytes(int G, int S) {
-  return sizeof(double) * (size_t)(64 / G) * (size_t)(RF_N * 2 * G + seg_lds_doubles(S));
+  return sizeof(double) * (size_t)(64 / G) * (size_t)(RF_N * ring_slots(G) + seg_lds_doubles(S));
+}
+size_t chain_lds_bytes_host(int G, int S) { return chain_lds_bytes(G, S); }
+
+// resident k_chain blocks per CU (registers and LDS), 0 if unknown
+int chain_blocks_per_cu(int G, int S) {
+  int nb = 0;
+  const size_t lds = chain_lds_bytes(G, S);
+  hipError_t e = hipErrorInvalidValue;
+  switch (G) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<1>, 64, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<2>, 64, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<4>, 64, lds); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<8>, 64, lds); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<16>, 64, lds); break;
+  }
+  return e == hipSuccess ? nb : 0;
 }
 
-hipError_t launch_local(const MDView &V, const MDProg &P, const double4 *Xs, double4 *Xd, hipStream_t s) {
+hipError_t launch_chain(const MDView &V, const MDProg &P, const double4 *X, hipStream_t s) {
   const int G = V.chain_lanes;
   const long long threads = (long long)V.n * G;
   const int nb = (int)((threads + 63) / 64);   // wave-sized blocks spread the few long waves over all CUs
-  bool jumps = false;
-  for (int o = 0; o < P.nops; ++o) jumps |= (P.ops[o].kind == OP_J || P.ops[o].kind == OP_C);
-  const size_t lds = jumps ? chain_lds_bytes(G, V.S) : 0;
+  const size_t lds = chain_lds_bytes(G, V.S);
   switch (G) {
-    case 1: hipLaunchKernelGGL((k_local<1>), dim3(nb), dim3(64), lds, s, V, P, Xs, Xd); break;
-    case 2: hipLaunchKernelGGL((k_local<2>), dim3(nb), dim3(64), lds, s, V, P, Xs, Xd); break;
-    case 4: hipLaunchKernelGGL((k_local<4>), dim3(nb), dim3(64), lds, s, V, P, Xs, Xd); break;
-    case 8: hipLaunchKernelGGL((k_local<8>), dim3(nb), dim3(64), lds, s, V, P, Xs, Xd); break;
-    default: hipLaunchKernelGGL((k_local<16>), dim3(nb), dim3(64), lds, s, V, P, Xs, Xd); break;
+    case 1: hipLaunchKernelGGL((k_chain<1>), dim3(nb), dim3(64), lds, s, V, P, X); break;
+    case 2: hipLaunchKernelGGL((k_chain<2>), dim3(nb), dim3(64), lds, s, V, P, X); break;
+    case 4: hipLaunchKernelGGL((k_chain<4>), dim3(nb), dim3(64), lds, s, V, P, X); break;
+    case 8: hipLaunchKernelGGL((k_chain<8>), dim3(nb), dim3(64), lds, s, V, P, X); break;
+    default: hipLaunchKernelGGL((k_chain<16>), dim3(nb), dim3(64), lds, s, V, P, X); break;
   }
   return hipGetLastError();
 }
 
-size_t chain_lds_bytes_host(int G, int S) { return chain_lds_bytes(G, S); }
+hipError_t launch_local(const MDView &V, const MDProg &P, const double4 *Xs, double4 *Xd, hipStream_t s) {
+  const int nb = (V.n + 255) / 256;
+  hipLaunchKernelGGL(k_local, dim3(nb), dim3(256), 0, s, V, P, Xs, Xd);
+  return hipGetLastError();
+}
 
 hipError_t launch_rebuild(const MDView &V, const double4 *X, int want, int slot, int forced, int autob,
                           double thr2, int pc, int ps, bool check_only, int count, hipStream_t s) {

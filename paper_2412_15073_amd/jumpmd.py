@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libjumpmd.so")
 MD_OK, MD_ERR_ARG, MD_ERR_HIP, MD_ERR_BOUND, MD_ERR_LIST, MD_ERR_UNSTABLE, MD_ERR_OOM, MD_ERR_CAPACITY = \
     0, -1, -2, -3, -4, -5, -6, -7
 MD_OBS_PE = 1
-MD_K_LOCAL, MD_K_FORCE, MD_K_BONDED, MD_K_REBUILD = 0, 1, 2, 3
+MD_K_LOCAL, MD_K_FORCE, MD_K_BONDED, MD_K_REBUILD, MD_K_CHAIN = 0, 1, 2, 3, 4
 PHASE = {"J1": 2, "J2": 3, "C1": 4, "C2": 5}
 
 _dp = C.POINTER(C.c_double)
@@ -78,18 +78,21 @@ class MDError(RuntimeError):
 
 
 def load():
-    """Load libjumpmd.so (raises if it is missing: no fallback path exists)."""
+    """Load libjumpmd.so (raises if it is missing: no fallback path exists).
+
+    JUMPMD_LIBRARY may name another build of the same library."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} not built; run paper_2412_15073_amd/build.py (hipcc, gfx950)")
+    path = os.environ.get("JUMPMD_LIBRARY", LIB_PATH)
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not built; run paper_2412_15073_amd/build.py (hipcc, gfx950)")
     # PyTorch ships its own HIP runtime. Loading torch first makes the
     # library's libamdhip64.so.7 / libhsa-runtime64.so.1 dependencies resolve
     # (by SONAME) to the copies torch already mapped: one runtime per process,
     # and torch streams are valid handles for the library.
     import torch  # noqa: F401
-    L = C.CDLL(LIB_PATH)
+    L = C.CDLL(path)
     L.md_create.argtypes = [C.POINTER(MDSystem), C.POINTER(MDSplit), C.POINTER(MDParams), C.c_void_p,
                             C.POINTER(C.c_void_p)]
     L.md_destroy.argtypes = [C.c_void_p]
