@@ -13,6 +13,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions stay off: hipcc -O3 would otherwise form
          # v_pk_* FP32 operations from scalar float code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # machine-level loop-invariant code motion hoists the constants of the
+         # FP64 math routines out of the chain loops into registers (occupancy)
+         "-mllvm", "-disable-machine-licm",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-value",
          "-Wno-unused-result"]
 

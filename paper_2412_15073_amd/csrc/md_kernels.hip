@@ -79,14 +79,17 @@ __device__ __forceinline__ double long_grad_d(const MDView &V, double4 xi, doubl
   return Fx * Fx + Fy * Fy + Fz * Fz;
 }
 
+// PREC: MD_FP64 or MD_FP32_MIXED (pair arithmetic and Theta in float)
+template <int PREC>
 __device__ __forceinline__ double long_grad(const MDView &V, double4 xi, double4 xj, int a, int b, int coul,
                                             const double *L, const double *iL, double &Fx, double &Fy, double &Fz) {
-  if (V.precision == MD_FP32_MIXED) return long_grad_f(V, xi, xj, a, b, coul, L, iL, Fx, Fy, Fz);
+  if (PREC == MD_FP32_MIXED) return long_grad_f(V, xi, xj, a, b, coul, L, iL, Fx, Fy, Fz);
   return long_grad_d(V, xi, xj, a, b, coul, L, iL, Fx, Fy, Fz);
 }
 
-__device__ __forceinline__ double theta_p(const MDView &V, double eta) {
-  return V.precision == MD_FP32_MIXED ? (double)theta_fn_f((float)eta) : theta_fn(eta);
+template <int PREC>
+__device__ __forceinline__ double theta_p(double eta) {
+  return PREC == MD_FP32_MIXED ? (double)theta_fn_f((float)eta) : theta_fn(eta);
 }
 
 struct AtomStats { long long nprop, nacc, nviol; uint64_t hash; };
@@ -265,7 +268,7 @@ __device__ __forceinline__ bool z_iteration(double eta, double u0, double u1, do
 // Z iterations it0, it0 + 1, ... with G of them in parallel: lane r tries
 // it = base + r; the first accepted iteration (in order) wins.
 template <int G>
-__device__ __noinline__ double zsample_grp(double eta, uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
+__device__ __forceinline__ double zsample_grp(double eta, uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
                                            int phase, int64_t k, int r, int it0, int &overflow) {
   overflow = 0;
   for (int base = it0; base < MD_ZS_MAXIT; base += G) {
@@ -301,7 +304,7 @@ __device__ __forceinline__ int ring_add(int s, int d, int M) {
 // Block (step, i, phase, k): u0 -> E_k, u1 -> bound part (adaptive C),
 // u2 -> candidate, u3 -> acceptance; block (step, i, phase | 1 << 24, k) ->
 // first Z iteration.
-template <int G>
+template <int G, int PREC>
 __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
                          double &vx, double &vy, double &vz, double me, double ax, double ay, double az,
                          const MDOp &op, AtomStats &st, const double *L, const double *iL, double *ring,
@@ -363,7 +366,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
         double ell, Fx, Fy, Fz;
         const int jb = row[T.pick_by_bound(V, u.u[2], ell)];
-        long_grad(V, xi, X[jb], a, V.type[jb], isC ? 1 : 0, L, iL, Fx, Fy, Fz);
+        long_grad<PREC>(V, xi, X[jb], a, V.type[jb], isC ? 1 : 0, L, iL, Fx, Fy, Fz);
         ring[RF_E * M + sl] = -log(u.u[0]);
         ring[RF_U1 * M + sl] = u.u[1];
         ring[RF_U3 * M + sl] = u.u[3];
@@ -372,7 +375,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         int jf = jb;
         if (adaptive) {
           jf = row[T.pick_uniform(V, u.u[2], ell)];
-          long_grad(V, xi, X[jf], a, V.type[jf], 1, L, iL, Fx, Fy, Fz);
+          long_grad<PREC>(V, xi, X[jf], a, V.type[jf], 1, L, iL, Fx, Fy, Fz);
           ring[RF_FX * M + sl] = Fx; ring[RF_FY * M + sl] = Fy; ring[RF_FZ * M + sl] = Fz;
           ring[RF_FL * M + sl] = ell;
         }
@@ -416,11 +419,11 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       if (!out && F2 > 0.0) {
         if (adaptive) {
           eta = eps0 * sqrt(beta * me) * vF;
-          lam = sqrt(beta / me) / eps0 * theta_p(V, eta);
+          lam = sqrt(beta / me) / eps0 * theta_p<PREC>(eta);
         } else {
           const double Fn = sqrt(F2);
           eta = eps0 * sqrt(beta * me) * vF / Fn;
-          lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * theta_p(V, eta);
+          lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * theta_p<PREC>(eta);
         }
       }
       p = lam / c;
@@ -479,9 +482,9 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
 // Dynamic LDS: the proposal rings of the block's 64/G atoms, then their
 // segment tables.
 #ifndef MD_CHAIN_WAVES_PER_SIMD
-#define MD_CHAIN_WAVES_PER_SIMD 1   // register budget of the chain kernel: 512 / this per lane
+#define MD_CHAIN_WAVES_PER_SIMD 2   // register budget of the chain kernel: 512 / this per lane
 #endif
-template <int G>
+template <int G, int PREC>
 __global__ __launch_bounds__(64, MD_CHAIN_WAVES_PER_SIMD) void k_chain(MDView V, MDProg P,
                                                                       const double4 *__restrict__ X) {
   extern __shared__ double lds_chain[];
@@ -520,7 +523,7 @@ __global__ __launch_bounds__(64, MD_CHAIN_WAVES_PER_SIMD) void k_chain(MDView V,
         ay = (fn.y + (op.flags == 0 ? fb.y : 0.0)) / me;
         az = (fn.z + (op.flags == 0 ? fb.z : 0.0)) / me;
       }
-      chain_op<G>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, T);
+      chain_op<G, PREC>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, T);
     }
   }
   if (r == 0) {
@@ -1122,27 +1125,33 @@ int chain_blocks_per_cu(int G, int S) {
   const size_t lds = chain_lds_bytes(G, S);
   hipError_t e = hipErrorInvalidValue;
   switch (G) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<1>, 64, lds); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<2>, 64, lds); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<4>, 64, lds); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<8>, 64, lds); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<16>, 64, lds); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<1, MD_FP64>, 64, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<2, MD_FP64>, 64, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<4, MD_FP64>, 64, lds); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<8, MD_FP64>, 64, lds); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<16, MD_FP64>, 64, lds); break;
   }
   return e == hipSuccess ? nb : 0;
 }
 
-hipError_t launch_chain(const MDView &V, const MDProg &P, const double4 *X, hipStream_t s) {
+template <int PREC>
+static void launch_chain_p(const MDView &V, const MDProg &P, const double4 *X, hipStream_t s) {
   const int G = V.chain_lanes;
   const long long threads = (long long)V.n * G;
   const int nb = (int)((threads + 63) / 64);   // wave-sized blocks spread the few long waves over all CUs
   const size_t lds = chain_lds_bytes(G, V.S);
   switch (G) {
-    case 1: hipLaunchKernelGGL((k_chain<1>), dim3(nb), dim3(64), lds, s, V, P, X); break;
-    case 2: hipLaunchKernelGGL((k_chain<2>), dim3(nb), dim3(64), lds, s, V, P, X); break;
-    case 4: hipLaunchKernelGGL((k_chain<4>), dim3(nb), dim3(64), lds, s, V, P, X); break;
-    case 8: hipLaunchKernelGGL((k_chain<8>), dim3(nb), dim3(64), lds, s, V, P, X); break;
-    default: hipLaunchKernelGGL((k_chain<16>), dim3(nb), dim3(64), lds, s, V, P, X); break;
+    case 1: hipLaunchKernelGGL((k_chain<1, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
+    case 2: hipLaunchKernelGGL((k_chain<2, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
+    case 4: hipLaunchKernelGGL((k_chain<4, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
+    case 8: hipLaunchKernelGGL((k_chain<8, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
+    default: hipLaunchKernelGGL((k_chain<16, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
   }
+}
+
+hipError_t launch_chain(const MDView &V, const MDProg &P, const double4 *X, hipStream_t s) {
+  if (V.precision == MD_FP32_MIXED) launch_chain_p<MD_FP32_MIXED>(V, P, X, s);
+  else launch_chain_p<MD_FP64>(V, P, X, s);
   return hipGetLastError();
 }
 
