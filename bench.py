@@ -3,10 +3,16 @@
 
 Workload (default): flexible 3-site water, 4096 molecules (12288 atoms) in a
 49.7 A box at 300 K, FP64; pair potentials split at r_s = 5 A (switch 1 A),
-long part out to r_c = 10 A handled by jumps (LJ: BPS, Coulomb: adaptive MRZ),
-dt = 1 fs, gamma = 1/ps. The comparator integrates the same system with
-BAOAB and full-range (r < r_c) forces. Inputs are synthetic (lattice start,
-then an untimed BAOAB equilibration); everything timed is resident in HBM.
+long part out to r_c = 10 A handled by jumps (LJ: BPS, Coulomb: adaptive MRZ,
+eps0 = 0.1 (kcal/mol/A)^-1), dt = 1 fs, gamma = 1/ps. The comparator
+integrates the same system with BAOAB and full-range (r < r_c) forces.
+Inputs are synthetic (lattice start, then an untimed BAOAB equilibration);
+everything timed is resident in HBM.
+
+Timed region: K steps replayed as HIP graphs of --graph-steps steps (plain
+launches with --graph-steps 0). Per-kernel durations for the roofline come
+from a second, profiled run of plain launches in the same process (HIP events
+on the library's stream).
 
 Prints ONE JSON line. --gpus N > 1 exits: this build runs on one GPU.
 """
@@ -19,15 +25,27 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 vector
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic work units (counted from the formulas):
-# one short-range pair term (chi * (LJ + DSF) and its gradient) and one jump
-# proposal (pair gradient of the long part + rate + acceptance).
+# Algorithmic work units, counted from the formulas (one flop per add, mul,
+# fma, division, square root or transcendental call):
+#  a short-range pair term: chi * (LJ + DSF) and its gradient, 78 flops;
+#  a full-range pair term (BAOAB comparator): LJ + DSF and gradient, 60 flops;
+#  a jump proposal: long-range pair gradient (1 - chi) U, rate at the
+#  proposal time, clock and acceptance, 93 flops.
 FLOP_PER_SHORT_PAIR = 78
 FLOP_PER_FULL_PAIR = 60
+FLOP_PER_PROPOSAL = 93
 BYTES_PER_ATOM_LOCAL = 7 * 32   # x (read+write), v (read+write), f_nb, f_b, x_ref reads
+# HBM bytes per launch of the chain kernel from FETCH_SIZE / WRITE_SIZE counters
+# scaled by a 256 MiB copy (profiles/k_chain_water4096_fp64.md), valid for the
+# kernel source whose sha256 starts with the given prefix, default workload only.
+CHAIN_TRAFFIC = {"sha256": "7b6d7d7c2c5be102", "bytes": 37191680,
+                 "workload": ("fp64", 4096, 12, 0.5, 0.1)}
+KERNELS = {0: "k_local (B/A/O updates)", 1: "k_force (short pairs)", 2: "k_bonded", 3: "row rebuild",
+           4: "k_chain (J/C jump chains)"}
 
 
 def parse():
@@ -38,14 +56,31 @@ def parse():
     ap.add_argument("--equil", type=int, default=4000, help="untimed BAOAB steps at 0.5 fs, gamma 10/ps")
     ap.add_argument("--n-mol", type=int, default=4096)
     ap.add_argument("--eps0", type=float, default=0.1, help="adaptive eps0 in (kcal/mol/A)^-1")
-    ap.add_argument("--rings", type=int, default=6)
-    ap.add_argument("--skin", type=float, default=1.0)
+    ap.add_argument("--rings", type=int, default=12)
+    ap.add_argument("--skin", type=float, default=0.5)
+    ap.add_argument("--baoab-skin", type=float, default=None, help="list skin of the BAOAB comparator (default: --skin)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-baoab", action="store_true")
     ap.add_argument("--chain-lanes", type=int, default=0, help="lanes per atom in the jump chains (0 = auto)")
-    ap.add_argument("--graph-steps", type=int, default=0, help="steps per replayed HIP graph (0 = plain launches)")
+    ap.add_argument("--graph-steps", type=int, default=20, help="steps per replayed HIP graph (0 = plain launches)")
+    ap.add_argument("--profile-steps", type=int, default=200, help="plain-launch steps timed per kernel")
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
+                    help="pair arithmetic of forces and jump rates (fp32: mixed, FP64 state)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}), flush=True)
 
 
 def timed(sim, fn, steps, warmup):
@@ -53,15 +88,28 @@ def timed(sim, fn, steps, warmup):
     fn(warmup)
     sim.sync()
     torch.cuda.synchronize()
-    sim.profile(True)
     t0 = time.perf_counter()
     fn(steps)
     sim.sync()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = {k: sim.profile_read(k) for k in range(5)}
+    return time.perf_counter() - t0
+
+
+def kernel_profile(sim, fn, steps):
+    """Per-kernel totals (ms) and launch counts over `steps` plain-launch steps."""
+    import torch
+    sim.sync()
+    torch.cuda.synchronize()
+    sim.profile(True)
+    fn(steps)
+    sim.sync()
+    prof = {k: sim.profile_read(k) for k in KERNELS}
     sim.profile(False)
-    return t1 - t0, prof
+    return prof
+
+
+def ns_per_day(dt_ps, steps, seconds):
+    return dt_ps * 1e-3 * (steps / seconds) * 86400.0
 
 
 def main():
@@ -70,11 +118,15 @@ def main():
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
-    import numpy as np
     import torch
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    if a.calibrate_copy:
+        calibrate_copy(a.calibrate_copy)
+        return
+    import ctypes as C
     from paper_2412_15073_amd import jumpmd, systems as S
 
-    assert torch.cuda.is_available(), "bench needs a GPU"
+    prec = 1 if a.precision == "fp32" else 0
     sysm = S.water_box(a.n_mol, seed=1)
     split = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=a.skin, n_rings=a.rings)
     print(f"[bench] water {a.n_mol} molecules ({sysm.n_atoms} atoms), box {sysm.box[0]:.2f} A", flush=True)
@@ -90,72 +142,98 @@ def main():
           flush=True)
     sysm.pos, sysm.vel = x, v
 
-    # JUMP (C' J' A O A J' C'), FP64
-    pj = S.water_params(eps0_per_kcal=a.eps0)
-    pj.chain_lanes = a.chain_lanes
-    pj.graph_steps = a.graph_steps
+    def params(jumps, graph):
+        p = S.water_params(eps0_per_kcal=a.eps0, jumps=jumps)
+        p.chain_lanes = a.chain_lanes
+        p.graph_steps = graph
+        p.precision = prec
+        return p
+
+    # JUMP (C' J' A O A J' C'): timed run
+    pj = params(True, a.graph_steps)
     js = jumpmd.Sim(sysm, split, pj)
     p0 = js.proposals_total()
-    dt_j, prof_j = timed(js, js.step_jump, a.steps, a.warmup)
+    dt_j = timed(js, js.step_jump, a.steps, a.warmup)
     props = (js.proposals_total() - p0) / (a.steps + a.warmup)
-    pairs_short = js._counters_pairs() if hasattr(js, "_counters_pairs") else None
     obs_j = js.observables()
-    import ctypes as C
     pl, pt = C.c_int64(0), C.c_int64(0)
     jumpmd.load().md_counters(js._h, C.byref(pl), C.byref(pt))
     pairs_short = pl.value
+    xj, vj = js.state()
     js.close()
     ms_j = 1e3 * dt_j / a.steps
-    ns_day_j = pj.dt * 1e3 * 1e-6 * (a.steps / dt_j) * 86400.0
+    ns_day_j = ns_per_day(pj.dt, a.steps, dt_j)
     print(f"[bench] JUMP {ms_j:.4f} ms/step, {ns_day_j:.1f} ns/day, T = {obs_j['temperature']:.1f} K, "
           f"{props:.0f} proposals/step, {pairs_short} short pairs", flush=True)
 
-    # BAOAB, full-range forces, FP64 (comparator)
+    # JUMP per-kernel profile: plain launches from the timed run's final state
+    s2 = S.water_box(a.n_mol, seed=1)
+    s2.pos, s2.vel = xj, vj
+    jp = jumpmd.Sim(s2, split, params(True, 0))
+    jp.step_jump(a.warmup)
+    q0 = jp.proposals_total()
+    prof_j = kernel_profile(jp, jp.step_jump, a.profile_steps)
+    props_prof = (jp.proposals_total() - q0) / a.profile_steps
+    jp.close()
+
+    # BAOAB, full-range forces (comparator)
     ns_day_b = ms_b = pairs_full = None
     prof_b = None
     if not a.no_baoab:
-        pb = S.water_params(jumps=False)
-        pb.graph_steps = a.graph_steps
-        bs = jumpmd.Sim(sysm, split, pb)
-        dt_b, prof_b = timed(bs, bs.step_baoab, a.steps, a.warmup)
+        split_b = split if a.baoab_skin is None else S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=a.baoab_skin,
+                                                                   n_rings=a.rings)
+        pb = params(False, a.graph_steps)
+        bs = jumpmd.Sim(sysm, split_b, pb)
+        dt_b = timed(bs, bs.step_baoab, a.steps, a.warmup)
         jumpmd.load().md_counters(bs._h, C.byref(pl), C.byref(pt))
         pairs_full = pl.value
         obs_b = bs.observables()
         bs.close()
         ms_b = 1e3 * dt_b / a.steps
-        ns_day_b = pb.dt * 1e3 * 1e-6 * (a.steps / dt_b) * 86400.0
+        ns_day_b = ns_per_day(pb.dt, a.steps, dt_b)
+        bp = jumpmd.Sim(sysm, split_b, params(False, 0))
+        bp.step_baoab(a.warmup)
+        prof_b = kernel_profile(bp, bp.step_baoab, a.profile_steps)
+        bp.close()
         print(f"[bench] BAOAB-full {ms_b:.4f} ms/step, {ns_day_b:.1f} ns/day, T = {obs_b['temperature']:.1f} K, "
               f"{pairs_full} pairs", flush=True)
 
     # dominant kernel of the JUMP step and its roofline
-    names = {0: "k_local (B/A/O updates)", 1: "k_force (short pairs)", 2: "k_bonded", 3: "row rebuild",
-             4: "k_chain (J/C jump chains)"}
     dom = max(prof_j, key=lambda k: prof_j[k][0])
     tot_ms, launches = prof_j[dom]
     avg_s = tot_ms * 1e-3 / max(launches, 1)
-    if dom == 1:
+    peak = PEAK_FP32_TFLOPS if prec else PEAK_FP64_TFLOPS
+    if dom == 4:
+        # one launch = one step's chains: proposals x algorithmic flops per proposal
+        work = props_prof * FLOP_PER_PROPOSAL
+        roof = {"bound": "alu", "achieved": work / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s"}
+    elif dom == 1:
         work = pairs_short * FLOP_PER_SHORT_PAIR
-        roof = {"kernel": names[dom], "bound": "alu", "achieved": work / avg_s / 1e12,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
-    elif dom == 4:
-        # per launch: one step's chains; work = proposals x pair-gradient flops
-        work = props * FLOP_PER_SHORT_PAIR
-        roof = {"kernel": names[dom], "bound": "alu", "achieved": work / avg_s / 1e12,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+        roof = {"bound": "alu", "achieved": work / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s"}
     else:
         work = sysm.n_atoms * BYTES_PER_ATOM_LOCAL
-        roof = {"kernel": names[dom], "bound": "hbm", "achieved": work / avg_s / 1e9,
-                "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+        roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["avg_launch_us"] = avg_s * 1e6
     roof["traffic"] = None
-    kernel_ms = {names[k]: round(prof_j[k][0] / max(1, a.steps), 5) for k in prof_j}
+    if dom == 4 and (a.precision, a.n_mol, a.rings, a.skin, a.eps0) == CHAIN_TRAFFIC["workload"]:
+        import hashlib
+        src = os.path.join(ROOT, "paper_2412_15073_amd", "csrc", "md_kernels.hip")
+        with open(src, "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest().startswith(CHAIN_TRAFFIC["sha256"]):
+                roof["traffic"] = CHAIN_TRAFFIC["bytes"]
+    roof["kernel"] = KERNELS[dom]
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["launches"] = launches
+
+    def per_step(prof):
+        return {KERNELS[k]: round(prof[k][0] / a.profile_steps, 5) for k in prof if prof[k][1]}
 
     # CPU baseline: the oracle, single thread, on a bounded sample of the same workload
     cpu = None
     if not a.no_cpu_baseline:
         from oracle.oracle import OracleSim
-        o = OracleSim(sysm, split, pj)
+        po = params(True, 0)
+        o = OracleSim(sysm, split, po)
         t = time.perf_counter()
         o.step_jump(1)
         first = time.perf_counter() - t
@@ -163,18 +241,17 @@ def main():
         t = time.perf_counter()
         o.step_jump(n_more)
         el = time.perf_counter() - t
-        cpu = {"value": pj.dt * 1e3 * 1e-6 * (n_more / el) * 86400.0, "unit": "ns/day", "cores": 1,
-               "kind": "oracle",
+        cpu = {"value": ns_per_day(po.dt, n_more, el), "unit": "ns/day", "cores": 1, "kind": "oracle",
                "sample": f"{n_more} JUMP steps of the same {sysm.n_atoms}-atom water system after 1 untimed step "
-                         f"(brute-force O(N^2) pair sums), {el:.1f} s"}
+                         f"(brute-force O(N^2) pair sums, single thread), {el:.1f} s"}
         print(f"[bench] oracle {el / n_more:.3f} s/step", flush=True)
 
     line = {
         "metric": "ns/day & pair-interactions/s, JUMP vs full-force BAOAB, 1 MI355X, matched T/RDF/D",
         "value": ns_day_j, "unit": "ns/day", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms_j, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic (lattice water, BAOAB-equilibrated, seeded)",
-        "config": {"workload": f"water_{a.n_mol}mol_jump_fp64", "n_atoms": sysm.n_atoms,
+        "dtype": "f64" if prec == 0 else "f32+f64", "data": "synthetic (lattice water, BAOAB-equilibrated, seeded)",
+        "config": {"workload": f"water_{a.n_mol}mol_jump_{a.precision}", "n_atoms": sysm.n_atoms,
                    "box_A": round(float(sysm.box[0]), 3), "r_s": 5.0, "r_c": 10.0, "switch": 1.0,
                    "skin": a.skin, "rings": a.rings, "dt_fs": 1.0, "gamma_per_ps": 1.0, "T_K": 300,
                    "eps0_per_kcal_mol_A": a.eps0, "jumps": "LJ BPS + Coulomb adaptive MRZ",
@@ -186,7 +263,8 @@ def main():
             "effective": (pairs_full * a.steps / dt_j) if pairs_full else None,
             "baoab_full": (pairs_full * 1e3 / ms_b) if pairs_full else None},
         "proposals_per_step": props, "short_pairs": pairs_short, "full_pairs": pairs_full,
-        "kernel_ms_per_step": kernel_ms,
+        "kernel_ms_per_step": per_step(prof_j),
+        "baoab_kernel_ms_per_step": per_step(prof_b) if prof_b else None,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -201,10 +201,11 @@ class Sim:
         if rc != MD_OK:
             raise MDError(rc, L.md_last_error(None).decode())
         self._h = h
+        self._lib = L   # kept for close() during interpreter shutdown
 
     def close(self):
         if getattr(self, "_h", None):
-            load().md_destroy(self._h)
+            self._lib.md_destroy(self._h)
             self._h = None
 
     __del__ = close
