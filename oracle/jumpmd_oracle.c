@@ -44,42 +44,42 @@
 #define MAX_PROPOSALS (1ll << 22) /* per chain and half step */
 
 /* ------------------------------------------------------------------------ */
-/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of a
- * multiply-based bijection keyed by a Weyl sequence. */
-static void mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo) {
-  unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
-  *hi = (uint64_t)(p >> 64);
-  *lo = (uint64_t)p;
-}
-
-void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
-  uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
-  uint64_t k0 = key[0], k1 = key[1];
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of a
+ * multiply-based bijection on four 32-bit words, keyed by a Weyl sequence
+ * on two 32-bit key words. */
+void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
   for (int r = 0; r < 10; r++) {
     if (r > 0) {
-      k0 += 0x9E3779B97F4A7C15ULL;
-      k1 += 0xBB67AE8584CAA73BULL;
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
     }
-    uint64_t hi0, lo0, hi1, lo1;
-    mulhilo64(0xD2E7470EE14C6C93ULL, c0, &hi0, &lo0);
-    mulhilo64(0xCA5A826395121157ULL, c2, &hi1, &lo1);
-    uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
     c0 = n0; c1 = n1; c2 = n2; c3 = n3;
   }
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* uniform in the open interval (0,1): (top 52 bits + 1/2) / 2^52, exact */
-double orc_u01(uint64_t w) {
-  return ((double)(w >> 12) + 0.5) * (1.0 / 4503599627370496.0);
+/* uniform in the open interval (0,1): (word + 1/2) / 2^32, exact */
+double orc_u01(uint32_t w) {
+  return ((double)w + 0.5) * (1.0 / 4294967296.0);
 }
 
+/* One block of four uniforms. Counter words: step, local atom index,
+ * tag = phase | substep << 8 | Z-iteration << 24, proposal index k (each
+ * taken modulo 2^32); key words: low and high halves of the seed, the
+ * high half xor the replica index. */
 static void draw4(uint64_t seed, uint64_t replica, int64_t step, int64_t atom,
                   uint64_t tag, int64_t k, double u[4]) {
-  uint64_t ctr[4] = {(uint64_t)step, (uint64_t)atom, tag, (uint64_t)k};
-  uint64_t key[2] = {seed, replica};
-  uint64_t w[4];
-  orc_philox4x64(ctr, key, w);
+  uint32_t ctr[4] = {(uint32_t)step, (uint32_t)atom, (uint32_t)tag, (uint32_t)k};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ (uint32_t)replica};
+  uint32_t w[4];
+  orc_philox4x32(ctr, key, w);
   for (int q = 0; q < 4; q++) u[q] = orc_u01(w[q]);
 }
 
@@ -463,6 +463,15 @@ static double long_grad(const orc_sim *s, int i, int j, int coulomb, double F[3]
 }
 
 /* ------------------------------------------------------------ event log */
+/* Per-atom fingerprint of the accepted jumps (not part of the method): each
+ * event (step, phase, partner) is folded in with one multiply-xorshift. */
+uint64_t orc_event_mix(uint64_t h, int64_t step, int32_t phase, int32_t j) {
+  uint64_t key = (uint64_t)step * 0x9E3779B97F4A7C15ULL + (uint64_t)(uint32_t)phase * 0xC2B2AE3D27D4EB4FULL +
+                 (uint64_t)(uint32_t)j;
+  h = (h ^ key) * 0xFF51AFD7ED558CCDULL;
+  return h ^ (h >> 29);
+}
+
 static uint64_t fnv1a_bytes(uint64_t h, const void *p, size_t n) {
   const unsigned char *b = (const unsigned char *)p;
   for (size_t q = 0; q < n; q++) {
@@ -473,13 +482,7 @@ static uint64_t fnv1a_bytes(uint64_t h, const void *p, size_t n) {
 }
 
 static void log_event(orc_sim *s, int32_t phase, int i, int j, int64_t k) {
-  uint64_t st = (uint64_t)s->step;
-  uint32_t ph = (uint32_t)phase, jj = (uint32_t)j;
-  uint64_t h = s->hash[i];
-  h = fnv1a_bytes(h, &st, 8);
-  h = fnv1a_bytes(h, &ph, 4);
-  h = fnv1a_bytes(h, &jj, 4);
-  s->hash[i] = h;
+  s->hash[i] = orc_event_mix(s->hash[i], s->step, phase, j);
   s->nacc[i]++;
   if (!s->log_events) return;
   if (s->nev == s->evcap) {

@@ -73,8 +73,9 @@ typedef struct {
 typedef struct orc_sim orc_sim;
 
 /* primitives */
-void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
-double orc_u01(uint64_t w);
+void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_u01(uint32_t w);
+uint64_t orc_event_mix(uint64_t h, int64_t step, int32_t phase, int32_t j);
 double orc_theta(double eta);
 double orc_zsample(double eta, uint64_t seed, uint64_t replica, int64_t step,
                    int64_t atom, int32_t phase, int64_t k, int32_t *iters);

@@ -21,6 +21,7 @@ _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 _lp = C.POINTER(C.c_int64)
 _up = C.POINTER(C.c_uint64)
+_u32p = C.POINTER(C.c_uint32)
 
 
 class OrcSystem(C.Structure):
@@ -92,9 +93,11 @@ def lib():
         L.orc_phase_c.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_int]
         L.orc_phase_j.argtypes = [C.c_void_p, C.c_int32, C.c_double]
         L.orc_phase_o.argtypes = [C.c_void_p, C.c_double, C.c_int32]
-        L.orc_philox4x64.argtypes = [_up, _up, _up]
-        L.orc_u01.argtypes = [C.c_uint64]
+        L.orc_philox4x32.argtypes = [_u32p, _u32p, _u32p]
+        L.orc_u01.argtypes = [C.c_uint32]
         L.orc_u01.restype = C.c_double
+        L.orc_event_mix.argtypes = [C.c_uint64, C.c_int64, C.c_int32, C.c_int32]
+        L.orc_event_mix.restype = C.c_uint64
         L.orc_theta.argtypes = [C.c_double]
         L.orc_theta.restype = C.c_double
         L.orc_zsample.argtypes = [C.c_double, C.c_uint64, C.c_uint64, C.c_int64, C.c_int64,
@@ -110,16 +113,20 @@ def _ptr(a, t):
 
 
 # ------------------------------------------------------------------ primitives
-def philox4x64(ctr, key):
-    c = np.ascontiguousarray(ctr, dtype=np.uint64)
-    k = np.ascontiguousarray(key, dtype=np.uint64)
-    out = np.zeros(4, dtype=np.uint64)
-    lib().orc_philox4x64(_ptr(c, _up), _ptr(k, _up), _ptr(out, _up))
+def philox4x32(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32(_ptr(c, _u32p), _ptr(k, _u32p), _ptr(out, _u32p))
     return out
 
 
 def u01(w):
-    return lib().orc_u01(C.c_uint64(int(w)))
+    return lib().orc_u01(C.c_uint32(int(w)))
+
+
+def event_mix(h, step, phase, j):
+    return lib().orc_event_mix(C.c_uint64(int(h)), int(step), int(phase), int(j))
 
 
 def theta(eta):

@@ -414,7 +414,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
 
   MDView &V = c->V;
   V.n = n; V.nt = nt; V.nrep = nrep; V.nr = nr; V.S = c->S;
-  V.rs = sp->r_s; V.rc = sp->r_c; V.w = sp->switch_width; V.rlo = sp->r_s - sp->switch_width;
+  V.rs = sp->r_s; V.rc = sp->r_c; V.w = sp->switch_width; V.inv_w = 1.0 / sp->switch_width; V.rlo = sp->r_s - sp->switch_width;
   V.skin = sp->skin; V.rin = V.rlo - V.skin; V.rout = V.rc + V.skin;
   V.rw = nr == 1 ? V.rout - V.rin : sp->ring_width;
   V.alpha = sp->coulomb_alpha; V.ke = s->coulomb_k;

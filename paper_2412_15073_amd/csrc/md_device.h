@@ -14,36 +14,37 @@
 #define MD_INV_SQRT_2PI 0.3989422804014327
 
 // ----------------------------------------------------------------- random
-// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11). Counter words:
-// (step, local atom index, phase | substep<<8 | zsampler_iteration<<24, k);
-// key words: (seed, replica index).
-struct u64x4 { uint64_t w[4]; };
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). Counter words: step,
+// local atom index, tag = phase | substep << 8 | Z iteration << 24, proposal
+// index k (each modulo 2^32); key words: low half of the seed, high half of
+// the seed xor the replica index.
+struct u32x4 { uint32_t w[4]; };
 
-__device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                                uint64_t k0, uint64_t k1) {
+__device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    if (r > 0) { k0 += 0x9E3779B97F4A7C15ull; k1 += 0xBB67AE8584CAA73Bull; }
-    const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
-    uint64_t hi0 = __umul64hi(m0, c0), lo0 = m0 * c0;
-    uint64_t hi1 = __umul64hi(m1, c2), lo1 = m1 * c2;
-    uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
   }
-  u64x4 o; o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
+  u32x4 o; o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
   return o;
 }
 
-// uniform in (0,1): (w >> 12 + 1/2) * 2^-52, exact in FP64
-__device__ __forceinline__ double u01(uint64_t w) {
-  return ((double)(w >> 12) + 0.5) * 2.220446049250313080847263336181640625e-16;
+// uniform in (0,1): (w + 1/2) * 2^-32, exact in FP64
+__device__ __forceinline__ double u01(uint32_t w) {
+  return ((double)w + 0.5) * 2.3283064365386962890625e-10;
 }
 
 struct Uni4 { double u[4]; };
 
 __device__ __forceinline__ Uni4 draw4(uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
                                       uint64_t tag, int64_t k) {
-  u64x4 r = philox4x64_10((uint64_t)step, (uint64_t)atom, tag, (uint64_t)k, seed, rep);
+  const u32x4 r = philox4x32_10((uint32_t)step, (uint32_t)atom, (uint32_t)tag, (uint32_t)k,
+                                (uint32_t)seed, (uint32_t)(seed >> 32) ^ (uint32_t)rep);
   Uni4 o;
 #pragma unroll
   for (int q = 0; q < 4; ++q) o.u[q] = u01(r.w[q]);
@@ -51,12 +52,13 @@ __device__ __forceinline__ Uni4 draw4(uint64_t seed, uint64_t rep, int64_t step,
 }
 
 // ------------------------------------------------------------ event hash
-__device__ __forceinline__ uint64_t fnv1a_u64(uint64_t h, uint64_t x, int nbytes) {
-  for (int b = 0; b < nbytes; ++b) {
-    h ^= (x >> (8 * b)) & 0xffull;
-    h *= 0x100000001b3ull;
-  }
-  return h;
+// Per-atom fingerprint of the accepted jumps (step, phase, partner), one
+// multiply-xorshift per event.
+__device__ __forceinline__ uint64_t event_mix(uint64_t h, int64_t step, int phase, int j) {
+  const uint64_t key = (uint64_t)step * 0x9E3779B97F4A7C15ull + (uint64_t)(uint32_t)phase * 0xC2B2AE3D27D4EB4Full +
+                       (uint64_t)(uint32_t)j;
+  h = (h ^ key) * 0xFF51AFD7ED558CCDull;
+  return h ^ (h >> 29);
 }
 
 // ------------------------------------------------------- context view
@@ -131,7 +133,7 @@ struct MDView {
   MDCtl *ctl;
   MDEventDev *ev; long long ev_cap;
   // constants
-  double rs, rc, w, rlo, skin, rin, rout, rw, alpha, ke;
+  double rs, rc, w, inv_w, rlo, skin, rin, rout, rw, alpha, ke;
   double dsf_erfc_rc_over_rc, dsf_fc, two_a_sqpi;
   double beta, kT, eps0;
   int jlj, jc, log_events, precision;
@@ -146,53 +148,53 @@ __device__ __forceinline__ double min_img(double d, double L, double iL) {
 
 // --------------------------------------------------------- pair terms (FP64)
 // LJ energy-shifted at r_c: U = c12/r^12 - c6/r^6 - shift; Sec. 3.2.
-__device__ __forceinline__ void lj_pair(double r2, double r, double c12, double c6, double shift,
-                                        double &U, double &dU) {
-  double ir2 = 1.0 / r2, ir6 = ir2 * ir2 * ir2;
+// ir = 1/r (one reciprocal per pair serves every term).
+__device__ __forceinline__ void lj_pair(double ir, double c12, double c6, double shift, double &U, double &dU) {
+  const double ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
   U = ir6 * (c12 * ir6 - c6) - shift;
-  dU = (-12.0 * c12 * ir6 * ir6 + 6.0 * c6 * ir6) / r;
+  dU = (-12.0 * c12 * ir6 * ir6 + 6.0 * c6 * ir6) * ir;
 }
 
 // Damped shifted-force Coulomb (Fennell-Gezelter 2006), zero value and slope at r_c.
-__device__ __forceinline__ void dsf_pair(double r, double kqq, const MDView &V, double &U, double &dU) {
-  double e = erfc(V.alpha * r);
-  double g = exp(-V.alpha * V.alpha * r * r);
-  U = kqq * (e / r - V.dsf_erfc_rc_over_rc + V.dsf_fc * (r - V.rc));
-  dU = kqq * (-(e / (r * r) + V.two_a_sqpi * g / r) + V.dsf_fc);
+__device__ __forceinline__ void dsf_pair(double r, double ir, double kqq, const MDView &V, double &U, double &dU) {
+  const double e = erfc(V.alpha * r);
+  const double g = exp(-V.alpha * V.alpha * r * r);
+  U = kqq * (e * ir - V.dsf_erfc_rc_over_rc + V.dsf_fc * (r - V.rc));
+  dU = kqq * (-(e * ir * ir + V.two_a_sqpi * g * ir) + V.dsf_fc);
 }
 
 // C2 quintic switch, 1 below r_s - w, 0 above r_s.
 __device__ __forceinline__ void switch_fn(double r, const MDView &V, double &chi, double &dchi) {
   if (r <= V.rlo) { chi = 1.0; dchi = 0.0; return; }
   if (r >= V.rs) { chi = 0.0; dchi = 0.0; return; }
-  double t = (r - V.rlo) / V.w;
+  const double t = (r - V.rlo) * V.inv_w;
   chi = 1.0 - t * t * t * (10.0 - 15.0 * t + 6.0 * t * t);
-  dchi = -30.0 * t * t * (1.0 - t) * (1.0 - t) / V.w;
+  dchi = -30.0 * t * t * (1.0 - t) * (1.0 - t) * V.inv_w;
 }
 
 // FP32 variants (mixed-precision path): pair arithmetic in float, with the
 // constants of the run rounded once; accumulation stays in FP64.
-__device__ __forceinline__ void lj_pair_f(float r2, float r, float c12, float c6, float shift, float &U, float &dU) {
-  float ir2 = 1.0f / r2, ir6 = ir2 * ir2 * ir2;
+__device__ __forceinline__ void lj_pair_f(float ir, float c12, float c6, float shift, float &U, float &dU) {
+  const float ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
   U = ir6 * (c12 * ir6 - c6) - shift;
-  dU = (-12.0f * c12 * ir6 * ir6 + 6.0f * c6 * ir6) / r;
+  dU = (-12.0f * c12 * ir6 * ir6 + 6.0f * c6 * ir6) * ir;
 }
 
-__device__ __forceinline__ void dsf_pair_f(float r, float kqq, const MDView &V, float &U, float &dU) {
+__device__ __forceinline__ void dsf_pair_f(float r, float ir, float kqq, const MDView &V, float &U, float &dU) {
   const float alpha = (float)V.alpha;
-  float e = erfcf(alpha * r);
-  float g = __expf(-alpha * alpha * r * r);
-  U = kqq * (e / r - (float)V.dsf_erfc_rc_over_rc + (float)V.dsf_fc * (r - (float)V.rc));
-  dU = kqq * (-(e / (r * r) + (float)V.two_a_sqpi * g / r) + (float)V.dsf_fc);
+  const float e = erfcf(alpha * r);
+  const float g = __expf(-alpha * alpha * r * r);
+  U = kqq * (e * ir - (float)V.dsf_erfc_rc_over_rc + (float)V.dsf_fc * (r - (float)V.rc));
+  dU = kqq * (-(e * ir * ir + (float)V.two_a_sqpi * g * ir) + (float)V.dsf_fc);
 }
 
 __device__ __forceinline__ void switch_fn_f(float r, const MDView &V, float &chi, float &dchi) {
-  const float rlo = (float)V.rlo, rs = (float)V.rs, w = (float)V.w;
+  const float rlo = (float)V.rlo, rs = (float)V.rs, iw = (float)V.inv_w;
   if (r <= rlo) { chi = 1.0f; dchi = 0.0f; return; }
   if (r >= rs) { chi = 0.0f; dchi = 0.0f; return; }
-  float t = (r - rlo) / w;
+  const float t = (r - rlo) * iw;
   chi = 1.0f - t * t * t * (10.0f - 15.0f * t + 6.0f * t * t);
-  dchi = -30.0f * t * t * (1.0f - t) * (1.0f - t) / w;
+  dchi = -30.0f * t * t * (1.0f - t) * (1.0f - t) * iw;
 }
 
 __device__ __forceinline__ float theta_fn_f(float eta) {

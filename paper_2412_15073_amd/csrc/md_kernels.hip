@@ -34,20 +34,21 @@ __device__ __forceinline__ double long_grad_f(const MDView &V, double4 xi, doubl
   const float dz = (float)min_img(xi.z - xj.z, L[2], iL[2]);
   const float r2 = dx * dx + dy * dy + dz * dz;
   const float r = sqrtf(r2);
+  const float ir = 1.0f / r;
   float U = 0.0f, dU = 0.0f;
   if (r < (float)V.rc) {
     if (coul) {
       const float qq = (float)(xi.w * xj.w);
-      if (qq != 0.0f) dsf_pair_f(r, (float)V.ke * qq, V, U, dU);
+      if (qq != 0.0f) dsf_pair_f(r, ir, (float)V.ke * qq, V, U, dU);
     } else {
       const int ab = a * V.nt + b;
       const float c12 = (float)V.c12[ab], c6 = (float)V.c6[ab];
-      if (c12 != 0.0f || c6 != 0.0f) lj_pair_f(r2, r, c12, c6, (float)V.ljshift[ab], U, dU);
+      if (c12 != 0.0f || c6 != 0.0f) lj_pair_f(ir, c12, c6, (float)V.ljshift[ab], U, dU);
     }
   }
   float chi, dchi;
   switch_fn_f(r, V, chi, dchi);
-  const float g = ((1.0f - chi) * dU - dchi * U) / r;
+  const float g = ((1.0f - chi) * dU - dchi * U) * ir;
   Fx = (double)(g * dx); Fy = (double)(g * dy); Fz = (double)(g * dz);
   return Fx * Fx + Fy * Fy + Fz * Fz;
 }
@@ -61,21 +62,22 @@ __device__ __forceinline__ double long_grad_d(const MDView &V, double4 xi, doubl
   double dz = min_img(xi.z - xj.z, L[2], iL[2]);
   double r2 = dx * dx + dy * dy + dz * dz;
   double r = sqrt(r2);
+  const double ir = 1.0 / r;
   double U = 0.0, dU = 0.0;
   if (r < V.rc) {
     if (coul) {
       double qq = xi.w * xj.w;
-      if (qq != 0.0) dsf_pair(r, V.ke * qq, V, U, dU);
+      if (qq != 0.0) dsf_pair(r, ir, V.ke * qq, V, U, dU);
     } else {
       int ab = a * V.nt + b;
       double c12 = V.c12[ab], c6 = V.c6[ab];
-      if (c12 != 0.0 || c6 != 0.0) lj_pair(r2, r, c12, c6, V.ljshift[ab], U, dU);
+      if (c12 != 0.0 || c6 != 0.0) lj_pair(ir, c12, c6, V.ljshift[ab], U, dU);
     }
   }
   double chi, dchi;
   switch_fn(r, V, chi, dchi);
-  double g = (1.0 - chi) * dU - dchi * U;
-  Fx = g * dx / r; Fy = g * dy / r; Fz = g * dz / r;
+  const double g = ((1.0 - chi) * dU - dchi * U) * ir;
+  Fx = g * dx; Fy = g * dy; Fz = g * dz;
   return Fx * Fx + Fy * Fy + Fz * Fz;
 }
 
@@ -96,11 +98,7 @@ struct AtomStats { long long nprop, nacc, nviol; uint64_t hash; };
 
 __device__ __forceinline__ void log_jump(const MDView &V, AtomStats &st, int64_t step, int phase,
                                          int i, int j, int64_t k) {
-  uint64_t h = st.hash;
-  h = fnv1a_u64(h, (uint64_t)step, 8);
-  h = fnv1a_u64(h, (uint64_t)(uint32_t)phase, 4);
-  h = fnv1a_u64(h, (uint64_t)(uint32_t)V.loc[j], 4);
-  st.hash = h;
+  st.hash = event_mix(st.hash, step, phase, V.loc[j]);
   st.nacc++;
   if (V.log_events) {
     unsigned long long e = atomicAdd(&V.ctl->n_events, 1ull);
@@ -113,11 +111,7 @@ __device__ __forceinline__ void log_jump(const MDView &V, AtomStats &st, int64_t
 
 // the part of log_jump every lane of a group repeats (replicated statistics)
 __device__ __forceinline__ void log_jump_hash_only(const MDView &V, AtomStats &st, int64_t step, int phase, int j) {
-  uint64_t h = st.hash;
-  h = fnv1a_u64(h, (uint64_t)step, 8);
-  h = fnv1a_u64(h, (uint64_t)(uint32_t)phase, 4);
-  h = fnv1a_u64(h, (uint64_t)(uint32_t)V.loc[j], 4);
-  st.hash = h;
+  st.hash = event_mix(st.hash, step, phase, V.loc[j]);
   st.nacc++;
 }
 
@@ -154,17 +148,25 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int G>
-__device__ __forceinline__ int group_min(int x) {
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, G));
+// Reductions over the G lanes of a group (G <= 16, groups aligned in the
+// wave) with DPP lane permutations: swap neighbours, swap pairs, mirror
+// within 8 lanes, mirror within 16 lanes. Every lane of the group must be
+// active (group control flow is uniform).
+template <int G, typename Op>
+__device__ __forceinline__ int group_reduce(int x, Op op) {
+  if (G >= 2) x = op(x, __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  if (G >= 4) x = op(x, __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  if (G >= 8) x = op(x, __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  if (G >= 16) x = op(x, __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false)); // row_mirror
   return x;
 }
 template <int G>
+__device__ __forceinline__ int group_min(int x) {
+  return group_reduce<G>(x, [](int a, int b) { return a < b ? a : b; });
+}
+template <int G>
 __device__ __forceinline__ int group_sum(int x) {
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, G);
-  return x;
+  return group_reduce<G>(x, [](int a, int b) { return a + b; });
 }
 
 // |F|^2 evaluated the same way wherever it is needed
@@ -254,9 +256,9 @@ __device__ __forceinline__ bool z_iteration(double eta, double u0, double u1, do
   if (eta > 0.0) {
     const double p_ray = 1.0 / (1.0 + eta * 2.5066282746310002);
     const double rad = sqrt(-2.0 * log(u1));
-    const double y = (u0 < p_ray) ? rad : rad * cos(2.0 * MD_PI * u2);
+    const double y = (u0 < p_ray) ? rad : rad * cospi(2.0 * u2);
     z = eta + y;
-    return (y >= 0.0) || (z > 0.0 && u3 <= z / eta);
+    return (y >= 0.0) || (z > 0.0 && u3 * eta <= z);
   } else if (eta >= -1.0) {
     z = sqrt(-2.0 * log(u0));
     return u1 <= exp(eta * z);
@@ -322,10 +324,16 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   const int64_t li = V.loc[i];
   const double h = op.h;
   const double vn = sqrt(vx * vx + vy * vy + vz * vz);   // J: |v| for the whole op
+  // per-op constants of the MRZ rate and kernel (Sec. 2.4)
+  const double sbm = sqrt(beta * me);
+  const double k_eta = eps0 * sbm;
+  const double k_lam = adaptive ? sqrt(beta / me) / eps0 : sqrt(beta) / (eps0 * sqrt(me));
+  const double k_coef = adaptive ? 2.0 * eps0 / sbm : 2.0 * eps0 / ((1.0 + eps0 * eps0) * sbm);
+  int n_counted = 0, n_viol = 0;   // lane-local, reduced over the group at the end
   int64_t w0 = 0, computed = 0;
   int ws = 0, cs = 0;   // ring slots of w0 and of computed
   double vex = vx, vey = vy, vez = vz, te = 0.0, base = 0.0;
-  double tau = h, bBv = 0.0, Wb = 0.0, Lam = 0.0;
+  double tau = h, bBv = 0.0, Wb = 0.0, Lam = 0.0, iLam = 0.0;
   bool live = true, epoch = true;
   auto finish = [&]() {
     if (isC) { vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az; }
@@ -342,6 +350,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         bBv = beta * Bv;
         Wb = bBv * T.W;
         Lam = adaptive ? Wb + f * T.nf : (bBv + f) * T.W;
+        iLam = 1.0 / Lam;
         base = 0.0;
         if (!(Lam > 0.0) || !isfinite(Lam)) {
           if (!(Lam <= 0.0) && r == 0) atomicAdd(&V.ctl->nonfinite, 1ull);
@@ -349,6 +358,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         }
       } else {
         Lam = V.beta * vn * T.W;
+        iLam = 1.0 / Lam;
         if (!(Lam > 0.0)) finish();
         else if (!isfinite(Lam)) { if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull); finish(); }
       }
@@ -406,10 +416,11 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     const double ell = ring[fo + RF_BL * M + sl];
     const double F2 = norm2_nc(Fx, Fy, Fz);
     const double u3 = ring[RF_U3 * M + sl];
-    bool out, acc;
-    double p, eta = 0.0, tk = 0.0;
+    // acceptance u3 <= lam / c and bound violation lam > c, tested without dividing
+    bool out, acc, viol;
+    double eta = 0.0, tk = 0.0;
     if (isC) {
-      tk = te + s / Lam;
+      tk = te + s * iLam;
       out = tk > h;
       const double dtk = tk - te;
       const double vkx = vex + dtk * ax, vky = vey + dtk * ay, vkz = vez + dtk * az;
@@ -418,33 +429,37 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       const double vF = vkx * Fx + vky * Fy + vkz * Fz;
       if (!out && F2 > 0.0) {
         if (adaptive) {
-          eta = eps0 * sqrt(beta * me) * vF;
-          lam = sqrt(beta / me) / eps0 * theta_p<PREC>(eta);
+          eta = k_eta * vF;
+          lam = k_lam * theta_p<PREC>(eta);
         } else {
           const double Fn = sqrt(F2);
-          eta = eps0 * sqrt(beta * me) * vF / Fn;
-          lam = sqrt(beta) / (eps0 * sqrt(me)) * Fn * theta_p<PREC>(eta);
+          eta = k_eta * vF / Fn;
+          lam = k_lam * Fn * theta_p<PREC>(eta);
         }
       }
-      p = lam / c;
+      acc = !out && lam > 0.0 && u3 * c <= lam;
+      viol = lam > c;
     } else {
-      out = s / Lam > h;
+      out = s * iLam > h;
       const double vF = vx * Fx + vy * Fy + vz * Fz;
-      p = (vF > 0.0 ? vF : 0.0) / (vn * ell);
+      const double c = vn * ell;
+      acc = !out && vF > 0.0 && u3 * c <= vF;
+      viol = vF > c;
     }
-    acc = !out && p > 0.0 && u3 <= p;
     const int first = group_min<G>((out || acc) ? r : G);
     // proposals evaluated in this window: ranks before the event, plus an accepted one
     const bool counted = r < first || (r == first && acc);
-    st.nprop += group_sum<G>(counted ? 1 : 0);
-    st.nviol += group_sum<G>((counted && p > 1.0) ? 1 : 0);
+    n_counted += counted ? 1 : 0;
+    n_viol += (counted && viol) ? 1 : 0;
     if (first == G) { base = tot; w0 += G; ws = ring_add(ws, G, M); continue; }
     if (__shfl((int)out, first, G)) { finish(); continue; }
-    const double Fxs = __shfl(Fx, first, G), Fys = __shfl(Fy, first, G), Fzs = __shfl(Fz, first, G);
-    const double F2s = __shfl(F2, first, G);
+    // the accepted proposal's gradient, read by every lane of the group
     const int fs = ring_add(ws, first, M);
+    const int fos = __shfl(fo, first, G);
+    const double Fxs = ring[fos + RF_BX * M + fs], Fys = ring[fos + RF_BY * M + fs], Fzs = ring[fos + RF_BZ * M + fs];
+    const double F2s = norm2_nc(Fxs, Fys, Fzs);
     const int2 jj = ((const int2 *)(ring + RF_J * M))[fs];
-    const int j = __shfl((int)use_f, first, G) ? jj.y : jj.x;
+    const int j = fos ? jj.y : jj.x;
     const int64_t kstar = w0 + first;
     if (isC) {
       const double etas = __shfl(eta, first, G);
@@ -456,8 +471,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         Z = zsample_grp<G>(etas, V.seed, rep, op.step, li, op.phase, kstar, r, 1, ovf);
         if (ovf && r == 0) atomicAdd(&V.ctl->n_zs_overflow, 1ull);
       }
-      const double coef = adaptive ? 2.0 * eps0 * Z / ((1.0 + eps0 * eps0 * F2s) * sqrt(beta * me))
-                                   : 2.0 * eps0 * Z / ((1.0 + eps0 * eps0) * sqrt(beta * me) * sqrt(F2s));
+      const double coef = adaptive ? k_coef * Z / (1.0 + eps0 * eps0 * F2s) : k_coef * Z / sqrt(F2s);
       const double dts = tks - te;
       vex = vex + dts * ax - coef * Fxs;
       vey = vey + dts * ay - coef * Fys;
@@ -475,6 +489,8 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     w0 = kstar + 1;
     ws = ring_add(ws, first + 1, M);
   }
+  st.nprop += group_sum<G>(n_counted);
+  st.nviol += group_sum<G>(n_viol);
 }
 
 // Chain kernel: the position-preserving prefix of a step program (B kicks,
@@ -851,14 +867,15 @@ __global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__rest
       const float r2 = dx * dx + dy * dy + dz * dz;
       if (r2 < cut2) {
         const float rr = sqrtf(r2);
+        const float ir = 1.0f / rr;
         const int ab = a * V.nt + V.type[j];
         float U = 0.0f, dU = 0.0f;
         const float c12 = (float)V.c12[ab], c6 = (float)V.c6[ab];
-        if (c12 != 0.0f || c6 != 0.0f) lj_pair_f(r2, rr, c12, c6, (float)V.ljshift[ab], U, dU);
+        if (c12 != 0.0f || c6 != 0.0f) lj_pair_f(ir, c12, c6, (float)V.ljshift[ab], U, dU);
         const float kqq = kq * (float)xj.w;
         if (kqq != 0.0f) {
           float Uc, dUc;
-          dsf_pair_f(rr, kqq, V, Uc, dUc);
+          dsf_pair_f(rr, ir, kqq, V, Uc, dUc);
           U += Uc; dU += dUc;
         }
         float g = dU;
@@ -867,7 +884,7 @@ __global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__rest
           switch_fn_f(rr, V, chi, dchi);
           g = chi * dU + dchi * U;
         }
-        const float sc = -g / rr;
+        const float sc = -g * ir;
         fx += (double)(sc * dx); fy += (double)(sc * dy); fz += (double)(sc * dz);
       }
     }
@@ -904,14 +921,15 @@ __global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restri
       double r2 = dx * dx + dy * dy + dz * dz;
       if (r2 < cut2) {
         double rr = sqrt(r2);
+        const double ir = 1.0 / rr;
         int ab = a * V.nt + V.type[j];
         double U = 0.0, dU = 0.0;
         double c12 = V.c12[ab], c6 = V.c6[ab];
-        if (c12 != 0.0 || c6 != 0.0) lj_pair(r2, rr, c12, c6, V.ljshift[ab], U, dU);
+        if (c12 != 0.0 || c6 != 0.0) lj_pair(ir, c12, c6, V.ljshift[ab], U, dU);
         double qq = xi.w * xj.w;
         if (qq != 0.0) {
           double Uc, dUc;
-          dsf_pair(rr, V.ke * qq, V, Uc, dUc);
+          dsf_pair(rr, ir, V.ke * qq, V, Uc, dUc);
           U += Uc; dU += dUc;
         }
         double g = dU;
@@ -920,7 +938,7 @@ __global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restri
           switch_fn(rr, V, chi, dchi);
           g = chi * dU + dchi * U;
         }
-        double s = -g / rr;
+        double s = -g * ir;
         fx += s * dx; fy += s * dy; fz += s * dz;
       }
     }
@@ -1019,9 +1037,10 @@ __global__ void k_pair_energy(MDView V, const double4 *__restrict__ X, int which
     if (rr >= V.rc) continue;
     int ab = a * V.nt + V.type[j];
     double U = 0.0, dU = 0.0;
-    if (V.c12[ab] != 0.0 || V.c6[ab] != 0.0) lj_pair(r2, rr, V.c12[ab], V.c6[ab], V.ljshift[ab], U, dU);
+    const double ir = 1.0 / rr;
+    if (V.c12[ab] != 0.0 || V.c6[ab] != 0.0) lj_pair(ir, V.c12[ab], V.c6[ab], V.ljshift[ab], U, dU);
     double qq = xi.w * xj.w;
-    if (qq != 0.0) { double Uc, dUc; dsf_pair(rr, V.ke * qq, V, Uc, dUc); U += Uc; }
+    if (qq != 0.0) { double Uc, dUc; dsf_pair(rr, ir, V.ke * qq, V, Uc, dUc); U += Uc; }
     double chi, dchi;
     switch_fn(rr, V, chi, dchi);
     if (which == 0 || which == 2) s += 0.5 * chi * U;

@@ -28,6 +28,15 @@ def rel_err(a, b):
     return float(np.abs(a - b).max() / scale)
 
 
+def event_mix(h, step, phase, j):
+    """Per-atom fingerprint update for one accepted jump (step, phase, partner):
+    h <- (h xor key) * C, then h xor (h >> 29), all modulo 2^64."""
+    m = 0xFFFFFFFFFFFFFFFF
+    key = (step * 0x9E3779B97F4A7C15 + (phase & 0xFFFFFFFF) * 0xC2B2AE3D27D4EB4F + (j & 0xFFFFFFFF)) & m
+    h = ((h ^ key) * 0xFF51AFD7ED558CCD) & m
+    return h ^ (h >> 29)
+
+
 def fnv1a64(h, data: bytes):
     for c in data:
         h ^= c

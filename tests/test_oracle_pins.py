@@ -13,32 +13,41 @@ import scipy.stats as st
 
 from oracle import oracle as O
 from paper_2412_15073_amd import systems as S
-from tests.helpers import lj_small, water_small, fnv1a64, rel_err
+from tests.helpers import lj_small, water_small, fnv1a64, event_mix, rel_err
 
 
 # ------------------------------------------------------------ random numbers
-def test_philox_matches_numpy():
-    """Philox4x64-10 against numpy's Philox bit generator (which advances the
-    counter by one before producing each block)."""
-    rng = np.random.default_rng(2024)
-    for _ in range(25):
-        key = rng.integers(0, 2 ** 63, size=2, dtype=np.uint64)
-        ctr = rng.integers(0, 2 ** 63, size=4, dtype=np.uint64)
-        expected = np.random.Philox(key=key, counter=ctr).random_raw(4)
-        c1 = ctr.copy()
-        c1[0] += np.uint64(1)
-        np.testing.assert_array_equal(O.philox4x64(c1, key), expected)
-    # carry into the second counter word
-    ctr = np.array([2 ** 64 - 1, 7, 0, 0], dtype=np.uint64)
-    key = np.array([1, 2], dtype=np.uint64)
-    expected = np.random.Philox(key=key, counter=ctr).random_raw(4)
-    np.testing.assert_array_equal(O.philox4x64(np.array([0, 8, 0, 0], np.uint64), key), expected)
+GOLDEN = __import__("pathlib").Path(__file__).parent / "golden"
+
+
+def test_philox4x32_known_answers():
+    """Philox4x32-10 against the published known-answer vectors (Random123)."""
+    n = 0
+    for line in (GOLDEN / "philox4x32_10_kat.txt").read_text().splitlines():
+        if not line.strip() or line.startswith("#"):
+            continue
+        w = [int(x, 16) for x in line.split()]
+        np.testing.assert_array_equal(O.philox4x32(w[0:4], w[4:6]), np.array(w[6:10], np.uint32))
+        n += 1
+    assert n == 3
+
+
+def test_philox4x32_is_a_bijection_of_the_counter():
+    """Distinct counters give distinct blocks (no collisions over a sample),
+    and words are uniform: mean and variance of u01 over 4 x 20000 draws."""
+    key = [0x12345678, 0x9ABCDEF0]
+    outs = np.array([O.philox4x32([c, 7, 3, 0], key) for c in range(20000)], dtype=np.uint64)
+    packed = set(map(tuple, outs.tolist()))
+    assert len(packed) == len(outs)
+    u = (outs.astype(np.float64) + 0.5) / 2.0 ** 32
+    assert abs(u.mean() - 0.5) < 5 * np.sqrt(1 / 12 / u.size)
+    assert abs(u.var() - 1 / 12) < 5 * np.sqrt(1 / 180 / u.size)
 
 
 def test_uniform_open_interval():
-    assert O.u01(0) == 2.0 ** -53
-    assert O.u01(2 ** 64 - 1) == 1.0 - 2.0 ** -53
-    assert O.u01(1 << 63) == 0.5 + 2.0 ** -53
+    assert O.u01(0) == 2.0 ** -33
+    assert O.u01(2 ** 32 - 1) == 1.0 - 2.0 ** -33
+    assert O.u01(1 << 31) == 0.5 + 2.0 ** -33
 
 
 # ----------------------------------------------------------- pair potentials
@@ -322,8 +331,7 @@ def test_event_log_and_hash_agree():
     assert len(ev) == stt["n_acc"].sum() > 0
     h = np.full(sy.n_atoms, 0xCBF29CE484222325, dtype=object)
     for step, phase, i, j, k in ev:
-        b = int(step).to_bytes(8, "little") + int(phase).to_bytes(4, "little") + int(j).to_bytes(4, "little")
-        h[i] = fnv1a64(int(h[i]), b)
+        h[i] = event_mix(int(h[i]), int(step), int(phase), int(j))
     np.testing.assert_array_equal(np.array(h, dtype=np.uint64), stt["hash"])
     run = 0xCBF29CE484222325
     for x in stt["hash"]:
