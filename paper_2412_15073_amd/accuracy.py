@@ -1,11 +1,17 @@
 """Sampling and dynamical accuracy of JUMP against full-range BAOAB on the GPU.
 
-Runs the same equilibrated water box with both integrators and compares the
-mean temperature, the O-O radial distribution function and the O diffusion
-constant (the quantities the paper uses to validate JUMP, Sec. 4: Fig. 1
-RDF/T, Fig. 2 diffusion). Prints one JSON line.
+Runs the same equilibrated water box with full-range BAOAB (FP64), JUMP
+(FP64) and JUMP with FP32 pair arithmetic, and compares the mean
+temperature, the mean potential energy, the O-O radial distribution function
+and the O self-diffusion constant: the quantities Sec. 4 of the paper uses to
+validate JUMP (temperature and RDF of water, Fig. 1; diffusion, Fig. 2).
+Prints one JSON line.
 
-    python -m paper_2412_15073_amd.accuracy --n-mol 1000 --ps 40
+    python -m paper_2412_15073_amd.accuracy --n-mol 4096 --ps 40
+
+Run specs (--runs, comma separated): baoab or jump, optionally with
+parameters after a colon, e.g. "baoab:dt=0.5", "jump:eps0=0.01;rs=7;fp32=1"
+(dt in fs, eps0 in (kcal/mol/A)^-1, rs = split radius in A).
 """
 import argparse
 import json
@@ -16,31 +22,31 @@ import numpy as np
 from . import analysis, jumpmd, systems as S
 
 
-def run(sim, step_fn, n_steps, every, n_o, o_idx, r_max, n_bins):
-    temps, frames = [], []
+def run(sim, step_fn, n_steps, every, o_idx, r_max, n_bins):
+    temps, pes, frames = [], [], []
     counts = np.zeros(n_bins)
-    nf = 0
     for _ in range(n_steps // every):
         step_fn(every)
-        obs = sim.observables()
+        obs = sim.observables(pe=True)
         temps.append(obs["temperature"])
+        pes.append(obs["pe_short"] + obs["pe_long"] + obs["pe_bonded"])
         x, _ = sim.state()
         frames.append(x[o_idx].copy())
         counts += sim.rdf_counts(0, 0, r_max, n_bins)
-        nf += 1
-    return np.array(temps), np.array(frames), counts, nf
+    return np.array(temps), np.array(pes), np.array(frames), counts
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n-mol", type=int, default=1000)
-    ap.add_argument("--ps", type=float, default=40.0, help="production length per integrator")
+    ap.add_argument("--n-mol", type=int, default=4096)
+    ap.add_argument("--ps", type=float, default=40.0, help="production length per run")
     ap.add_argument("--equil-ps", type=float, default=10.0)
     ap.add_argument("--eps0", type=float, default=0.1)
     ap.add_argument("--rings", type=int, default=12)
     ap.add_argument("--skin", type=float, default=0.5)
-    ap.add_argument("--every", type=int, default=50, help="steps between samples")
-    ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--every", type=int, default=50, help="fs between samples")
+    ap.add_argument("--blocks", type=int, default=4, help="blocks for the diffusion error")
+    ap.add_argument("--runs", default="baoab,jump,jump:fp32=1")
     ap.add_argument("--seed", type=int, default=7)
     a = ap.parse_args()
 
@@ -57,32 +63,55 @@ def main():
     eq.close()
     sysm.pos, sysm.vel = x, v
 
-    n_steps = int(round(a.ps / 0.001))
     res = {}
-    for name in ("baoab", "jump"):
-        pa = S.water_params(eps0_per_kcal=a.eps0, jumps=(name == "jump"), seed=a.seed + 1)
-        pa.precision = a.precision
-        sim = jumpmd.Sim(sysm, split, pa)
+    for spec in a.runs.split(","):
+        name, _, opts = spec.partition(":")
+        kv = dict(x.split("=") for x in opts.split(";") if x)
+        jumps = name == "jump"
+        dt_fs = float(kv.get("dt", 1.0))
+        eps0 = float(kv.get("eps0", a.eps0))
+        rs = float(kv.get("rs", 5.0))
+        sp = S.water_split(r_s=rs, r_c=10.0, w=1.0, skin=a.skin, n_rings=a.rings)
+        pa = S.water_params(dt=dt_fs * 1e-3, eps0_per_kcal=eps0, jumps=jumps, seed=a.seed + 1)
+        pa.precision = int(kv.get("fp32", 0))
+        sim = jumpmd.Sim(sysm, sp, pa)
+        n_steps = int(round(a.ps / (dt_fs * 1e-3)))
+        every = max(1, int(round(a.every / dt_fs)))
         t0 = time.perf_counter()
-        T, frames, counts, nf = run(sim, sim.step_jump if name == "jump" else sim.step_baoab,
-                                    n_steps, a.every, n_o, o_idx, r_max, n_bins)
+        T, pe, frames, counts = run(sim, sim.step_jump if jumps else sim.step_baoab, n_steps, every,
+                                    o_idx, r_max, n_bins)
         el = time.perf_counter() - t0
-        r, g = analysis.rdf_from_counts(counts, n_o, n_o, L ** 3, r_max, True, nf)
-        D, dD = analysis.block_diffusion(frames, a.every * 0.001, n_blocks=4)
-        res[name] = dict(T=float(T.mean()), T_err=float(T.std(ddof=1) / np.sqrt(len(T))), g=g, D=D, D_err=dD,
-                         seconds=el)
+        nf = len(T)
+        _, g = analysis.rdf_from_counts(counts, n_o, n_o, L ** 3, r_max, True, nf)
+        D, dD = analysis.block_diffusion(frames, every * dt_fs * 1e-3, n_blocks=a.blocks)
+        key = spec if spec not in ("jump:fp32=1",) else "jump_fp32"
+        res[key] = dict(T=float(T.mean()), T_err=float(T.std(ddof=1) / np.sqrt(nf)),
+                        pe=float(pe.mean()), pe_err=float(pe.std(ddof=1) / np.sqrt(nf)),
+                        g=g, D=D, D_err=dD, seconds=el, ms_per_step=1e3 * el / n_steps)
         sim.close()
-    b, j = res["baoab"], res["jump"]
-    out = {
-        "workload": f"water_{a.n_mol}mol", "ps_each": a.ps, "eps0_per_kcal_mol_A": a.eps0,
-        "rings": a.rings, "skin": a.skin, "precision": "fp32_mixed" if a.precision else "fp64",
-        "T_baoab": b["T"], "T_jump": j["T"], "T_rel_diff": (j["T"] - b["T"]) / b["T"],
-        "rdf_oo_l2": analysis.rdf_l2(b["g"], j["g"]),
-        "D_baoab_A2_per_ps": b["D"], "D_baoab_err": b["D_err"],
-        "D_jump_A2_per_ps": j["D"], "D_jump_err": j["D_err"], "D_rel_diff": (j["D"] - b["D"]) / b["D"],
-        "targets": {"T": 0.01, "rdf_l2": 1e-2, "D": 0.05},
-        "seconds": {"baoab": b["seconds"], "jump": j["seconds"]},
-    }
+        print(f"[accuracy] {spec}: T {res[key]['T']:.2f} K, PE {res[key]['pe']:.1f}, D {D:.4f} +- {dD:.4f}, "
+              f"{el:.1f} s", flush=True)
+
+    ref = res.get("baoab")
+    out = {"workload": f"water_{a.n_mol}mol", "ps_each": a.ps, "eps0_per_kcal_mol_A": a.eps0,
+           "rings": a.rings, "skin": a.skin, "sample_every_fs": a.every,
+           "targets": {"T_rel": 0.01, "rdf_l2": 1e-2, "D_rel": 0.05}}
+    for name, r in res.items():
+        row = {"T_K": r["T"], "T_err": r["T_err"], "pe_kJ_mol": r["pe"], "pe_err": r["pe_err"],
+               "D_A2_per_ps": r["D"], "D_err": r["D_err"], "seconds": r["seconds"],
+               "ms_per_step_with_sampling": r["ms_per_step"]}
+        if ref is not None and name != "baoab":
+            row["vs_baoab"] = {"T_rel": (r["T"] - ref["T"]) / ref["T"],
+                               "pe_rel": (r["pe"] - ref["pe"]) / abs(ref["pe"]),
+                               "rdf_l2": analysis.rdf_l2(ref["g"], r["g"]),
+                               "D_rel": (r["D"] - ref["D"]) / ref["D"]}
+        out[name] = row
+    if "jump" in res and "jump_fp32" in res:
+        j, f = res["jump"], res["jump_fp32"]
+        out["jump_fp32"]["vs_jump_fp64"] = {"T_rel": (f["T"] - j["T"]) / j["T"],
+                                            "pe_rel": (f["pe"] - j["pe"]) / abs(j["pe"]),
+                                            "rdf_l2": analysis.rdf_l2(j["g"], f["g"]),
+                                            "D_rel": (f["D"] - j["D"]) / j["D"]}
     print(json.dumps(out), flush=True)
 
 

@@ -663,6 +663,10 @@ __global__ __launch_bounds__(1024) void k_cell_scan(MDView V, int slot, int forc
                                                     int count) {
   __shared__ int part[1024];
   const int T = blockDim.x, t = threadIdx.x, nc = V.ncell_total;
+  // nothing to do on steps where no replica rebuilds
+  int any = 0;
+  for (int r = t; r < V.nrep && !any; r += T) any = rebuild_now(V, slot, forced, autob, thr2, r) ? 1 : 0;
+  if (!__syncthreads_or(any)) return;
   const int per = (nc + T - 1) / T;
   const int b = min(nc, t * per), e = min(nc, b + per);
   int s = 0;
@@ -745,6 +749,10 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
   const int cl = V.atom_cell[i] - coff;
   const int cx = cl % nd[0], cy = (cl / nd[0]) % nd[1], cz = cl / (nd[0] * nd[1]);
   const int x0 = V.xptr ? V.xptr[i] : 0, x1 = V.xptr ? V.xptr[i + 1] : 0;
+  // up to four excluded partners in registers; more are looked up in memory
+  int ex[4] = {-1, -1, -1, -1};
+  for (int e = x0; e < x1 && e < x0 + 4; ++e) ex[e - x0] = V.xj[e];
+  const bool ex_more = x1 - x0 > 4;
   const double rs_out = V.rs + V.skin;
   const int capk = (want & 4) ? V.cap_c : V.cap_f;
   int nk = 0, nsr = 0, over = 0;
@@ -752,61 +760,84 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
   stencil_range(cz, nd[2], zlo, zhi);
   stencil_range(cy, nd[1], ylo, yhi);
   stencil_range(cx, nd[0], xlo, xhi);
-  for (int zz = zlo; zz <= zhi; ++zz)
-    for (int yy = ylo; yy <= yhi; ++yy) {
-      const int ccz = (zz + nd[2]) % nd[2], ccy = (yy + nd[1]) % nd[1];
-      const int row0 = coff + (ccz * nd[1] + ccy) * nd[0];
-      // x-run as at most two contiguous spans of cells
-      int sp_lo[2], sp_hi[2], nsp = 1;
-      if (xlo >= 0 && xhi < nd[0]) { sp_lo[0] = xlo; sp_hi[0] = xhi; }
-      else if (xlo < 0) { sp_lo[0] = xlo + nd[0]; sp_hi[0] = nd[0] - 1; sp_lo[1] = 0; sp_hi[1] = xhi; nsp = 2; }
-      else { sp_lo[0] = xlo; sp_hi[0] = nd[0] - 1; sp_lo[1] = 0; sp_hi[1] = xhi - nd[0]; nsp = 2; }
-      for (int t = 0; t < nsp; ++t) {
-        const int beg = V.cell_start[row0 + sp_lo[t]], end = V.cell_start[row0 + sp_hi[t] + 1];
-        for (int p = beg; p < end; p += 64) {
-          const int q = p + lane;
-          int j = -1;
-          bool ok = q < end;
-          double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
-          if (ok) {
-            j = V.cell_atoms[q];
-            xj = V.xcell[q];
-            ok = (j != i);
-            for (int e = x0; ok && e < x1; ++e) ok = (V.xj[e] != j);
-          }
-          bool bs = false, bk = false;
-          unsigned key = 0;
-          if (ok) {
-            const double ddx = min_img(xi.x - xj.x, L[0], iL[0]);
-            const double ddy = min_img(xi.y - xj.y, L[1], iL[1]);
-            const double ddz = min_img(xi.z - xj.z, L[2], iL[2]);
-            const double rr = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-            bs = (want & 1) && rr < rs_out;
-            if (want & 4) {
-              bk = rr >= V.rin && rr < V.rout;
-              int ring = (int)floor((rr - V.rin) / V.rw);
-              ring = ring < 0 ? 0 : (ring > V.nr - 1 ? V.nr - 1 : ring);
-              key = ((unsigned)(V.type[j] * V.nr + ring) << 24) | (unsigned)j;
-            } else if (want & 2) {
-              bk = rr < V.rout;
-              key = (unsigned)j;
-            }
-          }
-          const unsigned long long mk = __ballot(bk), ms = __ballot(bs);
-          const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-          if (bk) {
-            const int pos = nk + __popcll(mk & below);
-            if (pos < pc) kc[pos] = key; else over = 1;
-          }
-          if (bs) {
-            const int pos = nsr + __popcll(ms & below);
-            if (pos < ps) ks[pos] = (unsigned)j; else over = 1;
-          }
-          nk += __popcll(mk);
-          nsr += __popcll(ms);
+  // The stencil as at most 50 contiguous spans of the cell-ordered arrays:
+  // (z, y) rows of x-runs, each run split in two where it wraps. Lane t
+  // resolves span t; an inclusive scan gives every candidate a flat index,
+  // so the whole stencil streams through 64-wide chunks with independent loads.
+  const int ny = yhi - ylo + 1, nz = zhi - zlo + 1;
+  int sb = 0, sl = 0;
+  if (lane < 2 * ny * nz) {
+    const int part = lane & 1, yz = lane >> 1;
+    const int zz = zlo + yz / ny, yy = ylo + yz % ny;
+    const int ccz = (zz + nd[2]) % nd[2], ccy = (yy + nd[1]) % nd[1];
+    const int row0 = coff + (ccz * nd[1] + ccy) * nd[0];
+    int lo = -1, hi = -2;
+    if (xlo >= 0 && xhi < nd[0]) { if (part == 0) { lo = xlo; hi = xhi; } }
+    else if (xlo < 0) { if (part == 0) { lo = xlo + nd[0]; hi = nd[0] - 1; } else { lo = 0; hi = xhi; } }
+    else { if (part == 0) { lo = xlo; hi = nd[0] - 1; } else { lo = 0; hi = xhi - nd[0]; } }
+    if (hi >= lo) { sb = V.cell_start[row0 + lo]; sl = V.cell_start[row0 + hi + 1] - sb; }
+  }
+  int incl = sl;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  __shared__ int s_beg[64], s_pre[65];
+  s_beg[lane] = sb;
+  s_pre[lane + 1] = incl;
+  if (lane == 0) s_pre[0] = 0;
+  __syncthreads();
+  const int total = s_pre[64];
+  int span = 0;   // per lane: the span holding its current flat index (indices only grow)
+  auto examine = [&](int f, int &j, double4 &xj) -> bool {
+    if (f >= total) return false;
+    while (s_pre[span + 1] <= f) ++span;
+    const int q = s_beg[span] + (f - s_pre[span]);
+    j = V.cell_atoms[q];
+    xj = V.xcell[q];
+    return true;
+  };
+  for (int base = 0; base < total; base += 64) {
+    int j = -1;
+    double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
+    bool ok = examine(base + lane, j, xj);
+    ok = ok && j != i && j != ex[0] && j != ex[1] && j != ex[2] && j != ex[3];
+    if (ok && ex_more)
+      for (int e = x0 + 4; ok && e < x1; ++e) ok = (V.xj[e] != j);
+    bool bs = false, bk = false;
+    unsigned key = 0;
+    if (ok) {
+      const double ddx = min_img(xi.x - xj.x, L[0], iL[0]);
+      const double ddy = min_img(xi.y - xj.y, L[1], iL[1]);
+      const double ddz = min_img(xi.z - xj.z, L[2], iL[2]);
+      const double rr = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+      bs = (want & 1) && rr < rs_out;
+      if (want & 4) {
+        bk = rr >= V.rin && rr < V.rout;
+        if (bk) {
+          int ring = (int)floor((rr - V.rin) / V.rw);
+          ring = ring < 0 ? 0 : (ring > V.nr - 1 ? V.nr - 1 : ring);
+          key = ((unsigned)(V.type[j] * V.nr + ring) << 24) | (unsigned)j;
         }
+      } else if (want & 2) {
+        bk = rr < V.rout;
+        key = (unsigned)j;
       }
     }
+    const unsigned long long mk = __ballot(bk), ms = __ballot(bs);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (bk) {
+      const int pos = nk + __popcll(mk & below);
+      if (pos < pc) kc[pos] = key; else over = 1;
+    }
+    if (bs) {
+      const int pos = nsr + __popcll(ms & below);
+      if (pos < ps) ks[pos] = (unsigned)j; else over = 1;
+    }
+    nk += __popcll(mk);
+    nsr += __popcll(ms);
+  }
   if (nk > capk || nsr > V.cap_s) over = 1;
   if (__any(over) && lane == 0) atomicMax(&V.ctl->overflow_rows, max(nk, nsr));
   const int nkk = min(nk, min(capk, pc)), nss = min(nsr, min(V.cap_s, ps));
