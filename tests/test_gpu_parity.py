@@ -194,3 +194,26 @@ def test_graph_replay_matches_oracle(jm, scheme):
         _compare_stats(g, o)
         np.testing.assert_array_equal(g.events(), o.events())
     assert g.observables()["n_rebuilds"] == o.n_rebuilds
+
+
+@pytest.mark.parametrize("precision_scheme", ["jump", "baoab"])
+def test_water_4096_full_size_in_bench_configuration(jm, precision_scheme):
+    """The benchmark's 4096-molecule water box at full size, in the launch
+    configuration the benchmark times (automatic chain lanes, HIP-graph
+    replays of 2 steps), 4 steps: exact jump events and 1e-9 state against
+    the oracle (brute-force O(N^2) pair sums, ~0.6 s per step)."""
+    sy = S.water_box(4096, seed=1, jitter=0.05)
+    sp = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=0.5, n_rings=12)
+    pa = S.water_params(eps0_per_kcal=0.1, jumps=(precision_scheme == "jump"))
+    pa.log_events = 1
+    pa.graph_steps = 2
+    g, o = _pair(jm, sy, sp, pa)
+    if precision_scheme == "jump":
+        g.step_jump(4)
+        o.step_jump(4)
+        _compare_stats(g, o)
+        np.testing.assert_array_equal(g.events(), o.events())
+    else:
+        g.step_baoab(4)
+        o.step_baoab(4)
+    _compare_state(g, o)
