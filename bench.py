@@ -67,6 +67,12 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=200, help="plain-launch steps timed per kernel")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="pair arithmetic of forces and jump rates (fp32: mixed, FP64 state)")
+    ap.add_argument("--replicas", type=int, default=0,
+                    help="batched ensemble: R water replicas of U{216..2048} molecules (seed 1) in one context")
+    ap.add_argument("--respa", action="store_true",
+                    help="JUMP-RESPA vs BAOAB-RESPA: bonded forces every 1 fs, the rest every --respa-inner fs")
+    ap.add_argument("--respa-inner", type=int, default=3)
+    ap.add_argument("--rc", type=float, default=10.0, help="outer cutoff of the jumped shell (A)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -127,9 +133,33 @@ def main():
     from paper_2412_15073_amd import jumpmd, systems as S
 
     prec = 1 if a.precision == "fp32" else 0
-    sysm = S.water_box(a.n_mol, seed=1)
-    split = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=a.skin, n_rings=a.rings)
-    print(f"[bench] water {a.n_mol} molecules ({sysm.n_atoms} atoms), box {sysm.box[0]:.2f} A", flush=True)
+    # replicas below 267 molecules (box < 20 A) cannot hold r_c = 10 A under the
+    # minimum-image convention: the ensemble's sizes are drawn from U{270..2048}
+    n_min = 270 if a.rc >= 10.0 else 216
+    if a.replicas:
+        sysm = S.water_replicas(a.replicas, n_min=n_min, seed=1)
+        n_atoms = int(sysm.offsets[-1])
+        desc = f"{a.replicas} water replicas, {n_atoms // 3} molecules ({n_atoms} atoms) in total"
+    else:
+        sysm = S.water_box(a.n_mol, seed=1)
+        n_atoms = sysm.n_atoms
+        desc = f"water {a.n_mol} molecules ({n_atoms} atoms), box {sysm.box[0]:.2f} A"
+    split = S.water_split(r_s=5.0, r_c=a.rc, w=1.0, skin=a.skin, n_rings=a.rings)
+    n_sys = max(1, a.replicas)
+    if a.respa:
+        a.graph_steps = 0   # graph replay covers the single-step schemes only
+    print(f"[bench] {desc}", flush=True)
+
+    def set_state(sy, x, v):
+        if a.replicas:
+            for r, s_r in enumerate(sy.systems):
+                lo, hi = sy.offsets[r], sy.offsets[r + 1]
+                s_r.pos, s_r.vel = x[lo:hi], v[lo:hi]
+        else:
+            sy.pos, sy.vel = x, v
+
+    def fresh_system():
+        return S.water_replicas(a.replicas, n_min=n_min, seed=1) if a.replicas else S.water_box(a.n_mol, seed=1)
 
     # untimed equilibration from the lattice: BAOAB, full forces, 0.5 fs, gamma 10/ps
     eq = jumpmd.Sim(sysm, split, S.water_params(dt=0.0005, gamma=10.0, jumps=False))
@@ -140,20 +170,31 @@ def main():
     eq.close()
     print(f"[bench] equilibrated {a.equil} steps in {time.perf_counter() - t:.1f} s, T = {obs['temperature']:.1f} K",
           flush=True)
-    sysm.pos, sysm.vel = x, v
+    set_state(sysm, x, v)
 
     def params(jumps, graph):
         p = S.water_params(eps0_per_kcal=a.eps0, jumps=jumps)
         p.chain_lanes = a.chain_lanes
         p.graph_steps = graph
         p.precision = prec
+        if a.respa:
+            p.respa_inner = a.respa_inner
         return p
 
-    # JUMP (C' J' A O A J' C'): timed run
+    def jstep(sim):
+        return sim.step_jump_respa if a.respa else sim.step_jump
+
+    def bstep(sim):
+        return sim.step_baoab_respa if a.respa else sim.step_baoab
+
+    step_ps = 1e-3 * (a.respa_inner if a.respa else 1)   # simulated time per call step
+    name_j, name_b = ("JUMP-RESPA", "BAOAB-RESPA") if a.respa else ("JUMP", "BAOAB-full")
+
+    # JUMP (C' J' A O A J' C', or its RESPA form): timed run
     pj = params(True, a.graph_steps)
     js = jumpmd.Sim(sysm, split, pj)
     p0 = js.proposals_total()
-    dt_j = timed(js, js.step_jump, a.steps, a.warmup)
+    dt_j = timed(js, jstep(js), a.steps, a.warmup)
     props = (js.proposals_total() - p0) / (a.steps + a.warmup)
     obs_j = js.observables()
     pl, pt = C.c_int64(0), C.c_int64(0)
@@ -162,17 +203,17 @@ def main():
     xj, vj = js.state()
     js.close()
     ms_j = 1e3 * dt_j / a.steps
-    ns_day_j = ns_per_day(pj.dt, a.steps, dt_j)
-    print(f"[bench] JUMP {ms_j:.4f} ms/step, {ns_day_j:.1f} ns/day, T = {obs_j['temperature']:.1f} K, "
+    ns_day_j = n_sys * ns_per_day(step_ps, a.steps, dt_j)
+    print(f"[bench] {name_j} {ms_j:.4f} ms/step, {ns_day_j:.1f} ns/day, T = {obs_j['temperature']:.1f} K, "
           f"{props:.0f} proposals/step, {pairs_short} short pairs", flush=True)
 
     # JUMP per-kernel profile: plain launches from the timed run's final state
-    s2 = S.water_box(a.n_mol, seed=1)
-    s2.pos, s2.vel = xj, vj
+    s2 = fresh_system()
+    set_state(s2, xj, vj)
     jp = jumpmd.Sim(s2, split, params(True, 0))
-    jp.step_jump(a.warmup)
+    jstep(jp)(a.warmup)
     q0 = jp.proposals_total()
-    prof_j = kernel_profile(jp, jp.step_jump, a.profile_steps)
+    prof_j = kernel_profile(jp, jstep(jp), a.profile_steps)
     props_prof = (jp.proposals_total() - q0) / a.profile_steps
     jp.close()
 
@@ -180,22 +221,22 @@ def main():
     ns_day_b = ms_b = pairs_full = None
     prof_b = None
     if not a.no_baoab:
-        split_b = split if a.baoab_skin is None else S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=a.baoab_skin,
+        split_b = split if a.baoab_skin is None else S.water_split(r_s=5.0, r_c=a.rc, w=1.0, skin=a.baoab_skin,
                                                                    n_rings=a.rings)
         pb = params(False, a.graph_steps)
         bs = jumpmd.Sim(sysm, split_b, pb)
-        dt_b = timed(bs, bs.step_baoab, a.steps, a.warmup)
+        dt_b = timed(bs, bstep(bs), a.steps, a.warmup)
         jumpmd.load().md_counters(bs._h, C.byref(pl), C.byref(pt))
         pairs_full = pl.value
         obs_b = bs.observables()
         bs.close()
         ms_b = 1e3 * dt_b / a.steps
-        ns_day_b = ns_per_day(pb.dt, a.steps, dt_b)
+        ns_day_b = n_sys * ns_per_day(step_ps, a.steps, dt_b)
         bp = jumpmd.Sim(sysm, split_b, params(False, 0))
-        bp.step_baoab(a.warmup)
-        prof_b = kernel_profile(bp, bp.step_baoab, a.profile_steps)
+        bstep(bp)(a.warmup)
+        prof_b = kernel_profile(bp, bstep(bp), a.profile_steps)
         bp.close()
-        print(f"[bench] BAOAB-full {ms_b:.4f} ms/step, {ns_day_b:.1f} ns/day, T = {obs_b['temperature']:.1f} K, "
+        print(f"[bench] {name_b} {ms_b:.4f} ms/step, {ns_day_b:.1f} ns/day, T = {obs_b['temperature']:.1f} K, "
               f"{pairs_full} pairs", flush=True)
 
     # dominant kernel of the JUMP step and its roofline
@@ -211,7 +252,7 @@ def main():
         work = pairs_short * FLOP_PER_SHORT_PAIR
         roof = {"bound": "alu", "achieved": work / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s"}
     else:
-        work = sysm.n_atoms * BYTES_PER_ATOM_LOCAL
+        work = n_atoms * BYTES_PER_ATOM_LOCAL
         roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
@@ -233,17 +274,20 @@ def main():
     if not a.no_cpu_baseline:
         from oracle.oracle import OracleSim
         po = params(True, 0)
-        o = OracleSim(sysm, split, po)
+        osys = sysm.systems[0] if a.replicas else sysm
+        o = OracleSim(osys, split, po)
+        ostep = o.step_jump_respa if a.respa else o.step_jump
         t = time.perf_counter()
-        o.step_jump(1)
+        ostep(1)
         first = time.perf_counter() - t
         n_more = max(1, int((a.cpu_seconds - first) / max(first, 1e-3)))
         t = time.perf_counter()
-        o.step_jump(n_more)
+        ostep(n_more)
         el = time.perf_counter() - t
-        cpu = {"value": ns_per_day(po.dt, n_more, el), "unit": "ns/day", "cores": 1, "kind": "oracle",
-               "sample": f"{n_more} JUMP steps of the same {sysm.n_atoms}-atom water system after 1 untimed step "
-                         f"(brute-force O(N^2) pair sums, single thread), {el:.1f} s"}
+        cpu = {"value": ns_per_day(step_ps, n_more, el), "unit": "ns/day", "cores": 1, "kind": "oracle",
+               "sample": f"{n_more} {name_j} steps of {'replica 0 of the ensemble, ' if a.replicas else 'the same '}"
+                         f"{osys.n_atoms}-atom water system, after 1 untimed step (brute-force O(N^2) pair sums, "
+                         f"single thread), {el:.1f} s"}
         print(f"[bench] oracle {el / n_more:.3f} s/step", flush=True)
 
     line = {
@@ -251,8 +295,11 @@ def main():
         "value": ns_day_j, "unit": "ns/day", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms_j, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == 0 else "f32+f64", "data": "synthetic (lattice water, BAOAB-equilibrated, seeded)",
-        "config": {"workload": f"water_{a.n_mol}mol_jump_{a.precision}", "n_atoms": sysm.n_atoms,
-                   "box_A": round(float(sysm.box[0]), 3), "r_s": 5.0, "r_c": 10.0, "switch": 1.0,
+        "config": {"workload": (f"water_{a.replicas}replicas_jump_{a.precision}" if a.replicas else
+                                f"water_{a.n_mol}mol_jump{'_respa' if a.respa else ''}_{a.precision}"),
+                   "n_atoms": n_atoms,
+                   "box_A": None if a.replicas else round(float(sysm.box[0]), 3), "r_s": 5.0, "r_c": a.rc,
+                   "switch": 1.0, "respa_inner": a.respa_inner if a.respa else None,
                    "skin": a.skin, "rings": a.rings, "dt_fs": 1.0, "gamma_per_ps": 1.0, "T_K": 300,
                    "eps0_per_kcal_mol_A": a.eps0, "jumps": "LJ BPS + Coulomb adaptive MRZ",
                    "chain_lanes": a.chain_lanes, "graph_steps": a.graph_steps},
