@@ -251,19 +251,24 @@ struct SegL {
   }
 };
 
-// One Z iteration (Sec. 2.4 regimes) from the block's four uniforms.
+// One Z iteration (Sec. 2.4 regimes) from the block's four uniforms. Both
+// logarithms and the square root are shared by the regimes (lanes of a wave
+// often sit in different regimes), and the acceptance tests of the first two
+// regimes are taken in log space or without division.
 __device__ __forceinline__ bool z_iteration(double eta, double u0, double u1, double u2, double u3, double &z) {
+  const double l0 = log(u0), l1 = log(u1);
+  const double rad = sqrt(-2.0 * (eta > 0.0 ? l1 : l0));
   if (eta > 0.0) {
-    const double p_ray = 1.0 / (1.0 + eta * 2.5066282746310002);
-    const double rad = sqrt(-2.0 * log(u1));
-    const double y = (u0 < p_ray) ? rad : rad * cospi(2.0 * u2);
+    // Rayleigh part with probability 1 / (1 + eta sqrt(2 pi)), else Gaussian
+    const double y = (u0 * (1.0 + eta * 2.5066282746310002) < 1.0) ? rad : rad * cospi(2.0 * u2);
     z = eta + y;
     return (y >= 0.0) || (z > 0.0 && u3 * eta <= z);
-  } else if (eta >= -1.0) {
-    z = sqrt(-2.0 * log(u0));
-    return u1 <= exp(eta * z);
   }
-  z = -(log(u0) + log(u1)) / (-eta);
+  if (eta >= -1.0) {
+    z = rad;
+    return l1 <= eta * z;
+  }
+  z = (l0 + l1) / eta;
   return u2 <= exp(-0.5 * z * z);
 }
 
@@ -330,8 +335,8 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   const double k_lam = adaptive ? sqrt(beta / me) / eps0 : sqrt(beta) / (eps0 * sqrt(me));
   const double k_coef = adaptive ? 2.0 * eps0 / sbm : 2.0 * eps0 / ((1.0 + eps0 * eps0) * sbm);
   int n_counted = 0, n_viol = 0;   // lane-local, reduced over the group at the end
-  int64_t w0 = 0, computed = 0;
-  int ws = 0, cs = 0;   // ring slots of w0 and of computed
+  int w0 = 0, computed = 0;   // proposal indices (below MD_MAX_PROPOSALS)
+  int ws = 0, cs = 0;         // ring slots of w0 and of computed
   double vex = vx, vey = vy, vez = vz, te = 0.0, base = 0.0;
   double tau = h, bBv = 0.0, Wb = 0.0, Lam = 0.0, iLam = 0.0;
   bool live = true, epoch = true;
@@ -370,8 +375,8 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     // wave-synchronous refill: every atom with room for G more proposals
     if (__any(live && computed - w0 < G)) {
       wave_lds_sync();   // reads of the slots being replaced are complete
-      if (live && (int)(computed - w0) <= M - G) {
-        const int64_t k = computed + r;
+      if (live && computed - w0 <= M - G) {
+        const int k = computed + r;
         const int sl = ring_add(cs, r, M);
         Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
         double ell, Fx, Fy, Fz;
@@ -460,7 +465,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     const double F2s = norm2_nc(Fxs, Fys, Fzs);
     const int2 jj = ((const int2 *)(ring + RF_J * M))[fs];
     const int j = fos ? jj.y : jj.x;
-    const int64_t kstar = w0 + first;
+    const int kstar = w0 + first;
     if (isC) {
       const double etas = __shfl(eta, first, G);
       const double tks = __shfl(tk, first, G);
