@@ -109,6 +109,7 @@ struct MDView {
   const double *c12, *c6, *ljshift;     // [nt*nt]
   const double *ell_lj, *ell_cu;        // [nt*nt*nr] bound per unit (Coulomb: per unit charge product)
   const double *qmax;                   // [nt]
+  const double *qseg;                   // [nt*nr] qmax of the type of segment sg
   // exclusions and bonded incidence
   const int *xptr, *xj;
   const int *bptr, *bterm;              // per atom: term code (idx << 1 | is_angle)

@@ -17,11 +17,12 @@
 #include "md_internal.h"
 
 // ------------------------------------------------------------- helpers
+// bound of segment sg = (type b, ring k) for an atom of type a; the table
+// index (a * nt + b) * nr + k equals a * S + sg
 __device__ __forceinline__ double seg_ell(const MDView &V, int a, int sg, int coul, double absq) {
-  int b = sg / V.nr, k = sg - b * V.nr;
-  int idx = (a * V.nt + b) * V.nr + k;
+  const int idx = a * V.S + sg;
   if (!coul) return V.ell_lj[idx];
-  return (absq * V.qmax[b]) * V.ell_cu[idx];
+  return (absq * V.qseg[sg]) * V.ell_cu[idx];
 }
 
 // long-range gradient in FP32 (mixed-precision path): displacement in FP64,
@@ -715,7 +716,8 @@ __device__ __forceinline__ void bitonic_sort_lds(unsigned *keys, int m) {
   for (int k = 2; k <= m; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int t = lane; t < (m >> 1); t += 64) {
-        const int a = 2 * j * (t / j) + (t % j);
+        // j is a power of two: a = 2j floor(t / j) + t mod j
+        const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
         const int b = a + j;
         const bool up = (a & k) == 0;
         const unsigned ka = keys[a], kb = keys[b];
