@@ -570,6 +570,8 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   A(d_aijk, std::max(1, 3 * s->n_angles)); A(d_ak, std::max(1, s->n_angles)); A(d_at0, std::max(1, s->n_angles));
   A(V.cell_count, V.ncell_total); A(V.cell_start, V.ncell_total + 1); A(V.cell_atoms, n);
   A(V.cell_tmp, V.ncell_total); A(V.rep_maxd2, 2 * nrep); A(V.xcell, n);
+  int *d_chain_perm;
+  A(d_chain_perm, n);
   int *d_cell_rep;
   A(d_cell_rep, V.ncell_total);
   A(V.atom_cell, n); A(V.atom_slot, n);
@@ -625,6 +627,31 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   up(d_ak, s->angle_k, sizeof(double) * s->n_angles);
   up(d_at0, s->angle_t0, sizeof(double) * s->n_angles);
   up(c->d_rep_off, c->rep_off.data(), sizeof(int) * (nrep + 1));
+  // Chain order: atoms grouped by type into type-pure waves (atoms of one type
+  // have similar jump counts, so a wave is not held up by its busiest type),
+  // and the waves of the types interleaved in proportion so that every part
+  // of the device gets a similar mix. Results do not depend on the order.
+  std::vector<int> chain_perm;
+  {
+    const int apw = 64 / V.chain_lanes;
+    std::vector<std::vector<int>> by_type(nt);
+    for (int i = 0; i < n; ++i) by_type[s->type[i]].push_back(i);
+    struct Chunk { double key; int t, beg, len; };
+    std::vector<Chunk> full, part;
+    for (int t = 0; t < nt; ++t) {
+      const int m = (int)by_type[t].size(), nw = (m + apw - 1) / apw;
+      for (int w = 0; w < nw; ++w) {
+        Chunk ch{(w + 0.5) / nw, t, w * apw, std::min(apw, m - w * apw)};
+        (ch.len == apw ? full : part).push_back(ch);
+      }
+    }
+    std::stable_sort(full.begin(), full.end(), [](const Chunk &a, const Chunk &b) { return a.key < b.key; });
+    chain_perm.reserve(n);
+    for (auto *v : {&full, &part})
+      for (const Chunk &ch : *v)
+        for (int q = 0; q < ch.len; ++q) chain_perm.push_back(by_type[ch.t][ch.beg + q]);
+    up(d_chain_perm, chain_perm.data(), sizeof(int) * n);
+  }
   {
     std::vector<int> cr(V.ncell_total);
     for (int r = 0; r < nrep; ++r)
@@ -653,7 +680,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.bond_ij = d_bij; V.bond_k = d_bk; V.bond_r0 = d_br0;
   V.angle_ijk = d_aijk; V.angle_k = d_ak; V.angle_t0 = d_at0;
   V.rep_cell_off = d_coff; V.rep_cdim = d_cdim;
-  V.cell_rep = d_cell_rep; V.rep_off = c->d_rep_off;
+  V.cell_rep = d_cell_rep; V.rep_off = c->d_rep_off; V.chain_perm = d_chain_perm;
   c->cur = 0;
   c->fkind = -1;
   c->fb_valid = false;

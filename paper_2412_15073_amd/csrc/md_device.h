@@ -139,6 +139,7 @@ struct MDView {
   double beta, kT, eps0;
   int jlj, jc, log_events, precision;
   int chain_lanes;       // lanes cooperating on one atom's jump chain (1, 2, 4, 8, 16)
+  const int *chain_perm; // [n] atom handled by chain group g (type-pure waves, interleaved)
   uint64_t seed;
 };
 

@@ -90,10 +90,9 @@ __device__ __forceinline__ double long_grad(const MDView &V, double4 xi, double4
   return long_grad_d(V, xi, xj, a, b, coul, L, iL, Fx, Fy, Fz);
 }
 
-template <int PREC>
-__device__ __forceinline__ double theta_p(double eta) {
-  return PREC == MD_FP32_MIXED ? (double)theta_fn_f((float)eta) : theta_fn(eta);
-}
+// Theta in the chain's real type (float in the mixed path)
+__device__ __forceinline__ double theta_r(double eta) { return theta_fn(eta); }
+__device__ __forceinline__ float theta_r(float eta) { return theta_fn_f(eta); }
 
 struct AtomStats { long long nprop, nacc, nviol; uint64_t hash; };
 
@@ -130,12 +129,21 @@ __device__ __forceinline__ void log_jump_hash_only(const MDView &V, AtomStats &s
 // the half step) is found with a group minimum. Every decision is the one the
 // one-proposal-at-a-time chain takes.
 
-// ring fields (doubles, field-major: field f of slot s at f*M + s); RF_J holds
-// the two candidates (by-bound, uniform) as a pair of ints
-enum { RF_E = 0, RF_U1, RF_U3, RF_BX, RF_BY, RF_BZ, RF_BL, RF_FX, RF_FY, RF_FZ, RF_FL, RF_J,
+// ring fields (chain real type R, field-major: field f of slot s at f*M + s),
+// followed by the candidate pairs (by-bound, uniform) as M int2
+enum { RF_E = 0, RF_U1, RF_U3, RF_BX, RF_BY, RF_BZ, RF_BL, RF_FX, RF_FY, RF_FZ, RF_FL,
        RF_Z0, RF_Z1, RF_Z2, RF_Z3, RF_N };
 
+// real type of the chain arithmetic: FP64, or float in the mixed path
+template <int PREC> struct ChainReal { using T = double; };
+template <> struct ChainReal<MD_FP32_MIXED> { using T = float; };
+
 __host__ __device__ constexpr int ring_slots(int G) { return G == 1 ? 3 : (5 * G) / 2; }
+
+// LDS bytes of one atom's ring: R fields (8-byte aligned), then the int2 pairs
+__host__ __device__ constexpr int ring_bytes(int G, int rsize) {
+  return ((RF_N * ring_slots(G) * rsize + 7) / 8) * 8 + 8 * ring_slots(G);
+}
 
 // LDS doubles per atom of the segment table for S segments: cumulative
 // weights (S), cumulative counts (S, plus one spare: last usable segment)
@@ -171,7 +179,8 @@ __device__ __forceinline__ int group_sum(int x) {
 }
 
 // |F|^2 evaluated the same way wherever it is needed
-__device__ __forceinline__ double norm2_nc(double x, double y, double z) {
+template <typename R>
+__device__ __forceinline__ R norm2_nc(R x, R y, R z) {
 #pragma clang fp contract(off)
   return x * x + y * y + z * z;
 }
@@ -256,43 +265,44 @@ struct SegL {
 // logarithms and the square root are shared by the regimes (lanes of a wave
 // often sit in different regimes), and the acceptance tests of the first two
 // regimes are taken in log space or without division.
-__device__ __forceinline__ bool z_iteration(double eta, double u0, double u1, double u2, double u3, double &z) {
-  const double l0 = log(u0), l1 = log(u1);
-  const double rad = sqrt(-2.0 * (eta > 0.0 ? l1 : l0));
-  if (eta > 0.0) {
+template <typename R>
+__device__ __forceinline__ bool z_iteration(R eta, R u0, R u1, R u2, R u3, R &z) {
+  const R l0 = log(u0), l1 = log(u1);
+  const R rad = sqrt(R(-2) * (eta > R(0) ? l1 : l0));
+  if (eta > R(0)) {
     // Rayleigh part with probability 1 / (1 + eta sqrt(2 pi)), else Gaussian
-    const double y = (u0 * (1.0 + eta * 2.5066282746310002) < 1.0) ? rad : rad * cospi(2.0 * u2);
+    const R y = (u0 * (R(1) + eta * R(2.5066282746310002)) < R(1)) ? rad : rad * cospi(R(2) * u2);
     z = eta + y;
-    return (y >= 0.0) || (z > 0.0 && u3 * eta <= z);
+    return (y >= R(0)) || (z > R(0) && u3 * eta <= z);
   }
-  if (eta >= -1.0) {
+  if (eta >= R(-1)) {
     z = rad;
     return l1 <= eta * z;
   }
   z = (l0 + l1) / eta;
-  return u2 <= exp(-0.5 * z * z);
+  return u2 <= exp(R(-0.5) * z * z);
 }
 
 // Z iterations it0, it0 + 1, ... with G of them in parallel: lane r tries
 // it = base + r; the first accepted iteration (in order) wins.
-template <int G>
-__device__ __forceinline__ double zsample_grp(double eta, uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
-                                           int phase, int64_t k, int r, int it0, int &overflow) {
+template <int G, typename R>
+__device__ __forceinline__ R zsample_grp(R eta, uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
+                                         int phase, int64_t k, int r, int it0, int &overflow) {
   overflow = 0;
   for (int base = it0; base < MD_ZS_MAXIT; base += G) {
     const int it = base + r;
-    double z = 0.0;
+    R z = R(0);
     bool ok = false;
     if (it < MD_ZS_MAXIT) {
       const uint64_t tag = (uint64_t)(uint32_t)phase | ((uint64_t)(it + 1) << 24);
       Uni4 u = draw4(seed, rep, step, atom, tag, k);
-      ok = z_iteration(eta, u.u[0], u.u[1], u.u[2], u.u[3], z);
+      ok = z_iteration<R>((R)eta, (R)u.u[0], (R)u.u[1], (R)u.u[2], (R)u.u[3], z);
     }
     const int first = group_min<G>(ok ? r : G);
     if (first < G) return __shfl(z, first, G);
   }
   overflow = 1;
-  return 0.5 * (eta + sqrt(eta * eta + 4.0));
+  return R(0.5) * (eta + sqrt(eta * eta + R(4)));
 }
 
 __device__ __forceinline__ int ring_add(int s, int d, int M) {
@@ -314,35 +324,39 @@ __device__ __forceinline__ int ring_add(int s, int d, int M) {
 // first Z iteration.
 template <int G, int PREC>
 __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
-                         double &vx, double &vy, double &vz, double me, double ax, double ay, double az,
-                         const MDOp &op, AtomStats &st, const double *L, const double *iL, double *ring,
-                         SegL &T) {
+                         double &vx, double &vy, double &vz, double me, double ax_d, double ay_d, double az_d,
+                         const MDOp &op, AtomStats &st, const double *L, const double *iL,
+                         typename ChainReal<PREC>::T *ring, int2 *jring, SegL &T) {
+  using R = typename ChainReal<PREC>::T;
   constexpr int M = ring_slots(G);
   const bool isC = op.kind == OP_C;
   const int a = V.type[i];
   T.build(V, i, a, isC ? 1 : 0, isC ? fabs(xi.w) : 0.0, r);
   const int *row = V.crow + (size_t)i * V.cap_c;
   const bool adaptive = isC && (V.jc == MD_JUMP_MRZ_ADAPTIVE);
-  const double beta = V.beta, eps0 = V.eps0;
-  const double f = sqrt(beta / (2.0 * MD_PI * me)) / eps0;
-  const double aa = ax * ax + ay * ay + az * az;
+  const R beta = (R)V.beta, eps0 = (R)V.eps0, mr = (R)me;
+  const R f = sqrt(beta / (R(2) * R(MD_PI) * mr)) / eps0;
+  const R ax = (R)ax_d, ay = (R)ay_d, az = (R)az_d;
+  const R aa = ax * ax + ay * ay + az * az;
   const uint64_t rep = (uint64_t)V.rep[i];
   const int64_t li = V.loc[i];
-  const double h = op.h;
-  const double vn = sqrt(vx * vx + vy * vy + vz * vz);   // J: |v| for the whole op
+  const R h = (R)op.h;
+  const R vn = sqrt((R)vx * (R)vx + (R)vy * (R)vy + (R)vz * (R)vz);   // J: |v| for the whole op
   // per-op constants of the MRZ rate and kernel (Sec. 2.4)
-  const double sbm = sqrt(beta * me);
-  const double k_eta = eps0 * sbm;
-  const double k_lam = adaptive ? sqrt(beta / me) / eps0 : sqrt(beta) / (eps0 * sqrt(me));
-  const double k_coef = adaptive ? 2.0 * eps0 / sbm : 2.0 * eps0 / ((1.0 + eps0 * eps0) * sbm);
+  const R sbm = sqrt(beta * mr);
+  const R k_eta = eps0 * sbm;
+  const R k_lam = adaptive ? sqrt(beta / mr) / eps0 : sqrt(beta) / (eps0 * sqrt(mr));
+  const R k_coef = adaptive ? R(2) * eps0 / sbm : R(2) * eps0 / ((R(1) + eps0 * eps0) * sbm);
+  const R W = (R)T.W, nfr = (R)T.nf;
   int n_counted = 0, n_viol = 0;   // lane-local, reduced over the group at the end
   int w0 = 0, computed = 0;   // proposal indices (below MD_MAX_PROPOSALS)
   int ws = 0, cs = 0;         // ring slots of w0 and of computed
-  double vex = vx, vey = vy, vez = vz, te = 0.0, base = 0.0;
-  double tau = h, bBv = 0.0, Wb = 0.0, Lam = 0.0, iLam = 0.0;
+  double vex = vx, vey = vy, vez = vz;   // velocity at the last event (FP64 state)
+  R te = R(0), base = R(0);
+  R tau = h, bBv = R(0), Wb = R(0), Lam = R(0), iLam = R(0);
   bool live = true, epoch = true;
   auto finish = [&]() {
-    if (isC) { vx = vex + tau * ax; vy = vey + tau * ay; vz = vez + tau * az; }
+    if (isC) { vx = vex + (double)tau * ax_d; vy = vey + (double)tau * ay_d; vz = vez + (double)tau * az_d; }
     live = false;
   };
   while (__any(live)) {
@@ -350,22 +364,23 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       epoch = false;
       if (isC) {
         tau = h - te;
-        const double vv = vex * vex + vey * vey + vez * vez;
-        const double va = vex * ax + vey * ay + vez * az;
-        const double Bv = sqrt(vv + tau * tau * aa + 2.0 * tau * (va > 0.0 ? va : 0.0));
+        const R vxr = (R)vex, vyr = (R)vey, vzr = (R)vez;
+        const R vv = vxr * vxr + vyr * vyr + vzr * vzr;
+        const R va = vxr * ax + vyr * ay + vzr * az;
+        const R Bv = sqrt(vv + tau * tau * aa + R(2) * tau * (va > R(0) ? va : R(0)));
         bBv = beta * Bv;
-        Wb = bBv * T.W;
-        Lam = adaptive ? Wb + f * T.nf : (bBv + f) * T.W;
-        iLam = 1.0 / Lam;
-        base = 0.0;
-        if (!(Lam > 0.0) || !isfinite(Lam)) {
-          if (!(Lam <= 0.0) && r == 0) atomicAdd(&V.ctl->nonfinite, 1ull);
+        Wb = bBv * W;
+        Lam = adaptive ? Wb + f * nfr : (bBv + f) * W;
+        iLam = R(1) / Lam;
+        base = R(0);
+        if (!(Lam > R(0)) || !isfinite(Lam)) {
+          if (!(Lam <= R(0)) && r == 0) atomicAdd(&V.ctl->nonfinite, 1ull);
           finish();
         }
       } else {
-        Lam = V.beta * vn * T.W;
-        iLam = 1.0 / Lam;
-        if (!(Lam > 0.0)) finish();
+        Lam = beta * vn * W;
+        iLam = R(1) / Lam;
+        if (!(Lam > R(0))) finish();
         else if (!isfinite(Lam)) { if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull); finish(); }
       }
     }
@@ -383,24 +398,23 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         double ell, Fx, Fy, Fz;
         const int jb = row[T.pick_by_bound(V, u.u[2], ell)];
         long_grad<PREC>(V, xi, X[jb], a, V.type[jb], isC ? 1 : 0, L, iL, Fx, Fy, Fz);
-        ring[RF_E * M + sl] = -log(u.u[0]);
-        ring[RF_U1 * M + sl] = u.u[1];
-        ring[RF_U3 * M + sl] = u.u[3];
-        ring[RF_BX * M + sl] = Fx; ring[RF_BY * M + sl] = Fy; ring[RF_BZ * M + sl] = Fz;
-        ring[RF_BL * M + sl] = ell;
+        ring[RF_E * M + sl] = (R)(-log(u.u[0]));
+        ring[RF_U1 * M + sl] = (R)u.u[1];
+        ring[RF_U3 * M + sl] = (R)u.u[3];
+        ring[RF_BX * M + sl] = (R)Fx; ring[RF_BY * M + sl] = (R)Fy; ring[RF_BZ * M + sl] = (R)Fz;
+        ring[RF_BL * M + sl] = (R)ell;
         int jf = jb;
         if (adaptive) {
           jf = row[T.pick_uniform(V, u.u[2], ell)];
           long_grad<PREC>(V, xi, X[jf], a, V.type[jf], 1, L, iL, Fx, Fy, Fz);
-          ring[RF_FX * M + sl] = Fx; ring[RF_FY * M + sl] = Fy; ring[RF_FZ * M + sl] = Fz;
-          ring[RF_FL * M + sl] = ell;
+          ring[RF_FX * M + sl] = (R)Fx; ring[RF_FY * M + sl] = (R)Fy; ring[RF_FZ * M + sl] = (R)Fz;
+          ring[RF_FL * M + sl] = (R)ell;
         }
-        int2 *jp = (int2 *)(ring + RF_J * M);
-        jp[sl] = make_int2(jb, jf);
+        jring[sl] = make_int2(jb, jf);
         if (isC) {
           Uni4 z = draw4(V.seed, rep, op.step, li, (uint64_t)(uint32_t)op.phase | (1ull << 24), k);
-          ring[RF_Z0 * M + sl] = z.u[0]; ring[RF_Z1 * M + sl] = z.u[1];
-          ring[RF_Z2 * M + sl] = z.u[2]; ring[RF_Z3 * M + sl] = z.u[3];
+          ring[RF_Z0 * M + sl] = (R)z.u[0]; ring[RF_Z1 * M + sl] = (R)z.u[1];
+          ring[RF_Z2 * M + sl] = (R)z.u[2]; ring[RF_Z3 * M + sl] = (R)z.u[3];
         }
         computed += G;
         cs = ring_add(cs, G, M);
@@ -410,7 +424,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     if (!live) continue;
     // window [w0, w0 + G): lane r holds proposal w0 + r
     const int sl = ring_add(ws, r, M);
-    double s = base, tot = base;
+    R s = base, tot = base;
 #pragma unroll
     for (int m = 0; m < G; ++m) {
       tot += ring[RF_E * M + ring_add(ws, m, M)];
@@ -418,38 +432,38 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     }
     const bool use_f = adaptive && !(ring[RF_U1 * M + sl] * Lam < Wb);
     const int fo = use_f ? (RF_FX - RF_BX) * M : 0;
-    const double Fx = ring[fo + RF_BX * M + sl], Fy = ring[fo + RF_BY * M + sl], Fz = ring[fo + RF_BZ * M + sl];
-    const double ell = ring[fo + RF_BL * M + sl];
-    const double F2 = norm2_nc(Fx, Fy, Fz);
-    const double u3 = ring[RF_U3 * M + sl];
+    const R Fx = ring[fo + RF_BX * M + sl], Fy = ring[fo + RF_BY * M + sl], Fz = ring[fo + RF_BZ * M + sl];
+    const R ell = ring[fo + RF_BL * M + sl];
+    const R F2 = norm2_nc(Fx, Fy, Fz);
+    const R u3 = ring[RF_U3 * M + sl];
     // acceptance u3 <= lam / c and bound violation lam > c, tested without dividing
     bool out, acc, viol;
-    double eta = 0.0, tk = 0.0;
+    R eta = R(0), tk = R(0);
     if (isC) {
       tk = te + s * iLam;
       out = tk > h;
-      const double dtk = tk - te;
-      const double vkx = vex + dtk * ax, vky = vey + dtk * ay, vkz = vez + dtk * az;
-      const double c = adaptive ? bBv * ell + f : ell * (bBv + f);
-      double lam = 0.0;
-      const double vF = vkx * Fx + vky * Fy + vkz * Fz;
-      if (!out && F2 > 0.0) {
+      const R dtk = tk - te;
+      const R vkx = (R)vex + dtk * ax, vky = (R)vey + dtk * ay, vkz = (R)vez + dtk * az;
+      const R c = adaptive ? bBv * ell + f : ell * (bBv + f);
+      R lam = R(0);
+      const R vF = vkx * Fx + vky * Fy + vkz * Fz;
+      if (!out && F2 > R(0)) {
         if (adaptive) {
           eta = k_eta * vF;
-          lam = k_lam * theta_p<PREC>(eta);
+          lam = k_lam * theta_r(eta);
         } else {
-          const double Fn = sqrt(F2);
+          const R Fn = sqrt(F2);
           eta = k_eta * vF / Fn;
-          lam = k_lam * Fn * theta_p<PREC>(eta);
+          lam = k_lam * Fn * theta_r(eta);
         }
       }
-      acc = !out && lam > 0.0 && u3 * c <= lam;
+      acc = !out && lam > R(0) && u3 * c <= lam;
       viol = lam > c;
     } else {
       out = s * iLam > h;
-      const double vF = vx * Fx + vy * Fy + vz * Fz;
-      const double c = vn * ell;
-      acc = !out && vF > 0.0 && u3 * c <= vF;
+      const R vF = (R)vx * Fx + (R)vy * Fy + (R)vz * Fz;
+      const R c = vn * ell;
+      acc = !out && vF > R(0) && u3 * c <= vF;
       viol = vF > c;
     }
     const int first = group_min<G>((out || acc) ? r : G);
@@ -462,32 +476,39 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     // the accepted proposal's gradient, read by every lane of the group
     const int fs = ring_add(ws, first, M);
     const int fos = __shfl(fo, first, G);
-    const double Fxs = ring[fos + RF_BX * M + fs], Fys = ring[fos + RF_BY * M + fs], Fzs = ring[fos + RF_BZ * M + fs];
-    const double F2s = norm2_nc(Fxs, Fys, Fzs);
-    const int2 jj = ((const int2 *)(ring + RF_J * M))[fs];
+    const R Fxs = ring[fos + RF_BX * M + fs], Fys = ring[fos + RF_BY * M + fs], Fzs = ring[fos + RF_BZ * M + fs];
+    const R F2s = norm2_nc(Fxs, Fys, Fzs);
+    const int2 jj = jring[fs];
     const int j = fos ? jj.y : jj.x;
     const int kstar = w0 + first;
     if (isC) {
-      const double etas = __shfl(eta, first, G);
-      const double tks = __shfl(tk, first, G);
-      double Z;
-      if (!z_iteration(etas, ring[RF_Z0 * M + fs], ring[RF_Z1 * M + fs], ring[RF_Z2 * M + fs],
-                       ring[RF_Z3 * M + fs], Z)) {
+      const R etas = __shfl(eta, first, G);
+      const R tks = __shfl(tk, first, G);
+      R Z;
+      if (!z_iteration<R>(etas, ring[RF_Z0 * M + fs], ring[RF_Z1 * M + fs], ring[RF_Z2 * M + fs],
+                          ring[RF_Z3 * M + fs], Z)) {
         int ovf;
-        Z = zsample_grp<G>(etas, V.seed, rep, op.step, li, op.phase, kstar, r, 1, ovf);
+        Z = zsample_grp<G, R>(etas, V.seed, rep, op.step, li, op.phase, kstar, r, 1, ovf);
         if (ovf && r == 0) atomicAdd(&V.ctl->n_zs_overflow, 1ull);
       }
-      const double coef = adaptive ? k_coef * Z / (1.0 + eps0 * eps0 * F2s) : k_coef * Z / sqrt(F2s);
-      const double dts = tks - te;
-      vex = vex + dts * ax - coef * Fxs;
-      vey = vey + dts * ay - coef * Fys;
-      vez = vez + dts * az - coef * Fzs;
+      const R coef = adaptive ? k_coef * Z / (R(1) + eps0 * eps0 * F2s) : k_coef * Z / sqrt(F2s);
+      const R dts = tks - te;
+      if (PREC == MD_FP32_MIXED) {
+        // float kick, FP64 accumulation of the velocity
+        vex += (double)(dts * ax - coef * Fxs);
+        vey += (double)(dts * ay - coef * Fys);
+        vez += (double)(dts * az - coef * Fzs);
+      } else {
+        vex = vex + dts * ax - coef * Fxs;
+        vey = vey + dts * ay - coef * Fys;
+        vez = vez + dts * az - coef * Fzs;
+      }
       te = tks;
       epoch = true;   // new bound from (t_e, v_e)
     } else {
-      const double vFs = vx * Fxs + vy * Fys + vz * Fzs;
-      const double c = 2.0 * vFs / F2s;
-      vx -= c * Fxs; vy -= c * Fys; vz -= c * Fzs;
+      const R vFs = (R)vx * Fxs + (R)vy * Fys + (R)vz * Fzs;
+      const R c = R(2) * vFs / F2s;
+      vx -= (double)(c * Fxs); vy -= (double)(c * Fys); vz -= (double)(c * Fzs);
       base = __shfl(s, first, G);
     }
     if (r == first) log_jump(V, st, op.step, op.phase, i, j, kstar);
@@ -511,8 +532,9 @@ __global__ __launch_bounds__(64, MD_CHAIN_WAVES_PER_SIMD) void k_chain(MDView V,
                                                                       const double4 *__restrict__ X) {
   extern __shared__ double lds_chain[];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = gid / G, r = gid - (gid / G) * G;
-  if (i >= V.n) return;
+  const int grp = gid / G, r = gid - (gid / G) * G;
+  if (grp >= V.n) return;
+  const int i = V.chain_perm[grp];
   const double4 xi = X[i];
   const double4 vv = V.v[i];
   double vx = vv.x, vy = vv.y, vz = vv.z;
@@ -523,12 +545,16 @@ __global__ __launch_bounds__(64, MD_CHAIN_WAVES_PER_SIMD) void k_chain(MDView V,
   AtomStats st;
   st.nprop = V.nprop[i]; st.nacc = V.nacc[i]; st.nviol = V.nviol[i]; st.hash = V.hash[i];
   const double4 fn = V.fnb[i], fb = V.fb[i];
+  using R = typename ChainReal<PREC>::T;
   constexpr int M = ring_slots(G);
   constexpr int APB = 64 / G;
+  constexpr int RB = ring_bytes(G, (int)sizeof(R));
   const int ab = (int)threadIdx.x / G;
-  double *ring = lds_chain + ab * (RF_N * M);
+  char *base_b = (char *)lds_chain + ab * RB;
+  R *ring = (R *)base_b;
+  int2 *jring = (int2 *)(base_b + ((RF_N * M * (int)sizeof(R) + 7) / 8) * 8);
   SegL T;
-  T.attach(lds_chain + APB * (RF_N * M) + ab * seg_lds_doubles(V.S), V.S);
+  T.attach((double *)((char *)lds_chain + APB * RB) + ab * seg_lds_doubles(V.S), V.S);
   const int64_t sbase = P.dev_step ? (int64_t)V.ctl->step_base : 0;
   for (int o = 0; o < P.nops; ++o) {
     MDOp op = P.ops[o];
@@ -545,7 +571,7 @@ __global__ __launch_bounds__(64, MD_CHAIN_WAVES_PER_SIMD) void k_chain(MDView V,
         ay = (fn.y + (op.flags == 0 ? fb.y : 0.0)) / me;
         az = (fn.z + (op.flags == 0 ? fb.z : 0.0)) / me;
       }
-      chain_op<G, PREC>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, T);
+      chain_op<G, PREC>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, jring, T);
     }
   }
   if (r == 0) {
@@ -1170,9 +1196,9 @@ __global__ void k_set_step(MDCtl *ctl, long long step) { ctl->step_base = step; 
 // ------------------------------------------------------------- launchers
 #define CHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
-// LDS bytes of one k_chain block with G lanes per atom
-static size_t chain_lds_bytes(int G, int S) {
-  return sizeof(double) * (size_t)(64 / G) * (size_t)(RF_N * ring_slots(G) + seg_lds_doubles(S));
+// LDS bytes of one k_chain block with G lanes per atom (rsize: bytes of the chain real type)
+static size_t chain_lds_bytes(int G, int S, int rsize = 8) {
+  return (size_t)(64 / G) * ((size_t)ring_bytes(G, rsize) + sizeof(double) * (size_t)seg_lds_doubles(S));
 }
 size_t chain_lds_bytes_host(int G, int S) { return chain_lds_bytes(G, S); }
 
@@ -1196,7 +1222,7 @@ static void launch_chain_p(const MDView &V, const MDProg &P, const double4 *X, h
   const int G = V.chain_lanes;
   const long long threads = (long long)V.n * G;
   const int nb = (int)((threads + 63) / 64);   // wave-sized blocks spread the few long waves over all CUs
-  const size_t lds = chain_lds_bytes(G, V.S);
+  const size_t lds = chain_lds_bytes(G, V.S, PREC == MD_FP32_MIXED ? 4 : 8);
   switch (G) {
     case 1: hipLaunchKernelGGL((k_chain<1, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
     case 2: hipLaunchKernelGGL((k_chain<2, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
