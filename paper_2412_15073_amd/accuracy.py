@@ -36,6 +36,15 @@ def run(sim, step_fn, n_steps, every, o_idx, r_max, n_bins):
     return np.array(temps), np.array(pes), np.array(frames), counts
 
 
+def block_err(x, n_blocks):
+    """Standard error of the mean from n_blocks consecutive block means
+    (correlated samples: the naive error understates it)."""
+    x = np.asarray(x, float)
+    m = len(x) // n_blocks
+    b = x[: m * n_blocks].reshape(n_blocks, m).mean(1)
+    return float(b.std(ddof=1) / np.sqrt(n_blocks))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n-mol", type=int, default=4096)
@@ -45,7 +54,7 @@ def main():
     ap.add_argument("--rings", type=int, default=12)
     ap.add_argument("--skin", type=float, default=0.5)
     ap.add_argument("--every", type=int, default=50, help="fs between samples")
-    ap.add_argument("--blocks", type=int, default=4, help="blocks for the diffusion error")
+    ap.add_argument("--blocks", type=int, default=4, help="blocks for the error estimates")
     ap.add_argument("--runs", default="baoab,jump,jump:fp32=1")
     ap.add_argument("--seed", type=int, default=7)
     a = ap.parse_args()
@@ -85,8 +94,8 @@ def main():
         _, g = analysis.rdf_from_counts(counts, n_o, n_o, L ** 3, r_max, True, nf)
         D, dD = analysis.block_diffusion(frames, every * dt_fs * 1e-3, n_blocks=a.blocks)
         key = spec if spec not in ("jump:fp32=1",) else "jump_fp32"
-        res[key] = dict(T=float(T.mean()), T_err=float(T.std(ddof=1) / np.sqrt(nf)),
-                        pe=float(pe.mean()), pe_err=float(pe.std(ddof=1) / np.sqrt(nf)),
+        res[key] = dict(T=float(T.mean()), T_err=block_err(T, a.blocks),
+                        pe=float(pe.mean()), pe_err=block_err(pe, a.blocks),
                         g=g, D=D, D_err=dD, seconds=el, ms_per_step=1e3 * el / n_steps)
         sim.close()
         print(f"[accuracy] {spec}: T {res[key]['T']:.2f} K, PE {res[key]['pe']:.1f}, D {D:.4f} +- {dD:.4f}, "
