@@ -58,7 +58,8 @@ def parse():
     ap.add_argument("--eps0", type=float, default=0.1, help="adaptive eps0 in (kcal/mol/A)^-1")
     ap.add_argument("--rings", type=int, default=12)
     ap.add_argument("--skin", type=float, default=0.5)
-    ap.add_argument("--baoab-skin", type=float, default=None, help="list skin of the BAOAB comparator (default: --skin)")
+    ap.add_argument("--baoab-skin", type=float, default=1.0,
+                    help="list skin of the BAOAB comparator (its fastest; JUMP's fastest is 0.5)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-baoab", action="store_true")
@@ -221,8 +222,7 @@ def main():
     ns_day_b = ms_b = pairs_full = None
     prof_b = None
     if not a.no_baoab:
-        split_b = split if a.baoab_skin is None else S.water_split(r_s=5.0, r_c=a.rc, w=1.0, skin=a.baoab_skin,
-                                                                   n_rings=a.rings)
+        split_b = S.water_split(r_s=5.0, r_c=a.rc, w=1.0, skin=a.baoab_skin, n_rings=a.rings)
         pb = params(False, a.graph_steps)
         bs = jumpmd.Sim(sysm, split_b, pb)
         dt_b = timed(bs, bstep(bs), a.steps, a.warmup)
@@ -300,7 +300,7 @@ def main():
                    "n_atoms": n_atoms,
                    "box_A": None if a.replicas else round(float(sysm.box[0]), 3), "r_s": 5.0, "r_c": a.rc,
                    "switch": 1.0, "respa_inner": a.respa_inner if a.respa else None,
-                   "skin": a.skin, "rings": a.rings, "dt_fs": 1.0, "gamma_per_ps": 1.0, "T_K": 300,
+                   "skin": a.skin, "baoab_skin": a.baoab_skin, "rings": a.rings, "dt_fs": 1.0, "gamma_per_ps": 1.0, "T_K": 300,
                    "eps0_per_kcal_mol_A": a.eps0, "jumps": "LJ BPS + Coulomb adaptive MRZ",
                    "chain_lanes": a.chain_lanes, "graph_steps": a.graph_steps},
         "baoab_full_ns_per_day": ns_day_b, "baoab_full_ms_per_step": ms_b,

@@ -754,6 +754,79 @@ __device__ __forceinline__ void bitonic_sort_lds(unsigned *keys, int m) {
   }
 }
 
+// Bitonic sort of m = 64 K keys held in registers (element e = K lane + q):
+// compare-exchange partners e ^ j are in the same lane for j < K (register
+// swaps) and in lane ^ (j / K) otherwise (one cross-lane exchange per key).
+// Ascending where (e & k) == 0 for the merge of size k.
+template <int K>
+__device__ __forceinline__ void bitonic_sort_regs(unsigned (&v)[K], int m) {
+  const int lane = threadIdx.x;
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j >= K; j >>= 1) {
+      const int lm = j / K;
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const int e = lane * K + q;
+        const unsigned o = (unsigned)__shfl_xor((int)v[q], lm, 64);
+        const bool keep_min = ((e & j) == 0) == ((e & k) == 0);
+        v[q] = keep_min ? min(v[q], o) : max(v[q], o);
+      }
+    }
+#pragma unroll
+    for (int jj = K / 2; jj > 0; jj >>= 1) {
+      if (jj < k) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          if ((q & jj) == 0) {
+            const int e = lane * K + q;
+            const bool up = (e & k) == 0;
+            const unsigned a = v[q], b = v[q + jj];
+            if ((a > b) == up) { v[q] = b; v[q + jj] = a; }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Sort keys[0, n) of LDS in place (padding to a power of two m >= 64 with
+// 0xffffffff); registers for m <= 1024, the LDS network above that.
+__device__ __forceinline__ void sort_keys(unsigned *keys, int n) {
+  const int lane = threadIdx.x;
+  int m = 64;
+  while (m < n) m <<= 1;
+  if (m > 1024) {
+    for (int e = n + lane; e < m; e += 64) keys[e] = 0xffffffffu;
+    __syncthreads();
+    bitonic_sort_lds(keys, m);
+    return;
+  }
+  auto run = [&](auto kk) {
+    constexpr int K = decltype(kk)::value;
+    unsigned v[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const int e = lane * K + q;
+      v[q] = e < n ? keys[e] : 0xffffffffu;
+    }
+    bitonic_sort_regs<K>(v, m);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const int e = lane * K + q;
+      if (e < n) keys[e] = v[q];
+    }
+    __syncthreads();
+  };
+  switch (m) {
+    case 64: run(std::integral_constant<int, 1>()); break;
+    case 128: run(std::integral_constant<int, 2>()); break;
+    case 256: run(std::integral_constant<int, 4>()); break;
+    case 512: run(std::integral_constant<int, 8>()); break;
+    default: run(std::integral_constant<int, 16>()); break;
+  }
+}
+
 // cells of one stencil dimension: offsets -2..2 when the replica has at least
 // 5 cells along it (cell edge >= (r_c + skin)/2), otherwise every cell once
 __device__ __forceinline__ void stencil_range(int c, int nd, int &lo, int &hi) {
@@ -875,11 +948,8 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
   if (__any(over) && lane == 0) atomicMax(&V.ctl->overflow_rows, max(nk, nsr));
   const int nkk = min(nk, min(capk, pc)), nss = min(nsr, min(V.cap_s, ps));
   if (want & 6) {
-    int m = 1;
-    while (m < nkk) m <<= 1;
-    for (int e = nkk + lane; e < m; e += 64) kc[e] = 0xffffffffu;
     __syncthreads();
-    bitonic_sort_lds(kc, m);
+    sort_keys(kc, nkk);
     int *row = (want & 4) ? V.crow + (size_t)i * V.cap_c : V.frow + (size_t)i * V.cap_f;
     for (int e = lane; e < nkk; e += 64) row[e] = (int)(kc[e] & 0xffffffu);
     if (lane == 0) { if (want & 4) V.ccnt[i] = nkk; else V.fcnt[i] = nkk; }
@@ -893,11 +963,8 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
     }
   }
   if (want & 1) {
-    int m = 1;
-    while (m < nss) m <<= 1;
-    for (int e = nss + lane; e < m; e += 64) ks[e] = 0xffffffffu;
     __syncthreads();
-    bitonic_sort_lds(ks, m);
+    sort_keys(ks, nss);
     int *row = V.srow + (size_t)i * V.cap_s;
     for (int e = lane; e < nss; e += 64) row[e] = (int)ks[e];
     if (lane == 0) V.scnt[i] = nss;
