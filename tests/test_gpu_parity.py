@@ -71,6 +71,31 @@ def test_candidate_rows(jm, case):
         np.testing.assert_array_equal(sg, o.seg_start(i), err_msg=f"segments {i}")
 
 
+def test_long_candidate_rows_and_jumps(jm):
+    """Rows longer than 1024 candidates (r_c = 14 A water: ~1300 per atom),
+    which the row builder sorts with its LDS network instead of registers;
+    then 3 JUMP steps with exact events."""
+    sy = S.water_box(1000, seed=3, jitter=0.05)
+    sp = S.water_split(r_s=5.0, r_c=14.0, w=1.0, skin=0.5, n_rings=8)
+    pa = S.water_params()
+    pa.log_events = 1
+    g, o = _pair(jm, sy, sp, pa)
+    o.build_lists()
+    S_ = o.n_segments
+    lens = []
+    for i in range(0, sy.n_atoms, 7):
+        jg, sg = g.cand_row(i, S_)
+        lens.append(len(jg))
+        np.testing.assert_array_equal(jg, o.cand_row(i), err_msg=f"row {i}")
+        np.testing.assert_array_equal(sg, o.seg_start(i), err_msg=f"segments {i}")
+    assert max(lens) > 1024
+    g.step_jump(3)
+    o.step_jump(3)
+    _compare_state(g, o)
+    _compare_stats(g, o)
+    np.testing.assert_array_equal(g.events(), o.events())
+
+
 def test_jump_lj_trajectory(jm):
     sy, sp = lj_small()
     pa = S.lj_params()
