@@ -14,7 +14,7 @@ launches with --graph-steps 0). Per-kernel durations for the roofline come
 from a second, profiled run of plain launches in the same process (HIP events
 on the library's stream).
 
-Prints ONE JSON line. --gpus N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line. --gpus N > 1 exits: the benchmark runs on one GPU.
 """
 import argparse
 import json
@@ -122,7 +122,7 @@ def ns_per_day(dt_ps, steps, seconds):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on exactly one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch

@@ -1,9 +1,11 @@
 """GPU (HIP) path against the CPU FP64 oracle on the same seeded inputs.
 
 Integer outputs (candidate rows, jump counts, accepted (step, phase, i, j)
-events, per-atom hashes) must match exactly; FP64 state within 1e-9 relative
-(different summation order, libm vs device math; see the FP64 tolerance
-derivation in the design doc).
+events, per-atom fingerprints) must match exactly; FP64 state within 1e-9
+relative. Both sides evaluate the same formulas in FP64 and differ only in
+summation order and libm vs device math (a few ulp per operation); over 100
+steps of chaotic dynamics that grows by at most ~1e3, far below 1e-9, while
+any formula error shows at 1e-6 or more.
 """
 import numpy as np
 import pytest
