@@ -424,29 +424,83 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.beta = 1.0 / p->kT; V.kT = p->kT; V.eps0 = p->eps;
   V.jlj = p->jump_lj; V.jc = p->jump_coul; V.log_events = p->log_events; V.precision = p->precision;
   V.seed = p->seed;
+  // Jump-chain layout. G (lanes per atom), automatic: the most lanes per atom
+  // whose waves still fit the device in one round (resident blocks per CU
+  // from the kernel's registers and LDS).
+  std::vector<int> chain_perm;
   {
-    // automatic: the most lanes per atom whose waves still fit the device in
-    // one round (resident blocks per CU from the kernel's registers and LDS)
+    const int prec = p->precision, S = V.nt * V.nr;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     int g = p->chain_lanes;
-    const int S = V.nt * V.nr;
     if (g <= 0) {
-      int dev = 0, ncu = 256;
-      if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
       g = 1;
       for (int cand = 2; cand <= 16; cand *= 2) {
-        if (chain_lds_bytes_host(cand, S) > 65536) continue;
-        int bpc = chain_blocks_per_cu(cand, S);
+        if (chain_lds_bytes_host(cand, S, prec) > 65536) continue;
+        int bpc = chain_blocks_per_cu(cand, S, prec, 1);
         if (bpc <= 0) bpc = 4;
         if ((long long)n * cand / 64 <= (long long)ncu * bpc) g = cand;
       }
-      if (chain_lds_bytes_host(g, S) > 65536) g = 2;
+      if (chain_lds_bytes_host(g, S, prec) > 65536) g = 2;
     }
     if (g != 1 && g != 2 && g != 4 && g != 8 && g != 16) { delete c; return fail(nullptr, MD_ERR_ARG, "chain_lanes must be 0, 1, 2, 4, 8 or 16"); }
-    if (chain_lds_bytes_host(g, S) > 65536) {
+    if (chain_lds_bytes_host(g, S, prec) > 65536) {
       delete c;
-      return fail(nullptr, MD_ERR_ARG, "chain_lanes too small for this many segments (jump-chain LDS above 64 KiB per block)");
+      return fail(nullptr, MD_ERR_ARG, "chain_lanes too small for this many segments (jump-chain LDS above 64 KiB per wave)");
     }
     V.chain_lanes = g;
+
+    // Waves are type-pure (atoms of one type have similar jump counts, so a
+    // wave is not held up by its busiest type), heaviest type first: jump
+    // rates scale as 1/sqrt(mass) (MRZ rate sqrt(beta/m), BPS rate through
+    // |v|), so light atoms run the longest chains.
+    const int apw = 64 / g;
+    std::vector<std::vector<int>> by_type(nt);
+    std::vector<double> cost(nt, 0.0);
+    for (int i = 0; i < n; ++i) {
+      by_type[s->type[i]].push_back(i);
+      cost[s->type[i]] += 1.0 / std::sqrt(s->mass[i]);
+    }
+    for (int t = 0; t < nt; ++t)
+      if (!by_type[t].empty()) cost[t] /= (double)by_type[t].size();
+    std::vector<int> torder(nt);
+    for (int t = 0; t < nt; ++t) torder[t] = t;
+    std::stable_sort(torder.begin(), torder.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    struct Chunk { int t, beg, len; };
+    std::vector<Chunk> waves, part;
+    for (int t : torder) {
+      const int m = (int)by_type[t].size();
+      for (int w = 0; w * apw < m; ++w) {
+        Chunk ch{t, w * apw, std::min(apw, m - w * apw)};
+        (ch.len == apw ? waves : part).push_back(ch);
+      }
+    }
+    waves.insert(waves.end(), part.begin(), part.end());
+    const long long nw = (long long)waves.size();
+
+    // Block size. When every wave is resident at once, waves are packed into
+    // blocks of bw (one block per CU) and the q-th wave of the order above
+    // goes to block q mod nb, slot q / nb: a block's waves spread over the
+    // CU's SIMDs, so the heaviest waves of the device land on distinct
+    // SIMDs instead of sharing one. With more waves than resident slots,
+    // one-wave blocks let the dispatcher balance the load.
+    int bw = 1;
+    const int bpc1 = chain_blocks_per_cu(g, S, prec, 1);
+    if (bpc1 > 1 && nw <= (long long)ncu * bpc1)
+      bw = (int)std::min<long long>({(long long)bpc1, (long long)MD_CHAIN_MAX_BLOCK_WAVES, (nw + ncu - 1) / ncu});
+#ifdef MD_CHAIN_BLOCK_WAVES
+    bw = std::max(1, std::min(MD_CHAIN_BLOCK_WAVES, MD_CHAIN_MAX_BLOCK_WAVES));
+#endif
+    while (bw > 1 && chain_blocks_per_cu(g, S, prec, bw) < 1) --bw;
+    const long long nb = (nw + bw - 1) / bw;
+    chain_perm.assign((size_t)(nb * bw * apw), -1);
+    for (long long q = 0; q < nw; ++q) {
+      const long long wv = (q % nb) * bw + q / nb;
+      const Chunk &ch = waves[(size_t)q];
+      for (int k = 0; k < ch.len; ++k) chain_perm[(size_t)(wv * apw + k)] = by_type[ch.t][ch.beg + k];
+    }
+    V.chain_block_waves = bw;
+    V.chain_groups = (int)chain_perm.size();
   }
 
   // --- host tables
@@ -571,7 +625,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   A(V.cell_count, V.ncell_total); A(V.cell_start, V.ncell_total + 1); A(V.cell_atoms, n);
   A(V.cell_tmp, V.ncell_total); A(V.rep_maxd2, 2 * nrep); A(V.xcell, n);
   int *d_chain_perm;
-  A(d_chain_perm, n);
+  A(d_chain_perm, chain_perm.size());
   int *d_cell_rep;
   A(d_cell_rep, V.ncell_total);
   A(V.atom_cell, n); A(V.atom_slot, n);
@@ -627,31 +681,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   up(d_ak, s->angle_k, sizeof(double) * s->n_angles);
   up(d_at0, s->angle_t0, sizeof(double) * s->n_angles);
   up(c->d_rep_off, c->rep_off.data(), sizeof(int) * (nrep + 1));
-  // Chain order: atoms grouped by type into type-pure waves (atoms of one type
-  // have similar jump counts, so a wave is not held up by its busiest type),
-  // and the waves of the types interleaved in proportion so that every part
-  // of the device gets a similar mix. Results do not depend on the order.
-  std::vector<int> chain_perm;
-  {
-    const int apw = 64 / V.chain_lanes;
-    std::vector<std::vector<int>> by_type(nt);
-    for (int i = 0; i < n; ++i) by_type[s->type[i]].push_back(i);
-    struct Chunk { double key; int t, beg, len; };
-    std::vector<Chunk> full, part;
-    for (int t = 0; t < nt; ++t) {
-      const int m = (int)by_type[t].size(), nw = (m + apw - 1) / apw;
-      for (int w = 0; w < nw; ++w) {
-        Chunk ch{(w + 0.5) / nw, t, w * apw, std::min(apw, m - w * apw)};
-        (ch.len == apw ? full : part).push_back(ch);
-      }
-    }
-    std::stable_sort(full.begin(), full.end(), [](const Chunk &a, const Chunk &b) { return a.key < b.key; });
-    chain_perm.reserve(n);
-    for (auto *v : {&full, &part})
-      for (const Chunk &ch : *v)
-        for (int q = 0; q < ch.len; ++q) chain_perm.push_back(by_type[ch.t][ch.beg + q]);
-    up(d_chain_perm, chain_perm.data(), sizeof(int) * n);
-  }
+  up(d_chain_perm, chain_perm.data(), sizeof(int) * chain_perm.size());
   {
     std::vector<int> cr(V.ncell_total);
     for (int r = 0; r < nrep; ++r)

@@ -10,6 +10,7 @@
 #define MD_MAX_OPS 12
 #define MD_ZS_MAXIT 64
 #define MD_MAX_PROPOSALS (1ll << 22)  // per chain and half step; reaching it flags the run as unstable
+#define MD_CHAIN_MAX_BLOCK_WAVES 8     // waves per k_chain block at most (two per SIMD of a CU)
 #define MD_PI 3.14159265358979323846
 #define MD_INV_SQRT_2PI 0.3989422804014327
 
@@ -25,8 +26,10 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    // one 32x32 -> 64 multiply gives both halves (a single v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
   }
@@ -139,7 +142,9 @@ struct MDView {
   double beta, kT, eps0;
   int jlj, jc, log_events, precision;
   int chain_lanes;       // lanes cooperating on one atom's jump chain (1, 2, 4, 8, 16)
-  const int *chain_perm; // [n] atom handled by chain group g (type-pure waves, interleaved)
+  int chain_block_waves; // waves per k_chain block
+  int chain_groups;      // length of chain_perm (>= n)
+  const int *chain_perm; // [chain_groups] atom whose chain group g runs, -1: idle group
   uint64_t seed;
 };
 

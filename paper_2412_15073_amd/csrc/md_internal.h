@@ -14,8 +14,8 @@
 
 hipError_t launch_local(const MDView &V, const MDProg &P, const double4 *Xs, double4 *Xd, hipStream_t s);
 hipError_t launch_chain(const MDView &V, const MDProg &P, const double4 *X, hipStream_t s);
-size_t chain_lds_bytes_host(int G, int S);   // dynamic LDS of one k_chain block
-int chain_blocks_per_cu(int G, int S);       // resident k_chain blocks per CU (0: unknown)
+size_t chain_lds_bytes_host(int G, int S, int precision);   // dynamic LDS of one k_chain wave
+int chain_blocks_per_cu(int G, int S, int precision, int bw); // resident blocks of bw waves per CU (0: unknown)
 hipError_t launch_rebuild(const MDView &V, const double4 *X, int want, int slot, int forced, int autob,
                           double thr2, int pc, int ps, bool check_only, int count, hipStream_t s);
 hipError_t launch_force(const MDView &V, const double4 *X, int mode, hipStream_t s);

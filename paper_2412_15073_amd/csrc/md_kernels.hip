@@ -1,10 +1,12 @@
 // md_kernels.hip — HIP kernels of libjumpmd for gfx950 (CDNA4, wave64).
 //
-//  k_local     fused per-atom program: B / A / O updates (Sec. 2.3), J chains
-//              (BPS jumps, Sec. 3.2, Alg. 5 in exponential-clock form) and C
-//              chains (acceleration + MRZ jumps, Sec. 2.4, Alg. 4), one atom
-//              per lane; positions are double-buffered so that chains read
-//              a stable copy while drift writes the other.
+//  k_chain     the position-preserving prefix of a step program: B kicks,
+//              J chains (BPS jumps, Sec. 3.2, Alg. 5 in exponential-clock
+//              form) and C chains (acceleration + MRZ jumps, Sec. 2.4,
+//              Alg. 4); G lanes per atom, proposal rings in LDS.
+//  k_local     the rest of the program, one atom per lane: B / A / O updates
+//              (Sec. 2.3) and the displacement check; positions are
+//              double-buffered (read one copy, write the other).
 //  k_cell_*    counting sort of atoms into per-replica cells.
 //  k_build     neighbour rows, one wavefront per atom: candidates gathered
 //              from the cell stencil with ballot compaction into LDS, bitonic
@@ -96,22 +98,24 @@ __device__ __forceinline__ float theta_r(float eta) { return theta_fn_f(eta); }
 
 struct AtomStats { long long nprop, nacc, nviol; uint64_t hash; };
 
+// accepted jump of atom i with partner lj (index within the replica)
 __device__ __forceinline__ void log_jump(const MDView &V, AtomStats &st, int64_t step, int phase,
-                                         int i, int j, int64_t k) {
-  st.hash = event_mix(st.hash, step, phase, V.loc[j]);
+                                         int i, int lj, int64_t k) {
+  st.hash = event_mix(st.hash, step, phase, lj);
   st.nacc++;
   if (V.log_events) {
     unsigned long long e = atomicAdd(&V.ctl->n_events, 1ull);
     if ((long long)e < V.ev_cap) {
-      MDEventDev ev; ev.step = step; ev.phase = phase; ev.atom = i; ev.partner = j; ev.proposal = (int)k;
+      MDEventDev ev; ev.step = step; ev.phase = phase; ev.atom = i; ev.partner = V.rep_off[V.rep[i]] + lj;
+      ev.proposal = (int)k;
       V.ev[e] = ev;
     }
   }
 }
 
 // the part of log_jump every lane of a group repeats (replicated statistics)
-__device__ __forceinline__ void log_jump_hash_only(const MDView &V, AtomStats &st, int64_t step, int phase, int j) {
-  st.hash = event_mix(st.hash, step, phase, V.loc[j]);
+__device__ __forceinline__ void log_jump_hash_only(AtomStats &st, int64_t step, int phase, int lj) {
+  st.hash = event_mix(st.hash, step, phase, lj);
   st.nacc++;
 }
 
@@ -148,7 +152,7 @@ __host__ __device__ constexpr int ring_bytes(int G, int rsize) {
 // LDS doubles per atom of the segment table for S segments: cumulative
 // weights (S), cumulative counts (S, plus one spare: last usable segment)
 // and starts (S + 1 ints)
-__host__ __device__ constexpr int seg_lds_doubles(int S) { return 2 * S + 1 + (S + 2) / 2; }
+__host__ __device__ constexpr int seg_lds_doubles(int S) { return 3 * S + 1 + (S + 2) / 2; }
 
 // wave-scope ordering of LDS writes by some lanes before reads by others
 __device__ __forceinline__ void wave_lds_sync() {
@@ -189,16 +193,20 @@ __device__ __forceinline__ R norm2_nc(R x, R y, R z) {
 // sum n_q l_q and cumulative counts of the candidates whose bound is nonzero.
 // The first segment whose cumulative value exceeds a target always has
 // n_q l_q > 0, so the searches need no validity test.
+// Per-atom segment table in LDS: cumulative weights cw[S], cumulative usable
+// counts cn[S] (+ spare slot: last usable segment), bounds el[S], segment
+// starts st[S + 1].
 struct SegL {
-  double *cw, *cn;
+  double *cw, *cn, *el;
   int *st;
-  int S, last, a, coul;
+  int S, top, last, a, coul;   // top: largest power of two <= S
   double W, nf, absq;
 
   __device__ __forceinline__ void attach(double *base, int S_) {
     S = S_;
-    cw = base; cn = base + S;
-    st = (int *)(base + 2 * S + 1);
+    top = 1 << (31 - __clz(S_));
+    cw = base; cn = base + S; el = base + 2 * S + 1;
+    st = (int *)(base + 3 * S + 1);
   }
   // lane r == 0 of the group writes; every lane reads back the totals
   __device__ __forceinline__ void build(const MDView &V, int i, int a_, int coul_, double absq_, int r) {
@@ -217,7 +225,7 @@ struct SegL {
         w += (double)nq * l;
         if (l > 0.0) c += nq;
         if (nq > 0 && l > 0.0) lst = q;
-        cw[q] = w; cn[q] = (double)c; st[q + 1] = s1;
+        cw[q] = w; cn[q] = (double)c; el[q] = l; st[q + 1] = s1;
         s0 = s1;
       }
       cn[S] = (double)lst;   // spare slot: last usable segment
@@ -227,37 +235,39 @@ struct SegL {
     nf = cn[S - 1];
     last = (int)cn[S];
   }
-  __device__ __forceinline__ int first_above(const double *c, double target) const {
-    int lo = 0, hi = S;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (target < c[mid]) hi = mid; else lo = mid + 1;
+  // Candidates of both branches for one uniform u (the second only if
+  // both): by bound (segment by n_q l_q, then uniform inside from the
+  // residual) and uniform among those with a nonzero bound. Each segment is
+  // the first whose cumulative value exceeds the target (the last usable one
+  // past the end), found by two interleaved fixed-step bisections.
+  __device__ __forceinline__ void pick2(double u, bool both, int &pb, double &ellb, int &segb, int &pf,
+                                        double &ellf, int &segf) const {
+    const double tb = u * W, tf = u * nf;
+    int qb = 0, qf = 0;
+    for (int step = top; step > 0; step >>= 1) {
+      const int xb = qb + step, xf = qf + step;
+      const double cb = cw[(xb <= S ? xb : S) - 1], cf = cn[(xf <= S ? xf : S) - 1];
+      if (xb <= S && cb <= tb) qb = xb;
+      if (xf <= S && cf <= tf) qf = xf;
     }
-    return lo < S ? lo : last;
-  }
-  // candidate in proportion to its bound: segment by n_q l_q, then uniform
-  // inside from the residual
-  __device__ __forceinline__ int pick_by_bound(const MDView &V, double u, double &ell_s) const {
-    const double target = u * W;
-    const int s = first_above(cw, target);
-    const double below = s > 0 ? cw[s - 1] : 0.0;
-    const double el_s = seg_ell(V, a, s, coul, absq);
-    const int base = st[s], n = st[s + 1] - base;
-    long long idx = (long long)floor((target - below) / el_s);
-    idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
-    ell_s = el_s;
-    return base + (int)idx;
-  }
-  // candidate uniform among those with a nonzero bound
-  __device__ __forceinline__ int pick_uniform(const MDView &V, double u, double &ell_s) const {
-    const double target = u * nf;
-    const int s = first_above(cn, target);
-    const double below = s > 0 ? cn[s - 1] : 0.0;
-    const int base = st[s], n = st[s + 1] - base;
-    long long idx = (long long)floor(target - below);
-    idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
-    ell_s = seg_ell(V, a, s, coul, absq);
-    return base + (int)idx;
+    {
+      const int sg = qb < S ? qb : last;
+      const double below = sg > 0 ? cw[sg - 1] : 0.0;
+      const double el_s = el[sg];
+      const int base = st[sg], n = st[sg + 1] - base;
+      long long idx = (long long)floor((tb - below) / el_s);
+      idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
+      pb = base + (int)idx; ellb = el_s; segb = sg;
+    }
+    pf = pb; ellf = 0.0; segf = segb;
+    if (both) {
+      const int sg = qf < S ? qf : last;
+      const double below = sg > 0 ? cn[sg - 1] : 0.0;
+      const int base = st[sg], n = st[sg + 1] - base;
+      long long idx = (long long)floor(tf - below);
+      idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
+      pf = base + (int)idx; ellf = el[sg]; segf = sg;
+    }
   }
 };
 
@@ -333,6 +343,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   const int a = V.type[i];
   T.build(V, i, a, isC ? 1 : 0, isC ? fabs(xi.w) : 0.0, r);
   const int *row = V.crow + (size_t)i * V.cap_c;
+  const double inv_nr = 1.0 / (double)V.nr;
   const bool adaptive = isC && (V.jc == MD_JUMP_MRZ_ADAPTIVE);
   const R beta = (R)V.beta, eps0 = (R)V.eps0, mr = (R)me;
   const R f = sqrt(beta / (R(2) * R(MD_PI) * mr)) / eps0;
@@ -388,37 +399,46 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       if (r == 0) atomicAdd(&V.ctl->nonfinite, 1ull);
       finish();
     }
-    // wave-synchronous refill: every atom with room for G more proposals
+    // wave-synchronous refill: every atom tops up as many slots as are free
+    // (at most G, one per lane); an atom below G takes G since M >= 2G
     if (__any(live && computed - w0 < G)) {
       wave_lds_sync();   // reads of the slots being replaced are complete
-      if (live && computed - w0 <= M - G) {
+      const int free_slots = M - (computed - w0);
+      const int take = live ? (free_slots < G ? free_slots : G) : 0;
+      if (r < take) {
         const int k = computed + r;
         const int sl = ring_add(cs, r, M);
         Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
-        double ell, Fx, Fy, Fz;
-        const int jb = row[T.pick_by_bound(V, u.u[2], ell)];
-        long_grad<PREC>(V, xi, X[jb], a, V.type[jb], isC ? 1 : 0, L, iL, Fx, Fy, Fz);
+        // candidates of both branches first, so that their gathers overlap
+        double ellb, ellf;
+        int pb, pf, sb, sf;
+        T.pick2(u.u[2], adaptive, pb, ellb, sb, pf, ellf, sf);
+        const int jb = row[pb], jf = row[pf];
+        const double4 xb = X[jb], xf = X[jf];
+        const int lb = V.loc[jb], lf = V.loc[jf];
+        Uni4 z;
+        if (isC) z = draw4(V.seed, rep, op.step, li, (uint64_t)(uint32_t)op.phase | (1ull << 24), k);
         ring[RF_E * M + sl] = (R)(-log(u.u[0]));
         ring[RF_U1 * M + sl] = (R)u.u[1];
         ring[RF_U3 * M + sl] = (R)u.u[3];
+        double Fx, Fy, Fz;
+        // segment sg = b * nr + ring: the partner's type without a load
+        long_grad<PREC>(V, xi, xb, a, (int)(((double)sb + 0.5) * inv_nr), isC ? 1 : 0, L, iL, Fx, Fy, Fz);
         ring[RF_BX * M + sl] = (R)Fx; ring[RF_BY * M + sl] = (R)Fy; ring[RF_BZ * M + sl] = (R)Fz;
-        ring[RF_BL * M + sl] = (R)ell;
-        int jf = jb;
+        ring[RF_BL * M + sl] = (R)ellb;
         if (adaptive) {
-          jf = row[T.pick_uniform(V, u.u[2], ell)];
-          long_grad<PREC>(V, xi, X[jf], a, V.type[jf], 1, L, iL, Fx, Fy, Fz);
+          long_grad<PREC>(V, xi, xf, a, 0, 1, L, iL, Fx, Fy, Fz);
           ring[RF_FX * M + sl] = (R)Fx; ring[RF_FY * M + sl] = (R)Fy; ring[RF_FZ * M + sl] = (R)Fz;
-          ring[RF_FL * M + sl] = (R)ell;
+          ring[RF_FL * M + sl] = (R)ellf;
         }
-        jring[sl] = make_int2(jb, jf);
+        jring[sl] = make_int2(lb, lf);   // replica-local indices (event hash)
         if (isC) {
-          Uni4 z = draw4(V.seed, rep, op.step, li, (uint64_t)(uint32_t)op.phase | (1ull << 24), k);
           ring[RF_Z0 * M + sl] = (R)z.u[0]; ring[RF_Z1 * M + sl] = (R)z.u[1];
           ring[RF_Z2 * M + sl] = (R)z.u[2]; ring[RF_Z3 * M + sl] = (R)z.u[3];
         }
-        computed += G;
-        cs = ring_add(cs, G, M);
       }
+      computed += take;
+      cs = ring_add(cs, take, M);
       wave_lds_sync();
     }
     if (!live) continue;
@@ -439,6 +459,8 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     // acceptance u3 <= lam / c and bound violation lam > c, tested without dividing
     bool out, acc, viol;
     R eta = R(0), tk = R(0);
+    R zown = R(0);     // first Z iteration of this lane's proposal, taken if it is accepted
+    bool zok = false;
     if (isC) {
       tk = te + s * iLam;
       out = tk > h;
@@ -459,6 +481,11 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       }
       acc = !out && lam > R(0) && u3 * c <= lam;
       viol = lam > c;
+      // the first accepted proposal's Z is evaluated by its own lane, off the
+      // sequential path after the group minimum
+      if (acc)
+        zok = z_iteration<R>(eta, ring[RF_Z0 * M + sl], ring[RF_Z1 * M + sl], ring[RF_Z2 * M + sl],
+                             ring[RF_Z3 * M + sl], zown);
     } else {
       out = s * iLam > h;
       const R vF = (R)vx * Fx + (R)vy * Fy + (R)vz * Fz;
@@ -473,20 +500,19 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     n_viol += (counted && viol) ? 1 : 0;
     if (first == G) { base = tot; w0 += G; ws = ring_add(ws, G, M); continue; }
     if (__shfl((int)out, first, G)) { finish(); continue; }
-    // the accepted proposal's gradient, read by every lane of the group
+    // the accepted proposal's gradient, from the lane that holds it
     const int fs = ring_add(ws, first, M);
     const int fos = __shfl(fo, first, G);
-    const R Fxs = ring[fos + RF_BX * M + fs], Fys = ring[fos + RF_BY * M + fs], Fzs = ring[fos + RF_BZ * M + fs];
-    const R F2s = norm2_nc(Fxs, Fys, Fzs);
+    const R Fxs = __shfl(Fx, first, G), Fys = __shfl(Fy, first, G), Fzs = __shfl(Fz, first, G);
+    const R F2s = __shfl(F2, first, G);
     const int2 jj = jring[fs];
     const int j = fos ? jj.y : jj.x;
     const int kstar = w0 + first;
     if (isC) {
       const R etas = __shfl(eta, first, G);
       const R tks = __shfl(tk, first, G);
-      R Z;
-      if (!z_iteration<R>(etas, ring[RF_Z0 * M + fs], ring[RF_Z1 * M + fs], ring[RF_Z2 * M + fs],
-                          ring[RF_Z3 * M + fs], Z)) {
+      R Z = __shfl(zown, first, G);
+      if (!__shfl((int)zok, first, G)) {
         int ovf;
         Z = zsample_grp<G, R>(etas, V.seed, rep, op.step, li, op.phase, kstar, r, 1, ovf);
         if (ovf && r == 0) atomicAdd(&V.ctl->n_zs_overflow, 1ull);
@@ -512,7 +538,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       base = __shfl(s, first, G);
     }
     if (r == first) log_jump(V, st, op.step, op.phase, i, j, kstar);
-    else log_jump_hash_only(V, st, op.step, op.phase, j);
+    else log_jump_hash_only(st, op.step, op.phase, j);
     w0 = kstar + 1;
     ws = ring_add(ws, first + 1, M);
   }
@@ -521,20 +547,22 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
 }
 
 // Chain kernel: the position-preserving prefix of a step program (B kicks,
-// J and C chains) for every atom; G lanes per atom, one wave per block.
-// Dynamic LDS: the proposal rings of the block's 64/G atoms, then their
-// segment tables.
+// J and C chains) for every atom; G lanes per atom, 64/G atoms per wave and
+// one or more independent waves per block (no block-wide barrier). Group g
+// runs the chain of atom chain_perm[g] (-1: idle). Dynamic LDS per wave: the
+// proposal rings of its 64/G atoms, then their segment tables.
 #ifndef MD_CHAIN_WAVES_PER_SIMD
 #define MD_CHAIN_WAVES_PER_SIMD 2   // register budget of the chain kernel: 512 / this per lane
 #endif
 template <int G, int PREC>
-__global__ __launch_bounds__(64, MD_CHAIN_WAVES_PER_SIMD) void k_chain(MDView V, MDProg P,
-                                                                      const double4 *__restrict__ X) {
+__global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_SIMD) void k_chain(
+    MDView V, MDProg P, const double4 *__restrict__ X) {
   extern __shared__ double lds_chain[];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int grp = gid / G, r = gid - (gid / G) * G;
-  if (grp >= V.n) return;
+  if (grp >= V.chain_groups) return;
   const int i = V.chain_perm[grp];
+  if (i < 0) return;   // empty group of a partial wave
   const double4 xi = X[i];
   const double4 vv = V.v[i];
   double vx = vv.x, vy = vv.y, vz = vv.z;
@@ -549,12 +577,14 @@ __global__ __launch_bounds__(64, MD_CHAIN_WAVES_PER_SIMD) void k_chain(MDView V,
   constexpr int M = ring_slots(G);
   constexpr int APB = 64 / G;
   constexpr int RB = ring_bytes(G, (int)sizeof(R));
-  const int ab = (int)threadIdx.x / G;
-  char *base_b = (char *)lds_chain + ab * RB;
+  // each wave of the block owns one slice: the rings of its APB atoms, then their segment tables
+  const int ab = ((int)threadIdx.x & 63) / G;
+  char *wave_b = (char *)lds_chain + ((int)threadIdx.x >> 6) * (APB * RB + APB * 8 * seg_lds_doubles(V.S));
+  char *base_b = wave_b + ab * RB;
   R *ring = (R *)base_b;
   int2 *jring = (int2 *)(base_b + ((RF_N * M * (int)sizeof(R) + 7) / 8) * 8);
   SegL T;
-  T.attach((double *)((char *)lds_chain + APB * RB) + ab * seg_lds_doubles(V.S), V.S);
+  T.attach((double *)(wave_b + APB * RB) + ab * seg_lds_doubles(V.S), V.S);
   const int64_t sbase = P.dev_step ? (int64_t)V.ctl->step_base : 0;
   for (int o = 0; o < P.nops; ++o) {
     MDOp op = P.ops[o];
@@ -1263,39 +1293,48 @@ __global__ void k_set_step(MDCtl *ctl, long long step) { ctl->step_base = step; 
 // ------------------------------------------------------------- launchers
 #define CHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
-// LDS bytes of one k_chain block with G lanes per atom (rsize: bytes of the chain real type)
+// LDS bytes of one k_chain wave with G lanes per atom (rsize: bytes of the chain real type)
 static size_t chain_lds_bytes(int G, int S, int rsize = 8) {
   return (size_t)(64 / G) * ((size_t)ring_bytes(G, rsize) + sizeof(double) * (size_t)seg_lds_doubles(S));
 }
-size_t chain_lds_bytes_host(int G, int S) { return chain_lds_bytes(G, S); }
+size_t chain_lds_bytes_host(int G, int S, int precision) {
+  return chain_lds_bytes(G, S, precision == MD_FP32_MIXED ? 4 : 8);
+}
 
-// resident k_chain blocks per CU (registers and LDS), 0 if unknown
-int chain_blocks_per_cu(int G, int S) {
-  int nb = 0;
-  const size_t lds = chain_lds_bytes(G, S);
-  hipError_t e = hipErrorInvalidValue;
+template <int PREC>
+static hipError_t chain_occupancy(int G, int threads, size_t lds, int *nb) {
   switch (G) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<1, MD_FP64>, 64, lds); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<2, MD_FP64>, 64, lds); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<4, MD_FP64>, 64, lds); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<8, MD_FP64>, 64, lds); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_chain<16, MD_FP64>, 64, lds); break;
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<1, PREC>, threads, lds);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<2, PREC>, threads, lds);
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<4, PREC>, threads, lds);
+    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<8, PREC>, threads, lds);
+    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<16, PREC>, threads, lds);
   }
+  return hipErrorInvalidValue;
+}
+
+// resident k_chain blocks of bw waves per CU (registers and LDS), 0 if unknown
+int chain_blocks_per_cu(int G, int S, int precision, int bw) {
+  int nb = 0;
+  if (bw < 1 || bw > MD_CHAIN_MAX_BLOCK_WAVES) return 0;
+  const size_t lds = (size_t)bw * chain_lds_bytes_host(G, S, precision);
+  const hipError_t e = precision == MD_FP32_MIXED ? chain_occupancy<MD_FP32_MIXED>(G, 64 * bw, lds, &nb)
+                                                  : chain_occupancy<MD_FP64>(G, 64 * bw, lds, &nb);
   return e == hipSuccess ? nb : 0;
 }
 
 template <int PREC>
 static void launch_chain_p(const MDView &V, const MDProg &P, const double4 *X, hipStream_t s) {
-  const int G = V.chain_lanes;
-  const long long threads = (long long)V.n * G;
-  const int nb = (int)((threads + 63) / 64);   // wave-sized blocks spread the few long waves over all CUs
-  const size_t lds = chain_lds_bytes(G, V.S, PREC == MD_FP32_MIXED ? 4 : 8);
+  const int G = V.chain_lanes, bw = V.chain_block_waves;
+  const int nb = (int)(((long long)V.chain_groups * G + 64 * bw - 1) / (64 * bw));
+  const size_t lds = (size_t)bw * chain_lds_bytes(G, V.S, PREC == MD_FP32_MIXED ? 4 : 8);
+  const dim3 grid(nb), block(64 * bw);
   switch (G) {
-    case 1: hipLaunchKernelGGL((k_chain<1, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
-    case 2: hipLaunchKernelGGL((k_chain<2, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
-    case 4: hipLaunchKernelGGL((k_chain<4, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
-    case 8: hipLaunchKernelGGL((k_chain<8, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
-    default: hipLaunchKernelGGL((k_chain<16, PREC>), dim3(nb), dim3(64), lds, s, V, P, X); break;
+    case 1: hipLaunchKernelGGL((k_chain<1, PREC>), grid, block, lds, s, V, P, X); break;
+    case 2: hipLaunchKernelGGL((k_chain<2, PREC>), grid, block, lds, s, V, P, X); break;
+    case 4: hipLaunchKernelGGL((k_chain<4, PREC>), grid, block, lds, s, V, P, X); break;
+    case 8: hipLaunchKernelGGL((k_chain<8, PREC>), grid, block, lds, s, V, P, X); break;
+    default: hipLaunchKernelGGL((k_chain<16, PREC>), grid, block, lds, s, V, P, X); break;
   }
 }
 
