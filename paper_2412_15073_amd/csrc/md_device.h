@@ -44,10 +44,16 @@ __device__ __forceinline__ double u01(uint32_t w) {
 
 struct Uni4 { double u[4]; };
 
+// the four raw words of block (step, atom, tag, k) under key (seed, replica)
+__device__ __forceinline__ u32x4 draw4w(uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
+                                        uint64_t tag, int64_t k) {
+  return philox4x32_10((uint32_t)step, (uint32_t)atom, (uint32_t)tag, (uint32_t)k,
+                       (uint32_t)seed, (uint32_t)(seed >> 32) ^ (uint32_t)rep);
+}
+
 __device__ __forceinline__ Uni4 draw4(uint64_t seed, uint64_t rep, int64_t step, int64_t atom,
                                       uint64_t tag, int64_t k) {
-  const u32x4 r = philox4x32_10((uint32_t)step, (uint32_t)atom, (uint32_t)tag, (uint32_t)k,
-                                (uint32_t)seed, (uint32_t)(seed >> 32) ^ (uint32_t)rep);
+  const u32x4 r = draw4w(seed, rep, step, atom, tag, k);
   Uni4 o;
 #pragma unroll
   for (int q = 0; q < 4; ++q) o.u[q] = u01(r.w[q]);

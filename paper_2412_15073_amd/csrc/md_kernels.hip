@@ -133,10 +133,13 @@ __device__ __forceinline__ void log_jump_hash_only(AtomStats &st, int64_t step, 
 // the half step) is found with a group minimum. Every decision is the one the
 // one-proposal-at-a-time chain takes.
 
-// ring fields (chain real type R, field-major: field f of slot s at f*M + s),
-// followed by the candidate pairs (by-bound, uniform) as M int2
-enum { RF_E = 0, RF_U1, RF_U3, RF_BX, RF_BY, RF_BZ, RF_BL, RF_FX, RF_FY, RF_FZ, RF_FL,
-       RF_Z0, RF_Z1, RF_Z2, RF_Z3, RF_N };
+// ring fields (chain real type R, field-major: field f of slot s at f*M + s):
+// clock E, gradient and bound of each branch, and the first Z iteration's
+// velocity-independent part (log u0, log u1, cospi(2 u2), u2). Then, per slot,
+// the raw words (u1, u3) of the proposal block and (u0, u3) of the Z block
+// (uint2 each), and the candidate pair (by-bound, uniform) as int2.
+enum { RF_E = 0, RF_BX, RF_BY, RF_BZ, RF_BL, RF_FX, RF_FY, RF_FZ, RF_FL,
+       RF_ZL0, RF_ZL1, RF_ZCP, RF_ZU2, RF_N };
 
 // real type of the chain arithmetic: FP64, or float in the mixed path
 template <int PREC> struct ChainReal { using T = double; };
@@ -144,10 +147,10 @@ template <> struct ChainReal<MD_FP32_MIXED> { using T = float; };
 
 __host__ __device__ constexpr int ring_slots(int G) { return G == 1 ? 3 : (5 * G) / 2; }
 
-// LDS bytes of one atom's ring: R fields (8-byte aligned), then the int2 pairs
-__host__ __device__ constexpr int ring_bytes(int G, int rsize) {
-  return ((RF_N * ring_slots(G) * rsize + 7) / 8) * 8 + 8 * ring_slots(G);
-}
+// LDS bytes of one atom's ring: R fields (8-byte aligned), then the two
+// uint2 word pairs and the int2 candidate pair of every slot
+__host__ __device__ constexpr int ring_rbytes(int G, int rsize) { return ((RF_N * ring_slots(G) * rsize + 7) / 8) * 8; }
+__host__ __device__ constexpr int ring_bytes(int G, int rsize) { return ring_rbytes(G, rsize) + 24 * ring_slots(G); }
 
 // LDS doubles per atom of the segment table for S segments: cumulative
 // weights (S), cumulative counts (S, plus one spare: last usable segment)
@@ -275,22 +278,38 @@ struct SegL {
 // logarithms and the square root are shared by the regimes (lanes of a wave
 // often sit in different regimes), and the acceptance tests of the first two
 // regimes are taken in log space or without division.
+// The iteration splits into its velocity-independent part (two logarithms
+// and a cosine of the uniforms) and the eta-dependent rest.
+template <typename R> struct ZPre { R l0, l1, cp; };
+
+__device__ __forceinline__ double cospi_r(double x) { return cospi(x); }
+__device__ __forceinline__ float cospi_r(float x) { return cospif(x); }
+
 template <typename R>
-__device__ __forceinline__ bool z_iteration(R eta, R u0, R u1, R u2, R u3, R &z) {
-  const R l0 = log(u0), l1 = log(u1);
-  const R rad = sqrt(R(-2) * (eta > R(0) ? l1 : l0));
+__device__ __forceinline__ ZPre<R> z_pre(R u0, R u1, R u2) {
+  return ZPre<R>{log(u0), log(u1), cospi_r(R(2) * u2)};
+}
+
+template <typename R>
+__device__ __forceinline__ bool z_accept(R eta, const ZPre<R> &p, R u0, R u2, R u3, R &z) {
+  const R rad = sqrt(R(-2) * (eta > R(0) ? p.l1 : p.l0));
   if (eta > R(0)) {
     // Rayleigh part with probability 1 / (1 + eta sqrt(2 pi)), else Gaussian
-    const R y = (u0 * (R(1) + eta * R(2.5066282746310002)) < R(1)) ? rad : rad * cospi(R(2) * u2);
+    const R y = (u0 * (R(1) + eta * R(2.5066282746310002)) < R(1)) ? rad : rad * p.cp;
     z = eta + y;
     return (y >= R(0)) || (z > R(0) && u3 * eta <= z);
   }
   if (eta >= R(-1)) {
     z = rad;
-    return l1 <= eta * z;
+    return p.l1 <= eta * z;
   }
-  z = (l0 + l1) / eta;
+  z = (p.l0 + p.l1) / eta;
   return u2 <= exp(R(-0.5) * z * z);
+}
+
+template <typename R>
+__device__ __forceinline__ bool z_iteration(R eta, R u0, R u1, R u2, R u3, R &z) {
+  return z_accept<R>(eta, z_pre<R>(u0, u1, u2), u0, u2, u3, z);
 }
 
 // Z iterations it0, it0 + 1, ... with G of them in parallel: lane r tries
@@ -336,7 +355,8 @@ template <int G, int PREC>
 __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
                          double &vx, double &vy, double &vz, double me, double ax_d, double ay_d, double az_d,
                          const MDOp &op, AtomStats &st, const double *L, const double *iL,
-                         typename ChainReal<PREC>::T *ring, int2 *jring, SegL &T) {
+                         typename ChainReal<PREC>::T *ring, uint2 *pwords, uint2 *zwords, int2 *jring,
+                         SegL &T) {
   using R = typename ChainReal<PREC>::T;
   constexpr int M = ring_slots(G);
   const bool isC = op.kind == OP_C;
@@ -408,19 +428,18 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       if (r < take) {
         const int k = computed + r;
         const int sl = ring_add(cs, r, M);
-        Uni4 u = draw4(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
+        const u32x4 uw = draw4w(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
         // candidates of both branches first, so that their gathers overlap
         double ellb, ellf;
         int pb, pf, sb, sf;
-        T.pick2(u.u[2], adaptive, pb, ellb, sb, pf, ellf, sf);
+        T.pick2(u01(uw.w[2]), adaptive, pb, ellb, sb, pf, ellf, sf);
         const int jb = row[pb], jf = row[pf];
         const double4 xb = X[jb], xf = X[jf];
         const int lb = V.loc[jb], lf = V.loc[jf];
-        Uni4 z;
-        if (isC) z = draw4(V.seed, rep, op.step, li, (uint64_t)(uint32_t)op.phase | (1ull << 24), k);
-        ring[RF_E * M + sl] = (R)(-log(u.u[0]));
-        ring[RF_U1 * M + sl] = (R)u.u[1];
-        ring[RF_U3 * M + sl] = (R)u.u[3];
+        u32x4 zw;
+        if (isC) zw = draw4w(V.seed, rep, op.step, li, (uint64_t)(uint32_t)op.phase | (1ull << 24), k);
+        ring[RF_E * M + sl] = (R)(-log(u01(uw.w[0])));
+        pwords[sl] = make_uint2(uw.w[1], uw.w[3]);
         double Fx, Fy, Fz;
         // segment sg = b * nr + ring: the partner's type without a load
         long_grad<PREC>(V, xi, xb, a, (int)(((double)sb + 0.5) * inv_nr), isC ? 1 : 0, L, iL, Fx, Fy, Fz);
@@ -433,8 +452,11 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         }
         jring[sl] = make_int2(lb, lf);   // replica-local indices (event hash)
         if (isC) {
-          ring[RF_Z0 * M + sl] = (R)z.u[0]; ring[RF_Z1 * M + sl] = (R)z.u[1];
-          ring[RF_Z2 * M + sl] = (R)z.u[2]; ring[RF_Z3 * M + sl] = (R)z.u[3];
+          const R zu2 = (R)u01(zw.w[2]);
+          const ZPre<R> zp = z_pre<R>((R)u01(zw.w[0]), (R)u01(zw.w[1]), zu2);
+          ring[RF_ZL0 * M + sl] = zp.l0; ring[RF_ZL1 * M + sl] = zp.l1;
+          ring[RF_ZCP * M + sl] = zp.cp; ring[RF_ZU2 * M + sl] = zu2;
+          zwords[sl] = make_uint2(zw.w[0], zw.w[3]);
         }
       }
       computed += take;
@@ -450,12 +472,13 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       tot += ring[RF_E * M + ring_add(ws, m, M)];
       if (m == r) s = tot;
     }
-    const bool use_f = adaptive && !(ring[RF_U1 * M + sl] * Lam < Wb);
+    const uint2 pw = pwords[sl];
+    const bool use_f = adaptive && !((R)u01(pw.x) * Lam < Wb);
     const int fo = use_f ? (RF_FX - RF_BX) * M : 0;
     const R Fx = ring[fo + RF_BX * M + sl], Fy = ring[fo + RF_BY * M + sl], Fz = ring[fo + RF_BZ * M + sl];
     const R ell = ring[fo + RF_BL * M + sl];
     const R F2 = norm2_nc(Fx, Fy, Fz);
-    const R u3 = ring[RF_U3 * M + sl];
+    const R u3 = (R)u01(pw.y);
     // acceptance u3 <= lam / c and bound violation lam > c, tested without dividing
     bool out, acc, viol;
     R eta = R(0), tk = R(0);
@@ -483,9 +506,11 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       viol = lam > c;
       // the first accepted proposal's Z is evaluated by its own lane, off the
       // sequential path after the group minimum
-      if (acc)
-        zok = z_iteration<R>(eta, ring[RF_Z0 * M + sl], ring[RF_Z1 * M + sl], ring[RF_Z2 * M + sl],
-                             ring[RF_Z3 * M + sl], zown);
+      if (acc) {
+        const uint2 zz = zwords[sl];
+        const ZPre<R> zp{ring[RF_ZL0 * M + sl], ring[RF_ZL1 * M + sl], ring[RF_ZCP * M + sl]};
+        zok = z_accept<R>(eta, zp, (R)u01(zz.x), ring[RF_ZU2 * M + sl], (R)u01(zz.y), zown);
+      }
     } else {
       out = s * iLam > h;
       const R vF = (R)vx * Fx + (R)vy * Fy + (R)vz * Fz;
@@ -582,7 +607,9 @@ __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_S
   char *wave_b = (char *)lds_chain + ((int)threadIdx.x >> 6) * (APB * RB + APB * 8 * seg_lds_doubles(V.S));
   char *base_b = wave_b + ab * RB;
   R *ring = (R *)base_b;
-  int2 *jring = (int2 *)(base_b + ((RF_N * M * (int)sizeof(R) + 7) / 8) * 8);
+  uint2 *pwords = (uint2 *)(base_b + ring_rbytes(G, (int)sizeof(R)));
+  uint2 *zwords = pwords + M;
+  int2 *jring = (int2 *)(zwords + M);
   SegL T;
   T.attach((double *)(wave_b + APB * RB) + ab * seg_lds_doubles(V.S), V.S);
   const int64_t sbase = P.dev_step ? (int64_t)V.ctl->step_base : 0;
@@ -601,7 +628,7 @@ __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_S
         ay = (fn.y + (op.flags == 0 ? fb.y : 0.0)) / me;
         az = (fn.z + (op.flags == 0 ? fb.z : 0.0)) / me;
       }
-      chain_op<G, PREC>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, jring, T);
+      chain_op<G, PREC>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, pwords, zwords, jring, T);
     }
   }
   if (r == 0) {
