@@ -207,6 +207,15 @@ int md_profile_read(md_ctx *ctx, int32_t kid, double *total_ms, int64_t *launche
  * creation. Synchronises. */
 int md_counters(md_ctx *ctx, int64_t *pairs_last, int64_t *proposals_total);
 
+/* Diagnostic of the float screen of Theta (Sec. 2.2, Theta(eta) = eta Phi(eta)
+ * + phi(eta)) that the FP64 jump chains use to take most acceptance decisions
+ * without FP64 Theta: the largest relative error of the screen against FP64
+ * Theta over n >= 2 points evenly spaced in [eta_lo, eta_hi], computed on the
+ * current device (a few hundred bytes of scratch, freed on return).
+ * *max_rel_err receives it. Synchronous. MD_ERR_ARG for n < 2 or
+ * eta_lo >= eta_hi; the message is then in md_last_error(NULL). */
+int md_theta_screen_error(double eta_lo, double eta_hi, int32_t n, double *max_rel_err);
+
 #ifdef __cplusplus
 }
 #endif

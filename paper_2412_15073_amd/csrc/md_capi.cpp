@@ -1173,3 +1173,20 @@ extern "C" int md_counters(md_ctx *c, int64_t *pairs_last, int64_t *proposals_to
   }
   return rc;
 }
+
+// ---------------------------------------------------------- diagnostics
+extern "C" int md_theta_screen_error(double eta_lo, double eta_hi, int32_t n, double *max_rel_err) {
+  if (n < 2 || !(eta_lo < eta_hi) || !max_rel_err) return fail(nullptr, MD_ERR_ARG, "need n >= 2, eta_lo < eta_hi");
+  unsigned long long *d = nullptr;
+  if (hipMalloc(&d, sizeof(unsigned long long)) != hipSuccess) return fail(nullptr, MD_ERR_OOM, "device allocation failed");
+  unsigned long long h = 0;
+  hipError_t e = hipMemset(d, 0, sizeof(h));
+  if (e == hipSuccess) e = launch_theta_screen_err(eta_lo, eta_hi, n, d, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(&h, d, sizeof(h), hipMemcpyDeviceToHost);
+  hipFree(d);
+  if (e != hipSuccess) return fail(nullptr, MD_ERR_HIP, std::string("theta screen check: ") + hipGetErrorString(e));
+  double v;
+  std::memcpy(&v, &h, sizeof(v));
+  *max_rel_err = v;
+  return MD_OK;
+}

@@ -214,6 +214,16 @@ __device__ __forceinline__ float theta_fn_f(float eta) {
   return eta * (0.5f * erfcf(-eta * 0.70710678f)) + __expf(-0.5f * eta * eta) * 0.39894228f;
 }
 
+// Screen of Theta in float with the accurate erfcf and expf: relative error
+// below MD_THETA_SCREEN_TOL / 4 against theta_fn for eta >= MD_THETA_SCREEN_LO
+// (there the cancellation between the two terms amplifies rounding by less
+// than 2 eta^2 = 50; the bound is checked on the device by a test).
+#define MD_THETA_SCREEN_LO (-5.0)
+#define MD_THETA_SCREEN_TOL 2.44140625e-4   // 2^-12
+__device__ __forceinline__ float theta_screen(float eta) {
+  return eta * (0.5f * erfcf(-eta * 0.70710678f)) + expf(-0.5f * eta * eta) * 0.39894228f;
+}
+
 // Theta(eta) = E[(eta+G)_+] = eta Phi(eta) + phi(eta)  (Sec. 2.2)
 __device__ __forceinline__ double theta_fn(double eta) {
   return eta * (0.5 * erfc(-eta * 0.70710678118654752440)) + exp(-0.5 * eta * eta) * MD_INV_SQRT_2PI;

@@ -480,7 +480,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     const R F2 = norm2_nc(Fx, Fy, Fz);
     const R u3 = (R)u01(pw.y);
     // acceptance u3 <= lam / c and bound violation lam > c, tested without dividing
-    bool out, acc, viol;
+    bool out, acc = false, viol = false;
     R eta = R(0), tk = R(0);
     R zown = R(0);     // first Z iteration of this lane's proposal, taken if it is accepted
     bool zok = false;
@@ -492,18 +492,36 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       const R c = adaptive ? bBv * ell + f : ell * (bBv + f);
       R lam = R(0);
       const R vF = vkx * Fx + vky * Fy + vkz * Fz;
+      bool decided = false;
       if (!out && F2 > R(0)) {
+        R scale;
         if (adaptive) {
           eta = k_eta * vF;
-          lam = k_lam * theta_r(eta);
+          scale = k_lam;
         } else {
           const R Fn = sqrt(F2);
           eta = k_eta * vF / Fn;
-          lam = k_lam * Fn * theta_r(eta);
+          scale = k_lam * Fn;
         }
+        if (PREC == MD_FP64 && eta >= R(MD_THETA_SCREEN_LO)) {
+          // Both decisions (acceptance u3 c <= lam, bound violation lam > c)
+          // from the float screen when each lies outside its error bound;
+          // they are then the FP64 decisions. FP64 Theta only otherwise.
+          const R lam_s = scale * (R)theta_screen((float)eta);
+          const R d = R(MD_THETA_SCREEN_TOL) * lam_s;
+          const R thr = u3 * c;
+          if ((lam_s - d >= thr || lam_s + d < thr) && (lam_s - d > c || lam_s + d <= c)) {
+            acc = lam_s - d >= thr;
+            viol = lam_s - d > c;
+            decided = true;
+          }
+        }
+        if (!decided) lam = scale * theta_r(eta);
       }
-      acc = !out && lam > R(0) && u3 * c <= lam;
-      viol = lam > c;
+      if (!decided) {
+        acc = !out && lam > R(0) && u3 * c <= lam;
+        viol = lam > c;
+      }
       // the first accepted proposal's Z is evaluated by its own lane, off the
       // sequential path after the group minimum
       if (acc) {
@@ -1437,6 +1455,22 @@ hipError_t launch_count_pairs(const MDView &V, const double4 *X, int which, doub
                               hipStream_t s) {
   int nb = (V.n + 255) / 256;
   hipLaunchKernelGGL(k_count_pairs, dim3(nb), dim3(256), 0, s, V, X, which, cut, out);
+  return hipGetLastError();
+}
+
+// largest relative error of theta_screen against theta_fn over n points of
+// [lo, hi]; nonnegative doubles order as their bit patterns
+__global__ void k_theta_screen_err(double lo, double hi, int n, unsigned long long *out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double eta = lo + (hi - lo) * ((double)t / (double)(n - 1));
+  const double ref = theta_fn(eta);
+  const double e = fabs((double)theta_screen((float)eta) - ref) / ref;
+  atomicMax(out, (unsigned long long)__double_as_longlong(e));
+}
+
+hipError_t launch_theta_screen_err(double lo, double hi, int n, unsigned long long *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_theta_screen_err, dim3((n + 255) / 256), dim3(256), 0, s, lo, hi, n, out);
   return hipGetLastError();
 }
 

@@ -66,7 +66,7 @@ EXPORTS = ["md_create", "md_destroy", "md_last_error", "md_step_baoab", "md_step
            "md_step_jump_respa", "md_step_baoab_respa", "md_observables", "md_sync", "md_get_state",
            "md_set_state", "md_get_accel", "md_get_atom_stats", "md_get_events", "md_rdf",
            "md_get_cand_row", "md_get_row_counts", "md_run_phase", "md_profile", "md_profile_read",
-           "md_counters"]
+           "md_counters", "md_theta_screen_error"]
 
 _lib = None
 
@@ -115,6 +115,7 @@ def load():
     L.md_profile.argtypes = [C.c_void_p, C.c_int32]
     L.md_profile_read.argtypes = [C.c_void_p, C.c_int32, _dp, _lp]
     L.md_counters.argtypes = [C.c_void_p, _lp, _lp]
+    L.md_theta_screen_error.argtypes = [C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double)]
     for fn in EXPORTS:
         if fn not in ("md_destroy", "md_last_error"):
             getattr(L, fn).restype = C.c_int
@@ -124,6 +125,17 @@ def load():
 
 def _ptr(a, t):
     return None if a is None else a.ctypes.data_as(t)
+
+
+def theta_screen_error(eta_lo, eta_hi, n):
+    """Largest relative error of the device's float screen of Theta against
+    FP64 Theta over n points of [eta_lo, eta_hi] (md_theta_screen_error)."""
+    L = load()
+    out = C.c_double(0.0)
+    rc = L.md_theta_screen_error(float(eta_lo), float(eta_hi), int(n), C.byref(out))
+    if rc != 0:
+        raise MDError(rc, L.md_last_error(None).decode())
+    return out.value
 
 
 def _concat(systems):

@@ -50,3 +50,12 @@ def test_create_rejects_bad_arguments_without_touching_the_device():
     with pytest.raises(jumpmd.MDError) as e:
         jumpmd.Sim(sy, bad, S.lj_params(), stream=0)
     assert e.value.code == jumpmd.MD_ERR_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libjumpmd.so not built")
+def test_theta_screen_check_rejects_bad_arguments_without_touching_the_device():
+    from paper_2412_15073_amd import jumpmd
+    for lo, hi, n in ((-5.0, 60.0, 1), (1.0, 1.0, 100), (2.0, -1.0, 100)):
+        with pytest.raises(jumpmd.MDError) as e:
+            jumpmd.theta_screen_error(lo, hi, n)
+        assert e.value.code == jumpmd.MD_ERR_ARG

@@ -244,3 +244,16 @@ def test_water_4096_full_size_in_bench_configuration(jm, precision_scheme):
         g.step_baoab(4)
         o.step_baoab(4)
     _compare_state(g, o)
+
+
+def test_theta_screen_error_bound(jm):
+    """The FP64 chains take an acceptance or bound-violation decision from the
+    float screen of Theta only when the decision lies more than 2^-12 (relative)
+    from the screened rate. That decision equals the FP64 one if the screen's
+    relative error stays below 2^-12; this checks a quarter of that on the
+    device's math library, with a finer grid at the negative end, where the
+    two terms of Theta cancel."""
+    bound = 2.0 ** -12 / 4
+    assert jm.theta_screen_error(-5.0, 60.0, 1 << 22) < bound
+    assert jm.theta_screen_error(-5.0, -2.0, 1 << 22) < bound
+    assert jm.theta_screen_error(-0.5, 0.5, 1 << 20) < bound
