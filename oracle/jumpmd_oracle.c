@@ -204,6 +204,7 @@ struct orc_sim {
   double bound_scale;  /* test knob: every bound multiplied by this (1 by default) */
   /* statistics */
   int64_t *nprop, *nacc, *nviol; uint64_t *hash;
+  int64_t *knext;   /* per atom: first unused proposal of the last closing C' stream */
   int64_t n_rebuilds, n_zs_overflow, n_list_err;
   int64_t nev, evcap; int64_t *ev;
 };
@@ -607,8 +608,13 @@ static void jstep_atom(orc_sim *s, int i, int32_t phase, double h) {
  * u0 -> E_k (time t_e + (E_first + ... + E_k)/Lambda), u1 -> which part of
  * c_j proposes (the beta B_v l part or the f part, adaptive only), u2 -> the
  * candidate (by bound, or uniform over candidates with l > 0), u3 ->
- * acceptance lambda_ij / c_j. */
-static void cstep_atom(orc_sim *s, int i, int32_t phase, double h, const double a[3]) {
+ * acceptance lambda_ij / c_j.
+ * The proposals come from the stream (rstep, rphase) starting at index k0;
+ * the return value is the first index the chain did not use (the one after
+ * the proposal past the end of the half step). Events keep the op's own
+ * (step, phase) labels. */
+static int64_t cstep_atom(orc_sim *s, int i, int32_t phase, double h, const double a[3], int64_t rstep,
+                          int32_t rphase, int64_t k0) {
   double *v = s->v + 3 * i;
   segtab_t T;
   seg_table(s, i, 1, &T);
@@ -618,7 +624,7 @@ static void cstep_atom(orc_sim *s, int i, int32_t phase, double h, const double 
   double aa = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
   double ve[3] = {v[0], v[1], v[2]};
   double te = 0.0;
-  int64_t k = 0;
+  int64_t k = k0;
   int done = 0;
   while (!done) {
     /* epoch: bound from (t_e, v_e) */
@@ -637,12 +643,13 @@ static void cstep_atom(orc_sim *s, int i, int32_t phase, double h, const double 
     for (;; k++) {
       if (k >= MAX_PROPOSALS) { done = 1; for (int q = 0; q < 3; q++) v[q] = ve[q] + tau * a[q]; break; }
       double u[4];
-      draw4(s->seed, s->replica, s->step, i, (uint64_t)phase, k, u);
+      draw4(s->seed, s->replica, rstep, i, (uint64_t)rphase, k, u);
       sumE += -log(u[0]);
       double tk = te + sumE / Lam;
       if (tk > h) {
         for (int q = 0; q < 3; q++) v[q] = ve[q] + tau * a[q];
         done = 1;
+        k++;   /* this proposal's clock decided the end */
         break;
       }
       double vk[3];
@@ -674,7 +681,7 @@ static void cstep_atom(orc_sim *s, int i, int32_t phase, double h, const double 
       if (p > 1.0) s->nviol[i]++;
       if (p > 0.0 && u[3] <= p) {
         int32_t it;
-        double Z = orc_zsample(eta, s->seed, s->replica, s->step, i, phase, k, &it);
+        double Z = orc_zsample(eta, s->seed, s->replica, rstep, i, rphase, k, &it);
         if (it < 0) s->n_zs_overflow++;
         /* Eq. (majvitesse) restricted to atom i (Sec. 3.1) */
         double coef;
@@ -688,6 +695,7 @@ static void cstep_atom(orc_sim *s, int i, int32_t phase, double h, const double 
       }
     }
   }
+  return k;
 }
 
 /* ------------------------------------------------------------- B, A, O */
@@ -725,8 +733,13 @@ void orc_phase_j(orc_sim *s, int32_t phase, double h) {
   for (int i = 0; i < s->n; i++) jstep_atom(s, i, phase, h);
 }
 
-/* a_kind 0: acceleration from short non-bonded + bonded, 1: short non-bonded */
-void orc_phase_c(orc_sim *s, int32_t phase, double h, int a_kind) {
+/* C for every atom. stream 0: own stream (step, phase) from index 0;
+ * STREAM_SAVE: the same, and the first unused index is kept per atom;
+ * STREAM_CONTINUE: the stream (step - 1, ORC_PH_C2) from the kept index.
+ * a_kind 0: acceleration from short non-bonded + bonded, 1: short non-bonded */
+#define STREAM_SAVE 1
+#define STREAM_CONTINUE 2
+static void phase_c(orc_sim *s, int32_t phase, double h, int a_kind, int stream) {
   if (!s->lists_valid) orc_build_lists(s);
   ensure_forces(s, ORC_F_SHORT);
   for (int i = 0; i < s->n; i++) {
@@ -735,13 +748,20 @@ void orc_phase_c(orc_sim *s, int32_t phase, double h, int a_kind) {
       double fc = s->fnb[3 * i + c] + (a_kind == 0 ? s->fb[3 * i + c] : 0.0);
       a[c] = fc / s->me[i];
     }
-    cstep_atom(s, i, phase, h, a);
+    if (stream == STREAM_CONTINUE) {
+      cstep_atom(s, i, phase, h, a, s->step - 1, ORC_PH_C2, s->knext[i]);
+    } else {
+      const int64_t kend = cstep_atom(s, i, phase, h, a, s->step, phase, 0);
+      if (stream == STREAM_SAVE) s->knext[i] = kend;
+    }
   }
 }
 
+void orc_phase_c(orc_sim *s, int32_t phase, double h, int a_kind) { phase_c(s, phase, h, a_kind, 0); }
+
 /* (C') or plain (B) depending on whether Coulomb jumps are on */
-static void c_or_b(orc_sim *s, int32_t phase, double h, int a_kind) {
-  if (s->jc != ORC_JUMP_NONE) orc_phase_c(s, phase, h, a_kind);
+static void c_or_b(orc_sim *s, int32_t phase, double h, int a_kind, int stream) {
+  if (s->jc != ORC_JUMP_NONE) phase_c(s, phase, h, a_kind, stream);
   else kick(s, h, 1, a_kind == 0);
 }
 
@@ -763,13 +783,17 @@ int orc_step_baoab(orc_sim *s, int64_t n) {
   return 0;
 }
 
-/* JUMP: B J A O A J B, or C' J' A O A J' C' (Sec. 2.3, Sec. 3.3). */
+/* JUMP: B J A O A J B, or C' J' A O A J' C' (Sec. 2.3, Sec. 3.3). The
+ * closing C' of a step and the opening C' of the next act at the same
+ * positions; the opening one draws its proposals from the closing one's
+ * stream, from the proposal after the one that ended it. Those proposals
+ * were never used, so they are fresh draws and the law is unchanged. */
 int orc_step_jump(orc_sim *s, int64_t n) {
   double h = 0.5 * s->dt;
   if (!s->lists_valid) orc_build_lists(s);
   ensure_forces(s, ORC_F_SHORT);
   for (int64_t it = 0; it < n; it++) {
-    c_or_b(s, ORC_PH_C1, h, 0);
+    c_or_b(s, ORC_PH_C1, h, 0, STREAM_CONTINUE);
     if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J1, h);
     drift(s, h);
     orc_phase_o(s, s->dt, 0);
@@ -777,7 +801,7 @@ int orc_step_jump(orc_sim *s, int64_t n) {
     maybe_rebuild(s);
     ensure_forces(s, ORC_F_SHORT);
     if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J2, h);
-    c_or_b(s, ORC_PH_C2, h, 0);
+    c_or_b(s, ORC_PH_C2, h, 0, STREAM_SAVE);
     s->step++;
   }
   return 0;
@@ -792,7 +816,7 @@ int orc_step_jump_respa(orc_sim *s, int64_t n_outer) {
   if (!s->lists_valid) orc_build_lists(s);
   ensure_forces(s, ORC_F_SHORT);
   for (int64_t it = 0; it < n_outer; it++) {
-    c_or_b(s, ORC_PH_C1, H, 1);
+    c_or_b(s, ORC_PH_C1, H, 1, 0);
     if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J1, H);
     for (int sub = 0; sub < m; sub++) {
       kick(s, h, 0, 1);
@@ -806,7 +830,7 @@ int orc_step_jump_respa(orc_sim *s, int64_t n_outer) {
     maybe_rebuild(s);
     ensure_forces(s, ORC_F_SHORT);
     if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J2, H);
-    c_or_b(s, ORC_PH_C2, H, 1);
+    c_or_b(s, ORC_PH_C2, H, 1, 0);
     s->step++;
   }
   return 0;
@@ -916,6 +940,7 @@ orc_sim *orc_create(const orc_system *sy, const orc_split *sp, const orc_params 
   s->ell_cu = (double *)xmalloc(sizeof(double) * (size_t)(nt * nt * s->nr));
   s->qmax = (double *)xmalloc(sizeof(double) * (size_t)nt);
   s->nprop = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)n);
+  s->knext = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)n);
   s->nacc = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)n);
   s->nviol = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)n);
   s->hash = (uint64_t *)xmalloc(sizeof(uint64_t) * (size_t)n);
@@ -936,7 +961,7 @@ void orc_destroy(orc_sim *s) {
   free(s->me); free(s->q); free(s->type); free(s->eps); free(s->sig); free(s->bij);
   free(s->bk); free(s->br0); free(s->aijk); free(s->ak); free(s->at0); free(s->xptr);
   free(s->xj); free(s->cptr); free(s->cand); free(s->segst); free(s->ell_lj);
-  free(s->ell_cu); free(s->qmax); free(s->nprop); free(s->nacc); free(s->nviol);
+  free(s->ell_cu); free(s->qmax); free(s->nprop); free(s->knext); free(s->nacc); free(s->nviol);
   free(s->hash); free(s->ev); free(s);
 }
 

@@ -164,9 +164,11 @@ struct ProgBuilder {
   MDProg P;
   bool has_a = false, has_chain_after_a = false;
   ProgBuilder() { memset(&P, 0, sizeof(P)); P.reset_slot = -1; P.disp_slot = 0; }
-  void add(const MDOp &o) {
+  // ops with their own proposal stream get the words (step, phase)
+  void add(MDOp o) {
     if (o.kind == OP_A) has_a = true;
     if ((o.kind == OP_J || o.kind == OP_C) && has_a) has_chain_after_a = true;
+    if (o.stream != MD_STREAM_CONTINUE) { o.rstep = o.step; o.rphase = o.phase; }
     P.ops[P.nops++] = o;
   }
 };
@@ -191,13 +193,18 @@ static void add_J(ProgBuilder &b, int phase, double h, int64_t step) {
   o.step = step;
   b.add(o);
 }
-// (C') when Coulomb jumps are on, otherwise the plain kick it reduces to
-static void add_C_or_B(md_ctx *c, ProgBuilder &b, int phase, double h, int64_t step, int a_nb_only) {
+// (C') when Coulomb jumps are on, otherwise the plain kick it reduces to.
+// stream: 0, MD_STREAM_SAVE, or MD_STREAM_CONTINUE (of the closing C' of the
+// step before, whose words are (step - 1, OP_PHASE_C2))
+static void add_C_or_B(md_ctx *c, ProgBuilder &b, int phase, double h, int64_t step, int a_nb_only,
+                       int stream = 0) {
   if (c->par.jump_coul != MD_JUMP_NONE) {
     MDOp o = op_base(OP_C, h);
     o.phase = phase;
     o.step = step;
     o.flags = a_nb_only;
+    o.stream = stream;
+    if (stream == MD_STREAM_CONTINUE) { o.rstep = step - 1; o.rphase = OP_PHASE_C2; }
     b.add(o);
   } else {
     add_B(b, h, a_nb_only ? 1 : 3);
@@ -217,7 +224,7 @@ static int run_prog(md_ctx *c, ProgBuilder &b) {
   if (c->capturing) {
     // step words become offsets from the device-side base set before each replay
     b.P.dev_step = 1;
-    for (int o = 0; o < b.P.nops; ++o) b.P.ops[o].step -= c->step_rel0;
+    for (int o = 0; o < b.P.nops; ++o) { b.P.ops[o].step -= c->step_rel0; b.P.ops[o].rstep -= c->step_rel0; }
   }
   int cut = 0;
   bool chain = false;
@@ -632,7 +639,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   A(V.srow, (size_t)n * V.cap_s); A(V.scnt, n);
   A(V.frow, (size_t)n * V.cap_f); A(V.fcnt, n);
   A(V.crow, (size_t)n * V.cap_c); A(V.ccnt, n); A(V.segst, (size_t)n * (c->S + 1));
-  A(V.nprop, n); A(V.nacc, n); A(V.nviol, n); A(V.hash, n);
+  A(V.nprop, n); A(V.nacc, n); A(V.nviol, n); A(V.hash, n); A(V.knext, n);
   A(V.ctl, 1);
   V.ev_cap = p->log_events ? (1ll << 22) : 0;
   if (V.ev_cap) A(V.ev, V.ev_cap);
@@ -694,6 +701,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   if (hipMemsetAsync(V.nprop, 0, sizeof(long long) * n, st) != hipSuccess) ok = false;
   if (hipMemsetAsync(V.nacc, 0, sizeof(long long) * n, st) != hipSuccess) ok = false;
   if (hipMemsetAsync(V.nviol, 0, sizeof(long long) * n, st) != hipSuccess) ok = false;
+  if (hipMemsetAsync(V.knext, 0, sizeof(int) * n, st) != hipSuccess) ok = false;
   if (hipMemsetAsync(fnb, 0, sizeof(double4) * n, st) != hipSuccess) ok = false;
   if (hipMemsetAsync(fb, 0, sizeof(double4) * n, st) != hipSuccess) ok = false;
   {
@@ -766,12 +774,15 @@ static int jump_plain(md_ctx *c, int64_t nsteps) {
   const bool lj = c->par.jump_lj == MD_JUMP_BPS;
   for (int64_t it = 0; it <= nsteps; ++it) {
     ProgBuilder b;
+    // The opening C' of a step continues the proposal stream of the closing
+    // C' of the step before, after the proposal that ended it: both act at
+    // the same positions, and those proposals were never used (fresh draws).
     if (it > 0) {                                    // J' C' closing the previous step
       if (lj) add_J(b, OP_PHASE_J2, h, c->step - 1);
-      add_C_or_B(c, b, OP_PHASE_C2, h, c->step - 1, 0);
+      add_C_or_B(c, b, OP_PHASE_C2, h, c->step - 1, 0, MD_STREAM_SAVE);
     }
     if (it < nsteps) {                               // C' J' A O A
-      add_C_or_B(c, b, OP_PHASE_C1, h, c->step, 0);
+      add_C_or_B(c, b, OP_PHASE_C1, h, c->step, 0, MD_STREAM_CONTINUE);
       if (lj) add_J(b, OP_PHASE_J1, h, c->step);
       add_A(b, h);
       add_O(c, b, c->par.dt, 0, c->step);

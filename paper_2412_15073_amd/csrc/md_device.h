@@ -78,8 +78,15 @@ struct MDOp {
   int flags;     // B: bit0 non-bonded, bit1 bonded; C: 0 -> a from nb+bonded, 1 -> nb only
   double h;      // duration
   double c1, c2; // O: exp(-gamma h), sqrt(1 - c1^2)
-  int64_t step;  // random-stream step word
+  int64_t step;  // random-stream step word (and the label of logged events)
+  // J/C proposal stream: words (rstep, rphase); stream 0: from index 0,
+  // 1 (MD_STREAM_SAVE): from 0, first unused index kept per atom,
+  // 2 (MD_STREAM_CONTINUE): from the kept index
+  int64_t rstep;
+  int rphase, stream;
 };
+#define MD_STREAM_SAVE 1
+#define MD_STREAM_CONTINUE 2
 
 enum { OP_B = 1, OP_A = 2, OP_O = 3, OP_J = 4, OP_C = 5, OP_DISP = 6 };
 
@@ -140,6 +147,7 @@ struct MDView {
   // statistics
   long long *nprop, *nacc, *nviol;
   unsigned long long *hash;
+  int *knext;            // [n] first unused proposal index of the last saved C stream
   MDCtl *ctl;
   MDEventDev *ev; long long ev_cap;
   // constants

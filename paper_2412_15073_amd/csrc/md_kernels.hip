@@ -96,7 +96,9 @@ __device__ __forceinline__ double long_grad(const MDView &V, double4 xi, double4
 __device__ __forceinline__ double theta_r(double eta) { return theta_fn(eta); }
 __device__ __forceinline__ float theta_r(float eta) { return theta_fn_f(eta); }
 
-struct AtomStats { long long nprop, nacc, nviol; uint64_t hash; };
+// per-atom statistics of one launch: counts since its start (added to the
+// stored totals at its end) and the running event fingerprint
+struct AtomStats { int nprop, nacc, nviol; uint64_t hash; };
 
 // accepted jump of atom i with partner lj (index within the replica)
 __device__ __forceinline__ void log_jump(const MDView &V, AtomStats &st, int64_t step, int phase,
@@ -348,20 +350,32 @@ __device__ __forceinline__ int ring_add(int s, int d, int M) {
 //    constant acceleration a between jumps plus MRZ jumps of the Coulomb long
 //    part; the bound is re-evaluated after each accepted jump (Sec. 2.4): from
 //    (t_e, v_e), B_v = sqrt(|v_e|^2 + tau^2 |a|^2 + 2 tau (v_e.a)_+), tau = h - t_e.
-// Block (step, i, phase, k): u0 -> E_k, u1 -> bound part (adaptive C),
-// u2 -> candidate, u3 -> acceptance; block (step, i, phase | 1 << 24, k) ->
+// Block (rstep, i, rphase, k): u0 -> E_k, u1 -> bound part (adaptive C),
+// u2 -> candidate, u3 -> acceptance; block (rstep, i, rphase | 1 << 24, k) ->
 // first Z iteration.
+// Ring position: proposals [w0, computed) sit in slots [ws, cs) of the ring.
+// It outlives an op: an op that continues the stream an op of the same
+// launch saved (same positions, same candidates) keeps its ring contents.
+struct RingPos { int w0, ws, computed, cs; bool saved; };
+
 template <int G, int PREC>
 __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
                          double &vx, double &vy, double &vz, double me, double ax_d, double ay_d, double az_d,
                          const MDOp &op, AtomStats &st, const double *L, const double *iL,
                          typename ChainReal<PREC>::T *ring, uint2 *pwords, uint2 *zwords, int2 *jring,
-                         SegL &T) {
+                         SegL &T, RingPos &rp) {
   using R = typename ChainReal<PREC>::T;
   constexpr int M = ring_slots(G);
   const bool isC = op.kind == OP_C;
   const int a = V.type[i];
-  T.build(V, i, a, isC ? 1 : 0, isC ? fabs(xi.w) : 0.0, r);
+  const bool cont = op.stream == MD_STREAM_CONTINUE;
+  if (!(cont && rp.saved)) {
+    // the table of the saved op is the one this op needs (same kind, positions)
+    T.build(V, i, a, isC ? 1 : 0, isC ? fabs(xi.w) : 0.0, r);
+    rp.w0 = rp.computed = cont ? V.knext[i] : 0;
+    rp.ws = rp.cs = 0;
+  }
+  rp.saved = false;
   const int *row = V.crow + (size_t)i * V.cap_c;
   const double inv_nr = 1.0 / (double)V.nr;
   const bool adaptive = isC && (V.jc == MD_JUMP_MRZ_ADAPTIVE);
@@ -370,7 +384,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   const R ax = (R)ax_d, ay = (R)ay_d, az = (R)az_d;
   const R aa = ax * ax + ay * ay + az * az;
   const uint64_t rep = (uint64_t)V.rep[i];
-  const int64_t li = V.loc[i];
+  const int li = V.loc[i];
   const R h = (R)op.h;
   const R vn = sqrt((R)vx * (R)vx + (R)vy * (R)vy + (R)vz * (R)vz);   // J: |v| for the whole op
   // per-op constants of the MRZ rate and kernel (Sec. 2.4)
@@ -380,8 +394,8 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   const R k_coef = adaptive ? R(2) * eps0 / sbm : R(2) * eps0 / ((R(1) + eps0 * eps0) * sbm);
   const R W = (R)T.W, nfr = (R)T.nf;
   int n_counted = 0, n_viol = 0;   // lane-local, reduced over the group at the end
-  int w0 = 0, computed = 0;   // proposal indices (below MD_MAX_PROPOSALS)
-  int ws = 0, cs = 0;         // ring slots of w0 and of computed
+  int &w0 = rp.w0, &computed = rp.computed;   // proposal indices (below MD_MAX_PROPOSALS)
+  int &ws = rp.ws, &cs = rp.cs;               // ring slots of w0 and of computed
   double vex = vx, vey = vy, vez = vz;   // velocity at the last event (FP64 state)
   R te = R(0), base = R(0);
   R tau = h, bBv = R(0), Wb = R(0), Lam = R(0), iLam = R(0);
@@ -428,7 +442,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       if (r < take) {
         const int k = computed + r;
         const int sl = ring_add(cs, r, M);
-        const u32x4 uw = draw4w(V.seed, rep, op.step, li, (uint64_t)op.phase, k);
+        const u32x4 uw = draw4w(V.seed, rep, op.rstep, li, (uint64_t)op.rphase, k);
         // candidates of both branches first, so that their gathers overlap
         double ellb, ellf;
         int pb, pf, sb, sf;
@@ -437,7 +451,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         const double4 xb = X[jb], xf = X[jf];
         const int lb = V.loc[jb], lf = V.loc[jf];
         u32x4 zw;
-        if (isC) zw = draw4w(V.seed, rep, op.step, li, (uint64_t)(uint32_t)op.phase | (1ull << 24), k);
+        if (isC) zw = draw4w(V.seed, rep, op.rstep, li, (uint64_t)(uint32_t)op.rphase | (1ull << 24), k);
         ring[RF_E * M + sl] = (R)(-log(u01(uw.w[0])));
         pwords[sl] = make_uint2(uw.w[1], uw.w[3]);
         double Fx, Fy, Fz;
@@ -542,7 +556,13 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     n_counted += counted ? 1 : 0;
     n_viol += (counted && viol) ? 1 : 0;
     if (first == G) { base = tot; w0 += G; ws = ring_add(ws, G, M); continue; }
-    if (__shfl((int)out, first, G)) { finish(); continue; }
+    if (__shfl((int)out, first, G)) {
+      // the proposal past the end is used up; the stream resumes after it
+      w0 += first + 1;
+      ws = ring_add(ws, first + 1, M);
+      finish();
+      continue;
+    }
     // the accepted proposal's gradient, from the lane that holds it
     const int fs = ring_add(ws, first, M);
     const int fos = __shfl(fo, first, G);
@@ -557,7 +577,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       R Z = __shfl(zown, first, G);
       if (!__shfl((int)zok, first, G)) {
         int ovf;
-        Z = zsample_grp<G, R>(etas, V.seed, rep, op.step, li, op.phase, kstar, r, 1, ovf);
+        Z = zsample_grp<G, R>(etas, V.seed, rep, op.rstep, li, op.rphase, kstar, r, 1, ovf);
         if (ovf && r == 0) atomicAdd(&V.ctl->n_zs_overflow, 1ull);
       }
       const R coef = adaptive ? k_coef * Z / (R(1) + eps0 * eps0 * F2s) : k_coef * Z / sqrt(F2s);
@@ -587,6 +607,10 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   }
   st.nprop += group_sum<G>(n_counted);
   st.nviol += group_sum<G>(n_viol);
+  if (op.stream == MD_STREAM_SAVE) {
+    if (r == 0) V.knext[i] = w0;
+    rp.saved = true;
+  }
 }
 
 // Chain kernel: the position-preserving prefix of a step program (B kicks,
@@ -614,7 +638,7 @@ __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_S
   const double L[3] = {V.box[3 * rp], V.box[3 * rp + 1], V.box[3 * rp + 2]};
   const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
   AtomStats st;
-  st.nprop = V.nprop[i]; st.nacc = V.nacc[i]; st.nviol = V.nviol[i]; st.hash = V.hash[i];
+  st.nprop = 0; st.nacc = 0; st.nviol = 0; st.hash = V.hash[i];
   const double4 fn = V.fnb[i], fb = V.fb[i];
   using R = typename ChainReal<PREC>::T;
   constexpr int M = ring_slots(G);
@@ -631,9 +655,11 @@ __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_S
   SegL T;
   T.attach((double *)(wave_b + APB * RB) + ab * seg_lds_doubles(V.S), V.S);
   const int64_t sbase = P.dev_step ? (int64_t)V.ctl->step_base : 0;
+  RingPos pos{0, 0, 0, 0, false};
   for (int o = 0; o < P.nops; ++o) {
     MDOp op = P.ops[o];
     op.step += sbase;
+    op.rstep += sbase;
     if (op.kind == OP_B) {
       const double fx = ((op.flags & 1) ? fn.x : 0.0) + ((op.flags & 2) ? fb.x : 0.0);
       const double fy = ((op.flags & 1) ? fn.y : 0.0) + ((op.flags & 2) ? fb.y : 0.0);
@@ -646,13 +672,14 @@ __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_S
         ay = (fn.y + (op.flags == 0 ? fb.y : 0.0)) / me;
         az = (fn.z + (op.flags == 0 ? fb.z : 0.0)) / me;
       }
-      chain_op<G, PREC>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, pwords, zwords, jring, T);
+      chain_op<G, PREC>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, pwords, zwords, jring, T,
+                        pos);
     }
   }
   if (r == 0) {
     if (!(isfinite(vx) && isfinite(vy) && isfinite(vz))) atomicAdd(&V.ctl->nonfinite, 1ull);
     V.v[i] = make_double4(vx, vy, vz, me);
-    V.nprop[i] = st.nprop; V.nacc[i] = st.nacc; V.nviol[i] = st.nviol; V.hash[i] = st.hash;
+    V.nprop[i] += st.nprop; V.nacc[i] += st.nacc; V.nviol[i] += st.nviol; V.hash[i] = st.hash;
   }
 }
 
