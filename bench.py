@@ -42,8 +42,8 @@ BYTES_PER_ATOM_LOCAL = 7 * 32   # x (read+write), v (read+write), f_nb, f_b, x_r
 # HBM bytes per launch of the chain kernel from FETCH_SIZE / WRITE_SIZE counters
 # scaled by a 256 MiB copy (profiles/k_chain_water4096_fp64.md), valid for the
 # kernel source whose sha256 starts with the given prefix, default workload only.
-CHAIN_TRAFFIC = {"sha256": "b40319fdc947182a", "bytes": 40183682,
-                 "workload": ("fp64", 4096, 12, 0.5, 0.1)}
+CHAIN_TRAFFIC = {"sha256": "450fbbcbf412f8d7", "bytes": 37723887,
+                 "workload": ("fp64", 4096, 12, 0.5, 0.1, 0, False, 10.0)}
 KERNELS = {0: "k_local (B/A/O updates)", 1: "k_force (short pairs)", 2: "k_bonded", 3: "row rebuild",
            4: "k_chain (J/C jump chains)"}
 
@@ -256,7 +256,8 @@ def main():
         roof = {"bound": "hbm", "achieved": work / avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
-    if dom == 4 and (a.precision, a.n_mol, a.rings, a.skin, a.eps0) == CHAIN_TRAFFIC["workload"]:
+    if dom == 4 and (a.precision, a.n_mol, a.rings, a.skin, a.eps0, a.replicas, a.respa,
+                     a.rc) == CHAIN_TRAFFIC["workload"]:
         import hashlib
         src = os.path.join(ROOT, "paper_2412_15073_amd", "csrc", "md_kernels.hip")
         with open(src, "rb") as fh:
@@ -277,13 +278,15 @@ def main():
         osys = sysm.systems[0] if a.replicas else sysm
         o = OracleSim(osys, split, po)
         ostep = o.step_jump_respa if a.respa else o.step_jump
-        t = time.perf_counter()
-        ostep(1)
-        first = time.perf_counter() - t
-        n_more = max(1, int((a.cpu_seconds - first) / max(first, 1e-3)))
-        t = time.perf_counter()
-        ostep(n_more)
-        el = time.perf_counter() - t
+        ostep(1)   # untimed: builds the oracle's rows
+        # timed: whole steps until the budget is spent
+        n_more, t = 0, time.perf_counter()
+        while True:
+            ostep(1)
+            n_more += 1
+            el = time.perf_counter() - t
+            if el >= a.cpu_seconds:
+                break
         cpu = {"value": ns_per_day(step_ps, n_more, el), "unit": "ns/day", "cores": 1, "kind": "oracle",
                "sample": f"{n_more} {name_j} steps of {'replica 0 of the ensemble, ' if a.replicas else 'the same '}"
                          f"{osys.n_atoms}-atom water system, after 1 untimed step (brute-force O(N^2) pair sums, "

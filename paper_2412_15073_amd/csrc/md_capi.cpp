@@ -433,7 +433,8 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.seed = p->seed;
   // Jump-chain layout. G (lanes per atom), automatic: the most lanes per atom
   // whose waves still fit the device in one round (resident blocks per CU
-  // from the kernel's registers and LDS).
+  // from the kernel's registers and LDS); when none does, 2 (on an ensemble
+  // of 900k atoms, 2 lanes ran faster than 1 or 4).
   std::vector<int> chain_perm;
   {
     const int prec = p->precision, S = V.nt * V.nr;
@@ -441,14 +442,14 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     int g = p->chain_lanes;
     if (g <= 0) {
-      g = 1;
-      for (int cand = 2; cand <= 16; cand *= 2) {
+      g = 2;
+      for (int cand = 4; cand <= 16; cand *= 2) {
         if (chain_lds_bytes_host(cand, S, prec) > 65536) continue;
         int bpc = chain_blocks_per_cu(cand, S, prec, 1);
         if (bpc <= 0) bpc = 4;
         if ((long long)n * cand / 64 <= (long long)ncu * bpc) g = cand;
       }
-      if (chain_lds_bytes_host(g, S, prec) > 65536) g = 2;
+      while (g < 16 && chain_lds_bytes_host(g, S, prec) > 65536) g *= 2;   // fewer atoms per wave
     }
     if (g != 1 && g != 2 && g != 4 && g != 8 && g != 16) { delete c; return fail(nullptr, MD_ERR_ARG, "chain_lanes must be 0, 1, 2, 4, 8 or 16"); }
     if (chain_lds_bytes_host(g, S, prec) > 65536) {

@@ -137,7 +137,8 @@ __device__ __forceinline__ void log_jump_hash_only(AtomStats &st, int64_t step, 
 
 // ring fields (chain real type R, field-major: field f of slot s at f*M + s):
 // clock E, gradient and bound of each branch, and the first Z iteration's
-// velocity-independent part (log u0, log u1, cospi(2 u2), u2). Then, per slot,
+// velocity-independent part (log u0, log u1, cospi(2 u2), u2; with G < 4 the
+// uniforms u0, u1, -, u2 instead). Then, per slot,
 // the raw words (u1, u3) of the proposal block and (u0, u3) of the Z block
 // (uint2 each), and the candidate pair (by-bound, uniform) as int2.
 enum { RF_E = 0, RF_BX, RF_BY, RF_BZ, RF_BL, RF_FX, RF_FY, RF_FZ, RF_FL,
@@ -157,7 +158,9 @@ __host__ __device__ constexpr int ring_bytes(int G, int rsize) { return ring_rby
 // LDS doubles per atom of the segment table for S segments: cumulative
 // weights (S), cumulative counts (S, plus one spare: last usable segment)
 // and starts (S + 1 ints)
-__host__ __device__ constexpr int seg_lds_doubles(int S) { return 3 * S + 1 + (S + 2) / 2; }
+// (with_el: the per-segment bounds too; kept in LDS when G >= 4 lanes share an atom)
+__host__ __device__ constexpr int seg_lds_doubles(int S, bool with_el) { return (with_el ? 2 * S : S) + S + 1; }
+__host__ __device__ constexpr bool seg_el_in_lds(int G) { return G >= 4; }
 
 // wave-scope ordering of LDS writes by some lanes before reads by others
 __device__ __forceinline__ void wave_lds_sync() {
@@ -198,20 +201,28 @@ __device__ __forceinline__ R norm2_nc(R x, R y, R z) {
 // sum n_q l_q and cumulative counts of the candidates whose bound is nonzero.
 // The first segment whose cumulative value exceeds a target always has
 // n_q l_q > 0, so the searches need no validity test.
-// Per-atom segment table in LDS: cumulative weights cw[S], cumulative usable
-// counts cn[S] (+ spare slot: last usable segment), bounds el[S], segment
-// starts st[S + 1].
+// Per-atom segment table in LDS: cumulative weights cw[S], bounds el[S] (or
+// read from the global table with fewer than 4 lanes per atom, where 64 / G
+// tables per wave would cost occupancy), cumulative usable counts cn[S] (+
+// spare slot: last usable segment) and segment starts st[S + 1].
 struct SegL {
-  double *cw, *cn, *el;
-  int *st;
+  double *cw, *el;
+  int *cn, *st;
   int S, top, last, a, coul;   // top: largest power of two <= S
   double W, nf, absq;
 
-  __device__ __forceinline__ void attach(double *base, int S_) {
+  __device__ __forceinline__ void attach(double *base, int S_, bool with_el) {
     S = S_;
     top = 1 << (31 - __clz(S_));
-    cw = base; cn = base + S; el = base + 2 * S + 1;
-    st = (int *)(base + 3 * S + 1);
+    cw = base;
+    el = with_el ? base + S : nullptr;
+    cn = (int *)(base + (with_el ? 2 * S : S));
+    st = cn + S + 1;
+  }
+  // bound of segment sg (the value seg_ell gives); EL: the table holds el
+  template <bool EL>
+  __device__ __forceinline__ double bound(const MDView &V, int sg) const {
+    return EL ? el[sg] : seg_ell(V, a, sg, coul, absq);
   }
   // lane r == 0 of the group writes; every lane reads back the totals
   __device__ __forceinline__ void build(const MDView &V, int i, int a_, int coul_, double absq_, int r) {
@@ -230,35 +241,37 @@ struct SegL {
         w += (double)nq * l;
         if (l > 0.0) c += nq;
         if (nq > 0 && l > 0.0) lst = q;
-        cw[q] = w; cn[q] = (double)c; el[q] = l; st[q + 1] = s1;
+        cw[q] = w; cn[q] = c; st[q + 1] = s1;
+        if (el) el[q] = l;
         s0 = s1;
       }
-      cn[S] = (double)lst;   // spare slot: last usable segment
+      cn[S] = lst;   // spare slot: last usable segment
     }
     wave_lds_sync();
     W = cw[S - 1];
-    nf = cn[S - 1];
-    last = (int)cn[S];
+    nf = (double)cn[S - 1];
+    last = cn[S];
   }
   // Candidates of both branches for one uniform u (the second only if
   // both): by bound (segment by n_q l_q, then uniform inside from the
   // residual) and uniform among those with a nonzero bound. Each segment is
   // the first whose cumulative value exceeds the target (the last usable one
   // past the end), found by two interleaved fixed-step bisections.
-  __device__ __forceinline__ void pick2(double u, bool both, int &pb, double &ellb, int &segb, int &pf,
-                                        double &ellf, int &segf) const {
+  template <bool EL>
+  __device__ __forceinline__ void pick2(const MDView &V, double u, bool both, int &pb, double &ellb, int &segb,
+                                        int &pf, double &ellf, int &segf) const {
     const double tb = u * W, tf = u * nf;
     int qb = 0, qf = 0;
     for (int step = top; step > 0; step >>= 1) {
       const int xb = qb + step, xf = qf + step;
-      const double cb = cw[(xb <= S ? xb : S) - 1], cf = cn[(xf <= S ? xf : S) - 1];
+      const double cb = cw[(xb <= S ? xb : S) - 1], cf = (double)cn[(xf <= S ? xf : S) - 1];
       if (xb <= S && cb <= tb) qb = xb;
       if (xf <= S && cf <= tf) qf = xf;
     }
     {
       const int sg = qb < S ? qb : last;
       const double below = sg > 0 ? cw[sg - 1] : 0.0;
-      const double el_s = el[sg];
+      const double el_s = bound<EL>(V, sg);
       const int base = st[sg], n = st[sg + 1] - base;
       long long idx = (long long)floor((tb - below) / el_s);
       idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
@@ -267,11 +280,11 @@ struct SegL {
     pf = pb; ellf = 0.0; segf = segb;
     if (both) {
       const int sg = qf < S ? qf : last;
-      const double below = sg > 0 ? cn[sg - 1] : 0.0;
+      const double below = sg > 0 ? (double)cn[sg - 1] : 0.0;
       const int base = st[sg], n = st[sg + 1] - base;
       long long idx = (long long)floor(tf - below);
       idx = idx < 0 ? 0 : (idx > n - 1 ? n - 1 : idx);
-      pf = base + (int)idx; ellf = el[sg]; segf = sg;
+      pf = base + (int)idx; ellf = bound<EL>(V, sg); segf = sg;
     }
   }
 };
@@ -366,6 +379,11 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
                          SegL &T, RingPos &rp) {
   using R = typename ChainReal<PREC>::T;
   constexpr int M = ring_slots(G);
+  // The refill computes the velocity-independent part of the first Z
+  // iteration of every proposal when G lanes share an atom (the window would
+  // otherwise repeat it on every lane of the group); with fewer lanes only
+  // the accepted proposals (about half) pay for it, in the window.
+  constexpr bool kZPre = G >= 4;
   const bool isC = op.kind == OP_C;
   const int a = V.type[i];
   const bool cont = op.stream == MD_STREAM_CONTINUE;
@@ -446,7 +464,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         // candidates of both branches first, so that their gathers overlap
         double ellb, ellf;
         int pb, pf, sb, sf;
-        T.pick2(u01(uw.w[2]), adaptive, pb, ellb, sb, pf, ellf, sf);
+        T.pick2<seg_el_in_lds(G)>(V, u01(uw.w[2]), adaptive, pb, ellb, sb, pf, ellf, sf);
         const int jb = row[pb], jf = row[pf];
         const double4 xb = X[jb], xf = X[jf];
         const int lb = V.loc[jb], lf = V.loc[jf];
@@ -467,9 +485,13 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         jring[sl] = make_int2(lb, lf);   // replica-local indices (event hash)
         if (isC) {
           const R zu2 = (R)u01(zw.w[2]);
-          const ZPre<R> zp = z_pre<R>((R)u01(zw.w[0]), (R)u01(zw.w[1]), zu2);
-          ring[RF_ZL0 * M + sl] = zp.l0; ring[RF_ZL1 * M + sl] = zp.l1;
-          ring[RF_ZCP * M + sl] = zp.cp; ring[RF_ZU2 * M + sl] = zu2;
+          if (kZPre) {
+            const ZPre<R> zp = z_pre<R>((R)u01(zw.w[0]), (R)u01(zw.w[1]), zu2);
+            ring[RF_ZL0 * M + sl] = zp.l0; ring[RF_ZL1 * M + sl] = zp.l1; ring[RF_ZCP * M + sl] = zp.cp;
+          } else {
+            ring[RF_ZL0 * M + sl] = (R)u01(zw.w[0]); ring[RF_ZL1 * M + sl] = (R)u01(zw.w[1]);
+          }
+          ring[RF_ZU2 * M + sl] = zu2;
           zwords[sl] = make_uint2(zw.w[0], zw.w[3]);
         }
       }
@@ -540,7 +562,8 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       // sequential path after the group minimum
       if (acc) {
         const uint2 zz = zwords[sl];
-        const ZPre<R> zp{ring[RF_ZL0 * M + sl], ring[RF_ZL1 * M + sl], ring[RF_ZCP * M + sl]};
+        const ZPre<R> zp = kZPre ? ZPre<R>{ring[RF_ZL0 * M + sl], ring[RF_ZL1 * M + sl], ring[RF_ZCP * M + sl]}
+                                 : z_pre<R>(ring[RF_ZL0 * M + sl], ring[RF_ZL1 * M + sl], ring[RF_ZU2 * M + sl]);
         zok = z_accept<R>(eta, zp, (R)u01(zz.x), ring[RF_ZU2 * M + sl], (R)u01(zz.y), zown);
       }
     } else {
@@ -646,14 +669,15 @@ __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_S
   constexpr int RB = ring_bytes(G, (int)sizeof(R));
   // each wave of the block owns one slice: the rings of its APB atoms, then their segment tables
   const int ab = ((int)threadIdx.x & 63) / G;
-  char *wave_b = (char *)lds_chain + ((int)threadIdx.x >> 6) * (APB * RB + APB * 8 * seg_lds_doubles(V.S));
+  constexpr bool kEl = seg_el_in_lds(G);
+  char *wave_b = (char *)lds_chain + ((int)threadIdx.x >> 6) * (APB * RB + APB * 8 * seg_lds_doubles(V.S, kEl));
   char *base_b = wave_b + ab * RB;
   R *ring = (R *)base_b;
   uint2 *pwords = (uint2 *)(base_b + ring_rbytes(G, (int)sizeof(R)));
   uint2 *zwords = pwords + M;
   int2 *jring = (int2 *)(zwords + M);
   SegL T;
-  T.attach((double *)(wave_b + APB * RB) + ab * seg_lds_doubles(V.S), V.S);
+  T.attach((double *)(wave_b + APB * RB) + ab * seg_lds_doubles(V.S, kEl), V.S, kEl);
   const int64_t sbase = P.dev_step ? (int64_t)V.ctl->step_base : 0;
   RingPos pos{0, 0, 0, 0, false};
   for (int o = 0; o < P.nops; ++o) {
@@ -1367,7 +1391,8 @@ __global__ void k_set_step(MDCtl *ctl, long long step) { ctl->step_base = step; 
 
 // LDS bytes of one k_chain wave with G lanes per atom (rsize: bytes of the chain real type)
 static size_t chain_lds_bytes(int G, int S, int rsize = 8) {
-  return (size_t)(64 / G) * ((size_t)ring_bytes(G, rsize) + sizeof(double) * (size_t)seg_lds_doubles(S));
+  return (size_t)(64 / G) *
+         ((size_t)ring_bytes(G, rsize) + sizeof(double) * (size_t)seg_lds_doubles(S, seg_el_in_lds(G)));
 }
 size_t chain_lds_bytes_host(int G, int S, int precision) {
   return chain_lds_bytes(G, S, precision == MD_FP32_MIXED ? 4 : 8);
