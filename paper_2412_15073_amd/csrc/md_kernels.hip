@@ -8,9 +8,10 @@
 //              (Sec. 2.3) and the displacement check; positions are
 //              double-buffered (read one copy, write the other).
 //  k_cell_*    counting sort of atoms into per-replica cells.
-//  k_build     neighbour rows, one wavefront per atom: candidates gathered
-//              from the cell stencil with ballot compaction into LDS, bitonic
-//              sort in LDS, segment starts by binary search.
+//  k_build     neighbour rows, one wavefront per atom: the cell stencil
+//              passes a float distance filter, the survivors the exact FP64
+//              tests; ballot compaction into LDS, bitonic sort, segment starts
+//              by binary search.
 //  k_force     non-bonded pair forces over fixed-capacity rows, SG lanes per
 //              atom, shuffle reduction.
 //  k_bonded    bonds and angles, per atom over its incident terms.
@@ -1022,18 +1023,53 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
   __syncthreads();
   const int total = s_pre[64];
   int span = 0;   // per lane: the span holding its current flat index (indices only grow)
-  auto examine = [&](int f, int &j, double4 &xj) -> bool {
-    if (f >= total) return false;
-    while (s_pre[span + 1] <= f) ++span;
-    const int q = s_beg[span] + (f - s_pre[span]);
-    j = V.cell_atoms[q];
-    xj = V.xcell[q];
-    return true;
-  };
+  // Pass 1: a float distance filter over the whole stencil queues the
+  // cell-array indices of the atoms that may lie within the outer cutoff
+  // (in kc, which pass 2 overwrites only at slots it has already read). The
+  // margin covers the float rounding of the FP64 difference and of the
+  // minimum image with a factor above 8 (positions are not wrapped).
+  const double rcut = (want & 6) ? V.rout : rs_out;
+  const float Lf[3] = {(float)L[0], (float)L[1], (float)L[2]};
+  const float iLf[3] = {(float)iL[0], (float)iL[1], (float)iL[2]};
+  const float margin0 = 1e-3f + 3e-6f * (Lf[0] + Lf[1] + Lf[2]);
+  const float rcf = (float)rcut;
+  int nq = 0;
   for (int base = 0; base < total; base += 64) {
+    const int f = base + lane;
+    bool keep = false;
+    int q = 0;
+    if (f < total) {
+      while (s_pre[span + 1] <= f) ++span;
+      q = s_beg[span] + (f - s_pre[span]);
+      const double4 xj = V.xcell[q];
+      float dx = (float)(xi.x - xj.x), dy = (float)(xi.y - xj.y), dz = (float)(xi.z - xj.z);
+      const float rc_m = rcf + margin0 + 1e-6f * (fabsf(dx) + fabsf(dy) + fabsf(dz));
+      dx -= Lf[0] * rintf(dx * iLf[0]);
+      dy -= Lf[1] * rintf(dy * iLf[1]);
+      dz -= Lf[2] * rintf(dz * iLf[2]);
+      keep = dx * dx + dy * dy + dz * dz < rc_m * rc_m;
+    }
+    const unsigned long long mq = __ballot(keep);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (keep) {
+      const int pos = nq + __popcll(mq & below);
+      if (pos < pc) kc[pos] = (unsigned)q; else over = 1;
+    }
+    nq += __popcll(mq);
+  }
+  const int nqq = min(nq, pc);
+  wave_lds_sync();
+  // Pass 2: exact FP64 decisions for the queued atoms.
+  for (int base = 0; base < nqq; base += 64) {
     int j = -1;
     double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
-    bool ok = examine(base + lane, j, xj);
+    bool ok = base + lane < nqq;
+    if (ok) {
+      const int q = (int)kc[base + lane];
+      j = V.cell_atoms[q];
+      xj = V.xcell[q];
+    }
+    wave_lds_sync();   // every queue slot of this chunk is read before keys overwrite it
     ok = ok && j != i && j != ex[0] && j != ex[1] && j != ex[2] && j != ex[3];
     if (ok && ex_more)
       for (int e = x0 + 4; ok && e < x1; ++e) ok = (V.xj[e] != j);
@@ -1071,7 +1107,7 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
     nsr += __popcll(ms);
   }
   if (nk > capk || nsr > V.cap_s) over = 1;
-  if (__any(over) && lane == 0) atomicMax(&V.ctl->overflow_rows, max(nk, nsr));
+  if (__any(over) && lane == 0) atomicMax(&V.ctl->overflow_rows, max(max(nk, nsr), nq));
   const int nkk = min(nk, min(capk, pc)), nss = min(nsr, min(V.cap_s, ps));
   if (want & 6) {
     __syncthreads();

@@ -223,6 +223,33 @@ def test_graph_replay_matches_oracle(jm, scheme):
     assert g.observables()["n_rebuilds"] == o.n_rebuilds
 
 
+def test_jump_call_grouping_and_graph_chunks_change_nothing(jm):
+    """The opening C' continues the closing C' stream from an index kept per
+    atom on the device: within one launch the ring contents carry over, across
+    launches and graph chunks the stream restarts from that index. One call of
+    7 steps, calls of 2 + 5 steps with 4-step graph chunks (the second call:
+    one chunk, one plain step), and the oracle in one call give the same
+    trajectory and events."""
+    sy, sp = water_small()
+    pa = S.water_params()
+    pa.log_events = 1
+    g1, o = _pair(jm, sy, sp, pa)
+    pa2 = S.water_params()
+    pa2.log_events = 1
+    pa2.graph_steps = 4
+    g2 = jm.Sim(sy, sp, pa2)
+    g1.step_jump(7)
+    g2.step_jump(2)
+    g2.step_jump(5)
+    o.step_jump(7)
+    _compare_state(g1, o)
+    _compare_state(g2, o)
+    _compare_stats(g1, o)
+    _compare_stats(g2, o)
+    np.testing.assert_array_equal(g1.events(), o.events())
+    np.testing.assert_array_equal(g2.events(), o.events())
+
+
 @pytest.mark.parametrize("precision_scheme", ["jump", "baoab"])
 def test_water_4096_full_size_in_bench_configuration(jm, precision_scheme):
     """The benchmark's 4096-molecule water box at full size, in the launch
