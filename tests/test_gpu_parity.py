@@ -98,6 +98,23 @@ def test_long_candidate_rows_and_jumps(jm):
     np.testing.assert_array_equal(g.events(), o.events())
 
 
+def test_partial_waves_in_multi_wave_blocks(jm):
+    """1001 waters (3003 atoms), automatic layout: 8 lanes per atom, type-pure
+    waves of 8 atoms (251 hydrogen and 126 oxygen waves, the last of each
+    type partial), packed two waves per block so that one slot of one block
+    stays idle. 3 JUMP steps: exact events and 1e-9 state."""
+    sy = S.water_box(1001, seed=5, jitter=0.05)
+    sp = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=0.5, n_rings=12)
+    pa = S.water_params(eps0_per_kcal=0.1)
+    pa.log_events = 1
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_jump(3)
+    o.step_jump(3)
+    _compare_state(g, o)
+    _compare_stats(g, o)
+    np.testing.assert_array_equal(g.events(), o.events())
+
+
 def test_jump_lj_trajectory(jm):
     sy, sp = lj_small()
     pa = S.lj_params()
