@@ -44,7 +44,7 @@ BYTES_PER_ATOM_LOCAL = 7 * 32   # x (read+write), v (read+write), f_nb, f_b, x_r
 # kernel source whose sha256 starts with the given prefix, default workload only.
 CHAIN_TRAFFIC = {"sha256": "d6508e636dc6b3c0", "bytes": 37797209,
                  "workload": ("fp64", 4096, 12, 0.5, 0.1, 0, False, 10.0)}
-KERNELS = {0: "k_local (B/A/O updates)", 1: "k_force (short pairs)", 2: "k_bonded", 3: "row rebuild",
+KERNELS = {0: "k_local (B/A/O updates)", 1: "k_force (pairs, with bonded when fused)", 2: "k_bonded (separate)", 3: "row rebuild",
            4: "k_chain (J/C jump chains)"}
 
 

@@ -193,7 +193,7 @@ int md_run_phase(md_ctx *ctx, int32_t which, int32_t phase, double h);
  * returns the total milliseconds and launch count of kernel `kid`
  * (MD_K_* below). */
 #define MD_K_LOCAL 0      /* per-atom B/A/O updates and displacement check */
-#define MD_K_FORCE 1      /* non-bonded pair forces */
+#define MD_K_FORCE 1      /* non-bonded pair forces (with the bonded forces when both are due) */
 #define MD_K_BONDED 2
 #define MD_K_REBUILD 3    /* all neighbour-row kernels of a step */
 #define MD_K_CHAIN 4      /* jump chains (J and C ops, with the kicks between them) */

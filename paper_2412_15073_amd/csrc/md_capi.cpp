@@ -44,6 +44,7 @@ struct md_ctx {
   int rows_valid = 0;          // ROW_* bits valid for the current reference positions
   int64_t since_build = 0;
   int pc = 0, ps = 0;          // LDS key capacities of the row builder
+  bool fuse_forces[2] = {false, false};   // per force kind: bonded blocks appended to the pair launch
   int nbonds = 0, nangles = 0;
   double kB = 1.0;
   std::vector<double> box;
@@ -324,7 +325,7 @@ static int step_rebuild(md_ctx *c, int mode, int64_t step) {
 static int eval_nb(md_ctx *c, int kind) {
   hipEvent_t e0{};
   prof_begin(c, MD_K_FORCE, &e0);
-  HIPCHK(c, launch_force(c->V, Xcur(c), kind, c->stream));
+  HIPCHK(c, launch_force(c->V, Xcur(c), kind, false, c->stream));
   prof_end(c, MD_K_FORCE, e0);
   c->fkind = kind;
   return MD_OK;
@@ -341,13 +342,28 @@ static int eval_bonded(md_ctx *c) {
   return MD_OK;
 }
 
+// pair forces of this kind and bonded forces, in one launch when both are due
+static int eval_forces(md_ctx *c, int kind) {
+  if (c->fkind != kind && !c->fb_valid && c->nbonds + c->nangles > 0 && c->fuse_forces[kind]) {
+    hipEvent_t e0{};
+    prof_begin(c, MD_K_FORCE, &e0);
+    HIPCHK(c, launch_force(c->V, Xcur(c), kind, true, c->stream));
+    prof_end(c, MD_K_FORCE, e0);
+    c->fkind = kind;
+    c->fb_valid = true;
+    return MD_OK;
+  }
+  int rc;
+  if (c->fkind != kind && (rc = eval_nb(c, kind))) return rc;
+  if (!c->fb_valid && (rc = eval_bonded(c))) return rc;
+  return MD_OK;
+}
+
 static int ensure_forces(md_ctx *c, int mode) {
   int rc = ensure_rows(c, rows_for_mode(mode));
   if (rc) return rc;
   int kind = (mode == MODE_JUMP || mode == MODE_JUMP_RESPA) ? 0 : 1;
-  if (c->fkind != kind && (rc = eval_nb(c, kind))) return rc;
-  if (!c->fb_valid && (rc = eval_bonded(c))) return rc;
-  return MD_OK;
+  return eval_forces(c, kind);
 }
 
 // ------------------------------------------------------------ creation
@@ -690,6 +706,8 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   up(d_at0, s->angle_t0, sizeof(double) * s->n_angles);
   up(c->d_rep_off, c->rep_off.data(), sizeof(int) * (nrep + 1));
   up(d_chain_perm, chain_perm.data(), sizeof(int) * chain_perm.size());
+  c->fuse_forces[0] = force_fused_fits(V, 0);
+  c->fuse_forces[1] = force_fused_fits(V, 1);
   {
     std::vector<int> cr(V.ncell_total);
     for (int r = 0; r < nrep; ++r)
@@ -762,7 +780,7 @@ static int baoab_plain(md_ctx *c, int64_t nsteps) {
     if ((rc = run_prog(c, b))) return rc;
     if (it == nsteps) break;
     if ((rc = step_rebuild(c, MODE_BAOAB, c->step))) return rc;
-    if ((rc = eval_nb(c, 1)) || (rc = eval_bonded(c))) return rc;
+    if ((rc = eval_forces(c, 1))) return rc;
     c->step++;
   }
   return MD_OK;
@@ -793,7 +811,7 @@ static int jump_plain(md_ctx *c, int64_t nsteps) {
     if ((rc = run_prog(c, b))) return rc;
     if (it == nsteps) break;
     if ((rc = step_rebuild(c, MODE_JUMP, c->step))) return rc;
-    if ((rc = eval_nb(c, 0)) || (rc = eval_bonded(c))) return rc;
+    if ((rc = eval_forces(c, 0))) return rc;
     c->step++;
   }
   return MD_OK;

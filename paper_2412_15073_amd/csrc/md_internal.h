@@ -18,7 +18,8 @@ size_t chain_lds_bytes_host(int G, int S, int precision);   // dynamic LDS of on
 int chain_blocks_per_cu(int G, int S, int precision, int bw); // resident blocks of bw waves per CU (0: unknown)
 hipError_t launch_rebuild(const MDView &V, const double4 *X, int want, int slot, int forced, int autob,
                           double thr2, int pc, int ps, bool check_only, int count, hipStream_t s);
-hipError_t launch_force(const MDView &V, const double4 *X, int mode, hipStream_t s);
+hipError_t launch_force(const MDView &V, const double4 *X, int mode, bool with_bonded, hipStream_t s);
+bool force_fused_fits(const MDView &V, int mode);   // pair + bonded blocks resident in one round
 hipError_t launch_bonded(const MDView &V, const double4 *X, hipStream_t s);
 hipError_t launch_ke(const MDView &V, double *part, int *nblocks, hipStream_t s);
 hipError_t launch_pair_energy(const MDView &V, const double4 *X, int which, double *es, double *el,

@@ -1134,10 +1134,61 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
 }
 
 // -------------------------------------------------------------- forces
-// MODE 0: -grad chi U over r < r_s (short rows); MODE 1: -grad U over r < r_c (full rows)
+// bonded force on atom i: harmonic bonds and angles over its incident terms
+__device__ __forceinline__ void bonded_atom(const MDView &V, const double4 *__restrict__ X, int i) {
+  const int r = V.rep[i];
+  const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+  const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int e = V.bptr[i]; e < V.bptr[i + 1]; ++e) {
+    int code = V.bterm[e], t = code >> 1;
+    if (!(code & 1)) {
+      int p = V.bond_ij[2 * t], q = V.bond_ij[2 * t + 1];
+      double4 xp = X[p], xq = X[q];
+      double d[3] = {min_img(xp.x - xq.x, L[0], iL[0]), min_img(xp.y - xq.y, L[1], iL[1]),
+                     min_img(xp.z - xq.z, L[2], iL[2])};
+      double b = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      double db = b - V.bond_r0[t];
+      double sgn = (i == p) ? 1.0 : -1.0;
+      for (int c = 0; c < 3; ++c) f[c] += sgn * (-V.bond_k[t] * db * d[c] / b);
+    } else {
+      int p = V.angle_ijk[3 * t], m = V.angle_ijk[3 * t + 1], q = V.angle_ijk[3 * t + 2];
+      double4 xp = X[p], xm = X[m], xq = X[q];
+      double u[3] = {min_img(xp.x - xm.x, L[0], iL[0]), min_img(xp.y - xm.y, L[1], iL[1]),
+                     min_img(xp.z - xm.z, L[2], iL[2])};
+      double w[3] = {min_img(xq.x - xm.x, L[0], iL[0]), min_img(xq.y - xm.y, L[1], iL[1]),
+                     min_img(xq.z - xm.z, L[2], iL[2])};
+      double ru = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      double rw = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+      double cs = (u[0] * w[0] + u[1] * w[1] + u[2] * w[2]) / (ru * rw);
+      cs = fmin(1.0, fmax(-1.0, cs));
+      double th = acos(cs), sn = sqrt(1.0 - cs * cs);
+      double dUdth = V.angle_k[t] * (th - V.angle_t0[t]);
+      for (int c = 0; c < 3; ++c) {
+        double fi = dUdth * (w[c] / (ru * rw) - cs * u[c] / (ru * ru)) / sn;
+        double fk = dUdth * (u[c] / (ru * rw) - cs * w[c] / (rw * rw)) / sn;
+        if (i == p) f[c] += fi;
+        else if (i == q) f[c] += fk;
+        else f[c] -= fi + fk;
+      }
+    }
+  }
+  V.fb[i] = make_double4(f[0], f[1], f[2], 0.0);
+}
+
+// MODE 0: -grad chi U over r < r_s (short rows); MODE 1: -grad U over r < r_c (full rows).
+// BONDED: blocks from nb_pair on compute the bonded forces instead (one atom
+// per lane), so that they run beside the pair blocks in one launch (a
+// separate instantiation: the bonded path's registers would cost the plain
+// pair kernel occupancy).
 // FP32 pair arithmetic with FP64 accumulation (mixed-precision path)
-template <int MODE, int SG>
-__global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__restrict__ X) {
+template <int MODE, int SG, bool BONDED>
+__global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__restrict__ X, int nb_pair) {
+  if (BONDED && (int)blockIdx.x >= nb_pair) {
+    const int ib = ((int)blockIdx.x - nb_pair) * (int)blockDim.x + (int)threadIdx.x;
+    if (ib < V.n) bonded_atom(V, X, ib);
+    return;
+  }
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid / SG, lane = gid % SG;
   double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -1191,8 +1242,13 @@ __global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__rest
   if (i < V.n && lane == 0) V.fnb[i] = make_double4(fx, fy, fz, 0.0);
 }
 
-template <int MODE, int SG>
-__global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restrict__ X) {
+template <int MODE, int SG, bool BONDED>
+__global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restrict__ X, int nb_pair) {
+  if (BONDED && (int)blockIdx.x >= nb_pair) {
+    const int ib = ((int)blockIdx.x - nb_pair) * (int)blockDim.x + (int)threadIdx.x;
+    if (ib < V.n) bonded_atom(V, X, ib);
+    return;
+  }
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid / SG, lane = gid % SG;
   double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -1248,45 +1304,7 @@ __global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restri
 // bonds (k/2)(b-b0)^2 and angles (k/2)(theta-theta0)^2, per atom over incident terms
 __global__ void k_bonded(MDView V, const double4 *__restrict__ X) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= V.n) return;
-  const int r = V.rep[i];
-  const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
-  const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
-  double f[3] = {0.0, 0.0, 0.0};
-  for (int e = V.bptr[i]; e < V.bptr[i + 1]; ++e) {
-    int code = V.bterm[e], t = code >> 1;
-    if (!(code & 1)) {
-      int p = V.bond_ij[2 * t], q = V.bond_ij[2 * t + 1];
-      double4 xp = X[p], xq = X[q];
-      double d[3] = {min_img(xp.x - xq.x, L[0], iL[0]), min_img(xp.y - xq.y, L[1], iL[1]),
-                     min_img(xp.z - xq.z, L[2], iL[2])};
-      double b = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      double db = b - V.bond_r0[t];
-      double sgn = (i == p) ? 1.0 : -1.0;
-      for (int c = 0; c < 3; ++c) f[c] += sgn * (-V.bond_k[t] * db * d[c] / b);
-    } else {
-      int p = V.angle_ijk[3 * t], m = V.angle_ijk[3 * t + 1], q = V.angle_ijk[3 * t + 2];
-      double4 xp = X[p], xm = X[m], xq = X[q];
-      double u[3] = {min_img(xp.x - xm.x, L[0], iL[0]), min_img(xp.y - xm.y, L[1], iL[1]),
-                     min_img(xp.z - xm.z, L[2], iL[2])};
-      double w[3] = {min_img(xq.x - xm.x, L[0], iL[0]), min_img(xq.y - xm.y, L[1], iL[1]),
-                     min_img(xq.z - xm.z, L[2], iL[2])};
-      double ru = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-      double rw = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-      double cs = (u[0] * w[0] + u[1] * w[1] + u[2] * w[2]) / (ru * rw);
-      cs = fmin(1.0, fmax(-1.0, cs));
-      double th = acos(cs), sn = sqrt(1.0 - cs * cs);
-      double dUdth = V.angle_k[t] * (th - V.angle_t0[t]);
-      for (int c = 0; c < 3; ++c) {
-        double fi = dUdth * (w[c] / (ru * rw) - cs * u[c] / (ru * ru)) / sn;
-        double fk = dUdth * (u[c] / (ru * rw) - cs * w[c] / (rw * rw)) / sn;
-        if (i == p) f[c] += fi;
-        else if (i == q) f[c] += fk;
-        else f[c] -= fi + fk;
-      }
-    }
-  }
-  V.fb[i] = make_double4(f[0], f[1], f[2], 0.0);
+  if (i < V.n) bonded_atom(V, X, i);
 }
 
 // --------------------------------------------------------- observables
@@ -1498,16 +1516,48 @@ hipError_t launch_rebuild(const MDView &V, const double4 *X, int want, int slot,
   return hipGetLastError();
 }
 
-hipError_t launch_force(const MDView &V, const double4 *X, int mode, hipStream_t s) {
+// whether the pair-force launch of this mode with the bonded blocks appended
+// is resident in one round (then the bonded blocks hide beside the pair
+// blocks; beyond that their registers cost the pair blocks occupancy)
+bool force_fused_fits(const MDView &V, int mode) {
   const bool f32 = V.precision == MD_FP32_MIXED;
+  const long long nb = mode == 0 ? ((long long)V.n * 8 + 255) / 256 : ((long long)V.n * 16 + 255) / 256;
+  const long long nbb = (V.n + 255) / 256;
+  int dev = 0, ncu = 0, bpc = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+  hipError_t e;
+  if (mode == 0) e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_force_f<0, 8, true>, 256, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_force<0, 8, true>, 256, 0);
+  else e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_force_f<1, 16, true>, 256, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_force<1, 16, true>, 256, 0);
+  return e == hipSuccess && bpc > 0 && nb + nbb <= (long long)ncu * bpc;
+}
+
+hipError_t launch_force(const MDView &V, const double4 *X, int mode, bool with_bonded, hipStream_t s) {
+  const bool f32 = V.precision == MD_FP32_MIXED;
+  const int nbb = with_bonded ? (V.n + 255) / 256 : 0;   // bonded blocks after the pair blocks
+  const dim3 blk(256);
   if (mode == 0) {
-    int nb = (int)(((long long)V.n * 8 + 255) / 256);
-    if (f32) hipLaunchKernelGGL((k_force_f<0, 8>), dim3(nb), dim3(256), 0, s, V, X);
-    else hipLaunchKernelGGL((k_force<0, 8>), dim3(nb), dim3(256), 0, s, V, X);
+    const int nb = (int)(((long long)V.n * 8 + 255) / 256);
+    const dim3 grid(nb + nbb);
+    if (f32) {
+      if (with_bonded) hipLaunchKernelGGL((k_force_f<0, 8, true>), grid, blk, 0, s, V, X, nb);
+      else hipLaunchKernelGGL((k_force_f<0, 8, false>), grid, blk, 0, s, V, X, nb);
+    } else {
+      if (with_bonded) hipLaunchKernelGGL((k_force<0, 8, true>), grid, blk, 0, s, V, X, nb);
+      else hipLaunchKernelGGL((k_force<0, 8, false>), grid, blk, 0, s, V, X, nb);
+    }
   } else {
-    int nb = (int)(((long long)V.n * 16 + 255) / 256);
-    if (f32) hipLaunchKernelGGL((k_force_f<1, 16>), dim3(nb), dim3(256), 0, s, V, X);
-    else hipLaunchKernelGGL((k_force<1, 16>), dim3(nb), dim3(256), 0, s, V, X);
+    const int nb = (int)(((long long)V.n * 16 + 255) / 256);
+    const dim3 grid(nb + nbb);
+    if (f32) {
+      if (with_bonded) hipLaunchKernelGGL((k_force_f<1, 16, true>), grid, blk, 0, s, V, X, nb);
+      else hipLaunchKernelGGL((k_force_f<1, 16, false>), grid, blk, 0, s, V, X, nb);
+    } else {
+      if (with_bonded) hipLaunchKernelGGL((k_force<1, 16, true>), grid, blk, 0, s, V, X, nb);
+      else hipLaunchKernelGGL((k_force<1, 16, false>), grid, blk, 0, s, V, X, nb);
+    }
   }
   return hipGetLastError();
 }
