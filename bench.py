@@ -40,9 +40,10 @@ FLOP_PER_FULL_PAIR = 60
 FLOP_PER_PROPOSAL = 93
 BYTES_PER_ATOM_LOCAL = 7 * 32   # x (read+write), v (read+write), f_nb, f_b, x_ref reads
 # HBM bytes per launch of the chain kernel from FETCH_SIZE / WRITE_SIZE counters
-# scaled by a 256 MiB copy (profiles/k_chain_water4096_fp64.md), valid for the
-# kernel source whose sha256 starts with the given prefix, default workload only.
-CHAIN_TRAFFIC = {"sha256": "d6508e636dc6b3c0", "bytes": 37797209,
+# scaled by a 256 MiB copy (profiles/k_chain_water4096_fp64.md), valid while the
+# sha256 of the chain kernel's sources (md_chain.hip, then md_device.h) starts
+# with the given prefix, default workload only.
+CHAIN_TRAFFIC = {"sha256": "a88b87d79f54b034", "bytes": 37797209,
                  "workload": ("fp64", 4096, 12, 0.5, 0.1, 0, False, 10.0)}
 KERNELS = {0: "k_local (B/A/O updates)", 1: "k_force (pairs, with bonded when fused)", 2: "k_bonded (separate)", 3: "row rebuild",
            4: "k_chain (J/C jump chains)"}
@@ -259,10 +260,12 @@ def main():
     if dom == 4 and (a.precision, a.n_mol, a.rings, a.skin, a.eps0, a.replicas, a.respa,
                      a.rc) == CHAIN_TRAFFIC["workload"]:
         import hashlib
-        src = os.path.join(ROOT, "paper_2412_15073_amd", "csrc", "md_kernels.hip")
-        with open(src, "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest().startswith(CHAIN_TRAFFIC["sha256"]):
-                roof["traffic"] = CHAIN_TRAFFIC["bytes"]
+        h = hashlib.sha256()
+        for f in ("md_chain.hip", "md_device.h"):
+            with open(os.path.join(ROOT, "paper_2412_15073_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest().startswith(CHAIN_TRAFFIC["sha256"]):
+            roof["traffic"] = CHAIN_TRAFFIC["bytes"]
     roof["kernel"] = KERNELS[dom]
     roof["avg_launch_us"] = avg_s * 1e6
     roof["launches"] = launches

@@ -162,6 +162,13 @@ struct MDView {
   uint64_t seed;
 };
 
+// wave-scope ordering of LDS writes by some lanes before reads by others
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // -------------------------------------------------------------- geometry
 __device__ __forceinline__ double min_img(double d, double L, double iL) {
   return d - L * rint(d * iL);
