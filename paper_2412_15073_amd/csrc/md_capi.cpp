@@ -639,6 +639,8 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   A(d_type, n); A(d_rep, n); A(d_loc, n); A(d_cdim, 3 * nrep); A(d_coff, nrep + 1);
   A(d_box, 3 * nrep); A(d_c12, nt * nt); A(d_c6, nt * nt); A(d_shift, nt * nt);
   A(d_elj, nt * nt * nr); A(d_ecu, nt * nt * nr); A(d_qmax, nt); A(d_qseg, nt * nr);
+  int *d_tact;
+  A(d_tact, 2 * nt);
   int *d_xptr = nullptr, *d_xj = nullptr;
   if (s->excl_ptr) { A(d_xptr, n + 1); A(d_xj, std::max(1, s->excl_ptr[n])); }
   int *d_bptr, *d_bterm, *d_bij, *d_aijk;
@@ -691,6 +693,15 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
     std::vector<double> qseg(nt * nr);   // max |q| of the type of each segment
     for (int sg = 0; sg < nt * nr; ++sg) qseg[sg] = qmax[sg / nr];
     up(d_qseg, qseg.data(), sizeof(double) * nt * nr);
+    // per type: whether any LJ / Coulomb segment bound is nonzero (otherwise
+    // the J / C chains of its atoms propose nothing)
+    std::vector<int> tact(2 * nt, 0);
+    for (int a = 0; a < nt; ++a)
+      for (int sg = 0; sg < nt * nr; ++sg) {
+        if (ell_lj[a * nt * nr + sg] > 0.0) tact[2 * a] = 1;
+        if (qseg[sg] * ell_cu[a * nt * nr + sg] > 0.0) tact[2 * a + 1] = 1;
+      }
+    up(d_tact, tact.data(), sizeof(int) * 2 * nt);
   }
   if (s->excl_ptr) {
     up(d_xptr, s->excl_ptr, sizeof(int) * (n + 1));
@@ -733,6 +744,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.x0 = x0; V.x1 = x1; V.v = v; V.fnb = fnb; V.fb = fb; V.xref = xref;
   V.type = d_type; V.rep = d_rep; V.loc = d_loc; V.box = d_box;
   V.c12 = d_c12; V.c6 = d_c6; V.ljshift = d_shift; V.ell_lj = d_elj; V.ell_cu = d_ecu; V.qmax = d_qmax; V.qseg = d_qseg;
+  V.type_active = d_tact;
   V.xptr = d_xptr; V.xj = d_xj; V.bptr = d_bptr; V.bterm = d_bterm;
   V.bond_ij = d_bij; V.bond_k = d_bk; V.bond_r0 = d_br0;
   V.angle_ijk = d_aijk; V.angle_k = d_ak; V.angle_t0 = d_at0;

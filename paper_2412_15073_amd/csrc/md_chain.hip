@@ -207,26 +207,34 @@ struct SegL {
   __device__ __forceinline__ double bound(const MDView &V, int sg) const {
     return EL ? el[sg] : seg_ell(V, a, sg, coul, absq);
   }
-  // lane r == 0 of the group writes; every lane reads back the totals
+  // a table with no usable segment (no proposals), left untouched in LDS
+  __device__ __forceinline__ void set_empty(int a_, int coul_, double absq_) {
+    a = a_; coul = coul_; absq = absq_;
+    W = 0.0; nf = 0.0; last = -1;
+  }
+  // The group's G lanes gather the segment starts and bounds in parallel;
+  // lane r == 0 then forms the running sums in segment order from LDS, and
+  // every lane reads back the totals.
+  template <int G>
   __device__ __forceinline__ void build(const MDView &V, int i, int a_, int coul_, double absq_, int r) {
     a = a_; coul = coul_; absq = absq_;
     wave_lds_sync();   // earlier reads of the table by the group are complete
+    const int *sst = V.segst + (size_t)i * (S + 1);
+    for (int q = r; q <= S; q += G) st[q] = sst[q];
+    for (int q = r; q < S; q += G) cw[q] = seg_ell(V, a, q, coul, absq);   // bound; running sum below
+    wave_lds_sync();
     if (r == 0) {
-      const int *sst = V.segst + (size_t)i * (S + 1);
       double w = 0.0;
       int c = 0, lst = -1;
-      int s0 = sst[0];
-      st[0] = s0;
+#pragma unroll 4
       for (int q = 0; q < S; ++q) {
-        const int s1 = sst[q + 1];
-        const double l = seg_ell(V, a, q, coul, absq);
-        const int nq = s1 - s0;
+        const double l = cw[q];
+        const int nq = st[q + 1] - st[q];
         w += (double)nq * l;
         if (l > 0.0) c += nq;
         if (nq > 0 && l > 0.0) lst = q;
-        cw[q] = w; cn[q] = c; st[q + 1] = s1;
+        cw[q] = w; cn[q] = c;
         if (el) el[q] = l;
-        s0 = s1;
       }
       cn[S] = lst;   // spare slot: last usable segment
     }
@@ -372,7 +380,10 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   const bool cont = op.stream == MD_STREAM_CONTINUE;
   if (!(cont && rp.saved)) {
     // the table of the saved op is the one this op needs (same kind, positions)
-    T.build(V, i, a, isC ? 1 : 0, isC ? fabs(xi.w) : 0.0, r);
+    const double absq = isC ? fabs(xi.w) : 0.0;
+    const bool active = V.type_active[2 * a + (isC ? 1 : 0)] && (!isC || absq > 0.0);
+    if (__any(active)) T.build<G>(V, i, a, isC ? 1 : 0, absq, r);   // a whole wave or none builds
+    else T.set_empty(a, isC ? 1 : 0, absq);
     rp.w0 = rp.computed = cont ? V.knext[i] : 0;
     rp.ws = rp.cs = 0;
   }

@@ -126,6 +126,7 @@ struct MDView {
   const double *ell_lj, *ell_cu;        // [nt*nt*nr] bound per unit (Coulomb: per unit charge product)
   const double *qmax;                   // [nt]
   const double *qseg;                   // [nt*nr] qmax of the type of segment sg
+  const int *type_active;               // [2*nt] type has a nonzero LJ / Coulomb segment bound
   // exclusions and bonded incidence
   const int *xptr, *xj;
   const int *bptr, *bterm;              // per atom: term code (idx << 1 | is_angle)
