@@ -809,14 +809,16 @@ int orc_step_jump(orc_sim *s, int64_t n) {
 
 /* JUMP-RESPA (Sec. 2.3.2 and Sec. 3.3): bonded forces at the inner step dt,
  * short non-bonded forces and all jumps at the outer step n*dt. Inner steps
- * are B_b A O A B_b; the O draw carries the inner index. */
+ * are B_b A O A B_b; the O draw carries the inner index. As in JUMP, the
+ * opening C' continues the stream of the closing C' of the outer step before
+ * (both act at the same positions). */
 int orc_step_jump_respa(orc_sim *s, int64_t n_outer) {
   int m = s->respa_inner > 0 ? s->respa_inner : 1;
   double H = 0.5 * s->dt * m, h = 0.5 * s->dt;
   if (!s->lists_valid) orc_build_lists(s);
   ensure_forces(s, ORC_F_SHORT);
   for (int64_t it = 0; it < n_outer; it++) {
-    c_or_b(s, ORC_PH_C1, H, 1, 0);
+    c_or_b(s, ORC_PH_C1, H, 1, STREAM_CONTINUE);
     if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J1, H);
     for (int sub = 0; sub < m; sub++) {
       kick(s, h, 0, 1);
@@ -830,7 +832,7 @@ int orc_step_jump_respa(orc_sim *s, int64_t n_outer) {
     maybe_rebuild(s);
     ensure_forces(s, ORC_F_SHORT);
     if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J2, H);
-    c_or_b(s, ORC_PH_C2, H, 1, 0);
+    c_or_b(s, ORC_PH_C2, H, 1, STREAM_SAVE);
     s->step++;
   }
   return 0;

@@ -903,7 +903,7 @@ static int respa(md_ctx *c, int64_t n_outer, bool jump) {
       add_B(b, h, 2);
       if (jump) {
         if (lj) add_J(b, OP_PHASE_J2, H, c->step - 1);
-        add_C_or_B(c, b, OP_PHASE_C2, H, c->step - 1, 1);
+        add_C_or_B(c, b, OP_PHASE_C2, H, c->step - 1, 1, MD_STREAM_SAVE);
       } else {
         add_B(b, H, 1);
       }
@@ -911,7 +911,7 @@ static int respa(md_ctx *c, int64_t n_outer, bool jump) {
     if (it == n_outer) { if ((rc = run_prog(c, b))) return rc; break; }
     // start of this outer step, fused with the first inner B_b A O A
     if (jump) {
-      add_C_or_B(c, b, OP_PHASE_C1, H, c->step, 1);
+      add_C_or_B(c, b, OP_PHASE_C1, H, c->step, 1, MD_STREAM_CONTINUE);   // as in jump_plain
       if (lj) add_J(b, OP_PHASE_J1, H, c->step);
     } else {
       add_B(b, H, 1);

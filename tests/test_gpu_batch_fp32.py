@@ -117,14 +117,17 @@ def test_gpu_c_step_mean_kick_equals_long_force(jm, precision):
     assert st.chi2.sf((z * z).sum(), z.size) > 1e-3
 
 
-def test_fp32_jump_run_is_stable_and_close(jm):
+@pytest.mark.parametrize("lanes", [0, 2])
+def test_fp32_jump_run_is_stable_and_close(jm, lanes):
     """100 FP32-mixed JUMP steps: finite, same temperature and proposal rate
-    as the FP64 path within statistical noise."""
+    as the FP64 path within statistical noise; automatic lanes, and 2 lanes
+    per atom (the layout of large ensembles)."""
     sy, sp = water_small()
     out = {}
     for prec in (S.FP64, S.FP32_MIXED):
         pa = S.water_params()
         pa.precision = prec
+        pa.chain_lanes = lanes
         g = jm.Sim(sy, sp, pa)
         g.step_jump(100)
         obs = g.observables(pe=True)

@@ -199,6 +199,13 @@ def test_jump_results_do_not_depend_on_call_grouping():
     np.testing.assert_array_equal(va, vb)
     np.testing.assert_array_equal(a.events(), b.events())
     assert len(a.events()) > 0
+    pa.respa_inner = 3
+    a, b = _oracle(sy, sp, pa), _oracle(sy, sp, pa)
+    a.step_jump_respa(4)
+    for n in (1, 3):
+        b.step_jump_respa(n)
+    np.testing.assert_array_equal(a.state()[1], b.state()[1])
+    np.testing.assert_array_equal(a.events(), b.events())
 
 
 def test_newton_third_law():
