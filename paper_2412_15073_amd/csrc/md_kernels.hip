@@ -279,8 +279,12 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
                                               int forced, int autob, double thr2, int pc, int ps) {
   if (!rebuild_now(V, slot, forced, autob, thr2, V.rep[blockIdx.x])) return;
   extern __shared__ unsigned lds[];
-  unsigned *kc = lds;       // candidate or full keys [pc]
-  unsigned *ks = lds + pc;  // short keys [ps]
+  // candidate or full keys [pc], and the pass-1 queue of stencil atoms, which
+  // also holds the atom itself, its excluded partners and the margin band:
+  // 64 slots more; then the short keys [ps]
+  unsigned *kc = lds;
+  const int pq = pc + 64;
+  unsigned *ks = lds + pq;
   const int i = blockIdx.x, lane = threadIdx.x;
   const double4 xi = X[i];
   const int r = V.rep[i];
@@ -362,11 +366,11 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     if (keep) {
       const int pos = nq + __popcll(mq & below);
-      if (pos < pc) kc[pos] = (unsigned)q; else over = 1;
+      if (pos < pq) kc[pos] = (unsigned)q; else over = 1;
     }
     nq += __popcll(mq);
   }
-  const int nqq = min(nq, pc);
+  const int nqq = min(nq, pq);
   wave_lds_sync();
   // Pass 2: exact FP64 decisions for the queued atoms.
   for (int base = 0; base < nqq; base += 64) {
@@ -768,7 +772,7 @@ hipError_t launch_rebuild(const MDView &V, const double4 *X, int want, int slot,
   CHK(hipGetLastError());
   hipLaunchKernelGGL(k_cell_scatter, dim3(nb), dim3(256), 0, s, V, slot, forced, autob, thr2);
   CHK(hipGetLastError());
-  size_t lds = sizeof(unsigned) * (size_t)(pc + ps);
+  size_t lds = sizeof(unsigned) * (size_t)(pc + 64 + ps);   // keys + queue margin, short keys
   hipLaunchKernelGGL(k_build, dim3(V.n), dim3(64), lds, s, V, X, want, slot, forced, autob, thr2, pc, ps);
   return hipGetLastError();
 }

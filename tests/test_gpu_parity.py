@@ -115,6 +115,26 @@ def test_partial_waves_in_multi_wave_blocks(jm):
     np.testing.assert_array_equal(g.events(), o.events())
 
 
+def test_two_particle_system(jm):
+    """The smallest system on which both jump kinds act: two like charges with
+    LJ cores (one partial wave, rows of one candidate, a single cell per
+    dimension pair of the stencil). 3000 JUMP steps (BPS on the LJ long part,
+    adaptive MRZ on the Coulomb one): exact events, 1e-9 state."""
+    sy = S.two_charges()
+    sp = S.Split(r_s=3.0, r_c=5.0, switch_width=0.5, skin=0.3, coulomb_alpha=0.2)
+    pa = S.Params(dt=0.005, gamma=2.0, kT=0.722, seed=3, jump_lj=S.JUMP_BPS,
+                  jump_coul=S.JUMP_MRZ_ADAPTIVE, eps=0.5)
+    pa.log_events = 1
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_jump(3000)
+    o.step_jump(3000)
+    _compare_state(g, o)
+    _compare_stats(g, o)
+    ev = o.events()
+    assert len(ev) > 10
+    np.testing.assert_array_equal(g.events(), ev)
+
+
 def test_jump_lj_trajectory(jm):
     sy, sp = lj_small()
     pa = S.lj_params()
