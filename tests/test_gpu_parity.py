@@ -135,6 +135,28 @@ def test_two_particle_system(jm):
     np.testing.assert_array_equal(g.events(), ev)
 
 
+def test_neutral_atoms_and_no_lj(jm):
+    """Ion lattice with every fifth site a neutral third type and no LJ: the
+    neutral atoms' C chains and every J chain have no usable bound (their
+    segment tables are skipped), the charged atoms jump. 50 JUMP steps:
+    exact events, 1e-9 state."""
+    sy = S.ion_lattice(4, 3.3, jitter=0.1, neutral_every=5)
+    sp = S.Split(r_s=3.0, r_c=5.0, switch_width=1.0, skin=0.3, coulomb_alpha=0.2, n_rings=3,
+                 ring_width=(5.3 - 1.7) / 3)
+    pa = S.Params(dt=0.01, gamma=1.0, kT=1.0, seed=5, jump_lj=S.JUMP_BPS, jump_coul=S.JUMP_MRZ_ADAPTIVE, eps=0.3)
+    pa.log_events = 1
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_jump(50)
+    o.step_jump(50)
+    _compare_state(g, o)
+    _compare_stats(g, o)
+    ev = o.events()
+    assert len(ev) > 0
+    np.testing.assert_array_equal(g.events(), ev)
+    neutral = np.asarray(sy.charge) == 0.0
+    assert (o.atom_stats()["n_prop"][neutral] == 0).all()
+
+
 def test_jump_lj_trajectory(jm):
     sy, sp = lj_small()
     pa = S.lj_params()
