@@ -149,8 +149,16 @@ __host__ __device__ constexpr int ring_bytes(int G, int rsize) { return ring_rby
 // weights (S), cumulative counts (S, plus one spare: last usable segment)
 // and starts (S + 1 ints)
 // (with_el: the per-segment bounds too; kept in LDS when G >= 4 lanes share an atom)
-__host__ __device__ constexpr int seg_lds_doubles(int S, bool with_el) { return (with_el ? 2 * S : S) + S + 1; }
+// cw, [el,] then cn and st (32-bit with G >= 4; 16-bit below, where 64 / G
+// tables per wave bound occupancy; row positions stay below 8192)
+__host__ __device__ constexpr int seg_count_bytes(int G) { return G >= 4 ? 4 : 2; }
+__host__ __device__ constexpr int seg_lds_doubles(int S, int G) {
+  return (G >= 4 ? 2 * S : S) + (2 * seg_count_bytes(G) * (S + 1) + 7) / 8;
+}
 __host__ __device__ constexpr bool seg_el_in_lds(int G) { return G >= 4; }
+template <int G> struct SegCount { using T = int; };
+template <> struct SegCount<1> { using T = unsigned short; };
+template <> struct SegCount<2> { using T = unsigned short; };
 
 // Reductions over the G lanes of a group (G <= 16, groups aligned in the
 // wave) with DPP lane permutations: swap neighbours, swap pairs, mirror
@@ -187,10 +195,12 @@ __device__ __forceinline__ R norm2_nc(R x, R y, R z) {
 // Per-atom segment table in LDS: cumulative weights cw[S], bounds el[S] (or
 // read from the global table with fewer than 4 lanes per atom, where 64 / G
 // tables per wave would cost occupancy), cumulative usable counts cn[S] (+
-// spare slot: last usable segment) and segment starts st[S + 1].
+// spare slot: last usable segment + 1) and segment starts st[S + 1], of
+// integer type CT (rows hold at most 8192 candidates).
+template <typename CT>
 struct SegL {
   double *cw, *el;
-  int *cn, *st;
+  CT *cn, *st;
   int S, top, last, a, coul;   // top: largest power of two <= S
   double W, nf, absq;
 
@@ -199,7 +209,7 @@ struct SegL {
     top = 1 << (31 - __clz(S_));
     cw = base;
     el = with_el ? base + S : nullptr;
-    cn = (int *)(base + (with_el ? 2 * S : S));
+    cn = (CT *)(base + (with_el ? 2 * S : S));
     st = cn + S + 1;
   }
   // bound of segment sg (the value seg_ell gives); EL: the table holds el
@@ -220,7 +230,7 @@ struct SegL {
     a = a_; coul = coul_; absq = absq_;
     wave_lds_sync();   // earlier reads of the table by the group are complete
     const int *sst = V.segst + (size_t)i * (S + 1);
-    for (int q = r; q <= S; q += G) st[q] = sst[q];
+    for (int q = r; q <= S; q += G) st[q] = (CT)sst[q];
     for (int q = r; q < S; q += G) cw[q] = seg_ell(V, a, q, coul, absq);   // bound; running sum below
     wave_lds_sync();
     if (r == 0) {
@@ -229,19 +239,19 @@ struct SegL {
 #pragma unroll 4
       for (int q = 0; q < S; ++q) {
         const double l = cw[q];
-        const int nq = st[q + 1] - st[q];
+        const int nq = (int)st[q + 1] - (int)st[q];
         w += (double)nq * l;
         if (l > 0.0) c += nq;
         if (nq > 0 && l > 0.0) lst = q;
-        cw[q] = w; cn[q] = c;
+        cw[q] = w; cn[q] = (CT)c;
         if (el) el[q] = l;
       }
-      cn[S] = lst;   // spare slot: last usable segment
+      cn[S] = (CT)(lst + 1);   // spare slot: last usable segment + 1
     }
     wave_lds_sync();
     W = cw[S - 1];
     nf = (double)cn[S - 1];
-    last = cn[S];
+    last = (int)cn[S] - 1;
   }
   // Candidates of both branches for one uniform u (the second only if
   // both): by bound (segment by n_q l_q, then uniform inside from the
@@ -367,7 +377,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
                          double &vx, double &vy, double &vz, double me, double ax_d, double ay_d, double az_d,
                          const MDOp &op, AtomStats &st, const double *L, const double *iL,
                          typename ChainReal<PREC>::T *ring, uint2 *pwords, uint2 *zwords, int2 *jring,
-                         SegL &T, RingPos &rp) {
+                         SegL<typename SegCount<G>::T> &T, RingPos &rp) {
   using R = typename ChainReal<PREC>::T;
   constexpr int M = ring_slots(G);
   // The refill computes the velocity-independent part of the first Z
@@ -382,7 +392,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     // the table of the saved op is the one this op needs (same kind, positions)
     const double absq = isC ? fabs(xi.w) : 0.0;
     const bool active = V.type_active[2 * a + (isC ? 1 : 0)] && (!isC || absq > 0.0);
-    if (__any(active)) T.build<G>(V, i, a, isC ? 1 : 0, absq, r);   // a whole wave or none builds
+    if (__any(active)) T.template build<G>(V, i, a, isC ? 1 : 0, absq, r);   // a whole wave or none builds
     else T.set_empty(a, isC ? 1 : 0, absq);
     rp.w0 = rp.computed = cont ? V.knext[i] : 0;
     rp.ws = rp.cs = 0;
@@ -458,7 +468,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         // candidates of both branches first, so that their gathers overlap
         double ellb, ellf;
         int pb, pf, sb, sf;
-        T.pick2<seg_el_in_lds(G)>(V, u01(uw.w[2]), adaptive, pb, ellb, sb, pf, ellf, sf);
+        T.template pick2<seg_el_in_lds(G)>(V, u01(uw.w[2]), adaptive, pb, ellb, sb, pf, ellf, sf);
         const int jb = row[pb], jf = row[pf];
         const double4 xb = X[jb], xf = X[jf];
         const int lb = V.loc[jb], lf = V.loc[jf];
@@ -664,14 +674,14 @@ __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_S
   // each wave of the block owns one slice: the rings of its APB atoms, then their segment tables
   const int ab = ((int)threadIdx.x & 63) / G;
   constexpr bool kEl = seg_el_in_lds(G);
-  char *wave_b = (char *)lds_chain + ((int)threadIdx.x >> 6) * (APB * RB + APB * 8 * seg_lds_doubles(V.S, kEl));
+  char *wave_b = (char *)lds_chain + ((int)threadIdx.x >> 6) * (APB * RB + APB * 8 * seg_lds_doubles(V.S, G));
   char *base_b = wave_b + ab * RB;
   R *ring = (R *)base_b;
   uint2 *pwords = (uint2 *)(base_b + ring_rbytes(G, (int)sizeof(R)));
   uint2 *zwords = pwords + M;
   int2 *jring = (int2 *)(zwords + M);
-  SegL T;
-  T.attach((double *)(wave_b + APB * RB) + ab * seg_lds_doubles(V.S, kEl), V.S, kEl);
+  SegL<typename SegCount<G>::T> T;
+  T.attach((double *)(wave_b + APB * RB) + ab * seg_lds_doubles(V.S, G), V.S, kEl);
   const int64_t sbase = P.dev_step ? (int64_t)V.ctl->step_base : 0;
   RingPos pos{0, 0, 0, 0, false};
   for (int o = 0; o < P.nops; ++o) {
@@ -705,7 +715,7 @@ __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_S
 // LDS bytes of one k_chain wave with G lanes per atom (rsize: bytes of the chain real type)
 static size_t chain_lds_bytes(int G, int S, int rsize = 8) {
   return (size_t)(64 / G) *
-         ((size_t)ring_bytes(G, rsize) + sizeof(double) * (size_t)seg_lds_doubles(S, seg_el_in_lds(G)));
+         ((size_t)ring_bytes(G, rsize) + sizeof(double) * (size_t)seg_lds_doubles(S, G));
 }
 size_t chain_lds_bytes_host(int G, int S, int precision) {
   return chain_lds_bytes(G, S, precision == MD_FP32_MIXED ? 4 : 8);
