@@ -104,8 +104,10 @@ typedef struct {
   double kT;            /* energy */
   uint64_t seed;        /* Philox4x64-10 key word 0; key word 1 = replica index */
   int32_t jump_lj;      /* MD_JUMP_NONE or MD_JUMP_BPS (J step, Alg. 5) */
-  int32_t jump_coul;    /* MD_JUMP_NONE, MD_JUMP_MRZ_CONST or MD_JUMP_MRZ_ADAPTIVE (C step, Alg. 4) */
-  double eps;           /* eps (constant) or eps0 (adaptive, 1/force units) */
+  int32_t jump_coul;    /* MD_JUMP_NONE, MD_JUMP_MRZ_CONST or MD_JUMP_MRZ_ADAPTIVE (C step, Alg. 4),
+                           or MD_JUMP_BPS: bounces of Sec. 3.2 in the C step (the eps -> infinity
+                           end of the MRZ family, Sec. 2.2) */
+  double eps;           /* eps (constant) or eps0 (adaptive, 1/force units); unused with BPS */
   int32_t precision;    /* MD_FP64 or MD_FP32_MIXED */
   int32_t rebuild_every;/* 0: rebuild when max displacement > skin/2; k>0: every k steps */
   int32_t respa_inner;  /* inner steps per outer step of the RESPA schemes (>= 1) */

@@ -27,6 +27,8 @@
  *  - in Alg. 1/2/4 the overflow branch ends the half step;
  *  - adaptive eps: eps = eps0 |F_ij| (Sec. 2.2) inserted in Eqs.
  *    (tauxsaut),(majvitesse), per-candidate bound beta*B_v*l_j + sqrt(beta/(2 pi m))/eps0;
+ *  - BPS kernel for the Coulomb long part runs in the C step (acceleration
+ *    between bounces), the eps -> infinity end of the MRZ family (Sec. 2.2);
  *  - Z = eta + G~ is drawn by exact rejection from the density
  *    z exp(-(z-eta)^2/2) on z > 0 with the regimes of Sec. 2.4
  *    (Gamma(2) for eta < -1, Rayleigh for -1 <= eta <= 0, mixed
@@ -604,11 +606,17 @@ static void jstep_atom(orc_sim *s, int i, int32_t phase, double h) {
  * bounds |v(t)| up to the end of the half step (Alg. 4). Per-candidate bound
  *   adaptive eps:  c_j = beta B_v l_s + f,   f = sqrt(beta/(2 pi m_i))/eps0
  *   constant eps:  c_j = l_s (beta B_v + sqrt(beta/(2 pi m_i))/eps)
+ *   BPS kernel:    c_j = beta B_v l_s
  * and Lambda = sum_j c_j. Proposal k (Philox block (step, i, phase, k)):
  * u0 -> E_k (time t_e + (E_first + ... + E_k)/Lambda), u1 -> which part of
  * c_j proposes (the beta B_v l part or the f part, adaptive only), u2 -> the
  * candidate (by bound, or uniform over candidates with l > 0), u3 ->
  * acceptance lambda_ij / c_j.
+ * With the BPS kernel on the Coulomb long part (the bounces of Sec. 3.2 in
+ * place of Eqs. (tauxsaut),(majvitesse), i.e. the eps -> infinity end of the
+ * MRZ family, Sec. 2.2) the rate is beta (v.F_ij)_+ and an accepted jump
+ * reflects v about the plane orthogonal to F_ij; the acceleration between
+ * jumps and the bound B_v are those of the MRZ case.
  * The proposals come from the stream (rstep, rphase) starting at index k0;
  * the return value is the first index the chain did not use (the one after
  * the proposal past the end of the half step). Events keep the op's own
@@ -620,7 +628,8 @@ static int64_t cstep_atom(orc_sim *s, int i, int32_t phase, double h, const doub
   seg_table(s, i, 1, &T);
   double me = s->me[i], beta = s->beta, eps0 = s->eps0;
   int adaptive = (s->jc == ORC_JUMP_MRZ_ADAPTIVE);
-  double f = sqrt(beta / (2.0 * PI * me)) / eps0;
+  int bps = (s->jc == ORC_JUMP_BPS);
+  double f = bps ? 0.0 : sqrt(beta / (2.0 * PI * me)) / eps0;
   double aa = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
   double ve[3] = {v[0], v[1], v[2]};
   double te = 0.0;
@@ -634,7 +643,7 @@ static int64_t cstep_atom(orc_sim *s, int i, int32_t phase, double h, const doub
     double Bv = sqrt(vv + tau * tau * aa + 2.0 * tau * (va > 0.0 ? va : 0.0));
     double bBv = beta * Bv;
     double Wb = bBv * T.W;
-    double Lam = adaptive ? Wb + f * T.nf : (bBv + f) * T.W;
+    double Lam = adaptive ? Wb + f * T.nf : (bps ? Wb : (bBv + f) * T.W);
     if (!(Lam > 0.0) || !isfinite(Lam)) {
       for (int q = 0; q < 3; q++) v[q] = ve[q] + tau * a[q];
       break;
@@ -663,9 +672,23 @@ static int64_t cstep_atom(orc_sim *s, int i, int32_t phase, double h, const doub
       double F2 = long_grad(s, i, j, 1, F);
       s->nprop[i]++;
       double ell = T.ell[sg];
-      double c = adaptive ? bBv * ell + f : ell * (bBv + f);
+      double c = adaptive ? bBv * ell + f : (bps ? bBv * ell : ell * (bBv + f));
       double lam = 0.0, eta = 0.0;
       double vF = vk[0] * F[0] + vk[1] * F[1] + vk[2] * F[2];
+      if (bps) {
+        lam = vF > 0.0 ? beta * vF : 0.0;
+        double p = lam / c;
+        if (p > 1.0) s->nviol[i]++;
+        if (p > 0.0 && u[3] <= p) {
+          double cr = 2.0 * vF / F2;   /* reflection R_ij at the jump time */
+          for (int q = 0; q < 3; q++) ve[q] = vk[q] - cr * F[q];
+          te = tk;
+          log_event(s, phase, i, j, k);
+          k++;
+          break; /* new epoch */
+        }
+        continue;
+      }
       if (F2 > 0.0) {
         if (adaptive) {
           /* eps = eps0 |F|: lambda = sqrt(beta/m)/eps0 Theta(eps0 sqrt(beta m) v.F) */
@@ -928,9 +951,11 @@ orc_sim *orc_create(const orc_system *sy, const orc_split *sp, const orc_params 
   s->respa_inner = pa->respa_inner; s->rebuild_every = pa->rebuild_every;
   s->log_events = pa->log_events;
   if (s->jlj != ORC_JUMP_NONE && s->jlj != ORC_JUMP_BPS) FAIL("LJ jumps: NONE or BPS");
-  if (s->jc != ORC_JUMP_NONE && s->jc != ORC_JUMP_MRZ_CONST && s->jc != ORC_JUMP_MRZ_ADAPTIVE)
-    FAIL("Coulomb jumps: NONE, MRZ_CONST or MRZ_ADAPTIVE");
-  if (s->jc != ORC_JUMP_NONE && !(s->eps0 > 0.0)) FAIL("eps must be positive");
+  if (s->jc != ORC_JUMP_NONE && s->jc != ORC_JUMP_BPS && s->jc != ORC_JUMP_MRZ_CONST &&
+      s->jc != ORC_JUMP_MRZ_ADAPTIVE)
+    FAIL("Coulomb jumps: NONE, BPS, MRZ_CONST or MRZ_ADAPTIVE");
+  if ((s->jc == ORC_JUMP_MRZ_CONST || s->jc == ORC_JUMP_MRZ_ADAPTIVE) && !(s->eps0 > 0.0))
+    FAIL("eps must be positive");
   /* the LJ bound needs |U|, |U'| non-increasing beyond r_s - w */
   for (int ab = 0; ab < nt * nt; ab++)
     if (s->eps[ab] != 0.0 && s->rlo < 1.25 * s->sig[ab]) FAIL("r_s - w must be >= 1.25 sigma");

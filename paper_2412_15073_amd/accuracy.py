@@ -11,7 +11,10 @@ Prints one JSON line.
 
 Run specs (--runs, comma separated): baoab or jump, optionally with
 parameters after a colon, e.g. "baoab:dt=0.5", "jump:eps0=0.01;rs=7;fp32=1"
-(dt in fs, eps0 in (kcal/mol/A)^-1, rs = split radius in A).
+(dt in fs, eps0 in (kcal/mol/A)^-1, rs = split radius in A). coul= picks the
+Coulomb long part's treatment in JUMP: mrz (adaptive MRZ jumps, default),
+bps (BPS bounces in the C step), or none (the long part dropped: the
+negative control of Fig. 1b, whose structure must differ).
 """
 import argparse
 import json
@@ -83,6 +86,9 @@ def main():
         sp = S.water_split(r_s=rs, r_c=10.0, w=1.0, skin=a.skin, n_rings=a.rings)
         pa = S.water_params(dt=dt_fs * 1e-3, eps0_per_kcal=eps0, jumps=jumps, seed=a.seed + 1)
         pa.precision = int(kv.get("fp32", 0))
+        if jumps:
+            pa.jump_coul = {"mrz": S.JUMP_MRZ_ADAPTIVE, "bps": S.JUMP_BPS,
+                            "none": S.JUMP_NONE}[kv.get("coul", "mrz")]
         sim = jumpmd.Sim(sysm, sp, pa)
         n_steps = int(round(a.ps / (dt_fs * 1e-3)))
         every = max(1, int(round(a.every / dt_fs)))

@@ -380,9 +380,11 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
   if (!(p->dt > 0.0) || p->gamma < 0.0 || !(p->kT > 0.0)) return fail(nullptr, MD_ERR_ARG, "bad dt/gamma/kT");
   if (p->jump_lj != MD_JUMP_NONE && p->jump_lj != MD_JUMP_BPS)
     return fail(nullptr, MD_ERR_ARG, "jump_lj must be NONE or BPS");
-  if (p->jump_coul != MD_JUMP_NONE && p->jump_coul != MD_JUMP_MRZ_CONST && p->jump_coul != MD_JUMP_MRZ_ADAPTIVE)
-    return fail(nullptr, MD_ERR_ARG, "jump_coul must be NONE, MRZ_CONST or MRZ_ADAPTIVE");
-  if (p->jump_coul != MD_JUMP_NONE && !(p->eps > 0.0)) return fail(nullptr, MD_ERR_ARG, "eps must be > 0");
+  if (p->jump_coul != MD_JUMP_NONE && p->jump_coul != MD_JUMP_BPS && p->jump_coul != MD_JUMP_MRZ_CONST &&
+      p->jump_coul != MD_JUMP_MRZ_ADAPTIVE)
+    return fail(nullptr, MD_ERR_ARG, "jump_coul must be NONE, BPS, MRZ_CONST or MRZ_ADAPTIVE");
+  if ((p->jump_coul == MD_JUMP_MRZ_CONST || p->jump_coul == MD_JUMP_MRZ_ADAPTIVE) && !(p->eps > 0.0))
+    return fail(nullptr, MD_ERR_ARG, "eps must be > 0");
   if (p->precision != MD_FP64 && p->precision != MD_FP32_MIXED)
     return fail(nullptr, MD_ERR_ARG, "precision must be MD_FP64 or MD_FP32_MIXED");
   if (s->n_types * std::max(1, sp->n_rings) > 32)
@@ -444,7 +446,10 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.two_a_sqpi = 2.0 * V.alpha / std::sqrt(M_PI);
   V.dsf_erfc_rc_over_rc = std::erfc(V.alpha * V.rc) / V.rc;
   V.dsf_fc = std::erfc(V.alpha * V.rc) / (V.rc * V.rc) + V.two_a_sqpi * std::exp(-V.alpha * V.alpha * V.rc * V.rc) / V.rc;
-  V.beta = 1.0 / p->kT; V.kT = p->kT; V.eps0 = p->eps;
+  V.beta = 1.0 / p->kT; V.kT = p->kT;
+  // bounces are the eps -> infinity end of the MRZ family: the floor term of
+  // the C-step bound, sqrt(beta / (2 pi m)) / eps, is then exactly zero
+  V.eps0 = p->jump_coul == MD_JUMP_BPS ? INFINITY : p->eps;
   V.jlj = p->jump_lj; V.jc = p->jump_coul; V.log_events = p->log_events; V.precision = p->precision;
   V.seed = p->seed;
   // Jump-chain layout. G (lanes per atom), automatic: the most lanes per atom

@@ -364,6 +364,9 @@ __device__ __forceinline__ int ring_add(int s, int d, int M) {
 //    constant acceleration a between jumps plus MRZ jumps of the Coulomb long
 //    part; the bound is re-evaluated after each accepted jump (Sec. 2.4): from
 //    (t_e, v_e), B_v = sqrt(|v_e|^2 + tau^2 |a|^2 + 2 tau (v_e.a)_+), tau = h - t_e.
+//    With the BPS kernel on the Coulomb part (the eps -> infinity end of the
+//    MRZ family, Sec. 2.2) the rate is beta (v.F)_+ against the bound
+//    beta B_v l_s, and an accepted jump reflects v as in J.
 // Block (rstep, i, rphase, k): u0 -> E_k, u1 -> bound part (adaptive C),
 // u2 -> candidate, u3 -> acceptance; block (rstep, i, rphase | 1 << 24, k) ->
 // first Z iteration.
@@ -401,8 +404,12 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   const int *row = V.crow + (size_t)i * V.cap_c;
   const double inv_nr = 1.0 / (double)V.nr;
   const bool adaptive = isC && (V.jc == MD_JUMP_MRZ_ADAPTIVE);
+  // C with BPS bounces: no Z (the refill still fills the Z fields of every C
+  // op; keeping one code path there costs less than the registers a second takes)
+  const bool bpsC = isC && (V.jc == MD_JUMP_BPS);
+  const bool mrz = isC && !bpsC;
   const R beta = (R)V.beta, eps0 = (R)V.eps0, mr = (R)me;
-  const R f = sqrt(beta / (R(2) * R(MD_PI) * mr)) / eps0;
+  const R f = sqrt(beta / (R(2) * R(MD_PI) * mr)) / eps0;   // 0 with bounces (eps0 = infinity)
   const R ax = (R)ax_d, ay = (R)ay_d, az = (R)az_d;
   const R aa = ax * ax + ay * ay + az * az;
   const uint64_t rep = (uint64_t)V.rep[i];
@@ -521,7 +528,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     const R u3 = (R)u01(pw.y);
     // acceptance u3 <= lam / c and bound violation lam > c, tested without dividing
     bool out, acc = false, viol = false;
-    R eta = R(0), tk = R(0);
+    R eta = R(0), tk = R(0);   // eta: MRZ argument of Theta, or v.F with BPS
     R zown = R(0);     // first Z iteration of this lane's proposal, taken if it is accepted
     bool zok = false;
     if (isC) {
@@ -532,8 +539,13 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       const R c = adaptive ? bBv * ell + f : ell * (bBv + f);
       R lam = R(0);
       const R vF = vkx * Fx + vky * Fy + vkz * Fz;
-      bool decided = false;
-      if (!out && F2 > R(0)) {
+      bool decided = bpsC;
+      if (bpsC) {
+        eta = vF;
+        lam = vF > R(0) ? beta * vF : R(0);
+        acc = !out && lam > R(0) && u3 * c <= lam;
+        viol = lam > c;
+      } else if (!out && F2 > R(0)) {
         R scale;
         if (adaptive) {
           eta = k_eta * vF;
@@ -564,7 +576,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       }
       // the first accepted proposal's Z is evaluated by its own lane, off the
       // sequential path after the group minimum
-      if (acc) {
+      if (acc && mrz) {
         const uint2 zz = zwords[sl];
         const ZPre<R> zp = kZPre ? ZPre<R>{ring[RF_ZL0 * M + sl], ring[RF_ZL1 * M + sl], ring[RF_ZCP * M + sl]}
                                  : z_pre<R>(ring[RF_ZL0 * M + sl], ring[RF_ZL1 * M + sl], ring[RF_ZU2 * M + sl]);
@@ -599,15 +611,20 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
     const int j = fos ? jj.y : jj.x;
     const int kstar = w0 + first;
     if (isC) {
-      const R etas = __shfl(eta, first, G);
       const R tks = __shfl(tk, first, G);
-      R Z = __shfl(zown, first, G);
-      if (!__shfl((int)zok, first, G)) {
-        int ovf;
-        Z = zsample_grp<G, R>(etas, V.seed, rep, op.rstep, li, op.rphase, kstar, r, 1, ovf);
-        if (ovf && r == 0) atomicAdd(&V.ctl->n_zs_overflow, 1ull);
+      R coef;
+      if (bpsC) {
+        coef = R(2) * __shfl(eta, first, G) / F2s;   // reflection at t_k
+      } else {
+        const R etas = __shfl(eta, first, G);
+        R Z = __shfl(zown, first, G);
+        if (!__shfl((int)zok, first, G)) {
+          int ovf;
+          Z = zsample_grp<G, R>(etas, V.seed, rep, op.rstep, li, op.rphase, kstar, r, 1, ovf);
+          if (ovf && r == 0) atomicAdd(&V.ctl->n_zs_overflow, 1ull);
+        }
+        coef = adaptive ? k_coef * Z / (R(1) + eps0 * eps0 * F2s) : k_coef * Z / sqrt(F2s);
       }
-      const R coef = adaptive ? k_coef * Z / (R(1) + eps0 * eps0 * F2s) : k_coef * Z / sqrt(F2s);
       const R dts = tks - te;
       if (PREC == MD_FP32_MIXED) {
         // float kick, FP64 accumulation of the velocity

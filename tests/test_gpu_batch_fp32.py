@@ -86,16 +86,18 @@ def test_fp32_forces_match_fp64_oracle(jm):
     assert rel_err(g.accel(1), o.accel(F_FULL)) < 2e-5
 
 
+@pytest.mark.parametrize("kind", [S.JUMP_MRZ_ADAPTIVE, S.JUMP_BPS])
 @pytest.mark.parametrize("precision", [S.FP64, S.FP32_MIXED])
-def test_gpu_c_step_mean_kick_equals_long_force(jm, precision):
+def test_gpu_c_step_mean_kick_equals_long_force(jm, precision, kind):
     """Generator-moment identity run on the GPU path: from Maxwell-Boltzmann
     velocities the C step changes v by -h grad U_long / m on average (ion
-    lattice, short force exactly zero), in FP64 and with FP32 rates."""
+    lattice, short force exactly zero), in FP64 and with FP32 rates, for the
+    adaptive MRZ jumps and for the BPS bounces."""
     from oracle.oracle import OracleSim, F_FULL
     sy = S.ion_lattice(4, 3.3, jitter=0.1, neutral_every=5)
     sp = S.Split(r_s=3.0, r_c=5.0, switch_width=1.0, skin=0.3, coulomb_alpha=0.2, n_rings=3,
                  ring_width=(5.3 - 1.7) / 3)
-    pa = S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_coul=S.JUMP_MRZ_ADAPTIVE, eps=0.3, precision=precision)
+    pa = S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_coul=kind, eps=0.3, precision=precision)
     g = jm.Sim(sy, sp, pa)
     h, K = 0.05, 6000
     expected = h * OracleSim(sy, sp, S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_coul=S.JUMP_MRZ_ADAPTIVE,

@@ -255,6 +255,43 @@ def test_chain_lanes_do_not_change_results(jm, lanes):
     np.testing.assert_array_equal(g.events(), o.events())
 
 
+@pytest.mark.parametrize("kind", [S.JUMP_MRZ_CONST, S.JUMP_BPS])
+@pytest.mark.parametrize("lanes", [1, 2, 8])
+def test_coulomb_jump_kinds(jm, kind, lanes):
+    """C' steps with constant-eps MRZ jumps (Alg. 4) and with BPS bounces on
+    the Coulomb long part (no Z draw, reflection at the jump time): same
+    decisions and states as the oracle."""
+    sy, sp = water_small()
+    pa = S.water_params()
+    pa.jump_coul = kind
+    if kind == S.JUMP_MRZ_CONST:
+        pa.eps = 0.05
+    pa.log_events = 1
+    pa.chain_lanes = lanes
+    g, o = _pair(jm, sy, sp, pa)
+    for _ in range(2):
+        g.step_jump(6)
+        o.step_jump(6)
+        _compare_state(g, o)
+    _compare_stats(g, o)
+    np.testing.assert_array_equal(g.events(), o.events())
+    assert o.atom_stats()["n_acc"].sum() > 0
+
+
+def test_bps_coulomb_jump_respa(jm):
+    sy, sp = water_small()
+    pa = S.water_params()
+    pa.jump_coul = S.JUMP_BPS
+    pa.respa_inner = 3
+    pa.log_events = 1
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_jump_respa(4)
+    o.step_jump_respa(4)
+    _compare_state(g, o)
+    _compare_stats(g, o)
+    np.testing.assert_array_equal(g.events(), o.events())
+
+
 @pytest.mark.parametrize("lanes", [1, 8])
 def test_lj_chain_lanes(jm, lanes):
     sy, sp = lj_small()

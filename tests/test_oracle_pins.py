@@ -385,13 +385,14 @@ def test_velocity_verlet_energy_error_scales_as_dt_squared():
     assert 3.0 < ratio < 5.3, ratio
 
 
-def test_thinning_exact_under_bound_inflation():
+@pytest.mark.parametrize("coul", [O.JUMP_MRZ_ADAPTIVE, O.JUMP_BPS])
+def test_thinning_exact_under_bound_inflation(coul):
     """Poisson thinning does not depend on the bound (Sec. 2.4): inflating all
     bounds x3 leaves the law of the C and J updates unchanged (per-atom means
     of dv over independent streams, chi-square over all atoms and components)."""
-    sy, sp = water_small(n_mol=64, n_rings=3) if False else (S.water_box(125, seed=4), S.water_split(
-        r_s=5.0, r_c=7.0, w=1.0, skin=0.5, n_rings=3))
+    sy, sp = S.water_box(125, seed=4), S.water_split(r_s=5.0, r_c=7.0, w=1.0, skin=0.5, n_rings=3)
     pa = S.water_params(eps0_per_kcal=0.5)
+    pa.jump_coul = coul
     res = []
     K = 150
     for scale in (1.0, 3.0):
@@ -463,7 +464,7 @@ def test_c_step_small_eps_is_kick_with_full_force():
     assert np.all(np.abs(mean - expected) < 4.5 * se + 0.01 * abs(expected[0])), (mean, se, expected)
 
 
-@pytest.mark.parametrize("kind", [O.JUMP_MRZ_ADAPTIVE, O.JUMP_MRZ_CONST])
+@pytest.mark.parametrize("kind", [O.JUMP_MRZ_ADAPTIVE, O.JUMP_MRZ_CONST, O.JUMP_BPS])
 def test_c_step_bound_holds_under_strong_acceleration(kind):
     """Starting at rest with a strong short force, the velocity grows during
     the half step; the bound B_v of Alg. 4 must still dominate every rate
@@ -506,19 +507,64 @@ def _moment_check(o, phase_fn, h, K, kT, seed=11):
     return float((z * z).sum()), float((z0 * z0).sum()), int(z.size)
 
 
-def test_c_step_mean_kick_equals_long_force():
+@pytest.mark.parametrize("kind", [O.JUMP_MRZ_ADAPTIVE, O.JUMP_BPS])
+def test_c_step_mean_kick_equals_long_force(kind):
     """Ions on a jittered lattice (+/- charges and neutral sites, 3 rings, all
-    pairs beyond r_s): averaged over Maxwell-Boltzmann velocities, the adaptive-MRZ C step
-    changes v by -h grad U_long / m. Detects a biased choice of proposal part,
-    segment or index, a wrong floor count, jump size or sign."""
+    pairs beyond r_s): averaged over Maxwell-Boltzmann velocities, the C step
+    (adaptive MRZ, or the BPS bounces) changes v by -h grad U_long / m. Detects
+    a biased choice of proposal part, segment or index, a wrong floor count,
+    jump size or sign."""
     sy = S.ion_lattice(4, 3.3, jitter=0.1, neutral_every=5)   # neutral third type: segments with l = 0
     sp = S.Split(r_s=3.0, r_c=5.0, switch_width=1.0, skin=0.3, coulomb_alpha=0.2, n_rings=3,
                  ring_width=(5.3 - 1.7) / 3)
-    pa = S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_coul=O.JUMP_MRZ_ADAPTIVE, eps=0.3)
+    pa = S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_coul=kind, eps=0.3)
     o = _oracle(sy, sp, pa)
     chi2, signal, dof = _moment_check(o, lambda h: o.phase_c(O.PH_C1, h), 0.05, 20000, pa.kT)
     assert signal > 10 * dof                      # the drift is resolved
     assert st.chi2.sf(chi2, dof) > 1e-3, chi2
+
+
+def _dv_moments(o, h, K, kT, seed=5):
+    """Per-atom mean and mean square of the velocity change of one C step over
+    K independent streams started from Maxwell-Boltzmann velocities."""
+    x0, v0 = o.state()
+    rng = np.random.default_rng(seed)
+    dv = []
+    for k in range(K):
+        v = rng.standard_normal(v0.shape) * np.sqrt(kT)
+        o.set_state(vel=v, step=k)
+        o.phase_c(O.PH_C1, h)
+        dv.append(o.state()[1] - v)
+    dv = np.array(dv).reshape(K, -1)
+    return dv.mean(0), (dv * dv).mean(0), dv.var(0, ddof=1), (dv * dv).var(0, ddof=1)
+
+
+def test_mrz_large_eps_has_the_law_of_bps():
+    """Sec. 2.2: the MRZ family interpolates between Hamiltonian drift (eps ->
+    0) and the BPS bounces (eps -> infinity). With constant eps = 1e3 the mean
+    and the mean square of the C-step velocity change match the BPS kernel's
+    (two-sample chi-square over atoms and components); with eps = 0.3 the
+    mean square differs (the test can tell the kernels apart)."""
+    sy = S.ion_lattice(4, 3.3, jitter=0.1)
+    sp = S.Split(r_s=3.0, r_c=5.0, switch_width=1.0, skin=0.3, coulomb_alpha=0.2, n_rings=3,
+                 ring_width=(5.3 - 1.7) / 3)
+    K, h = 4000, 0.05
+    mom = {}
+    for name, kind, eps in (("bps", O.JUMP_BPS, 0.0), ("big", O.JUMP_MRZ_CONST, 1e3),
+                            ("small", O.JUMP_MRZ_CONST, 0.3)):
+        pa = S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_coul=kind, eps=eps)
+        mom[name] = _dv_moments(_oracle(sy, sp, pa), h, K, pa.kT)
+
+    def chi2_sf(a, b):
+        m1, s1, vm1, vs1 = a
+        m2, s2, vm2, vs2 = b
+        zm = (m1 - m2) ** 2 / ((vm1 + vm2) / K)
+        zs = (s1 - s2) ** 2 / ((vs1 + vs2) / K)
+        z = np.concatenate([zm, zs])
+        return st.chi2.sf(z.sum(), z.size)
+
+    assert chi2_sf(mom["bps"], mom["big"]) > 1e-3
+    assert chi2_sf(mom["bps"], mom["small"]) < 1e-6
 
 
 def test_j_step_mean_kick_equals_long_lj_force():
@@ -543,21 +589,22 @@ def _gibbs_reference(sy, sp, kT, edges):
     return p / p.sum()
 
 
-@pytest.mark.parametrize("scheme", ["jump", "baoab"])
+@pytest.mark.parametrize("scheme", ["jump", "jump_bps", "baoab"])
 def test_two_particle_gibbs_marginal(scheme):
     """Two charged LJ particles: the distance histogram (r < L/2) of a long run
     matches p(r) ~ r^2 exp(-beta U(r)) by quadrature, and <v^2> = kT/m.
-    JUMP uses BPS for the LJ long part and adaptive MRZ for the Coulomb one."""
+    JUMP uses BPS for the LJ long part and adaptive MRZ (jump_bps: BPS
+    bounces) for the Coulomb one."""
     sy = S.two_charges()
     sp = S.Split(r_s=3.0, r_c=5.0, switch_width=0.5, skin=0.3, coulomb_alpha=0.2)
     pa = S.Params(dt=0.005, gamma=2.0, kT=0.722, seed=3,
-                  jump_lj=O.JUMP_BPS if scheme == "jump" else 0,
-                  jump_coul=O.JUMP_MRZ_ADAPTIVE if scheme == "jump" else 0, eps=0.5)
+                  jump_lj=O.JUMP_BPS if scheme != "baoab" else 0,
+                  jump_coul={"jump": O.JUMP_MRZ_ADAPTIVE, "jump_bps": O.JUMP_BPS, "baoab": 0}[scheme], eps=0.5)
     o = _oracle(sy, sp, pa)
     L = sy.box[0]
     rs, v2 = [], []
     for _ in range(6000):
-        (o.step_jump if scheme == "jump" else o.step_baoab)(100)
+        (o.step_baoab if scheme == "baoab" else o.step_jump)(100)
         x, v = o.state()
         d = x[1] - x[0]
         d -= L * np.rint(d / L)
@@ -572,5 +619,5 @@ def test_two_particle_gibbs_marginal(scheme):
     chi2 = ((cnt - exp) ** 2 / exp).sum()
     assert st.chi2.sf(chi2, len(cnt) - 1) > 1e-3, (cnt, exp.round(1))
     assert abs(np.mean(v2) - pa.kT) < 0.03 * pa.kT
-    if scheme == "jump":
-        assert o.atom_stats()["n_acc"].sum() > 1000
+    if scheme != "baoab":   # the jumps act (BPS accepts only on approach, so far fewer)
+        assert o.atom_stats()["n_acc"].sum() > (1000 if scheme == "jump" else 200)
