@@ -25,18 +25,24 @@ import numpy as np
 from . import analysis, jumpmd, systems as S
 
 
-def run(sim, step_fn, n_steps, every, o_idx, r_max, n_bins):
+def run(sim, step_fn, n_steps, every, o_idx, r_max, n_bins, t_stop):
+    """Samples every `every` steps. Stops early when the kinetic temperature
+    exceeds t_stop (a run that heats without bound; a transient after a change
+    of potential stays well below it); returns the samples so far and the
+    number of steps done."""
     temps, pes, frames = [], [], []
     counts = np.zeros(n_bins)
-    for _ in range(n_steps // every):
+    for s in range(n_steps // every):
         step_fn(every)
         obs = sim.observables(pe=True)
+        if not obs["temperature"] < t_stop:
+            return None, (s + 1) * every, obs["temperature"]
         temps.append(obs["temperature"])
         pes.append(obs["pe_short"] + obs["pe_long"] + obs["pe_bonded"])
         x, _ = sim.state()
         frames.append(x[o_idx].copy())
         counts += sim.rdf_counts(0, 0, r_max, n_bins)
-    return np.array(temps), np.array(pes), np.array(frames), counts
+    return (np.array(temps), np.array(pes), np.array(frames), counts), n_steps, None
 
 
 def block_err(x, n_blocks):
@@ -75,7 +81,7 @@ def main():
     eq.close()
     sysm.pos, sysm.vel = x, v
 
-    res = {}
+    res, unstable = {}, {}
     for spec in a.runs.split(","):
         name, _, opts = spec.partition(":")
         kv = dict(x.split("=") for x in opts.split(";") if x)
@@ -93,13 +99,20 @@ def main():
         n_steps = int(round(a.ps / (dt_fs * 1e-3)))
         every = max(1, int(round(a.every / dt_fs)))
         t0 = time.perf_counter()
-        T, pe, frames, counts = run(sim, sim.step_jump if jumps else sim.step_baoab, n_steps, every,
-                                    o_idx, r_max, n_bins)
+        out_run, done, t_bad = run(sim, sim.step_jump if jumps else sim.step_baoab, n_steps, every,
+                                   o_idx, r_max, n_bins, 10.0 * 300.0)
         el = time.perf_counter() - t0
+        key = spec if spec not in ("jump:fp32=1",) else "jump_fp32"
+        if out_run is None:
+            unstable[key] = {"unstable_after_ps": done * dt_fs * 1e-3, "T_K_at_stop": t_bad}
+            sim.close()
+            print(f"[accuracy] {spec}: unstable, T = {t_bad:.0f} K after {done * dt_fs * 1e-3:.3f} ps",
+                  flush=True)
+            continue
+        T, pe, frames, counts = out_run
         nf = len(T)
         _, g = analysis.rdf_from_counts(counts, n_o, n_o, L ** 3, r_max, True, nf)
         D, dD = analysis.block_diffusion(frames, every * dt_fs * 1e-3, n_blocks=a.blocks)
-        key = spec if spec not in ("jump:fp32=1",) else "jump_fp32"
         res[key] = dict(T=float(T.mean()), T_err=block_err(T, a.blocks),
                         pe=float(pe.mean()), pe_err=block_err(pe, a.blocks),
                         g=g, D=D, D_err=dD, seconds=el, ms_per_step=1e3 * el / n_steps)
@@ -121,6 +134,7 @@ def main():
                                "rdf_l2": analysis.rdf_l2(ref["g"], r["g"]),
                                "D_rel": (r["D"] - ref["D"]) / ref["D"]}
         out[name] = row
+    out.update(unstable)
     if "jump" in res and "jump_fp32" in res:
         j, f = res["jump"], res["jump_fp32"]
         out["jump_fp32"]["vs_jump_fp64"] = {"T_rel": (f["T"] - j["T"]) / j["T"],

@@ -375,7 +375,9 @@ __device__ __forceinline__ int ring_add(int s, int d, int M) {
 // launch saved (same positions, same candidates) keeps its ring contents.
 struct RingPos { int w0, ws, computed, cs; bool saved; };
 
-template <int G, int PREC>
+// CB: the Coulomb jumps are BPS bounces (a separate instantiation, so that
+// the MRZ chains carry none of the bounce code)
+template <int G, int PREC, bool CB>
 __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, int r, double4 xi,
                          double &vx, double &vy, double &vz, double me, double ax_d, double ay_d, double az_d,
                          const MDOp &op, AtomStats &st, const double *L, const double *iL,
@@ -404,9 +406,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   const int *row = V.crow + (size_t)i * V.cap_c;
   const double inv_nr = 1.0 / (double)V.nr;
   const bool adaptive = isC && (V.jc == MD_JUMP_MRZ_ADAPTIVE);
-  // C with BPS bounces: no Z (the refill still fills the Z fields of every C
-  // op; keeping one code path there costs less than the registers a second takes)
-  const bool bpsC = isC && (V.jc == MD_JUMP_BPS);
+  const bool bpsC = CB && isC;   // C with BPS bounces: no Z
   const bool mrz = isC && !bpsC;
   const R beta = (R)V.beta, eps0 = (R)V.eps0, mr = (R)me;
   const R f = sqrt(beta / (R(2) * R(MD_PI) * mr)) / eps0;   // 0 with bounces (eps0 = infinity)
@@ -480,7 +480,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         const double4 xb = X[jb], xf = X[jf];
         const int lb = V.loc[jb], lf = V.loc[jf];
         u32x4 zw;
-        if (isC) zw = draw4w(V.seed, rep, op.rstep, li, (uint64_t)(uint32_t)op.rphase | (1ull << 24), k);
+        if (mrz) zw = draw4w(V.seed, rep, op.rstep, li, (uint64_t)(uint32_t)op.rphase | (1ull << 24), k);
         ring[RF_E * M + sl] = (R)(-log(u01(uw.w[0])));
         pwords[sl] = make_uint2(uw.w[1], uw.w[3]);
         double Fx, Fy, Fz;
@@ -494,7 +494,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
           ring[RF_FL * M + sl] = (R)ellf;
         }
         jring[sl] = make_int2(lb, lf);   // replica-local indices (event hash)
-        if (isC) {
+        if (mrz) {
           const R zu2 = (R)u01(zw.w[2]);
           if (kZPre) {
             const ZPre<R> zp = z_pre<R>((R)u01(zw.w[0]), (R)u01(zw.w[1]), zu2);
@@ -665,7 +665,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
 #ifndef MD_CHAIN_WAVES_PER_SIMD
 #define MD_CHAIN_WAVES_PER_SIMD 2   // register budget of the chain kernel: 512 / this per lane
 #endif
-template <int G, int PREC>
+template <int G, int PREC, bool CB>
 __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_SIMD) void k_chain(
     MDView V, MDProg P, const double4 *__restrict__ X) {
   extern __shared__ double lds_chain[];
@@ -717,8 +717,8 @@ __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_S
         ay = (fn.y + (op.flags == 0 ? fb.y : 0.0)) / me;
         az = (fn.z + (op.flags == 0 ? fb.z : 0.0)) / me;
       }
-      chain_op<G, PREC>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, pwords, zwords, jring, T,
-                        pos);
+      chain_op<G, PREC, CB>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, pwords, zwords, jring,
+                            T, pos);
     }
   }
   if (r == 0) {
@@ -738,14 +738,17 @@ size_t chain_lds_bytes_host(int G, int S, int precision) {
   return chain_lds_bytes(G, S, precision == MD_FP32_MIXED ? 4 : 8);
 }
 
+// Occupancy of the MRZ instantiation. The bounce instantiation has the same
+// LDS and at most the same registers (the launch bounds cap both), so this is
+// also a lower bound for it.
 template <int PREC>
 static hipError_t chain_occupancy(int G, int threads, size_t lds, int *nb) {
   switch (G) {
-    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<1, PREC>, threads, lds);
-    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<2, PREC>, threads, lds);
-    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<4, PREC>, threads, lds);
-    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<8, PREC>, threads, lds);
-    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<16, PREC>, threads, lds);
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<1, PREC, false>, threads, lds);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<2, PREC, false>, threads, lds);
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<4, PREC, false>, threads, lds);
+    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<8, PREC, false>, threads, lds);
+    case 16: return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_chain<16, PREC, false>, threads, lds);
   }
   return hipErrorInvalidValue;
 }
@@ -760,24 +763,30 @@ int chain_blocks_per_cu(int G, int S, int precision, int bw) {
   return e == hipSuccess ? nb : 0;
 }
 
-template <int PREC>
+template <int PREC, bool CB>
 static void launch_chain_p(const MDView &V, const MDProg &P, const double4 *X, hipStream_t s) {
   const int G = V.chain_lanes, bw = V.chain_block_waves;
   const int nb = (int)(((long long)V.chain_groups * G + 64 * bw - 1) / (64 * bw));
   const size_t lds = (size_t)bw * chain_lds_bytes(G, V.S, PREC == MD_FP32_MIXED ? 4 : 8);
   const dim3 grid(nb), block(64 * bw);
   switch (G) {
-    case 1: hipLaunchKernelGGL((k_chain<1, PREC>), grid, block, lds, s, V, P, X); break;
-    case 2: hipLaunchKernelGGL((k_chain<2, PREC>), grid, block, lds, s, V, P, X); break;
-    case 4: hipLaunchKernelGGL((k_chain<4, PREC>), grid, block, lds, s, V, P, X); break;
-    case 8: hipLaunchKernelGGL((k_chain<8, PREC>), grid, block, lds, s, V, P, X); break;
-    default: hipLaunchKernelGGL((k_chain<16, PREC>), grid, block, lds, s, V, P, X); break;
+    case 1: hipLaunchKernelGGL((k_chain<1, PREC, CB>), grid, block, lds, s, V, P, X); break;
+    case 2: hipLaunchKernelGGL((k_chain<2, PREC, CB>), grid, block, lds, s, V, P, X); break;
+    case 4: hipLaunchKernelGGL((k_chain<4, PREC, CB>), grid, block, lds, s, V, P, X); break;
+    case 8: hipLaunchKernelGGL((k_chain<8, PREC, CB>), grid, block, lds, s, V, P, X); break;
+    default: hipLaunchKernelGGL((k_chain<16, PREC, CB>), grid, block, lds, s, V, P, X); break;
   }
 }
 
 hipError_t launch_chain(const MDView &V, const MDProg &P, const double4 *X, hipStream_t s) {
-  if (V.precision == MD_FP32_MIXED) launch_chain_p<MD_FP32_MIXED>(V, P, X, s);
-  else launch_chain_p<MD_FP64>(V, P, X, s);
+  const bool cb = V.jc == MD_JUMP_BPS;
+  if (V.precision == MD_FP32_MIXED) {
+    if (cb) launch_chain_p<MD_FP32_MIXED, true>(V, P, X, s);
+    else launch_chain_p<MD_FP32_MIXED, false>(V, P, X, s);
+  } else {
+    if (cb) launch_chain_p<MD_FP64, true>(V, P, X, s);
+    else launch_chain_p<MD_FP64, false>(V, P, X, s);
+  }
   return hipGetLastError();
 }
 
