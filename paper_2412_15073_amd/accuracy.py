@@ -9,9 +9,11 @@ Prints one JSON line.
 
     python -m paper_2412_15073_amd.accuracy --n-mol 4096 --ps 40
 
-Run specs (--runs, comma separated): baoab or jump, optionally with
-parameters after a colon, e.g. "baoab:dt=0.5", "jump:eps0=0.01;rs=7;fp32=1"
-(dt in fs, eps0 in (kcal/mol/A)^-1, rs = split radius in A). coul= picks the
+Run specs (--runs, comma separated): baoab, jump, baoab_respa or
+jump_respa, optionally with parameters after a colon, e.g. "baoab:dt=0.5",
+"jump:eps0=0.01;rs=7;fp32=1", "jump_respa:n=4" (dt in fs, the inner step of
+the RESPA schemes; n inner steps per outer step, default 3; eps0 in
+(kcal/mol/A)^-1; rs = split radius in A). coul= picks the
 Coulomb long part's treatment in JUMP: mrz (adaptive MRZ jumps, default),
 bps (BPS bounces in the C step), or none (the long part dropped: the
 negative control of Fig. 1b, whose structure must differ).
@@ -85,8 +87,10 @@ def main():
     for spec in a.runs.split(","):
         name, _, opts = spec.partition(":")
         kv = dict(x.split("=") for x in opts.split(";") if x)
-        jumps = name == "jump"
+        jumps = name.startswith("jump")
+        respa = name.endswith("_respa")
         dt_fs = float(kv.get("dt", 1.0))
+        n_in = int(kv.get("n", 3)) if respa else 1
         eps0 = float(kv.get("eps0", a.eps0))
         rs = float(kv.get("rs", 5.0))
         sp = S.water_split(r_s=rs, r_c=10.0, w=1.0, skin=a.skin, n_rings=a.rings)
@@ -95,24 +99,27 @@ def main():
         if jumps:
             pa.jump_coul = {"mrz": S.JUMP_MRZ_ADAPTIVE, "bps": S.JUMP_BPS,
                             "none": S.JUMP_NONE}[kv.get("coul", "mrz")]
+        pa.respa_inner = n_in
         sim = jumpmd.Sim(sysm, sp, pa)
-        n_steps = int(round(a.ps / (dt_fs * 1e-3)))
-        every = max(1, int(round(a.every / dt_fs)))
+        step_fs = dt_fs * n_in                        # time per call of the step function
+        n_steps = int(round(a.ps / (step_fs * 1e-3)))
+        every = max(1, int(round(a.every / step_fs)))
+        step_fn = {"baoab": sim.step_baoab, "jump": sim.step_jump, "baoab_respa": sim.step_baoab_respa,
+                   "jump_respa": sim.step_jump_respa}[name]
         t0 = time.perf_counter()
-        out_run, done, t_bad = run(sim, sim.step_jump if jumps else sim.step_baoab, n_steps, every,
-                                   o_idx, r_max, n_bins, 10.0 * 300.0)
+        out_run, done, t_bad = run(sim, step_fn, n_steps, every, o_idx, r_max, n_bins, 10.0 * 300.0)
         el = time.perf_counter() - t0
         key = spec if spec not in ("jump:fp32=1",) else "jump_fp32"
         if out_run is None:
-            unstable[key] = {"unstable_after_ps": done * dt_fs * 1e-3, "T_K_at_stop": t_bad}
+            unstable[key] = {"unstable_after_ps": done * step_fs * 1e-3, "T_K_at_stop": t_bad}
             sim.close()
-            print(f"[accuracy] {spec}: unstable, T = {t_bad:.0f} K after {done * dt_fs * 1e-3:.3f} ps",
+            print(f"[accuracy] {spec}: unstable, T = {t_bad:.0f} K after {done * step_fs * 1e-3:.3f} ps",
                   flush=True)
             continue
         T, pe, frames, counts = out_run
         nf = len(T)
         _, g = analysis.rdf_from_counts(counts, n_o, n_o, L ** 3, r_max, True, nf)
-        D, dD = analysis.block_diffusion(frames, every * dt_fs * 1e-3, n_blocks=a.blocks)
+        D, dD = analysis.block_diffusion(frames, every * step_fs * 1e-3, n_blocks=a.blocks)
         res[key] = dict(T=float(T.mean()), T_err=block_err(T, a.blocks),
                         pe=float(pe.mean()), pe_err=block_err(pe, a.blocks),
                         g=g, D=D, D_err=dD, seconds=el, ms_per_step=1e3 * el / n_steps)

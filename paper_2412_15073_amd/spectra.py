@@ -2,17 +2,19 @@
 
 Sec. 4 of the paper reads integrator artifacts off velocity autocorrelation
 spectra (resonance effects, Figs. 3-4): for water, a libration band below
-1000 cm^-1, the bending peak, the stretching peaks near 3500 cm^-1, and any
-weight beyond them is an artifact of the time stepping. This module computes
+1000 cm^-1, the bending peak, the stretching peaks near 3500 cm^-1; weight
+beyond them comes from the time stepping (resonances) or, with jumps, from
+the velocity kicks, which are white in time. This module computes
 the mass-weighted spectrum
 
     I(nu) = sum_i m_i sum_c |sum_t w(t) v_ic(t) e^{-2 pi i nu t}|^2
 
 from velocities sampled every step. By the Wiener-Khinchin theorem it is the
 Fourier transform of the mass-weighted VACF; `vacf` gives that function in
-the time domain. Running it compares JUMP with BAOAB on the same water box:
+the time domain. Running it compares JUMP with BAOAB on the same water box
+(run specs as in accuracy.py, e.g. "jump:eps0=0.01;rs=7"):
 
-    python -m paper_2412_15073_amd.spectra --n-mol 1000 --ps 4
+    python -m paper_2412_15073_amd.spectra --n-mol 1000 --ps 4 --runs "baoab,jump,jump:eps0=0.01;rs=7"
 """
 import argparse
 import json
@@ -85,10 +87,14 @@ def main():
 
     dt = 0.001
     n = int(round(a.ps / dt))
-    res, spec = {}, {}
-    for name in a.runs.split(","):
+    res, spectra_ = {}, {}
+    for spec in a.runs.split(","):
+        name, _, opts = spec.partition(":")
+        kv = dict(x.split("=") for x in opts.split(";") if x)
         jumps = name == "jump"
-        sim = jumpmd.Sim(sysm, split, S.water_params(dt=dt, jumps=jumps, seed=a.seed + 1))
+        sp = S.water_split(r_s=float(kv.get("rs", 5.0)), r_c=10.0, w=1.0, skin=0.5, n_rings=12)
+        pa = S.water_params(dt=dt, jumps=jumps, eps0_per_kcal=float(kv.get("eps0", 0.1)), seed=a.seed + 1)
+        sim = jumpmd.Sim(sysm, sp, pa)
         step = sim.step_jump if jumps else sim.step_baoab
         vs = np.empty((n, sysm.n_atoms, 3))
         for t in range(n):
@@ -96,16 +102,16 @@ def main():
             vs[t] = sim.state()[1]
         sim.close()
         nu, p = spectrum(vs, dt, sysm.mass)
-        spec[name] = p
+        spectra_[spec] = p
         c = vacf(vs, sysm.mass, n_lags=200)
-        res[name] = {"bands": band_summary(nu, p), "vacf_zero_crossing_fs": int(np.argmax(c < 0))}
-        print(f"[spectra] {name}: " + ", ".join(
+        res[spec] = {"bands": band_summary(nu, p), "vacf_zero_crossing_fs": int(np.argmax(c < 0))}
+        print(f"[spectra] {spec}: " + ", ".join(
             f"{k} {b['weight']:.3f}" + (f" @ {b['peak_cm']:.0f}" if b["peak_cm"] else "")
-            for k, b in res[name]["bands"].items()), flush=True)
-    if "baoab" in spec:
-        for name, p in spec.items():
-            if name != "baoab":
-                res[name]["l1_vs_baoab"] = float(np.abs(p - spec["baoab"]).sum())
+            for k, b in res[spec]["bands"].items()), flush=True)
+    if "baoab" in spectra_:
+        for k, p in spectra_.items():
+            if k != "baoab":
+                res[k]["l1_vs_baoab"] = float(np.abs(p - spectra_["baoab"]).sum())
     print(json.dumps({"workload": f"water_{a.n_mol}mol", "ps_each": a.ps, "resolution_cm": CM_PER_PS / a.ps,
                       "runs": res}), flush=True)
 

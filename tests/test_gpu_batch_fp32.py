@@ -30,15 +30,18 @@ def _batch():
     return S.Batch(systems), sp
 
 
-@pytest.mark.parametrize("scheme", ["jump", "baoab", "jump_respa"])
+@pytest.mark.parametrize("scheme", ["jump", "baoab", "jump_respa", "jump_bps"])
 def test_batched_replicas_match_single_replica_oracle(jm, scheme):
     from oracle.oracle import OracleSim
     batch, sp = _batch()
     pa = S.water_params(jumps=(scheme != "baoab"))
+    if scheme == "jump_bps":
+        pa.jump_coul = S.JUMP_BPS
     pa.log_events = 1
     pa.respa_inner = 3
     g = jm.Sim(batch, sp, pa)
-    run = {"jump": "step_jump", "baoab": "step_baoab", "jump_respa": "step_jump_respa"}[scheme]
+    run = {"jump": "step_jump", "baoab": "step_baoab", "jump_respa": "step_jump_respa",
+           "jump_bps": "step_jump"}[scheme]
     getattr(g, run)(6)
     xg, vg = g.state()
     sg = g.atom_stats()

@@ -589,22 +589,28 @@ def _gibbs_reference(sy, sp, kT, edges):
     return p / p.sum()
 
 
-@pytest.mark.parametrize("scheme", ["jump", "jump_bps", "baoab"])
+@pytest.mark.parametrize("scheme", ["jump", "jump_bps", "jump_respa", "baoab"])
 def test_two_particle_gibbs_marginal(scheme):
     """Two charged LJ particles: the distance histogram (r < L/2) of a long run
     matches p(r) ~ r^2 exp(-beta U(r)) by quadrature, and <v^2> = kT/m.
     JUMP uses BPS for the LJ long part and adaptive MRZ (jump_bps: BPS
-    bounces) for the Coulomb one."""
+    bounces) for the Coulomb one; jump_respa runs them at the outer step of
+    JUMP-RESPA with three inner steps (Sec. 3.3)."""
     sy = S.two_charges()
     sp = S.Split(r_s=3.0, r_c=5.0, switch_width=0.5, skin=0.3, coulomb_alpha=0.2)
     pa = S.Params(dt=0.005, gamma=2.0, kT=0.722, seed=3,
                   jump_lj=O.JUMP_BPS if scheme != "baoab" else 0,
-                  jump_coul={"jump": O.JUMP_MRZ_ADAPTIVE, "jump_bps": O.JUMP_BPS, "baoab": 0}[scheme], eps=0.5)
+                  jump_coul={"jump": O.JUMP_MRZ_ADAPTIVE, "jump_bps": O.JUMP_BPS, "jump_respa": O.JUMP_MRZ_ADAPTIVE,
+                             "baoab": 0}[scheme], eps=0.5)
+    pa.respa_inner = 3
     o = _oracle(sy, sp, pa)
     L = sy.box[0]
     rs, v2 = [], []
     for _ in range(6000):
-        (o.step_baoab if scheme == "baoab" else o.step_jump)(100)
+        if scheme == "jump_respa":
+            o.step_jump_respa(34)
+        else:
+            (o.step_baoab if scheme == "baoab" else o.step_jump)(100)
         x, v = o.state()
         d = x[1] - x[0]
         d -= L * np.rint(d / L)
@@ -620,4 +626,4 @@ def test_two_particle_gibbs_marginal(scheme):
     assert st.chi2.sf(chi2, len(cnt) - 1) > 1e-3, (cnt, exp.round(1))
     assert abs(np.mean(v2) - pa.kT) < 0.03 * pa.kT
     if scheme != "baoab":   # the jumps act (BPS accepts only on approach, so far fewer)
-        assert o.atom_stats()["n_acc"].sum() > (1000 if scheme == "jump" else 200)
+        assert o.atom_stats()["n_acc"].sum() > (200 if scheme == "jump_bps" else 1000)
