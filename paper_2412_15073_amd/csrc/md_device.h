@@ -136,7 +136,6 @@ struct MDView {
   const int *rep_cell_off;              // [nrep+1]
   const int *rep_cdim;                  // [3*nrep]
   int *cell_count, *cell_start, *cell_atoms, *atom_cell, *atom_slot;
-  int *cell_tmp;                        // [ncell] scratch of the cell scan
   double4 *xcell;                       // [n] build positions in cell order
   const int *cell_rep;                  // [ncell] replica of each cell
   const int *rep_off;                   // [nrep+1] first atom of each replica

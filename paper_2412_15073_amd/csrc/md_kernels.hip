@@ -124,45 +124,40 @@ __global__ void k_cell_count(MDView V, const double4 *__restrict__ X, int slot, 
   V.xref[i] = x;
 }
 
-// One block: exclusive scan of the cell counts (replicas that do not rebuild
-// contribute zero), then per rebuilding replica cell starts offset to the
-// replica's own atom range; the other replicas' cells are left untouched.
-__global__ __launch_bounds__(1024) void k_cell_scan(MDView V, int slot, int forced, int autob, double thr2,
-                                                    int count) {
-  __shared__ int part[1024];
-  const int T = blockDim.x, t = threadIdx.x, nc = V.ncell_total;
-  // nothing to do on steps where no replica rebuilds
-  int any = 0;
-  for (int r = t; r < V.nrep && !any; r += T) any = rebuild_now(V, slot, forced, autob, thr2, r) ? 1 : 0;
-  if (!__syncthreads_or(any)) return;
-  const int per = (nc + T - 1) / T;
-  const int b = min(nc, t * per), e = min(nc, b + per);
-  int s = 0;
-  for (int c = b; c < e; ++c) s += V.cell_count[c];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < T; off <<= 1) {
-    int v = (t >= off) ? part[t - off] : 0;
+// One block per replica: exclusive scan of the replica's cell counts into
+// cell starts offset to the replica's own atom range, counts cleared for the
+// next binning. Replicas that do not rebuild leave their cells untouched.
+// Tiles of 256 cells: coalesced loads, a shuffle scan per wave, the four wave
+// totals through LDS, and a running carry across tiles.
+__global__ __launch_bounds__(256) void k_cell_scan(MDView V, int slot, int forced, int autob, double thr2,
+                                                   int count) {
+  __shared__ int wsum[4];
+  const int r = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (r == 0 && t == 0) V.cell_start[V.ncell_total] = V.n;
+  if (!rebuild_now(V, slot, forced, autob, thr2, r)) return;   // uniform over the block
+  const int c0 = V.rep_cell_off[r], c1 = V.rep_cell_off[r + 1];
+  int carry = V.rep_off[r];
+  for (int base = c0; base < c1; base += 256) {
+    const int c = base + t;
+    const int v = c < c1 ? V.cell_count[c] : 0;
+    int x = v;   // inclusive scan within the wave
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
     __syncthreads();
-    part[t] += v;
-    __syncthreads();
+    int before = carry;
+    for (int q = 0; q < w; ++q) before += wsum[q];
+    const int tile = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (c < c1) {
+      V.cell_start[c] = before + x - v;
+      V.cell_count[c] = 0;
+    }
+    carry += tile;
+    __syncthreads();   // wsum is rewritten by the next tile
   }
-  int run = part[t] - s;
-  for (int c = b; c < e; ++c) {
-    V.cell_tmp[c] = run;
-    run += V.cell_count[c];
-  }
-  __syncthreads();
-  for (int c = b; c < e; ++c) {
-    const int r = V.cell_rep[c];
-    if (!rebuild_now(V, slot, forced, autob, thr2, r)) continue;
-    V.cell_start[c] = V.rep_off[r] + V.cell_tmp[c] - V.cell_tmp[V.rep_cell_off[r]];
-    V.cell_count[c] = 0;
-  }
-  if (t == 0) V.cell_start[nc] = V.n;
-  if (count)
-    for (int r = t; r < V.nrep; r += T)
-      if (rebuild_now(V, slot, forced, autob, thr2, r)) atomicAdd(&V.ctl->n_rebuilds, 1ull);
+  if (count && t == 0) atomicAdd(&V.ctl->n_rebuilds, 1ull);
 }
 
 __global__ void k_cell_scatter(MDView V, int slot, int forced, int autob, double thr2) {
@@ -768,7 +763,7 @@ hipError_t launch_rebuild(const MDView &V, const double4 *X, int want, int slot,
   hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(256), 0, s, V, X, slot, forced, autob, thr2);
   CHK(hipGetLastError());
   if (check_only) return hipSuccess;
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, V, slot, forced, autob, thr2, count);
+  hipLaunchKernelGGL(k_cell_scan, dim3(V.nrep), dim3(256), 0, s, V, slot, forced, autob, thr2, count);
   CHK(hipGetLastError());
   hipLaunchKernelGGL(k_cell_scatter, dim3(nb), dim3(256), 0, s, V, slot, forced, autob, thr2);
   CHK(hipGetLastError());
