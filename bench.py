@@ -43,7 +43,7 @@ BYTES_PER_ATOM_LOCAL = 7 * 32   # x (read+write), v (read+write), f_nb, f_b, x_r
 # scaled by a 256 MiB copy (profiles/k_chain_water4096_fp64.md), valid while the
 # sha256 of the chain kernel's sources (md_chain.hip, then md_device.h) starts
 # with the given prefix, default workload only.
-CHAIN_TRAFFIC = {"sha256": "91521154159d6548", "bytes": 37556154,
+CHAIN_TRAFFIC = {"sha256": "35aa22ab282dcad4", "bytes": 37496513,
                  "workload": ("fp64", 4096, 12, 0.5, 0.1, 0, False, 10.0)}
 KERNELS = {0: "k_local (B/A/O updates)", 1: "k_force (pairs, with bonded when fused)", 2: "k_bonded (separate)", 3: "row rebuild",
            4: "k_chain (J/C jump chains)"}

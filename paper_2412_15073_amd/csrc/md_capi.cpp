@@ -654,7 +654,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   A(d_bij, std::max(1, 2 * s->n_bonds)); A(d_bk, std::max(1, s->n_bonds)); A(d_br0, std::max(1, s->n_bonds));
   A(d_aijk, std::max(1, 3 * s->n_angles)); A(d_ak, std::max(1, s->n_angles)); A(d_at0, std::max(1, s->n_angles));
   A(V.cell_count, V.ncell_total); A(V.cell_start, V.ncell_total + 1); A(V.cell_atoms, n);
-  A(V.rep_maxd2, 2 * nrep); A(V.xcell, n);
+  A(V.rep_maxd2, 2 * nrep); A(V.xcell, n); A(V.xcellf, n);
   int *d_chain_perm;
   A(d_chain_perm, chain_perm.size());
   int *d_cell_rep;

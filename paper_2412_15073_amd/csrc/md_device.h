@@ -137,6 +137,7 @@ struct MDView {
   const int *rep_cdim;                  // [3*nrep]
   int *cell_count, *cell_start, *cell_atoms, *atom_cell, *atom_slot;
   double4 *xcell;                       // [n] build positions in cell order
+  float4 *xcellf;                       // [n] the same wrapped into the box, float (row prefilter)
   const int *cell_rep;                  // [ncell] replica of each cell
   const int *rep_off;                   // [nrep+1] first atom of each replica
   unsigned long long *rep_maxd2;        // [2*nrep] max |x - x_ref|^2 (double bits) per step parity and replica

@@ -165,7 +165,12 @@ __global__ void k_cell_scatter(MDView V, int slot, int forced, int autob, double
   if (i >= V.n || !rebuild_now(V, slot, forced, autob, thr2, V.rep[i])) return;
   const int p = V.cell_start[V.atom_cell[i]] + V.atom_slot[i];
   V.cell_atoms[p] = i;
-  V.xcell[p] = V.xref[i];   // positions in cell order: contiguous reads in the row builder
+  const double4 x = V.xref[i];
+  V.xcell[p] = x;   // positions in cell order: contiguous reads in the row builder
+  const int r = V.rep[i];
+  const double Lx = V.box[3 * r], Ly = V.box[3 * r + 1], Lz = V.box[3 * r + 2];
+  V.xcellf[p] = make_float4((float)(x.x - Lx * floor(x.x / Lx)), (float)(x.y - Ly * floor(x.y / Ly)),
+                            (float)(x.z - Lz * floor(x.z / Lz)), 0.0f);
 }
 
 __device__ __forceinline__ void bitonic_sort_lds(unsigned *keys, int m) {
@@ -333,14 +338,19 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
   int span = 0;   // per lane: the span holding its current flat index (indices only grow)
   // Pass 1: a float distance filter over the whole stencil queues the
   // cell-array indices of the atoms that may lie within the outer cutoff
-  // (in kc, which pass 2 overwrites only at slots it has already read). The
-  // margin covers the float rounding of the FP64 difference and of the
-  // minimum image with a factor above 8 (positions are not wrapped).
+  // (in kc, which pass 2 overwrites only at slots it has already read). It
+  // reads the float copy of the positions wrapped into the box (16 B per
+  // stencil atom instead of 32). The margin covers the rounding of the
+  // wrapped coordinates, of their difference and of the minimum image (each
+  // a few float ulps of L) with a factor above 8.
   const double rcut = (want & 6) ? V.rout : rs_out;
   const float Lf[3] = {(float)L[0], (float)L[1], (float)L[2]};
   const float iLf[3] = {(float)iL[0], (float)iL[1], (float)iL[2]};
   const float margin0 = 1e-3f + 3e-6f * (Lf[0] + Lf[1] + Lf[2]);
   const float rcf = (float)rcut;
+  const float xiw = (float)(xi.x - L[0] * floor(xi.x / L[0]));
+  const float yiw = (float)(xi.y - L[1] * floor(xi.y / L[1]));
+  const float ziw = (float)(xi.z - L[2] * floor(xi.z / L[2]));
   int nq = 0;
   for (int base = 0; base < total; base += 64) {
     const int f = base + lane;
@@ -349,8 +359,8 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
     if (f < total) {
       while (s_pre[span + 1] <= f) ++span;
       q = s_beg[span] + (f - s_pre[span]);
-      const double4 xj = V.xcell[q];
-      float dx = (float)(xi.x - xj.x), dy = (float)(xi.y - xj.y), dz = (float)(xi.z - xj.z);
+      const float4 xj = V.xcellf[q];
+      float dx = xiw - xj.x, dy = yiw - xj.y, dz = ziw - xj.z;
       const float rc_m = rcf + margin0 + 1e-6f * (fabsf(dx) + fabsf(dy) + fabsf(dz));
       dx -= Lf[0] * rintf(dx * iLf[0]);
       dy -= Lf[1] * rintf(dy * iLf[1]);
