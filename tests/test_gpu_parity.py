@@ -73,6 +73,32 @@ def test_candidate_rows(jm, case):
         np.testing.assert_array_equal(sg, o.seg_start(i), err_msg=f"segments {i}")
 
 
+def test_rows_with_far_unwrapped_positions(jm):
+    """Unwrapped positions far outside the box (whole molecules shifted by up
+    to +-40 box lengths, as long runs accumulate): the row builder's float
+    prefilter works on positions wrapped into the box, so rows and a few JUMP
+    steps still match the oracle exactly."""
+    sy, sp = water_small()
+    L = sy.box[0]
+    rng = np.random.default_rng(9)
+    shift = rng.integers(-40, 41, size=(sy.n_atoms // 3, 3)).repeat(3, axis=0) * L
+    sy.pos = sy.pos + shift
+    pa = S.water_params()
+    pa.log_events = 1
+    g, o = _pair(jm, sy, sp, pa)
+    o.build_lists()
+    S_ = o.n_segments
+    for i in range(sy.n_atoms):
+        jg, sg = g.cand_row(i, S_)
+        np.testing.assert_array_equal(jg, o.cand_row(i), err_msg=f"row {i}")
+        np.testing.assert_array_equal(sg, o.seg_start(i), err_msg=f"segments {i}")
+    g.step_jump(6)
+    o.step_jump(6)
+    _compare_state(g, o)
+    _compare_stats(g, o)
+    np.testing.assert_array_equal(g.events(), o.events())
+
+
 def test_long_candidate_rows_and_jumps(jm):
     """Rows longer than 1024 candidates (r_c = 14 A water: ~1300 per atom),
     which the row builder sorts with its LDS network instead of registers;
