@@ -318,6 +318,22 @@ def test_bps_coulomb_jump_respa(jm):
     np.testing.assert_array_equal(g.events(), o.events())
 
 
+def test_jump_respa_with_one_inner_step_is_jump_on_gpu(jm):
+    """With one inner step and no bonded terms, JUMP-RESPA reduces to JUMP:
+    the GPU's two program layouts (one launch pair per step, against inner
+    loops with separate bonded evaluations) must give the same bits."""
+    sy, sp = lj_small()
+    pa = S.lj_params()
+    pa.log_events = 1
+    pa.respa_inner = 1
+    a, b = jm.Sim(sy, sp, pa), jm.Sim(sy, sp, pa)
+    a.step_jump(30)
+    b.step_jump_respa(30)
+    (xa, va), (xb, vb) = a.state(), b.state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    np.testing.assert_array_equal(a.events(), b.events())
+
+
 @pytest.mark.parametrize("lanes", [1, 8])
 def test_lj_chain_lanes(jm, lanes):
     sy, sp = lj_small()

@@ -385,6 +385,23 @@ def test_velocity_verlet_energy_error_scales_as_dt_squared():
     assert 3.0 < ratio < 5.3, ratio
 
 
+def test_jump_respa_with_one_inner_step_is_jump():
+    """Special case of the JUMP-RESPA composition (Sec. 3.3): with one inner
+    step and no bonded terms, the inner bonded kicks vanish and the scheme is
+    C' J' A O A J' C' at the same step, so it must reproduce JUMP bit for bit
+    (same random streams, same events)."""
+    sy, sp = lj_small()
+    pa = S.lj_params()
+    pa.log_events = 1
+    pa.respa_inner = 1
+    a, b = _oracle(sy, sp, pa), _oracle(sy, sp, pa)
+    a.step_jump(30)
+    b.step_jump_respa(30)
+    (xa, va), (xb, vb) = a.state(), b.state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    assert len(a.events()) > 50 and np.array_equal(a.events(), b.events())
+
+
 @pytest.mark.parametrize("coul", [O.JUMP_MRZ_ADAPTIVE, O.JUMP_BPS])
 def test_thinning_exact_under_bound_inflation(coul):
     """Poisson thinning does not depend on the bound (Sec. 2.4): inflating all
