@@ -334,6 +334,17 @@ def test_jump_respa_with_one_inner_step_is_jump_on_gpu(jm):
     np.testing.assert_array_equal(a.events(), b.events())
 
 
+def test_baoab_respa_with_one_inner_step_is_baoab_on_gpu(jm):
+    sy, sp = lj_small()
+    pa = S.lj_params(jumps=False)
+    pa.respa_inner = 1
+    a, b = jm.Sim(sy, sp, pa), jm.Sim(sy, sp, pa)
+    a.step_baoab(30)
+    b.step_baoab_respa(30)
+    (xa, va), (xb, vb) = a.state(), b.state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+
+
 @pytest.mark.parametrize("lanes", [1, 8])
 def test_lj_chain_lanes(jm, lanes):
     sy, sp = lj_small()

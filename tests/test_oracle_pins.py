@@ -402,6 +402,18 @@ def test_jump_respa_with_one_inner_step_is_jump():
     assert len(a.events()) > 50 and np.array_equal(a.events(), b.events())
 
 
+def test_baoab_respa_with_one_inner_step_is_baoab():
+    """Same reduction for the comparator: one inner step, no bonded terms."""
+    sy, sp = lj_small()
+    pa = S.lj_params(jumps=False)
+    pa.respa_inner = 1
+    a, b = _oracle(sy, sp, pa), _oracle(sy, sp, pa)
+    a.step_baoab(30)
+    b.step_baoab_respa(30)
+    (xa, va), (xb, vb) = a.state(), b.state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+
+
 @pytest.mark.parametrize("coul", [O.JUMP_MRZ_ADAPTIVE, O.JUMP_BPS])
 def test_thinning_exact_under_bound_inflation(coul):
     """Poisson thinning does not depend on the bound (Sec. 2.4): inflating all
