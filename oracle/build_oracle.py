@@ -8,15 +8,17 @@ SRC = os.path.join(HERE, "jumpmd_oracle.c")
 OUT = os.path.join(HERE, "libjumpmd_oracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = OUT, plant: int = 0) -> str:
+    """Compile the oracle into `out`; plant > 0 builds the mutant with planted
+    mistake `plant` (mutation tests only)."""
     # -O2 without fast-math: IEEE semantics, no reassociation; no FMA contraction
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-Wall", "-Wno-unused-function", "-o", OUT + ".tmp", SRC, "-lm"]
+           "-Wall", "-Wno-unused-function", f"-DORC_PLANT={int(plant)}", "-o", out + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(OUT + ".tmp", OUT)
-    return OUT
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -41,6 +41,13 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Planted mistakes for the mutation tests (tests/test_oracle_mutants.py):
+ * a build with -DORC_PLANT=k > 0 plants mistake k, which at least one pin of
+ * tests/test_oracle_pins.py must catch. The default build plants nothing. */
+#ifndef ORC_PLANT
+#define ORC_PLANT 0
+#endif
+
 #define PI 3.14159265358979323846
 #define ZS_MAXIT 64
 #define MAX_PROPOSALS (1ll << 22) /* per chain and half step */
@@ -830,6 +837,36 @@ int orc_step_jump(orc_sim *s, int64_t n) {
   return 0;
 }
 
+/* The inner loop shared by JUMP-RESPA and BAOAB-RESPA (Sec. 2.3.2): m
+ * steps B_b A O A B_b of length dt = 2h with the bonded forces only, the
+ * bonded forces re-evaluated after each pair of drifts; the O draw of inner
+ * step `sub` carries `sub` in its counter. */
+static void respa_inner_steps(orc_sim *s, int m, double h) {
+  for (int sub = 0; sub < m; sub++) {
+#if ORC_PLANT == 1   /* planted mistake: the opening inner kick of the first inner step is dropped */
+    if (sub > 0) kick(s, h, 0, 1);
+#elif ORC_PLANT == 2 /* planted mistake: inner kicks last the outer half step m*h */
+    kick(s, m * h, 0, 1);
+#else
+    kick(s, h, 0, 1);
+#endif
+    drift(s, h);
+    orc_phase_o(s, s->dt, sub);
+    drift(s, h);
+#if ORC_PLANT == 3   /* planted mistake: the bonded forces are not re-evaluated after the drifts */
+    if (sub == m - 1) bonded_forces(s, s->fb);
+#else
+    bonded_forces(s, s->fb);
+#endif
+    s->fb_valid = 1;
+#if ORC_PLANT == 2
+    kick(s, m * h, 0, 1);
+#else
+    kick(s, h, 0, 1);
+#endif
+  }
+}
+
 /* JUMP-RESPA (Sec. 2.3.2 and Sec. 3.3): bonded forces at the inner step dt,
  * short non-bonded forces and all jumps at the outer step n*dt. Inner steps
  * are B_b A O A B_b; the O draw carries the inner index. As in JUMP, the
@@ -843,15 +880,7 @@ int orc_step_jump_respa(orc_sim *s, int64_t n_outer) {
   for (int64_t it = 0; it < n_outer; it++) {
     c_or_b(s, ORC_PH_C1, H, 1, STREAM_CONTINUE);
     if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J1, H);
-    for (int sub = 0; sub < m; sub++) {
-      kick(s, h, 0, 1);
-      drift(s, h);
-      orc_phase_o(s, s->dt, sub);
-      drift(s, h);
-      bonded_forces(s, s->fb);
-      s->fb_valid = 1;
-      kick(s, h, 0, 1);
-    }
+    respa_inner_steps(s, m, h);
     maybe_rebuild(s);
     ensure_forces(s, ORC_F_SHORT);
     if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J2, H);
@@ -868,15 +897,7 @@ int orc_step_baoab_respa(orc_sim *s, int64_t n_outer) {
   ensure_forces(s, ORC_F_FULL);
   for (int64_t it = 0; it < n_outer; it++) {
     kick(s, H, 1, 0);
-    for (int sub = 0; sub < m; sub++) {
-      kick(s, h, 0, 1);
-      drift(s, h);
-      orc_phase_o(s, s->dt, sub);
-      drift(s, h);
-      bonded_forces(s, s->fb);
-      s->fb_valid = 1;
-      kick(s, h, 0, 1);
-    }
+    respa_inner_steps(s, m, h);
     maybe_rebuild(s);
     ensure_forces(s, ORC_F_FULL);
     kick(s, H, 1, 0);
@@ -1062,7 +1083,11 @@ void orc_rdf(const orc_sim *s, int ta, int tb, double r_max, int n_bins, double 
       if (!((a == ta && b == tb) || (a == tb && b == ta))) continue;
       double d[3], r = pair_vec(s, i, j, d);
       if (r >= r_max) continue;
+#if ORC_PLANT == 4   /* planted mistake: bins rounded to the nearest edge */
+      int bin = (int)(r / dr + 0.5);
+#else
       int bin = (int)(r / dr);
+#endif
       if (bin < n_bins) hist[bin] += 1.0;
     }
 }

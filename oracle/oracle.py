@@ -12,6 +12,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libjumpmd_oracle.so")
+# JUMPMD_ORACLE_LIBRARY may name another build of the oracle (the mutation
+# tests load builds with a planted mistake this way)
+_LIB_ENV = "JUMPMD_ORACLE_LIBRARY"
 
 JUMP_NONE, JUMP_BPS, JUMP_MRZ_CONST, JUMP_MRZ_ADAPTIVE = 0, 1, 2, 3
 PH_O, PH_J1, PH_J2, PH_C1, PH_C2 = 1, 2, 3, 4, 5
@@ -55,10 +58,11 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = os.environ.get(_LIB_ENV, LIB_PATH)
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
             from oracle import build_oracle
             build_oracle.build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(OrcSystem), C.POINTER(OrcSplit), C.POINTER(OrcParams),
                                  C.c_char_p, C.c_int]

@@ -1,0 +1,45 @@
+"""Mutation tests of the oracle's pins (CPU only).
+
+The oracle source holds a few planted mistakes behind ORC_PLANT (off in the
+normal build). Each one is built into its own library here and the pins
+named for it are run against that build in a child process: every planted
+mistake must make at least one of them fail, while the normal build passes
+them (tests/test_oracle_pins.py).
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from oracle import build_oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# planted mistake -> pins that must catch it
+PLANTS = {
+    1: ("dropped opening inner bonded kick of RESPA",
+        ["test_respa_inner_loop_is_baoab_on_bonded_water"]),
+    2: ("RESPA inner kicks of the outer length",
+        ["test_respa_inner_loop_is_baoab_on_bonded_water", "test_jump_respa_samples_the_bond_length_law"]),
+    3: ("stale bonded forces inside the RESPA inner loop",
+        ["test_respa_inner_loop_is_baoab_on_bonded_water"]),
+    4: ("pair histogram bins rounded to the nearest edge",
+        ["test_rdf_counts_on_rock_salt_lattice"]),
+}
+
+
+@pytest.mark.parametrize("plant", sorted(PLANTS))
+def test_planted_mistake_is_caught(plant, tmp_path):
+    what, pins = PLANTS[plant]
+    lib = build_oracle.build(out=str(tmp_path / f"liboracle_plant{plant}.so"), plant=plant)
+    env = dict(os.environ, JUMPMD_ORACLE_LIBRARY=lib)
+    caught = []
+    for pin in pins:
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            f"tests/test_oracle_pins.py::{pin}"], cwd=ROOT, env=env,
+                           capture_output=True, text=True, timeout=600)
+        caught.append(r.returncode != 0)
+    assert any(caught), f"planted mistake {plant} ({what}) passed every pin: {pins}"
+    # the pins named first are the ones meant for it: all of them must fail
+    assert all(caught), f"planted mistake {plant} ({what}) slipped past {[p for p, c in zip(pins, caught) if not c]}"

@@ -414,6 +414,107 @@ def test_baoab_respa_with_one_inner_step_is_baoab():
     assert np.array_equal(xa, xb) and np.array_equal(va, vb)
 
 
+def _bonds_only(sy):
+    """The same molecules with no charges and no LJ: only bonds and angles act."""
+    return S.with_(sy, charge=np.zeros(sy.n_atoms), lj_eps=np.zeros_like(sy.lj_eps))
+
+
+@pytest.mark.parametrize("scheme", ["baoab_respa", "jump_respa"])
+def test_respa_inner_loop_is_baoab_on_bonded_water(scheme):
+    """Special case of the RESPA compositions (Sec. 2.3.2, Sec. 3.3) on
+    molecules with bonds and angles but no non-bonded terms, at gamma = 0:
+    the outer non-bonded kicks (or C' with no candidates) add exactly zero
+    and O is the identity, so n outer steps of 3 inner steps B_b A O A B_b
+    must reproduce 3n BAOAB steps at the inner step bit for bit. A dropped,
+    doubled, mistimed or stale inner bonded kick breaks this (BAOAB itself is
+    pinned by the dt^2 energy law on bonded water)."""
+    sy, sp = water_small()
+    sy = _bonds_only(sy)
+    pa = S.water_params(gamma=0.0, jumps=(scheme == "jump_respa"))
+    pa.respa_inner = 3
+    a, b = _oracle(sy, sp, pa), _oracle(sy, sp, pa)
+    a.step_baoab(60)
+    (b.step_jump_respa if scheme == "jump_respa" else b.step_baoab_respa)(20)
+    (xa, va), (xb, vb) = a.state(), b.state()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    assert rel_err(vb, sy.vel) > 1e-2   # the bonded forces did act
+
+
+def test_baoab_respa_energy_error_scales_as_step_squared():
+    """BAOAB-RESPA at gamma = 0 with all forces on (bonded at the inner step,
+    full-range non-bonded at the outer step, Sec. 2.3.2) is a symplectic
+    second-order integrator: with the inner count fixed, halving the inner
+    (and so the outer) step cuts the total-energy fluctuation about 4x."""
+    sy, sp = water_small(n_mol=125)
+    flucts = []
+    for dt in (0.0002, 0.0001):
+        pa = S.water_params(dt=dt, gamma=0.0, jumps=False)
+        pa.respa_inner = 3
+        o = _oracle(sy, sp, pa)
+        es = []
+        for _ in range(10):
+            o.step_baoab_respa(int(round(0.0024 / (3 * dt))))
+            e = o.energies()
+            es.append(e["ke"] + e["pe_full"])
+        flucts.append(np.std(es))
+    ratio = flucts[0] / flucts[1]
+    assert 3.0 < ratio < 5.3, ratio
+
+
+def test_jump_respa_samples_the_bond_length_law():
+    """One flexible water molecule under JUMP-RESPA (3 inner steps of
+    0.5 fs, gamma 50/ps): the O-H bond length b has the marginal
+    b^2 exp(-beta k_b (b - b0)^2 / 2) of the Gibbs measure (the bonded energy
+    separates in (b1, b2, theta) with Jacobian b1^2 b2^2 sin(theta)); the
+    histogram matches it by quadrature, and <v^2> = kT/m per component."""
+    sy = S.water_box(1, density=1.0 / 27000.0, seed=2, jitter=0.02)   # box 30 A
+    sp = S.water_split(r_s=5.0, r_c=7.0, w=1.0, skin=0.5, n_rings=1)
+    pa = S.water_params(dt=0.0005, gamma=50.0)
+    pa.respa_inner = 3
+    o = _oracle(sy, sp, pa)
+    kT, kb, b0 = pa.kT, sy.bond_k[0], sy.bond_r0[0]
+    bs, ke = [], []
+    for _ in range(12000):
+        o.step_jump_respa(40)   # 60 fs
+        x, v = o.state()
+        bs += [np.linalg.norm(x[1] - x[0]), np.linalg.norm(x[2] - x[0])]
+        ke.append((0.5 * sy.mass[:, None] * v * v).sum() / S.ACCEL_KJ)
+    bs = np.array(bs)
+    sd = np.sqrt(kT / kb)
+    edges = b0 + sd * np.array([-3.5, -2.0, -1.2, -0.6, -0.2, 0.2, 0.6, 1.2, 2.0, 3.5])
+    dens = lambda b: b * b * np.exp(-0.5 * kb * (b - b0) ** 2 / kT)
+    p = np.array([si.quad(dens, lo, hi, epsabs=0)[0] for lo, hi in zip(edges[:-1], edges[1:])])
+    sel = bs[(bs >= edges[0]) & (bs < edges[-1])]
+    cnt, _ = np.histogram(sel, edges)
+    exp = p / p.sum() * len(sel)
+    chi2 = ((cnt - exp) ** 2 / exp).sum()
+    assert st.chi2.sf(chi2, len(cnt) - 1) > 1e-3, (cnt, exp.round(1))
+    # 9 degrees of freedom: <KE> = 9 kT / 2 within 3 %
+    assert abs(np.mean(ke) / (4.5 * kT) - 1.0) < 0.03, np.mean(ke) / (4.5 * kT)
+
+
+def test_rdf_counts_on_rock_salt_lattice():
+    """Pair-count histogram against the coordination shells of a rock-salt
+    lattice (6 x 6 x 6 sites, spacing a, alternating types): unlike pairs at
+    a, sqrt(3) a, sqrt(5) a (6, 8, 24 per site), like pairs at sqrt(2) a, 2a,
+    sqrt(6) a, sqrt(8) a (12, 6, 24, 12 per site), every shell below L/2."""
+    a = 1.53
+    sy = S.ion_lattice(6, a, jitter=0.0)
+    sp = S.Split(r_s=2.0, r_c=3.0, switch_width=0.5, skin=0.3)
+    o = _oracle(sy, sp, S.Params(dt=0.001, gamma=1.0, kT=1.0))
+    n_half = sy.n_atoms // 2
+    r_max, nb = 4.5, 45
+    dr = r_max / nb
+    for (ta, tb), shells in (((0, 1), {1: 6, 3: 8, 5: 24}), ((0, 0), {2: 12 // 2, 4: 6 // 2, 6: 24 // 2, 8: 12 // 2}),
+                             ((1, 1), {2: 12 // 2, 4: 6 // 2, 6: 24 // 2, 8: 12 // 2})):
+        want = np.zeros(nb)
+        for sq, z in shells.items():
+            r = a * np.sqrt(sq)
+            assert abs(r / dr - round(r / dr)) > 0.05   # no shell on a bin edge
+            want[int(r / dr)] += n_half * z
+        np.testing.assert_array_equal(o.rdf_counts(ta, tb, r_max, nb), want)
+
+
 @pytest.mark.parametrize("coul", [O.JUMP_MRZ_ADAPTIVE, O.JUMP_BPS])
 def test_thinning_exact_under_bound_inflation(coul):
     """Poisson thinning does not depend on the bound (Sec. 2.4): inflating all
