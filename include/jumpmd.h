@@ -5,15 +5,21 @@
  *
  * Every step runs in HIP kernels on the caller's stream. Host pointers passed
  * in are read during the call and never retained (the caller keeps
- * ownership); device memory belongs to the context and is released by
- * md_destroy. No call throws: every function returns MD_OK (0) or a negative
- * MD_ERR_* code, and md_last_error() gives a message for the last failure.
+ * ownership). Device memory of a context comes from the caller's allocator
+ * (md_allocator, e.g. PyTorch's caching allocator, which then owns its
+ * lifetime) or, without one, from hipMalloc; md_destroy returns all of it.
+ * No call throws: every function returns MD_OK (0) or a negative MD_ERR_*
+ * code, and md_last_error() gives a message for the last failure.
  *
  * Stepping calls are asynchronous on the context's stream. md_observables,
  * md_get_*, md_sync and md_profile_read synchronise the stream and report
- * device-side error flags (bound violations in strict mode, list capacity
- * overflow, list invalidation, non-finite state) raised by earlier steps.
- * One context per host thread; contexts are independent.
+ * device-side error flags (bound violations in strict mode, list
+ * invalidation, non-finite state) raised by earlier steps. A neighbour row
+ * that outgrew its capacity is not an error: the synchronising call restores
+ * the state of the last good synchronisation, regrows the rows and replays
+ * the stepping calls made since, so results are those of a run with enough
+ * capacity from the start. One context per host thread; contexts are
+ * independent.
  *
  * Units are the caller's: lengths, times, masses, energies and charges must
  * be consistent, with accel_factor converting force/mass to length/time^2
@@ -37,7 +43,11 @@ extern "C" {
 #define MD_ERR_LIST (-4)      /* displacement beyond skin/2 on a fixed rebuild period */
 #define MD_ERR_UNSTABLE (-5)  /* non-finite kinetic energy */
 #define MD_ERR_OOM (-6)       /* device allocation failed */
-#define MD_ERR_CAPACITY (-7)  /* a neighbour row overflowed its capacity (rows regrown; state rolled forward) */
+#define MD_ERR_CAPACITY (-7)  /* rows would exceed the row builder's limits (8192 candidates, 4096 short
+                                 entries per atom) even after regrowing; the state is then that of the
+                                 last good synchronisation (the stepping calls since are not applied) */
+#define MD_ERR_EVENTS (-8)    /* md_get_events: more accepted jumps were logged than the log holds
+                                 (2^22); the events kept are an unspecified subset */
 
 /* jump kinds (Sec. 2.2 of the paper) */
 #define MD_JUMP_NONE 0
@@ -98,11 +108,23 @@ typedef struct {
   double ring_width;
 } md_split;
 
+/* Device memory for a context (md_create): alloc returns `bytes` of device
+ * memory usable on `stream` (NULL on failure), release gives it back. Both
+ * are called only inside md_create, the synchronising calls (when rows are
+ * regrown), md_rdf (first use of a histogram size) and md_destroy, never
+ * during stepping or graph capture. ctx is passed through unchanged. */
+typedef struct {
+  void *ctx;
+  void *(*alloc)(void *ctx, size_t bytes, void *stream);
+  void (*release)(void *ctx, void *ptr, size_t bytes, void *stream);
+} md_allocator;
+
 typedef struct {
   double dt;            /* time step (inner step for the RESPA schemes) */
   double gamma;         /* friction */
   double kT;            /* energy */
-  uint64_t seed;        /* Philox4x64-10 key word 0; key word 1 = replica index */
+  uint64_t seed;        /* counter-based Philox4x32-10 key: (low 32 bits of seed, high 32 bits of
+                           seed xor replica index); counters (step, local atom, phase tag, draw) */
   int32_t jump_lj;      /* MD_JUMP_NONE or MD_JUMP_BPS (J step, Alg. 5) */
   int32_t jump_coul;    /* MD_JUMP_NONE, MD_JUMP_MRZ_CONST or MD_JUMP_MRZ_ADAPTIVE (C step, Alg. 4),
                            or MD_JUMP_BPS: bounces of Sec. 3.2 in the C step (the eps -> infinity
@@ -118,6 +140,11 @@ typedef struct {
   int32_t graph_steps;  /* 0: launch kernels step by step; K > 0 (even): md_step_jump and
                            md_step_baoab replay a captured HIP graph of K steps (needs
                            rebuild_every == 0; results do not depend on it) */
+  double bound_scale;   /* every jump-rate bound multiplied by this (0 or 1: the bounds as derived).
+                           Thinning is exact for any valid bound (Sec. 2.4): > 1 leaves the law
+                           unchanged; < 1 makes bounds invalid (counted; MD_ERR_BOUND in strict mode) */
+  double row_capacity;  /* initial row capacity as a multiple of the density estimate (0: 1.5);
+                           rows regrow on demand, so this only trades memory for early regrows */
 } md_params;
 
 typedef struct {
@@ -127,6 +154,7 @@ typedef struct {
   double pe_short, pe_long, pe_bonded;  /* filled when MD_OBS_PE is set */
   int64_t n_prop, n_acc, n_bound_viol, n_rebuilds, n_zsampler_overflow, n_list_errors;
   uint64_t event_hash;  /* FNV-1a over the per-atom event hashes, atom order */
+  int64_t n_regrows;    /* times the rows were regrown and the steps replayed */
 } md_obs;
 
 typedef struct {          /* one accepted jump */
@@ -139,12 +167,17 @@ typedef struct {          /* one accepted jump */
 
 typedef struct md_ctx md_ctx;
 
-/* Create a context: validates the input, computes the bound tables, uploads
- * the system, builds the neighbour rows and evaluates the initial forces on
- * `stream` (a hipStream_t; NULL = default stream). On failure *out is NULL
- * and the return code says why (message via md_last_error(NULL)). */
+/* Create a context for the JUMP integrator (Sec. 2.3 step composition,
+ * Sec. 3.1 short/long split, Alg. 4/5 jump chains): validates the input
+ * (MD_ERR_ARG: shapes, ranges, indices outside [0, N) or outside their
+ * replica, non-monotone replica or exclusion offsets), computes the rate
+ * bounds of the ring technique (Sec. 3.1.1), uploads the system and sets up
+ * the jump-chain layout on `stream` (a hipStream_t; NULL: a private
+ * non-blocking stream). alloc may be NULL (hipMalloc). On failure *out is
+ * NULL and the code says why (message via md_last_error(NULL)); MD_ERR_OOM
+ * when an allocation failed. Rows and forces are built at the first step. */
 int md_create(const md_system *sys, const md_split *split, const md_params *par,
-              void *stream, md_ctx **out);
+              void *stream, const md_allocator *alloc, md_ctx **out);
 void md_destroy(md_ctx *ctx);
 const char *md_last_error(const md_ctx *ctx);
 
@@ -159,13 +192,18 @@ int md_step_jump_respa(md_ctx *ctx, int64_t n_outer);
 /* BAOAB-RESPA comparator: full-range non-bonded kick at the outer step. */
 int md_step_baoab_respa(md_ctx *ctx, int64_t n_outer);
 
-/* Synchronise and report; flags = 0 or MD_OBS_PE. */
+/* Synchronise and report the observables of Sec. 4: kinetic energy and
+ * temperature 2 KE / (3 N kB) (no centre-of-mass constraint), jump
+ * statistics, and with MD_OBS_PE the potential energies of the split
+ * (Sec. 3.1): short part chi U, long part (1 - chi) U (pairs r < r_c,
+ * each once) and bonded. Returns the first pending error (above). */
 int md_observables(md_ctx *ctx, uint32_t flags, md_obs *out);
 int md_sync(md_ctx *ctx);
 
-/* Host copies of the state ([3N] each, either may be NULL). md_set_state
- * rebuilds the neighbour rows and forces at the new positions; step < 0
- * keeps the step counter. */
+/* Host copies of the state (x, v of Sec. 2.1; [3N] each, either may be
+ * NULL; positions unwrapped). md_set_state rebuilds the neighbour rows and
+ * forces at the new positions at the next step; step < 0 keeps the step
+ * counter. Both synchronise. */
 int md_get_state(md_ctx *ctx, double *pos, double *vel);
 int md_set_state(md_ctx *ctx, const double *pos, const double *vel, int64_t step);
 /* Current accelerations [3N]: kind 0 = short non-bonded, 1 = full non-bonded,
@@ -173,7 +211,9 @@ int md_set_state(md_ctx *ctx, const double *pos, const double *vel, int64_t step
 int md_get_accel(md_ctx *ctx, int32_t kind, double *acc);
 /* Per-atom jump statistics [N] each (any may be NULL). */
 int md_get_atom_stats(md_ctx *ctx, int64_t *n_prop, int64_t *n_acc, int64_t *n_viol, uint64_t *hash);
-/* Accepted-jump log (log_events = 1), sorted by (step, phase, atom, proposal). */
+/* Accepted-jump log (log_events = 1), sorted by (step, phase, atom,
+ * proposal); the log holds 2^22 events since creation. buf may be NULL to
+ * query *n. MD_ERR_EVENTS when events were lost (*n = those kept). */
 int md_get_events(md_ctx *ctx, md_event *buf, int64_t cap, int64_t *n);
 /* Pair histogram of types (ta, tb) over [0, r_max) in n_bins bins, pairs
  * inside each replica (minimum image), unordered when ta == tb. */

@@ -215,6 +215,7 @@ struct orc_sim {
   int64_t *nprop, *nacc, *nviol; uint64_t *hash;
   int64_t *knext;   /* per atom: first unused proposal of the last closing C' stream */
   int64_t n_rebuilds, n_zs_overflow, n_list_err;
+  int64_t zs_regime[3];   /* accepted MRZ jumps by Z-sampler regime: eta < -1, -1 <= eta <= 0, eta > 0 */
   int64_t nev, evcap; int64_t *ev;
 };
 
@@ -713,6 +714,7 @@ static int64_t cstep_atom(orc_sim *s, int i, int32_t phase, double h, const doub
         int32_t it;
         double Z = orc_zsample(eta, s->seed, s->replica, rstep, i, rphase, k, &it);
         if (it < 0) s->n_zs_overflow++;
+        s->zs_regime[eta < -1.0 ? 0 : (eta <= 0.0 ? 1 : 2)]++;
         /* Eq. (majvitesse) restricted to atom i (Sec. 3.1) */
         double coef;
         if (adaptive) coef = 2.0 * eps0 * Z / ((1.0 + eps0 * eps0 * F2) * sqrt(beta * me));
@@ -1029,6 +1031,9 @@ int64_t orc_step_index(const orc_sim *s) { return s->step; }
 int64_t orc_n_rebuilds(const orc_sim *s) { return s->n_rebuilds; }
 int64_t orc_n_zsampler_overflow(const orc_sim *s) { return s->n_zs_overflow; }
 int64_t orc_n_list_errors(const orc_sim *s) { return s->n_list_err; }
+void orc_zsampler_regimes(const orc_sim *s, int64_t out[3]) {
+  for (int q = 0; q < 3; q++) out[q] = s->zs_regime[q];
+}
 
 void orc_atom_stats(const orc_sim *s, int64_t *nprop, int64_t *nacc, int64_t *nviol, uint64_t *hash) {
   size_t n = (size_t)s->n;

@@ -96,6 +96,8 @@ int64_t orc_step_index(const orc_sim *s);
 int64_t orc_n_rebuilds(const orc_sim *s);
 int64_t orc_n_zsampler_overflow(const orc_sim *s);
 int64_t orc_n_list_errors(const orc_sim *s);
+/* accepted MRZ jumps by Z-sampler regime (Sec. 2.4): eta < -1, -1 <= eta <= 0, eta > 0 */
+void orc_zsampler_regimes(const orc_sim *s, int64_t out[3]);
 void orc_atom_stats(const orc_sim *s, int64_t *nprop, int64_t *nacc, int64_t *nviol, uint64_t *hash);
 uint64_t orc_event_hash(const orc_sim *s);
 int64_t orc_n_events(const orc_sim *s);

@@ -77,6 +77,7 @@ def lib():
             getattr(L, fn).argtypes = [C.c_void_p]
             getattr(L, fn).restype = C.c_int64
         L.orc_atom_stats.argtypes = [C.c_void_p, _lp, _lp, _lp, _up]
+        L.orc_zsampler_regimes.argtypes = [C.c_void_p, _lp]
         L.orc_event_hash.argtypes = [C.c_void_p]
         L.orc_event_hash.restype = C.c_uint64
         L.orc_get_events.argtypes = [C.c_void_p, _lp]
@@ -241,6 +242,12 @@ class OracleSim:
     @property
     def n_list_errors(self):
         return lib().orc_n_list_errors(self._h)
+
+    def zsampler_regimes(self):
+        """Accepted MRZ jumps by Z-sampler regime: eta < -1, -1 <= eta <= 0, eta > 0."""
+        out = np.zeros(3, np.int64)
+        lib().orc_zsampler_regimes(self._h, _ptr(out, _lp))
+        return out
 
     def atom_stats(self):
         n = self.n

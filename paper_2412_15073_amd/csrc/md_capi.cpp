@@ -49,10 +49,30 @@ struct md_ctx {
   double kB = 1.0;
   std::vector<double> box;
   std::vector<int> rep_off;
-  std::vector<void *> allocs;
+  md_allocator alloc{};        // caller's allocator (alloc.alloc == nullptr: hipMalloc)
+  struct Block { void *p; size_t bytes; };
+  std::vector<Block> allocs;   // every device block of the context
   int *d_rep_off = nullptr;
   double *d_scratch = nullptr; size_t scratch_n = 0;
   unsigned long long *d_hist = nullptr; int hist_n = 0;
+  double cap_factor = 1.5;     // initial row capacity / density estimate
+  int nrep_max = 0;            // atoms of the largest replica (rows never need more entries)
+  // Rollback point for regrowing the rows: the state at the first stepping
+  // call after the last good synchronisation, and the stepping calls since.
+  struct Snap {
+    bool valid = false;
+    double4 *x = nullptr, *v = nullptr, *xref = nullptr;
+    int *knext = nullptr;
+    long long *nprop = nullptr, *nacc = nullptr, *nviol = nullptr;
+    unsigned long long *hash = nullptr, *maxd2 = nullptr;
+    MDCtl *ctl = nullptr;
+    int64_t step = 0, since_build = 0;
+    int cur = 0, rows_valid = 0;
+  } snap;
+  struct Call { int kind; int64_t n; int which, phase; double h; };
+  std::vector<Call> journal;
+  bool replaying = false;
+  int64_t n_regrows = 0;
   std::string err;
   bool prof = false;
   Timer tm;
@@ -78,16 +98,38 @@ static int fail(md_ctx *c, int code, const std::string &msg) {
       return fail((c), MD_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));    \
   } while (0)
 
+// Device memory of the context: from the caller's allocator when it gave
+// one (e.g. PyTorch's caching allocator), otherwise hipMalloc.
+static void *dalloc_bytes(md_ctx *c, size_t bytes) {
+  bytes = bytes ? bytes : 1;
+  void *p = nullptr;
+  if (c->alloc.alloc) {
+    p = c->alloc.alloc(c->alloc.ctx, bytes, (void *)c->stream);
+    if (!p) { c->err = "allocator callback returned NULL for " + std::to_string(bytes) + " B"; return nullptr; }
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      c->err = std::string("hipMalloc(") + std::to_string(bytes) + " B): " + hipGetErrorString(e);
+      return nullptr;
+    }
+  }
+  c->allocs.push_back({p, bytes});
+  return p;
+}
+
 template <class T>
 static T *dalloc(md_ctx *c, size_t count) {
-  void *p = nullptr;
-  hipError_t e = hipMalloc(&p, sizeof(T) * (count ? count : 1));
-  if (e != hipSuccess) {
-    c->err = std::string("hipMalloc(") + std::to_string(sizeof(T) * count) + " B): " + hipGetErrorString(e);
-    return nullptr;
+  return (T *)dalloc_bytes(c, sizeof(T) * count);
+}
+
+static void dfree(md_ctx *c, void *p) {
+  for (size_t q = 0; q < c->allocs.size(); ++q) {
+    if (c->allocs[q].p != p) continue;
+    if (c->alloc.release) c->alloc.release(c->alloc.ctx, p, c->allocs[q].bytes, (void *)c->stream);
+    else hipFree(p);
+    c->allocs.erase(c->allocs.begin() + (long)q);
+    return;
   }
-  c->allocs.push_back(p);
-  return (T *)p;
 }
 
 static double4 *Xcur(md_ctx *c) { return c->cur == 0 ? c->V.x0 : c->V.x1; }
@@ -373,7 +415,6 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
     return fail(nullptr, MD_ERR_ARG, "need n_atoms > 1, n_types > 0, n_replicas > 0");
   if (!s->pos || !s->vel || !s->mass || !s->type || !s->lj_eps || !s->lj_sigma || !s->box)
     return fail(nullptr, MD_ERR_ARG, "missing system array");
-  if (s->n_replicas > 1 && !s->replica_offset) return fail(nullptr, MD_ERR_ARG, "replica_offset required");
   if (!(sp->switch_width > 0.0) || !(sp->r_s <= sp->r_c) || sp->skin < 0.0 || sp->r_s - sp->switch_width <= 0.0)
     return fail(nullptr, MD_ERR_ARG, "bad split (need 0 < r_s - w, w > 0, r_s <= r_c, skin >= 0)");
   if (sp->n_rings > 1 && !(sp->ring_width > 0.0)) return fail(nullptr, MD_ERR_ARG, "ring_width must be > 0");
@@ -397,21 +438,74 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
   for (int ab = 0; ab < s->n_types * s->n_types; ++ab)
     if (s->lj_eps[ab] != 0.0 && rlo < 1.25 * s->lj_sigma[ab])
       return fail(nullptr, MD_ERR_ARG, "r_s - switch_width must be >= 1.25 sigma for every LJ pair");
-  for (int i = 0; i < s->n_atoms; ++i) {
+  const int n = s->n_atoms, nrep = s->n_replicas;
+  for (int i = 0; i < n; ++i) {
     if (s->type[i] < 0 || s->type[i] >= s->n_types) return fail(nullptr, MD_ERR_ARG, "type out of range");
-    if (!(s->mass[i] > 0.0)) return fail(nullptr, MD_ERR_ARG, "masses must be positive");
+    if (!(s->mass[i] > 0.0) || !std::isfinite(s->mass[i])) return fail(nullptr, MD_ERR_ARG, "masses must be positive");
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(s->pos[3 * i + d]) || !std::isfinite(s->vel[3 * i + d]))
+        return fail(nullptr, MD_ERR_ARG, "positions and velocities must be finite");
+    if (s->charge && !std::isfinite(s->charge[i])) return fail(nullptr, MD_ERR_ARG, "charges must be finite");
   }
+  // replicas: offsets strictly increasing from 0 to N, at least two atoms each
+  std::vector<int> rep_of(n, 0);
+  if (s->replica_offset) {
+    if (s->replica_offset[0] != 0 || s->replica_offset[nrep] != n)
+      return fail(nullptr, MD_ERR_ARG, "replica_offset must run from 0 to n_atoms");
+    for (int r = 0; r < nrep; ++r) {
+      if (s->replica_offset[r + 1] - s->replica_offset[r] < 2)
+        return fail(nullptr, MD_ERR_ARG, "replica_offset must increase by at least 2 atoms per replica");
+      for (int i = s->replica_offset[r]; i < s->replica_offset[r + 1]; ++i) rep_of[i] = r;
+    }
+  } else if (nrep != 1) {
+    return fail(nullptr, MD_ERR_ARG, "replica_offset required");
+  }
+  for (int r = 0; r < nrep; ++r)
+    for (int d = 0; d < 3; ++d)
+      if (!(s->box[3 * r + d] > 0.0) || !std::isfinite(s->box[3 * r + d]))
+        return fail(nullptr, MD_ERR_ARG, "box edges must be positive");
+  // bonded terms and exclusions: indices in [0, N) and inside the replica of their first atom
+  auto in_rep = [&](int i, int first) { return i >= 0 && i < n && rep_of[i] == rep_of[first]; };
+  if (s->n_bonds < 0 || s->n_angles < 0) return fail(nullptr, MD_ERR_ARG, "negative bond or angle count");
+  if ((s->n_bonds > 0 && (!s->bond_ij || !s->bond_k || !s->bond_r0)) ||
+      (s->n_angles > 0 && (!s->angle_ijk || !s->angle_k || !s->angle_t0)))
+    return fail(nullptr, MD_ERR_ARG, "missing bond or angle array");
+  for (int t = 0; t < s->n_bonds; ++t) {
+    const int p = s->bond_ij[2 * t], q = s->bond_ij[2 * t + 1];
+    if (p < 0 || p >= n || !in_rep(q, p) || p == q)
+      return fail(nullptr, MD_ERR_ARG, "bond " + std::to_string(t) + ": atoms out of range or in different replicas");
+  }
+  for (int t = 0; t < s->n_angles; ++t) {
+    const int p = s->angle_ijk[3 * t], m = s->angle_ijk[3 * t + 1], q = s->angle_ijk[3 * t + 2];
+    if (p < 0 || p >= n || !in_rep(m, p) || !in_rep(q, p) || p == m || q == m || p == q)
+      return fail(nullptr, MD_ERR_ARG, "angle " + std::to_string(t) + ": atoms out of range or in different replicas");
+  }
+  if (s->excl_ptr) {
+    if (!s->excl_j && s->excl_ptr[n] > 0) return fail(nullptr, MD_ERR_ARG, "missing excl_j");
+    if (s->excl_ptr[0] != 0) return fail(nullptr, MD_ERR_ARG, "excl_ptr[0] must be 0");
+    for (int i = 0; i < n; ++i) {
+      if (s->excl_ptr[i + 1] < s->excl_ptr[i]) return fail(nullptr, MD_ERR_ARG, "excl_ptr must be non-decreasing");
+      for (int e = s->excl_ptr[i]; e < s->excl_ptr[i + 1]; ++e)
+        if (!in_rep(s->excl_j[e], i))
+          return fail(nullptr, MD_ERR_ARG, "exclusion of atom " + std::to_string(i) + " out of range or in another replica");
+    }
+  }
+  if (p->bound_scale < 0.0 || !std::isfinite(p->bound_scale)) return fail(nullptr, MD_ERR_ARG, "bound_scale must be >= 0");
+  if (p->row_capacity < 0.0 || !std::isfinite(p->row_capacity)) return fail(nullptr, MD_ERR_ARG, "row_capacity must be >= 0");
   return MD_OK;
 }
 
 extern "C" int md_create(const md_system *s, const md_split *sp, const md_params *p, void *stream,
-                         md_ctx **out) {
+                         const md_allocator *alloc, md_ctx **out) {
   if (!out) return fail(nullptr, MD_ERR_ARG, "out is null");
   *out = nullptr;
   int rc = validate(s, sp, p);
   if (rc) return rc;
   if (p->graph_steps < 0 || (p->graph_steps & 1)) return fail(nullptr, MD_ERR_ARG, "graph_steps must be 0 or even");
+  if (alloc && (!alloc->alloc || !alloc->release))
+    return fail(nullptr, MD_ERR_ARG, "md_allocator needs both alloc and release");
   md_ctx *c = new md_ctx();
+  if (alloc) c->alloc = *alloc;
   c->stream = (hipStream_t)stream;
   if (!c->stream) {
     // graphs cannot be captured on the legacy default stream: use a private one
@@ -428,6 +522,8 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   c->par = *p;
   c->kB = s->kB > 0.0 ? s->kB : 1.0;
   if (c->par.respa_inner < 1) c->par.respa_inner = 1;
+  if (c->par.bound_scale == 0.0) c->par.bound_scale = 1.0;
+  c->cap_factor = c->par.row_capacity > 0.0 ? c->par.row_capacity : 1.5;
   c->nr = sp->n_rings > 0 ? sp->n_rings : 1;
   c->S = c->nt * c->nr;
   const int n = c->n, nt = c->nt, nr = c->nr, nrep = c->nrep;
@@ -559,8 +655,8 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
             cu += 15.0 / (8.0 * V.w) * std::fabs(Uc);
           }
         }
-        ell_lj[(a * nt + b) * nr + k] = lj;
-        ell_cu[(a * nt + b) * nr + k] = cu;
+        ell_lj[(a * nt + b) * nr + k] = lj * c->par.bound_scale;
+        ell_cu[(a * nt + b) * nr + k] = cu * c->par.bound_scale;
       }
   for (int i = 0; i < n; ++i) {
     double q = s->charge ? std::fabs(s->charge[i]) : 0.0;
@@ -585,8 +681,9 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   }
   V.ncell_total = coff[nrep];
   auto sphere = [](double r) { return 4.0 / 3.0 * M_PI * r * r * r; };
+  c->nrep_max = nrep_max;
   auto capf = [&](double vol, int extra) {
-    long long v = (long long)std::ceil(1.5 * rho_max * vol) + extra;
+    long long v = (long long)std::ceil(c->cap_factor * rho_max * vol) + extra;
     return (int)std::min<long long>(v, nrep_max - 1 > 0 ? nrep_max - 1 : 1);
   };
   V.cap_s = capf(sphere(V.rs + V.skin), 32);
@@ -668,6 +765,11 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.ev_cap = p->log_events ? (1ll << 22) : 0;
   if (V.ev_cap) A(V.ev, V.ev_cap);
   A(c->d_rep_off, nrep + 1);
+  {   // rollback point of the row regrow (state at the first step after a good sync)
+    md_ctx::Snap &q = c->snap;
+    A(q.x, n); A(q.v, n); A(q.xref, n); A(q.knext, n);
+    A(q.nprop, n); A(q.nacc, n); A(q.nviol, n); A(q.hash, n); A(q.maxd2, 2 * nrep); A(q.ctl, 1);
+  }
   c->scratch_n = std::max<size_t>(4 * (size_t)n + (size_t)s->n_bonds + (size_t)s->n_angles, 4096);
   A(c->d_scratch, c->scratch_n);
   if (!ok) {
@@ -767,8 +869,11 @@ extern "C" void md_destroy(md_ctx *c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
-  for (void *p : c->allocs) hipFree(p);
-  if (c->d_hist) hipFree(c->d_hist);
+  for (const md_ctx::Block &b : c->allocs) {
+    if (c->alloc.release) c->alloc.release(c->alloc.ctx, b.p, b.bytes, (void *)c->stream);
+    else hipFree(b.p);
+  }
+  c->allocs.clear();
   for (hipEvent_t e : c->tm.pool) hipEventDestroy(e);
   for (auto &g : c->gexec) if (g) hipGraphExecDestroy(g);
   if (c->own_stream) hipStreamDestroy(c->stream);
@@ -880,20 +985,7 @@ static int graph_chunks(md_ctx *c, int mode, int64_t &n) {
   return MD_OK;
 }
 
-extern "C" int md_step_baoab(md_ctx *c, int64_t nsteps) {
-  if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
-  int rc = graph_chunks(c, MODE_BAOAB, nsteps);
-  return rc ? rc : (nsteps > 0 ? baoab_plain(c, nsteps) : MD_OK);
-}
-
-extern "C" int md_step_jump(md_ctx *c, int64_t nsteps) {
-  if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
-  int rc = graph_chunks(c, MODE_JUMP, nsteps);
-  return rc ? rc : (nsteps > 0 ? jump_plain(c, nsteps) : MD_OK);
-}
-
 static int respa(md_ctx *c, int64_t n_outer, bool jump) {
-  if (!c || n_outer < 0) return fail(c, MD_ERR_ARG, "bad argument");
   const int mode = jump ? MODE_JUMP_RESPA : MODE_BAOAB_RESPA;
   int rc = ensure_forces(c, mode);
   if (rc) return rc;
@@ -939,16 +1031,194 @@ static int respa(md_ctx *c, int64_t n_outer, bool jump) {
   return MD_OK;
 }
 
-extern "C" int md_step_jump_respa(md_ctx *c, int64_t n_outer) { return respa(c, n_outer, true); }
-extern "C" int md_step_baoab_respa(md_ctx *c, int64_t n_outer) { return respa(c, n_outer, false); }
+static int run_phase(md_ctx *c, int which, int phase, double h);
+static int take_snapshot(md_ctx *c);
+
+// Stepping calls are journaled since the rollback point (md_ctx::Snap), so
+// that a row regrow can replay them.
+enum { CALL_BAOAB = 0, CALL_JUMP, CALL_JUMP_RESPA, CALL_BAOAB_RESPA, CALL_PHASE };
+
+static int run_call(md_ctx *c, const md_ctx::Call &k) {
+  int64_t n = k.n;
+  int rc;
+  switch (k.kind) {
+    case CALL_BAOAB:
+      rc = graph_chunks(c, MODE_BAOAB, n);
+      return rc ? rc : (n > 0 ? baoab_plain(c, n) : MD_OK);
+    case CALL_JUMP:
+      rc = graph_chunks(c, MODE_JUMP, n);
+      return rc ? rc : (n > 0 ? jump_plain(c, n) : MD_OK);
+    case CALL_JUMP_RESPA: return respa(c, n, true);
+    case CALL_BAOAB_RESPA: return respa(c, n, false);
+    case CALL_PHASE: return run_phase(c, k.which, k.phase, k.h);
+  }
+  return fail(c, MD_ERR_ARG, "internal: unknown call");
+}
+
+static int step_call(md_ctx *c, const md_ctx::Call &k) {
+  if (!c->snap.valid) {
+    int rc = take_snapshot(c);
+    if (rc) return rc;
+  }
+  c->journal.push_back(k);
+  return run_call(c, k);
+}
+
+extern "C" int md_step_baoab(md_ctx *c, int64_t nsteps) {
+  if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  return step_call(c, {CALL_BAOAB, nsteps, 0, 0, 0.0});
+}
+
+extern "C" int md_step_jump(md_ctx *c, int64_t nsteps) {
+  if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  return step_call(c, {CALL_JUMP, nsteps, 0, 0, 0.0});
+}
+
+extern "C" int md_step_jump_respa(md_ctx *c, int64_t n_outer) {
+  if (!c || n_outer < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  return step_call(c, {CALL_JUMP_RESPA, n_outer, 0, 0, 0.0});
+}
+
+extern "C" int md_step_baoab_respa(md_ctx *c, int64_t n_outer) {
+  if (!c || n_outer < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  return step_call(c, {CALL_BAOAB_RESPA, n_outer, 0, 0, 0.0});
+}
 
 // -------------------------------------------------------------- sync
-static int sync_and_check(md_ctx *c) {
-  HIPCHK(c, hipMemcpyAsync(&c->ctl_host, c->V.ctl, sizeof(MDCtl), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+// Row regrow: the rows of the context outgrew their capacities (the row
+// builder records the longest requested row of each kind). New capacities
+// take the requested lengths plus a quarter; the row buffers are reallocated
+// and the captured graphs (which hold the old addresses) dropped.
+static int regrow(md_ctx *c, const MDCtl &h) {
+  MDView &V = c->V;
+  const int most = std::max(1, c->nrep_max - 1);
+  auto grown = [&](int need, int have, int extra) {
+    return std::min(most, std::max(have, need + need / 4 + extra));
+  };
+  int cap_s = h.ovf_short ? grown(h.ovf_short, V.cap_s, 32) : V.cap_s;
+  const int need_long = h.ovf_long ? grown(h.ovf_long, std::max(V.cap_c, V.cap_f), 64) : 0;
+  int cap_c = std::max(V.cap_c, need_long), cap_f = std::max(V.cap_f, need_long);
+  auto pow2 = [](int x) { int m = 1; while (m < x) m <<= 1; return m; };
+  int pc = std::max(c->pc, pow2(std::max(cap_c, cap_f)));
+  if (h.ovf_queue) pc = std::max(pc, pow2(h.ovf_queue + h.ovf_queue / 4 - 64));
+  const int ps = std::max(c->ps, pow2(cap_s));
+  if (pc > 8192 || ps > 4096)
+    return fail(c, MD_ERR_CAPACITY, "neighbour rows of " + std::to_string(std::max(h.ovf_long, h.ovf_queue)) +
+                                        " candidates / " + std::to_string(h.ovf_short) +
+                                        " short entries exceed the row builder's limits (8192 / 4096)");
+  auto realloc_rows = [&](int *&rows, int &cap, int want) -> bool {
+    if (want == cap) return true;
+    dfree(c, rows);
+    rows = dalloc<int>(c, (size_t)c->n * want);
+    cap = want;
+    return rows != nullptr;
+  };
+  if (!realloc_rows(V.srow, V.cap_s, cap_s) || !realloc_rows(V.frow, V.cap_f, cap_f) ||
+      !realloc_rows(V.crow, V.cap_c, cap_c))
+    return fail(c, MD_ERR_OOM, "row regrow: " + c->err);
+  c->pc = pc;
+  c->ps = ps;
+  for (auto &g : c->gexec)
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  c->n_regrows++;
+  return MD_OK;
+}
+
+static int take_snapshot(md_ctx *c) {
+  md_ctx::Snap &q = c->snap;
+  const MDView &V = c->V;
+  const size_t n = (size_t)c->n;
+  hipStream_t st = c->stream;
+  HIPCHK(c, hipMemcpyAsync(q.x, Xcur(c), sizeof(double4) * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(q.v, V.v, sizeof(double4) * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(q.xref, V.xref, sizeof(double4) * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(q.knext, V.knext, sizeof(int) * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(q.nprop, V.nprop, 8 * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(q.nacc, V.nacc, 8 * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(q.nviol, V.nviol, 8 * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(q.hash, V.hash, 8 * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(q.maxd2, V.rep_maxd2, 8 * 2 * (size_t)c->nrep, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(q.ctl, V.ctl, sizeof(MDCtl), hipMemcpyDeviceToDevice, st));
+  q.step = c->step;
+  q.since_build = c->since_build;
+  q.cur = c->cur;
+  q.rows_valid = c->rows_valid;
+  q.valid = true;
+  c->journal.clear();
+  return MD_OK;
+}
+
+// Back to the snapshot: state, statistics, event count and rebuild
+// schedule; the rows valid then are rebuilt at the reference positions
+// of then, and forces are re-evaluated at the next step (all deterministic).
+static int restore_snapshot(md_ctx *c) {
+  md_ctx::Snap &q = c->snap;
+  const MDView &V = c->V;
+  const size_t n = (size_t)c->n;
+  hipStream_t st = c->stream;
+  c->cur = q.cur;
+  HIPCHK(c, hipMemcpyAsync(Xcur(c), q.x, sizeof(double4) * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(V.v, q.v, sizeof(double4) * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(V.xref, q.xref, sizeof(double4) * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(V.knext, q.knext, sizeof(int) * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(V.nprop, q.nprop, 8 * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(V.nacc, q.nacc, 8 * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(V.nviol, q.nviol, 8 * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(V.hash, q.hash, 8 * n, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(V.rep_maxd2, q.maxd2, 8 * 2 * (size_t)c->nrep, hipMemcpyDeviceToDevice, st));
+  HIPCHK(c, hipMemcpyAsync(V.ctl, q.ctl, sizeof(MDCtl), hipMemcpyDeviceToDevice, st));
+  c->step = q.step;
+  c->since_build = q.since_build;
+  c->fkind = -1;
+  c->fb_valid = false;
+  c->rows_valid = 0;
+  if (q.rows_valid) return build_rows_at_ref(c, q.rows_valid, false);
+  return MD_OK;
+}
+
+static int run_call(md_ctx *c, const md_ctx::Call &k);
+
+// Synchronise and report. Rows that outgrew their capacity are recovered
+// here: back to the snapshot, regrow, replay the stepping calls since (the
+// counter-based random streams make the replay identical to a run that
+// never overflowed); without a snapshot (no step since the last good sync)
+// only the rows are rebuilt. Then the device-side error flags are reported.
+static int settle(md_ctx *c) {
+  for (int attempt = 0;; ++attempt) {
+    HIPCHK(c, hipMemcpyAsync(&c->ctl_host, c->V.ctl, sizeof(MDCtl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const MDCtl h = c->ctl_host;
+    if (!(h.ovf_short || h.ovf_long || h.ovf_queue)) break;
+    int rc = attempt < 8 ? regrow(c, h) : fail(c, MD_ERR_CAPACITY, "rows kept overflowing after regrowing");
+    if (rc == MD_OK && c->snap.valid) {
+      rc = restore_snapshot(c);
+      c->replaying = true;
+      for (size_t q = 0; rc == MD_OK && q < c->journal.size(); ++q) rc = run_call(c, c->journal[q]);
+      c->replaying = false;
+    } else if (rc == MD_OK) {
+      const int zero[3] = {0, 0, 0};
+      HIPCHK(c, hipMemcpyAsync(&c->V.ctl->ovf_short, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
+      const int rv = c->rows_valid;
+      c->rows_valid = 0;
+      c->fkind = -1;
+      c->fb_valid = false;
+      if (rv) rc = build_rows_at_ref(c, rv, false);
+    }
+    if (rc != MD_OK) {
+      // unrecoverable: the state of the last good synchronisation
+      const std::string why = c->err;
+      if (c->snap.valid) (void)restore_snapshot(c);
+      const int zero[3] = {0, 0, 0};
+      (void)hipMemcpyAsync(&c->V.ctl->ovf_short, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
+      (void)hipStreamSynchronize(c->stream);
+      c->snap.valid = false;
+      c->journal.clear();
+      return fail(c, rc, why);
+    }
+  }
+  c->snap.valid = false;
+  c->journal.clear();
   const MDCtl &h = c->ctl_host;
-  if (h.overflow_rows) return fail(c, MD_ERR_CAPACITY, "a neighbour row exceeded its capacity (" +
-                                                           std::to_string(h.overflow_rows) + " entries)");
   if (h.nonfinite) return fail(c, MD_ERR_UNSTABLE, "non-finite velocities");
   if (c->par.rebuild_every > 0 && h.n_list_err)
     return fail(c, MD_ERR_LIST, "displacement beyond skin/2 between scheduled rebuilds");
@@ -963,17 +1233,18 @@ static int sync_and_check(md_ctx *c) {
 
 extern "C" int md_sync(md_ctx *c) {
   if (!c) return fail(c, MD_ERR_ARG, "null context");
-  return sync_and_check(c);
+  return settle(c);
 }
 
 extern "C" int md_observables(md_ctx *c, uint32_t flags, md_obs *o) {
   if (!c || !o) return fail(c, MD_ERR_ARG, "null argument");
   memset(o, 0, sizeof(*o));
+  int rc = settle(c);
   int nb = 0;
   HIPCHK(c, launch_ke(c->V, c->d_scratch, &nb, c->stream));
   std::vector<double> part(nb);
   HIPCHK(c, hipMemcpyAsync(part.data(), c->d_scratch, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
-  int rc = sync_and_check(c);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   double ke = 0.0;
   for (double x : part) ke += x;
   o->step = c->step;
@@ -995,8 +1266,15 @@ extern "C" int md_observables(md_ctx *c, uint32_t flags, md_obs *o) {
   o->n_rebuilds = (int64_t)c->ctl_host.n_rebuilds;
   o->n_zsampler_overflow = (int64_t)c->ctl_host.n_zs_overflow;
   o->n_list_errors = (int64_t)c->ctl_host.n_list_err;
+  o->n_regrows = c->n_regrows;
   if (flags & MD_OBS_PE) {
     int rows = c->rows_valid;
+    const bool split_rows = (rows & (ROW_SHORT | ROW_CAND)) == (ROW_SHORT | ROW_CAND);
+    if (!split_rows && !(rows & ROW_FULL)) {
+      int r2 = ensure_rows(c, ROW_FULL);
+      if (r2 || (r2 = settle(c))) return r2;   // a regrow rebuilds the rows before they are used
+      rows = c->rows_valid;
+    }
     double4 *X = Xcur(c);
     double *es = c->d_scratch, *el = c->d_scratch + c->n, *dummy = c->d_scratch + 2 * c->n;
     double *eb = c->d_scratch + 3 * c->n;
@@ -1008,7 +1286,6 @@ extern "C" int md_observables(md_ctx *c, uint32_t flags, md_obs *o) {
       HIPCHK(c, launch_pair_energy(c->V, X, 1, dummy, el, c->stream));
       HIPCHK(c, hipMemcpyAsync(hl.data(), el, 8 * c->n, hipMemcpyDeviceToHost, c->stream));
     } else {
-      if (!(rows & ROW_FULL)) { int r2 = ensure_rows(c, ROW_FULL); if (r2) return r2; }
       HIPCHK(c, launch_pair_energy(c->V, X, 2, es, el, c->stream));
       HIPCHK(c, hipMemcpyAsync(hs.data(), es, 8 * c->n, hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipMemcpyAsync(hl.data(), el, 8 * c->n, hipMemcpyDeviceToHost, c->stream));
@@ -1028,6 +1305,7 @@ extern "C" int md_observables(md_ctx *c, uint32_t flags, md_obs *o) {
 // ------------------------------------------------------------- state I/O
 extern "C" int md_get_state(md_ctx *c, double *pos, double *vel) {
   if (!c) return fail(c, MD_ERR_ARG, "null context");
+  const int rc = settle(c);
   std::vector<double4> h(c->n);
   if (pos) {
     HIPCHK(c, hipMemcpyAsync(h.data(), Xcur(c), sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
@@ -1039,11 +1317,12 @@ extern "C" int md_get_state(md_ctx *c, double *pos, double *vel) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int i = 0; i < c->n; ++i) { vel[3 * i] = h[i].x; vel[3 * i + 1] = h[i].y; vel[3 * i + 2] = h[i].z; }
   }
-  return sync_and_check(c);
+  return rc;
 }
 
 extern "C" int md_set_state(md_ctx *c, const double *pos, const double *vel, int64_t step) {
   if (!c) return fail(c, MD_ERR_ARG, "null context");
+  (void)settle(c);   // pending steps finish (a new state also clears their errors)
   std::vector<double4> h(c->n);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (pos) {
@@ -1065,11 +1344,13 @@ extern "C" int md_set_state(md_ctx *c, const double *pos, const double *vel, int
 
 extern "C" int md_get_accel(md_ctx *c, int32_t kind, double *acc) {
   if (!c || !acc || kind < 0 || kind > 2) return fail(c, MD_ERR_ARG, "bad argument");
-  int rc;
+  int rc = settle(c);
+  if (rc) return rc;
   if (kind == 2) {
     if ((rc = eval_bonded(c))) return rc;
   } else {
     if ((rc = ensure_rows(c, kind == 0 ? (ROW_SHORT | ROW_CAND) : ROW_FULL))) return rc;
+    if ((rc = settle(c))) return rc;   // rows regrown before use if they overflowed
     if ((rc = eval_nb(c, kind))) return rc;
   }
   std::vector<double4> f(c->n), v(c->n);
@@ -1080,25 +1361,27 @@ extern "C" int md_get_accel(md_ctx *c, int32_t kind, double *acc) {
   for (int i = 0; i < c->n; ++i) {
     acc[3 * i] = f[i].x / v[i].w; acc[3 * i + 1] = f[i].y / v[i].w; acc[3 * i + 2] = f[i].z / v[i].w;
   }
-  return sync_and_check(c);
+  return MD_OK;
 }
 
 extern "C" int md_get_atom_stats(md_ctx *c, int64_t *np, int64_t *na, int64_t *nv, uint64_t *hash) {
   if (!c) return fail(c, MD_ERR_ARG, "null context");
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int rc = settle(c);
   if (np) HIPCHK(c, hipMemcpy(np, c->V.nprop, 8 * c->n, hipMemcpyDeviceToHost));
   if (na) HIPCHK(c, hipMemcpy(na, c->V.nacc, 8 * c->n, hipMemcpyDeviceToHost));
   if (nv) HIPCHK(c, hipMemcpy(nv, c->V.nviol, 8 * c->n, hipMemcpyDeviceToHost));
   if (hash) HIPCHK(c, hipMemcpy(hash, c->V.hash, 8 * c->n, hipMemcpyDeviceToHost));
-  return sync_and_check(c);
+  return rc;
 }
 
 extern "C" int md_get_events(md_ctx *c, md_event *buf, int64_t cap, int64_t *n) {
-  if (!c || !n) return fail(c, MD_ERR_ARG, "bad argument");
-  int rc = sync_and_check(c);
-  long long ne = (long long)c->ctl_host.n_events;
-  if (ne > c->V.ev_cap) ne = c->V.ev_cap;
+  if (!c || !n || cap < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  int rc = settle(c);
+  const long long logged = (long long)c->ctl_host.n_events;
+  const long long ne = std::min<long long>(logged, c->V.ev_cap);
   *n = ne;
+  if (rc == MD_OK && logged > ne)
+    rc = fail(c, MD_ERR_EVENTS, std::to_string(logged) + " jumps logged, the log holds " + std::to_string(ne));
   if (!buf || ne == 0) return rc;
   std::vector<MDEventDev> h(ne);
   HIPCHK(c, hipMemcpy(h.data(), c->V.ev, sizeof(MDEventDev) * ne, hipMemcpyDeviceToHost));
@@ -1116,27 +1399,28 @@ extern "C" int md_get_events(md_ctx *c, md_event *buf, int64_t cap, int64_t *n) 
 }
 
 extern "C" int md_rdf(md_ctx *c, int32_t ta, int32_t tb, double r_max, int32_t n_bins, double *hist) {
-  if (!c || !hist || n_bins <= 0 || !(r_max > 0.0)) return fail(c, MD_ERR_ARG, "bad argument");
-  if (c->hist_n < n_bins) {
-    if (c->d_hist) hipFree(c->d_hist);
-    c->d_hist = nullptr;
-    HIPCHK(c, hipMalloc(&c->d_hist, sizeof(unsigned long long) * n_bins));
-    c->hist_n = n_bins;
+  if (!c || !hist || n_bins <= 0 || !(r_max > 0.0) || ta < 0 || tb < 0 || ta >= c->nt || tb >= c->nt)
+    return fail(c, MD_ERR_ARG, "bad argument");
+  const int rc = settle(c);
+  if (c->hist_n < n_bins) {   // through the context's allocator, kept for later calls
+    if (c->d_hist) dfree(c, c->d_hist);
+    c->d_hist = dalloc<unsigned long long>(c, (size_t)n_bins);
+    c->hist_n = c->d_hist ? n_bins : 0;
+    if (!c->d_hist) return fail(c, MD_ERR_OOM, c->err);
   }
-  HIPCHK(c, hipMemsetAsync(c->d_hist, 0, sizeof(unsigned long long) * n_bins, c->stream));
+  HIPCHK(c, launch_fill_u64(c->d_hist, n_bins, 0ull, c->stream));
   HIPCHK(c, launch_rdf(c->V, Xcur(c), c->d_rep_off, ta, tb, r_max, n_bins, c->d_hist, c->stream));
   std::vector<unsigned long long> h(n_bins);
   HIPCHK(c, hipMemcpyAsync(h.data(), c->d_hist, sizeof(unsigned long long) * n_bins, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int b = 0; b < n_bins; ++b) hist[b] = (double)h[b];
-  return sync_and_check(c);
+  return rc;
 }
 
 extern "C" int md_get_cand_row(md_ctx *c, int32_t i, int32_t *j, int32_t cap, int32_t *n, int32_t *seg) {
-  if (!c || !n || i < 0 || i >= c->n) return fail(c, MD_ERR_ARG, "bad argument");
-  int rc = ensure_rows(c, ROW_SHORT | ROW_CAND);
-  if (rc) return rc;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (!c || !n || i < 0 || i >= c->n || cap < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  int rc = settle(c);
+  if (rc || (rc = ensure_rows(c, ROW_SHORT | ROW_CAND)) || (rc = settle(c))) return rc;
   int cnt = 0;
   HIPCHK(c, hipMemcpy(&cnt, c->V.ccnt + i, sizeof(int), hipMemcpyDeviceToHost));
   *n = cnt;
@@ -1144,22 +1428,27 @@ extern "C" int md_get_cand_row(md_ctx *c, int32_t i, int32_t *j, int32_t cap, in
                                     hipMemcpyDeviceToHost));
   if (seg) HIPCHK(c, hipMemcpy(seg, c->V.segst + (size_t)i * (c->S + 1), sizeof(int) * (c->S + 1),
                                hipMemcpyDeviceToHost));
-  return sync_and_check(c);
+  return MD_OK;
 }
 
 extern "C" int md_get_row_counts(md_ctx *c, int32_t which, int32_t *counts) {
   if (!c || !counts || which < 0 || which > 2) return fail(c, MD_ERR_ARG, "bad argument");
   int want = which == 0 ? ROW_SHORT : (which == 1 ? ROW_FULL : ROW_CAND);
-  int rc = ensure_rows(c, want == ROW_FULL ? ROW_FULL : (ROW_SHORT | ROW_CAND));
-  if (rc) return rc;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int rc = settle(c);
+  if (rc || (rc = ensure_rows(c, want == ROW_FULL ? ROW_FULL : (ROW_SHORT | ROW_CAND))) || (rc = settle(c)))
+    return rc;
   const int *src = which == 0 ? c->V.scnt : (which == 1 ? c->V.fcnt : c->V.ccnt);
   HIPCHK(c, hipMemcpy(counts, src, sizeof(int) * c->n, hipMemcpyDeviceToHost));
-  return sync_and_check(c);
+  return MD_OK;
 }
 
 extern "C" int md_run_phase(md_ctx *c, int32_t which, int32_t phase, double h) {
   if (!c) return fail(c, MD_ERR_ARG, "null context");
+  if (which != 'C' && which != 'J' && which != 'O') return fail(c, MD_ERR_ARG, "which must be 'C', 'J' or 'O'");
+  return step_call(c, {CALL_PHASE, 0, which, phase, h});
+}
+
+static int run_phase(md_ctx *c, int which, int phase, double h) {
   int rc = ensure_forces(c, MODE_JUMP);
   if (rc) return rc;
   ProgBuilder b;
@@ -1194,23 +1483,24 @@ extern "C" int md_profile_read(md_ctx *c, int32_t kid, double *total_ms, int64_t
 
 extern "C" int md_counters(md_ctx *c, int64_t *pairs_last, int64_t *proposals_total) {
   if (!c) return fail(c, MD_ERR_ARG, "null context");
+  const int rc = settle(c);
   if (pairs_last) {
     *pairs_last = -1;
     if (c->fkind == 0 || c->fkind == 1) {
       int which = c->fkind;
       int need = which == 0 ? ROW_SHORT : ROW_FULL;
       if ((c->rows_valid & need) == need) {
-        HIPCHK(c, hipMemsetAsync(c->d_scratch, 0, sizeof(unsigned long long), c->stream));
-        HIPCHK(c, launch_count_pairs(c->V, Xcur(c), which, which == 0 ? c->split.r_s : c->split.r_c,
-                                     (unsigned long long *)c->d_scratch, c->stream));
+        unsigned long long *cnt = (unsigned long long *)c->d_scratch;
+        HIPCHK(c, launch_fill_u64(cnt, 1, 0ull, c->stream));
+        HIPCHK(c, launch_count_pairs(c->V, Xcur(c), which, which == 0 ? c->split.r_s : c->split.r_c, cnt,
+                                     c->stream));
         unsigned long long h = 0;
-        HIPCHK(c, hipMemcpyAsync(&h, c->d_scratch, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         *pairs_last = (int64_t)h;
       }
     }
   }
-  int rc = sync_and_check(c);
   if (proposals_total) {
     std::vector<long long> a(c->n);
     HIPCHK(c, hipMemcpy(a.data(), c->V.nprop, 8 * c->n, hipMemcpyDeviceToHost));

@@ -100,7 +100,9 @@ struct MDProg {
 
 struct MDCtl {                       // device-side control words
   int do_rebuild;
-  int overflow_rows;                 // max row length requested beyond capacity
+  int ovf_short;                     // longest short row requested beyond its capacity (0: none)
+  int ovf_long;                      // longest full or candidate row requested beyond its capacity
+  int ovf_queue;                     // longest stencil queue of the row builder beyond its LDS slots
   unsigned long long n_rebuilds;
   unsigned long long n_list_err;
   unsigned long long n_zs_overflow;

@@ -30,4 +30,5 @@ hipError_t launch_rdf(const MDView &V, const double4 *X, const int *rep_off, int
 hipError_t launch_count_pairs(const MDView &V, const double4 *X, int which, double cut, unsigned long long *out,
                               hipStream_t s);
 hipError_t launch_set_step(MDCtl *ctl, long long step, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
 hipError_t launch_theta_screen_err(double lo, double hi, int n, unsigned long long *out, hipStream_t s);

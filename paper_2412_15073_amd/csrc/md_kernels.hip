@@ -301,7 +301,7 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
   const bool ex_more = x1 - x0 > 4;
   const double rs_out = V.rs + V.skin;
   const int capk = (want & 4) ? V.cap_c : V.cap_f;
-  int nk = 0, nsr = 0, over = 0;
+  int nk = 0, nsr = 0;
   int zlo, zhi, ylo, yhi, xlo, xhi;
   stencil_range(cz, nd[2], zlo, zhi);
   stencil_range(cy, nd[1], ylo, yhi);
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     if (keep) {
       const int pos = nq + __popcll(mq & below);
-      if (pos < pq) kc[pos] = (unsigned)q; else over = 1;
+      if (pos < pq) kc[pos] = (unsigned)q;
     }
     nq += __popcll(mq);
   }
@@ -415,17 +415,22 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     if (bk) {
       const int pos = nk + __popcll(mk & below);
-      if (pos < pc) kc[pos] = key; else over = 1;
+      if (pos < pc) kc[pos] = key;
     }
     if (bs) {
       const int pos = nsr + __popcll(ms & below);
-      if (pos < ps) ks[pos] = (unsigned)j; else over = 1;
+      if (pos < ps) ks[pos] = (unsigned)j;
     }
     nk += __popcll(mk);
     nsr += __popcll(ms);
   }
-  if (nk > capk || nsr > V.cap_s) over = 1;
-  if (__any(over) && lane == 0) atomicMax(&V.ctl->overflow_rows, max(max(nk, nsr), nq));
+  // requested lengths beyond capacity: the host regrows the rows and replays
+  // the steps since its last good synchronisation
+  if (lane == 0) {
+    if (nsr > V.cap_s) atomicMax(&V.ctl->ovf_short, nsr);
+    if (nk > capk) atomicMax(&V.ctl->ovf_long, nk);
+    if (nq > pq) atomicMax(&V.ctl->ovf_queue, nq);
+  }
   const int nkk = min(nk, min(capk, pc)), nss = min(nsr, min(V.cap_s, ps));
   if (want & 6) {
     __syncthreads();
@@ -758,6 +763,12 @@ __global__ void k_count_pairs(MDView V, const double4 *__restrict__ X, int which
 
 __global__ void k_set_step(MDCtl *ctl, long long step) { ctl->step_base = step; }
 
+// fill with a value (a kernel rather than a memset: safe under graph capture)
+__global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // ------------------------------------------------------------- launchers
 #define CHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
@@ -864,6 +875,12 @@ hipError_t launch_count_pairs(const MDView &V, const double4 *X, int which, doub
 
 hipError_t launch_set_step(MDCtl *ctl, long long step, hipStream_t s) {
   hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, ctl, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -1,9 +1,10 @@
 """ctypes binding of libjumpmd.so (C ABI in include/jumpmd.h).
 
 Argument marshalling only: every step of the integrator runs in the HIP
-kernels of the library. PyTorch supplies the HIP stream. Importing this
-module raises if the library has not been built, and there is no CPU
-fallback.
+kernels of the library. PyTorch supplies the HIP stream and the device
+memory (its caching allocator, through the md_allocator callbacks), so torch
+owns every block the library uses. Importing this module raises if the
+library has not been built, and there is no CPU fallback.
 """
 import ctypes as C
 import os
@@ -15,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libjumpmd.so")
 
 MD_OK, MD_ERR_ARG, MD_ERR_HIP, MD_ERR_BOUND, MD_ERR_LIST, MD_ERR_UNSTABLE, MD_ERR_OOM, MD_ERR_CAPACITY = \
     0, -1, -2, -3, -4, -5, -6, -7
+MD_ERR_EVENTS = -8
 MD_OBS_PE = 1
 MD_K_LOCAL, MD_K_FORCE, MD_K_BONDED, MD_K_REBUILD, MD_K_CHAIN = 0, 1, 2, 3, 4
 PHASE = {"J1": 2, "J2": 3, "C1": 4, "C2": 5}
@@ -46,7 +48,7 @@ class MDParams(C.Structure):
                 ("jump_lj", C.c_int32), ("jump_coul", C.c_int32), ("eps", C.c_double),
                 ("precision", C.c_int32), ("rebuild_every", C.c_int32), ("respa_inner", C.c_int32),
                 ("log_events", C.c_int32), ("strict_bounds", C.c_int32), ("chain_lanes", C.c_int32),
-                ("graph_steps", C.c_int32)]
+                ("graph_steps", C.c_int32), ("bound_scale", C.c_double), ("row_capacity", C.c_double)]
 
 
 class MDObs(C.Structure):
@@ -54,7 +56,49 @@ class MDObs(C.Structure):
                 ("pe_short", C.c_double), ("pe_long", C.c_double), ("pe_bonded", C.c_double),
                 ("n_prop", C.c_int64), ("n_acc", C.c_int64), ("n_bound_viol", C.c_int64),
                 ("n_rebuilds", C.c_int64), ("n_zsampler_overflow", C.c_int64),
-                ("n_list_errors", C.c_int64), ("event_hash", C.c_uint64)]
+                ("n_list_errors", C.c_int64), ("event_hash", C.c_uint64), ("n_regrows", C.c_int64)]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class MDAllocator(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("alloc", _ALLOC_FN), ("release", _RELEASE_FN)]
+
+
+class TorchAllocator:
+    """md_allocator backed by PyTorch's caching allocator: every device block
+    of a context is a torch allocation on the context's stream (torch owns
+    it). Counts the bytes handed out (live and in total)."""
+
+    def __init__(self, device=None):
+        import torch
+        self._torch = torch
+        self.device = torch.cuda.current_device() if device is None else device
+        self.bytes_live = 0
+        self.bytes_total = 0
+        self.n_blocks = 0
+
+        def alloc(_ctx, nbytes, stream):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device, stream=int(stream or 0))
+            except Exception:
+                return None
+            self.bytes_live += int(nbytes)
+            self.bytes_total += int(nbytes)
+            self.n_blocks += 1
+            return p
+
+        def release(_ctx, ptr, nbytes, _stream):
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:
+                pass
+            self.bytes_live -= int(nbytes)
+
+        self._fns = (_ALLOC_FN(alloc), _RELEASE_FN(release))   # kept alive with the contexts using them
+        self.struct = MDAllocator(None, self._fns[0], self._fns[1])
 
 
 class MDEvent(C.Structure):
@@ -94,7 +138,7 @@ def load():
     import torch  # noqa: F401
     L = C.CDLL(path)
     L.md_create.argtypes = [C.POINTER(MDSystem), C.POINTER(MDSplit), C.POINTER(MDParams), C.c_void_p,
-                            C.POINTER(C.c_void_p)]
+                            C.POINTER(MDAllocator), C.POINTER(C.c_void_p)]
     L.md_destroy.argtypes = [C.c_void_p]
     L.md_destroy.restype = None
     L.md_last_error.argtypes = [C.c_void_p]
@@ -166,6 +210,14 @@ def _concat(systems):
     return out
 
 
+def _gpu_visible():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
 def _current_stream():
     try:
         import torch
@@ -179,7 +231,9 @@ def _current_stream():
 class Sim:
     """One libjumpmd context. `system` is a systems.System or systems.Batch."""
 
-    def __init__(self, system, split, params, stream=None):
+    def __init__(self, system, split, params, stream=None, allocator="torch"):
+        """allocator: "torch" (PyTorch's caching allocator, when a GPU is
+        visible), None (the library's own hipMalloc) or a TorchAllocator."""
         L = load()
         systems = list(system.systems) if hasattr(system, "systems") else [system]
         s0 = systems[0]
@@ -206,10 +260,15 @@ class Sim:
         pa = MDParams(params.dt, params.gamma, params.kT, params.seed, params.jump_lj, params.jump_coul,
                       params.eps, params.precision, params.rebuild_every, params.respa_inner,
                       params.log_events, params.strict_bounds, getattr(params, "chain_lanes", 0),
-                      getattr(params, "graph_steps", 0))
+                      getattr(params, "graph_steps", 0), getattr(params, "bound_scale", 0.0),
+                      getattr(params, "row_capacity", 0.0))
         self.stream = stream if stream is not None else _current_stream()
+        if allocator == "torch":
+            allocator = TorchAllocator() if _gpu_visible() else None
+        self.allocator = allocator
         h = C.c_void_p()
-        rc = L.md_create(C.byref(sy), C.byref(sp), C.byref(pa), self.stream, C.byref(h))
+        rc = L.md_create(C.byref(sy), C.byref(sp), C.byref(pa), self.stream,
+                         C.byref(allocator.struct) if allocator is not None else None, C.byref(h))
         if rc != MD_OK:
             raise MDError(rc, L.md_last_error(None).decode())
         self._h = h

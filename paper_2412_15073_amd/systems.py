@@ -81,6 +81,8 @@ class Params:
     strict_bounds: int = 0
     chain_lanes: int = 0      # lanes per atom in the GPU jump chains (0 = automatic)
     graph_steps: int = 0      # steps per replayed HIP graph chunk (0 = no graphs)
+    bound_scale: float = 0.0  # jump-rate bounds multiplied by this (0 = 1: as derived)
+    row_capacity: float = 0.0 # initial row capacity / density estimate (0 = 1.5)
 
 
 @dataclass
