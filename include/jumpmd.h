@@ -47,7 +47,7 @@ extern "C" {
                                  entries per atom) even after regrowing; the state is then that of the
                                  last good synchronisation (the stepping calls since are not applied) */
 #define MD_ERR_EVENTS (-8)    /* md_get_events: more accepted jumps were logged than the log holds
-                                 (2^22); the events kept are an unspecified subset */
+                                 (md_params.event_capacity); the events kept are an unspecified subset */
 
 /* jump kinds (Sec. 2.2 of the paper) */
 #define MD_JUMP_NONE 0
@@ -145,6 +145,7 @@ typedef struct {
                            unchanged; < 1 makes bounds invalid (counted; MD_ERR_BOUND in strict mode) */
   double row_capacity;  /* initial row capacity as a multiple of the density estimate (0: 1.5);
                            rows regrow on demand, so this only trades memory for early regrows */
+  int64_t event_capacity; /* accepted jumps the event log holds (log_events = 1); 0: 2^22 */
 } md_params;
 
 typedef struct {
@@ -212,7 +213,7 @@ int md_get_accel(md_ctx *ctx, int32_t kind, double *acc);
 /* Per-atom jump statistics [N] each (any may be NULL). */
 int md_get_atom_stats(md_ctx *ctx, int64_t *n_prop, int64_t *n_acc, int64_t *n_viol, uint64_t *hash);
 /* Accepted-jump log (log_events = 1), sorted by (step, phase, atom,
- * proposal); the log holds 2^22 events since creation. buf may be NULL to
+ * proposal); the log holds event_capacity events since creation. buf may be NULL to
  * query *n. MD_ERR_EVENTS when events were lost (*n = those kept). */
 int md_get_events(md_ctx *ctx, md_event *buf, int64_t cap, int64_t *n);
 /* Pair histogram of types (ta, tb) over [0, r_max) in n_bins bins, pairs

@@ -492,6 +492,7 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
   }
   if (p->bound_scale < 0.0 || !std::isfinite(p->bound_scale)) return fail(nullptr, MD_ERR_ARG, "bound_scale must be >= 0");
   if (p->row_capacity < 0.0 || !std::isfinite(p->row_capacity)) return fail(nullptr, MD_ERR_ARG, "row_capacity must be >= 0");
+  if (p->event_capacity < 0 || p->event_capacity > (1ll << 31)) return fail(nullptr, MD_ERR_ARG, "event_capacity must be in [0, 2^31]");
   return MD_OK;
 }
 
@@ -762,7 +763,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   A(V.crow, (size_t)n * V.cap_c); A(V.ccnt, n); A(V.segst, (size_t)n * (c->S + 1));
   A(V.nprop, n); A(V.nacc, n); A(V.nviol, n); A(V.hash, n); A(V.knext, n);
   A(V.ctl, 1);
-  V.ev_cap = p->log_events ? (1ll << 22) : 0;
+  V.ev_cap = p->log_events ? (p->event_capacity > 0 ? (long long)p->event_capacity : (1ll << 22)) : 0;
   if (V.ev_cap) A(V.ev, V.ev_cap);
   A(c->d_rep_off, nrep + 1);
   {   // rollback point of the row regrow (state at the first step after a good sync)

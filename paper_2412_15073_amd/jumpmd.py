@@ -48,7 +48,8 @@ class MDParams(C.Structure):
                 ("jump_lj", C.c_int32), ("jump_coul", C.c_int32), ("eps", C.c_double),
                 ("precision", C.c_int32), ("rebuild_every", C.c_int32), ("respa_inner", C.c_int32),
                 ("log_events", C.c_int32), ("strict_bounds", C.c_int32), ("chain_lanes", C.c_int32),
-                ("graph_steps", C.c_int32), ("bound_scale", C.c_double), ("row_capacity", C.c_double)]
+                ("graph_steps", C.c_int32), ("bound_scale", C.c_double), ("row_capacity", C.c_double),
+                ("event_capacity", C.c_int64)]
 
 
 class MDObs(C.Structure):
@@ -261,7 +262,7 @@ class Sim:
                       params.eps, params.precision, params.rebuild_every, params.respa_inner,
                       params.log_events, params.strict_bounds, getattr(params, "chain_lanes", 0),
                       getattr(params, "graph_steps", 0), getattr(params, "bound_scale", 0.0),
-                      getattr(params, "row_capacity", 0.0))
+                      getattr(params, "row_capacity", 0.0), getattr(params, "event_capacity", 0))
         self.stream = stream if stream is not None else _current_stream()
         if allocator == "torch":
             allocator = TorchAllocator() if _gpu_visible() else None

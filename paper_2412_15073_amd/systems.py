@@ -83,6 +83,7 @@ class Params:
     graph_steps: int = 0      # steps per replayed HIP graph chunk (0 = no graphs)
     bound_scale: float = 0.0  # jump-rate bounds multiplied by this (0 = 1: as derived)
     row_capacity: float = 0.0 # initial row capacity / density estimate (0 = 1.5)
+    event_capacity: int = 0   # accepted jumps the GPU event log holds (0 = 2^22)
 
 
 @dataclass

@@ -105,6 +105,7 @@ def test_jump_water_100_steps(jm):
     sp = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=0.5, n_rings=12)
     pa = S.water_params(eps0_per_kcal=0.1)
     pa.log_events = 1
+    pa.event_capacity = 1 << 24   # about 9.4M accepted jumps in 100 steps
     pa.graph_steps = 20
     g, o = _pair(jm, sy, sp, pa)
     g.step_jump(100)
