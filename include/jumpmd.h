@@ -101,7 +101,11 @@ typedef struct {
  * candidates are binned by build-time distance in rings of ring_width
  * starting at r_s - switch_width - skin, each with its own bound (ring
  * technique of Sec. 3.1.1; n_rings = 1 is the uniform per-atom bound of
- * Alg. 4/5). Requires r_c < box/2 and r_s - w >= 1.25 sigma of every LJ pair. */
+ * Alg. 4/5). Requires every box edge > r_c + skin and r_s - w >= 1.25 sigma
+ * of every LJ pair. Where an edge is below 2 (r_c + skin) (at most 8192 atoms
+ * in such a replica), a partner can lie within the cutoff in two images:
+ * rows then hold every image within the cutoff, each its own pair term and
+ * jump candidate; elsewhere the nearest image is the only one. */
 typedef struct {
   double r_s, r_c, switch_width, skin, coulomb_alpha;
   int32_t n_rings;
@@ -221,9 +225,14 @@ int md_get_events(md_ctx *ctx, md_event *buf, int64_t cap, int64_t *n);
 int md_rdf(md_ctx *ctx, int32_t ta, int32_t tb, double r_max, int32_t n_bins, double *hist);
 
 /* Neighbour rows as last built (for checks): candidate row of atom i (global
- * j indices, sorted by (type of j, ring, j)) and its S+1 segment starts,
- * S = n_types*n_rings. *n receives the row length; j may be NULL. */
-int md_get_cand_row(md_ctx *ctx, int32_t i, int32_t *j, int32_t cap, int32_t *n, int32_t *seg_start);
+ * j indices, sorted by (type of j, ring, j, image)) and its S+1 segment
+ * starts, S = n_types*n_rings. *n receives the row length; j, img and
+ * seg_start may be NULL. In a replica with an edge below 2 (r_c + skin) a
+ * candidate is one periodic image x_j + n L of j (n an integer vector fixed
+ * at the row build) and img[k] = (n_x mod 8) | (n_y mod 8) << 3 |
+ * (n_z mod 8) << 6; elsewhere candidates are nearest images and img[k] = -1. */
+int md_get_cand_row(md_ctx *ctx, int32_t i, int32_t *j, int32_t *img, int32_t cap, int32_t *n,
+                    int32_t *seg_start);
 /* Number of (i,j) entries in the short rows (r < r_s + skin at build), both directions. */
 int md_get_row_counts(md_ctx *ctx, int32_t which, int32_t *counts);
 

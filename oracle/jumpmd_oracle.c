@@ -5,8 +5,9 @@
  * CPU-baseline leg of the benchmark; never by the GPU library. It shares no
  * code with the GPU path. Everything here is written for being checked by eye
  * against the paper, not for speed: all pair sums are brute force over every
- * pair of atoms (minimum image), candidate rows are built by brute force and
- * sorted with qsort, every jump chain is a sequential loop.
+ * pair of atoms and every periodic image within the cutoff, candidate rows are
+ * built by brute force and sorted with qsort, every jump chain is a sequential
+ * loop.
  *
  * Paper: Gouraud, Lagardere, Adjoua, Ple, Monmarche, Piquemal,
  * "Velocity Jumps for Molecular Dynamics", arXiv 2412.15073.
@@ -182,7 +183,12 @@ void orc_pair_terms(double r, double eps, double sigma, double qq, double coulom
 }
 
 /* ------------------------------------------------------------------------ */
-typedef struct { int32_t seg, j; } cand_t;
+/* A jump candidate of atom i is one periodic image of atom j: the image at
+ * x_j + n L (n an integer vector fixed when the row is built), so that its
+ * displacement is d = x_i - x_j - n L. img = (s_x+1) + 3 (s_y+1) + 9 (s_z+1)
+ * numbers the image by its offset s = n - m from the nearest image m at the
+ * build (the order of images of one j inside a row). */
+typedef struct { int32_t seg, j, img; int32_t n[3]; } cand_t;
 
 struct orc_sim {
   int n, nt;
@@ -226,6 +232,37 @@ static double min_image(double d, double L) { return d - L * rint(d / L); }
 static double pair_vec(const orc_sim *s, int i, int j, double d[3]) {
   for (int c = 0; c < 3; c++) d[c] = min_image(s->x[3 * i + c] - s->x[3 * j + c], s->L[c]);
   return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+}
+
+/* displacement from the image x_j + n L of atom j to atom i */
+static double pair_vec_n(const orc_sim *s, int i, int j, const int32_t n[3], double d[3]) {
+  for (int c = 0; c < 3; c++) d[c] = (s->x[3 * i + c] - s->x[3 * j + c]) - (double)n[c] * s->L[c];
+  return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+}
+
+/* Images of j that can lie within `cut` of i: the nearest image m plus, along
+ * every edge shorter than 2 cut, the neighbouring images m - 1 and m + 1
+ * (edges are longer than cut, so images two or more edges away from the
+ * nearest are farther than cut). *nimg receives their count (1 ... 27); n
+ * receives the lattice vectors and code the offset numbers (s+1) + 3 (s+1) + 9 (s+1),
+ * in increasing order of code. */
+static void images_within(const orc_sim *s, int i, int j, double cut, int *nimg, int32_t n[27][3],
+                          int32_t code[27]) {
+  int32_t m[3], lo[3], hi[3];
+  for (int c = 0; c < 3; c++) {
+    m[c] = (int32_t)rint((s->x[3 * i + c] - s->x[3 * j + c]) / s->L[c]);
+    lo[c] = s->L[c] < 2.0 * cut ? -1 : 0;
+    hi[c] = -lo[c];
+  }
+  int q = 0;
+  for (int sz = lo[2]; sz <= hi[2]; sz++)
+    for (int sy = lo[1]; sy <= hi[1]; sy++)
+      for (int sx = lo[0]; sx <= hi[0]; sx++) {
+        n[q][0] = m[0] + sx; n[q][1] = m[1] + sy; n[q][2] = m[2] + sz;
+        code[q] = (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1);
+        q++;
+      }
+  *nimg = q;
 }
 
 static int excluded(const orc_sim *s, int i, int j) {
@@ -291,23 +328,30 @@ static int cand_cmp(const void *pa, const void *pb) {
   const cand_t *a = (const cand_t *)pa, *b = (const cand_t *)pb;
   if (a->seg != b->seg) return a->seg < b->seg ? -1 : 1;
   if (a->j != b->j) return a->j < b->j ? -1 : 1;
+  if (a->img != b->img) return a->img < b->img ? -1 : 1;
   return 0;
 }
 
-/* Candidate rows (Remark of Sec. 3.1.1): for each i, every j != i, not
- * excluded, with r_s - w - skin <= r < r_c + skin at the build positions,
- * keyed by (type of j, ring) and sorted by (segment, j). */
+/* Candidate rows (Remark of Sec. 3.1.1): for each i, every image of every
+ * j != i, not excluded, with r_s - w - skin <= r < r_c + skin at the build
+ * positions, keyed by (type of j, ring) and sorted by (segment, j, image).
+ * An exclusion removes every image of the pair. */
 void orc_build_lists(orc_sim *s) {
   int n = s->n;
   int64_t total = 0;
   double rin = s->rlo - s->skin, rout = s->rc + s->skin;
+  int nimg;
+  int32_t nv[27][3], code[27];
   /* count */
   for (int i = 0; i < n; i++) {
     int64_t c = 0;
     for (int j = 0; j < n; j++) {
       if (j == i || excluded(s, i, j)) continue;
-      double d[3], r = pair_vec(s, i, j, d);
-      if (r >= rin && r < rout) c++;
+      images_within(s, i, j, rout, &nimg, nv, code);
+      for (int q = 0; q < nimg; q++) {
+        double d[3], r = pair_vec_n(s, i, j, nv[q], d);
+        if (r >= rin && r < rout) c++;
+      }
     }
     s->cptr[i + 1] = s->cptr[i] + c;
     total += c;
@@ -318,13 +362,17 @@ void orc_build_lists(orc_sim *s) {
     int64_t p = s->cptr[i];
     for (int j = 0; j < n; j++) {
       if (j == i || excluded(s, i, j)) continue;
-      double d[3], r = pair_vec(s, i, j, d);
-      if (r >= rin && r < rout) {
+      images_within(s, i, j, rout, &nimg, nv, code);
+      for (int q = 0; q < nimg; q++) {
+        double d[3], r = pair_vec_n(s, i, j, nv[q], d);
+        if (!(r >= rin && r < rout)) continue;
         int k = (int)floor((r - rin) / s->rw);
         if (k < 0) k = 0;
         if (k > s->nr - 1) k = s->nr - 1;
         s->cand[p].seg = s->type[j] * s->nr + k;
         s->cand[p].j = j;
+        s->cand[p].img = code[q];
+        for (int c = 0; c < 3; c++) s->cand[p].n[c] = nv[q][c];
         p++;
       }
     }
@@ -369,16 +417,22 @@ static void maybe_rebuild(orc_sim *s) {
 }
 
 /* ---------------------------------------------------------------- forces */
-/* Non-bonded forces by brute force over all pairs (minimum image).
- * kind SHORT: U_short = chi U for r < r_s; kind FULL: U for r < r_c. */
+/* Non-bonded forces by brute force over all pairs and all their periodic
+ * images within r_c (every box edge exceeds r_c + skin, so an atom never
+ * meets its own image). kind SHORT: U_short = chi U for r < r_s; kind FULL:
+ * U for r < r_c. */
 static void nb_forces(const orc_sim *s, int kind, double *f, double *pe_s, double *pe_l) {
   int n = s->n;
   memset(f, 0, sizeof(double) * 3 * (size_t)n);
   double es = 0.0, el = 0.0;
+  int nimg;
+  int32_t nv[27][3], code[27];
   for (int i = 0; i < n; i++)
     for (int j = i + 1; j < n; j++) {
       if (excluded(s, i, j)) continue;
-      double d[3], r = pair_vec(s, i, j, d);
+      images_within(s, i, j, s->rc, &nimg, nv, code);
+      for (int q = 0; q < nimg; q++) {
+      double d[3], r = pair_vec_n(s, i, j, nv[q], d);
       if (r >= s->rc) continue;
       int a = s->type[i], b = s->type[j];
       double Ul, dUl, Uc, dUc, chi, dchi;
@@ -399,6 +453,7 @@ static void nb_forces(const orc_sim *s, int kind, double *f, double *pe_s, doubl
         double fc = -g * d[c] / r;
         f[3 * i + c] += fc;
         f[3 * j + c] -= fc;
+      }
       }
     }
   if (pe_s) *pe_s = es;
@@ -458,11 +513,12 @@ static void ensure_forces(orc_sim *s, int kind) {
 
 static void positions_moved(orc_sim *s) { s->fkind = -1; s->fb_valid = 0; }
 
-/* Long-range gradient F_ij = grad_{x_i} (1 - chi) U_ij (Sec. 3.1, Sec. 3.2);
- * coulomb selects the DSF part, otherwise the LJ part. Zero when r <= r_s - w
- * or r >= r_c. */
-static double long_grad(const orc_sim *s, int i, int j, int coulomb, double F[3]) {
-  double d[3], r = pair_vec(s, i, j, d);
+/* Long-range gradient F_ij = grad_{x_i} (1 - chi) U_ij (Sec. 3.1, Sec. 3.2)
+ * for the candidate image (j, n); coulomb selects the DSF part, otherwise the
+ * LJ part. Zero when r <= r_s - w or r >= r_c. */
+static double long_grad(const orc_sim *s, int i, const cand_t *cj, int coulomb, double F[3]) {
+  const int j = cj->j;
+  double d[3], r = pair_vec_n(s, i, j, cj->n, d);
   int a = s->type[i], b = s->type[j];
   double U, dU, chi, dchi;
   if (coulomb) dsf_terms(r, s->q[i] * s->q[j], s->ke_c, s->alpha, s->rc, &U, &dU);
@@ -589,9 +645,10 @@ static void jstep_atom(orc_sim *s, int i, int32_t phase, double h) {
     if (sumE / Lam > h) break;
     int sg;
     int64_t pos = pick_by_bound(&T, u[2], &sg);
-    int j = s->cand[s->cptr[i] + pos].j;
+    const cand_t *cj = &s->cand[s->cptr[i] + pos];
+    int j = cj->j;
     double F[3];
-    double F2 = long_grad(s, i, j, 0, F);
+    double F2 = long_grad(s, i, cj, 0, F);
     s->nprop[i]++;
     double vF = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
     double p = (vF > 0.0 ? vF : 0.0) / (vn * T.ell[sg]);
@@ -675,9 +732,10 @@ static int64_t cstep_atom(orc_sim *s, int i, int32_t phase, double h, const doub
       int64_t pos;
       if (adaptive && !(u[1] * Lam < Wb)) pos = pick_uniform(&T, u[2], &sg);
       else pos = pick_by_bound(&T, u[2], &sg);
-      int j = s->cand[s->cptr[i] + pos].j;
+      const cand_t *cj = &s->cand[s->cptr[i] + pos];
+      int j = cj->j;
       double F[3];
-      double F2 = long_grad(s, i, j, 1, F);
+      double F2 = long_grad(s, i, cj, 1, F);
       s->nprop[i]++;
       double ell = T.ell[sg];
       double c = adaptive ? bBv * ell + f : (bps ? bBv * ell : ell * (bBv + f));
@@ -967,7 +1025,7 @@ orc_sim *orc_create(const orc_system *sy, const orc_split *sp, const orc_params 
   if (s->nr == 1) s->rw = (s->rc + s->skin) - (s->rlo - s->skin);
   if (!(s->w > 0.0) || !(s->rs <= s->rc) || s->skin < 0.0 || !(s->rw > 0.0)) FAIL("bad split");
   for (int c = 0; c < 3; c++)
-    if (!(s->rc < 0.5 * s->L[c])) FAIL("r_c must be below half the box edge");
+    if (!(s->L[c] > s->rc + s->skin)) FAIL("every box edge must exceed r_c + skin");
   s->dt = pa->dt; s->gamma = pa->gamma; s->kT = pa->kT; s->beta = 1.0 / pa->kT;
   s->seed = pa->seed; s->replica = pa->replica;
   s->jlj = pa->jump_lj; s->jc = pa->jump_coul; s->eps0 = pa->eps;
@@ -1099,23 +1157,33 @@ void orc_rdf(const orc_sim *s, int ta, int tb, double r_max, int n_bins, double 
 
 int32_t orc_n_segments(const orc_sim *s) { return s->S; }
 int64_t orc_cand_count(const orc_sim *s, int32_t i) { return s->cptr[i + 1] - s->cptr[i]; }
-void orc_cand_row(const orc_sim *s, int32_t i, int32_t *j) {
-  for (int64_t p = s->cptr[i]; p < s->cptr[i + 1]; p++) j[p - s->cptr[i]] = s->cand[p].j;
+void orc_cand_row(const orc_sim *s, int32_t i, int32_t *j, int32_t *n) {
+  for (int64_t p = s->cptr[i]; p < s->cptr[i + 1]; p++) {
+    j[p - s->cptr[i]] = s->cand[p].j;
+    if (n)
+      for (int c = 0; c < 3; c++) n[3 * (p - s->cptr[i]) + c] = s->cand[p].n[c];
+  }
 }
 void orc_seg_start(const orc_sim *s, int32_t i, int32_t *starts) {
   memcpy(starts, s->segst + (int64_t)i * (s->S + 1), sizeof(int32_t) * (size_t)(s->S + 1));
 }
 
-/* unordered non-excluded pairs (i<j) with r < rcut at the current positions */
+/* unordered non-excluded pairs (i<j, each periodic image once) with r < rcut
+ * at the current positions */
 int64_t orc_pairs_within(const orc_sim *s, double rcut, int32_t *ij, int64_t cap) {
   int64_t c = 0;
+  int nimg;
+  int32_t nv[27][3], code[27];
   for (int i = 0; i < s->n; i++)
     for (int j = i + 1; j < s->n; j++) {
       if (excluded(s, i, j)) continue;
-      double d[3], r = pair_vec(s, i, j, d);
-      if (r < rcut) {
-        if (c < cap) { ij[2 * c] = i; ij[2 * c + 1] = j; }
-        c++;
+      images_within(s, i, j, rcut, &nimg, nv, code);
+      for (int q = 0; q < nimg; q++) {
+        double d[3], r = pair_vec_n(s, i, j, nv[q], d);
+        if (r < rcut) {
+          if (c < cap) { ij[2 * c] = i; ij[2 * c + 1] = j; }
+          c++;
+        }
       }
     }
   return c;

@@ -110,7 +110,7 @@ void orc_rdf(const orc_sim *s, int ta, int tb, double r_max, int n_bins, double 
 void orc_build_lists(orc_sim *s);
 int32_t orc_n_segments(const orc_sim *s);
 int64_t orc_cand_count(const orc_sim *s, int32_t i);
-void orc_cand_row(const orc_sim *s, int32_t i, int32_t *j);
+void orc_cand_row(const orc_sim *s, int32_t i, int32_t *j, int32_t *n); /* n: [3*len] image vectors, may be NULL */
 void orc_seg_start(const orc_sim *s, int32_t i, int32_t *starts); /* [S+1] */
 int64_t orc_pairs_within(const orc_sim *s, double rcut, int32_t *ij, int64_t cap);
 void orc_bounds(const orc_sim *s, double *ell_lj, double *ell_coul_unit, double *qmax);

@@ -89,7 +89,7 @@ def lib():
         L.orc_n_segments.restype = C.c_int32
         L.orc_cand_count.argtypes = [C.c_void_p, C.c_int32]
         L.orc_cand_count.restype = C.c_int64
-        L.orc_cand_row.argtypes = [C.c_void_p, C.c_int32, _ip]
+        L.orc_cand_row.argtypes = [C.c_void_p, C.c_int32, _ip, _ip]
         L.orc_seg_start.argtypes = [C.c_void_p, C.c_int32, _ip]
         L.orc_pairs_within.argtypes = [C.c_void_p, C.c_double, _ip, C.c_int64]
         L.orc_pairs_within.restype = C.c_int64
@@ -292,11 +292,17 @@ class OracleSim:
         return lib().orc_n_segments(self._h)
 
     def cand_row(self, i):
+        return self.cand_row_images(i)[0]
+
+    def cand_row_images(self, i):
+        """Candidate row of atom i: partners j and the lattice vector n of
+        each candidate image (displacement x_i - x_j - n L), shape [len, 3]."""
         n = lib().orc_cand_count(self._h, i)
         j = np.zeros(n, np.int32)
+        img = np.zeros((n, 3), np.int32)
         if n:
-            lib().orc_cand_row(self._h, i, _ptr(j, _ip))
-        return j
+            lib().orc_cand_row(self._h, i, _ptr(j, _ip), _ptr(img, _ip))
+        return j, img
 
     def seg_start(self, i):
         s = np.zeros(self.n_segments + 1, np.int32)

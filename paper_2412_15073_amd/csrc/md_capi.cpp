@@ -56,7 +56,8 @@ struct md_ctx {
   double *d_scratch = nullptr; size_t scratch_n = 0;
   unsigned long long *d_hist = nullptr; int hist_n = 0;
   double cap_factor = 1.5;     // initial row capacity / density estimate
-  int nrep_max = 0;            // atoms of the largest replica (rows never need more entries)
+  int nrep_max = 0;            // atoms of the largest replica
+  int row_most = 1;            // longest possible row (entries)
   // Rollback point for regrowing the rows: the state at the first stepping
   // call after the last good synchronisation, and the stepping calls since.
   struct Snap {
@@ -430,10 +431,12 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
     return fail(nullptr, MD_ERR_ARG, "precision must be MD_FP64 or MD_FP32_MIXED");
   if (s->n_types * std::max(1, sp->n_rings) > 32)
     return fail(nullptr, MD_ERR_ARG, "n_types * n_rings must be <= 32");
+  // every edge above r_c + skin: an atom never meets its own image, and only
+  // the images next to the nearest one can come within r_c + skin
   for (int r = 0; r < s->n_replicas; ++r)
     for (int d = 0; d < 3; ++d)
-      if (!(sp->r_c < 0.5 * s->box[3 * r + d]))
-        return fail(nullptr, MD_ERR_ARG, "r_c must be below half of every box edge");
+      if (!(s->box[3 * r + d] > sp->r_c + sp->skin))
+        return fail(nullptr, MD_ERR_ARG, "every box edge must exceed r_c + skin");
   double rlo = sp->r_s - sp->switch_width;
   for (int ab = 0; ab < s->n_types * s->n_types; ++ab)
     if (s->lj_eps[ab] != 0.0 && rlo < 1.25 * s->lj_sigma[ab])
@@ -459,6 +462,15 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
     }
   } else if (nrep != 1) {
     return fail(nullptr, MD_ERR_ARG, "replica_offset required");
+  }
+  // replicas with an edge below 2 (r_c + skin) keep explicit images in their
+  // rows: 13 bits of local atom index in the row builder's sort keys
+  for (int r = 0; r < nrep; ++r) {
+    const double rout = sp->r_c + sp->skin;
+    const double *L = s->box + 3 * r;
+    const int na = s->replica_offset ? s->replica_offset[r + 1] - s->replica_offset[r] : n;
+    if ((L[0] < 2.0 * rout || L[1] < 2.0 * rout || L[2] < 2.0 * rout) && na > 8192)
+      return fail(nullptr, MD_ERR_ARG, "a replica with an edge below 2 (r_c + skin) may hold at most 8192 atoms");
   }
   for (int r = 0; r < nrep; ++r)
     for (int d = 0; d < 3; ++d)
@@ -683,9 +695,23 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.ncell_total = coff[nrep];
   auto sphere = [](double r) { return 4.0 / 3.0 * M_PI * r * r * r; };
   c->nrep_max = nrep_max;
+  // longest possible row: every other atom of the largest replica, in up to
+  // 27 images where some edge is below 2 (r_c + skin)
+  bool any_img = false;
+  int img_atoms = 0;   // atoms of the largest replica with explicit images
+  for (int r = 0; r < nrep; ++r) {
+    bool im = false;
+    for (int d = 0; d < 3; ++d) im = im || c->box[3 * r + d] < 2.0 * V.rout;
+    if (im) img_atoms = std::max(img_atoms, c->rep_off[r + 1] - c->rep_off[r]);
+    any_img = any_img || im;
+  }
+  c->row_most = std::max(1, any_img ? 27 * nrep_max : nrep_max - 1);
+  // the row builder's stencil queue of such a replica holds at most its atoms
+  V.qimg = 0;
+  if (any_img) { V.qimg = 64; while (V.qimg < img_atoms) V.qimg <<= 1; }
   auto capf = [&](double vol, int extra) {
     long long v = (long long)std::ceil(c->cap_factor * rho_max * vol) + extra;
-    return (int)std::min<long long>(v, nrep_max - 1 > 0 ? nrep_max - 1 : 1);
+    return (int)std::min<long long>(v, c->row_most);
   };
   V.cap_s = capf(sphere(V.rs + V.skin), 32);
   V.cap_f = capf(sphere(V.rout), 64);
@@ -693,11 +719,11 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   auto pow2 = [](int x) { int m = 1; while (m < x) m <<= 1; return m; };
   c->pc = pow2(std::max(V.cap_c, V.cap_f));
   c->ps = pow2(V.cap_s);
-  if (n >= (1 << 24)) {
+  if (n >= (1 << 23)) {
     delete c;
-    return fail(nullptr, MD_ERR_ARG, "at most 2^24 - 1 atoms (24-bit atom field of the row sort keys)");
+    return fail(nullptr, MD_ERR_ARG, "at most 2^23 - 1 atoms (23-bit atom field of the row entries)");
   }
-  if (c->pc > 8192 || c->ps > 4096) {
+  if (c->pc > 8192 || c->ps > 4096 || 4 * (c->pc + 64 + c->ps + V.qimg) > 65536) {
     delete c;
     return fail(nullptr, MD_ERR_ARG, "neighbour rows too long for the LDS row builder (density * (r_c + skin)^3 too large)");
   }
@@ -1092,7 +1118,7 @@ extern "C" int md_step_baoab_respa(md_ctx *c, int64_t n_outer) {
 // and the captured graphs (which hold the old addresses) dropped.
 static int regrow(md_ctx *c, const MDCtl &h) {
   MDView &V = c->V;
-  const int most = std::max(1, c->nrep_max - 1);
+  const int most = c->row_most;
   auto grown = [&](int need, int have, int extra) {
     return std::min(most, std::max(have, need + need / 4 + extra));
   };
@@ -1103,7 +1129,7 @@ static int regrow(md_ctx *c, const MDCtl &h) {
   int pc = std::max(c->pc, pow2(std::max(cap_c, cap_f)));
   if (h.ovf_queue) pc = std::max(pc, pow2(h.ovf_queue + h.ovf_queue / 4 - 64));
   const int ps = std::max(c->ps, pow2(cap_s));
-  if (pc > 8192 || ps > 4096)
+  if (pc > 8192 || ps > 4096 || 4 * (pc + 64 + ps + V.qimg) > 65536)
     return fail(c, MD_ERR_CAPACITY, "neighbour rows of " + std::to_string(std::max(h.ovf_long, h.ovf_queue)) +
                                         " candidates / " + std::to_string(h.ovf_short) +
                                         " short entries exceed the row builder's limits (8192 / 4096)");
@@ -1178,6 +1204,7 @@ static int restore_snapshot(md_ctx *c) {
 }
 
 static int run_call(md_ctx *c, const md_ctx::Call &k);
+static int report_flags(md_ctx *c);
 
 // Synchronise and report. Rows that outgrew their capacity are recovered
 // here: back to the snapshot, regrow, replay the stepping calls since (the
@@ -1219,6 +1246,12 @@ static int settle(md_ctx *c) {
   }
   c->snap.valid = false;
   c->journal.clear();
+  return report_flags(c);
+}
+
+// Device-side error flags of the last synchronisation (ctl_host), after any
+// row overflow has been dealt with.
+static int report_flags(md_ctx *c) {
   const MDCtl &h = c->ctl_host;
   if (h.nonfinite) return fail(c, MD_ERR_UNSTABLE, "non-finite velocities");
   if (c->par.rebuild_every > 0 && h.n_list_err)
@@ -1418,15 +1451,27 @@ extern "C" int md_rdf(md_ctx *c, int32_t ta, int32_t tb, double r_max, int32_t n
   return rc;
 }
 
-extern "C" int md_get_cand_row(md_ctx *c, int32_t i, int32_t *j, int32_t cap, int32_t *n, int32_t *seg) {
+extern "C" int md_get_cand_row(md_ctx *c, int32_t i, int32_t *j, int32_t *img, int32_t cap, int32_t *n,
+                               int32_t *seg) {
   if (!c || !n || i < 0 || i >= c->n || cap < 0) return fail(c, MD_ERR_ARG, "bad argument");
   int rc = settle(c);
   if (rc || (rc = ensure_rows(c, ROW_SHORT | ROW_CAND)) || (rc = settle(c))) return rc;
   int cnt = 0;
   HIPCHK(c, hipMemcpy(&cnt, c->V.ccnt + i, sizeof(int), hipMemcpyDeviceToHost));
   *n = cnt;
-  if (j && cnt) HIPCHK(c, hipMemcpy(j, c->V.crow + (size_t)i * c->V.cap_c, sizeof(int) * std::min(cnt, cap),
-                                    hipMemcpyDeviceToHost));
+  const int m = std::min(cnt, cap);
+  if ((j || img) && m > 0) {
+    std::vector<int> e(m);
+    HIPCHK(c, hipMemcpy(e.data(), c->V.crow + (size_t)i * c->V.cap_c, sizeof(int) * m, hipMemcpyDeviceToHost));
+    const int r = (int)(std::upper_bound(c->rep_off.begin(), c->rep_off.end(), i) - c->rep_off.begin()) - 1;
+    const double *L = c->box.data() + 3 * (size_t)r;
+    const double rout = c->V.rout;
+    const bool has_img = L[0] < 2.0 * rout || L[1] < 2.0 * rout || L[2] < 2.0 * rout;
+    for (int q = 0; q < m; ++q) {
+      if (j) j[q] = e[q] & 0x7fffff;
+      if (img) img[q] = has_img ? (int32_t)((uint32_t)e[q] >> 23) : -1;
+    }
+  }
   if (seg) HIPCHK(c, hipMemcpy(seg, c->V.segst + (size_t)i * (c->S + 1), sizeof(int) * (c->S + 1),
                                hipMemcpyDeviceToHost));
   return MD_OK;

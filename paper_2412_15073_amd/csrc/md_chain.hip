@@ -17,14 +17,15 @@ __device__ __forceinline__ double seg_ell(const MDView &V, int a, int sg, int co
   return (absq * V.qseg[sg]) * V.ell_cu[idx];
 }
 
-// long-range gradient in FP32 (mixed-precision path): displacement in FP64,
+// long-range gradient in FP32 (mixed-precision path) for the candidate image
+// of row entry e: displacement in FP64,
 // pair arithmetic in float, gradient returned in FP64
 __device__ __forceinline__ double long_grad_f(const MDView &V, double4 xi, double4 xj, int a, int b, int coul,
-                                              const double *L, const double *iL, double &Fx, double &Fy,
-                                              double &Fz) {
-  const float dx = (float)min_img(xi.x - xj.x, L[0], iL[0]);
-  const float dy = (float)min_img(xi.y - xj.y, L[1], iL[1]);
-  const float dz = (float)min_img(xi.z - xj.z, L[2], iL[2]);
+                                              const double *L, const double *iL, bool img, int e, double &Fx,
+                                              double &Fy, double &Fz) {
+  double ddx, ddy, ddz;
+  row_disp(xi, xj, L, iL, img, e, ddx, ddy, ddz);
+  const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
   const float r2 = dx * dx + dy * dy + dz * dz;
   const float r = sqrtf(r2);
   const float ir = 1.0f / r;
@@ -48,11 +49,10 @@ __device__ __forceinline__ double long_grad_f(const MDView &V, double4 xi, doubl
 
 // long-range gradient F_ij = grad_i (1 - chi) U_ij of one component (Sec. 3.1, 3.2)
 __device__ __forceinline__ double long_grad_d(const MDView &V, double4 xi, double4 xj, int a, int b,
-                                            int coul, const double *L, const double *iL,
+                                            int coul, const double *L, const double *iL, bool img, int e,
                                             double &Fx, double &Fy, double &Fz) {
-  double dx = min_img(xi.x - xj.x, L[0], iL[0]);
-  double dy = min_img(xi.y - xj.y, L[1], iL[1]);
-  double dz = min_img(xi.z - xj.z, L[2], iL[2]);
+  double dx, dy, dz;
+  row_disp(xi, xj, L, iL, img, e, dx, dy, dz);
   double r2 = dx * dx + dy * dy + dz * dz;
   double r = sqrt(r2);
   const double ir = 1.0 / r;
@@ -77,9 +77,10 @@ __device__ __forceinline__ double long_grad_d(const MDView &V, double4 xi, doubl
 // PREC: MD_FP64 or MD_FP32_MIXED (pair arithmetic and Theta in float)
 template <int PREC>
 __device__ __forceinline__ double long_grad(const MDView &V, double4 xi, double4 xj, int a, int b, int coul,
-                                            const double *L, const double *iL, double &Fx, double &Fy, double &Fz) {
-  if (PREC == MD_FP32_MIXED) return long_grad_f(V, xi, xj, a, b, coul, L, iL, Fx, Fy, Fz);
-  return long_grad_d(V, xi, xj, a, b, coul, L, iL, Fx, Fy, Fz);
+                                            const double *L, const double *iL, bool img, int e, double &Fx,
+                                            double &Fy, double &Fz) {
+  if (PREC == MD_FP32_MIXED) return long_grad_f(V, xi, xj, a, b, coul, L, iL, img, e, Fx, Fy, Fz);
+  return long_grad_d(V, xi, xj, a, b, coul, L, iL, img, e, Fx, Fy, Fz);
 }
 
 // Theta in the chain's real type (float in the mixed path)
@@ -404,6 +405,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   }
   rp.saved = false;
   const int *row = V.crow + (size_t)i * V.cap_c;
+  const bool img = rep_images(L, V.rout);   // row entries carry explicit images
   const double inv_nr = 1.0 / (double)V.nr;
   const bool adaptive = isC && (V.jc == MD_JUMP_MRZ_ADAPTIVE);
   const bool bpsC = CB && isC;   // C with BPS bounces: no Z
@@ -476,7 +478,8 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         double ellb, ellf;
         int pb, pf, sb, sf;
         T.template pick2<seg_el_in_lds(G)>(V, u01(uw.w[2]), adaptive, pb, ellb, sb, pf, ellf, sf);
-        const int jb = row[pb], jf = row[pf];
+        const int eb = row[pb], ef = row[pf];
+        const int jb = row_j(eb), jf = row_j(ef);
         const double4 xb = X[jb], xf = X[jf];
         const int lb = V.loc[jb], lf = V.loc[jf];
         u32x4 zw;
@@ -485,11 +488,12 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         pwords[sl] = make_uint2(uw.w[1], uw.w[3]);
         double Fx, Fy, Fz;
         // segment sg = b * nr + ring: the partner's type without a load
-        long_grad<PREC>(V, xi, xb, a, (int)(((double)sb + 0.5) * inv_nr), isC ? 1 : 0, L, iL, Fx, Fy, Fz);
+        long_grad<PREC>(V, xi, xb, a, (int)(((double)sb + 0.5) * inv_nr), isC ? 1 : 0, L, iL, img, eb, Fx, Fy,
+                        Fz);
         ring[RF_BX * M + sl] = (R)Fx; ring[RF_BY * M + sl] = (R)Fy; ring[RF_BZ * M + sl] = (R)Fz;
         ring[RF_BL * M + sl] = (R)ellb;
         if (adaptive) {
-          long_grad<PREC>(V, xi, xf, a, 0, 1, L, iL, Fx, Fy, Fz);
+          long_grad<PREC>(V, xi, xf, a, 0, 1, L, iL, img, ef, Fx, Fy, Fz);
           ring[RF_FX * M + sl] = (R)Fx; ring[RF_FY * M + sl] = (R)Fy; ring[RF_FZ * M + sl] = (R)Fz;
           ring[RF_FL * M + sl] = (R)ellf;
         }

@@ -144,6 +144,7 @@ struct MDView {
   const int *rep_off;                   // [nrep+1] first atom of each replica
   unsigned long long *rep_maxd2;        // [2*nrep] max |x - x_ref|^2 (double bits) per step parity and replica
   int ncell_total;
+  int qimg;                             // row builder queue slots of replicas with explicit images (0: none)
   // neighbour rows (row-major, fixed capacity)
   int cap_s, cap_f, cap_c;
   int *srow, *scnt, *frow, *fcnt, *crow, *ccnt, *segst;
@@ -175,6 +176,45 @@ __device__ __forceinline__ void wave_lds_sync() {
 // -------------------------------------------------------------- geometry
 __device__ __forceinline__ double min_img(double d, double L, double iL) {
   return d - L * rint(d * iL);
+}
+
+// Row entries: bits 0-22 hold the partner j (global index); in replicas with
+// an edge shorter than 2 (r_c + skin), where a partner can have several
+// images within the cutoff, bits 23-31 hold the image: the lattice vector n
+// of the image x_j + n L, each component modulo 8 (3 bits each, x lowest).
+// Between two row builds no atom moves by half an edge, so the nearest
+// image m of the current displacement is within 1 of the build's, and n
+// (within 1 of the build's nearest) is within 2 of m: n mod 8 fixes n.
+#define MD_ROW_J_MASK 0x7fffff
+#define MD_ROW_IMG_SHIFT 23
+
+__device__ __forceinline__ int row_j(int e) { return e & MD_ROW_J_MASK; }
+
+// whether the replica's rows carry explicit images (some edge < 2 (r_c + skin))
+__device__ __forceinline__ bool rep_images(const double *L, double rout) {
+  return L[0] < 2.0 * rout || L[1] < 2.0 * rout || L[2] < 2.0 * rout;
+}
+
+// d - n L for the image whose lattice component is congruent to c3 mod 8
+__device__ __forceinline__ double img_comp(double d, double L, double iL, int c3) {
+  const int m = (int)rint(d * iL);
+  int dd = (c3 - m) & 7;
+  dd = dd >= 4 ? dd - 8 : dd;
+  return d - L * (double)(m + dd);
+}
+
+// displacement x_i - (image of x_j) of row entry e
+__device__ __forceinline__ void row_disp(double4 xi, double4 xj, const double *L, const double *iL, bool img,
+                                         int e, double &dx, double &dy, double &dz) {
+  dx = xi.x - xj.x; dy = xi.y - xj.y; dz = xi.z - xj.z;
+  if (!img) {
+    dx = min_img(dx, L[0], iL[0]); dy = min_img(dy, L[1], iL[1]); dz = min_img(dz, L[2], iL[2]);
+  } else {
+    const unsigned c = (unsigned)e >> MD_ROW_IMG_SHIFT;
+    dx = img_comp(dx, L[0], iL[0], (int)(c & 7u));
+    dy = img_comp(dy, L[1], iL[1], (int)((c >> 3) & 7u));
+    dz = img_comp(dz, L[2], iL[2], (int)((c >> 6) & 7u));
+  }
 }
 
 // --------------------------------------------------------- pair terms (FP64)

@@ -279,16 +279,21 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
                                               int forced, int autob, double thr2, int pc, int ps) {
   if (!rebuild_now(V, slot, forced, autob, thr2, V.rep[blockIdx.x])) return;
   extern __shared__ unsigned lds[];
-  // candidate or full keys [pc], and the pass-1 queue of stencil atoms, which
-  // also holds the atom itself, its excluded partners and the margin band:
-  // 64 slots more; then the short keys [ps]
-  unsigned *kc = lds;
-  const int pq = pc + 64;
-  unsigned *ks = lds + pq;
   const int i = blockIdx.x, lane = threadIdx.x;
   const double4 xi = X[i];
   const int r = V.rep[i];
   const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+  const bool img = rep_images(L, V.rout);
+  // candidate or full keys [pc], and the pass-1 queue of stencil atoms, which
+  // also holds the atom itself, its excluded partners and the margin band:
+  // 64 slots more; then the short keys [ps]. Pass 2 writes at most one key
+  // per queued atom, so keys overwrite only queue slots already read. With
+  // explicit images one atom can give several keys: the queue then has its
+  // own V.qimg slots after the short keys (at least the replica's atoms).
+  unsigned *kc = lds;
+  unsigned *ks = lds + pc + 64;
+  unsigned *kq = img ? ks + ps : kc;
+  const int pq = img ? V.qimg : pc + 64;
   const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
   const int nd[3] = {V.rep_cdim[3 * r], V.rep_cdim[3 * r + 1], V.rep_cdim[3 * r + 2]};
   const int coff = V.rep_cell_off[r];
@@ -371,19 +376,26 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     if (keep) {
       const int pos = nq + __popcll(mq & below);
-      if (pos < pq) kc[pos] = (unsigned)q;
+      if (pos < pq) kq[pos] = (unsigned)q;
     }
     nq += __popcll(mq);
   }
   const int nqq = min(nq, pq);
   wave_lds_sync();
-  // Pass 2: exact FP64 decisions for the queued atoms.
+  // Pass 2: exact FP64 decisions for the queued atoms. In a replica with an
+  // edge below 2 (r_c + skin) every image of j next to the nearest one (along
+  // the short edges) is tested too, and keys carry the image: segment << 27
+  // | local j << 14 | image number << 9 | image code (the lattice vector mod 8
+  // of the row entry); the image number (s_x+1) + 3 (s_y+1) + 9 (s_z+1) of
+  // the offset s from the nearest image orders the images of one j.
+  // Otherwise keys are segment << 24 | j (candidates) or j.
+  const int rep0 = V.rep_off[r];
   for (int base = 0; base < nqq; base += 64) {
     int j = -1;
     double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
     bool ok = base + lane < nqq;
     if (ok) {
-      const int q = (int)kc[base + lane];
+      const int q = (int)kq[base + lane];
       j = V.cell_atoms[q];
       xj = V.xcell[q];
     }
@@ -391,38 +403,49 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
     ok = ok && j != i && j != ex[0] && j != ex[1] && j != ex[2] && j != ex[3];
     if (ok && ex_more)
       for (int e = x0 + 4; ok && e < x1; ++e) ok = (V.xj[e] != j);
-    bool bs = false, bk = false;
-    unsigned key = 0;
-    if (ok) {
-      const double ddx = min_img(xi.x - xj.x, L[0], iL[0]);
-      const double ddy = min_img(xi.y - xj.y, L[1], iL[1]);
-      const double ddz = min_img(xi.z - xj.z, L[2], iL[2]);
-      const double rr = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-      bs = (want & 1) && rr < rs_out;
-      if (want & 4) {
-        bk = rr >= V.rin && rr < V.rout;
-        if (bk) {
-          int ring = (int)floor((rr - V.rin) / V.rw);
-          ring = ring < 0 ? 0 : (ring > V.nr - 1 ? V.nr - 1 : ring);
-          key = ((unsigned)(V.type[j] * V.nr + ring) << 24) | (unsigned)j;
+    const double d0x = xi.x - xj.x, d0y = xi.y - xj.y, d0z = xi.z - xj.z;
+    const double mx = rint(d0x * iL[0]), my = rint(d0y * iL[1]), mz = rint(d0z * iL[2]);
+    for (int si = img ? 0 : 13; si < (img ? 27 : 14); ++si) {   // image offsets, uniform over the wave
+      const int sx = si % 3 - 1, sy = (si / 3) % 3 - 1, sz = si / 9 - 1;
+      if ((sx && !(L[0] < 2.0 * V.rout)) || (sy && !(L[1] < 2.0 * V.rout)) || (sz && !(L[2] < 2.0 * V.rout)))
+        continue;
+      bool bs = false, bk = false;
+      unsigned key = 0, skey = 0;
+      if (ok) {
+        const double nx = mx + (double)sx, ny = my + (double)sy, nz = mz + (double)sz;
+        const double ddx = d0x - L[0] * nx, ddy = d0y - L[1] * ny, ddz = d0z - L[2] * nz;
+        const double rr = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+        bs = (want & 1) && rr < rs_out;
+        const unsigned low = img ? ((unsigned)(j - rep0) << 14) | ((unsigned)si << 9) |
+                                       ((unsigned)((int)nx & 7)) | ((unsigned)((int)ny & 7) << 3) |
+                                       ((unsigned)((int)nz & 7) << 6)
+                                 : (unsigned)j;
+        skey = low;
+        if (want & 4) {
+          bk = rr >= V.rin && rr < V.rout;
+          if (bk) {
+            int ring = (int)floor((rr - V.rin) / V.rw);
+            ring = ring < 0 ? 0 : (ring > V.nr - 1 ? V.nr - 1 : ring);
+            key = ((unsigned)(V.type[j] * V.nr + ring) << (img ? 27 : 24)) | low;
+          }
+        } else if (want & 2) {
+          bk = rr < V.rout;
+          key = low;
         }
-      } else if (want & 2) {
-        bk = rr < V.rout;
-        key = (unsigned)j;
       }
+      const unsigned long long mk = __ballot(bk), ms = __ballot(bs);
+      const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+      if (bk) {
+        const int pos = nk + __popcll(mk & below);
+        if (pos < pc) kc[pos] = key;
+      }
+      if (bs) {
+        const int pos = nsr + __popcll(ms & below);
+        if (pos < ps) ks[pos] = skey;
+      }
+      nk += __popcll(mk);
+      nsr += __popcll(ms);
     }
-    const unsigned long long mk = __ballot(bk), ms = __ballot(bs);
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (bk) {
-      const int pos = nk + __popcll(mk & below);
-      if (pos < pc) kc[pos] = key;
-    }
-    if (bs) {
-      const int pos = nsr + __popcll(ms & below);
-      if (pos < ps) ks[pos] = (unsigned)j;
-    }
-    nk += __popcll(mk);
-    nsr += __popcll(ms);
   }
   // requested lengths beyond capacity: the host regrows the rows and replays
   // the steps since its last good synchronisation
@@ -432,17 +455,26 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
     if (nq > pq) atomicMax(&V.ctl->ovf_queue, nq);
   }
   const int nkk = min(nk, min(capk, pc)), nss = min(nsr, min(V.cap_s, ps));
+  // key -> row entry: the partner's global index, with the image code above it
+  auto entry = [&](unsigned key) -> int {
+    if (!img) return (int)(key & (unsigned)MD_ROW_J_MASK);
+    return (int)(((unsigned)rep0 + ((key >> 14) & 0x1fffu)) | ((key & 0x1ffu) << MD_ROW_IMG_SHIFT));
+  };
   if (want & 6) {
     __syncthreads();
     sort_keys(kc, nkk);
     int *row = (want & 4) ? V.crow + (size_t)i * V.cap_c : V.frow + (size_t)i * V.cap_f;
-    for (int e = lane; e < nkk; e += 64) row[e] = (int)(kc[e] & 0xffffffu);
+    for (int e = lane; e < nkk; e += 64) row[e] = entry(kc[e]);
     if (lane == 0) { if (want & 4) V.ccnt[i] = nkk; else V.fcnt[i] = nkk; }
     if (want & 4) {
       for (int sg = lane; sg <= V.S; sg += 64) {
-        const unsigned probe = (unsigned)sg << 24;
         int lo = 0, hi = nkk;
-        while (lo < hi) { int mid = (lo + hi) >> 1; if (kc[mid] < probe) lo = mid + 1; else hi = mid; }
+        if (sg < V.S) {   // (S << 27 would not fit 32 bits)
+          const unsigned probe = (unsigned)sg << (img ? 27 : 24);
+          while (lo < hi) { int mid = (lo + hi) >> 1; if (kc[mid] < probe) lo = mid + 1; else hi = mid; }
+        } else {
+          lo = nkk;
+        }
         V.segst[(size_t)i * (V.S + 1) + sg] = lo;
       }
     }
@@ -451,7 +483,7 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
     __syncthreads();
     sort_keys(ks, nss);
     int *row = V.srow + (size_t)i * V.cap_s;
-    for (int e = lane; e < nss; e += 64) row[e] = (int)ks[e];
+    for (int e = lane; e < nss; e += 64) row[e] = entry(ks[e]);
     if (lane == 0) V.scnt[i] = nss;
   }
 }
@@ -518,19 +550,20 @@ __global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__rest
   if (i < V.n) {
     const double4 xi = X[i];
     const int a = V.type[i], r = V.rep[i];
-    const double L0 = V.box[3 * r], L1 = V.box[3 * r + 1], L2 = V.box[3 * r + 2];
-    const double iL0 = 1.0 / L0, iL1 = 1.0 / L1, iL2 = 1.0 / L2;
+    const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+    const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+    const bool img = rep_images(L, V.rout);
     const int *row = MODE == 0 ? V.srow + (size_t)i * V.cap_s : V.frow + (size_t)i * V.cap_f;
     const int cnt = MODE == 0 ? V.scnt[i] : V.fcnt[i];
     const float cut = (float)(MODE == 0 ? V.rs : V.rc);
     const float cut2 = cut * cut;
     const float kq = (float)(V.ke * xi.w);
     for (int k = lane; k < cnt; k += SG) {
-      const int j = row[k];
+      const int e = row[k], j = row_j(e);
       const double4 xj = X[j];
-      const float dx = (float)min_img(xi.x - xj.x, L0, iL0);
-      const float dy = (float)min_img(xi.y - xj.y, L1, iL1);
-      const float dz = (float)min_img(xi.z - xj.z, L2, iL2);
+      double ddx, ddy, ddz;
+      row_disp(xi, xj, L, iL, img, e, ddx, ddy, ddz);
+      const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
       const float r2 = dx * dx + dy * dy + dz * dz;
       if (r2 < cut2) {
         const float rr = sqrtf(r2);
@@ -578,18 +611,18 @@ __global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restri
   if (i < V.n) {
     const double4 xi = X[i];
     const int a = V.type[i], r = V.rep[i];
-    const double L0 = V.box[3 * r], L1 = V.box[3 * r + 1], L2 = V.box[3 * r + 2];
-    const double iL0 = 1.0 / L0, iL1 = 1.0 / L1, iL2 = 1.0 / L2;
+    const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+    const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+    const bool img = rep_images(L, V.rout);
     const int *row = MODE == 0 ? V.srow + (size_t)i * V.cap_s : V.frow + (size_t)i * V.cap_f;
     const int cnt = MODE == 0 ? V.scnt[i] : V.fcnt[i];
     const double cut = MODE == 0 ? V.rs : V.rc;
     const double cut2 = cut * cut;
     for (int k = lane; k < cnt; k += SG) {
-      const int j = row[k];
+      const int e = row[k], j = row_j(e);
       const double4 xj = X[j];
-      double dx = min_img(xi.x - xj.x, L0, iL0);
-      double dy = min_img(xi.y - xj.y, L1, iL1);
-      double dz = min_img(xi.z - xj.z, L2, iL2);
+      double dx, dy, dz;
+      row_disp(xi, xj, L, iL, img, e, dx, dy, dz);
       double r2 = dx * dx + dy * dy + dz * dz;
       if (r2 < cut2) {
         double rr = sqrt(r2);
@@ -656,17 +689,18 @@ __global__ void k_pair_energy(MDView V, const double4 *__restrict__ X, int which
   const double4 xi = X[i];
   const int a = V.type[i], r = V.rep[i];
   const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+  const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+  const bool img = rep_images(L, V.rout);
   const int *row; int cnt;
   if (which == 0) { row = V.srow + (size_t)i * V.cap_s; cnt = V.scnt[i]; }
   else if (which == 1) { row = V.crow + (size_t)i * V.cap_c; cnt = V.ccnt[i]; }
   else { row = V.frow + (size_t)i * V.cap_f; cnt = V.fcnt[i]; }
   double s = 0.0, l = 0.0;
   for (int k = 0; k < cnt; ++k) {
-    int j = row[k];
+    const int e = row[k], j = row_j(e);
     double4 xj = X[j];
-    double dx = min_img(xi.x - xj.x, L[0], 1.0 / L[0]);
-    double dy = min_img(xi.y - xj.y, L[1], 1.0 / L[1]);
-    double dz = min_img(xi.z - xj.z, L[2], 1.0 / L[2]);
+    double dx, dy, dz;
+    row_disp(xi, xj, L, iL, img, e, dx, dy, dz);
     double r2 = dx * dx + dy * dy + dz * dz, rr = sqrt(r2);
     if (rr >= V.rc) continue;
     int ab = a * V.nt + V.type[j];
@@ -746,16 +780,17 @@ __global__ void k_count_pairs(MDView V, const double4 *__restrict__ X, int which
   const double4 xi = X[i];
   const int r = V.rep[i];
   const double L[3] = {V.box[3 * r], V.box[3 * r + 1], V.box[3 * r + 2]};
+  const double iL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+  const bool img = rep_images(L, V.rout);
   const int *row = which == 0 ? V.srow + (size_t)i * V.cap_s : V.frow + (size_t)i * V.cap_f;
   const int cnt = which == 0 ? V.scnt[i] : V.fcnt[i];
   unsigned long long c = 0;
   for (int k = 0; k < cnt; ++k) {
-    int j = row[k];
+    const int e = row[k], j = row_j(e);
     if (j <= i) continue;
     double4 xj = X[j];
-    double dx = min_img(xi.x - xj.x, L[0], 1.0 / L[0]);
-    double dy = min_img(xi.y - xj.y, L[1], 1.0 / L[1]);
-    double dz = min_img(xi.z - xj.z, L[2], 1.0 / L[2]);
+    double dx, dy, dz;
+    row_disp(xi, xj, L, iL, img, e, dx, dy, dz);
     if (dx * dx + dy * dy + dz * dz < cut * cut) ++c;
   }
   if (c) atomicAdd(out, c);
@@ -788,7 +823,7 @@ hipError_t launch_rebuild(const MDView &V, const double4 *X, int want, int slot,
   CHK(hipGetLastError());
   hipLaunchKernelGGL(k_cell_scatter, dim3(nb), dim3(256), 0, s, V, slot, forced, autob, thr2);
   CHK(hipGetLastError());
-  size_t lds = sizeof(unsigned) * (size_t)(pc + 64 + ps);   // keys + queue margin, short keys
+  size_t lds = sizeof(unsigned) * (size_t)(pc + 64 + ps + V.qimg);   // keys + queue margin, short keys, image queue
   hipLaunchKernelGGL(k_build, dim3(V.n), dim3(64), lds, s, V, X, want, slot, forced, autob, thr2, pc, ps);
   return hipGetLastError();
 }

@@ -154,7 +154,7 @@ def load():
     L.md_get_atom_stats.argtypes = [C.c_void_p, _lp, _lp, _lp, _up]
     L.md_get_events.argtypes = [C.c_void_p, C.POINTER(MDEvent), C.c_int64, _lp]
     L.md_rdf.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_int32, _dp]
-    L.md_get_cand_row.argtypes = [C.c_void_p, C.c_int32, _ip, C.c_int32, _ip, _ip]
+    L.md_get_cand_row.argtypes = [C.c_void_p, C.c_int32, _ip, _ip, C.c_int32, _ip, _ip]
     L.md_get_row_counts.argtypes = [C.c_void_p, C.c_int32, _ip]
     L.md_run_phase.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double]
     L.md_profile.argtypes = [C.c_void_p, C.c_int32]
@@ -341,12 +341,16 @@ class Sim:
         self._chk(load().md_rdf(self._h, ta, tb, r_max, n_bins, _ptr(h, _dp)))
         return h
 
-    def cand_row(self, i, n_segments):
+    def cand_row(self, i, n_segments, images=False):
         n = C.c_int32(0)
         seg = np.zeros(n_segments + 1, np.int32)
-        self._chk(load().md_get_cand_row(self._h, i, None, 0, C.byref(n), _ptr(seg, _ip)))
+        self._chk(load().md_get_cand_row(self._h, i, None, None, 0, C.byref(n), _ptr(seg, _ip)))
         j = np.zeros(max(1, n.value), np.int32)
-        self._chk(load().md_get_cand_row(self._h, i, _ptr(j, _ip), n.value, C.byref(n), _ptr(seg, _ip)))
+        img = np.zeros(max(1, n.value), np.int32)
+        self._chk(load().md_get_cand_row(self._h, i, _ptr(j, _ip), _ptr(img, _ip), n.value, C.byref(n),
+                                         _ptr(seg, _ip)))
+        if images:
+            return j[: n.value], img[: n.value], seg
         return j[: n.value], seg
 
     def row_counts(self, which):

@@ -194,12 +194,19 @@ def water_box(n_mol: int, density: float = 0.0334, T: float = 300.0, seed: int =
                   coulomb_k=COULOMB_K, accel_factor=ACCEL_KJ, kB=KB_KJ, name=f"water_{n_mol}")
 
 
+def water_replica_recipe(n_rep: int = 256, n_min: int = 216, n_max: int = 2048, seed: int = 1):
+    """(molecules, seed) of each replica of the ensemble: sizes uniform in
+    [n_min, n_max] molecules."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(n_min, n_max + 1, size=n_rep)
+    return [(int(m), seed * 100003 + r) for r, m in enumerate(sizes)]
+
+
 def water_replicas(n_rep: int = 256, n_min: int = 216, n_max: int = 2048, seed: int = 1,
                    density: float = 0.0334) -> Batch:
     """Replica sizes uniform in [n_min, n_max] molecules, each box at the density."""
-    rng = np.random.default_rng(seed)
-    sizes = rng.integers(n_min, n_max + 1, size=n_rep)
-    return Batch([water_box(int(m), density=density, seed=seed * 100003 + r) for r, m in enumerate(sizes)])
+    return Batch([water_box(m, density=density, seed=sr)
+                  for m, sr in water_replica_recipe(n_rep, n_min, n_max, seed)])
 
 
 # ------------------------------------------------------------------ configs

@@ -42,7 +42,7 @@ def test_create_rejects_bad_arguments_without_touching_the_device():
     """Validation happens before any HIP call: bad splits fail with MD_ERR_ARG."""
     from paper_2412_15073_amd import jumpmd, systems as S
     sy = S.lj_fcc(4)
-    bad = S.Split(r_s=2.0, r_c=3.5, switch_width=0.5, skin=0.3)   # r_c above half the box
+    bad = S.Split(r_s=2.0, r_c=6.5, switch_width=0.5, skin=0.3)   # r_c + skin above the box edge
     with pytest.raises(jumpmd.MDError) as e:
         jumpmd.Sim(sy, bad, S.lj_params(), stream=0)
     assert e.value.code == jumpmd.MD_ERR_ARG

@@ -1,0 +1,139 @@
+"""Replicas whose box edge is below 2 (r_c + skin): a partner can lie within
+the cutoff in two periodic images, and the rows hold every such image (an
+image code in each row entry). GPU against the oracle, which enumerates the
+images by brute force: rows (partner, lattice vector mod 8, segment starts)
+identical, forces within 1e-12, and JUMP / BAOAB runs with identical events
+and FP64 state within 1e-9. The sizes are those of the smallest replicas of
+the 256-replica ensemble (216 waters, 18.6 A, r_c = 10 A)."""
+import numpy as np
+import pytest
+
+from paper_2412_15073_amd import systems as S
+from tests.helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def jm():
+    from paper_2412_15073_amd import jumpmd
+    jumpmd.load()
+    return jumpmd
+
+
+def _small(n_mol=216, seed=31, r_c=10.0, skin=0.5, n_rings=12):
+    sy = S.water_box(n_mol, seed=seed, jitter=0.05)
+    sp = S.water_split(r_s=5.0, r_c=r_c, w=1.0, skin=skin, n_rings=n_rings)
+    assert sy.box[0] < 2 * (r_c + skin)
+    return sy, sp
+
+
+def _code(n):
+    n = np.asarray(n, np.int64) & 7
+    return (n[:, 0] | (n[:, 1] << 3) | (n[:, 2] << 6)).astype(np.int32)
+
+
+def test_rows_with_periodic_images(jm):
+    from oracle.oracle import OracleSim
+    sy, sp = _small()
+    pa = S.water_params()
+    g = jm.Sim(sy, sp, pa)
+    o = OracleSim(sy, sp, pa)
+    o.build_lists()
+    n_multi = 0
+    for i in range(sy.n_atoms):
+        jg, cg, sg = g.cand_row(i, o.n_segments, images=True)
+        jo, no = o.cand_row_images(i)
+        np.testing.assert_array_equal(jg, jo, err_msg=f"row {i}")
+        np.testing.assert_array_equal(cg, _code(no), err_msg=f"images of row {i}")
+        np.testing.assert_array_equal(sg, o.seg_start(i), err_msg=f"segments of row {i}")
+        n_multi += len(jo) - len(set(jo.tolist()))
+    assert n_multi > 1000
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_forces_with_periodic_images(jm, kind):
+    """kind 0: short forces chi U (r < r_s); 1: full-range forces (r < r_c),
+    where partners meet in two images."""
+    from oracle.oracle import OracleSim
+    sy, sp = _small(seed=32)
+    pa = S.water_params(jumps=(kind == 0))
+    g = jm.Sim(sy, sp, pa)
+    o = OracleSim(sy, sp, pa)
+    assert rel_err(g.accel(kind), o.accel(kind)) < 1e-12
+    assert rel_err(g.accel(2), o.accel(2)) < 1e-12
+
+
+@pytest.mark.parametrize("scheme", ["jump", "baoab", "jump_respa"])
+def test_runs_with_periodic_images(jm, scheme):
+    """20 steps (JUMP: adaptive MRZ Coulomb + BPS LJ jumps; BAOAB with full
+    forces; JUMP-RESPA with 3 inner steps) with every accepted jump and all
+    per-atom counts identical."""
+    from oracle.oracle import OracleSim
+    sy, sp = _small(seed=33)
+    pa = S.water_params(jumps=(scheme != "baoab"))
+    pa.log_events = 1
+    pa.respa_inner = 3
+    g = jm.Sim(sy, sp, pa)
+    o = OracleSim(sy, sp, pa)
+    run = {"jump": "step_jump", "baoab": "step_baoab", "jump_respa": "step_jump_respa"}[scheme]
+    n = 7 if scheme == "jump_respa" else 20
+    getattr(g, run)(n)
+    getattr(o, run)(n)
+    xg, vg = g.state()
+    xo, vo = o.state()
+    assert rel_err(xg, xo) < TOL and rel_err(vg, vo) < TOL
+    sg, so = g.atom_stats(), o.atom_stats()
+    for k in ("n_prop", "n_acc", "hash"):
+        np.testing.assert_array_equal(sg[k], so[k], err_msg=k)
+    if scheme != "baoab":
+        eo = o.events()
+        assert len(eo) > 10000
+        np.testing.assert_array_equal(g.events(), eo)
+
+
+def test_ensemble_sized_batch_with_periodic_images(jm):
+    """A batch of the ensemble's kind (fp64 here): replicas of 216, 230, 300
+    and 520 waters at r_c = 10 A, the first three with edges below 21 A; each
+    replica identical to its own oracle run over 10 JUMP steps."""
+    from oracle.oracle import OracleSim
+    sizes = [216, 230, 300, 520]
+    reps = [S.water_box(m, seed=40 + k, jitter=0.05) for k, m in enumerate(sizes)]
+    sp = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=0.5, n_rings=12)
+    pa = S.water_params()
+    pa.log_events = 1
+    batch = S.Batch(reps)
+    g = jm.Sim(batch, sp, pa)
+    g.step_jump(10)
+    xg, vg = g.state()
+    sg = g.atom_stats()
+    evg = g.events()
+    off = batch.offsets
+    for r, sysr in enumerate(reps):
+        o = OracleSim(sysr, sp, pa, replica=r)
+        o.step_jump(10)
+        xo, vo = o.state()
+        a, b = off[r], off[r + 1]
+        assert rel_err(xg[a:b], xo) < TOL and rel_err(vg[a:b], vo) < TOL, r
+        so = o.atom_stats()
+        for k in ("n_prop", "n_acc", "hash"):
+            np.testing.assert_array_equal(sg[k][a:b], so[k], err_msg=f"replica {r} {k}")
+        mine = evg[(evg[:, 2] >= a) & (evg[:, 2] < b)].copy()
+        mine[:, 2] -= a
+        mine[:, 3] -= a
+        np.testing.assert_array_equal(mine, o.events())
+
+
+def test_energies_with_periodic_images(jm):
+    from oracle.oracle import OracleSim
+    sy, sp = _small(seed=34)
+    pa = S.water_params()
+    g = jm.Sim(sy, sp, pa)
+    o = OracleSim(sy, sp, pa)
+    g.step_jump(5)
+    o.step_jump(5)
+    og, oo = g.observables(pe=True), o.energies()
+    for k in ("pe_short", "pe_long", "pe_bonded"):
+        assert abs(og[k] - oo[k]) <= TOL * abs(oo[k]), (k, og[k], oo[k])

@@ -297,6 +297,109 @@ def test_candidate_rows_brute_force(case):
         np.testing.assert_array_equal(o.seg_start(i), starts)
 
 
+def _small_water(n_mol=216, seed=7, r_c=10.0, skin=0.5, n_rings=4):
+    """216 waters in an 18.6 A box with r_c = 10 A: edges below 2 (r_c + skin),
+    so partners can lie within the cutoff in two periodic images."""
+    sy = S.water_box(n_mol, seed=seed, jitter=0.05)
+    sp = S.water_split(r_s=5.0, r_c=r_c, w=1.0, skin=skin, n_rings=n_rings)
+    assert sy.box[0] < 2 * (r_c + skin)
+    return sy, sp
+
+
+def _image_pairs(sy, i, cut, lo=0.0):
+    """Brute force over every lattice vector n in {-2..2}^3 (a superset of
+    the images any cutoff below the edge can reach): (j, n, r) of the images
+    x_j + n L with lo <= |x_i - x_j - n L| < cut, j != i."""
+    L = sy.box
+    out = []
+    ns = np.array([(a, b, c) for c in range(-2, 3) for b in range(-2, 3) for a in range(-2, 3)])
+    for j in range(sy.n_atoms):
+        if j == i:
+            continue
+        d = (sy.pos[i] - sy.pos[j])[None, :] - ns * L
+        r = np.sqrt((d * d).sum(1))
+        for n, rr in zip(ns, r):
+            if lo <= rr < cut:
+                out.append((j, tuple(int(x) for x in n), rr))
+    return out
+
+
+def test_candidate_rows_with_periodic_images_brute_force():
+    """In a box below 2 (r_c + skin) a candidate is one periodic image of j:
+    the rows hold every image x_j + n L with r_s - w - skin <= r < r_c + skin
+    (brute force over n in {-2..2}^3), sorted by (segment, j, image offset
+    from the nearest image), with the image's lattice vector n."""
+    sy, sp = _small_water()
+    o = _oracle(sy, sp, S.water_params())
+    o.build_lists()
+    rlo = sp.r_s - sp.switch_width
+    rin, rout = rlo - sp.skin, sp.r_c + sp.skin
+    nr = sp.n_rings
+    excl = {i: set(sy.excl_j[sy.excl_ptr[i]:sy.excl_ptr[i + 1]].tolist()) for i in range(sy.n_atoms)}
+    n_multi = 0
+    for i in range(0, sy.n_atoms, 37):
+        cands = [(j, n, r) for j, n, r in _image_pairs(sy, i, rout, rin) if j not in excl[i]]
+        keys = []
+        for j, n, r in cands:
+            ring = min(nr - 1, max(0, int(np.floor((r - rin) / sp.ring_width))))
+            m = np.rint((sy.pos[i] - sy.pos[j]) / sy.box).astype(int)
+            s = np.array(n) - m
+            keys.append((int(sy.type[j]) * nr + ring, j, int((s[0] + 1) + 3 * (s[1] + 1) + 9 * (s[2] + 1)), n))
+        keys.sort()
+        jo, no = o.cand_row_images(i)
+        np.testing.assert_array_equal(jo, [k[1] for k in keys])
+        np.testing.assert_array_equal(no, np.array([k[3] for k in keys]).reshape(-1, 3))
+        starts = [sum(1 for k in keys if k[0] < q) for q in range(o.n_segments + 1)]
+        np.testing.assert_array_equal(o.seg_start(i), starts)
+        js = [k[1] for k in keys]
+        n_multi += len(js) - len(set(js))
+    assert n_multi > 0   # some partners do appear in two images
+
+
+def test_energy_and_forces_with_periodic_images():
+    """Small box: the non-bonded energy is the sum over every pair and every
+    periodic image within r_c (brute force over n in {-2..2}^3 with the pinned
+    pair terms), forces are minus its gradient (central differences), and
+    they sum to zero."""
+    sy, sp = _small_water(n_mol=216, seed=8)
+    o = _oracle(sy, sp, S.water_params())
+    excl = {i: set(sy.excl_j[sy.excl_ptr[i]:sy.excl_ptr[i + 1]].tolist()) for i in range(sy.n_atoms)}
+
+    def brute(pos):
+        tot = 0.0
+        s2 = S.System(**{**sy.__dict__, "pos": pos})
+        for i in range(sy.n_atoms):
+            for j, n, r in _image_pairs(s2, i, sp.r_c):
+                if j <= i or j in excl[i]:
+                    continue
+                ti, tj = sy.type[i], sy.type[j]
+                t = O.pair_terms(r, sy.lj_eps[ti * 2 + tj], sy.lj_sigma[ti * 2 + tj], sy.charge[i] * sy.charge[j],
+                                 sy.coulomb_k, sp.coulomb_alpha, sp.r_s, sp.switch_width, sp.r_c)
+                tot += t[0] + t[2]
+        return tot
+
+    e = o.energies()
+    ref = brute(sy.pos)
+    assert abs(e["pe_short"] + e["pe_long"] - ref) < 1e-9 * abs(ref)
+    acc = o.accel(O.F_FULL)
+    me = sy.mass / sy.accel_factor
+    f = acc * me[:, None]
+    assert np.abs(f.sum(0)).max() < 1e-9 * np.abs(f).sum()
+    h = 1e-5
+    for i in (0, 100, 401):
+        for c in range(3):
+            xp, xm = sy.pos.copy(), sy.pos.copy()
+            xp[i, c] += h
+            xm[i, c] -= h
+            o.set_state(pos=xp)
+            ep = o.energies()
+            o.set_state(pos=xm)
+            em = o.energies()
+            fd = -((ep["pe_short"] + ep["pe_long"]) - (em["pe_short"] + em["pe_long"])) / (2 * h)
+            assert abs(f[i, c] - fd) < 1e-5 * max(1.0, abs(fd)), (i, c, f[i, c], fd)
+    o.set_state(pos=sy.pos)
+
+
 def test_bounds_dominate_long_gradient():
     """Each ring bound is >= |grad (1-chi) U| on a dense grid of distances the
     ring can reach (sup over [e_k - skin, r_c))."""
