@@ -224,6 +224,20 @@ int md_get_events(md_ctx *ctx, md_event *buf, int64_t cap, int64_t *n);
  * inside each replica (minimum image), unordered when ta == tb. */
 int md_rdf(md_ctx *ctx, int32_t ta, int32_t tb, double r_max, int32_t n_bins, double *hist);
 
+/* Allocation-free variant of md_rdf, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments and result as md_rdf; n_bins at most
+ * 16384 (MD_ERR_ARG above). The counts live in a static device array of the
+ * library (256 KiB per device, held until the process ends), set up once per
+ * device at md_create; the call allocates nothing and synchronises the
+ * stream. All calls on one device share that array: calls that overlap on
+ * one device (other host threads or streams) race. Rows that outgrew their
+ * capacity since the last synchronisation are not regrown here (regrowing
+ * allocates): the call then returns MD_ERR_CAPACITY and changes nothing, and
+ * md_sync must run first. Other pending device-side errors are reported as by
+ * md_sync. */
+int md_rdf_noalloc(md_ctx *ctx, int32_t ta, int32_t tb, double r_max, int32_t n_bins, double *hist);
+
 /* Neighbour rows as last built (for checks): candidate row of atom i (global
  * j indices, sorted by (type of j, ring, j, image)) and its S+1 segment
  * starts, S = n_types*n_rings. *n receives the row length; j, img and

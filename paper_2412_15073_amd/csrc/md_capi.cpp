@@ -33,6 +33,7 @@ struct Timer {
 
 struct md_ctx {
   hipStream_t stream = nullptr;
+  int dev = 0;                 // device current at creation (the context's device)
   int n = 0, nt = 0, nrep = 0, nr = 1, S = 0;
   md_split split{};
   md_params par{};
@@ -519,6 +520,15 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
     return fail(nullptr, MD_ERR_ARG, "md_allocator needs both alloc and release");
   md_ctx *c = new md_ctx();
   if (alloc) c->alloc = *alloc;
+  if (hipGetDevice(&c->dev) != hipSuccess) {
+    delete c;
+    return fail(nullptr, MD_ERR_HIP, "hipGetDevice failed");
+  }
+  // set-up of the allocation-free entry point on this device (once per device)
+  if (rdf_scratch_setup(c->dev) != hipSuccess) {
+    delete c;
+    return fail(nullptr, MD_ERR_HIP, "hipGetSymbolAddress of the static scratch array failed");
+  }
   c->stream = (hipStream_t)stream;
   if (!c->stream) {
     // graphs cannot be captured on the legacy default stream: use a private one
@@ -1449,6 +1459,33 @@ extern "C" int md_rdf(md_ctx *c, int32_t ta, int32_t tb, double r_max, int32_t n
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int b = 0; b < n_bins; ++b) hist[b] = (double)h[b];
   return rc;
+}
+
+// Allocation-free variant of md_rdf: the counts live in the library's static
+// device scratch array (per device, at the address looked up at creation),
+// cleared by a fill kernel, converted to doubles on the device and copied
+// straight into the caller's array. No device or host allocation; rows that
+// outgrew their capacity are not regrown here (that allocates).
+extern "C" int md_rdf_noalloc(md_ctx *c, int32_t ta, int32_t tb, double r_max, int32_t n_bins, double *hist) {
+  if (!c || !hist || n_bins <= 0 || !(r_max > 0.0) || ta < 0 || tb < 0 || ta >= c->nt || tb >= c->nt)
+    return fail(c, MD_ERR_ARG, "bad argument");
+  if (n_bins > MD_RDF_NOALLOC_MAX_BINS)
+    return fail(c, MD_ERR_ARG, "n_bins above the static scratch of md_rdf_noalloc (" +
+                                   std::to_string(MD_RDF_NOALLOC_MAX_BINS) + " bins)");
+  unsigned long long *sp = rdf_scratch_ptr(c->dev);
+  if (!sp) return fail(c, MD_ERR_HIP, "static scratch not set up on this device");
+  HIPCHK(c, hipMemcpyAsync(&c->ctl_host, c->V.ctl, sizeof(MDCtl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->ctl_host.ovf_short || c->ctl_host.ovf_long || c->ctl_host.ovf_queue)
+    return fail(c, MD_ERR_CAPACITY, "neighbour rows outgrew their capacity since the last synchronisation; "
+                                    "md_sync regrows them (it allocates) and must run first");
+  HIPCHK(c, launch_rdf_noalloc(c->V, Xcur(c), c->d_rep_off, ta, tb, r_max, n_bins, sp, c->stream));
+  HIPCHK(c, hipMemcpyAsync(hist, (const double *)(sp + MD_RDF_NOALLOC_MAX_BINS), sizeof(double) * n_bins,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->snap.valid = false;   // a synchronisation with no overflow pending: the state is good
+  c->journal.clear();
+  return report_flags(c);
 }
 
 extern "C" int md_get_cand_row(md_ctx *c, int32_t i, int32_t *j, int32_t *img, int32_t cap, int32_t *n,

@@ -12,6 +12,9 @@
 #define OP_PHASE_C1 4
 #define OP_PHASE_C2 5
 
+#define MD_RDF_NOALLOC_MAX_BINS 16384   // bins of md_rdf_noalloc (its static device scratch)
+#define MD_MAX_DEVICES 64
+
 hipError_t launch_local(const MDView &V, const MDProg &P, const double4 *Xs, double4 *Xd, hipStream_t s);
 hipError_t launch_chain(const MDView &V, const MDProg &P, const double4 *X, hipStream_t s);
 size_t chain_lds_bytes_host(int G, int S, int precision);   // dynamic LDS of one k_chain wave
@@ -32,3 +35,7 @@ hipError_t launch_count_pairs(const MDView &V, const double4 *X, int which, doub
 hipError_t launch_set_step(MDCtl *ctl, long long step, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
 hipError_t launch_theta_screen_err(double lo, double hi, int n, unsigned long long *out, hipStream_t s);
+hipError_t rdf_scratch_setup(int dev);            // once per device, that device current
+unsigned long long *rdf_scratch_ptr(int dev);     // device address of the static scratch on dev
+hipError_t launch_rdf_noalloc(const MDView &V, const double4 *X, const int *rep_off, int ta, int tb, double rmax,
+                              int nbins, unsigned long long *sp, hipStream_t s);

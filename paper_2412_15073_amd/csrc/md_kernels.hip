@@ -14,6 +14,8 @@
 //              they fit the same round).
 //  k_bonded    bonds and angles, per atom over its incident terms.
 //  observables: kinetic energy, pair energies, pair histograms.
+#include <mutex>
+
 #include "md_device.h"
 #include "md_internal.h"
 
@@ -796,6 +798,12 @@ __global__ void k_count_pairs(MDView V, const double4 *__restrict__ X, int which
   if (c) atomicAdd(out, c);
 }
 
+// counts to doubles (the histogram of the allocation-free entry point)
+__global__ void k_u64_to_double(const unsigned long long *__restrict__ a, double *__restrict__ b, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
 __global__ void k_set_step(MDCtl *ctl, long long step) { ctl->step_base = step; }
 
 // fill with a value (a kernel rather than a memset: safe under graph capture)
@@ -806,6 +814,55 @@ __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v) {
 
 // ------------------------------------------------------------- launchers
 #define CHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
+
+// ---------------------------------------- allocation-free pair histogram
+// Device scratch of md_rdf_noalloc: the counts (u64), then the histogram
+// converted to doubles, MD_RDF_NOALLOC_MAX_BINS of each (256 KiB in all).
+// Every device holds its own copy for the life of the process; all calls on
+// one device share it. In host code the name is only a stand-in: kernels get
+// the device address that hipGetSymbolAddress returned for that device.
+static __device__ __align__(256) unsigned long long scratch[2 * MD_RDF_NOALLOC_MAX_BINS];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MD_MAX_DEVICES] = {};
+}  // namespace
+
+// Once per device, with that device current (context creation): look up and
+// keep the device address of the scratch array.
+hipError_t rdf_scratch_setup(int dev) {
+  if (dev < 0 || dev >= MD_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[dev] = p;
+  return hipSuccess;
+}
+
+// device address of the scratch array on dev (nullptr before its setup)
+unsigned long long *rdf_scratch_ptr(int dev) {
+  if (dev < 0 || dev >= MD_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (unsigned long long *)g_scratch_ptr[dev];
+}
+
+// the pair histogram into the scratch array at sp (counts cleared first by a
+// fill kernel), then converted to doubles in its second half
+hipError_t launch_rdf_noalloc(const MDView &V, const double4 *X, const int *rep_off, int ta, int tb, double rmax,
+                              int nbins, unsigned long long *sp, hipStream_t s) {
+  if (!sp || nbins <= 0 || nbins > MD_RDF_NOALLOC_MAX_BINS) return hipErrorInvalidValue;
+  const int nbk = (nbins + 255) / 256;
+  hipLaunchKernelGGL(k_fill_u64, dim3(nbk), dim3(256), 0, s, sp, nbins, 0ull);
+  CHK(hipGetLastError());
+  hipLaunchKernelGGL(k_rdf, dim3((V.n + 255) / 256), dim3(256), 0, s, V, X, rep_off, ta, tb, rmax, nbins, sp);
+  CHK(hipGetLastError());
+  hipLaunchKernelGGL(k_u64_to_double, dim3(nbk), dim3(256), 0, s, sp, (double *)(sp + MD_RDF_NOALLOC_MAX_BINS),
+                     nbins);
+  return hipGetLastError();
+}
 
 hipError_t launch_local(const MDView &V, const MDProg &P, const double4 *Xs, double4 *Xd, hipStream_t s) {
   const int nb = (V.n + 255) / 256;

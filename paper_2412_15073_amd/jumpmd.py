@@ -109,7 +109,7 @@ class MDEvent(C.Structure):
 
 EXPORTS = ["md_create", "md_destroy", "md_last_error", "md_step_baoab", "md_step_jump",
            "md_step_jump_respa", "md_step_baoab_respa", "md_observables", "md_sync", "md_get_state",
-           "md_set_state", "md_get_accel", "md_get_atom_stats", "md_get_events", "md_rdf",
+           "md_set_state", "md_get_accel", "md_get_atom_stats", "md_get_events", "md_rdf", "md_rdf_noalloc",
            "md_get_cand_row", "md_get_row_counts", "md_run_phase", "md_profile", "md_profile_read",
            "md_counters", "md_theta_screen_error"]
 
@@ -154,6 +154,7 @@ def load():
     L.md_get_atom_stats.argtypes = [C.c_void_p, _lp, _lp, _lp, _up]
     L.md_get_events.argtypes = [C.c_void_p, C.POINTER(MDEvent), C.c_int64, _lp]
     L.md_rdf.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_int32, _dp]
+    L.md_rdf_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_int32, _dp]
     L.md_get_cand_row.argtypes = [C.c_void_p, C.c_int32, _ip, _ip, C.c_int32, _ip, _ip]
     L.md_get_row_counts.argtypes = [C.c_void_p, C.c_int32, _ip]
     L.md_run_phase.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double]
