@@ -54,6 +54,10 @@ extern "C" {
 #define MD_JUMP_BPS 1          /* bouncy-particle rate beta (v.F)_+ and reflection, Eqs. (tauxbps),(reflexion) */
 #define MD_JUMP_MRZ_CONST 2    /* rate/kernel of Eqs. (tauxsaut),(majvitesse), constant eps (Alg. 4) */
 #define MD_JUMP_MRZ_ADAPTIVE 3 /* same with eps(x) = eps0 |F_ij(x)| */
+#define MD_JUMP_BOUNCE 4       /* jump_coul only: the BOUNCE scheme of Sec. 3, B J A O A J B, with BPS
+                                  bounces on the Coulomb long part in the (J) step together with the LJ
+                                  ones (one chain over the whole long part, no acceleration between
+                                  jumps); the (C) steps reduce to plain kicks */
 
 /* arithmetic of the pair terms */
 #define MD_FP64 0
@@ -132,7 +136,7 @@ typedef struct {
   int32_t jump_lj;      /* MD_JUMP_NONE or MD_JUMP_BPS (J step, Alg. 5) */
   int32_t jump_coul;    /* MD_JUMP_NONE, MD_JUMP_MRZ_CONST or MD_JUMP_MRZ_ADAPTIVE (C step, Alg. 4),
                            or MD_JUMP_BPS: bounces of Sec. 3.2 in the C step (the eps -> infinity
-                           end of the MRZ family, Sec. 2.2) */
+                           end of the MRZ family, Sec. 2.2), or MD_JUMP_BOUNCE: bounces in the J step */
   double eps;           /* eps (constant) or eps0 (adaptive, 1/force units); unused with BPS */
   int32_t precision;    /* MD_FP64 or MD_FP32_MIXED */
   int32_t rebuild_every;/* 0: rebuild when max displacement > skin/2; k>0: every k steps */
@@ -150,6 +154,8 @@ typedef struct {
   double row_capacity;  /* initial row capacity as a multiple of the density estimate (0: 1.5);
                            rows regrow on demand, so this only trades memory for early regrows */
   int64_t event_capacity; /* accepted jumps the event log holds (log_events = 1); 0: 2^22 */
+  int32_t chain_order;  /* wave order of the jump chains: 0 or 1 by atom type (heaviest chains first),
+                           2 replica by replica (each by type); results do not depend on it */
 } md_params;
 
 typedef struct {
@@ -272,6 +278,38 @@ int md_profile_read(md_ctx *ctx, int32_t kid, double *total_ms, int64_t *launche
  * BAOAB; -1 if no force is current), and the jump proposals evaluated since
  * creation. Synchronises. */
 int md_counters(md_ctx *ctx, int64_t *pairs_last, int64_t *proposals_total);
+
+/* Autotuner of the launch and list settings that leave the method's law
+ * unchanged: lanes per atom of the jump chains (results do not depend on
+ * them), the Verlet skin and the ring count of the rate bounds (exact thinning
+ * for any valid bound, Sec. 2.4, Sec. 3.1.1: they change the random proposals
+ * drawn, not the law of the process), and HIP-graph replay. Each trial creates
+ * a context for `sys` with one setting (device memory from alloc, as
+ * md_create), runs untimed warm-up steps of `scheme` and times `steps` steps
+ * with HIP events on `stream`; a coordinate descent over lanes {auto, 1, 2, 4,
+ * 8, 16}, the wave order of the chains (several replicas: by type, by
+ * replica), skin x {0.6, 0.8, 1.2, 1.5, 2} (edges must stay above
+ * r_c + skin), rings x {1/2, 3/2, 2} (n_types * n_rings <= 32) and graph
+ * steps {0, 10, 20, 50}, then lanes again. *split_out / *params_out receive the caller's split
+ * and parameters with the fastest setting, *ms_out its ms per step; trials
+ * (may be NULL) receives up to cap of the settings timed, *n_trials their
+ * number. The result is cached per process (same system shape, split,
+ * parameters, scheme and steps: no trials). Synchronous. */
+#define MD_SCHEME_BAOAB 0
+#define MD_SCHEME_JUMP 1
+#define MD_SCHEME_JUMP_RESPA 2
+#define MD_SCHEME_BAOAB_RESPA 3
+typedef struct {
+  int32_t chain_lanes;
+  double skin;
+  int32_t n_rings;
+  int32_t graph_steps;
+  int32_t chain_order;
+  double ms_per_step;
+} md_tune_trial;
+int md_tune(const md_system *sys, const md_split *split, const md_params *params, void *stream,
+            const md_allocator *alloc, int32_t scheme, int32_t steps, md_split *split_out,
+            md_params *params_out, double *ms_out, md_tune_trial *trials, int32_t cap, int32_t *n_trials);
 
 /* Diagnostic of the float screen of Theta (Sec. 2.2, Theta(eta) = eta Phi(eta)
  * + phi(eta)) that the FP64 jump chains use to take most acceptance decisions

@@ -311,11 +311,14 @@ static void compute_bounds(orc_sim *s) {
     if (fabs(s->q[i]) > s->qmax[s->type[i]]) s->qmax[s->type[i]] = fabs(s->q[i]);
 }
 
-/* bound of candidates of atom i in segment sg (class = type of j, ring) */
+/* bound of candidates of atom i in segment sg (class = type of j, ring) for
+ * one jump component: 0 the LJ long part, 1 the Coulomb long part, 2 both
+ * (their sum bounds the gradient of the whole long part) */
 static double seg_bound(const orc_sim *s, int i, int sg, int coulomb) {
   int b = sg / s->nr, k = sg % s->nr, a = s->type[i];
   int idx = (a * s->nt + b) * s->nr + k;
-  double ell = coulomb ? (fabs(s->q[i]) * s->qmax[b]) * s->ell_cu[idx] : s->ell_lj[idx];
+  double lj = s->ell_lj[idx], cu = (fabs(s->q[i]) * s->qmax[b]) * s->ell_cu[idx];
+  double ell = coulomb == 2 ? lj + cu : (coulomb ? cu : lj);
   return s->bound_scale == 1.0 ? ell : ell * s->bound_scale;
 }
 
@@ -521,8 +524,20 @@ static double long_grad(const orc_sim *s, int i, const cand_t *cj, int coulomb, 
   double d[3], r = pair_vec_n(s, i, j, cj->n, d);
   int a = s->type[i], b = s->type[j];
   double U, dU, chi, dchi;
-  if (coulomb) dsf_terms(r, s->q[i] * s->q[j], s->ke_c, s->alpha, s->rc, &U, &dU);
-  else lj_terms(r, s->eps[a * s->nt + b], s->sig[a * s->nt + b], s->rc, &U, &dU);
+  if (coulomb == 1) {
+    dsf_terms(r, s->q[i] * s->q[j], s->ke_c, s->alpha, s->rc, &U, &dU);
+  } else if (coulomb == 0) {
+    lj_terms(r, s->eps[a * s->nt + b], s->sig[a * s->nt + b], s->rc, &U, &dU);
+  } else {   /* both parts: the long part of the whole pair potential */
+    double Uc, dUc;
+    lj_terms(r, s->eps[a * s->nt + b], s->sig[a * s->nt + b], s->rc, &U, &dU);
+    dsf_terms(r, s->q[i] * s->q[j], s->ke_c, s->alpha, s->rc, &Uc, &dUc);
+#if ORC_PLANT == 5   /* planted mistake: the BOUNCE gradient keeps the LJ part only */
+    Uc = 0.0; dUc = 0.0;
+#endif
+    U += Uc;
+    dU += dUc;
+  }
   switch_terms(r, s->rs, s->w, &chi, &dchi);
   double g = (1.0 - chi) * dU - dchi * U;
   for (int c = 0; c < 3; c++) F[c] = g * d[c] / r;
@@ -629,11 +644,14 @@ static int64_t pick_uniform(const segtab_t *T, double u, int *seg) {
  * Alg. 2. The bound beta |v_i| l_s per candidate is constant over the half
  * step (|v_i| is preserved), so proposal k happens at (E_0 + ... + E_k)/Lambda.
  * Proposal k uses Philox block (step, i, phase, k): u0 -> E_k, u2 -> candidate,
- * u3 -> acceptance (u1 unused). */
+ * u3 -> acceptance (u1 unused). In the BOUNCE scheme (Sec. 3: bounces on the
+ * Coulomb part as well, in (J)) one chain covers the long part of the whole
+ * pair potential: bounds l_LJ + l_Coulomb, F_ij the gradient of both. */
 static void jstep_atom(orc_sim *s, int i, int32_t phase, double h) {
   double *v = s->v + 3 * i;
+  const int comp = s->jc == ORC_JUMP_BOUNCE ? 2 : 0;
   segtab_t T;
-  seg_table(s, i, 0, &T);
+  seg_table(s, i, comp, &T);
   double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
   double Lam = s->beta * vn * T.W;
   if (!(Lam > 0.0) || !isfinite(Lam)) return;
@@ -648,7 +666,7 @@ static void jstep_atom(orc_sim *s, int i, int32_t phase, double h) {
     const cand_t *cj = &s->cand[s->cptr[i] + pos];
     int j = cj->j;
     double F[3];
-    double F2 = long_grad(s, i, cj, 0, F);
+    double F2 = long_grad(s, i, cj, comp, F);
     s->nprop[i]++;
     double vF = v[0] * F[0] + v[1] * F[1] + v[2] * F[2];
     double p = (vF > 0.0 ? vF : 0.0) / (vn * T.ell[sg]);
@@ -851,9 +869,12 @@ void orc_phase_c(orc_sim *s, int32_t phase, double h, int a_kind) { phase_c(s, p
 
 /* (C') or plain (B) depending on whether Coulomb jumps are on */
 static void c_or_b(orc_sim *s, int32_t phase, double h, int a_kind, int stream) {
-  if (s->jc != ORC_JUMP_NONE) phase_c(s, phase, h, a_kind, stream);
+  if (s->jc != ORC_JUMP_NONE && s->jc != ORC_JUMP_BOUNCE) phase_c(s, phase, h, a_kind, stream);
   else kick(s, h, 1, a_kind == 0);
 }
+
+/* whether the scheme has (J) steps: LJ bounces, or the BOUNCE scheme */
+static int has_j(const orc_sim *s) { return s->jlj == ORC_JUMP_BPS || s->jc == ORC_JUMP_BOUNCE; }
 
 /* ------------------------------------------------------------- schemes */
 /* BAOAB with full-range forces (Sec. 2.3 without J). */
@@ -884,13 +905,13 @@ int orc_step_jump(orc_sim *s, int64_t n) {
   ensure_forces(s, ORC_F_SHORT);
   for (int64_t it = 0; it < n; it++) {
     c_or_b(s, ORC_PH_C1, h, 0, STREAM_CONTINUE);
-    if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J1, h);
+    if (has_j(s)) orc_phase_j(s, ORC_PH_J1, h);
     drift(s, h);
     orc_phase_o(s, s->dt, 0);
     drift(s, h);
     maybe_rebuild(s);
     ensure_forces(s, ORC_F_SHORT);
-    if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J2, h);
+    if (has_j(s)) orc_phase_j(s, ORC_PH_J2, h);
     c_or_b(s, ORC_PH_C2, h, 0, STREAM_SAVE);
     s->step++;
   }
@@ -939,11 +960,11 @@ int orc_step_jump_respa(orc_sim *s, int64_t n_outer) {
   ensure_forces(s, ORC_F_SHORT);
   for (int64_t it = 0; it < n_outer; it++) {
     c_or_b(s, ORC_PH_C1, H, 1, STREAM_CONTINUE);
-    if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J1, H);
+    if (has_j(s)) orc_phase_j(s, ORC_PH_J1, H);
     respa_inner_steps(s, m, h);
     maybe_rebuild(s);
     ensure_forces(s, ORC_F_SHORT);
-    if (s->jlj == ORC_JUMP_BPS) orc_phase_j(s, ORC_PH_J2, H);
+    if (has_j(s)) orc_phase_j(s, ORC_PH_J2, H);
     c_or_b(s, ORC_PH_C2, H, 1, STREAM_SAVE);
     s->step++;
   }
@@ -1033,8 +1054,8 @@ orc_sim *orc_create(const orc_system *sy, const orc_split *sp, const orc_params 
   s->log_events = pa->log_events;
   if (s->jlj != ORC_JUMP_NONE && s->jlj != ORC_JUMP_BPS) FAIL("LJ jumps: NONE or BPS");
   if (s->jc != ORC_JUMP_NONE && s->jc != ORC_JUMP_BPS && s->jc != ORC_JUMP_MRZ_CONST &&
-      s->jc != ORC_JUMP_MRZ_ADAPTIVE)
-    FAIL("Coulomb jumps: NONE, BPS, MRZ_CONST or MRZ_ADAPTIVE");
+      s->jc != ORC_JUMP_MRZ_ADAPTIVE && s->jc != ORC_JUMP_BOUNCE)
+    FAIL("Coulomb jumps: NONE, BPS, MRZ_CONST, MRZ_ADAPTIVE or BOUNCE");
   if ((s->jc == ORC_JUMP_MRZ_CONST || s->jc == ORC_JUMP_MRZ_ADAPTIVE) && !(s->eps0 > 0.0))
     FAIL("eps must be positive");
   /* the LJ bound needs |U|, |U'| non-increasing beyond r_s - w */

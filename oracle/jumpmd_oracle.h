@@ -22,6 +22,8 @@ extern "C" {
 #define ORC_JUMP_BPS 1          /* Sec. 2.2 Eqs. (tauxbps),(reflexion); Sec. 3.2 */
 #define ORC_JUMP_MRZ_CONST 2    /* Sec. 2.2 Eqs. (tauxsaut),(majvitesse), constant eps; Alg. 4 */
 #define ORC_JUMP_MRZ_ADAPTIVE 3 /* same with eps(x) = eps0 |F_ij(x)| (Sec. 2.2, Sec. 3.1) */
+#define ORC_JUMP_BOUNCE 4       /* Coulomb: BPS bounces in the (J) step together with the LJ ones, no
+                                   acceleration between jumps (the BOUNCE scheme B J A O A J B, Sec. 3) */
 
 /* random-stream phase tags (counter word 2, low byte) */
 #define ORC_PH_O 1

@@ -243,7 +243,7 @@ static void add_J(ProgBuilder &b, int phase, double h, int64_t step) {
 // step before, whose words are (step - 1, OP_PHASE_C2))
 static void add_C_or_B(md_ctx *c, ProgBuilder &b, int phase, double h, int64_t step, int a_nb_only,
                        int stream = 0) {
-  if (c->par.jump_coul != MD_JUMP_NONE) {
+  if (c->par.jump_coul != MD_JUMP_NONE && c->par.jump_coul != MD_JUMP_BOUNCE) {
     MDOp o = op_base(OP_C, h);
     o.phase = phase;
     o.step = step;
@@ -424,8 +424,8 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
   if (p->jump_lj != MD_JUMP_NONE && p->jump_lj != MD_JUMP_BPS)
     return fail(nullptr, MD_ERR_ARG, "jump_lj must be NONE or BPS");
   if (p->jump_coul != MD_JUMP_NONE && p->jump_coul != MD_JUMP_BPS && p->jump_coul != MD_JUMP_MRZ_CONST &&
-      p->jump_coul != MD_JUMP_MRZ_ADAPTIVE)
-    return fail(nullptr, MD_ERR_ARG, "jump_coul must be NONE, BPS, MRZ_CONST or MRZ_ADAPTIVE");
+      p->jump_coul != MD_JUMP_MRZ_ADAPTIVE && p->jump_coul != MD_JUMP_BOUNCE)
+    return fail(nullptr, MD_ERR_ARG, "jump_coul must be NONE, BPS, MRZ_CONST, MRZ_ADAPTIVE or BOUNCE");
   if ((p->jump_coul == MD_JUMP_MRZ_CONST || p->jump_coul == MD_JUMP_MRZ_ADAPTIVE) && !(p->eps > 0.0))
     return fail(nullptr, MD_ERR_ARG, "eps must be > 0");
   if (p->precision != MD_FP64 && p->precision != MD_FP32_MIXED)
@@ -506,6 +506,7 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
   if (p->bound_scale < 0.0 || !std::isfinite(p->bound_scale)) return fail(nullptr, MD_ERR_ARG, "bound_scale must be >= 0");
   if (p->row_capacity < 0.0 || !std::isfinite(p->row_capacity)) return fail(nullptr, MD_ERR_ARG, "row_capacity must be >= 0");
   if (p->event_capacity < 0 || p->event_capacity > (1ll << 31)) return fail(nullptr, MD_ERR_ARG, "event_capacity must be in [0, 2^31]");
+  if (p->chain_order < 0 || p->chain_order > 2) return fail(nullptr, MD_ERR_ARG, "chain_order must be 0, 1 or 2");
   return MD_OK;
 }
 
@@ -568,9 +569,12 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   V.beta = 1.0 / p->kT; V.kT = p->kT;
   // bounces are the eps -> infinity end of the MRZ family: the floor term of
   // the C-step bound, sqrt(beta / (2 pi m)) / eps, is then exactly zero
-  V.eps0 = p->jump_coul == MD_JUMP_BPS ? INFINITY : p->eps;
+  V.eps0 = (p->jump_coul == MD_JUMP_BPS || p->jump_coul == MD_JUMP_BOUNCE) ? INFINITY : p->eps;
   V.jlj = p->jump_lj; V.jc = p->jump_coul; V.log_events = p->log_events; V.precision = p->precision;
   V.seed = p->seed;
+  auto rep_of_atom = [&](int i) {
+    return (int)(std::upper_bound(c->rep_off.begin(), c->rep_off.end(), i) - c->rep_off.begin()) - 1;
+  };
   // Jump-chain layout. G (lanes per atom), automatic: the most lanes per atom
   // whose waves still fit the device in one round (resident blocks per CU
   // from the kernel's registers and LDS); when none does, 2 (on an ensemble
@@ -614,16 +618,41 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
     std::vector<int> torder(nt);
     for (int t = 0; t < nt; ++t) torder[t] = t;
     std::stable_sort(torder.begin(), torder.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-    struct Chunk { int t, beg, len; };
-    std::vector<Chunk> waves, part;
-    for (int t : torder) {
-      const int m = (int)by_type[t].size();
-      for (int w = 0; w * apw < m; ++w) {
-        Chunk ch{t, w * apw, std::min(apw, m - w * apw)};
-        (ch.len == apw ? waves : part).push_back(ch);
+    // Type-major order (the default): all waves of the heaviest type, then
+    // the next type, partial waves last. Replica-major order: replica by
+    // replica, each type-pure and heaviest type first, so that the resident
+    // waves cover a run of consecutive replicas and gather from fewer
+    // candidate rows. On the 256-replica water ensemble it ran 2 % slower
+    // (5.26 against 5.14 ms per step): the load balance of heaviest-first
+    // matters more there; the autotuner tries both.
+    struct Chunk { const std::vector<int> *atoms; int beg, len; };
+    std::vector<Chunk> waves;
+    std::vector<std::vector<int>> by_rt;
+    auto type_major = [&]() {
+      std::vector<Chunk> part;
+      waves.clear();
+      for (int t : torder) {
+        const int m = (int)by_type[t].size();
+        for (int w = 0; w * apw < m; ++w) {
+          Chunk ch{&by_type[t], w * apw, std::min(apw, m - w * apw)};
+          (ch.len == apw ? waves : part).push_back(ch);
+        }
       }
+      waves.insert(waves.end(), part.begin(), part.end());
+    };
+    type_major();
+    const int order = p->chain_order != 0 ? p->chain_order : 1;
+    if (order == 2) {
+      by_rt.assign((size_t)nrep * nt, {});
+      for (int i = 0; i < n; ++i) by_rt[(size_t)rep_of_atom(i) * nt + s->type[i]].push_back(i);
+      waves.clear();
+      for (int r = 0; r < nrep; ++r)
+        for (int t : torder) {
+          const std::vector<int> &v = by_rt[(size_t)r * nt + t];
+          for (int w = 0; w * apw < (int)v.size(); ++w) waves.push_back(Chunk{&v, w * apw, std::min(apw, (int)v.size() - w * apw)});
+        }
     }
-    waves.insert(waves.end(), part.begin(), part.end());
+    V.chain_order = order;
     const long long nw = (long long)waves.size();
 
     // Block size. When every wave is resident at once, waves are packed into
@@ -645,7 +674,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
     for (long long q = 0; q < nw; ++q) {
       const long long wv = (q % nb) * bw + q / nb;
       const Chunk &ch = waves[(size_t)q];
-      for (int k = 0; k < ch.len; ++k) chain_perm[(size_t)(wv * apw + k)] = by_type[ch.t][ch.beg + k];
+      for (int k = 0; k < ch.len; ++k) chain_perm[(size_t)(wv * apw + k)] = (*ch.atoms)[ch.beg + k];
     }
     V.chain_block_waves = bw;
     V.chain_groups = (int)chain_perm.size();
@@ -949,7 +978,8 @@ static int jump_plain(md_ctx *c, int64_t nsteps) {
   int rc = ensure_forces(c, MODE_JUMP);
   if (rc) return rc;
   const double h = 0.5 * c->par.dt;
-  const bool lj = c->par.jump_lj == MD_JUMP_BPS;
+  // (J) steps: LJ bounces, or the BOUNCE scheme's bounces on the whole long part
+  const bool lj = c->par.jump_lj == MD_JUMP_BPS || c->par.jump_coul == MD_JUMP_BOUNCE;
   for (int64_t it = 0; it <= nsteps; ++it) {
     ProgBuilder b;
     // The opening C' of a step continues the proposal stream of the closing
@@ -1028,7 +1058,7 @@ static int respa(md_ctx *c, int64_t n_outer, bool jump) {
   if (rc) return rc;
   const int m = c->par.respa_inner;
   const double h = 0.5 * c->par.dt, H = 0.5 * c->par.dt * m;
-  const bool lj = jump && c->par.jump_lj == MD_JUMP_BPS;
+  const bool lj = jump && (c->par.jump_lj == MD_JUMP_BPS || c->par.jump_coul == MD_JUMP_BOUNCE);
   for (int64_t it = 0; it <= n_outer; ++it) {
     // end of the previous outer step: closing inner kick, then J' C' (or the
     // outer non-bonded kick of BAOAB-RESPA)
@@ -1536,7 +1566,8 @@ static int run_phase(md_ctx *c, int which, int phase, double h) {
   if (rc) return rc;
   ProgBuilder b;
   if (which == 'C') {
-    if (c->par.jump_coul == MD_JUMP_NONE) return fail(c, MD_ERR_ARG, "no Coulomb jumps configured");
+    if (c->par.jump_coul == MD_JUMP_NONE || c->par.jump_coul == MD_JUMP_BOUNCE)
+      return fail(c, MD_ERR_ARG, "no C-step jumps configured");
     MDOp o = op_base(OP_C, h); o.phase = phase; o.step = c->step; o.flags = 0; b.add(o);
   } else if (which == 'J') {
     add_J(b, phase, h, c->step);
@@ -1608,5 +1639,183 @@ extern "C" int md_theta_screen_error(double eta_lo, double eta_hi, int32_t n, do
   double v;
   std::memcpy(&v, &h, sizeof(v));
   *max_rel_err = v;
+  return MD_OK;
+}
+
+// ------------------------------------------------------------- autotuner
+// Launch and list settings are searched by timing: each trial creates a
+// context with one setting from the caller's state, runs `warm` untimed steps
+// (rows built, graphs captured) and times `steps` steps with HIP events on
+// the context's stream. Coordinate descent over chain lanes (jump schemes),
+// list skin, ring count (jump schemes) and graph replay (single-step schemes),
+// then lanes once more at the chosen skin and rings. Results are cached per
+// process by a fingerprint of the system's shape and the run settings.
+namespace {
+struct TuneEntry { md_split sp; md_params p; double ms; std::vector<md_tune_trial> trials; };
+std::vector<std::pair<uint64_t, TuneEntry>> g_tune_cache;
+
+uint64_t fnv_mix(uint64_t h, const void *p, size_t n) {
+  const unsigned char *b = (const unsigned char *)p;
+  for (size_t q = 0; q < n; ++q) { h ^= b[q]; h *= 0x100000001b3ull; }
+  return h;
+}
+
+uint64_t tune_key(const md_system *s, const md_split *sp, const md_params *p, int scheme, int steps) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  h = fnv_mix(h, &s->n_atoms, sizeof(int32_t));
+  h = fnv_mix(h, &s->n_replicas, sizeof(int32_t));
+  h = fnv_mix(h, &s->n_types, sizeof(int32_t));
+  h = fnv_mix(h, s->box, sizeof(double) * 3 * (size_t)s->n_replicas);
+  if (s->replica_offset) h = fnv_mix(h, s->replica_offset, sizeof(int32_t) * (size_t)(s->n_replicas + 1));
+  h = fnv_mix(h, sp, sizeof(md_split));
+  const double pk[4] = {p->dt, p->gamma, p->kT, p->eps};
+  const int32_t pi[7] = {p->jump_lj, p->jump_coul, p->precision, p->respa_inner, p->rebuild_every, scheme,
+                          p->chain_order};
+  h = fnv_mix(h, pk, sizeof(pk));
+  h = fnv_mix(h, pi, sizeof(pi));
+  return fnv_mix(h, &steps, sizeof(steps));
+}
+}  // namespace
+
+static int run_scheme(md_ctx *c, int scheme, int64_t n) {
+  switch (scheme) {
+    case MD_SCHEME_BAOAB: return md_step_baoab(c, n);
+    case MD_SCHEME_JUMP: return md_step_jump(c, n);
+    case MD_SCHEME_JUMP_RESPA: return md_step_jump_respa(c, n);
+    case MD_SCHEME_BAOAB_RESPA: return md_step_baoab_respa(c, n);
+  }
+  return fail(c, MD_ERR_ARG, "unknown scheme");
+}
+
+// one trial: ms per step of `scheme` with this split and these parameters
+static int tune_trial(const md_system *s, const md_split &sp, const md_params &p, void *stream,
+                      const md_allocator *alloc, int scheme, int warm, int steps, double *ms) {
+  md_ctx *c = nullptr;
+  int rc = md_create(s, &sp, &p, stream, alloc, &c);
+  if (rc) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(c, MD_ERR_HIP, "hipEventCreate");
+  if (!rc) rc = run_scheme(c, scheme, warm);
+  if (!rc) rc = md_sync(c);
+  if (!rc && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(c, MD_ERR_HIP, "hipEventRecord");
+  if (!rc) rc = run_scheme(c, scheme, steps);
+  if (!rc && hipEventRecord(e1, c->stream) != hipSuccess) rc = fail(c, MD_ERR_HIP, "hipEventRecord");
+  if (!rc) rc = md_sync(c);
+  float f = 0.0f;
+  if (!rc && hipEventElapsedTime(&f, e0, e1) != hipSuccess) rc = fail(c, MD_ERR_HIP, "hipEventElapsedTime");
+  if (!rc) *ms = (double)f / steps;
+  if (rc) g_create_error = c->err;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  md_destroy(c);
+  return rc;
+}
+
+extern "C" int md_tune(const md_system *s, const md_split *sp, const md_params *p, void *stream,
+                       const md_allocator *alloc, int32_t scheme, int32_t steps, md_split *sp_out,
+                       md_params *p_out, double *ms_out, md_tune_trial *trials, int32_t cap, int32_t *n_trials) {
+  if (!s || !sp || !p || !sp_out || !p_out || steps < 1 || cap < 0 ||
+      scheme < MD_SCHEME_BAOAB || scheme > MD_SCHEME_BAOAB_RESPA)
+    return fail(nullptr, MD_ERR_ARG, "md_tune: bad argument");
+  int rc = validate(s, sp, p);
+  if (rc) return rc;
+  const uint64_t key = tune_key(s, sp, p, scheme, steps);
+  const TuneEntry *hit = nullptr;
+  for (const auto &e : g_tune_cache)
+    if (e.first == key) hit = &e.second;
+  TuneEntry res;
+  if (hit) {
+    res = *hit;
+  } else {
+    const bool jumps = scheme == MD_SCHEME_JUMP || scheme == MD_SCHEME_JUMP_RESPA;
+    const bool graphs = (scheme == MD_SCHEME_JUMP || scheme == MD_SCHEME_BAOAB) && p->rebuild_every == 0;
+    const int warm = std::max(10, steps / 4);
+    double Lmin = s->box[0];
+    for (int q = 0; q < 3 * s->n_replicas; ++q) Lmin = std::min(Lmin, s->box[q]);
+    // ring_width spans the candidate distances [r_s - w - skin, r_c + skin)
+    auto with = [&](double skin, int rings) {
+      md_split t = *sp;
+      t.skin = skin;
+      t.n_rings = rings;
+      t.ring_width = rings > 1 ? ((t.r_c + skin) - (t.r_s - t.switch_width - skin)) / rings : 0.0;
+      return t;
+    };
+    md_split best_sp = *sp;
+    md_params best_p = *p;
+    best_p.graph_steps = graphs ? p->graph_steps : 0;
+    double best = INFINITY;
+    auto trial = [&](const md_split &t, const md_params &q) -> bool {
+      if (validate(s, &t, &q) != MD_OK || (q.graph_steps & 1)) return false;
+      double ms = 0.0;
+      if (tune_trial(s, t, q, stream, alloc, scheme, warm, steps, &ms) != MD_OK) return false;
+      res.trials.push_back(md_tune_trial{q.chain_lanes, t.skin, t.n_rings, q.graph_steps, q.chain_order, ms});
+      if (ms < best) { best = ms; best_sp = t; best_p = q; return true; }
+      return false;
+    };
+    auto tune_lanes = [&]() {
+      if (!jumps) return;
+      const md_split t = best_sp;
+      const md_params base = best_p;
+      for (int g : {0, 1, 2, 4, 8, 16}) {
+        if (g == base.chain_lanes) continue;
+        md_params q = base;
+        q.chain_lanes = g;
+        trial(t, q);
+      }
+    };
+    trial(best_sp, best_p);   // the caller's setting
+    if (!std::isfinite(best)) return fail(nullptr, MD_ERR_ARG, "md_tune: the caller's setting does not run: " +
+                                                                  g_create_error);
+    tune_lanes();
+    if (jumps && s->n_replicas > 1) {
+      const md_split t0 = best_sp;
+      const md_params base = best_p;
+      for (int o : {1, 2}) {
+        if (o == base.chain_order) continue;
+        md_params q = base;
+        q.chain_order = o;
+        trial(t0, q);
+      }
+    }
+    {
+      const md_split t0 = best_sp;
+      const md_params q = best_p;
+      for (double f : {0.6, 0.8, 1.2, 1.5, 2.0}) {
+        const double skin = sp->skin * f;
+        if (!(skin > 0.0) || !(Lmin > sp->r_c + skin)) continue;
+        trial(with(skin, t0.n_rings), q);
+      }
+    }
+    if (jumps) {
+      const md_split t0 = best_sp;
+      const md_params q = best_p;
+      const int nr0 = std::max(1, sp->n_rings);
+      for (int rings : {nr0 / 2, (3 * nr0) / 2, 2 * nr0}) {
+        if (rings < 1 || rings == t0.n_rings || s->n_types * rings > 32) continue;
+        trial(with(t0.skin, rings), q);
+      }
+    }
+    if (graphs) {
+      const md_split t0 = best_sp;
+      const md_params base = best_p;
+      for (int gs : {0, 10, 20, 50}) {
+        if (gs == base.graph_steps) continue;
+        md_params q = base;
+        q.graph_steps = gs;
+        trial(t0, q);
+      }
+    }
+    if (best_sp.skin != sp->skin || best_sp.n_rings != sp->n_rings) tune_lanes();
+    res.sp = best_sp;
+    res.p = best_p;
+    res.ms = best;
+    g_tune_cache.emplace_back(key, res);
+  }
+  *sp_out = res.sp;
+  *p_out = res.p;
+  if (ms_out) *ms_out = res.ms;
+  if (n_trials) *n_trials = (int32_t)res.trials.size();
+  if (trials)
+    for (int32_t q = 0; q < std::min<int32_t>(cap, (int32_t)res.trials.size()); ++q) trials[q] = res.trials[q];
   return MD_OK;
 }

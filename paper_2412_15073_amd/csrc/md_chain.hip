@@ -10,11 +10,14 @@
 
 // ------------------------------------------------------------- helpers
 // bound of segment sg = (type b, ring k) for an atom of type a; the table
-// index (a * nt + b) * nr + k equals a * S + sg
+// index (a * nt + b) * nr + k equals a * S + sg. Component coul: 0 the LJ
+// long part, 1 the Coulomb long part, 2 both (the BOUNCE chain: their sum
+// bounds the gradient of the whole long part)
 __device__ __forceinline__ double seg_ell(const MDView &V, int a, int sg, int coul, double absq) {
   const int idx = a * V.S + sg;
-  if (!coul) return V.ell_lj[idx];
-  return (absq * V.qseg[sg]) * V.ell_cu[idx];
+  if (coul == 0) return V.ell_lj[idx];
+  const double cu = (absq * V.qseg[sg]) * V.ell_cu[idx];
+  return coul == 1 ? cu : V.ell_lj[idx] + cu;
 }
 
 // long-range gradient in FP32 (mixed-precision path) for the candidate image
@@ -31,13 +34,18 @@ __device__ __forceinline__ double long_grad_f(const MDView &V, double4 xi, doubl
   const float ir = 1.0f / r;
   float U = 0.0f, dU = 0.0f;
   if (r < (float)V.rc) {
-    if (coul) {
-      const float qq = (float)(xi.w * xj.w);
-      if (qq != 0.0f) dsf_pair_f(r, ir, (float)V.ke * qq, V, U, dU);
-    } else {
+    if (coul != 1) {
       const int ab = a * V.nt + b;
       const float c12 = (float)V.c12[ab], c6 = (float)V.c6[ab];
       if (c12 != 0.0f || c6 != 0.0f) lj_pair_f(ir, c12, c6, (float)V.ljshift[ab], U, dU);
+    }
+    if (coul != 0) {
+      const float qq = (float)(xi.w * xj.w);
+      if (qq != 0.0f) {
+        float Uc, dUc;
+        dsf_pair_f(r, ir, (float)V.ke * qq, V, Uc, dUc);
+        U += Uc; dU += dUc;
+      }
     }
   }
   float chi, dchi;
@@ -47,7 +55,8 @@ __device__ __forceinline__ double long_grad_f(const MDView &V, double4 xi, doubl
   return Fx * Fx + Fy * Fy + Fz * Fz;
 }
 
-// long-range gradient F_ij = grad_i (1 - chi) U_ij of one component (Sec. 3.1, 3.2)
+// long-range gradient F_ij = grad_i (1 - chi) U_ij of component coul (0 LJ,
+// 1 Coulomb, 2 both; Sec. 3.1, 3.2)
 __device__ __forceinline__ double long_grad_d(const MDView &V, double4 xi, double4 xj, int a, int b,
                                             int coul, const double *L, const double *iL, bool img, int e,
                                             double &Fx, double &Fy, double &Fz) {
@@ -58,13 +67,18 @@ __device__ __forceinline__ double long_grad_d(const MDView &V, double4 xi, doubl
   const double ir = 1.0 / r;
   double U = 0.0, dU = 0.0;
   if (r < V.rc) {
-    if (coul) {
-      double qq = xi.w * xj.w;
-      if (qq != 0.0) dsf_pair(r, ir, V.ke * qq, V, U, dU);
-    } else {
+    if (coul != 1) {
       int ab = a * V.nt + b;
       double c12 = V.c12[ab], c6 = V.c6[ab];
       if (c12 != 0.0 || c6 != 0.0) lj_pair(ir, c12, c6, V.ljshift[ab], U, dU);
+    }
+    if (coul != 0) {
+      double qq = xi.w * xj.w;
+      if (qq != 0.0) {
+        double Uc, dUc;
+        dsf_pair(r, ir, V.ke * qq, V, Uc, dUc);
+        U += Uc; dU += dUc;
+      }
     }
   }
   double chi, dchi;
@@ -360,7 +374,9 @@ __device__ __forceinline__ int ring_add(int s, int d, int M) {
 // loop; groups that have finished stay masked until the wave is done).
 //  J (BPS jumps of the LJ long part, Alg. 5 in the exponential-clock form of
 //    Alg. 2): bound beta |v| l_s per candidate, constant over the op since a
-//    reflection keeps |v|; proposal k at (E_0 + ... + E_k)/Lambda.
+//    reflection keeps |v|; proposal k at (E_0 + ... + E_k)/Lambda. In the
+//    BOUNCE scheme (Sec. 3) the same chain covers the long part of the whole
+//    pair potential: bounds l_LJ + l_Coulomb, F_ij the gradient of both.
 //  C (Sec. 2.3 step (C), Alg. 1, Alg. 4; eps = eps0 |F| when adaptive):
 //    constant acceleration a between jumps plus MRZ jumps of the Coulomb long
 //    part; the bound is re-evaluated after each accepted jump (Sec. 2.4): from
@@ -392,14 +408,19 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   // the accepted proposals (about half) pay for it, in the window.
   constexpr bool kZPre = G >= 4;
   const bool isC = op.kind == OP_C;
+  // jump component: C the Coulomb long part; J the LJ long part, or both in
+  // the BOUNCE scheme
+  const int comp = isC ? 1 : (V.jc == MD_JUMP_BOUNCE ? 2 : 0);
   const int a = V.type[i];
   const bool cont = op.stream == MD_STREAM_CONTINUE;
   if (!(cont && rp.saved)) {
     // the table of the saved op is the one this op needs (same kind, positions)
-    const double absq = isC ? fabs(xi.w) : 0.0;
-    const bool active = V.type_active[2 * a + (isC ? 1 : 0)] && (!isC || absq > 0.0);
-    if (__any(active)) T.template build<G>(V, i, a, isC ? 1 : 0, absq, r);   // a whole wave or none builds
-    else T.set_empty(a, isC ? 1 : 0, absq);
+    const double absq = comp != 0 ? fabs(xi.w) : 0.0;
+    const bool act_lj = comp != 1 && V.type_active[2 * a];
+    const bool act_c = comp != 0 && V.type_active[2 * a + 1] && absq > 0.0;
+    const bool active = act_lj || act_c;
+    if (__any(active)) T.template build<G>(V, i, a, comp, absq, r);   // a whole wave or none builds
+    else T.set_empty(a, comp, absq);
     rp.w0 = rp.computed = cont ? V.knext[i] : 0;
     rp.ws = rp.cs = 0;
   }
@@ -416,6 +437,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   const R aa = ax * ax + ay * ay + az * az;
   const uint64_t rep = (uint64_t)V.rep[i];
   const int li = V.loc[i];
+  const int i0 = i - li;   // first atom of the replica
   const R h = (R)op.h;
   const R vn = sqrt((R)vx * (R)vx + (R)vy * (R)vy + (R)vz * (R)vz);   // J: |v| for the whole op
   // per-op constants of the MRZ rate and kernel (Sec. 2.4)
@@ -481,15 +503,14 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         const int eb = row[pb], ef = row[pf];
         const int jb = row_j(eb), jf = row_j(ef);
         const double4 xb = X[jb], xf = X[jf];
-        const int lb = V.loc[jb], lf = V.loc[jf];
+        const int lb = jb - i0, lf = jf - i0;   // partners lie in the atom's own replica
         u32x4 zw;
         if (mrz) zw = draw4w(V.seed, rep, op.rstep, li, (uint64_t)(uint32_t)op.rphase | (1ull << 24), k);
         ring[RF_E * M + sl] = (R)(-log(u01(uw.w[0])));
         pwords[sl] = make_uint2(uw.w[1], uw.w[3]);
         double Fx, Fy, Fz;
         // segment sg = b * nr + ring: the partner's type without a load
-        long_grad<PREC>(V, xi, xb, a, (int)(((double)sb + 0.5) * inv_nr), isC ? 1 : 0, L, iL, img, eb, Fx, Fy,
-                        Fz);
+        long_grad<PREC>(V, xi, xb, a, (int)(((double)sb + 0.5) * inv_nr), comp, L, iL, img, eb, Fx, Fy, Fz);
         ring[RF_BX * M + sl] = (R)Fx; ring[RF_BY * M + sl] = (R)Fy; ring[RF_BZ * M + sl] = (R)Fz;
         ring[RF_BL * M + sl] = (R)ellb;
         if (adaptive) {

@@ -162,6 +162,7 @@ struct MDView {
   int chain_lanes;       // lanes cooperating on one atom's jump chain (1, 2, 4, 8, 16)
   int chain_block_waves; // waves per k_chain block
   int chain_groups;      // length of chain_perm (>= n)
+  int chain_order;       // wave order of chain_perm: 1 type-major, 2 replica-major
   const int *chain_perm; // [chain_groups] atom whose chain group g runs, -1: idle group
   uint64_t seed;
 };

@@ -385,8 +385,8 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
   const int nqq = min(nq, pq);
   wave_lds_sync();
   // Pass 2: exact FP64 decisions for the queued atoms. In a replica with an
-  // edge below 2 (r_c + skin) every image of j next to the nearest one (along
-  // the short edges) is tested too, and keys carry the image: segment << 27
+  // edge below 2 (r_c + skin) the images of j next to the nearest one (along
+  // the short edges) are tested too, and keys carry the image: segment << 27
   // | local j << 14 | image number << 9 | image code (the lattice vector mod 8
   // of the row entry); the image number (s_x+1) + 3 (s_y+1) + 9 (s_z+1) of
   // the offset s from the nearest image orders the images of one j.
@@ -407,10 +407,18 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
       for (int e = x0 + 4; ok && e < x1; ++e) ok = (V.xj[e] != j);
     const double d0x = xi.x - xj.x, d0y = xi.y - xj.y, d0z = xi.z - xj.z;
     const double mx = rint(d0x * iL[0]), my = rint(d0y * iL[1]), mz = rint(d0z * iL[2]);
-    for (int si = img ? 0 : 13; si < (img ? 27 : 14); ++si) {   // image offsets, uniform over the wave
-      const int sx = si % 3 - 1, sy = (si / 3) % 3 - 1, sz = si / 9 - 1;
-      if ((sx && !(L[0] < 2.0 * V.rout)) || (sy && !(L[1] < 2.0 * V.rout)) || (sz && !(L[2] < 2.0 * V.rout)))
+    // Along an edge below 2 (r_c + skin) the next image on the side the
+    // nearest one leans to can also be within reach; the one on the other
+    // side is at least an edge away. Combination cb picks, per edge, the
+    // nearest image (bit clear) or that neighbour (bit set); uniform over the wave.
+    const int ax = d0x - L[0] * mx > 0.0 ? 1 : -1, ay = d0y - L[1] * my > 0.0 ? 1 : -1;
+    const int az = d0z - L[2] * mz > 0.0 ? 1 : -1;
+    for (int cb = 0; cb < (img ? 8 : 1); ++cb) {
+      if (((cb & 1) && !(L[0] < 2.0 * V.rout)) || ((cb & 2) && !(L[1] < 2.0 * V.rout)) ||
+          ((cb & 4) && !(L[2] < 2.0 * V.rout)))
         continue;
+      const int sx = (cb & 1) ? ax : 0, sy = (cb & 2) ? ay : 0, sz = (cb & 4) ? az : 0;
+      const int si = (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1);
       bool bs = false, bk = false;
       unsigned key = 0, skey = 0;
       if (ok) {

@@ -49,7 +49,7 @@ class MDParams(C.Structure):
                 ("precision", C.c_int32), ("rebuild_every", C.c_int32), ("respa_inner", C.c_int32),
                 ("log_events", C.c_int32), ("strict_bounds", C.c_int32), ("chain_lanes", C.c_int32),
                 ("graph_steps", C.c_int32), ("bound_scale", C.c_double), ("row_capacity", C.c_double),
-                ("event_capacity", C.c_int64)]
+                ("event_capacity", C.c_int64), ("chain_order", C.c_int32)]
 
 
 class MDObs(C.Structure):
@@ -102,6 +102,11 @@ class TorchAllocator:
         self.struct = MDAllocator(None, self._fns[0], self._fns[1])
 
 
+class MDTuneTrial(C.Structure):
+    _fields_ = [("chain_lanes", C.c_int32), ("skin", C.c_double), ("n_rings", C.c_int32),
+                ("graph_steps", C.c_int32), ("chain_order", C.c_int32), ("ms_per_step", C.c_double)]
+
+
 class MDEvent(C.Structure):
     _fields_ = [("step", C.c_int64), ("phase", C.c_int32), ("atom", C.c_int32),
                 ("partner", C.c_int32), ("proposal", C.c_int32)]
@@ -111,7 +116,7 @@ EXPORTS = ["md_create", "md_destroy", "md_last_error", "md_step_baoab", "md_step
            "md_step_jump_respa", "md_step_baoab_respa", "md_observables", "md_sync", "md_get_state",
            "md_set_state", "md_get_accel", "md_get_atom_stats", "md_get_events", "md_rdf", "md_rdf_noalloc",
            "md_get_cand_row", "md_get_row_counts", "md_run_phase", "md_profile", "md_profile_read",
-           "md_counters", "md_theta_screen_error"]
+           "md_counters", "md_theta_screen_error", "md_tune"]
 
 _lib = None
 
@@ -153,6 +158,9 @@ def load():
     L.md_get_accel.argtypes = [C.c_void_p, C.c_int32, _dp]
     L.md_get_atom_stats.argtypes = [C.c_void_p, _lp, _lp, _lp, _up]
     L.md_get_events.argtypes = [C.c_void_p, C.POINTER(MDEvent), C.c_int64, _lp]
+    L.md_tune.argtypes = [C.POINTER(MDSystem), C.POINTER(MDSplit), C.POINTER(MDParams), C.c_void_p,
+                          C.POINTER(MDAllocator), C.c_int32, C.c_int32, C.POINTER(MDSplit), C.POINTER(MDParams),
+                          C.POINTER(C.c_double), C.POINTER(MDTuneTrial), C.c_int32, C.POINTER(C.c_int32)]
     L.md_rdf.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_int32, _dp]
     L.md_rdf_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_int32, _dp]
     L.md_get_cand_row.argtypes = [C.c_void_p, C.c_int32, _ip, _ip, C.c_int32, _ip, _ip]
@@ -230,6 +238,80 @@ def _current_stream():
     return None
 
 
+def _marshal_system(system):
+    """MDSystem of a systems.System or systems.Batch, with the arrays it points
+    into (kept alive by the caller)."""
+    systems = list(system.systems) if hasattr(system, "systems") else [system]
+    s0 = systems[0]
+    a = _concat(systems)
+    a["eps"] = np.ascontiguousarray(s0.lj_eps, dtype=np.float64)
+    a["sig"] = np.ascontiguousarray(s0.lj_sigma, dtype=np.float64)
+    sy = MDSystem()
+    sy.n_atoms, sy.n_types, sy.n_replicas = int(a["offsets"][-1]), s0.n_types, len(systems)
+    sy.pos, sy.vel = _ptr(a["pos"], _dp), _ptr(a["vel"], _dp)
+    sy.mass, sy.charge, sy.type = _ptr(a["mass"], _dp), _ptr(a["charge"], _dp), _ptr(a["type"], _ip)
+    sy.lj_eps, sy.lj_sigma = _ptr(a["eps"], _dp), _ptr(a["sig"], _dp)
+    sy.box, sy.replica_offset = _ptr(a["box"], _dp), _ptr(a["offsets"], _ip)
+    sy.n_bonds, sy.bond_ij = len(a["bond_k"]), _ptr(a["bond_ij"], _ip)
+    sy.bond_k, sy.bond_r0 = _ptr(a["bond_k"], _dp), _ptr(a["bond_r0"], _dp)
+    sy.n_angles, sy.angle_ijk = len(a["angle_k"]), _ptr(a["angle_ijk"], _ip)
+    sy.angle_k, sy.angle_t0 = _ptr(a["angle_k"], _dp), _ptr(a["angle_t0"], _dp)
+    sy.excl_ptr, sy.excl_j = _ptr(a["excl_ptr"], _ip), _ptr(a["excl_j"], _ip)
+    sy.coulomb_k, sy.accel_factor, sy.kB = s0.coulomb_k, s0.accel_factor, s0.kB
+    return sy, a
+
+
+def _marshal_split(split):
+    return MDSplit(split.r_s, split.r_c, split.switch_width, split.skin, split.coulomb_alpha,
+                   split.n_rings, split.ring_width)
+
+
+def _marshal_params(params):
+    return MDParams(params.dt, params.gamma, params.kT, params.seed, params.jump_lj, params.jump_coul,
+                    params.eps, params.precision, params.rebuild_every, params.respa_inner,
+                    params.log_events, params.strict_bounds, getattr(params, "chain_lanes", 0),
+                    getattr(params, "graph_steps", 0), getattr(params, "bound_scale", 0.0),
+                    getattr(params, "row_capacity", 0.0), getattr(params, "event_capacity", 0),
+                    getattr(params, "chain_order", 0))
+
+
+def _allocator(allocator):
+    if allocator == "torch":
+        return TorchAllocator() if _gpu_visible() else None
+    return allocator
+
+
+SCHEMES = {"baoab": 0, "jump": 1, "jump_respa": 2, "baoab_respa": 3}
+
+
+def tune(system, split, params, scheme="jump", steps=50, stream=None, allocator="torch"):
+    """md_tune: the fastest lanes / skin / rings / graph setting for this
+    system and scheme. Returns (split, params, ms_per_step, trials): copies of
+    the inputs with the chosen setting, and every setting timed."""
+    import copy
+    L = load()
+    sy, keep = _marshal_system(system)
+    sp, pa = _marshal_split(split), _marshal_params(params)
+    alloc = _allocator(allocator)
+    sp_o, pa_o, ms = MDSplit(), MDParams(), C.c_double(0.0)
+    cap = 256
+    tr = (MDTuneTrial * cap)()
+    nt = C.c_int32(0)
+    st = stream if stream is not None else _current_stream()
+    rc = L.md_tune(C.byref(sy), C.byref(sp), C.byref(pa), st, C.byref(alloc.struct) if alloc is not None else None,
+                   SCHEMES[scheme], steps, C.byref(sp_o), C.byref(pa_o), C.byref(ms), tr, cap, C.byref(nt))
+    del keep
+    if rc != MD_OK:
+        raise MDError(rc, L.md_last_error(None).decode())
+    split2, params2 = copy.copy(split), copy.copy(params)
+    split2.skin, split2.n_rings, split2.ring_width = sp_o.skin, sp_o.n_rings, sp_o.ring_width
+    params2.chain_lanes, params2.graph_steps = pa_o.chain_lanes, pa_o.graph_steps
+    params2.chain_order = pa_o.chain_order
+    trials = [{"chain_lanes": t.chain_lanes, "skin": t.skin, "n_rings": t.n_rings, "graph_steps": t.graph_steps,
+               "chain_order": t.chain_order, "ms_per_step": t.ms_per_step} for t in tr[: min(cap, nt.value)]]
+    return split2, params2, ms.value, trials
+
+
 class Sim:
     """One libjumpmd context. `system` is a systems.System or systems.Batch."""
 
@@ -237,36 +319,13 @@ class Sim:
         """allocator: "torch" (PyTorch's caching allocator, when a GPU is
         visible), None (the library's own hipMalloc) or a TorchAllocator."""
         L = load()
-        systems = list(system.systems) if hasattr(system, "systems") else [system]
-        s0 = systems[0]
-        a = _concat(systems)
+        sy, a = _marshal_system(system)
         self._keep = a
         self.n = int(a["offsets"][-1])
         self.offsets = a["offsets"]
-        sy = MDSystem()
-        sy.n_atoms, sy.n_types, sy.n_replicas = self.n, s0.n_types, len(systems)
-        sy.pos, sy.vel = _ptr(a["pos"], _dp), _ptr(a["vel"], _dp)
-        sy.mass, sy.charge, sy.type = _ptr(a["mass"], _dp), _ptr(a["charge"], _dp), _ptr(a["type"], _ip)
-        self._eps = np.ascontiguousarray(s0.lj_eps, dtype=np.float64)
-        self._sig = np.ascontiguousarray(s0.lj_sigma, dtype=np.float64)
-        sy.lj_eps, sy.lj_sigma = _ptr(self._eps, _dp), _ptr(self._sig, _dp)
-        sy.box, sy.replica_offset = _ptr(a["box"], _dp), _ptr(a["offsets"], _ip)
-        sy.n_bonds, sy.bond_ij = len(a["bond_k"]), _ptr(a["bond_ij"], _ip)
-        sy.bond_k, sy.bond_r0 = _ptr(a["bond_k"], _dp), _ptr(a["bond_r0"], _dp)
-        sy.n_angles, sy.angle_ijk = len(a["angle_k"]), _ptr(a["angle_ijk"], _ip)
-        sy.angle_k, sy.angle_t0 = _ptr(a["angle_k"], _dp), _ptr(a["angle_t0"], _dp)
-        sy.excl_ptr, sy.excl_j = _ptr(a["excl_ptr"], _ip), _ptr(a["excl_j"], _ip)
-        sy.coulomb_k, sy.accel_factor, sy.kB = s0.coulomb_k, s0.accel_factor, s0.kB
-        sp = MDSplit(split.r_s, split.r_c, split.switch_width, split.skin, split.coulomb_alpha,
-                     split.n_rings, split.ring_width)
-        pa = MDParams(params.dt, params.gamma, params.kT, params.seed, params.jump_lj, params.jump_coul,
-                      params.eps, params.precision, params.rebuild_every, params.respa_inner,
-                      params.log_events, params.strict_bounds, getattr(params, "chain_lanes", 0),
-                      getattr(params, "graph_steps", 0), getattr(params, "bound_scale", 0.0),
-                      getattr(params, "row_capacity", 0.0), getattr(params, "event_capacity", 0))
+        sp, pa = _marshal_split(split), _marshal_params(params)
         self.stream = stream if stream is not None else _current_stream()
-        if allocator == "torch":
-            allocator = TorchAllocator() if _gpu_visible() else None
+        allocator = _allocator(allocator)
         self.allocator = allocator
         h = C.c_void_p()
         rc = L.md_create(C.byref(sy), C.byref(sp), C.byref(pa), self.stream,

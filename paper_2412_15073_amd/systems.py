@@ -18,7 +18,7 @@ from typing import List, Optional
 import numpy as np
 
 # jump kinds (same numbering on both sides of the boundary)
-JUMP_NONE, JUMP_BPS, JUMP_MRZ_CONST, JUMP_MRZ_ADAPTIVE = 0, 1, 2, 3
+JUMP_NONE, JUMP_BPS, JUMP_MRZ_CONST, JUMP_MRZ_ADAPTIVE, JUMP_BOUNCE = 0, 1, 2, 3, 4
 FP64, FP32_MIXED = 0, 1
 
 # water units: Angstrom, ps, amu, kJ/mol, e
@@ -84,6 +84,7 @@ class Params:
     bound_scale: float = 0.0  # jump-rate bounds multiplied by this (0 = 1: as derived)
     row_capacity: float = 0.0 # initial row capacity / density estimate (0 = 1.5)
     event_capacity: int = 0   # accepted jumps the GPU event log holds (0 = 2^22)
+    chain_order: int = 0      # wave order of the GPU jump chains (0 auto, 1 by type, 2 by replica)
 
 
 @dataclass

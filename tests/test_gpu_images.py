@@ -137,3 +137,63 @@ def test_energies_with_periodic_images(jm):
     og, oo = g.observables(pe=True), o.energies()
     for k in ("pe_short", "pe_long", "pe_bonded"):
         assert abs(og[k] - oo[k]) <= TOL * abs(oo[k]), (k, og[k], oo[k])
+
+
+def _ensemble():
+    batch = S.water_replicas(256, n_min=216, seed=1)
+    sp = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=0.5, n_rings=12)
+    return batch, sp
+
+
+def _sampled_replicas(batch):
+    """The smallest replica (explicit images), the largest, and one in between."""
+    n = np.diff(batch.offsets)
+    return sorted({int(np.argmin(n)), int(np.argmax(n)), int(np.argsort(n)[len(n) // 2])})
+
+
+def test_ensemble_full_size_in_bench_configuration(jm):
+    """The benchmark's 256-replica ensemble (880k atoms) at full size, in the
+    launch configuration the benchmark times (automatic chain lanes, HIP-graph
+    replays), FP64: 4 JUMP steps, and the smallest, a middle and the largest
+    replica against their own oracle runs: per-atom proposal and accept counts
+    and the order-sensitive per-atom fingerprints of every accepted jump
+    (step, phase, partner) identical (about 10^8 jumps in all: no event log),
+    state within 1e-9."""
+    from oracle.oracle import OracleSim
+    batch, sp = _ensemble()
+    pa = S.water_params(eps0_per_kcal=0.1)
+    pa.graph_steps = 2
+    g = jm.Sim(batch, sp, pa)
+    g.step_jump(4)
+    xg, vg = g.state()
+    sg = g.atom_stats()
+    off = batch.offsets
+    picks = _sampled_replicas(batch)
+    assert any(batch.systems[r].box[0] < 21.0 for r in picks)
+    for r in picks:
+        o = OracleSim(batch.systems[r], sp, pa, replica=r)
+        o.step_jump(4)
+        xo, vo = o.state()
+        a, b = off[r], off[r + 1]
+        assert rel_err(xg[a:b], xo) < TOL and rel_err(vg[a:b], vo) < TOL, r
+        so = o.atom_stats()
+        for k in ("n_prop", "n_acc", "hash"):
+            np.testing.assert_array_equal(sg[k][a:b], so[k], err_msg=f"replica {r} {k}")
+        assert so["n_acc"].sum() > 10000
+
+
+def test_ensemble_full_size_fp32_forces(jm):
+    """The same ensemble in the benchmark's FP32-mixed arithmetic: short and
+    full-range forces of the sampled replicas within 2e-5 of the FP64 oracle."""
+    from oracle.oracle import OracleSim
+    batch, sp = _ensemble()
+    pa = S.water_params(eps0_per_kcal=0.1)
+    pa.precision = S.FP32_MIXED
+    g = jm.Sim(batch, sp, pa)
+    a0, a1 = g.accel(0), g.accel(1)
+    off = batch.offsets
+    for r in _sampled_replicas(batch):
+        o = OracleSim(batch.systems[r], sp, pa, replica=r)
+        a, b = off[r], off[r + 1]
+        assert rel_err(a0[a:b], o.accel(0)) < 2e-5, r
+        assert rel_err(a1[a:b], o.accel(1)) < 2e-5, r

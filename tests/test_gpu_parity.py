@@ -304,6 +304,49 @@ def test_coulomb_jump_kinds(jm, kind, lanes):
     assert o.atom_stats()["n_acc"].sum() > 0
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 8])
+def test_bounce_scheme(jm, lanes):
+    """BOUNCE (Sec. 3): B J A O A J B with the Coulomb long part bounced in
+    the J step together with the LJ one (one chain per atom over the whole
+    long part, no acceleration between jumps): same decisions and states as
+    the oracle."""
+    sy, sp = water_small()
+    pa = S.water_params()
+    pa.jump_coul = S.JUMP_BOUNCE
+    pa.log_events = 1
+    pa.chain_lanes = lanes
+    g, o = _pair(jm, sy, sp, pa)
+    for _ in range(2):
+        g.step_jump(6)
+        o.step_jump(6)
+        _compare_state(g, o)
+    _compare_stats(g, o)
+    ev = o.events()
+    np.testing.assert_array_equal(g.events(), ev)
+    assert len(ev) > 100 and set(np.unique(ev[:, 1])) == {2, 3}   # J phases only
+
+
+def test_bounce_scheme_jump_respa_and_fp32(jm):
+    """BOUNCE at the outer step of JUMP-RESPA (3 inner steps), against the
+    oracle; and in FP32-mixed arithmetic, where its jumps must still act."""
+    sy, sp = water_small()
+    pa = S.water_params()
+    pa.jump_coul = S.JUMP_BOUNCE
+    pa.respa_inner = 3
+    pa.log_events = 1
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_jump_respa(4)
+    o.step_jump_respa(4)
+    _compare_state(g, o)
+    _compare_stats(g, o)
+    np.testing.assert_array_equal(g.events(), o.events())
+    pa.precision = S.FP32_MIXED
+    g32 = jm.Sim(sy, sp, pa)
+    g32.step_jump(10)
+    ob = g32.observables()
+    assert ob["n_acc"] > 100 and np.isfinite(ob["temperature"])
+
+
 def test_bps_coulomb_jump_respa(jm):
     sy, sp = water_small()
     pa = S.water_params()

@@ -26,6 +26,8 @@ PLANTS = {
         ["test_respa_inner_loop_is_baoab_on_bonded_water"]),
     4: ("pair histogram bins rounded to the nearest edge",
         ["test_rdf_counts_on_rock_salt_lattice"]),
+    5: ("BOUNCE chain without the Coulomb gradient",
+        ["test_bounce_j_step_mean_kick_equals_whole_long_force"]),
 }
 
 

@@ -811,6 +811,52 @@ def test_j_step_mean_kick_equals_long_lj_force():
     assert st.chi2.sf(chi2, dof) > 1e-3, chi2
 
 
+def test_bounce_j_step_mean_kick_equals_whole_long_force():
+    """BOUNCE (Sec. 3: bounces on the Coulomb part too, in the J step): one
+    BPS chain per atom over the long part of the whole pair potential (LJ +
+    Coulomb, bound l_LJ + l_Coulomb). Averaged over Maxwell-Boltzmann
+    velocities the J step changes v by -h grad U_long / m of both parts;
+    checked on charged LJ ions, where either part alone would miss."""
+    sy = S.ion_lattice(4, 3.7, q=1.0, lj_eps=5.0, lj_sigma=2.0, jitter=0.1)
+    sp = S.Split(r_s=3.5, r_c=6.0, switch_width=1.0, skin=0.3, coulomb_alpha=0.2, n_rings=3,
+                 ring_width=(6.3 - 2.2) / 3)
+    pa = S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_lj=O.JUMP_BPS, jump_coul=O.JUMP_BOUNCE)
+    o = _oracle(sy, sp, pa)
+    chi2, signal, dof = _moment_check(o, lambda h: o.phase_j(O.PH_J1, h), 0.1, 10000, pa.kT)
+    assert signal > 4 * dof
+    assert st.chi2.sf(chi2, dof) > 1e-3, chi2
+    # the Coulomb part matters here: the LJ chain alone misses its share of the force
+    pa_lj = S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_lj=O.JUMP_BPS)
+    o2 = _oracle(sy, sp, pa_lj)
+    chi2_lj, _, _ = _moment_check(o2, lambda h: o2.phase_j(O.PH_J1, h), 0.1, 10000, pa.kT)
+    assert st.chi2.sf(chi2_lj, dof) < 1e-6
+
+
+def test_bounce_thinning_exact_under_bound_inflation():
+    """BOUNCE's J chain on water: inflating every bound x3 leaves the law of
+    the velocity update unchanged (Sec. 2.4)."""
+    sy, sp = S.water_box(125, seed=4), S.water_split(r_s=5.0, r_c=7.0, w=1.0, skin=0.5, n_rings=3)
+    pa = S.water_params()
+    pa.jump_coul = O.JUMP_BOUNCE
+    res = []
+    K = 150
+    for scale in (1.0, 3.0):
+        o = _oracle(sy, sp, pa)
+        o.set_bound_scale(scale)
+        x0, v0 = o.state()
+        dv = []
+        for k in range(K):
+            o.set_state(vel=v0, step=1000 + k)
+            o.phase_j(O.PH_J1, 0.0005)
+            dv.append((o.state()[1] - v0).ravel())
+        dv = np.array(dv)
+        res.append((dv.mean(0), dv.var(0, ddof=1), o.atom_stats()["n_prop"].sum()))
+    (m1, v1, p1), (m2, v2, p2) = res
+    z2 = (m1 - m2) ** 2 / ((v1 + v2) / K + 1e-300)
+    assert st.chi2.sf(z2.sum(), z2.size) > 1e-3
+    assert p2 > 2.5 * p1
+
+
 # ------------------------------------------------------------ Gibbs marginal
 def _gibbs_reference(sy, sp, kT, edges):
     def u(r):
@@ -822,7 +868,7 @@ def _gibbs_reference(sy, sp, kT, edges):
     return p / p.sum()
 
 
-@pytest.mark.parametrize("scheme", ["jump", "jump_bps", "jump_respa", "baoab"])
+@pytest.mark.parametrize("scheme", ["jump", "jump_bps", "jump_respa", "baoab", "bounce"])
 def test_two_particle_gibbs_marginal(scheme):
     """Two charged LJ particles: the distance histogram (r < L/2) of a long run
     matches p(r) ~ r^2 exp(-beta U(r)) by quadrature, and <v^2> = kT/m.
@@ -834,7 +880,7 @@ def test_two_particle_gibbs_marginal(scheme):
     pa = S.Params(dt=0.005, gamma=2.0, kT=0.722, seed=3,
                   jump_lj=O.JUMP_BPS if scheme != "baoab" else 0,
                   jump_coul={"jump": O.JUMP_MRZ_ADAPTIVE, "jump_bps": O.JUMP_BPS, "jump_respa": O.JUMP_MRZ_ADAPTIVE,
-                             "baoab": 0}[scheme], eps=0.5)
+                             "baoab": 0, "bounce": O.JUMP_BOUNCE}[scheme], eps=0.5)
     pa.respa_inner = 3
     o = _oracle(sy, sp, pa)
     L = sy.box[0]
@@ -859,4 +905,4 @@ def test_two_particle_gibbs_marginal(scheme):
     assert st.chi2.sf(chi2, len(cnt) - 1) > 1e-3, (cnt, exp.round(1))
     assert abs(np.mean(v2) - pa.kT) < 0.03 * pa.kT
     if scheme != "baoab":   # the jumps act (BPS accepts only on approach, so far fewer)
-        assert o.atom_stats()["n_acc"].sum() > (200 if scheme == "jump_bps" else 1000)
+        assert o.atom_stats()["n_acc"].sum() > (200 if scheme in ("jump_bps", "bounce") else 1000)
