@@ -202,7 +202,10 @@ struct orc_sim {
   double ke_c, accel, kB;
   double rs, rc, w, skin, alpha, rlo; int nr; double rw;
   double dt, gamma, kT, beta; uint64_t seed, replica;
-  int jlj, jc; double eps0; int respa_inner, rebuild_every, log_events;
+  int jlj, jc; double eps0; int respa_inner, rebuild_every, log_events, respa_outer;
+  int coul_kind, kmax;  /* electrostatics: DSF, or DSF real part + Ewald reciprocal sum */
+  double *frec;         /* Ewald reciprocal-space forces (-grad), with the excluded-pair correction */
+  int frec_valid;
   /* state */
   int64_t step;
   double *xref;
@@ -449,6 +452,8 @@ static void nb_forces(const orc_sim *s, int kind, double *f, double *pe_s, doubl
       if (kind == ORC_F_SHORT) {
         if (r >= s->rs) continue;
         g = chi * dU + dchi * U;
+      } else if (kind == ORC_F_LONG) {
+        g = (1.0 - chi) * dU - dchi * U;
       } else {
         g = dU;
       }
@@ -503,6 +508,79 @@ static double bonded_forces(const orc_sim *s, double *f) {
   return e;
 }
 
+/* ------------------------------------------------------------- Ewald */
+/* Reciprocal-space part of the Ewald sum (Sec. 3.1: the paper's electrostatics
+ * are Ewald direct space plus a reciprocal part), written out plainly: for
+ * every lattice vector n with 0 < |n|^2 <= kmax^2, k = 2 pi (n_x/L_x, n_y/L_y,
+ * n_z/L_z) and the structure factor S(k) = sum_j q_j exp(i k.x_j),
+ *   E_k = (2 pi k_e / V) sum_k exp(-|k|^2 / (4 alpha^2)) / |k|^2 |S(k)|^2,
+ * whose gradient gives the force on atom i
+ *   f_i = (4 pi k_e q_i / V) sum_k exp(-|k|^2/(4 alpha^2)) / |k|^2 k (Re S sin(k.x_i) - Im S cos(k.x_i)).
+ * The self term E_self = -k_e alpha / sqrt(pi) sum_i q_i^2 removes each
+ * charge's interaction with its own screening cloud, and the excluded pairs,
+ * whose real-space term is left out, lose their reciprocal-space
+ * interaction by E_excl = -k_e q_i q_j erf(alpha r) / r (each pair once).
+ * The real-space part is the damped shifted-force term with the same alpha.
+ * Returns E_k + E_self + E_excl; f (may be NULL) receives the forces. */
+static double recip_part(const orc_sim *s, double *f) {
+  int n = s->n, K = s->kmax;
+  double V = s->L[0] * s->L[1] * s->L[2], a = s->alpha, ke = s->ke_c;
+  if (f) memset(f, 0, sizeof(double) * 3 * (size_t)n);
+  double ek = 0.0;
+  for (int nx = -K; nx <= K; nx++)
+    for (int ny = -K; ny <= K; ny++)
+      for (int nz = -K; nz <= K; nz++) {
+        int n2 = nx * nx + ny * ny + nz * nz;
+        if (n2 == 0 || n2 > K * K) continue;
+        double k[3] = {2.0 * PI * nx / s->L[0], 2.0 * PI * ny / s->L[1], 2.0 * PI * nz / s->L[2]};
+        double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        double w = exp(-k2 / (4.0 * a * a)) / k2;
+        double sre = 0.0, sim = 0.0;
+        for (int j = 0; j < n; j++) {
+          double ph = k[0] * s->x[3 * j] + k[1] * s->x[3 * j + 1] + k[2] * s->x[3 * j + 2];
+          sre += s->q[j] * cos(ph);
+          sim += s->q[j] * sin(ph);
+        }
+        ek += w * (sre * sre + sim * sim);
+        if (f)
+          for (int i = 0; i < n; i++) {
+            double ph = k[0] * s->x[3 * i] + k[1] * s->x[3 * i + 1] + k[2] * s->x[3 * i + 2];
+            double c = 4.0 * PI * ke * s->q[i] / V * w * (sre * sin(ph) - sim * cos(ph));
+            for (int q = 0; q < 3; q++) f[3 * i + q] += c * k[q];
+          }
+      }
+  ek *= 2.0 * PI * ke / V;
+  double eself = 0.0;
+  for (int i = 0; i < n; i++) eself += s->q[i] * s->q[i];
+  eself *= -ke * a / sqrt(PI);
+  double eexcl = 0.0;
+  if (s->xptr)
+    for (int i = 0; i < n; i++)
+      for (int e = s->xptr[i]; e < s->xptr[i + 1]; e++) {
+        int j = s->xj[e];
+        if (j <= i) continue;
+        double d[3], r = pair_vec(s, i, j, d);
+        double qq = ke * s->q[i] * s->q[j];
+        eexcl -= qq * erf(a * r) / r;
+        if (f) {
+          /* dE/dr of -qq erf(a r)/r, then f_i = -dE/dr d/r */
+          double dEdr = -qq * (2.0 * a / sqrt(PI) * exp(-a * a * r * r) / r - erf(a * r) / (r * r));
+          for (int q = 0; q < 3; q++) {
+            double fc = -dEdr * d[q] / r;
+            f[3 * i + q] += fc;
+            f[3 * j + q] -= fc;
+          }
+        }
+      }
+  return ek + eself + eexcl;
+}
+
+static void ensure_recip(orc_sim *s) {
+  if (s->coul_kind != ORC_COUL_EWALD || s->frec_valid) return;
+  recip_part(s, s->frec);
+  s->frec_valid = 1;
+}
+
 static void ensure_forces(orc_sim *s, int kind) {
   if (s->fkind != kind) {
     nb_forces(s, kind, s->fnb, NULL, NULL);
@@ -514,7 +592,7 @@ static void ensure_forces(orc_sim *s, int kind) {
   }
 }
 
-static void positions_moved(orc_sim *s) { s->fkind = -1; s->fb_valid = 0; }
+static void positions_moved(orc_sim *s) { s->fkind = -1; s->fb_valid = 0; s->frec_valid = 0; }
 
 /* Long-range gradient F_ij = grad_{x_i} (1 - chi) U_ij (Sec. 3.1, Sec. 3.2)
  * for the candidate image (j, n); coulomb selects the DSF part, otherwise the
@@ -815,6 +893,12 @@ static void kick(orc_sim *s, double h, int with_nb, int with_b) {
     }
 }
 
+/* v += h f / m for a force array f */
+static void kick_with(orc_sim *s, double h, const double *f) {
+  for (int i = 0; i < s->n; i++)
+    for (int c = 0; c < 3; c++) s->v[3 * i + c] += h * f[3 * i + c] / s->me[i];
+}
+
 static void drift(orc_sim *s, double h) {
   for (int i = 0; i < 3 * s->n; i++) s->x[i] += h * s->v[i];
   positions_moved(s);
@@ -877,18 +961,24 @@ static void c_or_b(orc_sim *s, int32_t phase, double h, int a_kind, int stream) 
 static int has_j(const orc_sim *s) { return s->jlj == ORC_JUMP_BPS || s->jc == ORC_JUMP_BOUNCE; }
 
 /* ------------------------------------------------------------- schemes */
-/* BAOAB with full-range forces (Sec. 2.3 without J). */
+/* BAOAB with full-range forces (Sec. 2.3 without J); with Ewald
+ * electrostatics the reciprocal-space forces are part of every kick. */
 int orc_step_baoab(orc_sim *s, int64_t n) {
   double h = 0.5 * s->dt;
+  int ew = s->coul_kind == ORC_COUL_EWALD;
   ensure_forces(s, ORC_F_FULL);
+  ensure_recip(s);
   for (int64_t it = 0; it < n; it++) {
     kick(s, h, 1, 1);
+    if (ew) kick_with(s, h, s->frec);
     drift(s, h);
     orc_phase_o(s, s->dt, 0);
     drift(s, h);
     maybe_rebuild(s);
     ensure_forces(s, ORC_F_FULL);
+    ensure_recip(s);
     kick(s, h, 1, 1);
+    if (ew) kick_with(s, h, s->frec);
     s->step++;
   }
   return 0;
@@ -900,6 +990,7 @@ int orc_step_baoab(orc_sim *s, int64_t n) {
  * stream, from the proposal after the one that ended it. Those proposals
  * were never used, so they are fresh draws and the law is unchanged. */
 int orc_step_jump(orc_sim *s, int64_t n) {
+  if (s->coul_kind == ORC_COUL_EWALD) return -1;   /* Ewald: the three-level schemes */
   double h = 0.5 * s->dt;
   if (!s->lists_valid) orc_build_lists(s);
   ensure_forces(s, ORC_F_SHORT);
@@ -954,6 +1045,7 @@ static void respa_inner_steps(orc_sim *s, int m, double h) {
  * opening C' continues the stream of the closing C' of the outer step before
  * (both act at the same positions). */
 int orc_step_jump_respa(orc_sim *s, int64_t n_outer) {
+  if (s->coul_kind == ORC_COUL_EWALD) return -1;
   int m = s->respa_inner > 0 ? s->respa_inner : 1;
   double H = 0.5 * s->dt * m, h = 0.5 * s->dt;
   if (!s->lists_valid) orc_build_lists(s);
@@ -973,6 +1065,7 @@ int orc_step_jump_respa(orc_sim *s, int64_t n_outer) {
 
 /* BAOAB-RESPA comparator: full-range non-bonded kick at the outer step. */
 int orc_step_baoab_respa(orc_sim *s, int64_t n_outer) {
+  if (s->coul_kind == ORC_COUL_EWALD) return -1;
   int m = s->respa_inner > 0 ? s->respa_inner : 1;
   double H = 0.5 * s->dt * m, h = 0.5 * s->dt;
   ensure_forces(s, ORC_F_FULL);
@@ -984,6 +1077,68 @@ int orc_step_baoab_respa(orc_sim *s, int64_t n_outer) {
     kick(s, H, 1, 0);
     s->step++;
   }
+  return 0;
+}
+
+/* JUMP-RESPA1 (Sec. 2.3.2, Sec. 3.3, Table 2): three levels. Bonded forces
+ * at the inner step dt (m inner steps per middle step), short non-bonded
+ * forces and all jumps at the middle step m dt (the JUMP-RESPA step above,
+ * with its C' streams continued from middle step to middle step), and the
+ * Ewald reciprocal-space forces at the outer step p m dt, as kicks of half
+ * an outer step around the p middle steps. */
+int orc_step_jump_respa1(orc_sim *s, int64_t n_outer) {
+  if (s->coul_kind != ORC_COUL_EWALD) return -1;
+  int m = s->respa_inner > 0 ? s->respa_inner : 1, p = s->respa_outer > 0 ? s->respa_outer : 1;
+  double h = 0.5 * s->dt, H = 0.5 * s->dt * m, HH = 0.5 * s->dt * m * p;
+  if (!s->lists_valid) orc_build_lists(s);
+  ensure_forces(s, ORC_F_SHORT);
+  ensure_recip(s);
+  for (int64_t it = 0; it < n_outer; it++) {
+    kick_with(s, HH, s->frec);
+    for (int q = 0; q < p; q++) {
+      c_or_b(s, ORC_PH_C1, H, 1, STREAM_CONTINUE);
+      if (has_j(s)) orc_phase_j(s, ORC_PH_J1, H);
+      respa_inner_steps(s, m, h);
+      maybe_rebuild(s);
+      ensure_forces(s, ORC_F_SHORT);
+      if (has_j(s)) orc_phase_j(s, ORC_PH_J2, H);
+      c_or_b(s, ORC_PH_C2, H, 1, STREAM_SAVE);
+      s->step++;
+    }
+    ensure_recip(s);
+    kick_with(s, HH, s->frec);
+  }
+  return 0;
+}
+
+/* BAOAB-RESPA1 comparator (Sec. 2.3.2, Table 2): bonded forces at dt, the
+ * short non-bonded forces chi U at m dt, the long real-space part (1 - chi) U
+ * and the reciprocal-space forces at p m dt. */
+int orc_step_baoab_respa1(orc_sim *s, int64_t n_outer) {
+  if (s->coul_kind != ORC_COUL_EWALD) return -1;
+  int m = s->respa_inner > 0 ? s->respa_inner : 1, p = s->respa_outer > 0 ? s->respa_outer : 1;
+  double h = 0.5 * s->dt, H = 0.5 * s->dt * m, HH = 0.5 * s->dt * m * p;
+  double *fl = (double *)xmalloc(sizeof(double) * 3 * (size_t)s->n);
+  nb_forces(s, ORC_F_LONG, fl, NULL, NULL);
+  ensure_recip(s);
+  ensure_forces(s, ORC_F_SHORT);
+  for (int64_t it = 0; it < n_outer; it++) {
+    kick_with(s, HH, fl);
+    kick_with(s, HH, s->frec);
+    for (int q = 0; q < p; q++) {
+      kick(s, H, 1, 0);
+      respa_inner_steps(s, m, h);
+      maybe_rebuild(s);
+      ensure_forces(s, ORC_F_SHORT);
+      kick(s, H, 1, 0);
+      s->step++;
+    }
+    nb_forces(s, ORC_F_LONG, fl, NULL, NULL);
+    ensure_recip(s);
+    kick_with(s, HH, fl);
+    kick_with(s, HH, s->frec);
+  }
+  free(fl);
   return 0;
 }
 
@@ -1051,7 +1206,11 @@ orc_sim *orc_create(const orc_system *sy, const orc_split *sp, const orc_params 
   s->seed = pa->seed; s->replica = pa->replica;
   s->jlj = pa->jump_lj; s->jc = pa->jump_coul; s->eps0 = pa->eps;
   s->respa_inner = pa->respa_inner; s->rebuild_every = pa->rebuild_every;
-  s->log_events = pa->log_events;
+  s->log_events = pa->log_events; s->respa_outer = pa->respa_outer;
+  s->coul_kind = sp->coulomb_kind; s->kmax = sp->ewald_kmax;
+  if (s->coul_kind != ORC_COUL_DSF && s->coul_kind != ORC_COUL_EWALD) FAIL("coulomb_kind: DSF or EWALD");
+  if (s->coul_kind == ORC_COUL_EWALD && (s->kmax < 1 || !(s->alpha > 0.0))) FAIL("Ewald needs kmax >= 1 and alpha > 0");
+  s->frec = (double *)xmalloc(sizeof(double) * 3 * (size_t)n);
   if (s->jlj != ORC_JUMP_NONE && s->jlj != ORC_JUMP_BPS) FAIL("LJ jumps: NONE or BPS");
   if (s->jc != ORC_JUMP_NONE && s->jc != ORC_JUMP_BPS && s->jc != ORC_JUMP_MRZ_CONST &&
       s->jc != ORC_JUMP_MRZ_ADAPTIVE && s->jc != ORC_JUMP_BOUNCE)
@@ -1091,7 +1250,7 @@ void orc_destroy(orc_sim *s) {
   free(s->bk); free(s->br0); free(s->aijk); free(s->ak); free(s->at0); free(s->xptr);
   free(s->xj); free(s->cptr); free(s->cand); free(s->segst); free(s->ell_lj);
   free(s->ell_cu); free(s->qmax); free(s->nprop); free(s->knext); free(s->nacc); free(s->nviol);
-  free(s->hash); free(s->ev); free(s);
+  free(s->hash); free(s->ev); free(s->frec); free(s);
 }
 
 /* ------------------------------------------------------------ accessors */
@@ -1134,7 +1293,7 @@ void orc_get_events(const orc_sim *s, int64_t *buf) {
   memcpy(buf, s->ev, sizeof(int64_t) * 5 * (size_t)s->nev);
 }
 
-void orc_energies(const orc_sim *s, double out[6]) {
+void orc_energies(const orc_sim *s, double out[7]) {
   double ke = 0.0;
   for (int i = 0; i < s->n; i++)
     for (int c = 0; c < 3; c++) ke += 0.5 * s->me[i] * s->v[3 * i + c] * s->v[3 * i + c];
@@ -1143,14 +1302,16 @@ void orc_energies(const orc_sim *s, double out[6]) {
   nb_forces(s, ORC_F_FULL, tmp, &es, &el);
   double eb = bonded_forces(s, tmp);
   free(tmp);
+  double er = s->coul_kind == ORC_COUL_EWALD ? recip_part(s, NULL) : 0.0;
   out[0] = ke;
   out[1] = 2.0 * ke / (3.0 * s->n * s->kB);
-  out[2] = es; out[3] = el; out[4] = eb; out[5] = es + el + eb;
+  out[2] = es; out[3] = el; out[4] = eb; out[5] = es + el + eb + er; out[6] = er;
 }
 
 void orc_accel(const orc_sim *s, int kind, double *acc) {
   double *f = (double *)xmalloc(sizeof(double) * 3 * (size_t)s->n);
   if (kind == ORC_F_BONDED) bonded_forces(s, f);
+  else if (kind == ORC_F_RECIP) { if (s->coul_kind == ORC_COUL_EWALD) recip_part(s, f); }
   else nb_forces(s, kind, f, NULL, NULL);
   for (int i = 0; i < s->n; i++)
     for (int c = 0; c < 3; c++) acc[3 * i + c] = f[3 * i + c] / s->me[i];

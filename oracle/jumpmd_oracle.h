@@ -36,6 +36,12 @@ extern "C" {
 #define ORC_F_SHORT 0   /* -grad of chi*U over r < r_s (non-bonded) */
 #define ORC_F_FULL 1    /* -grad of U over r < r_c (non-bonded) */
 #define ORC_F_BONDED 2  /* -grad of bonds + angles */
+#define ORC_F_LONG 3    /* -grad of (1-chi)*U over r < r_c (non-bonded) */
+#define ORC_F_RECIP 4   /* Ewald: -grad of the reciprocal-space energy and the excluded-pair correction */
+
+/* electrostatics */
+#define ORC_COUL_DSF 0    /* damped shifted-force Coulomb out to r_c, nothing beyond */
+#define ORC_COUL_EWALD 1  /* the same real-space term plus the Ewald reciprocal sum (Sec. 3.1) */
 
 typedef struct {
   int32_t n_atoms, n_types;
@@ -60,6 +66,8 @@ typedef struct {
   double r_s, r_c, switch_width, skin, coulomb_alpha;
   int32_t n_rings;
   double ring_width;
+  int32_t coulomb_kind;         /* ORC_COUL_DSF or ORC_COUL_EWALD */
+  int32_t ewald_kmax;           /* Ewald: lattice vectors n with 0 < |n|^2 <= kmax^2 */
 } orc_split;
 
 typedef struct {
@@ -70,6 +78,7 @@ typedef struct {
   int32_t respa_inner;
   int32_t rebuild_every;        /* 0: displacement-triggered */
   int32_t log_events;
+  int32_t respa_outer;          /* middle steps per outer step of the three-level schemes */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -92,6 +101,8 @@ int orc_step_baoab(orc_sim *s, int64_t n);
 int orc_step_jump(orc_sim *s, int64_t n);
 int orc_step_jump_respa(orc_sim *s, int64_t n_outer);
 int orc_step_baoab_respa(orc_sim *s, int64_t n_outer);
+int orc_step_jump_respa1(orc_sim *s, int64_t n_outer);   /* Ewald: three levels, Sec. 2.3.2 */
+int orc_step_baoab_respa1(orc_sim *s, int64_t n_outer);
 void orc_get_state(const orc_sim *s, double *pos, double *vel);
 void orc_set_state(orc_sim *s, const double *pos, const double *vel, int64_t step);
 int64_t orc_step_index(const orc_sim *s);
@@ -104,7 +115,9 @@ void orc_atom_stats(const orc_sim *s, int64_t *nprop, int64_t *nacc, int64_t *nv
 uint64_t orc_event_hash(const orc_sim *s);
 int64_t orc_n_events(const orc_sim *s);
 void orc_get_events(const orc_sim *s, int64_t *buf); /* 5 int64 per event: step, phase, i, j, k */
-void orc_energies(const orc_sim *s, double out[6]);  /* ke, T, pe_short, pe_long, pe_bonded, pe_full */
+void orc_energies(const orc_sim *s, double out[7]);  /* ke, T, pe_short, pe_long, pe_bonded, pe_full,
+                                                        pe_recip (Ewald: reciprocal + self + excluded-pair
+                                                        correction; 0 otherwise; included in pe_full) */
 void orc_accel(const orc_sim *s, int kind, double *acc); /* [3N], length/time^2 */
 void orc_rdf(const orc_sim *s, int ta, int tb, double r_max, int n_bins, double *hist);
 

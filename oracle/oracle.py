@@ -18,7 +18,8 @@ _LIB_ENV = "JUMPMD_ORACLE_LIBRARY"
 
 JUMP_NONE, JUMP_BPS, JUMP_MRZ_CONST, JUMP_MRZ_ADAPTIVE, JUMP_BOUNCE = 0, 1, 2, 3, 4
 PH_O, PH_J1, PH_J2, PH_C1, PH_C2 = 1, 2, 3, 4, 5
-F_SHORT, F_FULL, F_BONDED = 0, 1, 2
+F_SHORT, F_FULL, F_BONDED, F_LONG, F_RECIP = 0, 1, 2, 3, 4
+COUL_DSF, COUL_EWALD = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -41,7 +42,8 @@ class OrcSystem(C.Structure):
 class OrcSplit(C.Structure):
     _fields_ = [("r_s", C.c_double), ("r_c", C.c_double), ("switch_width", C.c_double),
                 ("skin", C.c_double), ("coulomb_alpha", C.c_double),
-                ("n_rings", C.c_int32), ("ring_width", C.c_double)]
+                ("n_rings", C.c_int32), ("ring_width", C.c_double),
+                ("coulomb_kind", C.c_int32), ("ewald_kmax", C.c_int32)]
 
 
 class OrcParams(C.Structure):
@@ -49,7 +51,7 @@ class OrcParams(C.Structure):
                 ("seed", C.c_uint64), ("replica", C.c_uint64),
                 ("jump_lj", C.c_int32), ("jump_coul", C.c_int32), ("eps", C.c_double),
                 ("respa_inner", C.c_int32), ("rebuild_every", C.c_int32),
-                ("log_events", C.c_int32)]
+                ("log_events", C.c_int32), ("respa_outer", C.c_int32)]
 
 
 _lib = None
@@ -67,7 +69,8 @@ def lib():
         L.orc_create.argtypes = [C.POINTER(OrcSystem), C.POINTER(OrcSplit), C.POINTER(OrcParams),
                                  C.c_char_p, C.c_int]
         L.orc_destroy.argtypes = [C.c_void_p]
-        for fn in ("orc_step_baoab", "orc_step_jump", "orc_step_jump_respa", "orc_step_baoab_respa"):
+        for fn in ("orc_step_baoab", "orc_step_jump", "orc_step_jump_respa", "orc_step_baoab_respa",
+                   "orc_step_jump_respa1", "orc_step_baoab_respa1"):
             getattr(L, fn).argtypes = [C.c_void_p, C.c_int64]
             getattr(L, fn).restype = C.c_int
         L.orc_get_state.argtypes = [C.c_void_p, _dp, _dp]
@@ -188,10 +191,11 @@ class OracleSim:
             sy.excl_j = _ptr(arr(s.excl_j, np.int32), _ip)
         sy.coulomb_k, sy.accel_factor, sy.kB = s.coulomb_k, s.accel_factor, s.kB
         sp = OrcSplit(split.r_s, split.r_c, split.switch_width, split.skin,
-                      split.coulomb_alpha, split.n_rings, split.ring_width)
+                      split.coulomb_alpha, split.n_rings, split.ring_width,
+                      getattr(split, "coulomb_kind", 0), getattr(split, "ewald_kmax", 0))
         pa = OrcParams(params.dt, params.gamma, params.kT, params.seed, replica,
                        params.jump_lj, params.jump_coul, params.eps, params.respa_inner,
-                       params.rebuild_every, params.log_events)
+                       params.rebuild_every, params.log_events, getattr(params, "respa_outer", 1))
         err = C.create_string_buffer(256)
         self._h = lib().orc_create(C.byref(sy), C.byref(sp), C.byref(pa), err, 256)
         if not self._h:
@@ -214,6 +218,14 @@ class OracleSim:
 
     def step_baoab_respa(self, n):
         lib().orc_step_baoab_respa(self._h, n)
+
+    def step_jump_respa1(self, n):
+        if lib().orc_step_jump_respa1(self._h, n) != 0:
+            raise RuntimeError("JUMP-RESPA1 needs Ewald electrostatics")
+
+    def step_baoab_respa1(self, n):
+        if lib().orc_step_baoab_respa1(self._h, n) != 0:
+            raise RuntimeError("BAOAB-RESPA1 needs Ewald electrostatics")
 
     # state
     def state(self):
@@ -269,9 +281,9 @@ class OracleSim:
         return ev[np.lexsort((ev[:, 4], ev[:, 2], ev[:, 1], ev[:, 0]))]
 
     def energies(self):
-        out = np.zeros(6)
+        out = np.zeros(7)
         lib().orc_energies(self._h, _ptr(out, _dp))
-        return dict(zip(("ke", "T", "pe_short", "pe_long", "pe_bonded", "pe_full"), out))
+        return dict(zip(("ke", "T", "pe_short", "pe_long", "pe_bonded", "pe_full", "pe_recip"), out))
 
     def accel(self, kind):
         a = np.zeros(3 * self.n)

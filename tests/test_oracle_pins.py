@@ -906,3 +906,88 @@ def test_two_particle_gibbs_marginal(scheme):
     assert abs(np.mean(v2) - pa.kT) < 0.03 * pa.kT
     if scheme != "baoab":   # the jumps act (BPS accepts only on approach, so far fewer)
         assert o.atom_stats()["n_acc"].sum() > (200 if scheme in ("jump_bps", "bounce") else 1000)
+
+
+# ------------------------------------------------------------------- Ewald
+MADELUNG_NACL = 1.747564594633182   # rock-salt Madelung constant (nearest-neighbour distance)
+
+
+def test_ewald_madelung_constant_of_rock_salt():
+    """Ewald electrostatics (damped shifted-force real part + reciprocal sum +
+    self term) on a perfect rock-salt lattice of 512 unit charges, nearest
+    neighbours at distance 1: the energy per ion is -M/2 k_e q^2 / a with the
+    rock-salt Madelung constant M (real part converged: erfc(alpha r_c) ~ 1e-13;
+    reciprocal sum converged: exp(-k^2 / 4 alpha^2) ~ 1e-13 at kmax)."""
+    sy = S.ion_lattice(8, 1.0, q=1.0, coulomb_k=1.0, jitter=0.0)
+    sp = S.Split(r_s=2.0, r_c=3.5, switch_width=0.5, skin=0.1, coulomb_alpha=1.5, coulomb_kind=1, ewald_kmax=21)
+    e = _oracle(sy, sp, S.Params(dt=0.01, gamma=0.0, kT=1.0)).energies()
+    per_ion = e["pe_full"] / sy.n_atoms
+    assert abs(per_ion + MADELUNG_NACL / 2) < 1e-9, per_ion
+    assert e["pe_recip"] != 0.0
+
+
+def _ewald_water(alpha, kmax, seed=9):
+    sy = S.water_box(125, seed=seed, jitter=0.05)
+    sp = S.water_split(r_s=5.0, r_c=7.5, w=1.0, skin=0.3, alpha=alpha, n_rings=3)
+    sp.coulomb_kind, sp.ewald_kmax = 1, kmax
+    return sy, sp
+
+
+def test_ewald_sum_independent_of_alpha():
+    """The Ewald total energy and forces do not depend on the splitting
+    parameter alpha once both sums have converged. On water (bonded
+    molecules whose intramolecular pairs are excluded) this also pins the
+    excluded-pair correction and the self term: without them the reciprocal
+    sum would count the excluded pairs by an alpha-dependent amount."""
+    out = []
+    for alpha, kmax in ((0.72, 19), (0.86, 23)):
+        sy, sp = _ewald_water(alpha, kmax)
+        o = _oracle(sy, sp, S.water_params())
+        e = o.energies()
+        f = o.accel(O.F_FULL) + o.accel(O.F_RECIP)
+        out.append((e["pe_full"] - e["pe_bonded"], f, e["pe_recip"]))
+    (e1, f1, r1), (e2, f2, r2) = out
+    assert abs(r1 - r2) > 1.0                       # the split moved energy between the parts
+    assert abs(e1 - e2) < 1e-9 * abs(e1), (e1, e2)
+    assert rel_err(f1, f2) < 1e-8
+
+
+def test_ewald_forces_are_minus_energy_gradient():
+    """Reciprocal-space forces (with the excluded-pair correction) and the
+    real-space forces are minus the gradient of the total energy (central
+    differences), at an alpha where the two parts are of similar size."""
+    sy, sp = _ewald_water(0.3, 8)
+    o = _oracle(sy, sp, S.water_params())
+    me = sy.mass / sy.accel_factor
+    f = (o.accel(O.F_FULL) + o.accel(O.F_RECIP)) * me[:, None]
+    fr = o.accel(O.F_RECIP) * me[:, None]
+    assert np.abs(fr).max() > 0.1 * np.abs(f).max()
+    h = 1e-5
+    for i in (0, 1, 200):
+        for c in range(3):
+            xp, xm = sy.pos.copy(), sy.pos.copy()
+            xp[i, c] += h
+            xm[i, c] -= h
+            o.set_state(pos=xp)
+            ep = o.energies()
+            o.set_state(pos=xm)
+            em = o.energies()
+            fd = -((ep["pe_full"] - ep["pe_bonded"]) - (em["pe_full"] - em["pe_bonded"])) / (2 * h)
+            assert abs(f[i, c] - fd) < 1e-5 * max(1.0, abs(fd)), (i, c, f[i, c], fd)
+    o.set_state(pos=sy.pos)
+    assert np.abs(f.sum(0)).max() < 1e-9 * np.abs(f).sum()
+
+
+def test_baoab_respa1_with_single_steps_is_baoab():
+    """BAOAB-RESPA1 with one inner and one middle step per outer step is BAOAB
+    with the same forces (bonded + short + long real part + reciprocal),
+    split over several kicks: trajectories agree to rounding."""
+    sy, sp = _ewald_water(0.3, 6)
+    pa = S.water_params(jumps=False)
+    pa.gamma = 1.0
+    o1, o2 = _oracle(sy, sp, pa), _oracle(sy, sp, pa)
+    o1.step_baoab(15)
+    o2.step_baoab_respa1(15)
+    x1, v1 = o1.state()
+    x2, v2 = o2.state()
+    assert rel_err(x2, x1) < 1e-12 and rel_err(v2, v1) < 1e-11
