@@ -20,6 +20,11 @@ comparator, kernel split and roofline:
   water32000_respa 32000 waters (96000 atoms, 98.6 A), r_c = 12 A, JUMP-RESPA
                    (bonded forces every 1 fs, short forces and jumps every
                    3 fs) FP32-mixed vs FP64 BAOAB-RESPA with full forces;
+  water4096_ewald_respa1  the 4096-water box with Ewald electrostatics (damped
+                   real part to 10 A with alpha 0.35 A^-1, reciprocal sum to
+                   |n| <= 20): JUMP-RESPA1 at 1:2:6 fs (bonded 1 fs, short forces
+                   and jumps 2 fs, reciprocal forces 6 fs) FP32-mixed vs FP64
+                   BAOAB-RESPA1 at the same steps;
   lj864            864 LJ atoms (fcc, rho 0.8442, kT 0.722), B J A O A J B with
                    BPS jumps between r_s = 3 and r_c = 5 sigma, vs BAOAB, FP64
                    (reduced units: tau/day).
@@ -61,6 +66,10 @@ PEAK_HBM_GBS = 8000.0
 FLOP_PER_SHORT_PAIR = 78
 FLOP_PER_FULL_PAIR = 60
 FLOP_PER_PROPOSAL = 93
+#  an (atom, k-vector) pair of the Ewald reciprocal sum: structure factor
+#  (k.x, sin, cos, two fmas: 9 flops) and force (k.x, sin, cos, weight times
+#  the structure-factor combination, three fmas: 14 flops), 23 flops.
+FLOP_PER_ATOM_K = 23
 BYTES_PER_ATOM_LOCAL = 7 * 32   # x (read+write), v (read+write), f_nb, f_b, x_ref reads
 # one row build: per atom, binning (x read, reference copy written, cell index
 # and slot), scatter (cell-ordered FP64 and FP32 position copies) and the
@@ -73,9 +82,9 @@ BYTES_PER_ROW_ENTRY = 4
 # sources (md_chain.hip, then md_device.h) starts with the given prefix.
 CHAIN_TRAFFIC = {}
 KERNELS = {0: "k_local (B/A/O updates)", 1: "k_force (pairs, with bonded when fused)", 2: "k_bonded (separate)",
-           3: "row rebuild", 4: "k_chain (J/C jump chains)"}
+           3: "row rebuild", 4: "k_chain (J/C jump chains)", 5: "Ewald reciprocal (k_sfac, k_recip_force)"}
 METRIC = "ns/day & pair-interactions/s, JUMP vs full-force BAOAB, 1 MI355X, matched T/RDF/D"
-ALL_WORKLOADS = ("ensemble", "water4096", "water4096_fp32", "water32000_respa", "lj864")
+ALL_WORKLOADS = ("ensemble", "water4096", "water4096_fp32", "water32000_respa", "water4096_ewald_respa1", "lj864")
 
 
 def parse():
@@ -239,12 +248,15 @@ class Workload:
     def __init__(self, name, a, S):
         self.name = name
         self.respa = name == "water32000_respa"
+        self.respa1 = name == "water4096_ewald_respa1"
         self.lj = name == "lj864"
         self.ensemble = name == "ensemble"
-        self.jump_prec = {"ensemble": 1, "water4096": 0, "water4096_fp32": 1, "water32000_respa": 1, "lj864": 0}[name]
+        self.jump_prec = {"ensemble": 1, "water4096": 0, "water4096_fp32": 1, "water32000_respa": 1,
+                          "water4096_ewald_respa1": 1, "lj864": 0}[name]
         self.rc = 12.0 if self.respa else 10.0
-        self.inner = 3 if self.respa else 1
-        self.graph = 0 if self.respa else a.graph_steps
+        self.inner = 3 if self.respa else (2 if self.respa1 else 1)
+        self.outer = 3 if self.respa1 else 1
+        self.graph = 0 if (self.respa or self.respa1) else a.graph_steps
         self.S = S
         self.a = a
         if self.ensemble:
@@ -257,11 +269,15 @@ class Workload:
             n_mol = 32000 if self.respa else 4096
             self.system = lambda: S.water_box(n_mol, seed=1)
             self.n_sys = 1
-        self.step_unit = 0.005 if self.lj else 1e-6 * self.inner   # simulated tau, or ns, per call step
+        self.step_unit = 0.005 if self.lj else 1e-6 * self.inner * self.outer   # simulated tau, or ns, per call step
 
     def split(self, skin):
         if self.lj:
             return self.S.lj_split(skin=0.3)
+        if self.respa1:
+            sp = self.S.water_split(r_s=5.0, r_c=self.rc, w=1.0, skin=skin, alpha=0.35, n_rings=self.a.rings)
+            sp.coulomb_kind, sp.ewald_kmax = 1, 20
+            return sp
         return self.S.water_split(r_s=5.0, r_c=self.rc, w=1.0, skin=skin, n_rings=self.a.rings)
 
     def params(self, jumps, prec, graph):
@@ -270,8 +286,9 @@ class Workload:
             p = S.lj_params(seed=2, jumps=jumps)
         else:
             p = S.water_params(eps0_per_kcal=self.a.eps0, jumps=jumps)
-            if self.respa:
+            if self.respa or self.respa1:
                 p.respa_inner = self.inner
+                p.respa_outer = self.outer
         p.chain_lanes = self.a.chain_lanes
         p.chain_order = self.a.chain_order
         p.graph_steps = graph
@@ -301,7 +318,13 @@ def set_state(sy, x, v):
         sy.pos, sy.vel = x, v
 
 
-def roofline(prof, steps_prof, props_prof, pairs_short, n_atoms, prec, build_bytes_prof=0.0):
+def half_space_kvectors(kmax):
+    """Integer vectors n != 0 with |n|^2 <= kmax^2, one of each pair +-n."""
+    r = range(-kmax, kmax + 1)
+    return sum(1 for x in r for y in r for z in r if 0 < x * x + y * y + z * z <= kmax * kmax) // 2
+
+
+def roofline(prof, steps_prof, props_prof, pairs_short, n_atoms, prec, build_bytes_prof=0.0, n_k=0):
     dom = max(prof, key=lambda k: prof[k][0])
     tot_ms, launches = prof[dom]
     avg_s = tot_ms * 1e-3 / max(launches, 1)
@@ -315,6 +338,11 @@ def roofline(prof, steps_prof, props_prof, pairs_short, n_atoms, prec, build_byt
         work = pairs_short * FLOP_PER_SHORT_PAIR
         roof = {"bound": "alu", "achieved": work / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
                 "algorithmic": f"{FLOP_PER_SHORT_PAIR} flop/pair x {pairs_short} pairs/launch"}
+    elif dom == 5:
+        # one evaluation: structure factors and forces over every (atom, k) pair, FP64
+        work = n_atoms * n_k * FLOP_PER_ATOM_K
+        roof = {"bound": "alu", "achieved": work / avg_s / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "algorithmic": f"{FLOP_PER_ATOM_K} flop x {n_atoms} atoms x {n_k} k-vectors per evaluation"}
     elif dom == 3:
         # every step launches the displacement check; builds happen on some steps
         work = build_bytes_prof / max(launches, 1)
@@ -347,8 +375,10 @@ def run_workload(w, jumpmd, C, cache):
     print(f"[bench] {w.name}: {n_atoms} atoms, equilibrated in {time.perf_counter() - t:.1f} s, T = {T_eq:.1f}",
           flush=True)
     set_state(sysm, x, v)
-    jstep = (lambda s: s.step_jump_respa) if w.respa else (lambda s: s.step_jump)
-    bstep = (lambda s: s.step_baoab_respa) if w.respa else (lambda s: s.step_baoab)
+    jstep = (lambda s: s.step_jump_respa) if w.respa else (
+        (lambda s: s.step_jump_respa1) if w.respa1 else (lambda s: s.step_jump))
+    bstep = (lambda s: s.step_baoab_respa) if w.respa else (
+        (lambda s: s.step_baoab_respa1) if w.respa1 else (lambda s: s.step_baoab))
     split_j = w.split(a.skin)
     pj = w.params(True, w.jump_prec, w.graph)
     tuned = None
@@ -399,8 +429,8 @@ def run_workload(w, jumpmd, C, cache):
     # comparator: FP64 BAOAB (or BAOAB-RESPA) with full-range forces
     base = None
     if not a.no_baoab:
-        if w.name == "water4096_fp32" and "water4096" in cache and cache["water4096"].get("baoab"):
-            base = cache["water4096"]["baoab"]
+        if w.name == "water4096_fp32" and cache.get("baoab:water4096"):
+            base = cache["baoab:water4096"]
         else:
             split_b = w.split(0.3 if w.lj else a.baoab_skin)
             pb = w.params(False, 0, w.graph)
@@ -432,7 +462,8 @@ def run_workload(w, jumpmd, C, cache):
             print(f"[bench] {w.name} BAOAB FP64 {ms_b:.4f} ms/step, {base['rate']:.1f} {unit}, "
                   f"T = {obs_b['temperature']:.1f}, {pairs_full} pairs", flush=True)
 
-    dom, roof = roofline(prof_j, a.profile_steps, props_prof, pairs_short, n_atoms, w.jump_prec, build_bytes)
+    n_k = half_space_kvectors(split_j.ewald_kmax) if w.respa1 else 0
+    dom, roof = roofline(prof_j, a.profile_steps, props_prof, pairs_short, n_atoms, w.jump_prec, build_bytes, n_k)
     tr = CHAIN_TRAFFIC.get(w.name)
     if dom == 4 and tr and chain_source_hash().startswith(tr["sha256"]):
         roof["traffic"] = tr["bytes"]
@@ -455,12 +486,16 @@ def run_workload(w, jumpmd, C, cache):
         "roofline": roof,
         "config": {"r_s": 3.0 if w.lj else 5.0, "r_c": 5.0 if w.lj else w.rc, "switch": 0.5 if w.lj else 1.0,
                    "skin": 0.3 if w.lj else split_j.skin, "baoab_skin": base["skin"] if base else None,
-                   "rings": 1 if w.lj else split_j.n_rings, "chain_lanes": pj.chain_lanes, "autotuned": tuned, "respa_inner": w.inner if w.respa else None,
+                   "rings": 1 if w.lj else split_j.n_rings, "chain_lanes": pj.chain_lanes, "autotuned": tuned,
+                   "respa_inner": w.inner if (w.respa or w.respa1) else None,
+                   "respa_outer": w.outer if w.respa1 else None,
+                   "electrostatics": "Ewald (alpha 0.35, kmax 20)" if w.respa1 else (None if w.lj else "DSF (alpha 0.2)"),
                    "dt": "0.005 tau" if w.lj else "1 fs", "graph_steps": pj.graph_steps,
                    "eps0_per_kcal_mol_A": None if w.lj else a.eps0,
                    "jumps": "LJ BPS" if w.lj else "LJ BPS + Coulomb adaptive MRZ"},
     }
-    cache[key] = {"state": (x, v, T_eq), "baoab": base}
+    cache[key] = {"state": (x, v, T_eq)}
+    cache["baoab:" + w.name] = base
     return res, (sysm, x, v)
 
 

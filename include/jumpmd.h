@@ -114,7 +114,17 @@ typedef struct {
   double r_s, r_c, switch_width, skin, coulomb_alpha;
   int32_t n_rings;
   double ring_width;
+  int32_t coulomb_kind;  /* MD_COUL_DSF or MD_COUL_EWALD */
+  int32_t ewald_kmax;    /* Ewald: lattice vectors n with 0 < |n|^2 <= kmax^2 in the reciprocal sum */
 } md_split;
+
+/* electrostatics (md_split.coulomb_kind) */
+#define MD_COUL_DSF 0    /* damped shifted-force Coulomb out to r_c, nothing beyond */
+#define MD_COUL_EWALD 1  /* Ewald (Sec. 3.1): the same real-space term with coulomb_alpha, plus the
+                            reciprocal-space sum over ewald_kmax (with the self term and the excluded
+                            pairs taken back); one replica only; schemes md_step_baoab (reciprocal
+                            forces in every kick) and the three-level md_step_jump_respa1 and
+                            md_step_baoab_respa1 */
 
 /* Device memory for a context (md_create): alloc returns `bytes` of device
  * memory usable on `stream` (NULL on failure), release gives it back. Both
@@ -156,6 +166,7 @@ typedef struct {
   int64_t event_capacity; /* accepted jumps the event log holds (log_events = 1); 0: 2^22 */
   int32_t chain_order;  /* wave order of the jump chains: 0 or 1 by atom type (heaviest chains first),
                            2 replica by replica (each by type); results do not depend on it */
+  int32_t respa_outer;  /* middle steps per outer step of the three-level RESPA schemes (>= 1) */
 } md_params;
 
 typedef struct {
@@ -166,6 +177,7 @@ typedef struct {
   int64_t n_prop, n_acc, n_bound_viol, n_rebuilds, n_zsampler_overflow, n_list_errors;
   uint64_t event_hash;  /* FNV-1a over the per-atom event hashes, atom order */
   int64_t n_regrows;    /* times the rows were regrown and the steps replayed */
+  double pe_recip;      /* MD_OBS_PE with Ewald: reciprocal sum + self term + excluded-pair correction */
 } md_obs;
 
 typedef struct {          /* one accepted jump */
@@ -202,6 +214,15 @@ int md_step_jump(md_ctx *ctx, int64_t nsteps);
 int md_step_jump_respa(md_ctx *ctx, int64_t n_outer);
 /* BAOAB-RESPA comparator: full-range non-bonded kick at the outer step. */
 int md_step_baoab_respa(md_ctx *ctx, int64_t n_outer);
+/* JUMP-RESPA1 (Sec. 2.3.2, Sec. 3.3, Table 2; needs MD_COUL_EWALD): three
+ * levels, bonded forces at dt, short non-bonded forces and all jumps at
+ * respa_inner*dt (the JUMP-RESPA step), reciprocal-space forces at
+ * respa_outer*respa_inner*dt. n_outer outer steps. */
+int md_step_jump_respa1(md_ctx *ctx, int64_t n_outer);
+/* BAOAB-RESPA1 comparator (needs MD_COUL_EWALD): bonded forces at dt, short
+ * non-bonded chi U at respa_inner*dt, the long real-space part (1 - chi) U and
+ * the reciprocal-space forces at respa_outer*respa_inner*dt. */
+int md_step_baoab_respa1(md_ctx *ctx, int64_t n_outer);
 
 /* Synchronise and report the observables of Sec. 4: kinetic energy and
  * temperature 2 KE / (3 N kB) (no centre-of-mass constraint), jump
@@ -218,7 +239,9 @@ int md_sync(md_ctx *ctx);
 int md_get_state(md_ctx *ctx, double *pos, double *vel);
 int md_set_state(md_ctx *ctx, const double *pos, const double *vel, int64_t step);
 /* Current accelerations [3N]: kind 0 = short non-bonded, 1 = full non-bonded,
- * 2 = bonded (evaluated at the current positions). */
+ * 2 = bonded, 3 = long real-space part (1 - chi) U, 4 = Ewald reciprocal
+ * space with the excluded-pair correction (evaluated at the current
+ * positions). */
 int md_get_accel(md_ctx *ctx, int32_t kind, double *acc);
 /* Per-atom jump statistics [N] each (any may be NULL). */
 int md_get_atom_stats(md_ctx *ctx, int64_t *n_prop, int64_t *n_acc, int64_t *n_viol, uint64_t *hash);
@@ -269,7 +292,8 @@ int md_run_phase(md_ctx *ctx, int32_t which, int32_t phase, double h);
 #define MD_K_BONDED 2
 #define MD_K_REBUILD 3    /* all neighbour-row kernels of a step */
 #define MD_K_CHAIN 4      /* jump chains (J and C ops, with the kicks between them) */
-#define MD_K_COUNT 5
+#define MD_K_RECIP 5      /* Ewald reciprocal-space forces */
+#define MD_K_COUNT 6
 int md_profile(md_ctx *ctx, int32_t enable);
 int md_profile_read(md_ctx *ctx, int32_t kid, double *total_ms, int64_t *launches);
 

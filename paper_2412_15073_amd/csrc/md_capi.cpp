@@ -19,7 +19,8 @@ namespace {
 thread_local std::string g_create_error;
 
 enum { ROW_SHORT = 1, ROW_FULL = 2, ROW_CAND = 4 };
-enum { MODE_NONE = -1, MODE_JUMP = 0, MODE_BAOAB = 1, MODE_JUMP_RESPA = 2, MODE_BAOAB_RESPA = 3 };
+enum { MODE_NONE = -1, MODE_JUMP = 0, MODE_BAOAB = 1, MODE_JUMP_RESPA = 2, MODE_BAOAB_RESPA = 3,
+       MODE_JUMP_RESPA1 = 4, MODE_BAOAB_RESPA1 = 5 };
 
 struct Timer {
   std::vector<hipEvent_t> pool;
@@ -42,6 +43,11 @@ struct md_ctx {
   int64_t step = 0;
   int fkind = -1;              // force kind held in fnb: 0 short, 1 full, -1 stale
   bool fb_valid = false;
+  bool ewald = false;          // Ewald electrostatics (reciprocal sum in frec)
+  bool frec_valid = false;     // frec holds the reciprocal-space forces at the current positions
+  bool flong_valid = false;    // flong holds the long real-space forces at the current positions
+  double2 *d_spart = nullptr, *d_sfac = nullptr;   // Ewald partial and total structure factors
+  double ew_ecoef = 0.0, ew_self = 0.0;            // Ewald energy prefactor (half space), self energy
   int rows_valid = 0;          // ROW_* bits valid for the current reference positions
   int64_t since_build = 0;
   int pc = 0, ps = 0;          // LDS key capacities of the row builder
@@ -302,13 +308,17 @@ static int run_prog(md_ctx *c, ProgBuilder &b) {
     c->cur ^= 1;
     c->fkind = -1;
     c->fb_valid = false;
+    c->frec_valid = false;
+    c->flong_valid = false;
   }
   return MD_OK;
 }
 
 // -------------------------------------------------------- rows and forces
 static int rows_for_mode(int mode) {
-  return (mode == MODE_JUMP || mode == MODE_JUMP_RESPA) ? (ROW_SHORT | ROW_CAND) : ROW_FULL;
+  if (mode == MODE_JUMP || mode == MODE_JUMP_RESPA || mode == MODE_JUMP_RESPA1) return ROW_SHORT | ROW_CAND;
+  if (mode == MODE_BAOAB_RESPA1) return ROW_SHORT | ROW_FULL;
+  return ROW_FULL;
 }
 
 // Build the requested rows at the reference positions without changing the
@@ -403,11 +413,36 @@ static int eval_forces(md_ctx *c, int kind) {
   return MD_OK;
 }
 
+// Ewald reciprocal-space forces at the current positions (into V.frec)
+static int eval_recip(md_ctx *c) {
+  if (!c->ewald) return MD_OK;
+  hipEvent_t e0{};
+  prof_begin(c, MD_K_RECIP, &e0);
+  HIPCHK(c, launch_recip(c->V, Xcur(c), c->d_spart, c->d_sfac, c->stream));
+  prof_end(c, MD_K_RECIP, e0);
+  c->frec_valid = true;
+  return MD_OK;
+}
+
+// long real-space part -grad (1 - chi) U at the current positions (into V.flong; full rows)
+static int eval_long(md_ctx *c) {
+  hipEvent_t e0{};
+  prof_begin(c, MD_K_FORCE, &e0);
+  HIPCHK(c, launch_force(c->V, Xcur(c), 2, false, c->stream));
+  prof_end(c, MD_K_FORCE, e0);
+  c->flong_valid = true;
+  return MD_OK;
+}
+
 static int ensure_forces(md_ctx *c, int mode) {
   int rc = ensure_rows(c, rows_for_mode(mode));
   if (rc) return rc;
-  int kind = (mode == MODE_JUMP || mode == MODE_JUMP_RESPA) ? 0 : 1;
-  return eval_forces(c, kind);
+  const bool short_kind = mode == MODE_JUMP || mode == MODE_JUMP_RESPA || mode == MODE_JUMP_RESPA1 ||
+                          mode == MODE_BAOAB_RESPA1;
+  if ((rc = eval_forces(c, short_kind ? 0 : 1))) return rc;
+  if (c->ewald && !c->frec_valid && (rc = eval_recip(c))) return rc;
+  if (mode == MODE_BAOAB_RESPA1 && !c->flong_valid && (rc = eval_long(c))) return rc;
+  return MD_OK;
 }
 
 // ------------------------------------------------------------ creation
@@ -507,6 +542,14 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
   if (p->row_capacity < 0.0 || !std::isfinite(p->row_capacity)) return fail(nullptr, MD_ERR_ARG, "row_capacity must be >= 0");
   if (p->event_capacity < 0 || p->event_capacity > (1ll << 31)) return fail(nullptr, MD_ERR_ARG, "event_capacity must be in [0, 2^31]");
   if (p->chain_order < 0 || p->chain_order > 2) return fail(nullptr, MD_ERR_ARG, "chain_order must be 0, 1 or 2");
+  if (p->respa_outer < 0) return fail(nullptr, MD_ERR_ARG, "respa_outer must be >= 0 (0: 1)");
+  if (sp->coulomb_kind != MD_COUL_DSF && sp->coulomb_kind != MD_COUL_EWALD)
+    return fail(nullptr, MD_ERR_ARG, "coulomb_kind must be MD_COUL_DSF or MD_COUL_EWALD");
+  if (sp->coulomb_kind == MD_COUL_EWALD) {
+    if (s->n_replicas != 1) return fail(nullptr, MD_ERR_ARG, "Ewald electrostatics: one replica per context");
+    if (sp->ewald_kmax < 1 || sp->ewald_kmax > 64 || !(sp->coulomb_alpha > 0.0))
+      return fail(nullptr, MD_ERR_ARG, "Ewald electrostatics need 1 <= ewald_kmax <= 64 and coulomb_alpha > 0");
+  }
   return MD_OK;
 }
 
@@ -836,7 +879,38 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
     A(q.x, n); A(q.v, n); A(q.xref, n); A(q.knext, n);
     A(q.nprop, n); A(q.nacc, n); A(q.nviol, n); A(q.hash, n); A(q.maxd2, 2 * nrep); A(q.ctl, 1);
   }
+  // Ewald reciprocal sum: k-vectors of the half space with 0 < |n|^2 <= kmax^2
+  std::vector<double4> kv;
+  c->ewald = sp->coulomb_kind == MD_COUL_EWALD;
+  if (c->ewald) {
+    const int K = sp->ewald_kmax;
+    const double *L = c->box.data();
+    const double vol = L[0] * L[1] * L[2];
+    for (int nx = 0; nx <= K; ++nx)
+      for (int ny = -K; ny <= K; ++ny)
+        for (int nz = -K; nz <= K; ++nz) {
+          const int n2 = nx * nx + ny * ny + nz * nz;
+          if (n2 == 0 || n2 > K * K) continue;
+          if (nx == 0 && (ny < 0 || (ny == 0 && nz < 0))) continue;   // one of k, -k
+          const double kx = 2.0 * M_PI * nx / L[0], ky = 2.0 * M_PI * ny / L[1], kz = 2.0 * M_PI * nz / L[2];
+          const double k2 = kx * kx + ky * ky + kz * kz;
+          kv.push_back(make_double4(kx, ky, kz, std::exp(-k2 / (4.0 * V.alpha * V.alpha)) / k2));
+        }
+    V.nk = (int)kv.size();
+    V.ew_fcoef = 2.0 * 4.0 * M_PI * V.ke / vol;
+    c->ew_ecoef = 2.0 * 2.0 * M_PI * V.ke / vol;
+    double q2 = 0.0;
+    for (int i = 0; i < n; ++i) q2 += s->charge ? s->charge[i] * s->charge[i] : 0.0;
+    c->ew_self = -V.ke * V.alpha / std::sqrt(M_PI) * q2;
+    double4 *d_kv;
+    A(d_kv, kv.size());
+    V.kvec = d_kv;
+    A(V.frec, n); A(V.flong, n);
+    A(c->d_spart, (size_t)((n + 255) / 256) * kv.size());
+    A(c->d_sfac, kv.size());
+  }
   c->scratch_n = std::max<size_t>(4 * (size_t)n + (size_t)s->n_bonds + (size_t)s->n_angles, 4096);
+  c->scratch_n = std::max<size_t>(c->scratch_n, kv.size() + (size_t)n);
   A(c->d_scratch, c->scratch_n);
   if (!ok) {
     std::string why = c->err;
@@ -890,6 +964,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   up(d_at0, s->angle_t0, sizeof(double) * s->n_angles);
   up(c->d_rep_off, c->rep_off.data(), sizeof(int) * (nrep + 1));
   up(d_chain_perm, chain_perm.data(), sizeof(int) * chain_perm.size());
+  if (c->ewald) up((void *)V.kvec, kv.data(), sizeof(double4) * kv.size());
   c->fuse_forces[0] = force_fused_fits(V, 0);
   c->fuse_forces[1] = force_fused_fits(V, 1);
   {
@@ -926,6 +1001,8 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   c->cur = 0;
   c->fkind = -1;
   c->fb_valid = false;
+  c->frec_valid = false;
+  c->flong_valid = false;
   c->rows_valid = 0;
   *out = c;
   return MD_OK;
@@ -955,11 +1032,12 @@ static int baoab_plain(md_ctx *c, int64_t nsteps) {
   int rc = ensure_forces(c, MODE_BAOAB);
   if (rc) return rc;
   const double h = 0.5 * c->par.dt;
+  const int fl = c->ewald ? 7 : 3;                   // non-bonded + bonded (+ reciprocal)
   for (int64_t it = 0; it <= nsteps; ++it) {
     ProgBuilder b;
-    if (it > 0) add_B(b, h, 3);                      // tail of the previous step
+    if (it > 0) add_B(b, h, fl);                     // tail of the previous step
     if (it < nsteps) {                               // head of this step
-      add_B(b, h, 3);
+      add_B(b, h, fl);
       add_A(b, h);
       add_O(c, b, c->par.dt, 0, c->step);
       add_A(b, h);
@@ -969,6 +1047,7 @@ static int baoab_plain(md_ctx *c, int64_t nsteps) {
     if (it == nsteps) break;
     if ((rc = step_rebuild(c, MODE_BAOAB, c->step))) return rc;
     if ((rc = eval_forces(c, 1))) return rc;
+    if ((rc = eval_recip(c))) return rc;
     c->step++;
   }
   return MD_OK;
@@ -1024,7 +1103,7 @@ static int graph_chunks(md_ctx *c, int mode, int64_t &n) {
   if (!c->gexec[key]) {
     const int64_t step0 = c->step;
     const int cur0 = c->cur, fk0 = c->fkind, rows0 = c->rows_valid;
-    const bool fb0 = c->fb_valid;
+    const bool fb0 = c->fb_valid, fr0 = c->frec_valid;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     c->capturing = true;
     c->step_rel0 = step0;
@@ -1032,7 +1111,7 @@ static int graph_chunks(md_ctx *c, int mode, int64_t &n) {
     c->capturing = false;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
-    c->step = step0; c->cur = cur0; c->fkind = fk0; c->rows_valid = rows0; c->fb_valid = fb0;
+    c->step = step0; c->cur = cur0; c->fkind = fk0; c->rows_valid = rows0; c->fb_valid = fb0; c->frec_valid = fr0;
     if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (e != hipSuccess) return fail(c, MD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(&c->gexec[key], g, nullptr, nullptr, 0);
@@ -1048,6 +1127,7 @@ static int graph_chunks(md_ctx *c, int mode, int64_t &n) {
   // a chunk ends with the forces and rows of this scheme current
   c->fkind = mode == MODE_JUMP ? 0 : 1;
   c->fb_valid = true;
+  c->frec_valid = c->ewald;
   c->rows_valid = rows_for_mode(mode);
   return MD_OK;
 }
@@ -1098,12 +1178,73 @@ static int respa(md_ctx *c, int64_t n_outer, bool jump) {
   return MD_OK;
 }
 
+// Three-level schemes (Ewald; Sec. 2.3.2, Sec. 3.3, Table 2). Inner steps
+// B_b A O A B_b at dt; middle steps at M = respa_inner*dt: JUMP-RESPA1 runs
+// the JUMP-RESPA step (C' J' [inner] J' C', short forces and all jumps),
+// BAOAB-RESPA1 kicks with the short forces chi U; outer steps at
+// respa_outer*M: a kick of half an outer step with the reciprocal-space
+// forces (BAOAB-RESPA1: plus the long real-space part (1 - chi) U) on either
+// side of the middle steps. Programs fuse the closing ops of one middle step
+// with the opening ops of the next (and the two outer kicks between outer
+// steps) into one position-preserving prefix, as in respa().
+static int respa1(md_ctx *c, int64_t n_outer, bool jump) {
+  const int mode = jump ? MODE_JUMP_RESPA1 : MODE_BAOAB_RESPA1;
+  int rc = ensure_forces(c, mode);
+  if (rc) return rc;
+  const int m = c->par.respa_inner, p = std::max(1, c->par.respa_outer);
+  const double h = 0.5 * c->par.dt, H = 0.5 * c->par.dt * m, HH = H * p;
+  const bool lj = jump && (c->par.jump_lj == MD_JUMP_BPS || c->par.jump_coul == MD_JUMP_BOUNCE);
+  const int outer_flags = jump ? 4 : (4 | 8);   // reciprocal (+ long real part)
+  const int64_t n_mid = n_outer * p;
+  for (int64_t it = 0; it <= n_mid; ++it) {
+    ProgBuilder b;
+    if (it > 0) {                                    // closing ops of middle step it-1
+      add_B(b, h, 2);
+      if (jump) {
+        if (lj) add_J(b, OP_PHASE_J2, H, c->step - 1);
+        add_C_or_B(c, b, OP_PHASE_C2, H, c->step - 1, 1, MD_STREAM_SAVE);
+      } else {
+        add_B(b, H, 1);
+      }
+      if (it % p == 0) add_B(b, HH, outer_flags);    // end of an outer step
+    }
+    if (it == n_mid) { if ((rc = run_prog(c, b))) return rc; break; }
+    if (it % p == 0) add_B(b, HH, outer_flags);      // start of an outer step
+    if (jump) {
+      add_C_or_B(c, b, OP_PHASE_C1, H, c->step, 1, MD_STREAM_CONTINUE);
+      if (lj) add_J(b, OP_PHASE_J1, H, c->step);
+    } else {
+      add_B(b, H, 1);
+    }
+    for (int sub = 0; sub < m; ++sub) {
+      if (sub > 0) add_B(b, h, 2);
+      add_B(b, h, 2);
+      add_A(b, h);
+      add_O(c, b, c->par.dt, sub, c->step);
+      add_A(b, h);
+      if (sub == m - 1) add_disp(b, (int)(c->step & 1));
+      if ((rc = run_prog(c, b))) return rc;
+      if ((rc = eval_bonded(c))) return rc;
+      b = ProgBuilder();
+    }
+    if ((rc = step_rebuild(c, mode, c->step))) return rc;
+    if ((rc = eval_nb(c, 0))) return rc;
+    if ((it + 1) % p == 0) {                         // forces of the outer level at the outer boundary
+      if ((rc = eval_recip(c))) return rc;
+      if (!jump && (rc = eval_long(c))) return rc;
+    }
+    c->step++;
+  }
+  return MD_OK;
+}
+
 static int run_phase(md_ctx *c, int which, int phase, double h);
 static int take_snapshot(md_ctx *c);
 
 // Stepping calls are journaled since the rollback point (md_ctx::Snap), so
 // that a row regrow can replay them.
-enum { CALL_BAOAB = 0, CALL_JUMP, CALL_JUMP_RESPA, CALL_BAOAB_RESPA, CALL_PHASE };
+enum { CALL_BAOAB = 0, CALL_JUMP, CALL_JUMP_RESPA, CALL_BAOAB_RESPA, CALL_PHASE, CALL_JUMP_RESPA1,
+       CALL_BAOAB_RESPA1 };
 
 static int run_call(md_ctx *c, const md_ctx::Call &k) {
   int64_t n = k.n;
@@ -1118,6 +1259,8 @@ static int run_call(md_ctx *c, const md_ctx::Call &k) {
     case CALL_JUMP_RESPA: return respa(c, n, true);
     case CALL_BAOAB_RESPA: return respa(c, n, false);
     case CALL_PHASE: return run_phase(c, k.which, k.phase, k.h);
+    case CALL_JUMP_RESPA1: return respa1(c, n, true);
+    case CALL_BAOAB_RESPA1: return respa1(c, n, false);
   }
   return fail(c, MD_ERR_ARG, "internal: unknown call");
 }
@@ -1138,17 +1281,32 @@ extern "C" int md_step_baoab(md_ctx *c, int64_t nsteps) {
 
 extern "C" int md_step_jump(md_ctx *c, int64_t nsteps) {
   if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  if (c->ewald) return fail(c, MD_ERR_ARG, "Ewald electrostatics: use md_step_baoab or the three-level schemes");
   return step_call(c, {CALL_JUMP, nsteps, 0, 0, 0.0});
 }
 
 extern "C" int md_step_jump_respa(md_ctx *c, int64_t n_outer) {
   if (!c || n_outer < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  if (c->ewald) return fail(c, MD_ERR_ARG, "Ewald electrostatics: use md_step_jump_respa1");
   return step_call(c, {CALL_JUMP_RESPA, n_outer, 0, 0, 0.0});
 }
 
 extern "C" int md_step_baoab_respa(md_ctx *c, int64_t n_outer) {
   if (!c || n_outer < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  if (c->ewald) return fail(c, MD_ERR_ARG, "Ewald electrostatics: use md_step_baoab_respa1");
   return step_call(c, {CALL_BAOAB_RESPA, n_outer, 0, 0, 0.0});
+}
+
+extern "C" int md_step_jump_respa1(md_ctx *c, int64_t n_outer) {
+  if (!c || n_outer < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  if (!c->ewald) return fail(c, MD_ERR_ARG, "the three-level schemes need Ewald electrostatics (MD_COUL_EWALD)");
+  return step_call(c, {CALL_JUMP_RESPA1, n_outer, 0, 0, 0.0});
+}
+
+extern "C" int md_step_baoab_respa1(md_ctx *c, int64_t n_outer) {
+  if (!c || n_outer < 0) return fail(c, MD_ERR_ARG, "bad argument");
+  if (!c->ewald) return fail(c, MD_ERR_ARG, "the three-level schemes need Ewald electrostatics (MD_COUL_EWALD)");
+  return step_call(c, {CALL_BAOAB_RESPA1, n_outer, 0, 0, 0.0});
 }
 
 // -------------------------------------------------------------- sync
@@ -1238,6 +1396,8 @@ static int restore_snapshot(md_ctx *c) {
   c->since_build = q.since_build;
   c->fkind = -1;
   c->fb_valid = false;
+  c->frec_valid = false;
+  c->flong_valid = false;
   c->rows_valid = 0;
   if (q.rows_valid) return build_rows_at_ref(c, q.rows_valid, false);
   return MD_OK;
@@ -1270,6 +1430,8 @@ static int settle(md_ctx *c) {
       c->rows_valid = 0;
       c->fkind = -1;
       c->fb_valid = false;
+      c->frec_valid = false;
+      c->flong_valid = false;
       if (rv) rc = build_rows_at_ref(c, rv, false);
     }
     if (rc != MD_OK) {
@@ -1372,6 +1534,17 @@ extern "C" int md_observables(md_ctx *c, uint32_t flags, md_obs *o) {
     for (int i = 0; i < c->n; ++i) { ps += hs[i]; pl += hl[i]; }
     for (int t = 0; t < c->nbonds + c->nangles; ++t) pb += hb[t];
     o->pe_short = ps; o->pe_long = pl; o->pe_bonded = pb;
+    if (c->ewald) {
+      const size_t ne = (size_t)c->V.nk + (size_t)c->n;
+      std::vector<double> he(ne);
+      HIPCHK(c, launch_ewald_energy(c->V, X, c->d_spart, c->d_sfac, c->d_scratch, c->stream));
+      HIPCHK(c, hipMemcpyAsync(he.data(), c->d_scratch, sizeof(double) * ne, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      double ek = 0.0, ex = 0.0;
+      for (int k = 0; k < c->V.nk; ++k) ek += he[k];
+      for (int i = 0; i < c->n; ++i) ex += he[c->V.nk + i];
+      o->pe_recip = c->ew_ecoef * ek + c->ew_self + ex;
+    }
   }
   return rc;
 }
@@ -1406,6 +1579,8 @@ extern "C" int md_set_state(md_ctx *c, const double *pos, const double *vel, int
     c->rows_valid = 0;
     c->fkind = -1;
     c->fb_valid = false;
+    c->frec_valid = false;
+    c->flong_valid = false;
   }
   if (vel) {
     HIPCHK(c, hipMemcpy(h.data(), c->V.v, sizeof(double4) * c->n, hipMemcpyDeviceToHost));
@@ -1417,19 +1592,30 @@ extern "C" int md_set_state(md_ctx *c, const double *pos, const double *vel, int
 }
 
 extern "C" int md_get_accel(md_ctx *c, int32_t kind, double *acc) {
-  if (!c || !acc || kind < 0 || kind > 2) return fail(c, MD_ERR_ARG, "bad argument");
+  if (!c || !acc || kind < 0 || kind > 4) return fail(c, MD_ERR_ARG, "bad argument");
+  if (kind == 4 && !c->ewald) return fail(c, MD_ERR_ARG, "no reciprocal-space forces without Ewald electrostatics");
   int rc = settle(c);
   if (rc) return rc;
+  const double4 *src = c->V.fnb;
   if (kind == 2) {
     if ((rc = eval_bonded(c))) return rc;
+    src = c->V.fb;
+  } else if (kind == 4) {
+    if ((rc = eval_recip(c))) return rc;
+    src = c->V.frec;
   } else {
     if ((rc = ensure_rows(c, kind == 0 ? (ROW_SHORT | ROW_CAND) : ROW_FULL))) return rc;
     if ((rc = settle(c))) return rc;   // rows regrown before use if they overflowed
-    if ((rc = eval_nb(c, kind))) return rc;
+    if (kind == 3) {
+      if (!c->V.flong) return fail(c, MD_ERR_ARG, "long real-space forces need Ewald electrostatics");
+      if ((rc = eval_long(c))) return rc;
+      src = c->V.flong;
+    } else if ((rc = eval_nb(c, kind))) {
+      return rc;
+    }
   }
   std::vector<double4> f(c->n), v(c->n);
-  HIPCHK(c, hipMemcpyAsync(f.data(), kind == 2 ? c->V.fb : c->V.fnb, sizeof(double4) * c->n,
-                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(f.data(), src, sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(v.data(), c->V.v, sizeof(double4) * c->n, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int i = 0; i < c->n; ++i) {

@@ -731,10 +731,8 @@ __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_S
     op.step += sbase;
     op.rstep += sbase;
     if (op.kind == OP_B) {
-      const double fx = ((op.flags & 1) ? fn.x : 0.0) + ((op.flags & 2) ? fb.x : 0.0);
-      const double fy = ((op.flags & 1) ? fn.y : 0.0) + ((op.flags & 2) ? fb.y : 0.0);
-      const double fz = ((op.flags & 1) ? fn.z : 0.0) + ((op.flags & 2) ? fb.z : 0.0);
-      vx += op.h * fx / me; vy += op.h * fy / me; vz += op.h * fz / me;
+      const double3 f = kick_force(V, op.flags, i, fn, fb);
+      vx += op.h * f.x / me; vy += op.h * f.y / me; vz += op.h * f.z / me;
     } else {
       double ax = 0.0, ay = 0.0, az = 0.0;
       if (op.kind == OP_C) {

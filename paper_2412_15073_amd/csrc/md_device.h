@@ -75,7 +75,8 @@ struct MDOp {
   int kind;      // OP_*
   int phase;     // random-stream phase tag (J/C/O)
   int substep;   // O: inner index of the RESPA schemes
-  int flags;     // B: bit0 non-bonded, bit1 bonded; C: 0 -> a from nb+bonded, 1 -> nb only
+  int flags;     // B: bit0 non-bonded, bit1 bonded, bit2 reciprocal, bit3 long real part;
+                 // C: 0 -> a from nb+bonded, 1 -> nb only
   double h;      // duration
   double c1, c2; // O: exp(-gamma h), sqrt(1 - c1^2)
   int64_t step;  // random-stream step word (and the label of logged events)
@@ -120,6 +121,8 @@ struct MDView {
   double4 *x0, *x1;      // xyz + charge
   double4 *v;            // velocity + mass in energy units (mass / accel_factor)
   double4 *fnb, *fb;     // forces (-grad): non-bonded, bonded
+  double4 *frec, *flong; // Ewald: reciprocal-space forces (with the excluded-pair correction), and the
+                         // long real-space part (1 - chi) U of the three-level BAOAB comparator
   double4 *xref;         // positions at the last row build
   const int *type, *rep, *loc;
   const double *box;     // [3*nrep]
@@ -145,6 +148,10 @@ struct MDView {
   unsigned long long *rep_maxd2;        // [2*nrep] max |x - x_ref|^2 (double bits) per step parity and replica
   int ncell_total;
   int qimg;                             // row builder queue slots of replicas with explicit images (0: none)
+  // Ewald reciprocal sum (one replica): k-vectors of the half space, w = exp(-k^2/(4 alpha^2)) / k^2
+  const double4 *kvec;                  // [nk] (kx, ky, kz, w)
+  int nk;
+  double ew_fcoef;                      // force prefactor 2 * 4 pi k_e / V (k and -k together)
   // neighbour rows (row-major, fixed capacity)
   int cap_s, cap_f, cap_c;
   int *srow, *scnt, *frow, *fcnt, *crow, *ccnt, *segst;
@@ -166,6 +173,16 @@ struct MDView {
   const int *chain_perm; // [chain_groups] atom whose chain group g runs, -1: idle group
   uint64_t seed;
 };
+
+// force of a B kick with these flags (see MDOp), atom i
+__device__ __forceinline__ double3 kick_force(const MDView &V, int flags, int i, double4 fn, double4 fb) {
+  double3 f = make_double3(0.0, 0.0, 0.0);
+  if (flags & 1) { f.x += fn.x; f.y += fn.y; f.z += fn.z; }
+  if (flags & 2) { f.x += fb.x; f.y += fb.y; f.z += fb.z; }
+  if (flags & 4) { const double4 r = V.frec[i]; f.x += r.x; f.y += r.y; f.z += r.z; }
+  if (flags & 8) { const double4 l = V.flong[i]; f.x += l.x; f.y += l.y; f.z += l.z; }
+  return f;
+}
 
 // wave-scope ordering of LDS writes by some lanes before reads by others
 __device__ __forceinline__ void wave_lds_sync() {

@@ -47,10 +47,8 @@ __global__ __launch_bounds__(256) void k_local(MDView V, MDProg P, const double4
     op.step += sbase;
     switch (op.kind) {
       case OP_B: {
-        const double fx = ((op.flags & 1) ? fn.x : 0.0) + ((op.flags & 2) ? fb.x : 0.0);
-        const double fy = ((op.flags & 1) ? fn.y : 0.0) + ((op.flags & 2) ? fb.y : 0.0);
-        const double fz = ((op.flags & 1) ? fn.z : 0.0) + ((op.flags & 2) ? fb.z : 0.0);
-        vx += op.h * fx / me; vy += op.h * fy / me; vz += op.h * fz / me;
+        const double3 f = kick_force(V, op.flags, ii, fn, fb);
+        vx += op.h * f.x / me; vy += op.h * f.y / me; vz += op.h * f.z / me;
       } break;
       case OP_A:
         xi.x += op.h * vx; xi.y += op.h * vy; xi.z += op.h * vz;
@@ -541,7 +539,8 @@ __device__ __forceinline__ void bonded_atom(const MDView &V, const double4 *__re
   V.fb[i] = make_double4(f[0], f[1], f[2], 0.0);
 }
 
-// MODE 0: -grad chi U over r < r_s (short rows); MODE 1: -grad U over r < r_c (full rows).
+// MODE 0: -grad chi U over r < r_s (short rows); MODE 1: -grad U over r < r_c (full rows);
+// MODE 2: -grad (1 - chi) U over r < r_c (full rows) into V.flong.
 // BONDED: blocks from nb_pair on compute the bonded forces instead (one atom
 // per lane), so that they run beside the pair blocks in one launch (a
 // separate instantiation: the bonded path's registers would cost the plain
@@ -593,6 +592,10 @@ __global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__rest
           float chi, dchi;
           switch_fn_f(rr, V, chi, dchi);
           g = chi * dU + dchi * U;
+        } else if (MODE == 2) {
+          float chi, dchi;
+          switch_fn_f(rr, V, chi, dchi);
+          g = (1.0f - chi) * dU - dchi * U;
         }
         const float sc = -g * ir;
         fx += (double)(sc * dx); fy += (double)(sc * dy); fz += (double)(sc * dz);
@@ -605,7 +608,7 @@ __global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__rest
     fy += __shfl_xor(fy, off, SG);
     fz += __shfl_xor(fz, off, SG);
   }
-  if (i < V.n && lane == 0) V.fnb[i] = make_double4(fx, fy, fz, 0.0);
+  if (i < V.n && lane == 0) (MODE == 2 ? V.flong : V.fnb)[i] = make_double4(fx, fy, fz, 0.0);
 }
 
 template <int MODE, int SG, bool BONDED>
@@ -652,6 +655,10 @@ __global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restri
           double chi, dchi;
           switch_fn(rr, V, chi, dchi);
           g = chi * dU + dchi * U;
+        } else if (MODE == 2) {
+          double chi, dchi;
+          switch_fn(rr, V, chi, dchi);
+          g = (1.0 - chi) * dU - dchi * U;
         }
         double s = -g * ir;
         fx += s * dx; fy += s * dy; fz += s * dz;
@@ -664,7 +671,7 @@ __global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restri
     fy += __shfl_xor(fy, off, SG);
     fz += __shfl_xor(fz, off, SG);
   }
-  if (i < V.n && lane == 0) V.fnb[i] = make_double4(fx, fy, fz, 0.0);
+  if (i < V.n && lane == 0) (MODE == 2 ? V.flong : V.fnb)[i] = make_double4(fx, fy, fz, 0.0);
 }
 
 // bonds (k/2)(b-b0)^2 and angles (k/2)(theta-theta0)^2, per atom over incident terms
@@ -806,6 +813,120 @@ __global__ void k_count_pairs(MDView V, const double4 *__restrict__ X, int which
   if (c) atomicAdd(out, c);
 }
 
+// ----------------------------------------------------------- Ewald sum
+// Reciprocal-space part of the Ewald sum (one replica): with k over the half
+// space (k and -k give equal terms), w_k = exp(-k^2 / (4 alpha^2)) / k^2 and
+// the structure factor S(k) = sum_j q_j exp(i k.x_j),
+//   E_k = 2 (2 pi k_e / V) sum_k w_k |S(k)|^2,
+//   f_i = 2 (4 pi k_e / V) q_i sum_k w_k k (Re S sin(k.x_i) - Im S cos(k.x_i)),
+// plus, for every excluded pair, the force of -k_e q_i q_j erf(alpha r) / r
+// (their real-space term is left out, so their reciprocal-space interaction
+// is taken back).
+// Partial structure factors: block (kb, t) stages atom tile t (256 atoms,
+// position and charge) in LDS; thread k sums its tile's terms.
+__global__ __launch_bounds__(256) void k_sfac(MDView V, const double4 *__restrict__ X, double2 *__restrict__ part) {
+  __shared__ double4 xs[256];
+  const int t = blockIdx.y, k = blockIdx.x * 256 + threadIdx.x;
+  const int i0 = t * 256, ia = i0 + threadIdx.x;
+  xs[threadIdx.x] = ia < V.n ? X[ia] : make_double4(0.0, 0.0, 0.0, 0.0);
+  __syncthreads();
+  if (k >= V.nk) return;
+  const double4 kv = V.kvec[k];
+  const int m = min(256, V.n - i0);
+  double sr = 0.0, si = 0.0;
+  for (int j = 0; j < m; ++j) {
+    const double4 x = xs[j];
+    double sn, cs;
+    sincos(kv.x * x.x + kv.y * x.y + kv.z * x.z, &sn, &cs);
+    sr += x.w * cs;
+    si += x.w * sn;
+  }
+  part[(size_t)t * V.nk + k] = make_double2(sr, si);
+}
+
+// S(k) = sum over tiles in tile order (deterministic)
+__global__ void k_sfac_sum(MDView V, const double2 *__restrict__ part, int ntiles, double2 *__restrict__ S) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= V.nk) return;
+  double sr = 0.0, si = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    const double2 p = part[(size_t)t * V.nk + k];
+    sr += p.x;
+    si += p.y;
+  }
+  S[k] = make_double2(sr, si);
+}
+
+// reciprocal-space forces, one atom per thread; k-vectors and S(k) staged in LDS
+__global__ __launch_bounds__(256) void k_recip_force(MDView V, const double4 *__restrict__ X,
+                                                     const double2 *__restrict__ S) {
+  __shared__ double4 ks[256];
+  __shared__ double2 ss[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const double4 xi = i < V.n ? X[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  for (int k0 = 0; k0 < V.nk; k0 += 256) {
+    __syncthreads();
+    if (k0 + (int)threadIdx.x < V.nk) { ks[threadIdx.x] = V.kvec[k0 + threadIdx.x]; ss[threadIdx.x] = S[k0 + threadIdx.x]; }
+    __syncthreads();
+    const int m = min(256, V.nk - k0);
+    for (int q = 0; q < m; ++q) {
+      const double4 kv = ks[q];
+      const double2 sq = ss[q];
+      double sn, cs;
+      sincos(kv.x * xi.x + kv.y * xi.y + kv.z * xi.z, &sn, &cs);
+      const double a = kv.w * (sq.x * sn - sq.y * cs);
+      fx += a * kv.x; fy += a * kv.y; fz += a * kv.z;
+    }
+  }
+  if (i >= V.n) return;
+  const double c = V.ew_fcoef * xi.w;
+  fx *= c; fy *= c; fz *= c;
+  if (V.xptr) {
+    const double L[3] = {V.box[0], V.box[1], V.box[2]};
+    const double a = V.alpha;
+    for (int e = V.xptr[i]; e < V.xptr[i + 1]; ++e) {
+      const int j = V.xj[e];
+      const double4 xj = X[j];
+      const double dx = min_img(xi.x - xj.x, L[0], 1.0 / L[0]);
+      const double dy = min_img(xi.y - xj.y, L[1], 1.0 / L[1]);
+      const double dz = min_img(xi.z - xj.z, L[2], 1.0 / L[2]);
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double qq = V.ke * xi.w * xj.w;
+      const double dEdr = -qq * (V.two_a_sqpi * exp(-a * a * r * r) / r - erf(a * r) / (r * r));
+      fx -= dEdr * dx / r; fy -= dEdr * dy / r; fz -= dEdr * dz / r;
+    }
+  }
+  V.frec[i] = make_double4(fx, fy, fz, 0.0);
+}
+
+// Ewald energy terms: w_k |S(k)|^2 per k into e[0, nk), and each atom's half
+// of its excluded pairs' correction -k_e q_i q_j erf(alpha r) / r into e[nk + i]
+__global__ void k_ewald_energy(MDView V, const double4 *__restrict__ X, const double2 *__restrict__ S,
+                               double *__restrict__ e) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < V.nk) {
+    const double2 sq = S[t];
+    e[t] = V.kvec[t].w * (sq.x * sq.x + sq.y * sq.y);
+  } else if (t < V.nk + V.n) {
+    const int i = t - V.nk;
+    const double4 xi = X[i];
+    double u = 0.0;
+    if (V.xptr) {
+      const double L[3] = {V.box[0], V.box[1], V.box[2]};
+      for (int q = V.xptr[i]; q < V.xptr[i + 1]; ++q) {
+        const double4 xj = X[V.xj[q]];
+        const double dx = min_img(xi.x - xj.x, L[0], 1.0 / L[0]);
+        const double dy = min_img(xi.y - xj.y, L[1], 1.0 / L[1]);
+        const double dz = min_img(xi.z - xj.z, L[2], 1.0 / L[2]);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        u -= 0.5 * V.ke * xi.w * xj.w * erf(V.alpha * r) / r;
+      }
+    }
+    e[t] = u;
+  }
+}
+
 // counts to doubles (the histogram of the allocation-free entry point)
 __global__ void k_u64_to_double(const unsigned long long *__restrict__ a, double *__restrict__ b, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -925,7 +1046,7 @@ hipError_t launch_force(const MDView &V, const double4 *X, int mode, bool with_b
       if (with_bonded) hipLaunchKernelGGL((k_force<0, 8, true>), grid, blk, 0, s, V, X, nb);
       else hipLaunchKernelGGL((k_force<0, 8, false>), grid, blk, 0, s, V, X, nb);
     }
-  } else {
+  } else if (mode == 1) {
     const int nb = (int)(((long long)V.n * 16 + 255) / 256);
     const dim3 grid(nb + nbb);
     if (f32) {
@@ -935,6 +1056,10 @@ hipError_t launch_force(const MDView &V, const double4 *X, int mode, bool with_b
       if (with_bonded) hipLaunchKernelGGL((k_force<1, 16, true>), grid, blk, 0, s, V, X, nb);
       else hipLaunchKernelGGL((k_force<1, 16, false>), grid, blk, 0, s, V, X, nb);
     }
+  } else {   // long real part (no bonded blocks)
+    const int nb = (int)(((long long)V.n * 16 + 255) / 256);
+    if (f32) hipLaunchKernelGGL((k_force_f<2, 16, false>), dim3(nb), blk, 0, s, V, X, nb);
+    else hipLaunchKernelGGL((k_force<2, 16, false>), dim3(nb), blk, 0, s, V, X, nb);
   }
   return hipGetLastError();
 }
@@ -981,6 +1106,28 @@ hipError_t launch_set_step(MDCtl *ctl, long long step, hipStream_t s) {
 hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// reciprocal-space forces into V.frec; part: [ceil(n/256) * nk] partial sums, S: [nk]
+hipError_t launch_recip(const MDView &V, const double4 *X, double2 *part, double2 *S, hipStream_t s) {
+  const int ntiles = (V.n + 255) / 256;
+  hipLaunchKernelGGL(k_sfac, dim3((V.nk + 255) / 256, ntiles), dim3(256), 0, s, V, X, part);
+  CHK(hipGetLastError());
+  hipLaunchKernelGGL(k_sfac_sum, dim3((V.nk + 255) / 256), dim3(256), 0, s, V, part, ntiles, S);
+  CHK(hipGetLastError());
+  hipLaunchKernelGGL(k_recip_force, dim3((V.n + 255) / 256), dim3(256), 0, s, V, X, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_ewald_energy(const MDView &V, const double4 *X, double2 *part, double2 *S, double *e,
+                               hipStream_t s) {
+  const int ntiles = (V.n + 255) / 256;
+  hipLaunchKernelGGL(k_sfac, dim3((V.nk + 255) / 256, ntiles), dim3(256), 0, s, V, X, part);
+  CHK(hipGetLastError());
+  hipLaunchKernelGGL(k_sfac_sum, dim3((V.nk + 255) / 256), dim3(256), 0, s, V, part, ntiles, S);
+  CHK(hipGetLastError());
+  hipLaunchKernelGGL(k_ewald_energy, dim3((V.nk + V.n + 255) / 256), dim3(256), 0, s, V, X, S, e);
   return hipGetLastError();
 }
 

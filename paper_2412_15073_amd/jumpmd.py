@@ -18,7 +18,7 @@ MD_OK, MD_ERR_ARG, MD_ERR_HIP, MD_ERR_BOUND, MD_ERR_LIST, MD_ERR_UNSTABLE, MD_ER
     0, -1, -2, -3, -4, -5, -6, -7
 MD_ERR_EVENTS = -8
 MD_OBS_PE = 1
-MD_K_LOCAL, MD_K_FORCE, MD_K_BONDED, MD_K_REBUILD, MD_K_CHAIN = 0, 1, 2, 3, 4
+MD_K_LOCAL, MD_K_FORCE, MD_K_BONDED, MD_K_REBUILD, MD_K_CHAIN, MD_K_RECIP = 0, 1, 2, 3, 4, 5
 PHASE = {"J1": 2, "J2": 3, "C1": 4, "C2": 5}
 
 _dp = C.POINTER(C.c_double)
@@ -40,7 +40,8 @@ class MDSystem(C.Structure):
 class MDSplit(C.Structure):
     _fields_ = [("r_s", C.c_double), ("r_c", C.c_double), ("switch_width", C.c_double),
                 ("skin", C.c_double), ("coulomb_alpha", C.c_double),
-                ("n_rings", C.c_int32), ("ring_width", C.c_double)]
+                ("n_rings", C.c_int32), ("ring_width", C.c_double),
+                ("coulomb_kind", C.c_int32), ("ewald_kmax", C.c_int32)]
 
 
 class MDParams(C.Structure):
@@ -49,7 +50,7 @@ class MDParams(C.Structure):
                 ("precision", C.c_int32), ("rebuild_every", C.c_int32), ("respa_inner", C.c_int32),
                 ("log_events", C.c_int32), ("strict_bounds", C.c_int32), ("chain_lanes", C.c_int32),
                 ("graph_steps", C.c_int32), ("bound_scale", C.c_double), ("row_capacity", C.c_double),
-                ("event_capacity", C.c_int64), ("chain_order", C.c_int32)]
+                ("event_capacity", C.c_int64), ("chain_order", C.c_int32), ("respa_outer", C.c_int32)]
 
 
 class MDObs(C.Structure):
@@ -57,7 +58,8 @@ class MDObs(C.Structure):
                 ("pe_short", C.c_double), ("pe_long", C.c_double), ("pe_bonded", C.c_double),
                 ("n_prop", C.c_int64), ("n_acc", C.c_int64), ("n_bound_viol", C.c_int64),
                 ("n_rebuilds", C.c_int64), ("n_zsampler_overflow", C.c_int64),
-                ("n_list_errors", C.c_int64), ("event_hash", C.c_uint64), ("n_regrows", C.c_int64)]
+                ("n_list_errors", C.c_int64), ("event_hash", C.c_uint64), ("n_regrows", C.c_int64),
+                ("pe_recip", C.c_double)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -113,7 +115,7 @@ class MDEvent(C.Structure):
 
 
 EXPORTS = ["md_create", "md_destroy", "md_last_error", "md_step_baoab", "md_step_jump",
-           "md_step_jump_respa", "md_step_baoab_respa", "md_observables", "md_sync", "md_get_state",
+           "md_step_jump_respa", "md_step_baoab_respa", "md_step_jump_respa1", "md_step_baoab_respa1", "md_observables", "md_sync", "md_get_state",
            "md_set_state", "md_get_accel", "md_get_atom_stats", "md_get_events", "md_rdf", "md_rdf_noalloc",
            "md_get_cand_row", "md_get_row_counts", "md_run_phase", "md_profile", "md_profile_read",
            "md_counters", "md_theta_screen_error", "md_tune"]
@@ -149,7 +151,8 @@ def load():
     L.md_destroy.restype = None
     L.md_last_error.argtypes = [C.c_void_p]
     L.md_last_error.restype = C.c_char_p
-    for fn in ("md_step_baoab", "md_step_jump", "md_step_jump_respa", "md_step_baoab_respa"):
+    for fn in ("md_step_baoab", "md_step_jump", "md_step_jump_respa", "md_step_baoab_respa",
+               "md_step_jump_respa1", "md_step_baoab_respa1"):
         getattr(L, fn).argtypes = [C.c_void_p, C.c_int64]
     L.md_observables.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(MDObs)]
     L.md_sync.argtypes = [C.c_void_p]
@@ -263,7 +266,8 @@ def _marshal_system(system):
 
 def _marshal_split(split):
     return MDSplit(split.r_s, split.r_c, split.switch_width, split.skin, split.coulomb_alpha,
-                   split.n_rings, split.ring_width)
+                   split.n_rings, split.ring_width, getattr(split, "coulomb_kind", 0),
+                   getattr(split, "ewald_kmax", 0))
 
 
 def _marshal_params(params):
@@ -272,7 +276,7 @@ def _marshal_params(params):
                     params.log_events, params.strict_bounds, getattr(params, "chain_lanes", 0),
                     getattr(params, "graph_steps", 0), getattr(params, "bound_scale", 0.0),
                     getattr(params, "row_capacity", 0.0), getattr(params, "event_capacity", 0),
-                    getattr(params, "chain_order", 0))
+                    getattr(params, "chain_order", 0), getattr(params, "respa_outer", 1))
 
 
 def _allocator(allocator):
@@ -355,6 +359,12 @@ class Sim:
 
     def step_jump_respa(self, n):
         self._chk(load().md_step_jump_respa(self._h, n))
+
+    def step_jump_respa1(self, n):
+        self._chk(load().md_step_jump_respa1(self._h, n))
+
+    def step_baoab_respa1(self, n):
+        self._chk(load().md_step_baoab_respa1(self._h, n))
 
     def step_baoab_respa(self, n):
         self._chk(load().md_step_baoab_respa(self._h, n))

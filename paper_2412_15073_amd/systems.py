@@ -63,6 +63,8 @@ class Split:
     coulomb_alpha: float = 0.0
     n_rings: int = 1
     ring_width: float = 0.0
+    coulomb_kind: int = 0     # 0: damped shifted-force Coulomb; 1: the same plus the Ewald reciprocal sum
+    ewald_kmax: int = 0       # Ewald: lattice vectors n with 0 < |n|^2 <= kmax^2
 
 
 @dataclass
@@ -75,6 +77,7 @@ class Params:
     jump_coul: int = JUMP_NONE
     eps: float = 1.0
     respa_inner: int = 1
+    respa_outer: int = 1      # middle steps per outer step of the three-level RESPA schemes
     rebuild_every: int = 0
     log_events: int = 0
     precision: int = FP64

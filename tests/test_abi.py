@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_2412_15073_amd", "libjumpmd.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(md_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(md_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
