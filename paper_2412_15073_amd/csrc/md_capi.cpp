@@ -47,6 +47,7 @@ struct md_ctx {
   bool frec_valid = false;     // frec holds the reciprocal-space forces at the current positions
   bool flong_valid = false;    // flong holds the long real-space forces at the current positions
   double2 *d_spart = nullptr, *d_sfac = nullptr;   // Ewald partial and total structure factors
+  double4 *d_fpart = nullptr;                       // Ewald partial forces per k-range
   double ew_ecoef = 0.0, ew_self = 0.0;            // Ewald energy prefactor (half space), self energy
   int rows_valid = 0;          // ROW_* bits valid for the current reference positions
   int64_t since_build = 0;
@@ -418,7 +419,7 @@ static int eval_recip(md_ctx *c) {
   if (!c->ewald) return MD_OK;
   hipEvent_t e0{};
   prof_begin(c, MD_K_RECIP, &e0);
-  HIPCHK(c, launch_recip(c->V, Xcur(c), c->d_spart, c->d_sfac, c->stream));
+  HIPCHK(c, launch_recip(c->V, Xcur(c), c->d_spart, c->d_sfac, c->d_fpart, c->stream));
   prof_end(c, MD_K_RECIP, e0);
   c->frec_valid = true;
   return MD_OK;
@@ -881,6 +882,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   }
   // Ewald reciprocal sum: k-vectors of the half space with 0 < |n|^2 <= kmax^2
   std::vector<double4> kv;
+  std::vector<int4> kn;
   c->ewald = sp->coulomb_kind == MD_COUL_EWALD;
   if (c->ewald) {
     const int K = sp->ewald_kmax;
@@ -895,8 +897,12 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
           const double kx = 2.0 * M_PI * nx / L[0], ky = 2.0 * M_PI * ny / L[1], kz = 2.0 * M_PI * nz / L[2];
           const double k2 = kx * kx + ky * ky + kz * kz;
           kv.push_back(make_double4(kx, ky, kz, std::exp(-k2 / (4.0 * V.alpha * V.alpha)) / k2));
+          const bool first = kn.empty() || kn.back().x != nx || kn.back().y != ny;
+          kn.push_back(make_int4(nx, ny, nz, first ? 1 : 0));
         }
     V.nk = (int)kv.size();
+    V.kmax = K;
+    ewald_ranges(n, V.nk, K, V.ew_ranges, V.ew_apb, V.ew_ta, V.ew_krange);
     V.ew_fcoef = 2.0 * 4.0 * M_PI * V.ke / vol;
     c->ew_ecoef = 2.0 * 2.0 * M_PI * V.ke / vol;
     double q2 = 0.0;
@@ -905,8 +911,12 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
     double4 *d_kv;
     A(d_kv, kv.size());
     V.kvec = d_kv;
+    int4 *d_kn;
+    A(d_kn, kn.size());
+    V.kint = d_kn;
     A(V.frec, n); A(V.flong, n);
-    A(c->d_spart, (size_t)((n + 255) / 256) * kv.size());
+    A(c->d_spart, (size_t)V.ew_ranges * kv.size());
+    A(c->d_fpart, (size_t)((V.nk + V.ew_krange - 1) / V.ew_krange) * n);
     A(c->d_sfac, kv.size());
   }
   c->scratch_n = std::max<size_t>(4 * (size_t)n + (size_t)s->n_bonds + (size_t)s->n_angles, 4096);
@@ -964,7 +974,10 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   up(d_at0, s->angle_t0, sizeof(double) * s->n_angles);
   up(c->d_rep_off, c->rep_off.data(), sizeof(int) * (nrep + 1));
   up(d_chain_perm, chain_perm.data(), sizeof(int) * chain_perm.size());
-  if (c->ewald) up((void *)V.kvec, kv.data(), sizeof(double4) * kv.size());
+  if (c->ewald) {
+    up((void *)V.kvec, kv.data(), sizeof(double4) * kv.size());
+    up((void *)V.kint, kn.data(), sizeof(int4) * kn.size());
+  }
   c->fuse_forces[0] = force_fused_fits(V, 0);
   c->fuse_forces[1] = force_fused_fits(V, 1);
   {

@@ -487,7 +487,9 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       finish();
     }
     // wave-synchronous refill: every atom tops up as many slots as are free
-    // (at most G, one per lane); an atom below G takes G since M >= 2G
+    // (at most G, one per lane); an atom below G takes G since M >= 2G. The
+    // candidate gathers (row entries, then positions) are issued before the
+    // work that needs no memory, so that it overlaps them.
     if (__any(live && computed - w0 < G)) {
       wave_lds_sync();   // reads of the slots being replaced are complete
       const int free_slots = M - (computed - w0);
@@ -501,25 +503,13 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         int pb, pf, sb, sf;
         T.template pick2<seg_el_in_lds(G)>(V, u01(uw.w[2]), adaptive, pb, ellb, sb, pf, ellf, sf);
         const int eb = row[pb], ef = row[pf];
-        const int jb = row_j(eb), jf = row_j(ef);
-        const double4 xb = X[jb], xf = X[jf];
-        const int lb = jb - i0, lf = jf - i0;   // partners lie in the atom's own replica
-        u32x4 zw;
-        if (mrz) zw = draw4w(V.seed, rep, op.rstep, li, (uint64_t)(uint32_t)op.rphase | (1ull << 24), k);
         ring[RF_E * M + sl] = (R)(-log(u01(uw.w[0])));
         pwords[sl] = make_uint2(uw.w[1], uw.w[3]);
-        double Fx, Fy, Fz;
-        // segment sg = b * nr + ring: the partner's type without a load
-        long_grad<PREC>(V, xi, xb, a, (int)(((double)sb + 0.5) * inv_nr), comp, L, iL, img, eb, Fx, Fy, Fz);
-        ring[RF_BX * M + sl] = (R)Fx; ring[RF_BY * M + sl] = (R)Fy; ring[RF_BZ * M + sl] = (R)Fz;
         ring[RF_BL * M + sl] = (R)ellb;
-        if (adaptive) {
-          long_grad<PREC>(V, xi, xf, a, 0, 1, L, iL, img, ef, Fx, Fy, Fz);
-          ring[RF_FX * M + sl] = (R)Fx; ring[RF_FY * M + sl] = (R)Fy; ring[RF_FZ * M + sl] = (R)Fz;
-          ring[RF_FL * M + sl] = (R)ellf;
-        }
-        jring[sl] = make_int2(lb, lf);   // replica-local indices (event hash)
+        if (adaptive) ring[RF_FL * M + sl] = (R)ellf;
+        // the first Z iteration's uniforms, while the row entries are in flight
         if (mrz) {
+          const u32x4 zw = draw4w(V.seed, rep, op.rstep, li, (uint64_t)(uint32_t)op.rphase | (1ull << 24), k);
           const R zu2 = (R)u01(zw.w[2]);
           if (kZPre) {
             const ZPre<R> zp = z_pre<R>((R)u01(zw.w[0]), (R)u01(zw.w[1]), zu2);
@@ -530,6 +520,17 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
           ring[RF_ZU2 * M + sl] = zu2;
           zwords[sl] = make_uint2(zw.w[0], zw.w[3]);
         }
+        const int jb = row_j(eb), jf = row_j(ef);
+        const double4 xb = X[jb], xf = X[jf];
+        double Fx, Fy, Fz;
+        // segment sg = b * nr + ring: the partner's type without a load
+        long_grad<PREC>(V, xi, xb, a, (int)(((double)sb + 0.5) * inv_nr), comp, L, iL, img, eb, Fx, Fy, Fz);
+        ring[RF_BX * M + sl] = (R)Fx; ring[RF_BY * M + sl] = (R)Fy; ring[RF_BZ * M + sl] = (R)Fz;
+        if (adaptive) {
+          long_grad<PREC>(V, xi, xf, a, 0, 1, L, iL, img, ef, Fx, Fy, Fz);
+          ring[RF_FX * M + sl] = (R)Fx; ring[RF_FY * M + sl] = (R)Fy; ring[RF_FZ * M + sl] = (R)Fz;
+        }
+        jring[sl] = make_int2(jb - i0, jf - i0);   // replica-local indices (event hash)
       }
       computed += take;
       cs = ring_add(cs, take, M);

@@ -149,8 +149,11 @@ struct MDView {
   int ncell_total;
   int qimg;                             // row builder queue slots of replicas with explicit images (0: none)
   // Ewald reciprocal sum (one replica): k-vectors of the half space, w = exp(-k^2/(4 alpha^2)) / k^2
-  const double4 *kvec;                  // [nk] (kx, ky, kz, w)
-  int nk;
+  const double4 *kvec;                  // [nk] (kx, ky, kz, w), ordered by (nx, ny, nz)
+  const int4 *kint;                     // [nk] (nx, ny, nz, 1 if the first of its (nx, ny) column)
+  int nk, kmax;
+  int ew_ranges, ew_apb, ew_ta;         // structure factor: atom ranges of ew_apb atoms (partials per range), tiles of ew_ta
+  int ew_krange;                        // reciprocal forces: k-vectors per range (partials per range)
   double ew_fcoef;                      // force prefactor 2 * 4 pi k_e / V (k and -k together)
   // neighbour rows (row-major, fixed capacity)
   int cap_s, cap_f, cap_c;

@@ -39,6 +39,8 @@ hipError_t rdf_scratch_setup(int dev);            // once per device, that devic
 unsigned long long *rdf_scratch_ptr(int dev);     // device address of the static scratch on dev
 hipError_t launch_rdf_noalloc(const MDView &V, const double4 *X, const int *rep_off, int ta, int tb, double rmax,
                               int nbins, unsigned long long *sp, hipStream_t s);
-hipError_t launch_recip(const MDView &V, const double4 *X, double2 *part, double2 *S, hipStream_t s);
+hipError_t launch_recip(const MDView &V, const double4 *X, double2 *part, double2 *S, double4 *fpart,
+                        hipStream_t s);
+void ewald_ranges(int n, int nk, int kmax, int &ranges, int &apb, int &ta, int &krange);
 hipError_t launch_ewald_energy(const MDView &V, const double4 *X, double2 *part, double2 *S, double *e,
                                hipStream_t s);

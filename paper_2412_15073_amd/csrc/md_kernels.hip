@@ -14,6 +14,7 @@
 //              they fit the same round).
 //  k_bonded    bonds and angles, per atom over its incident terms.
 //  observables: kinetic energy, pair energies, pair histograms.
+#include <algorithm>
 #include <mutex>
 
 #include "md_device.h"
@@ -822,34 +823,70 @@ __global__ void k_count_pairs(MDView V, const double4 *__restrict__ X, int which
 // plus, for every excluded pair, the force of -k_e q_i q_j erf(alpha r) / r
 // (their real-space term is left out, so their reciprocal-space interaction
 // is taken back).
-// Partial structure factors: block (kb, t) stages atom tile t (256 atoms,
-// position and charge) in LDS; thread k sums its tile's terms.
+// Partial structure factors. Block (kc, ar) covers k-vectors
+// [kc * EW_KPB, (kc + 1) * EW_KPB), EW_KPT per thread, and the atoms of range
+// ar in tiles of V.ew_ta atoms (at most EW_TA). For each tile the block tabulates in LDS the factors
+// e^{i 2 pi m x / L_x} (m = 0..K) and e^{i 2 pi m y / L_y}, e^{i 2 pi m z / L_z}
+// (m = -K..K) of every atom, so that each (atom, k) term is a product of three
+// table entries instead of a sine and a cosine of its own.
+constexpr int EW_TA = 16, EW_KPT = 4, EW_KPB = 256 * EW_KPT;
+static size_t ewald_lds_bytes(int kmax, int ta) { return sizeof(double2) * ta * (5 * kmax + 3) + sizeof(double) * ta; }
 __global__ __launch_bounds__(256) void k_sfac(MDView V, const double4 *__restrict__ X, double2 *__restrict__ part) {
-  __shared__ double4 xs[256];
-  const int t = blockIdx.y, k = blockIdx.x * 256 + threadIdx.x;
-  const int i0 = t * 256, ia = i0 + threadIdx.x;
-  xs[threadIdx.x] = ia < V.n ? X[ia] : make_double4(0.0, 0.0, 0.0, 0.0);
-  __syncthreads();
-  if (k >= V.nk) return;
-  const double4 kv = V.kvec[k];
-  const int m = min(256, V.n - i0);
-  double sr = 0.0, si = 0.0;
-  for (int j = 0; j < m; ++j) {
-    const double4 x = xs[j];
-    double sn, cs;
-    sincos(kv.x * x.x + kv.y * x.y + kv.z * x.z, &sn, &cs);
-    sr += x.w * cs;
-    si += x.w * sn;
+  extern __shared__ double2 ew_tab[];   // ew_ta atoms x (5K + 3) factors, then their charges
+  const int K = V.kmax, W = 5 * K + 3, TA = V.ew_ta;
+  double *qs = (double *)(ew_tab + TA * W);
+  const double iL[3] = {1.0 / V.box[0], 1.0 / V.box[1], 1.0 / V.box[2]};
+  int ox[EW_KPT], oy[EW_KPT], oz[EW_KPT];
+  double sr[EW_KPT], si[EW_KPT];
+#pragma unroll
+  for (int j = 0; j < EW_KPT; ++j) {
+    const int k = blockIdx.x * EW_KPB + j * 256 + threadIdx.x;
+    const int4 nk = k < V.nk ? V.kint[k] : make_int4(0, 0, 0, 0);
+    ox[j] = nk.x; oy[j] = K + 1 + nk.y + K; oz[j] = 3 * K + 2 + nk.z + K;
+    sr[j] = 0.0; si[j] = 0.0;
   }
-  part[(size_t)t * V.nk + k] = make_double2(sr, si);
+  const int a0 = blockIdx.y * V.ew_apb, a1 = min(V.n, a0 + V.ew_apb);
+  for (int t0 = a0; t0 < a1; t0 += TA) {
+    const int na = min(TA, a1 - t0);
+    __syncthreads();   // the previous tile's reads are complete
+    for (int e = threadIdx.x; e < na * W; e += 256) {
+      const int at = e / W, m = e - at * W;
+      const double4 x = X[t0 + at];
+      double ph;   // phase / pi
+      if (m <= K) ph = 2.0 * m * x.x * iL[0];
+      else if (m <= 3 * K + 1) ph = 2.0 * (m - (2 * K + 1)) * x.y * iL[1];
+      else ph = 2.0 * (m - (4 * K + 2)) * x.z * iL[2];
+      double sn, cs;
+      sincospi(ph, &sn, &cs);
+      ew_tab[e] = make_double2(cs, sn);
+    }
+    if ((int)threadIdx.x < na) qs[threadIdx.x] = X[t0 + threadIdx.x].w;
+    __syncthreads();
+    for (int at = 0; at < na; ++at) {
+      const double q = qs[at];
+      const double2 *ta = ew_tab + at * W;
+#pragma unroll
+      for (int j = 0; j < EW_KPT; ++j) {
+        const double2 cx = ta[ox[j]], cy = ta[oy[j]], cz = ta[oz[j]];
+        const double xr = cx.x * cy.x - cx.y * cy.y, xi = cx.x * cy.y + cx.y * cy.x;
+        sr[j] += q * (xr * cz.x - xi * cz.y);
+        si[j] += q * (xr * cz.y + xi * cz.x);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < EW_KPT; ++j) {
+    const int k = blockIdx.x * EW_KPB + j * 256 + threadIdx.x;
+    if (k < V.nk) part[(size_t)blockIdx.y * V.nk + k] = make_double2(sr[j], si[j]);
+  }
 }
 
-// S(k) = sum over tiles in tile order (deterministic)
-__global__ void k_sfac_sum(MDView V, const double2 *__restrict__ part, int ntiles, double2 *__restrict__ S) {
+// S(k) = sum over atom ranges in range order (deterministic)
+__global__ void k_sfac_sum(MDView V, const double2 *__restrict__ part, double2 *__restrict__ S) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= V.nk) return;
   double sr = 0.0, si = 0.0;
-  for (int t = 0; t < ntiles; ++t) {
+  for (int t = 0; t < V.ew_ranges; ++t) {
     const double2 p = part[(size_t)t * V.nk + k];
     sr += p.x;
     si += p.y;
@@ -857,29 +894,61 @@ __global__ void k_sfac_sum(MDView V, const double2 *__restrict__ part, int ntile
   S[k] = make_double2(sr, si);
 }
 
-// reciprocal-space forces, one atom per thread; k-vectors and S(k) staged in LDS
+// Reciprocal-space forces. Block (ab, kr) covers 256 atoms, one per lane,
+// and k-range kr of V.ew_krange k-vectors, staged in LDS with S(k); the
+// block writes the range's partial forces (summed in range order by
+// k_recip_sum). Along a column (nx, ny fixed, nz rising by one) e^{i k.x}
+// advances by the factor e^{i 2 pi z / L_z}; the first k-vector of each
+// column, and of each range, takes its sine and cosine directly.
 __global__ __launch_bounds__(256) void k_recip_force(MDView V, const double4 *__restrict__ X,
-                                                     const double2 *__restrict__ S) {
+                                                     const double2 *__restrict__ S, double4 *__restrict__ fpart) {
   __shared__ double4 ks[256];
   __shared__ double2 ss[256];
+  __shared__ int fs[256];
   const int i = blockIdx.x * 256 + threadIdx.x;
+  const int kb = blockIdx.y * V.ew_krange, ke = min(V.nk, kb + V.ew_krange);
   const double4 xi = i < V.n ? X[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+  double ezs, ezc;
+  sincospi(2.0 * xi.z / V.box[2], &ezs, &ezc);
+  double er = 1.0, ei = 0.0;   // e^{i k.x} of the current k-vector
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  for (int k0 = 0; k0 < V.nk; k0 += 256) {
+  for (int k0 = kb; k0 < ke; k0 += 256) {
     __syncthreads();
-    if (k0 + (int)threadIdx.x < V.nk) { ks[threadIdx.x] = V.kvec[k0 + threadIdx.x]; ss[threadIdx.x] = S[k0 + threadIdx.x]; }
+    if (k0 + (int)threadIdx.x < ke) {
+      ks[threadIdx.x] = V.kvec[k0 + threadIdx.x];
+      ss[threadIdx.x] = S[k0 + threadIdx.x];
+      fs[threadIdx.x] = V.kint[k0 + threadIdx.x].w || k0 + (int)threadIdx.x == kb;
+    }
     __syncthreads();
-    const int m = min(256, V.nk - k0);
+    const int m = min(256, ke - k0);
     for (int q = 0; q < m; ++q) {
       const double4 kv = ks[q];
       const double2 sq = ss[q];
-      double sn, cs;
-      sincos(kv.x * xi.x + kv.y * xi.y + kv.z * xi.z, &sn, &cs);
-      const double a = kv.w * (sq.x * sn - sq.y * cs);
+      if (fs[q]) {
+        sincos(kv.x * xi.x + kv.y * xi.y + kv.z * xi.z, &ei, &er);
+      } else {
+        const double t = er * ezc - ei * ezs;
+        ei = er * ezs + ei * ezc;
+        er = t;
+      }
+      const double a = kv.w * (sq.x * ei - sq.y * er);
       fx += a * kv.x; fy += a * kv.y; fz += a * kv.z;
     }
   }
+  if (i < V.n) fpart[(size_t)blockIdx.y * V.n + i] = make_double4(fx, fy, fz, 0.0);
+}
+
+// Forces = prefactor x (sum of the k-range partials in range order), plus,
+// for every excluded pair, the force of -k_e q_i q_j erf(alpha r) / r
+__global__ void k_recip_sum(MDView V, const double4 *__restrict__ X, const double4 *__restrict__ fpart, int nkr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= V.n) return;
+  const double4 xi = X[i];
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  for (int t = 0; t < nkr; ++t) {
+    const double4 p = fpart[(size_t)t * V.n + i];
+    fx += p.x; fy += p.y; fz += p.z;
+  }
   const double c = V.ew_fcoef * xi.w;
   fx *= c; fy *= c; fz *= c;
   if (V.xptr) {
@@ -1109,24 +1178,45 @@ hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, h
   return hipGetLastError();
 }
 
-// reciprocal-space forces into V.frec; part: [ceil(n/256) * nk] partial sums, S: [nk]
-hipError_t launch_recip(const MDView &V, const double4 *X, double2 *part, double2 *S, hipStream_t s) {
-  const int ntiles = (V.n + 255) / 256;
-  hipLaunchKernelGGL(k_sfac, dim3((V.nk + 255) / 256, ntiles), dim3(256), 0, s, V, X, part);
+// structure factors into S ([nk]) through the partials part ([ew_ranges * nk])
+static hipError_t launch_sfac(const MDView &V, const double4 *X, double2 *part, double2 *S, hipStream_t s) {
+  const size_t lds = ewald_lds_bytes(V.kmax, V.ew_ta);
+  hipLaunchKernelGGL(k_sfac, dim3((V.nk + EW_KPB - 1) / EW_KPB, V.ew_ranges), dim3(256), lds, s, V, X, part);
   CHK(hipGetLastError());
-  hipLaunchKernelGGL(k_sfac_sum, dim3((V.nk + 255) / 256), dim3(256), 0, s, V, part, ntiles, S);
+  hipLaunchKernelGGL(k_sfac_sum, dim3((V.nk + 255) / 256), dim3(256), 0, s, V, part, S);
+  return hipGetLastError();
+}
+
+// atom tile of the structure-factor launch (its tables within 60 KiB of LDS)
+// and atom ranges: enough blocks to cover the device about four times over,
+// each range a whole number of tiles
+void ewald_ranges(int n, int nk, int kmax, int &ranges, int &apb, int &ta, int &krange) {
+  ta = std::max(1, std::min(EW_TA, (60 * 1024 - 8 * EW_TA) / (16 * (5 * kmax + 3))));
+  const int kc = (nk + EW_KPB - 1) / EW_KPB;
+  const int tiles = (n + ta - 1) / ta;
+  ranges = std::max(1, std::min(tiles, (1024 + kc - 1) / kc));
+  apb = ((tiles + ranges - 1) / ranges) * ta;
+  ranges = (n + apb - 1) / apb;
+  // force launch: k-ranges of whole 256-vector chunks, about 1024 blocks in all
+  const int ab = (n + 255) / 256, chunks = (nk + 255) / 256;
+  const int nkr = std::max(1, std::min(chunks, (1024 + ab - 1) / ab));
+  krange = ((chunks + nkr - 1) / nkr) * 256;
+}
+
+// reciprocal-space forces into V.frec; fpart: [ceil(nk / ew_krange) * n] partial forces
+hipError_t launch_recip(const MDView &V, const double4 *X, double2 *part, double2 *S, double4 *fpart,
+                        hipStream_t s) {
+  CHK(launch_sfac(V, X, part, S, s));
+  const int nkr = (V.nk + V.ew_krange - 1) / V.ew_krange;
+  hipLaunchKernelGGL(k_recip_force, dim3((V.n + 255) / 256, nkr), dim3(256), 0, s, V, X, S, fpart);
   CHK(hipGetLastError());
-  hipLaunchKernelGGL(k_recip_force, dim3((V.n + 255) / 256), dim3(256), 0, s, V, X, S);
+  hipLaunchKernelGGL(k_recip_sum, dim3((V.n + 255) / 256), dim3(256), 0, s, V, X, fpart, nkr);
   return hipGetLastError();
 }
 
 hipError_t launch_ewald_energy(const MDView &V, const double4 *X, double2 *part, double2 *S, double *e,
                                hipStream_t s) {
-  const int ntiles = (V.n + 255) / 256;
-  hipLaunchKernelGGL(k_sfac, dim3((V.nk + 255) / 256, ntiles), dim3(256), 0, s, V, X, part);
-  CHK(hipGetLastError());
-  hipLaunchKernelGGL(k_sfac_sum, dim3((V.nk + 255) / 256), dim3(256), 0, s, V, part, ntiles, S);
-  CHK(hipGetLastError());
+  CHK(launch_sfac(V, X, part, S, s));
   hipLaunchKernelGGL(k_ewald_energy, dim3((V.nk + V.n + 255) / 256), dim3(256), 0, s, V, X, S, e);
   return hipGetLastError();
 }

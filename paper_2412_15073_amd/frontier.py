@@ -13,6 +13,13 @@ within 1e-2 (L2 over bins), D within 5 % of BAOAB. Prints one JSON line per
 point (and per reference), so that a long grid can be run in pieces.
 
     python -m paper_2412_15073_amd.frontier --rs 5,7,9 --eps0 0.003,0.01,0.03,0.1 --seeds 7,8
+
+The reference runs (FP64 BAOAB at 1 fs, and at 0.5 fs as a check of the
+1 fs reference's own time-step error) are printed first. `--summarize`
+reads such JSON lines back (from any number of logs) and prints the table
+of every point against the 1 fs reference, with the targets met or not:
+
+    python -m paper_2412_15073_amd.frontier --summarize log1 log2 ...
 """
 import argparse
 import json
@@ -70,7 +77,12 @@ def main():
     ap.add_argument("--skin", type=float, default=0.5)
     ap.add_argument("--rings", type=int, default=12)
     ap.add_argument("--no-reference", action="store_true")
+    ap.add_argument("--ref-dt", default="1.0,0.5", help="time steps (fs) of the FP64 BAOAB references")
+    ap.add_argument("--summarize", nargs="+", metavar="LOG", help="summarise logs of earlier runs and exit")
     a = ap.parse_args()
+    if a.summarize:
+        summarize(a.summarize)
+        return
 
     seeds = [int(x) for x in a.seeds.split(",")]
     split_eq = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=1.0, n_rings=a.rings)
@@ -83,14 +95,17 @@ def main():
 
     def measure(split, pa, scheme):
         per = []
+        step_fs = pa.dt * 1e3
+        n_run = int(round(a.ps / (step_fs * 1e-3)))
+        every = max(1, int(round(a.every / step_fs)))
         for s in seeds:
             p = S.Params(**{**pa.__dict__, "seed": s + 100})
             sim = jumpmd.Sim(starts[s], split, p)
             fn = sim.step_jump if scheme == "jump" else sim.step_baoab
-            T, frames, counts = sample(sim, fn, n_steps, a.every, o_idx, r_max, n_bins)
+            T, frames, counts = sample(sim, fn, n_run, every, o_idx, r_max, n_bins)
             sim.close()
             _, g = analysis.rdf_from_counts(counts, n_o, n_o, L ** 3, r_max, True, len(T))
-            D, dD = analysis.block_diffusion(frames, a.every * 1e-3, n_blocks=4)
+            D, dD = analysis.block_diffusion(frames, every * step_fs * 1e-3, n_blocks=4)
             per.append({"T": float(T.mean()), "g": g, "D": D, "D_err": dD})
         pt = dict(pa.__dict__)
         pt["graph_steps"] = 20
@@ -102,10 +117,12 @@ def main():
 
     if not a.no_reference:
         split_b = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=1.0, n_rings=a.rings)
-        per, ms = measure(split_b, S.water_params(jumps=False), "baoab")
-        print(json.dumps({"point": "baoab_fp64", "ms_per_step": ms, "ns_per_day": 86.4 / ms,
-                          "per_seed": [{"T": q["T"], "D": q["D"], "D_err": q["D_err"], "g": q["g"].tolist()}
-                                       for q in per]}), flush=True)
+        for dt_fs in [float(x) for x in a.ref_dt.split(",")]:
+            per, ms = measure(split_b, S.water_params(dt=dt_fs * 1e-3, jumps=False), "baoab")
+            print(json.dumps({"point": "baoab_fp64", "dt_fs": dt_fs, "ms_per_step": ms,
+                              "ns_per_day": 86.4 * dt_fs / ms, "r_max": r_max,
+                              "per_seed": [{"T": q["T"], "D": q["D"], "D_err": q["D_err"], "g": q["g"].tolist()}
+                                           for q in per]}), flush=True)
 
     for rs in [float(x) for x in a.rs.split(",")]:
         for eps0 in [float(x) for x in a.eps0.split(",")]:
@@ -114,10 +131,61 @@ def main():
             pa.precision = S.FP32_MIXED
             t0 = time.perf_counter()
             per, ms = measure(split, pa, "jump")
-            print(json.dumps({"point": "jump_fp32", "r_s": rs, "eps0": eps0, "ms_per_step": ms,
+            print(json.dumps({"point": "jump_fp32", "r_s": rs, "eps0": eps0, "dt_fs": 1.0, "ms_per_step": ms,
                               "ns_per_day": 86.4 / ms, "wall_s": time.perf_counter() - t0,
                               "per_seed": [{"T": q["T"], "D": q["D"], "D_err": q["D_err"], "g": q["g"].tolist()}
                                            for q in per]}), flush=True)
+
+
+TARGETS = {"T_rel": 0.01, "rdf_l2": 1e-2, "D_rel": 0.05}
+
+
+def _combine(point):
+    """Mean over seeds: T, g, D, and the standard error of D (block errors
+    of each seed combined with the spread between seeds)."""
+    per = point["per_seed"]
+    T = float(np.mean([q["T"] for q in per]))
+    g = np.mean([q["g"] for q in per], axis=0)
+    Ds = np.array([q["D"] for q in per])
+    e_block = np.sqrt(np.sum([q["D_err"] ** 2 for q in per])) / len(per)
+    e_seed = Ds.std(ddof=1) / np.sqrt(len(Ds)) if len(Ds) > 1 else 0.0
+    return T, g, float(Ds.mean()), float(max(e_block, e_seed))
+
+
+def summarize(logs):
+    pts = []
+    for f in logs:
+        with open(f) as fh:
+            for line in fh:
+                line = line.strip()
+                if line.startswith("{") and '"point"' in line:
+                    pts.append(json.loads(line))
+    refs = {p["dt_fs"]: p for p in pts if p["point"] == "baoab_fp64"}
+    ref = refs.get(1.0)
+    assert ref is not None, "no 1 fs BAOAB reference in the logs"
+    T0, g0, D0, e0 = _combine(ref)
+    rows = []
+    for p in pts:
+        T, g, D, e = _combine(p)
+        dT = (T - T0) / T0
+        l2 = float(np.sqrt(np.mean((g - g0) ** 2)))
+        dD = (D - D0) / D0
+        ok = abs(dT) <= TARGETS["T_rel"] and l2 <= TARGETS["rdf_l2"] and abs(dD) <= TARGETS["D_rel"]
+        name = (f"BAOAB FP64 {p['dt_fs']:g} fs" if p["point"] == "baoab_fp64"
+                else f"JUMP FP32 r_s {p['r_s']:g} eps0 {p['eps0']:g}")
+        rows.append((name, p["ms_per_step"], p["ns_per_day"], T, dT, l2, D, e, dD, ok))
+    print(f"{'run':34s} {'ms/step':>8s} {'ns/day':>8s} {'T (K)':>8s} {'dT':>7s} {'RDF L2':>7s} "
+          f"{'D':>7s} {'+-':>6s} {'dD':>7s}  all targets")
+    for r in rows:
+        print(f"{r[0]:34s} {r[1]:8.4f} {r[2]:8.1f} {r[3]:8.2f} {100 * r[4]:6.2f}% {r[5]:7.4f} {r[6]:7.4f} "
+              f"{r[7]:6.4f} {100 * r[8]:6.1f}%  {'yes' if r[9] else 'no'}")
+    best = [r for r in rows if r[9] and r[0].startswith("JUMP")]
+    if best:
+        b = max(best, key=lambda r: r[2])
+        print(f"fastest JUMP point meeting all targets: {b[0]}, {b[2]:.1f} ns/day "
+              f"({b[2] / ref['ns_per_day']:.2f}x the 1 fs BAOAB reference)")
+    else:
+        print("no JUMP point meets all targets")
 
 
 if __name__ == "__main__":

@@ -66,3 +66,27 @@ def test_spectrum_peaks_at_the_oscillation_wavenumbers():
     # weights m a^2 / 2: 16 * 1 vs 1 * 4
     assert abs(b["bend"]["weight"] - 0.8) < 0.01 and abs(b["stretch"]["weight"] - 0.2) < 0.01
     assert b["above_stretch"]["weight"] < 1e-6
+
+
+def test_frontier_summary_names_the_fastest_point_within_targets(tmp_path, capsys):
+    """The frontier table: errors against the 1 fs reference, targets
+    (T 1 %, RDF L2 1e-2, D 5 %) and the fastest JUMP point meeting all."""
+    import json
+    from paper_2412_15073_amd import frontier
+    g = [1.0] * 10
+
+    def pt(point, ms, T, D, dg=0.0, **kw):
+        seeds = [{"T": T, "D": D, "D_err": 0.001, "g": [x + dg for x in g]} for _ in range(2)]
+        return json.dumps({"point": point, "ms_per_step": ms, "ns_per_day": 86.4 * kw.get("dt_fs", 1.0) / ms,
+                           "per_seed": seeds, **kw})
+    lines = [pt("baoab_fp64", 0.1, 300.0, 0.25, dt_fs=1.0),
+             pt("jump_fp32", 0.08, 301.0, 0.24, r_s=7.0, eps0=0.01, dt_fs=1.0),     # meets all, fastest
+             pt("jump_fp32", 0.05, 300.0, 0.10, r_s=5.0, eps0=0.1, dt_fs=1.0),      # D off by 60 %
+             pt("jump_fp32", 0.09, 300.5, 0.25, r_s=9.0, eps0=0.01, dt_fs=1.0),     # meets all, slower
+             pt("jump_fp32", 0.06, 300.0, 0.25, dg=0.05, r_s=6.0, eps0=0.03, dt_fs=1.0)]   # RDF off
+    f = tmp_path / "log"
+    f.write_text("noise\n" + "\n".join(lines) + "\n")
+    frontier.summarize([str(f)])
+    out = capsys.readouterr().out
+    assert "fastest JUMP point meeting all targets: JUMP FP32 r_s 7 eps0 0.01" in out
+    assert "1080.0 ns/day (1.25x" in out
