@@ -20,11 +20,13 @@ comparator, kernel split and roofline:
   water32000_respa 32000 waters (96000 atoms, 98.6 A), r_c = 12 A, JUMP-RESPA
                    (bonded forces every 1 fs, short forces and jumps every
                    3 fs) FP32-mixed vs FP64 BAOAB-RESPA with full forces;
-  water4096_ewald_respa1  the 4096-water box with Ewald electrostatics (damped
-                   real part to 10 A with alpha 0.35 A^-1, reciprocal sum to
-                   |n| <= 20): JUMP-RESPA1 at 1:2:6 fs (bonded 1 fs, short forces
-                   and jumps 2 fs, reciprocal forces 6 fs) FP32-mixed vs FP64
-                   BAOAB-RESPA1 at the same steps;
+  water4096_pme_respa1  the 4096-water box with the paper's Ewald settings
+                   for its 12 000-atom water (damped real part to 7 A with
+                   alpha 0.554 A^-1, jumps between r_s = 5 A (switch 0.5 A) and
+                   7 A, the reciprocal sum by particle-mesh Ewald on a 64^3
+                   mesh, order 6): JUMP-RESPA1 at 1:2:6 fs (bonded 1 fs, short
+                   forces and jumps 2 fs, reciprocal forces 6 fs) FP32-mixed vs
+                   FP64 BAOAB-RESPA1 at the same steps;
   lj864            864 LJ atoms (fcc, rho 0.8442, kT 0.722), B J A O A J B with
                    BPS jumps between r_s = 3 and r_c = 5 sigma, vs BAOAB, FP64
                    (reduced units: tau/day).
@@ -66,10 +68,13 @@ PEAK_HBM_GBS = 8000.0
 FLOP_PER_SHORT_PAIR = 78
 FLOP_PER_FULL_PAIR = 60
 FLOP_PER_PROPOSAL = 93
-#  an (atom, k-vector) pair of the Ewald reciprocal sum: structure factor
-#  (k.x, sin, cos, two fmas: 9 flops) and force (k.x, sin, cos, weight times
-#  the structure-factor combination, three fmas: 14 flops), 23 flops.
-FLOP_PER_ATOM_K = 23
+#  particle-mesh Ewald, per evaluation: spreading (a product of three
+#  weights per grid point, 3 flops) and gathering (three products and three
+#  fmas per grid point, 9 flops) over p^3 points per atom, plus two complex
+#  three-dimensional transforms of 5 N log2 N flops each and the influence
+#  function (6 flops per grid point).
+FLOP_PME_SPREAD_GATHER = 12
+FLOP_PME_POINT = 6
 BYTES_PER_ATOM_LOCAL = 7 * 32   # x (read+write), v (read+write), f_nb, f_b, x_ref reads
 # one row build: per atom, binning (x read, reference copy written, cell index
 # and slot), scatter (cell-ordered FP64 and FP32 position copies) and the
@@ -82,9 +87,10 @@ BYTES_PER_ROW_ENTRY = 4
 # sources (md_chain.hip, then md_device.h) starts with the given prefix.
 CHAIN_TRAFFIC = {}
 KERNELS = {0: "k_local (B/A/O updates)", 1: "k_force (pairs, with bonded when fused)", 2: "k_bonded (separate)",
-           3: "row rebuild", 4: "k_chain (J/C jump chains)", 5: "Ewald reciprocal (k_sfac, k_recip_force)"}
+           3: "row rebuild", 4: "k_chain (J/C jump chains)", 5: "reciprocal space (particle-mesh Ewald)"}
 METRIC = "ns/day & pair-interactions/s, JUMP vs full-force BAOAB, 1 MI355X, matched T/RDF/D"
-ALL_WORKLOADS = ("ensemble", "water4096", "water4096_fp32", "water32000_respa", "water4096_ewald_respa1", "lj864")
+ALL_WORKLOADS = ("ensemble", "water4096", "water4096_fp32", "water32000_respa", "water4096_pme_respa1", "lj864")
+PME = {"alpha": 0.554, "r_s": 5.0, "r_c": 7.0, "switch": 0.5, "grid": 64, "order": 6}
 
 
 def parse():
@@ -248,12 +254,12 @@ class Workload:
     def __init__(self, name, a, S):
         self.name = name
         self.respa = name == "water32000_respa"
-        self.respa1 = name == "water4096_ewald_respa1"
+        self.respa1 = name == "water4096_pme_respa1"
         self.lj = name == "lj864"
         self.ensemble = name == "ensemble"
         self.jump_prec = {"ensemble": 1, "water4096": 0, "water4096_fp32": 1, "water32000_respa": 1,
-                          "water4096_ewald_respa1": 1, "lj864": 0}[name]
-        self.rc = 12.0 if self.respa else 10.0
+                          "water4096_pme_respa1": 1, "lj864": 0}[name]
+        self.rc = 12.0 if self.respa else (PME["r_c"] if self.respa1 else 10.0)
         self.inner = 3 if self.respa else (2 if self.respa1 else 1)
         self.outer = 3 if self.respa1 else 1
         self.graph = 0 if (self.respa or self.respa1) else a.graph_steps
@@ -275,8 +281,9 @@ class Workload:
         if self.lj:
             return self.S.lj_split(skin=0.3)
         if self.respa1:
-            sp = self.S.water_split(r_s=5.0, r_c=self.rc, w=1.0, skin=skin, alpha=0.35, n_rings=self.a.rings)
-            sp.coulomb_kind, sp.ewald_kmax = 1, 20
+            sp = self.S.water_split(r_s=PME["r_s"], r_c=self.rc, w=PME["switch"], skin=skin, alpha=PME["alpha"],
+                                    n_rings=6)
+            sp.coulomb_kind, sp.pme_grid, sp.pme_order = self.S.COUL_SPME, (PME["grid"],) * 3, PME["order"]
             return sp
         return self.S.water_split(r_s=5.0, r_c=self.rc, w=1.0, skin=skin, n_rings=self.a.rings)
 
@@ -318,13 +325,14 @@ def set_state(sy, x, v):
         sy.pos, sy.vel = x, v
 
 
-def half_space_kvectors(kmax):
-    """Integer vectors n != 0 with |n|^2 <= kmax^2, one of each pair +-n."""
-    r = range(-kmax, kmax + 1)
-    return sum(1 for x in r for y in r for z in r if 0 < x * x + y * y + z * z <= kmax * kmax) // 2
+def pme_flops(n_atoms, grid, order):
+    """Algorithmic flops of one particle-mesh Ewald evaluation."""
+    import math
+    ng = grid ** 3
+    return (n_atoms * order ** 3 * FLOP_PME_SPREAD_GATHER + 2 * 5 * ng * math.log2(ng) + FLOP_PME_POINT * ng)
 
 
-def roofline(prof, steps_prof, props_prof, pairs_short, n_atoms, prec, build_bytes_prof=0.0, n_k=0):
+def roofline(prof, steps_prof, props_prof, pairs_short, n_atoms, prec, build_bytes_prof=0.0, pme_work=0.0):
     dom = max(prof, key=lambda k: prof[k][0])
     tot_ms, launches = prof[dom]
     avg_s = tot_ms * 1e-3 / max(launches, 1)
@@ -339,10 +347,11 @@ def roofline(prof, steps_prof, props_prof, pairs_short, n_atoms, prec, build_byt
         roof = {"bound": "alu", "achieved": work / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
                 "algorithmic": f"{FLOP_PER_SHORT_PAIR} flop/pair x {pairs_short} pairs/launch"}
     elif dom == 5:
-        # one evaluation: structure factors and forces over every (atom, k) pair, FP64
-        work = n_atoms * n_k * FLOP_PER_ATOM_K
+        # one evaluation: spreading, two transforms, influence function, gathering, FP64
+        work = pme_work
         roof = {"bound": "alu", "achieved": work / avg_s / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "algorithmic": f"{FLOP_PER_ATOM_K} flop x {n_atoms} atoms x {n_k} k-vectors per evaluation"}
+                "algorithmic": f"{work:.3g} flop per evaluation (spread/gather {FLOP_PME_SPREAD_GATHER} flop x "
+                               f"order^3 per atom, 2 transforms x 5 N log2 N, {FLOP_PME_POINT} flop per mesh point)"}
     elif dom == 3:
         # every step launches the displacement check; builds happen on some steps
         work = build_bytes_prof / max(launches, 1)
@@ -419,7 +428,7 @@ def run_workload(w, jumpmd, C, cache):
     # times the bytes of an average replica's build (short + candidate rows)
     builds = jp.observables()["n_rebuilds"] - nb0
     entries = int(jp.row_counts(0).sum()) + int(jp.row_counts(2).sum())
-    n_seg = (1 if w.lj else a.rings) * (1 if w.lj else 2)
+    n_seg = (1 if w.lj else split_j.n_rings) * (1 if w.lj else 2)
     build_bytes = builds / w.n_sys * (BYTES_PER_ATOM_BUILD * n_atoms + BYTES_PER_ROW_ENTRY * (entries + n_atoms * (n_seg + 1)))
     jp.close()
     unit = "tau/day" if w.lj else "ns/day"
@@ -462,8 +471,8 @@ def run_workload(w, jumpmd, C, cache):
             print(f"[bench] {w.name} BAOAB FP64 {ms_b:.4f} ms/step, {base['rate']:.1f} {unit}, "
                   f"T = {obs_b['temperature']:.1f}, {pairs_full} pairs", flush=True)
 
-    n_k = half_space_kvectors(split_j.ewald_kmax) if w.respa1 else 0
-    dom, roof = roofline(prof_j, a.profile_steps, props_prof, pairs_short, n_atoms, w.jump_prec, build_bytes, n_k)
+    pme_work = pme_flops(n_atoms, PME["grid"], PME["order"]) if w.respa1 else 0.0
+    dom, roof = roofline(prof_j, a.profile_steps, props_prof, pairs_short, n_atoms, w.jump_prec, build_bytes, pme_work)
     tr = CHAIN_TRAFFIC.get(w.name)
     if dom == 4 and tr and chain_source_hash().startswith(tr["sha256"]):
         roof["traffic"] = tr["bytes"]
@@ -484,12 +493,14 @@ def run_workload(w, jumpmd, C, cache):
         "kernel_ms_per_step": {KERNELS[k]: round(prof_j[k][0] / a.profile_steps, 5) for k in prof_j if prof_j[k][1]},
         "baoab_kernel_ms_per_step": base["kernel_ms_per_step"] if base else None,
         "roofline": roof,
-        "config": {"r_s": 3.0 if w.lj else 5.0, "r_c": 5.0 if w.lj else w.rc, "switch": 0.5 if w.lj else 1.0,
+        "config": {"r_s": 3.0 if w.lj else 5.0, "r_c": 5.0 if w.lj else w.rc,
+                   "switch": 0.5 if (w.lj or w.respa1) else 1.0,
                    "skin": 0.3 if w.lj else split_j.skin, "baoab_skin": base["skin"] if base else None,
                    "rings": 1 if w.lj else split_j.n_rings, "chain_lanes": pj.chain_lanes, "autotuned": tuned,
                    "respa_inner": w.inner if (w.respa or w.respa1) else None,
                    "respa_outer": w.outer if w.respa1 else None,
-                   "electrostatics": "Ewald (alpha 0.35, kmax 20)" if w.respa1 else (None if w.lj else "DSF (alpha 0.2)"),
+                   "electrostatics": (f"particle-mesh Ewald (alpha {PME['alpha']}, {PME['grid']}^3 mesh, order "
+                                      f"{PME['order']})" if w.respa1 else (None if w.lj else "DSF (alpha 0.2)")),
                    "dt": "0.005 tau" if w.lj else "1 fs", "graph_steps": pj.graph_steps,
                    "eps0_per_kcal_mol_A": None if w.lj else a.eps0,
                    "jumps": "LJ BPS" if w.lj else "LJ BPS + Coulomb adaptive MRZ"},

@@ -114,17 +114,25 @@ typedef struct {
   double r_s, r_c, switch_width, skin, coulomb_alpha;
   int32_t n_rings;
   double ring_width;
-  int32_t coulomb_kind;  /* MD_COUL_DSF or MD_COUL_EWALD */
+  int32_t coulomb_kind;  /* MD_COUL_DSF, MD_COUL_EWALD or MD_COUL_SPME */
   int32_t ewald_kmax;    /* Ewald: lattice vectors n with 0 < |n|^2 <= kmax^2 in the reciprocal sum */
+  int32_t pme_grid[3];   /* SPME: grid points per box edge, powers of two in [8, 256], >= pme_order */
+  int32_t pme_order;     /* SPME: cardinal B-spline order, 4, 6 or 8 */
 } md_split;
 
 /* electrostatics (md_split.coulomb_kind) */
 #define MD_COUL_DSF 0    /* damped shifted-force Coulomb out to r_c, nothing beyond */
 #define MD_COUL_EWALD 1  /* Ewald (Sec. 3.1): the same real-space term with coulomb_alpha, plus the
                             reciprocal-space sum over ewald_kmax (with the self term and the excluded
-                            pairs taken back); one replica only; schemes md_step_baoab (reciprocal
-                            forces in every kick) and the three-level md_step_jump_respa1 and
-                            md_step_baoab_respa1 */
+                            pairs taken back); one replica only; schemes md_step_baoab and
+                            md_step_jump (reciprocal forces in every kick or C' acceleration) and the
+                            three-level md_step_jump_respa1 and md_step_baoab_respa1 */
+#define MD_COUL_SPME 2   /* as MD_COUL_EWALD, with the reciprocal sum by smooth particle-mesh Ewald
+                            (Essmann et al. 1995; the paper's Tinker runs use it): charges spread
+                            with order-pme_order B-splines on the pme_grid mesh, three-dimensional
+                            transforms, the B-spline-corrected influence function, forces gathered
+                            with the B-spline derivatives; spreading sums with atomics, so results
+                            agree between runs to rounding, not bit for bit */
 
 /* Device memory for a context (md_create): alloc returns `bytes` of device
  * memory usable on `stream` (NULL on failure), release gives it back. Both
@@ -207,19 +215,22 @@ const char *md_last_error(const md_ctx *ctx);
 /* BAOAB with full-range forces (r < r_c): B A O A B (Sec. 2.3 without J). */
 int md_step_baoab(md_ctx *ctx, int64_t nsteps);
 /* JUMP: C' J' A O A J' C' (Sec. 2.3, 3.3): C' = short forces + Coulomb jumps
- * (plain B kick if jump_coul is NONE), J' = LJ jumps (skipped if NONE). */
+ * (plain B kick if jump_coul is NONE), J' = LJ jumps (skipped if NONE). With
+ * Ewald electrostatics the jumps act on the damped real-space long part and
+ * the C' acceleration also carries the reciprocal-space forces, evaluated
+ * every step (Sec. 3.1: everything not jumped is in the acceleration). */
 int md_step_jump(md_ctx *ctx, int64_t nsteps);
 /* JUMP-RESPA (Sec. 2.3.2, 3.3): bonded forces at dt, short non-bonded forces
  * and all jumps at respa_inner*dt. */
 int md_step_jump_respa(md_ctx *ctx, int64_t n_outer);
 /* BAOAB-RESPA comparator: full-range non-bonded kick at the outer step. */
 int md_step_baoab_respa(md_ctx *ctx, int64_t n_outer);
-/* JUMP-RESPA1 (Sec. 2.3.2, Sec. 3.3, Table 2; needs MD_COUL_EWALD): three
+/* JUMP-RESPA1 (Sec. 2.3.2, Sec. 3.3, Table 2; needs MD_COUL_EWALD or MD_COUL_SPME): three
  * levels, bonded forces at dt, short non-bonded forces and all jumps at
  * respa_inner*dt (the JUMP-RESPA step), reciprocal-space forces at
  * respa_outer*respa_inner*dt. n_outer outer steps. */
 int md_step_jump_respa1(md_ctx *ctx, int64_t n_outer);
-/* BAOAB-RESPA1 comparator (needs MD_COUL_EWALD): bonded forces at dt, short
+/* BAOAB-RESPA1 comparator (needs MD_COUL_EWALD or MD_COUL_SPME): bonded forces at dt, short
  * non-bonded chi U at respa_inner*dt, the long real-space part (1 - chi) U and
  * the reciprocal-space forces at respa_outer*respa_inner*dt. */
 int md_step_baoab_respa1(md_ctx *ctx, int64_t n_outer);
@@ -252,6 +263,21 @@ int md_get_events(md_ctx *ctx, md_event *buf, int64_t cap, int64_t *n);
 /* Pair histogram of types (ta, tb) over [0, r_max) in n_bins bins, pairs
  * inside each replica (minimum image), unordered when ta == tb. */
 int md_rdf(md_ctx *ctx, int32_t ta, int32_t tb, double r_max, int32_t n_bins, double *hist);
+/* Velocity trace for autocorrelation spectra (Sec. 4, Figs. 3-4: spectra at
+ * the level of the smallest time step). From this call on, every O update
+ * (once per smallest step in every scheme: mid-step of BAOAB and JUMP, every
+ * inner step of the RESPA schemes) records the velocities of atoms
+ * [0, n_atoms) into a ring of `capacity` records on the device (memory from
+ * the context's allocator); steps then run without HIP-graph replay.
+ * n_atoms = 0 stops tracing and frees the ring. Records count from 0 at each
+ * call. MD_ERR_ARG for n_atoms outside [0, N] or capacity < 1 with
+ * n_atoms > 0; MD_ERR_OOM when the ring cannot be allocated. */
+int md_trace_velocities(md_ctx *ctx, int32_t n_atoms, int64_t capacity);
+/* The last min(recorded, capacity, max_records) records in time order, as
+ * [records][n_atoms][3] doubles in out (host); *n_out = records copied,
+ * *n_recorded = records taken since md_trace_velocities. MD_ERR_ARG when no
+ * trace is active. */
+int md_get_trace(md_ctx *ctx, double *out, int64_t max_records, int64_t *n_out, int64_t *n_recorded);
 
 /* Allocation-free variant of md_rdf, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that

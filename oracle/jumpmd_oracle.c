@@ -204,6 +204,7 @@ struct orc_sim {
   double dt, gamma, kT, beta; uint64_t seed, replica;
   int jlj, jc; double eps0; int respa_inner, rebuild_every, log_events, respa_outer;
   int coul_kind, kmax;  /* electrostatics: DSF, or DSF real part + Ewald reciprocal sum */
+  int pme_K[3], pme_p;  /* SPME grid and B-spline order */
   double *frec;         /* Ewald reciprocal-space forces (-grad), with the excluded-pair correction */
   int frec_valid;
   /* state */
@@ -522,11 +523,17 @@ static double bonded_forces(const orc_sim *s, double *f) {
  * interaction by E_excl = -k_e q_i q_j erf(alpha r) / r (each pair once).
  * The real-space part is the damped shifted-force term with the same alpha.
  * Returns E_k + E_self + E_excl; f (may be NULL) receives the forces. */
+static double spme_sum(const orc_sim *s, double *f);
+
 static double recip_part(const orc_sim *s, double *f) {
   int n = s->n, K = s->kmax;
   double V = s->L[0] * s->L[1] * s->L[2], a = s->alpha, ke = s->ke_c;
   if (f) memset(f, 0, sizeof(double) * 3 * (size_t)n);
   double ek = 0.0;
+  if (s->coul_kind == ORC_COUL_SPME) {
+    ek = spme_sum(s, f);
+    K = 0;   /* no plain sum */
+  }
   for (int nx = -K; nx <= K; nx++)
     for (int ny = -K; ny <= K; ny++)
       for (int nz = -K; nz <= K; nz++) {
@@ -549,12 +556,16 @@ static double recip_part(const orc_sim *s, double *f) {
             for (int q = 0; q < 3; q++) f[3 * i + q] += c * k[q];
           }
       }
-  ek *= 2.0 * PI * ke / V;
+  if (s->coul_kind != ORC_COUL_SPME) ek *= 2.0 * PI * ke / V;
   double eself = 0.0;
   for (int i = 0; i < n; i++) eself += s->q[i] * s->q[i];
   eself *= -ke * a / sqrt(PI);
   double eexcl = 0.0;
+#if ORC_PLANT == 7   /* planted mistake: no excluded-pair correction (energy and forces alike) */
+  if (0)
+#else
   if (s->xptr)
+#endif
     for (int i = 0; i < n; i++)
       for (int e = s->xptr[i]; e < s->xptr[i + 1]; e++) {
         int j = s->xj[e];
@@ -575,8 +586,143 @@ static double recip_part(const orc_sim *s, double *f) {
   return ek + eself + eexcl;
 }
 
+/* Smooth particle-mesh Ewald (Essmann et al., J. Chem. Phys. 103, 8577
+ * (1995)), the reciprocal sum the paper's Tinker runs use. Charges are
+ * spread on a K1 x K2 x K3 grid with cardinal B-splines of order p,
+ *   Q(k) = sum_i q_i M_p(u_i1 - k1) M_p(u_i2 - k2) M_p(u_i3 - k3),  u_id = K_d x_id / L_d
+ * (periodically), and with F(m) = sum_k Q(k) exp(2 pi i m.k / K) the energy is
+ *   E = (k_e / (2 pi V)) sum_{m != 0} exp(-pi^2 |m~|^2 / alpha^2) / |m~|^2 B(m) |F(m)|^2,
+ * m~_d = m'_d / L_d with m'_d the index centred on zero, B(m) = prod_d |b_d(m_d)|^2,
+ *   1 / b_d(m) = sum_{k=0}^{p-2} M_p(k + 1) exp(2 pi i m k / K_d)   (up to a phase).
+ * With Psi(k) = sum_m G(m) conj(F(m)) exp(2 pi i m.k / K), G the factor of
+ * |F|^2 above, the force is
+ *   f_id = -2 q_i (K_d / L_d) sum_k Psi(k) M_p'(u_id - k_d) prod_{d' != d} M_p(u_id' - k_d').
+ * Written out plainly: the B-splines by their recursion, the transforms as
+ * separable discrete Fourier sums. Returns E; f (may be NULL) gets the forces. */
+static double bspl(int p, double u) {
+  if (u <= 0.0 || u >= p) return 0.0;
+  if (p == 2) return 1.0 - fabs(u - 1.0);
+  return (u * bspl(p - 1, u) + (p - u) * bspl(p - 1, u - 1.0)) / (p - 1);
+}
+static double dbspl(int p, double u) { return bspl(p - 1, u) - bspl(p - 1, u - 1.0); }
+
+/* in-place discrete Fourier sum with exp(+2 pi i m k / K) along one axis of a
+ * K0 x K1 x K2 complex grid (re, im separate) */
+static void dft_axis(double *re, double *im, const int *K, int axis) {
+  int Ka = K[axis];
+  int st = axis == 0 ? K[1] * K[2] : (axis == 1 ? K[2] : 1);
+  double *tr = (double *)xmalloc(sizeof(double) * Ka), *ti = (double *)xmalloc(sizeof(double) * Ka);
+  for (int a = 0; a < K[0]; a++)
+    for (int b = 0; b < K[1]; b++)
+      for (int c = 0; c < K[2]; c++) {
+        int idx[3] = {a, b, c};
+        if (idx[axis] != 0) continue;   /* one line per start point */
+        int base = (a * K[1] + b) * K[2] + c;
+        for (int m = 0; m < Ka; m++) {
+          double sr = 0.0, si = 0.0;
+          for (int k = 0; k < Ka; k++) {
+            double ph = 2.0 * PI * (double)((long)m * k % Ka) / Ka;
+            double xr = re[base + k * st], xi = im[base + k * st];
+            sr += xr * cos(ph) - xi * sin(ph);
+            si += xr * sin(ph) + xi * cos(ph);
+          }
+          tr[m] = sr; ti[m] = si;
+        }
+        for (int m = 0; m < Ka; m++) { re[base + m * st] = tr[m]; im[base + m * st] = ti[m]; }
+      }
+  free(tr); free(ti);
+}
+
+static double spme_sum(const orc_sim *s, double *f) {
+  const int *K = s->pme_K, p = s->pme_p, n = s->n;
+  const int NG = K[0] * K[1] * K[2];
+  const double V = s->L[0] * s->L[1] * s->L[2], a = s->alpha, ke = s->ke_c;
+  double *qr = (double *)xmalloc(sizeof(double) * (size_t)NG), *qi = (double *)xmalloc(sizeof(double) * (size_t)NG);
+  /* spread */
+  for (int i = 0; i < n; i++) {
+    double u[3]; long k0[3];
+    for (int d = 0; d < 3; d++) { u[d] = K[d] * s->x[3 * i + d] / s->L[d]; k0[d] = (long)floor(u[d]); }
+    for (int j0 = 0; j0 < p; j0++)
+      for (int j1 = 0; j1 < p; j1++)
+        for (int j2 = 0; j2 < p; j2++) {
+          long kk[3] = {k0[0] - j0, k0[1] - j1, k0[2] - j2};
+          double w = s->q[i];
+          int g[3];
+          for (int d = 0; d < 3; d++) {
+            w *= bspl(p, u[d] - (double)kk[d]);
+            g[d] = (int)(((kk[d] % K[d]) + K[d]) % K[d]);
+          }
+          qr[(g[0] * K[1] + g[1]) * K[2] + g[2]] += w;
+        }
+  }
+  for (int d = 0; d < 3; d++) dft_axis(qr, qi, K, d);
+  /* influence function and energy; the grid then holds G conj(F) */
+  double e = 0.0;
+  for (int m0 = 0; m0 < K[0]; m0++)
+    for (int m1 = 0; m1 < K[1]; m1++)
+      for (int m2 = 0; m2 < K[2]; m2++) {
+        int m[3] = {m0, m1, m2}, idx = (m0 * K[1] + m1) * K[2] + m2;
+        double G = 0.0;
+        if (m0 || m1 || m2) {
+          double mm = 0.0, B = 1.0;
+          for (int d = 0; d < 3; d++) {
+            int mc = m[d] <= K[d] / 2 ? m[d] : m[d] - K[d];
+            mm += ((double)mc / s->L[d]) * ((double)mc / s->L[d]);
+            double br = 0.0, bi = 0.0;
+            for (int k = 0; k <= p - 2; k++) {
+              double ph = 2.0 * PI * (double)((long)m[d] * k % K[d]) / K[d];
+              br += bspl(p, k + 1.0) * cos(ph);
+              bi += bspl(p, k + 1.0) * sin(ph);
+            }
+#if ORC_PLANT == 8   /* planted mistake: no B-spline correction B(m) in the influence function */
+            (void)br; (void)bi;
+#else
+            B /= br * br + bi * bi;
+#endif
+          }
+          G = ke / (2.0 * PI * V) * exp(-PI * PI * mm / (a * a)) / mm * B;
+        }
+        e += G * (qr[idx] * qr[idx] + qi[idx] * qi[idx]);
+        qr[idx] *= G;
+        qi[idx] *= -G;
+      }
+  if (f) {
+    for (int d = 0; d < 3; d++) dft_axis(qr, qi, K, d);   /* qr = Psi */
+    for (int i = 0; i < n; i++) {
+      double u[3]; long k0[3];
+      for (int d = 0; d < 3; d++) { u[d] = K[d] * s->x[3 * i + d] / s->L[d]; k0[d] = (long)floor(u[d]); }
+      double fi[3] = {0.0, 0.0, 0.0};
+      for (int j0 = 0; j0 < p; j0++)
+        for (int j1 = 0; j1 < p; j1++)
+          for (int j2 = 0; j2 < p; j2++) {
+            long kk[3] = {k0[0] - j0, k0[1] - j1, k0[2] - j2};
+            double M[3], dM[3];
+            int g[3];
+            for (int d = 0; d < 3; d++) {
+              M[d] = bspl(p, u[d] - (double)kk[d]);
+              dM[d] = dbspl(p, u[d] - (double)kk[d]);
+              g[d] = (int)(((kk[d] % K[d]) + K[d]) % K[d]);
+            }
+            double psi = qr[(g[0] * K[1] + g[1]) * K[2] + g[2]];
+            fi[0] += psi * dM[0] * M[1] * M[2];
+#if ORC_PLANT == 9   /* planted mistake: the y force from the B-spline values instead of their derivative */
+            fi[1] += psi * M[0] * M[1] * M[2];
+#else
+            fi[1] += psi * M[0] * dM[1] * M[2];
+#endif
+            fi[2] += psi * M[0] * M[1] * dM[2];
+          }
+      for (int d = 0; d < 3; d++) f[3 * i + d] = -2.0 * s->q[i] * (K[d] / s->L[d]) * fi[d];
+    }
+  }
+  free(qr); free(qi);
+  return e;
+}
+
+static int has_recip(const orc_sim *s) { return s->coul_kind == ORC_COUL_EWALD || s->coul_kind == ORC_COUL_SPME; }
+
 static void ensure_recip(orc_sim *s) {
-  if (s->coul_kind != ORC_COUL_EWALD || s->frec_valid) return;
+  if (!has_recip(s) || s->frec_valid) return;
   recip_part(s, s->frec);
   s->frec_valid = 1;
 }
@@ -931,13 +1077,22 @@ void orc_phase_j(orc_sim *s, int32_t phase, double h) {
  * a_kind 0: acceleration from short non-bonded + bonded, 1: short non-bonded */
 #define STREAM_SAVE 1
 #define STREAM_CONTINUE 2
+/* a_kind 0: the acceleration is everything not jumped (short non-bonded,
+ * bonded and, with Ewald electrostatics, reciprocal-space forces); 1: the
+ * short non-bonded forces only (the RESPA schemes) */
 static void phase_c(orc_sim *s, int32_t phase, double h, int a_kind, int stream) {
   if (!s->lists_valid) orc_build_lists(s);
   ensure_forces(s, ORC_F_SHORT);
+#if ORC_PLANT == 6   /* planted mistake: the reciprocal forces are left out of the C' acceleration */
+  const int rec = 0;
+#else
+  const int rec = a_kind == 0 && has_recip(s);
+#endif
+  if (rec) ensure_recip(s);
   for (int i = 0; i < s->n; i++) {
     double a[3];
     for (int c = 0; c < 3; c++) {
-      double fc = s->fnb[3 * i + c] + (a_kind == 0 ? s->fb[3 * i + c] : 0.0);
+      double fc = s->fnb[3 * i + c] + (a_kind == 0 ? s->fb[3 * i + c] : 0.0) + (rec ? s->frec[3 * i + c] : 0.0);
       a[c] = fc / s->me[i];
     }
     if (stream == STREAM_CONTINUE) {
@@ -953,8 +1108,12 @@ void orc_phase_c(orc_sim *s, int32_t phase, double h, int a_kind) { phase_c(s, p
 
 /* (C') or plain (B) depending on whether Coulomb jumps are on */
 static void c_or_b(orc_sim *s, int32_t phase, double h, int a_kind, int stream) {
-  if (s->jc != ORC_JUMP_NONE && s->jc != ORC_JUMP_BOUNCE) phase_c(s, phase, h, a_kind, stream);
-  else kick(s, h, 1, a_kind == 0);
+  if (s->jc != ORC_JUMP_NONE && s->jc != ORC_JUMP_BOUNCE) {
+    phase_c(s, phase, h, a_kind, stream);
+  } else {
+    kick(s, h, 1, a_kind == 0);
+    if (a_kind == 0 && has_recip(s)) { ensure_recip(s); kick_with(s, h, s->frec); }
+  }
 }
 
 /* whether the scheme has (J) steps: LJ bounces, or the BOUNCE scheme */
@@ -965,7 +1124,7 @@ static int has_j(const orc_sim *s) { return s->jlj == ORC_JUMP_BPS || s->jc == O
  * electrostatics the reciprocal-space forces are part of every kick. */
 int orc_step_baoab(orc_sim *s, int64_t n) {
   double h = 0.5 * s->dt;
-  int ew = s->coul_kind == ORC_COUL_EWALD;
+  int ew = has_recip(s);
   ensure_forces(s, ORC_F_FULL);
   ensure_recip(s);
   for (int64_t it = 0; it < n; it++) {
@@ -984,13 +1143,14 @@ int orc_step_baoab(orc_sim *s, int64_t n) {
   return 0;
 }
 
-/* JUMP: B J A O A J B, or C' J' A O A J' C' (Sec. 2.3, Sec. 3.3). The
+/* JUMP: B J A O A J B, or C' J' A O A J' C' (Sec. 2.3, Sec. 3.3); with
+ * Ewald electrostatics the C' acceleration (or the B kick) also carries the
+ * reciprocal-space forces, re-evaluated every step. The
  * closing C' of a step and the opening C' of the next act at the same
  * positions; the opening one draws its proposals from the closing one's
  * stream, from the proposal after the one that ended it. Those proposals
  * were never used, so they are fresh draws and the law is unchanged. */
 int orc_step_jump(orc_sim *s, int64_t n) {
-  if (s->coul_kind == ORC_COUL_EWALD) return -1;   /* Ewald: the three-level schemes */
   double h = 0.5 * s->dt;
   if (!s->lists_valid) orc_build_lists(s);
   ensure_forces(s, ORC_F_SHORT);
@@ -1045,7 +1205,7 @@ static void respa_inner_steps(orc_sim *s, int m, double h) {
  * opening C' continues the stream of the closing C' of the outer step before
  * (both act at the same positions). */
 int orc_step_jump_respa(orc_sim *s, int64_t n_outer) {
-  if (s->coul_kind == ORC_COUL_EWALD) return -1;
+  if (has_recip(s)) return -1;
   int m = s->respa_inner > 0 ? s->respa_inner : 1;
   double H = 0.5 * s->dt * m, h = 0.5 * s->dt;
   if (!s->lists_valid) orc_build_lists(s);
@@ -1065,7 +1225,7 @@ int orc_step_jump_respa(orc_sim *s, int64_t n_outer) {
 
 /* BAOAB-RESPA comparator: full-range non-bonded kick at the outer step. */
 int orc_step_baoab_respa(orc_sim *s, int64_t n_outer) {
-  if (s->coul_kind == ORC_COUL_EWALD) return -1;
+  if (has_recip(s)) return -1;
   int m = s->respa_inner > 0 ? s->respa_inner : 1;
   double H = 0.5 * s->dt * m, h = 0.5 * s->dt;
   ensure_forces(s, ORC_F_FULL);
@@ -1087,7 +1247,7 @@ int orc_step_baoab_respa(orc_sim *s, int64_t n_outer) {
  * Ewald reciprocal-space forces at the outer step p m dt, as kicks of half
  * an outer step around the p middle steps. */
 int orc_step_jump_respa1(orc_sim *s, int64_t n_outer) {
-  if (s->coul_kind != ORC_COUL_EWALD) return -1;
+  if (!has_recip(s)) return -1;
   int m = s->respa_inner > 0 ? s->respa_inner : 1, p = s->respa_outer > 0 ? s->respa_outer : 1;
   double h = 0.5 * s->dt, H = 0.5 * s->dt * m, HH = 0.5 * s->dt * m * p;
   if (!s->lists_valid) orc_build_lists(s);
@@ -1115,7 +1275,7 @@ int orc_step_jump_respa1(orc_sim *s, int64_t n_outer) {
  * short non-bonded forces chi U at m dt, the long real-space part (1 - chi) U
  * and the reciprocal-space forces at p m dt. */
 int orc_step_baoab_respa1(orc_sim *s, int64_t n_outer) {
-  if (s->coul_kind != ORC_COUL_EWALD) return -1;
+  if (!has_recip(s)) return -1;
   int m = s->respa_inner > 0 ? s->respa_inner : 1, p = s->respa_outer > 0 ? s->respa_outer : 1;
   double h = 0.5 * s->dt, H = 0.5 * s->dt * m, HH = 0.5 * s->dt * m * p;
   double *fl = (double *)xmalloc(sizeof(double) * 3 * (size_t)s->n);
@@ -1208,8 +1368,15 @@ orc_sim *orc_create(const orc_system *sy, const orc_split *sp, const orc_params 
   s->respa_inner = pa->respa_inner; s->rebuild_every = pa->rebuild_every;
   s->log_events = pa->log_events; s->respa_outer = pa->respa_outer;
   s->coul_kind = sp->coulomb_kind; s->kmax = sp->ewald_kmax;
-  if (s->coul_kind != ORC_COUL_DSF && s->coul_kind != ORC_COUL_EWALD) FAIL("coulomb_kind: DSF or EWALD");
+  for (int d = 0; d < 3; d++) s->pme_K[d] = sp->pme_grid[d];
+  s->pme_p = sp->pme_order;
+  if (s->coul_kind != ORC_COUL_DSF && s->coul_kind != ORC_COUL_EWALD && s->coul_kind != ORC_COUL_SPME)
+    FAIL("coulomb_kind: DSF, EWALD or SPME");
   if (s->coul_kind == ORC_COUL_EWALD && (s->kmax < 1 || !(s->alpha > 0.0))) FAIL("Ewald needs kmax >= 1 and alpha > 0");
+  if (s->coul_kind == ORC_COUL_SPME &&
+      (!(s->alpha > 0.0) || s->pme_p < 4 || s->pme_p > 8 || (s->pme_p & 1) || s->pme_K[0] < s->pme_p ||
+       s->pme_K[1] < s->pme_p || s->pme_K[2] < s->pme_p))
+    FAIL("SPME needs alpha > 0, an even order 4..8 and at least `order` grid points per edge");
   s->frec = (double *)xmalloc(sizeof(double) * 3 * (size_t)n);
   if (s->jlj != ORC_JUMP_NONE && s->jlj != ORC_JUMP_BPS) FAIL("LJ jumps: NONE or BPS");
   if (s->jc != ORC_JUMP_NONE && s->jc != ORC_JUMP_BPS && s->jc != ORC_JUMP_MRZ_CONST &&
@@ -1302,7 +1469,7 @@ void orc_energies(const orc_sim *s, double out[7]) {
   nb_forces(s, ORC_F_FULL, tmp, &es, &el);
   double eb = bonded_forces(s, tmp);
   free(tmp);
-  double er = s->coul_kind == ORC_COUL_EWALD ? recip_part(s, NULL) : 0.0;
+  double er = has_recip(s) ? recip_part(s, NULL) : 0.0;
   out[0] = ke;
   out[1] = 2.0 * ke / (3.0 * s->n * s->kB);
   out[2] = es; out[3] = el; out[4] = eb; out[5] = es + el + eb + er; out[6] = er;
@@ -1311,7 +1478,7 @@ void orc_energies(const orc_sim *s, double out[7]) {
 void orc_accel(const orc_sim *s, int kind, double *acc) {
   double *f = (double *)xmalloc(sizeof(double) * 3 * (size_t)s->n);
   if (kind == ORC_F_BONDED) bonded_forces(s, f);
-  else if (kind == ORC_F_RECIP) { if (s->coul_kind == ORC_COUL_EWALD) recip_part(s, f); }
+  else if (kind == ORC_F_RECIP) { if (has_recip(s)) recip_part(s, f); }
   else nb_forces(s, kind, f, NULL, NULL);
   for (int i = 0; i < s->n; i++)
     for (int c = 0; c < 3; c++) acc[3 * i + c] = f[3 * i + c] / s->me[i];

@@ -42,6 +42,7 @@ extern "C" {
 /* electrostatics */
 #define ORC_COUL_DSF 0    /* damped shifted-force Coulomb out to r_c, nothing beyond */
 #define ORC_COUL_EWALD 1  /* the same real-space term plus the Ewald reciprocal sum (Sec. 3.1) */
+#define ORC_COUL_SPME 2   /* the same, the reciprocal sum by smooth particle-mesh Ewald (Sec. 3.1) */
 
 typedef struct {
   int32_t n_atoms, n_types;
@@ -66,8 +67,10 @@ typedef struct {
   double r_s, r_c, switch_width, skin, coulomb_alpha;
   int32_t n_rings;
   double ring_width;
-  int32_t coulomb_kind;         /* ORC_COUL_DSF or ORC_COUL_EWALD */
+  int32_t coulomb_kind;         /* ORC_COUL_DSF, ORC_COUL_EWALD or ORC_COUL_SPME */
   int32_t ewald_kmax;           /* Ewald: lattice vectors n with 0 < |n|^2 <= kmax^2 */
+  int32_t pme_grid[3];          /* SPME: grid points per box edge */
+  int32_t pme_order;            /* SPME: B-spline order (even, 4..8) */
 } orc_split;
 
 typedef struct {

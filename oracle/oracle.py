@@ -19,7 +19,7 @@ _LIB_ENV = "JUMPMD_ORACLE_LIBRARY"
 JUMP_NONE, JUMP_BPS, JUMP_MRZ_CONST, JUMP_MRZ_ADAPTIVE, JUMP_BOUNCE = 0, 1, 2, 3, 4
 PH_O, PH_J1, PH_J2, PH_C1, PH_C2 = 1, 2, 3, 4, 5
 F_SHORT, F_FULL, F_BONDED, F_LONG, F_RECIP = 0, 1, 2, 3, 4
-COUL_DSF, COUL_EWALD = 0, 1
+COUL_DSF, COUL_EWALD, COUL_SPME = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -43,7 +43,8 @@ class OrcSplit(C.Structure):
     _fields_ = [("r_s", C.c_double), ("r_c", C.c_double), ("switch_width", C.c_double),
                 ("skin", C.c_double), ("coulomb_alpha", C.c_double),
                 ("n_rings", C.c_int32), ("ring_width", C.c_double),
-                ("coulomb_kind", C.c_int32), ("ewald_kmax", C.c_int32)]
+                ("coulomb_kind", C.c_int32), ("ewald_kmax", C.c_int32),
+                ("pme_grid", C.c_int32 * 3), ("pme_order", C.c_int32)]
 
 
 class OrcParams(C.Structure):
@@ -192,7 +193,8 @@ class OracleSim:
         sy.coulomb_k, sy.accel_factor, sy.kB = s.coulomb_k, s.accel_factor, s.kB
         sp = OrcSplit(split.r_s, split.r_c, split.switch_width, split.skin,
                       split.coulomb_alpha, split.n_rings, split.ring_width,
-                      getattr(split, "coulomb_kind", 0), getattr(split, "ewald_kmax", 0))
+                      getattr(split, "coulomb_kind", 0), getattr(split, "ewald_kmax", 0),
+                      (C.c_int32 * 3)(*getattr(split, "pme_grid", (0, 0, 0))), getattr(split, "pme_order", 0))
         pa = OrcParams(params.dt, params.gamma, params.kT, params.seed, replica,
                        params.jump_lj, params.jump_coul, params.eps, params.respa_inner,
                        params.rebuild_every, params.log_events, getattr(params, "respa_outer", 1))

@@ -17,6 +17,19 @@ the RESPA schemes; n inner steps per outer step, default 3; eps0 in
 Coulomb long part's treatment in JUMP: mrz (adaptive MRZ jumps, default),
 bps (BPS bounces in the C step), or none (the long part dropped: the
 negative control of Fig. 1b, whose structure must differ).
+
+--ewald ALPHA,RC,KMAX[,W] switches every run (and the equilibration) to
+Ewald electrostatics: damped real part to RC with ALPHA, reciprocal sum over
+|n| <= KMAX, switch width W (default 1 A). The schemes are then baoab and
+jump (the reciprocal forces every step), baoab_respa1 and jump_respa1
+(params m: middle step in inner steps, default 2; p: outer step in middle
+steps, default 3). --pme ALPHA,RC,GRID,ORDER[,W] does the same with the
+reciprocal sum by smooth particle-mesh Ewald on a GRID^3 mesh with B-splines
+of order ORDER, e.g. the paper's water settings for 12 000 atoms (its mesh
+is 60^3):
+
+    python -m paper_2412_15073_amd.accuracy --pme 0.554,7,64,6,0.5 \
+        --runs "baoab,jump,baoab_respa1:p=3,jump_respa1:p=3"
 """
 import argparse
 import json
@@ -68,10 +81,28 @@ def main():
     ap.add_argument("--blocks", type=int, default=4, help="blocks for the error estimates")
     ap.add_argument("--runs", default="baoab,jump,jump:fp32=1")
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--ewald", default="", metavar="ALPHA,RC,KMAX[,W]")
+    ap.add_argument("--pme", default="", metavar="ALPHA,RC,GRID,ORDER[,W]")
     a = ap.parse_args()
 
+    ew = [float(x) for x in a.ewald.split(",")] if a.ewald else None
+    pme = [float(x) for x in a.pme.split(",")] if a.pme else None
+    ew = ew or (pme[:2] + [0.0] + pme[4:] if pme else None)
+    rc = ew[1] if ew else 10.0
+    w_sw = ew[3] if ew and len(ew) > 3 else 1.0
+
+    def make_split(rs):
+        if not ew:
+            return S.water_split(r_s=rs, r_c=10.0, w=1.0, skin=a.skin, n_rings=a.rings)
+        sp = S.water_split(r_s=rs, r_c=rc, w=w_sw, skin=a.skin, alpha=ew[0], n_rings=a.rings)
+        if pme:
+            sp.coulomb_kind, sp.pme_grid, sp.pme_order = S.COUL_SPME, (int(pme[2]),) * 3, int(pme[3])
+        else:
+            sp.coulomb_kind, sp.ewald_kmax = S.COUL_EWALD, int(ew[2])
+        return sp
+
     sysm = S.water_box(a.n_mol, seed=a.seed)
-    split = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=a.skin, n_rings=a.rings)
+    split = make_split(5.0)
     L = float(sysm.box[0])
     r_max, n_bins = min(0.5 * L, 12.0), 120
     o_idx = np.where(sysm.type == 0)[0]
@@ -89,23 +120,27 @@ def main():
         kv = dict(x.split("=") for x in opts.split(";") if x)
         jumps = name.startswith("jump")
         respa = name.endswith("_respa")
+        respa1 = name.endswith("_respa1")
         dt_fs = float(kv.get("dt", 1.0))
-        n_in = int(kv.get("n", 3)) if respa else 1
+        n_in = int(kv.get("n", 3)) if respa else (int(kv.get("m", 2)) if respa1 else 1)
+        n_out = int(kv.get("p", 3)) if respa1 else 1
         eps0 = float(kv.get("eps0", a.eps0))
         rs = float(kv.get("rs", 5.0))
-        sp = S.water_split(r_s=rs, r_c=10.0, w=1.0, skin=a.skin, n_rings=a.rings)
+        sp = make_split(rs)
         pa = S.water_params(dt=dt_fs * 1e-3, eps0_per_kcal=eps0, jumps=jumps, seed=a.seed + 1)
         pa.precision = int(kv.get("fp32", 0))
         if jumps:
             pa.jump_coul = {"mrz": S.JUMP_MRZ_ADAPTIVE, "bps": S.JUMP_BPS,
                             "none": S.JUMP_NONE}[kv.get("coul", "mrz")]
         pa.respa_inner = n_in
+        pa.respa_outer = n_out
         sim = jumpmd.Sim(sysm, sp, pa)
-        step_fs = dt_fs * n_in                        # time per call of the step function
+        step_fs = dt_fs * n_in * n_out                # time per call of the step function
         n_steps = int(round(a.ps / (step_fs * 1e-3)))
         every = max(1, int(round(a.every / step_fs)))
         step_fn = {"baoab": sim.step_baoab, "jump": sim.step_jump, "baoab_respa": sim.step_baoab_respa,
-                   "jump_respa": sim.step_jump_respa}[name]
+                   "jump_respa": sim.step_jump_respa, "baoab_respa1": sim.step_baoab_respa1,
+                   "jump_respa1": sim.step_jump_respa1}[name]
         t0 = time.perf_counter()
         out_run, done, t_bad = run(sim, step_fn, n_steps, every, o_idx, r_max, n_bins, 10.0 * 300.0)
         el = time.perf_counter() - t0
@@ -130,6 +165,10 @@ def main():
     ref = res.get("baoab")
     out = {"workload": f"water_{a.n_mol}mol", "ps_each": a.ps, "eps0_per_kcal_mol_A": a.eps0,
            "rings": a.rings, "skin": a.skin, "sample_every_fs": a.every,
+           "electrostatics": ({"kind": "SPME", "alpha": ew[0], "r_c": rc, "grid": int(pme[2]), "order": int(pme[3]),
+                               "switch": w_sw} if pme else
+                              {"kind": "Ewald", "alpha": ew[0], "r_c": rc, "kmax": int(ew[2]), "switch": w_sw}
+                              if ew else {"kind": "DSF", "alpha": 0.2, "r_c": 10.0, "switch": 1.0}),
            "targets": {"T_rel": 0.01, "rdf_l2": 1e-2, "D_rel": 0.05}}
     for name, r in res.items():
         row = {"T_K": r["T"], "T_err": r["T_err"], "pe_kJ_mol": r["pe"], "pe_err": r["pe_err"],

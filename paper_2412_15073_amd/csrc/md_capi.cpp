@@ -44,6 +44,7 @@ struct md_ctx {
   int fkind = -1;              // force kind held in fnb: 0 short, 1 full, -1 stale
   bool fb_valid = false;
   bool ewald = false;          // Ewald electrostatics (reciprocal sum in frec)
+  bool spme = false;           // the reciprocal sum by smooth particle-mesh Ewald
   bool frec_valid = false;     // frec holds the reciprocal-space forces at the current positions
   bool flong_valid = false;    // flong holds the long real-space forces at the current positions
   double2 *d_spart = nullptr, *d_sfac = nullptr;   // Ewald partial and total structure factors
@@ -68,6 +69,7 @@ struct md_ctx {
   int row_most = 1;            // longest possible row (entries)
   // Rollback point for regrowing the rows: the state at the first stepping
   // call after the last good synchronisation, and the stepping calls since.
+  int64_t trace_n = 0;   // velocity-trace records taken since md_trace_velocities
   struct Snap {
     bool valid = false;
     double4 *x = nullptr, *v = nullptr, *xref = nullptr;
@@ -75,7 +77,7 @@ struct md_ctx {
     long long *nprop = nullptr, *nacc = nullptr, *nviol = nullptr;
     unsigned long long *hash = nullptr, *maxd2 = nullptr;
     MDCtl *ctl = nullptr;
-    int64_t step = 0, since_build = 0;
+    int64_t step = 0, since_build = 0, trace_n = 0;
     int cur = 0, rows_valid = 0;
   } snap;
   struct Call { int kind; int64_t n; int which, phase; double h; };
@@ -235,6 +237,7 @@ static void add_O(md_ctx *c, ProgBuilder &b, double dt, int sub, int64_t step) {
   MDOp o = op_base(OP_O, dt);
   o.substep = sub;
   o.step = step;
+  o.rstep = c->V.trace ? c->trace_n++ : -1;   // velocity-trace record
   o.c1 = std::exp(-c->par.gamma * dt);
   o.c2 = std::sqrt(-std::expm1(-2.0 * c->par.gamma * dt));
   b.add(o);
@@ -248,18 +251,21 @@ static void add_J(ProgBuilder &b, int phase, double h, int64_t step) {
 // (C') when Coulomb jumps are on, otherwise the plain kick it reduces to.
 // stream: 0, MD_STREAM_SAVE, or MD_STREAM_CONTINUE (of the closing C' of the
 // step before, whose words are (step - 1, OP_PHASE_C2))
+// a_nb_only: the C acceleration (or the kick) takes the short non-bonded
+// forces only (RESPA schemes); otherwise also the bonded forces and, with
+// Ewald electrostatics, the reciprocal-space forces (plain JUMP)
 static void add_C_or_B(md_ctx *c, ProgBuilder &b, int phase, double h, int64_t step, int a_nb_only,
                        int stream = 0) {
   if (c->par.jump_coul != MD_JUMP_NONE && c->par.jump_coul != MD_JUMP_BOUNCE) {
     MDOp o = op_base(OP_C, h);
     o.phase = phase;
     o.step = step;
-    o.flags = a_nb_only;
+    o.flags = a_nb_only ? 1 : (c->ewald ? 4 : 0);
     o.stream = stream;
     if (stream == MD_STREAM_CONTINUE) { o.rstep = step - 1; o.rphase = OP_PHASE_C2; }
     b.add(o);
   } else {
-    add_B(b, h, a_nb_only ? 1 : 3);
+    add_B(b, h, a_nb_only ? 1 : (c->ewald ? 7 : 3));
   }
 }
 static void add_disp(ProgBuilder &b, int slot) {
@@ -419,7 +425,8 @@ static int eval_recip(md_ctx *c) {
   if (!c->ewald) return MD_OK;
   hipEvent_t e0{};
   prof_begin(c, MD_K_RECIP, &e0);
-  HIPCHK(c, launch_recip(c->V, Xcur(c), c->d_spart, c->d_sfac, c->d_fpart, c->stream));
+  if (c->spme) HIPCHK(c, launch_pme_forces(c->V, Xcur(c), c->stream));
+  else HIPCHK(c, launch_recip(c->V, Xcur(c), c->d_spart, c->d_sfac, c->d_fpart, c->stream));
   prof_end(c, MD_K_RECIP, e0);
   c->frec_valid = true;
   return MD_OK;
@@ -544,12 +551,21 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
   if (p->event_capacity < 0 || p->event_capacity > (1ll << 31)) return fail(nullptr, MD_ERR_ARG, "event_capacity must be in [0, 2^31]");
   if (p->chain_order < 0 || p->chain_order > 2) return fail(nullptr, MD_ERR_ARG, "chain_order must be 0, 1 or 2");
   if (p->respa_outer < 0) return fail(nullptr, MD_ERR_ARG, "respa_outer must be >= 0 (0: 1)");
-  if (sp->coulomb_kind != MD_COUL_DSF && sp->coulomb_kind != MD_COUL_EWALD)
-    return fail(nullptr, MD_ERR_ARG, "coulomb_kind must be MD_COUL_DSF or MD_COUL_EWALD");
-  if (sp->coulomb_kind == MD_COUL_EWALD) {
-    if (s->n_replicas != 1) return fail(nullptr, MD_ERR_ARG, "Ewald electrostatics: one replica per context");
-    if (sp->ewald_kmax < 1 || sp->ewald_kmax > 64 || !(sp->coulomb_alpha > 0.0))
-      return fail(nullptr, MD_ERR_ARG, "Ewald electrostatics need 1 <= ewald_kmax <= 64 and coulomb_alpha > 0");
+  if (sp->coulomb_kind != MD_COUL_DSF && sp->coulomb_kind != MD_COUL_EWALD && sp->coulomb_kind != MD_COUL_SPME)
+    return fail(nullptr, MD_ERR_ARG, "coulomb_kind must be MD_COUL_DSF, MD_COUL_EWALD or MD_COUL_SPME");
+  if (sp->coulomb_kind != MD_COUL_DSF && s->n_replicas != 1)
+    return fail(nullptr, MD_ERR_ARG, "Ewald electrostatics: one replica per context");
+  if (sp->coulomb_kind == MD_COUL_EWALD && (sp->ewald_kmax < 1 || sp->ewald_kmax > 64 || !(sp->coulomb_alpha > 0.0)))
+    return fail(nullptr, MD_ERR_ARG, "Ewald electrostatics need 1 <= ewald_kmax <= 64 and coulomb_alpha > 0");
+  if (sp->coulomb_kind == MD_COUL_SPME) {
+    bool ok = sp->coulomb_alpha > 0.0 && (sp->pme_order == 4 || sp->pme_order == 6 || sp->pme_order == 8);
+    for (int d = 0; d < 3; ++d) {
+      const int K = sp->pme_grid[d];
+      ok = ok && K >= 8 && K <= 256 && (K & (K - 1)) == 0 && K >= sp->pme_order;
+    }
+    if (!ok)
+      return fail(nullptr, MD_ERR_ARG, "SPME needs coulomb_alpha > 0, pme_order 4, 6 or 8 and pme_grid edges "
+                                       "that are powers of two in [8, 256]");
   }
   return MD_OK;
 }
@@ -883,8 +899,64 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   // Ewald reciprocal sum: k-vectors of the half space with 0 < |n|^2 <= kmax^2
   std::vector<double4> kv;
   std::vector<int4> kn;
-  c->ewald = sp->coulomb_kind == MD_COUL_EWALD;
-  if (c->ewald) {
+  c->ewald = sp->coulomb_kind == MD_COUL_EWALD || sp->coulomb_kind == MD_COUL_SPME;
+  c->spme = sp->coulomb_kind == MD_COUL_SPME;
+  std::vector<double> pinf;
+  std::vector<double2> ptw;
+  if (c->spme) {
+    // influence function G(m) = k_e / (2 pi V) exp(-pi^2 |m~|^2 / alpha^2) / |m~|^2 B(m),
+    // B(m) = prod_d 1 / |sum_{k=0}^{p-2} M_p(k + 1) exp(2 pi i m_d k / K_d)|^2, G(0) = 0
+    const int p = sp->pme_order;
+    const int *K = sp->pme_grid;
+    const double *L = c->box.data();
+    const double vol = L[0] * L[1] * L[2];
+    // M_p at the integers 1..p-1 by the recursion on the table of M_{n-1}
+    std::vector<double> Mi(p + 1, 0.0), Mn(p + 1, 0.0);
+    Mi[1] = 1.0;   // M_2 at 0, 1, 2
+    for (int nn = 3; nn <= p; ++nn) {
+      for (int u = 0; u <= nn; ++u)
+        Mn[u] = ((double)u * (u <= nn - 1 ? Mi[u] : 0.0) + (double)(nn - u) * (u >= 1 ? Mi[u - 1] : 0.0)) / (nn - 1);
+      Mi = Mn;
+    }
+    std::vector<double> bm[3];
+    for (int d = 0; d < 3; ++d) {
+      bm[d].assign(K[d], 0.0);
+      for (int m = 0; m < K[d]; ++m) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k <= p - 2; ++k) {
+          const double ph = 2.0 * M_PI * (double)((long long)m * k % K[d]) / K[d];
+          re += Mi[k + 1] * std::cos(ph);
+          im += Mi[k + 1] * std::sin(ph);
+        }
+        bm[d][m] = 1.0 / (re * re + im * im);
+      }
+    }
+    pinf.assign((size_t)K[0] * K[1] * K[2], 0.0);
+    for (int m0 = 0; m0 < K[0]; ++m0)
+      for (int m1 = 0; m1 < K[1]; ++m1)
+        for (int m2 = 0; m2 < K[2]; ++m2) {
+          if (!m0 && !m1 && !m2) continue;
+          const int mc[3] = {m0 <= K[0] / 2 ? m0 : m0 - K[0], m1 <= K[1] / 2 ? m1 : m1 - K[1],
+                             m2 <= K[2] / 2 ? m2 : m2 - K[2]};
+          double mm = 0.0;
+          for (int d = 0; d < 3; ++d) mm += (mc[d] / L[d]) * (mc[d] / L[d]);
+          pinf[((size_t)m0 * K[1] + m1) * K[2] + m2] = V.ke / (2.0 * M_PI * vol) *
+              std::exp(-M_PI * M_PI * mm / (V.alpha * V.alpha)) / mm * bm[0][m0] * bm[1][m1] * bm[2][m2];
+        }
+    const int tn = std::max(K[0], std::max(K[1], K[2]));
+    ptw.resize(tn / 2);
+    for (int k = 0; k < tn / 2; ++k) ptw[k] = make_double2(std::cos(2.0 * M_PI * k / tn), std::sin(2.0 * M_PI * k / tn));
+    V.spme = 1; V.porder = p; V.ptw_n = tn;
+    for (int d = 0; d < 3; ++d) V.pk[d] = K[d];
+    double2 *d_grid, *d_tw;
+    double *d_inf;
+    A(d_grid, pinf.size()); A(d_inf, pinf.size()); A(d_tw, ptw.size());
+    V.pgrid = d_grid; V.pinf = d_inf; V.ptw = d_tw;
+    A(V.frec, n); A(V.flong, n);
+    double q2 = 0.0;
+    for (int i = 0; i < n; ++i) q2 += s->charge ? s->charge[i] * s->charge[i] : 0.0;
+    c->ew_self = -V.ke * V.alpha / std::sqrt(M_PI) * q2;
+  } else if (c->ewald) {
     const int K = sp->ewald_kmax;
     const double *L = c->box.data();
     const double vol = L[0] * L[1] * L[2];
@@ -920,7 +992,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
     A(c->d_sfac, kv.size());
   }
   c->scratch_n = std::max<size_t>(4 * (size_t)n + (size_t)s->n_bonds + (size_t)s->n_angles, 4096);
-  c->scratch_n = std::max<size_t>(c->scratch_n, kv.size() + (size_t)n);
+  c->scratch_n = std::max<size_t>(c->scratch_n, kv.size() + pinf.size() + (size_t)n);
   A(c->d_scratch, c->scratch_n);
   if (!ok) {
     std::string why = c->err;
@@ -974,9 +1046,13 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
   up(d_at0, s->angle_t0, sizeof(double) * s->n_angles);
   up(c->d_rep_off, c->rep_off.data(), sizeof(int) * (nrep + 1));
   up(d_chain_perm, chain_perm.data(), sizeof(int) * chain_perm.size());
-  if (c->ewald) {
+  if (c->ewald && !c->spme) {
     up((void *)V.kvec, kv.data(), sizeof(double4) * kv.size());
     up((void *)V.kint, kn.data(), sizeof(int4) * kn.size());
+  }
+  if (c->spme) {
+    up((void *)V.pinf, pinf.data(), sizeof(double) * pinf.size());
+    up((void *)V.ptw, ptw.data(), sizeof(double2) * ptw.size());
   }
   c->fuse_forces[0] = force_fused_fits(V, 0);
   c->fuse_forces[1] = force_fused_fits(V, 1);
@@ -1093,6 +1169,7 @@ static int jump_plain(md_ctx *c, int64_t nsteps) {
     if (it == nsteps) break;
     if ((rc = step_rebuild(c, MODE_JUMP, c->step))) return rc;
     if ((rc = eval_forces(c, 0))) return rc;
+    if ((rc = eval_recip(c))) return rc;
     c->step++;
   }
   return MD_OK;
@@ -1102,6 +1179,7 @@ static int jump_plain(md_ctx *c, int64_t nsteps) {
 // scheme and position-buffer parity); the random-stream step base is set on
 // the device before each replay. Steps left over run kernel by kernel.
 static int graph_chunks(md_ctx *c, int mode, int64_t &n) {
+  if (c->V.trace) return MD_OK;   // traced steps run as plain launches (one record index per O op)
   const int K = c->par.graph_steps;
   if (K <= 0 || c->par.rebuild_every > 0 || n < K) return MD_OK;
   int (*plain)(md_ctx *, int64_t) = mode == MODE_JUMP ? jump_plain : baoab_plain;
@@ -1294,7 +1372,6 @@ extern "C" int md_step_baoab(md_ctx *c, int64_t nsteps) {
 
 extern "C" int md_step_jump(md_ctx *c, int64_t nsteps) {
   if (!c || nsteps < 0) return fail(c, MD_ERR_ARG, "bad argument");
-  if (c->ewald) return fail(c, MD_ERR_ARG, "Ewald electrostatics: use md_step_baoab or the three-level schemes");
   return step_call(c, {CALL_JUMP, nsteps, 0, 0, 0.0});
 }
 
@@ -1378,6 +1455,7 @@ static int take_snapshot(md_ctx *c) {
   HIPCHK(c, hipMemcpyAsync(q.maxd2, V.rep_maxd2, 8 * 2 * (size_t)c->nrep, hipMemcpyDeviceToDevice, st));
   HIPCHK(c, hipMemcpyAsync(q.ctl, V.ctl, sizeof(MDCtl), hipMemcpyDeviceToDevice, st));
   q.step = c->step;
+  q.trace_n = c->trace_n;
   q.since_build = c->since_build;
   q.cur = c->cur;
   q.rows_valid = c->rows_valid;
@@ -1406,6 +1484,7 @@ static int restore_snapshot(md_ctx *c) {
   HIPCHK(c, hipMemcpyAsync(V.rep_maxd2, q.maxd2, 8 * 2 * (size_t)c->nrep, hipMemcpyDeviceToDevice, st));
   HIPCHK(c, hipMemcpyAsync(V.ctl, q.ctl, sizeof(MDCtl), hipMemcpyDeviceToDevice, st));
   c->step = q.step;
+  c->trace_n = q.trace_n;
   c->since_build = q.since_build;
   c->fkind = -1;
   c->fb_valid = false;
@@ -1547,7 +1626,17 @@ extern "C" int md_observables(md_ctx *c, uint32_t flags, md_obs *o) {
     for (int i = 0; i < c->n; ++i) { ps += hs[i]; pl += hl[i]; }
     for (int t = 0; t < c->nbonds + c->nangles; ++t) pb += hb[t];
     o->pe_short = ps; o->pe_long = pl; o->pe_bonded = pb;
-    if (c->ewald) {
+    if (c->spme) {
+      const size_t ng = (size_t)c->V.pk[0] * c->V.pk[1] * c->V.pk[2];
+      std::vector<double> he(ng + (size_t)c->n);
+      HIPCHK(c, launch_pme_energy(c->V, X, c->d_scratch, c->stream));
+      HIPCHK(c, hipMemcpyAsync(he.data(), c->d_scratch, sizeof(double) * he.size(), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      double ek = 0.0, ex = 0.0;
+      for (size_t m = 0; m < ng; ++m) ek += he[m];
+      for (int i = 0; i < c->n; ++i) ex += he[ng + i];
+      o->pe_recip = ek + c->ew_self + ex;
+    } else if (c->ewald) {
       const size_t ne = (size_t)c->V.nk + (size_t)c->n;
       std::vector<double> he(ne);
       HIPCHK(c, launch_ewald_energy(c->V, X, c->d_spart, c->d_sfac, c->d_scratch, c->stream));
@@ -1687,6 +1776,49 @@ extern "C" int md_rdf(md_ctx *c, int32_t ta, int32_t tb, double r_max, int32_t n
   HIPCHK(c, hipMemcpyAsync(h.data(), c->d_hist, sizeof(unsigned long long) * n_bins, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int b = 0; b < n_bins; ++b) hist[b] = (double)h[b];
+  return rc;
+}
+
+// Velocity trace: the ring lives in the context's device memory; O ops take
+// consecutive record indices while it is active (add_O), and graph replay is
+// off meanwhile (a captured graph would repeat its record indices).
+extern "C" int md_trace_velocities(md_ctx *c, int32_t n_atoms, int64_t capacity) {
+  if (!c || n_atoms < 0 || n_atoms > c->n || (n_atoms > 0 && capacity < 1))
+    return fail(c, MD_ERR_ARG, "trace: need 0 <= n_atoms <= N and capacity >= 1");
+  const int rc = settle(c);   // pending steps (and replays) record into the old ring
+  if (c->V.trace) dfree(c, c->V.trace);
+  c->V.trace = nullptr;
+  c->V.ntrace = 0;
+  c->V.trace_cap = 0;
+  c->trace_n = 0;
+  if (n_atoms == 0) return rc;
+  if ((double)n_atoms * (double)capacity > 4.0e9)
+    return fail(c, MD_ERR_ARG, "trace: n_atoms x capacity above 4e9 records");
+  c->V.trace = dalloc<double4>(c, (size_t)n_atoms * (size_t)capacity);
+  if (!c->V.trace) return fail(c, MD_ERR_OOM, "trace: " + c->err);
+  c->V.ntrace = n_atoms;
+  c->V.trace_cap = capacity;
+  return rc;
+}
+
+extern "C" int md_get_trace(md_ctx *c, double *out, int64_t max_records, int64_t *n_out, int64_t *n_recorded) {
+  if (!c || !c->V.trace || max_records < 0 || (max_records > 0 && !out))
+    return fail(c, MD_ERR_ARG, "trace: no active trace, or bad output");
+  const int rc = settle(c);
+  const int64_t cap = c->V.trace_cap, tn = c->trace_n, na = c->V.ntrace;
+  const int64_t k = std::min(max_records, std::min(tn, cap));
+  std::vector<double4> buf((size_t)(k * na));
+  for (int64_t r = 0; r < k; ++r) {   // record tn - k + r sits in slot (tn - k + r) % cap
+    const int64_t slot = (tn - k + r) % cap;
+    HIPCHK(c, hipMemcpyAsync(buf.data() + r * na, c->V.trace + slot * na, sizeof(double4) * na,
+                             hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int64_t q = 0; q < k * na; ++q) {
+    out[3 * q] = buf[q].x; out[3 * q + 1] = buf[q].y; out[3 * q + 2] = buf[q].z;
+  }
+  if (n_out) *n_out = k;
+  if (n_recorded) *n_recorded = tn;
   return rc;
 }
 

@@ -737,9 +737,12 @@ __global__ __launch_bounds__(64 * MD_CHAIN_MAX_BLOCK_WAVES, MD_CHAIN_WAVES_PER_S
     } else {
       double ax = 0.0, ay = 0.0, az = 0.0;
       if (op.kind == OP_C) {
-        ax = (fn.x + (op.flags == 0 ? fb.x : 0.0)) / me;
-        ay = (fn.y + (op.flags == 0 ? fb.y : 0.0)) / me;
-        az = (fn.z + (op.flags == 0 ? fb.z : 0.0)) / me;
+        // flags bit 0: short non-bonded forces only; bit 2: plus the reciprocal-space forces
+        const bool wb = (op.flags & 1) == 0;
+        const double4 fr = (op.flags & 4) ? V.frec[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+        ax = (fn.x + (wb ? fb.x : 0.0) + fr.x) / me;
+        ay = (fn.y + (wb ? fb.y : 0.0) + fr.y) / me;
+        az = (fn.z + (wb ? fb.z : 0.0) + fr.z) / me;
       }
       chain_op<G, PREC, CB>(V, X, i, r, xi, vx, vy, vz, me, ax, ay, az, op, st, L, iL, ring, pwords, zwords, jring,
                             T, pos);

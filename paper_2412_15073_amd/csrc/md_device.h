@@ -76,9 +76,10 @@ struct MDOp {
   int phase;     // random-stream phase tag (J/C/O)
   int substep;   // O: inner index of the RESPA schemes
   int flags;     // B: bit0 non-bonded, bit1 bonded, bit2 reciprocal, bit3 long real part;
-                 // C: 0 -> a from nb+bonded, 1 -> nb only
+                 // C: 0 -> a from nb+bonded, 1 -> nb only, 4 -> nb+bonded+reciprocal
   double h;      // duration
   double c1, c2; // O: exp(-gamma h), sqrt(1 - c1^2)
+                 // (an O op carries its velocity-trace record index in rstep, -1: none)
   int64_t step;  // random-stream step word (and the label of logged events)
   // J/C proposal stream: words (rstep, rphase); stream 0: from index 0,
   // 1 (MD_STREAM_SAVE): from 0, first unused index kept per atom,
@@ -154,6 +155,18 @@ struct MDView {
   int nk, kmax;
   int ew_ranges, ew_apb, ew_ta;         // structure factor: atom ranges of ew_apb atoms (partials per range), tiles of ew_ta
   int ew_krange;                        // reciprocal forces: k-vectors per range (partials per range)
+  // smooth particle-mesh Ewald (one replica): K0 x K1 x K2 complex grid, influence
+  // function G(m) (zero at m = 0), twiddles exp(2 pi i k / ptw_n) for k < ptw_n / 2
+  int spme, porder;
+  int pk[3];
+  double2 *pgrid;
+  const double *pinf;
+  const double2 *ptw;
+  int ptw_n;
+  // velocity trace: O ops with rstep >= 0 record v of atoms [0, ntrace) into slot rstep % trace_cap
+  double4 *trace;
+  int ntrace;
+  long long trace_cap;
   double ew_fcoef;                      // force prefactor 2 * 4 pi k_e / V (k and -k together)
   // neighbour rows (row-major, fixed capacity)
   int cap_s, cap_f, cap_c;

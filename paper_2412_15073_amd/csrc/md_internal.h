@@ -42,5 +42,7 @@ hipError_t launch_rdf_noalloc(const MDView &V, const double4 *X, const int *rep_
 hipError_t launch_recip(const MDView &V, const double4 *X, double2 *part, double2 *S, double4 *fpart,
                         hipStream_t s);
 void ewald_ranges(int n, int nk, int kmax, int &ranges, int &apb, int &ta, int &krange);
+hipError_t launch_pme_forces(const MDView &V, const double4 *X, hipStream_t s);
+hipError_t launch_pme_energy(const MDView &V, const double4 *X, double *e, hipStream_t s);
 hipError_t launch_ewald_energy(const MDView &V, const double4 *X, double2 *part, double2 *S, double *e,
                                hipStream_t s);

@@ -65,6 +65,8 @@ __global__ __launch_bounds__(256) void k_local(MDView V, MDProg P, const double4
         vx = op.c1 * vx + op.c2 * sd * gx;
         vy = op.c1 * vy + op.c2 * sd * gy;
         vz = op.c1 * vz + op.c2 * sd * gz;
+        if (op.rstep >= 0 && valid && i < V.ntrace)
+          V.trace[(size_t)(op.rstep % V.trace_cap) * V.ntrace + i] = make_double4(vx, vy, vz, 0.0);
       } break;
       case OP_DISP: {
         const double4 xr = V.xref[ii];
@@ -938,8 +940,29 @@ __global__ __launch_bounds__(256) void k_recip_force(MDView V, const double4 *__
   if (i < V.n) fpart[(size_t)blockIdx.y * V.n + i] = make_double4(fx, fy, fz, 0.0);
 }
 
-// Forces = prefactor x (sum of the k-range partials in range order), plus,
-// for every excluded pair, the force of -k_e q_i q_j erf(alpha r) / r
+// Force on atom i of -k_e q_i q_j erf(alpha r) / r over its excluded partners
+// (their real-space term is left out, so their reciprocal-space
+// interaction is taken back)
+__device__ __forceinline__ void excluded_recip_force(const MDView &V, const double4 *__restrict__ X, int i,
+                                                     double4 xi, double &fx, double &fy, double &fz) {
+  if (!V.xptr) return;
+  const double L[3] = {V.box[0], V.box[1], V.box[2]};
+  const double a = V.alpha;
+  for (int e = V.xptr[i]; e < V.xptr[i + 1]; ++e) {
+    const int j = V.xj[e];
+    const double4 xj = X[j];
+    const double dx = min_img(xi.x - xj.x, L[0], 1.0 / L[0]);
+    const double dy = min_img(xi.y - xj.y, L[1], 1.0 / L[1]);
+    const double dz = min_img(xi.z - xj.z, L[2], 1.0 / L[2]);
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double qq = V.ke * xi.w * xj.w;
+    const double dEdr = -qq * (V.two_a_sqpi * exp(-a * a * r * r) / r - erf(a * r) / (r * r));
+    fx -= dEdr * dx / r; fy -= dEdr * dy / r; fz -= dEdr * dz / r;
+  }
+}
+
+// Forces = prefactor x (sum of the k-range partials in range order), plus
+// the excluded-pair correction
 __global__ void k_recip_sum(MDView V, const double4 *__restrict__ X, const double4 *__restrict__ fpart, int nkr) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= V.n) return;
@@ -951,22 +974,182 @@ __global__ void k_recip_sum(MDView V, const double4 *__restrict__ X, const doubl
   }
   const double c = V.ew_fcoef * xi.w;
   fx *= c; fy *= c; fz *= c;
+  excluded_recip_force(V, X, i, xi, fx, fy, fz);
+  V.frec[i] = make_double4(fx, fy, fz, 0.0);
+}
+
+// ------------------------------------------------ smooth particle-mesh Ewald
+// An atom at scaled coordinate u = K x / L = k0 + w (k0 = floor(u)) puts
+// weight M_p(u - k) = M_p(w + j) on grid points k = k0 - j, j = 0..p-1, with
+// M_p the cardinal B-spline of order p. T[j] = M_p(w + j) from the recursion
+// M_n(u) = (u M_{n-1}(u) + (n - u) M_{n-1}(u - 1)) / (n - 1), M_2(u) = 1 - |u - 1|,
+// taken over j from the top so that one array serves every order; the
+// derivative is dM_p(u) = M_{p-1}(u) - M_{p-1}(u - 1).
+template <int P>
+__device__ __forceinline__ void bspline_weights(double w, double *T, double *dT) {
+  T[0] = w;
+  T[1] = 1.0 - w;
+#pragma unroll
+  for (int j = 2; j < P; ++j) T[j] = 0.0;
+#pragma unroll
+  for (int n = 3; n <= P; ++n) {
+    if (n == P && dT) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) dT[j] = T[j] - (j > 0 ? T[j - 1] : 0.0);
+    }
+    const double inv = 1.0 / (n - 1);
+#pragma unroll
+    for (int j = n - 1; j >= 0; --j) T[j] = ((w + j) * T[j] + (j > 0 ? (n - w - j) * T[j - 1] : 0.0)) * inv;
+  }
+}
+
+__device__ __forceinline__ int wrap_index(int k, int K) {
+  k %= K;
+  return k < 0 ? k + K : k;
+}
+
+// charge spreading: one thread per atom, p^3 grid points, atomic sums into
+// the real parts of the (zeroed) complex grid
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_spread(MDView V, const double4 *__restrict__ X) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V.n) return;
+  const double4 x = X[i];
+  if (x.w == 0.0) return;
+  const double xs[3] = {x.x, x.y, x.z};
+  double T[3][P];
+  int k0[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double u = V.pk[d] * xs[d] / V.box[d];
+    const double fl = floor(u);
+    k0[d] = (int)fl;
+    bspline_weights<P>(u - fl, T[d], nullptr);
+  }
+  double *g = (double *)V.pgrid;
+  for (int j0 = 0; j0 < P; ++j0) {
+    const int g0 = wrap_index(k0[0] - j0, V.pk[0]) * V.pk[1];
+    for (int j1 = 0; j1 < P; ++j1) {
+      const int g01 = (g0 + wrap_index(k0[1] - j1, V.pk[1])) * V.pk[2];
+      const double w01 = x.w * T[0][j0] * T[1][j1];
+#pragma unroll
+      for (int j2 = 0; j2 < P; ++j2)
+        unsafeAtomicAdd(g + 2 * (size_t)(g01 + wrap_index(k0[2] - j2, V.pk[2])), w01 * T[2][j2]);
+    }
+  }
+}
+
+// In-place transform F(m) = sum_k x_k exp(+2 pi i m k / N) along one axis of
+// the grid, N a power of two: each line of the axis is loaded into LDS in
+// bit-reversed order and combined in log2 N radix-2 stages (iterative
+// Cooley-Tukey), N / 2 threads per line, several lines per block.
+__global__ __launch_bounds__(256) void k_fft_axis(double2 *__restrict__ g, const double2 *__restrict__ tw, int twn,
+                                                  int K0, int K1, int K2, int axis) {
+  extern __shared__ double2 fbuf[];
+  const int Na = axis == 0 ? K0 : (axis == 1 ? K1 : K2);
+  const int logN = 31 - __clz(Na);
+  const int half = Na >> 1;
+  const int lpb = blockDim.x / half;
+  const int lq = threadIdx.x / half, t = threadIdx.x - lq * half;
+  const int nlines = (K0 * K1 * K2) / Na;
+  const int line = blockIdx.x * lpb + lq;
+  const bool ok = line < nlines;
+  int base, stride;
+  if (axis == 2) { base = line * K2; stride = 1; }
+  else if (axis == 1) { const int a = line / K2, c = line - a * K2; base = a * K1 * K2 + c; stride = K2; }
+  else { base = line; stride = K1 * K2; }
+  double2 *Lb = fbuf + lq * Na;
+  if (ok)
+    for (int e = t; e < Na; e += half) Lb[__brev((unsigned)e) >> (32 - logN)] = g[(size_t)base + (size_t)e * stride];
+  __syncthreads();
+  for (int st = 1; st <= logN; ++st) {
+    const int m = 1 << st, hm = m >> 1;
+    const int grp = t / hm, j = t - grp * hm;
+    const int i0 = grp * m + j, i1 = i0 + hm;
+    if (ok) {
+      const double2 w = tw[j * (twn / m)];
+      const double2 u = Lb[i0], v = Lb[i1];
+      const double vr = v.x * w.x - v.y * w.y, vi = v.x * w.y + v.y * w.x;
+      Lb[i0] = make_double2(u.x + vr, u.y + vi);
+      Lb[i1] = make_double2(u.x - vr, u.y - vi);
+    }
+    __syncthreads();
+  }
+  if (ok)
+    for (int e = t; e < Na; e += half) g[(size_t)base + (size_t)e * stride] = Lb[e];
+}
+
+// grid <- G(m) conj(F(m)); e (if given) receives G(m) |F(m)|^2, the energy terms
+__global__ void k_pme_influence(MDView V, double *__restrict__ e) {
+  const int ng = V.pk[0] * V.pk[1] * V.pk[2];
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= ng) return;
+  const double G = V.pinf[m];
+  const double2 F = V.pgrid[m];
+  if (e) e[m] = G * (F.x * F.x + F.y * F.y);
+  V.pgrid[m] = make_double2(G * F.x, -G * F.y);
+}
+
+// forces from Psi (the real part of the grid after the second transform):
+// f_id = -2 q_i (K_d / L_d) sum_k Psi(k) dM(u_d - k_d) prod_{d' != d} M(u_d' - k_d'),
+// plus the excluded-pair correction
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_gather(MDView V, const double4 *__restrict__ X) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V.n) return;
+  const double4 x = X[i];
+  const double xs[3] = {x.x, x.y, x.z};
+  double T[3][P], D[3][P];
+  int k0[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double u = V.pk[d] * xs[d] / V.box[d];
+    const double fl = floor(u);
+    k0[d] = (int)fl;
+    bspline_weights<P>(u - fl, T[d], D[d]);
+  }
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int j0 = 0; j0 < P; ++j0) {
+    const int g0 = wrap_index(k0[0] - j0, V.pk[0]) * V.pk[1];
+    for (int j1 = 0; j1 < P; ++j1) {
+      const int g01 = (g0 + wrap_index(k0[1] - j1, V.pk[1])) * V.pk[2];
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int j2 = 0; j2 < P; ++j2) {
+        const double psi = V.pgrid[g01 + wrap_index(k0[2] - j2, V.pk[2])].x;
+        a += psi * T[2][j2];
+        b += psi * D[2][j2];
+      }
+      s0 += D[0][j0] * T[1][j1] * a;
+      s1 += T[0][j0] * D[1][j1] * a;
+      s2 += T[0][j0] * T[1][j1] * b;
+    }
+  }
+  double fx = -2.0 * x.w * (V.pk[0] / V.box[0]) * s0;
+  double fy = -2.0 * x.w * (V.pk[1] / V.box[1]) * s1;
+  double fz = -2.0 * x.w * (V.pk[2] / V.box[2]) * s2;
+  excluded_recip_force(V, X, i, x, fx, fy, fz);
+  V.frec[i] = make_double4(fx, fy, fz, 0.0);
+}
+
+// each atom's half of its excluded pairs' correction -k_e q_i q_j erf(alpha r) / r into e[i]
+__global__ void k_excl_energy(MDView V, const double4 *__restrict__ X, double *__restrict__ e) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V.n) return;
+  const double4 xi = X[i];
+  double u = 0.0;
   if (V.xptr) {
     const double L[3] = {V.box[0], V.box[1], V.box[2]};
-    const double a = V.alpha;
-    for (int e = V.xptr[i]; e < V.xptr[i + 1]; ++e) {
-      const int j = V.xj[e];
-      const double4 xj = X[j];
+    for (int q = V.xptr[i]; q < V.xptr[i + 1]; ++q) {
+      const double4 xj = X[V.xj[q]];
       const double dx = min_img(xi.x - xj.x, L[0], 1.0 / L[0]);
       const double dy = min_img(xi.y - xj.y, L[1], 1.0 / L[1]);
       const double dz = min_img(xi.z - xj.z, L[2], 1.0 / L[2]);
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
-      const double qq = V.ke * xi.w * xj.w;
-      const double dEdr = -qq * (V.two_a_sqpi * exp(-a * a * r * r) / r - erf(a * r) / (r * r));
-      fx -= dEdr * dx / r; fy -= dEdr * dy / r; fz -= dEdr * dz / r;
+      u -= 0.5 * V.ke * xi.w * xj.w * erf(V.alpha * r) / r;
     }
   }
-  V.frec[i] = make_double4(fx, fy, fz, 0.0);
+  e[i] = u;
 }
 
 // Ewald energy terms: w_k |S(k)|^2 per k into e[0, nk), and each atom's half
@@ -1218,6 +1401,57 @@ hipError_t launch_ewald_energy(const MDView &V, const double4 *X, double2 *part,
                                hipStream_t s) {
   CHK(launch_sfac(V, X, part, S, s));
   hipLaunchKernelGGL(k_ewald_energy, dim3((V.nk + V.n + 255) / 256), dim3(256), 0, s, V, X, S, e);
+  return hipGetLastError();
+}
+
+// three-dimensional transform: the three axes in turn, N / 2 threads per
+// line and 256 / (N / 2) lines per block (N <= 512)
+static hipError_t launch_fft3(const MDView &V, hipStream_t s) {
+  for (int axis = 2; axis >= 0; --axis) {
+    const int Na = V.pk[axis], half = Na / 2;
+    const int lpb = std::max(1, 256 / half);
+    const int nlines = V.pk[0] * V.pk[1] * V.pk[2] / Na;
+    hipLaunchKernelGGL(k_fft_axis, dim3((nlines + lpb - 1) / lpb), dim3(lpb * half), sizeof(double2) * lpb * Na, s,
+                       V.pgrid, V.ptw, V.ptw_n, V.pk[0], V.pk[1], V.pk[2], axis);
+    CHK(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+// SPME: zeroed grid, spreading, transform, influence function (e: energy
+// terms [NG] or NULL), and for forces the second transform and the gather
+static hipError_t pme_to_influence(const MDView &V, const double4 *X, double *e, hipStream_t s) {
+  const int ng = V.pk[0] * V.pk[1] * V.pk[2];
+  CHK(launch_fill_u64((unsigned long long *)V.pgrid, 2 * ng, 0ull, s));
+  const dim3 ga((V.n + 255) / 256);
+  switch (V.porder) {
+    case 4: hipLaunchKernelGGL(k_pme_spread<4>, ga, dim3(256), 0, s, V, X); break;
+    case 6: hipLaunchKernelGGL(k_pme_spread<6>, ga, dim3(256), 0, s, V, X); break;
+    default: hipLaunchKernelGGL(k_pme_spread<8>, ga, dim3(256), 0, s, V, X); break;
+  }
+  CHK(hipGetLastError());
+  CHK(launch_fft3(V, s));
+  hipLaunchKernelGGL(k_pme_influence, dim3((ng + 255) / 256), dim3(256), 0, s, V, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_pme_forces(const MDView &V, const double4 *X, hipStream_t s) {
+  CHK(pme_to_influence(V, X, nullptr, s));
+  CHK(launch_fft3(V, s));
+  const dim3 ga((V.n + 255) / 256);
+  switch (V.porder) {
+    case 4: hipLaunchKernelGGL(k_pme_gather<4>, ga, dim3(256), 0, s, V, X); break;
+    case 6: hipLaunchKernelGGL(k_pme_gather<6>, ga, dim3(256), 0, s, V, X); break;
+    default: hipLaunchKernelGGL(k_pme_gather<8>, ga, dim3(256), 0, s, V, X); break;
+  }
+  return hipGetLastError();
+}
+
+// energy terms: e[0, NG) = G |F|^2 per grid point, e[NG + i] = atom i's half of its excluded-pair correction
+hipError_t launch_pme_energy(const MDView &V, const double4 *X, double *e, hipStream_t s) {
+  const int ng = V.pk[0] * V.pk[1] * V.pk[2];
+  CHK(pme_to_influence(V, X, e, s));
+  hipLaunchKernelGGL(k_excl_energy, dim3((V.n + 255) / 256), dim3(256), 0, s, V, X, e + ng);
   return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ class MDSplit(C.Structure):
     _fields_ = [("r_s", C.c_double), ("r_c", C.c_double), ("switch_width", C.c_double),
                 ("skin", C.c_double), ("coulomb_alpha", C.c_double),
                 ("n_rings", C.c_int32), ("ring_width", C.c_double),
-                ("coulomb_kind", C.c_int32), ("ewald_kmax", C.c_int32)]
+                ("coulomb_kind", C.c_int32), ("ewald_kmax", C.c_int32),
+                ("pme_grid", C.c_int32 * 3), ("pme_order", C.c_int32)]
 
 
 class MDParams(C.Structure):
@@ -118,7 +119,7 @@ EXPORTS = ["md_create", "md_destroy", "md_last_error", "md_step_baoab", "md_step
            "md_step_jump_respa", "md_step_baoab_respa", "md_step_jump_respa1", "md_step_baoab_respa1", "md_observables", "md_sync", "md_get_state",
            "md_set_state", "md_get_accel", "md_get_atom_stats", "md_get_events", "md_rdf", "md_rdf_noalloc",
            "md_get_cand_row", "md_get_row_counts", "md_run_phase", "md_profile", "md_profile_read",
-           "md_counters", "md_theta_screen_error", "md_tune"]
+           "md_counters", "md_theta_screen_error", "md_tune", "md_trace_velocities", "md_get_trace"]
 
 _lib = None
 
@@ -166,6 +167,8 @@ def load():
                           C.POINTER(C.c_double), C.POINTER(MDTuneTrial), C.c_int32, C.POINTER(C.c_int32)]
     L.md_rdf.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_int32, _dp]
     L.md_rdf_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_int32, _dp]
+    L.md_trace_velocities.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
+    L.md_get_trace.argtypes = [C.c_void_p, _dp, C.c_int64, _lp, _lp]
     L.md_get_cand_row.argtypes = [C.c_void_p, C.c_int32, _ip, _ip, C.c_int32, _ip, _ip]
     L.md_get_row_counts.argtypes = [C.c_void_p, C.c_int32, _ip]
     L.md_run_phase.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double]
@@ -267,7 +270,8 @@ def _marshal_system(system):
 def _marshal_split(split):
     return MDSplit(split.r_s, split.r_c, split.switch_width, split.skin, split.coulomb_alpha,
                    split.n_rings, split.ring_width, getattr(split, "coulomb_kind", 0),
-                   getattr(split, "ewald_kmax", 0))
+                   getattr(split, "ewald_kmax", 0), (C.c_int32 * 3)(*getattr(split, "pme_grid", (0, 0, 0))),
+                   getattr(split, "pme_order", 0))
 
 
 def _marshal_params(params):
@@ -410,6 +414,22 @@ class Sim:
         h = np.zeros(n_bins)
         self._chk(load().md_rdf(self._h, ta, tb, r_max, n_bins, _ptr(h, _dp)))
         return h
+
+    def trace_velocities(self, n_atoms, capacity):
+        """Record the velocities of atoms [0, n_atoms) at every O update (once
+        per smallest time step) into a device ring of `capacity` records;
+        n_atoms = 0 stops."""
+        self._chk(load().md_trace_velocities(self._h, n_atoms, capacity))
+        self._trace = (n_atoms, capacity)
+
+    def trace(self):
+        """(velocities [records, n_atoms, 3] of the last min(recorded,
+        capacity) records in time order, records taken so far)."""
+        na, cap = self._trace
+        out = np.zeros((cap, na, 3))
+        k, tn = C.c_int64(0), C.c_int64(0)
+        self._chk(load().md_get_trace(self._h, _ptr(out, _dp), cap, C.byref(k), C.byref(tn)))
+        return out[:k.value], tn.value
 
     def cand_row(self, i, n_segments, images=False):
         n = C.c_int32(0)

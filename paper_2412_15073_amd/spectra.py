@@ -11,20 +11,22 @@ the mass-weighted spectrum
 
 from velocities sampled every step. By the Wiener-Khinchin theorem it is the
 Fourier transform of the mass-weighted VACF; `vacf` gives that function in
-the time domain. Running it compares JUMP with BAOAB on the same water box
-(run specs as in accuracy.py, e.g. "jump:eps0=0.01;rs=7"):
+the time domain.
+
+Velocities are taken at every smallest time step of every scheme (the
+library's velocity trace records them after each O update, i.e. at mid-step
+of BAOAB and JUMP and at every inner step of the RESPA schemes), as the
+paper does for its multi-time-step spectra (Sec. 4, Figs. 3-4): the Nyquist
+wavenumber is 16678 cm^-1 at 1 fs, so artifacts of the outer steps (the
+resonance peaks that move towards the stretch band as the outer step grows)
+show up where they are. Run specs as in accuracy.py, plus "baoab_respa:n=K",
+"jump_respa:n=K" (outer step K fs), and with --ewald (the same option as in
+accuracy.py, or --pme for the reciprocal sum by particle-mesh Ewald)
+"baoab_respa1:p=P", "jump_respa1:p=P" (1 : m : m P fs, m = 2):
 
     python -m paper_2412_15073_amd.spectra --n-mol 1000 --ps 4 --runs "baoab,jump,jump:eps0=0.01;rs=7"
-
-The RESPA schemes (specs "baoab_respa:n=K", "jump_respa:n=K": bonded forces
-every 1 fs, the rest every K fs) are sampled at their outer step, so their
-spectra reach K-fold lower wavenumbers (Nyquist 16678/K cm^-1, the stretch
-band aliased from K = 5 on); each is compared with the 1 fs BAOAB run
-subsampled at the same interval, so that the aliasing is the same on both
-sides and the difference is that of the integrators (the resonances of
-Sec. 4, Figs. 3-4):
-
-    python -m paper_2412_15073_amd.spectra --n-mol 1000 --ps 8 --runs "baoab,baoab_respa:n=3,jump_respa:n=3"
+    python -m paper_2412_15073_amd.spectra --n-mol 500 --ps 8 --pme 0.554,7,32,6,0.5 \\
+        --runs "baoab,baoab_respa1:p=2,baoab_respa1:p=3,jump_respa1:p=3"
 """
 import argparse
 import json
@@ -77,6 +79,24 @@ def band_summary(nu, p):
     return out
 
 
+def _sample(sim, step, n_calls, per_call, n_atoms, chunk):
+    """Velocities [n_calls * per_call, n_atoms, 3] from the trace, fetched in
+    chunks of `chunk` calls; None if the run turned unstable."""
+    sim.trace_velocities(n_atoms, chunk * per_call)
+    out = []
+    done = 0
+    while done < n_calls:
+        k = min(chunk, n_calls - done)
+        step(k)
+        rec, _ = sim.trace()
+        rec = rec[-k * per_call:]
+        if not np.isfinite(rec).all():
+            return None
+        out.append(rec.copy())
+        done += k
+    return np.concatenate(out)
+
+
 def main():
     from . import jumpmd, systems as S
     ap = argparse.ArgumentParser()
@@ -85,11 +105,27 @@ def main():
     ap.add_argument("--equil-ps", type=float, default=5.0)
     ap.add_argument("--runs", default="baoab,jump")
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--ewald", default="", metavar="ALPHA,RC,KMAX[,W]")
+    ap.add_argument("--pme", default="", metavar="ALPHA,RC,GRID,ORDER[,W]")
     a = ap.parse_args()
 
+    ew = [float(x) for x in a.ewald.split(",")] if a.ewald else None
+    pme = [float(x) for x in a.pme.split(",")] if a.pme else None
+    ew = ew or (pme[:2] + [0.0] + pme[4:] if pme else None)
+
+    def make_split(rs):
+        if not ew:
+            return S.water_split(r_s=rs, r_c=10.0, w=1.0, skin=0.5, n_rings=12)
+        sp = S.water_split(r_s=rs, r_c=ew[1], w=ew[3] if len(ew) > 3 else 1.0, skin=0.5, alpha=ew[0],
+                           n_rings=12)
+        if pme:
+            sp.coulomb_kind, sp.pme_grid, sp.pme_order = S.COUL_SPME, (int(pme[2]),) * 3, int(pme[3])
+        else:
+            sp.coulomb_kind, sp.ewald_kmax = S.COUL_EWALD, int(ew[2])
+        return sp
+
     sysm = S.water_box(a.n_mol, seed=a.seed)
-    split = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=0.5, n_rings=12)
-    eq = jumpmd.Sim(sysm, split, S.water_params(dt=0.0005, gamma=10.0, jumps=False, seed=a.seed))
+    eq = jumpmd.Sim(sysm, make_split(5.0), S.water_params(dt=0.0005, gamma=10.0, jumps=False, seed=a.seed))
     eq.step_baoab(int(round(a.equil_ps / 0.0005)))
     x, v = eq.state()
     eq.close()
@@ -98,47 +134,53 @@ def main():
     dt = 0.001
     n = int(round(a.ps / dt))
     res, spectra_ = {}, {}
-    v_baoab = None
     for spec in a.runs.split(","):
         name, _, opts = spec.partition(":")
         kv = dict(x.split("=") for x in opts.split(";") if x)
         jumps = name.startswith("jump")
         respa = name.endswith("_respa")
-        k_out = int(kv.get("n", 3)) if respa else 1
-        sp = S.water_split(r_s=float(kv.get("rs", 5.0)), r_c=10.0, w=1.0, skin=0.5, n_rings=12)
+        respa1 = name.endswith("_respa1")
+        m = int(kv.get("n", 3)) if respa else (int(kv.get("m", 2)) if respa1 else 1)
+        p_out = int(kv.get("p", 3)) if respa1 else 1
+        per_call = m * p_out                         # smallest steps per call
         pa = S.water_params(dt=dt, jumps=jumps, eps0_per_kcal=float(kv.get("eps0", 0.1)), seed=a.seed + 1)
-        pa.respa_inner = k_out
-        sim = jumpmd.Sim(sysm, sp, pa)
+        pa.respa_inner, pa.respa_outer = m, p_out
+        sim = jumpmd.Sim(sysm, make_split(float(kv.get("rs", 5.0))), pa)
         step = {"baoab": sim.step_baoab, "jump": sim.step_jump, "baoab_respa": sim.step_baoab_respa,
-                "jump_respa": sim.step_jump_respa}[name]
-        n_s = n // k_out
-        vs = np.empty((n_s, sysm.n_atoms, 3))
-        for t in range(n_s):
-            step(1)
-            vs[t] = sim.state()[1]
+                "jump_respa": sim.step_jump_respa, "baoab_respa1": sim.step_baoab_respa1,
+                "jump_respa1": sim.step_jump_respa1}[name]
+        try:
+            vs = _sample(sim, step, n // per_call, per_call, sysm.n_atoms, max(1, 1000 // per_call))
+        except jumpmd.MDError as e:
+            vs = None
+            print(f"[spectra] {spec}: {e}", flush=True)
         sim.close()
-        if name == "baoab":
-            v_baoab = vs
-        nu, p = spectrum(vs, dt * k_out, sysm.mass)
-        spectra_[spec] = (k_out, p)
-        c = vacf(vs, sysm.mass, n_lags=max(2, 200 // k_out))
-        res[spec] = {"bands": band_summary(nu, p), "sample_fs": k_out,
-                     "nyquist_cm": float(CM_PER_PS / (2 * dt * k_out)),
-                     "vacf_zero_crossing_fs": int(np.argmax(c < 0)) * k_out}
+        outer_fs = dt * 1e3 * per_call
+        if vs is None:
+            res[spec] = {"unstable": True, "outer_step_fs": outer_fs}
+            print(f"[spectra] {spec}: unstable", flush=True)
+            continue
+        nu, p = spectrum(vs, dt, sysm.mass)
+        spectra_[spec] = p
+        c = vacf(vs, sysm.mass, n_lags=200)
+        hi = nu >= BANDS["above_stretch"][0]
+        res[spec] = {"bands": band_summary(nu, p), "outer_step_fs": outer_fs,
+                     "nyquist_cm": float(CM_PER_PS / (2 * dt)),
+                     "artifact_peak_cm": float(nu[hi][np.argmax(p[hi])]),
+                     "vacf_zero_crossing_fs": int(np.argmax(c < 0))}
         print(f"[spectra] {spec}: " + ", ".join(
-            f"{k} {b['weight']:.3f}" + (f" @ {b['peak_cm']:.0f}" if b["peak_cm"] else "")
-            for k, b in res[spec]["bands"].items()), flush=True)
-    if v_baoab is not None:
-        for k, (k_out, p) in spectra_.items():
-            if k == "baoab":
-                continue
-            # the reference at the same sampling interval (same aliasing)
-            nu_r, p_r = spectrum(v_baoab[k_out - 1::k_out], dt * k_out, sysm.mass)
-            m = min(len(p), len(p_r))
-            res[k]["l1_vs_baoab"] = float(np.abs(p[:m] - p_r[:m]).sum())
-            if k_out > 1:
-                res[k]["baoab_subsampled_bands"] = band_summary(nu_r, p_r)
+            f"{k} {b['weight']:.4f}" + (f" @ {b['peak_cm']:.0f}" if b["peak_cm"] else "")
+            for k, b in res[spec]["bands"].items()) + f", artifact peak @ {res[spec]['artifact_peak_cm']:.0f}",
+            flush=True)
+    if "baoab" in spectra_:
+        for k, p in spectra_.items():
+            if k != "baoab":
+                res[k]["l1_vs_baoab"] = float(np.abs(p - spectra_["baoab"]).sum())
     print(json.dumps({"workload": f"water_{a.n_mol}mol", "ps_each": a.ps, "resolution_cm": CM_PER_PS / a.ps,
+                      "electrostatics": ({"kind": "SPME", "alpha": ew[0], "r_c": ew[1], "grid": int(pme[2]),
+                                          "order": int(pme[3])} if pme else
+                                         {"kind": "Ewald", "alpha": ew[0], "r_c": ew[1], "kmax": int(ew[2])}
+                                         if ew else {"kind": "DSF", "alpha": 0.2, "r_c": 10.0}),
                       "runs": res}), flush=True)
 
 

@@ -19,6 +19,7 @@ import numpy as np
 
 # jump kinds (same numbering on both sides of the boundary)
 JUMP_NONE, JUMP_BPS, JUMP_MRZ_CONST, JUMP_MRZ_ADAPTIVE, JUMP_BOUNCE = 0, 1, 2, 3, 4
+COUL_DSF, COUL_EWALD, COUL_SPME = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 
 # water units: Angstrom, ps, amu, kJ/mol, e
@@ -63,8 +64,11 @@ class Split:
     coulomb_alpha: float = 0.0
     n_rings: int = 1
     ring_width: float = 0.0
-    coulomb_kind: int = 0     # 0: damped shifted-force Coulomb; 1: the same plus the Ewald reciprocal sum
+    coulomb_kind: int = 0     # 0: damped shifted-force Coulomb; 1: the same plus the Ewald reciprocal sum;
+                              # 2: the same with the reciprocal sum by smooth particle-mesh Ewald
     ewald_kmax: int = 0       # Ewald: lattice vectors n with 0 < |n|^2 <= kmax^2
+    pme_grid: tuple = (0, 0, 0)   # SPME: grid points per box edge (powers of two on the GPU)
+    pme_order: int = 0        # SPME: B-spline order (4, 6 or 8)
 
 
 @dataclass

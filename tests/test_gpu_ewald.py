@@ -2,8 +2,8 @@
 the oracle: reciprocal-space forces (plain Ewald sum over the half space of
 k-vectors, excluded-pair correction) and the long real-space part within
 1e-12, energies within 1e-9, and BAOAB, JUMP-RESPA1 (1:2:6 fs, Sec. 2.3.2,
-Table 2) and BAOAB-RESPA1 runs with identical jump events and FP64 state
-within 1e-9."""
+Table 2), BAOAB-RESPA1 and plain JUMP (reciprocal forces in the C'
+acceleration) runs with identical jump events and FP64 state within 1e-9."""
 import numpy as np
 import pytest
 
@@ -104,10 +104,35 @@ def test_baoab_respa1_trajectory(jm):
     assert rel_err(xg, xo) < TOL and rel_err(vg, vo) < TOL
 
 
+@pytest.mark.parametrize("lanes,graph", [(2, 0), (8, 4)])
+def test_jump_with_ewald_trajectory(jm, lanes, graph):
+    """Plain JUMP with Ewald electrostatics: MRZ jumps of the damped
+    real-space long part, the C' acceleration with the reciprocal-space
+    forces re-evaluated every step; 12 steps (in HIP-graph chunks of 4 where
+    set) with identical events and FP64 state within 1e-9."""
+    sy, sp = _ewald_water(seed=15)
+    pa = S.water_params()
+    pa.log_events = 1
+    pa.chain_lanes = lanes
+    pa.graph_steps = graph
+    g, o = _pair(jm, sy, sp, pa)
+    g.step_jump(12)
+    o.step_jump(12)
+    xg, vg = g.state()
+    xo, vo = o.state()
+    assert rel_err(xg, xo) < TOL and rel_err(vg, vo) < TOL
+    sg, so = g.atom_stats(), o.atom_stats()
+    for k in ("n_prop", "n_acc", "hash"):
+        np.testing.assert_array_equal(sg[k], so[k], err_msg=k)
+    ev = o.events()
+    assert len(ev) > 1000
+    np.testing.assert_array_equal(g.events(), ev)
+
+
 def test_ewald_refuses_other_schemes(jm):
     sy, sp = _ewald_water(seed=14)
     g = jm.Sim(sy, sp, S.water_params())
-    for fn in (g.step_jump, g.step_jump_respa, g.step_baoab_respa):
+    for fn in (g.step_jump_respa, g.step_baoab_respa):
         with pytest.raises(jm.MDError) as e:
             fn(1)
         assert e.value.code == jm.MD_ERR_ARG

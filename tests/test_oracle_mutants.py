@@ -28,6 +28,14 @@ PLANTS = {
         ["test_rdf_counts_on_rock_salt_lattice"]),
     5: ("BOUNCE chain without the Coulomb gradient",
         ["test_bounce_j_step_mean_kick_equals_whole_long_force"]),
+    6: ("JUMP with Ewald: reciprocal forces left out of the C' acceleration",
+        ["test_jump_with_ewald_and_no_long_pairs_is_baoab"]),
+    7: ("Ewald sum without the excluded-pair correction",
+        ["test_ewald_sum_independent_of_alpha"]),
+    8: ("SPME influence function without the B-spline correction",
+        ["test_spme_converges_to_the_ewald_sum"]),
+    9: ("SPME y force from the B-spline values instead of their derivative",
+        ["test_spme_forces_are_minus_energy_gradient", "test_spme_converges_to_the_ewald_sum"]),
 }
 
 

@@ -926,6 +926,30 @@ def test_ewald_madelung_constant_of_rock_salt():
     assert e["pe_recip"] != 0.0
 
 
+@pytest.mark.parametrize("coul", ["mrz", "none"])
+def test_jump_with_ewald_and_no_long_pairs_is_baoab(coul):
+    """JUMP with Ewald electrostatics: the C' acceleration (or, without
+    Coulomb jumps, the kick) carries the reciprocal-space forces, re-evaluated
+    every step. Two charges 3.5 apart, the switch confined to [4.85, 4.9] =
+    r_c: no pair or candidate reaches the long part, so C' J' A O A J' C' is
+    B A O A B with the same forces and JUMP follows BAOAB to rounding. A
+    dropped, doubled or stale reciprocal term fails (the reciprocal forces
+    are a sizeable part of the total)."""
+    sy = S.two_charges(L=10.0776, r0=3.5)
+    sp = S.Split(r_s=4.9, r_c=4.9, switch_width=0.05, skin=0.3, coulomb_alpha=0.6, coulomb_kind=1, ewald_kmax=8)
+    pa = S.Params(dt=0.005, gamma=2.0, kT=0.722, seed=5, jump_lj=O.JUMP_BPS,
+                  jump_coul=O.JUMP_MRZ_ADAPTIVE if coul == "mrz" else 0, eps=0.5)
+    o1, o2 = _oracle(sy, sp, pa), _oracle(sy, sp, pa)
+    fr, ff = o1.accel(O.F_RECIP), o1.accel(O.F_FULL)
+    assert np.abs(fr).max() > 0.05 * np.abs(ff).max()
+    o1.step_baoab(40)
+    o2.step_jump(40)
+    x1, v1 = o1.state()
+    x2, v2 = o2.state()
+    assert rel_err(x2, x1) < 1e-12 and rel_err(v2, v1) < 1e-12
+    assert o2.atom_stats()["n_prop"].sum() == 0
+
+
 def _ewald_water(alpha, kmax, seed=9):
     sy = S.water_box(125, seed=seed, jitter=0.05)
     sp = S.water_split(r_s=5.0, r_c=7.5, w=1.0, skin=0.3, alpha=alpha, n_rings=3)
@@ -950,6 +974,53 @@ def test_ewald_sum_independent_of_alpha():
     assert abs(r1 - r2) > 1.0                       # the split moved energy between the parts
     assert abs(e1 - e2) < 1e-9 * abs(e1), (e1, e2)
     assert rel_err(f1, f2) < 1e-8
+
+
+def _spme_water(grid, order, alpha=0.3, seed=9):
+    sy, sp = _ewald_water(alpha, 0, seed)
+    sp.coulomb_kind, sp.pme_grid, sp.pme_order = O.COUL_SPME, grid, order
+    return sy, sp
+
+
+def test_spme_converges_to_the_ewald_sum():
+    """Smooth particle-mesh Ewald approximates the plain reciprocal sum (its
+    own pins above) by B-spline interpolation of the structure factor: on
+    125 waters the reciprocal energy and forces agree with the converged
+    plain sum to 1e-7 on a 32^3 grid with order 8, and the error falls as
+    the grid and the order grow (16^3, order 4: about 1 %)."""
+    sy, sp = _ewald_water(0.3, 12)
+    ref = _oracle(sy, sp, S.water_params())
+    e0, f0 = ref.energies()["pe_recip"], ref.accel(O.F_RECIP)
+    errs = []
+    for grid, order in (((16, 16, 16), 4), ((32, 32, 32), 8)):
+        sy2, sp2 = _spme_water(grid, order)
+        o = _oracle(sy2, sp2, S.water_params())
+        e, f = o.energies()["pe_recip"], o.accel(O.F_RECIP)
+        errs.append((abs(e - e0) / abs(e0), rel_err(f, f0)))
+    assert errs[1][0] < 1e-7 and errs[1][1] < 5e-8, errs
+    assert errs[0][0] > 100 * errs[1][0] and errs[0][1] > 100 * errs[1][1], errs
+
+
+def test_spme_forces_are_minus_energy_gradient():
+    """SPME forces (B-spline derivatives on the transformed grid) are minus
+    the gradient of the SPME energy (central differences), on a grid that is
+    not cubic."""
+    sy, sp = _spme_water((16, 32, 16), 6)
+    o = _oracle(sy, sp, S.water_params())
+    me = sy.mass / sy.accel_factor
+    fr = o.accel(O.F_RECIP) * me[:, None]
+    h = 1e-5
+    for i in (0, 1, 200):
+        for c in range(3):
+            xp, xm = sy.pos.copy(), sy.pos.copy()
+            xp[i, c] += h
+            xm[i, c] -= h
+            o.set_state(pos=xp)
+            ep = o.energies()["pe_recip"]
+            o.set_state(pos=xm)
+            em = o.energies()["pe_recip"]
+            fd = -(ep - em) / (2 * h)
+            assert abs(fr[i, c] - fd) < 1e-6 * max(1.0, abs(fd)), (i, c, fr[i, c], fd)
 
 
 def test_ewald_forces_are_minus_energy_gradient():
