@@ -218,11 +218,12 @@ struct ProgBuilder {
   MDProg P;
   bool has_a = false, has_chain_after_a = false;
   ProgBuilder() { memset(&P, 0, sizeof(P)); P.reset_slot = -1; P.disp_slot = 0; }
-  // ops with their own proposal stream get the words (step, phase)
+  // jump ops with their own proposal stream get the words (step, phase); an
+  // O op keeps its velocity-trace record index in rstep
   void add(MDOp o) {
     if (o.kind == OP_A) has_a = true;
     if ((o.kind == OP_J || o.kind == OP_C) && has_a) has_chain_after_a = true;
-    if (o.stream != MD_STREAM_CONTINUE) { o.rstep = o.step; o.rphase = o.phase; }
+    if ((o.kind == OP_J || o.kind == OP_C) && o.stream != MD_STREAM_CONTINUE) { o.rstep = o.step; o.rphase = o.phase; }
     P.ops[P.nops++] = o;
   }
 };

@@ -1008,12 +1008,14 @@ __device__ __forceinline__ int wrap_index(int k, int K) {
   return k < 0 ? k + K : k;
 }
 
-// charge spreading: one thread per atom, p^3 grid points, atomic sums into
-// the real parts of the (zeroed) complex grid
+// charge spreading: 8 lanes per atom, lane j0 < p the p^2 grid points of
+// the slice k0 - j0 along the first axis, atomic sums into the real parts of
+// the (zeroed) complex grid
 template <int P>
 __global__ __launch_bounds__(256) void k_pme_spread(MDView V, const double4 *__restrict__ X) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= V.n) return;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = gid >> 3, j0 = gid & 7;
+  if (i >= V.n || j0 >= P) return;
   const double4 x = X[i];
   if (x.w == 0.0) return;
   const double xs[3] = {x.x, x.y, x.z};
@@ -1027,15 +1029,16 @@ __global__ __launch_bounds__(256) void k_pme_spread(MDView V, const double4 *__r
     bspline_weights<P>(u - fl, T[d], nullptr);
   }
   double *g = (double *)V.pgrid;
-  for (int j0 = 0; j0 < P; ++j0) {
-    const int g0 = wrap_index(k0[0] - j0, V.pk[0]) * V.pk[1];
-    for (int j1 = 0; j1 < P; ++j1) {
-      const int g01 = (g0 + wrap_index(k0[1] - j1, V.pk[1])) * V.pk[2];
-      const double w01 = x.w * T[0][j0] * T[1][j1];
+  double t0 = 0.0;
 #pragma unroll
-      for (int j2 = 0; j2 < P; ++j2)
-        unsafeAtomicAdd(g + 2 * (size_t)(g01 + wrap_index(k0[2] - j2, V.pk[2])), w01 * T[2][j2]);
-    }
+  for (int j = 0; j < P; ++j) t0 = j == j0 ? T[0][j] : t0;
+  const int g0 = wrap_index(k0[0] - j0, V.pk[0]) * V.pk[1];
+  for (int j1 = 0; j1 < P; ++j1) {
+    const int g01 = (g0 + wrap_index(k0[1] - j1, V.pk[1])) * V.pk[2];
+    const double w01 = x.w * t0 * T[1][j1];
+#pragma unroll
+    for (int j2 = 0; j2 < P; ++j2)
+      unsafeAtomicAdd(g + 2 * (size_t)(g01 + wrap_index(k0[2] - j2, V.pk[2])), w01 * T[2][j2]);
   }
 }
 
@@ -1050,7 +1053,10 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2 *__restrict__ g, const
   const int logN = 31 - __clz(Na);
   const int half = Na >> 1;
   const int lpb = blockDim.x / half;
-  const int lq = threadIdx.x / half, t = threadIdx.x - lq * half;
+  // contiguous axis: a line's elements on consecutive threads; strided axes:
+  // consecutive lines (adjacent in memory) on consecutive threads
+  const int lq = axis == 2 ? (int)threadIdx.x / half : (int)threadIdx.x % lpb;
+  const int t = axis == 2 ? (int)threadIdx.x - lq * half : (int)threadIdx.x / lpb;
   const int nlines = (K0 * K1 * K2) / Na;
   const int line = blockIdx.x * lpb + lq;
   const bool ok = line < nlines;
@@ -1058,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2 *__restrict__ g, const
   if (axis == 2) { base = line * K2; stride = 1; }
   else if (axis == 1) { const int a = line / K2, c = line - a * K2; base = a * K1 * K2 + c; stride = K2; }
   else { base = line; stride = K1 * K2; }
-  double2 *Lb = fbuf + lq * Na;
+  double2 *Lb = fbuf + lq * (Na + 1);   // one element of padding per line (LDS banks)
   if (ok)
     for (int e = t; e < Na; e += half) Lb[__brev((unsigned)e) >> (32 - logN)] = g[(size_t)base + (size_t)e * stride];
   __syncthreads();
@@ -1092,11 +1098,14 @@ __global__ void k_pme_influence(MDView V, double *__restrict__ e) {
 
 // forces from Psi (the real part of the grid after the second transform):
 // f_id = -2 q_i (K_d / L_d) sum_k Psi(k) dM(u_d - k_d) prod_{d' != d} M(u_d' - k_d'),
-// plus the excluded-pair correction
+// 8 lanes per atom (lane j0 < p sums the slice k0 - j0, then a shuffle
+// reduction), plus the excluded-pair correction
 template <int P>
 __global__ __launch_bounds__(256) void k_pme_gather(MDView V, const double4 *__restrict__ X) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= V.n) return;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i0 = gid >> 3, j0 = gid & 7;
+  const bool live = i0 < V.n;
+  const int i = live ? i0 : V.n - 1;
   const double4 x = X[i];
   const double xs[3] = {x.x, x.y, x.z};
   double T[3][P], D[3][P];
@@ -1109,7 +1118,13 @@ __global__ __launch_bounds__(256) void k_pme_gather(MDView V, const double4 *__r
     bspline_weights<P>(u - fl, T[d], D[d]);
   }
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int j0 = 0; j0 < P; ++j0) {
+  if (j0 < P) {
+    double t0 = 0.0, d0 = 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      t0 = j == j0 ? T[0][j] : t0;
+      d0 = j == j0 ? D[0][j] : d0;
+    }
     const int g0 = wrap_index(k0[0] - j0, V.pk[0]) * V.pk[1];
     for (int j1 = 0; j1 < P; ++j1) {
       const int g01 = (g0 + wrap_index(k0[1] - j1, V.pk[1])) * V.pk[2];
@@ -1120,11 +1135,18 @@ __global__ __launch_bounds__(256) void k_pme_gather(MDView V, const double4 *__r
         a += psi * T[2][j2];
         b += psi * D[2][j2];
       }
-      s0 += D[0][j0] * T[1][j1] * a;
-      s1 += T[0][j0] * D[1][j1] * a;
-      s2 += T[0][j0] * T[1][j1] * b;
+      s0 += d0 * T[1][j1] * a;
+      s1 += t0 * D[1][j1] * a;
+      s2 += t0 * T[1][j1] * b;
     }
   }
+#pragma unroll
+  for (int off = 4; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off, 8);
+    s1 += __shfl_xor(s1, off, 8);
+    s2 += __shfl_xor(s2, off, 8);
+  }
+  if (!live || j0 != 0) return;
   double fx = -2.0 * x.w * (V.pk[0] / V.box[0]) * s0;
   double fy = -2.0 * x.w * (V.pk[1] / V.box[1]) * s1;
   double fz = -2.0 * x.w * (V.pk[2] / V.box[2]) * s2;
@@ -1411,7 +1433,7 @@ static hipError_t launch_fft3(const MDView &V, hipStream_t s) {
     const int Na = V.pk[axis], half = Na / 2;
     const int lpb = std::max(1, 256 / half);
     const int nlines = V.pk[0] * V.pk[1] * V.pk[2] / Na;
-    hipLaunchKernelGGL(k_fft_axis, dim3((nlines + lpb - 1) / lpb), dim3(lpb * half), sizeof(double2) * lpb * Na, s,
+    hipLaunchKernelGGL(k_fft_axis, dim3((nlines + lpb - 1) / lpb), dim3(lpb * half), sizeof(double2) * lpb * (Na + 1), s,
                        V.pgrid, V.ptw, V.ptw_n, V.pk[0], V.pk[1], V.pk[2], axis);
     CHK(hipGetLastError());
   }
@@ -1423,7 +1445,7 @@ static hipError_t launch_fft3(const MDView &V, hipStream_t s) {
 static hipError_t pme_to_influence(const MDView &V, const double4 *X, double *e, hipStream_t s) {
   const int ng = V.pk[0] * V.pk[1] * V.pk[2];
   CHK(launch_fill_u64((unsigned long long *)V.pgrid, 2 * ng, 0ull, s));
-  const dim3 ga((V.n + 255) / 256);
+  const dim3 ga((8 * V.n + 255) / 256);   // 8 lanes per atom
   switch (V.porder) {
     case 4: hipLaunchKernelGGL(k_pme_spread<4>, ga, dim3(256), 0, s, V, X); break;
     case 6: hipLaunchKernelGGL(k_pme_spread<6>, ga, dim3(256), 0, s, V, X); break;
@@ -1438,7 +1460,7 @@ static hipError_t pme_to_influence(const MDView &V, const double4 *X, double *e,
 hipError_t launch_pme_forces(const MDView &V, const double4 *X, hipStream_t s) {
   CHK(pme_to_influence(V, X, nullptr, s));
   CHK(launch_fft3(V, s));
-  const dim3 ga((V.n + 255) / 256);
+  const dim3 ga((8 * V.n + 255) / 256);   // 8 lanes per atom
   switch (V.porder) {
     case 4: hipLaunchKernelGGL(k_pme_gather<4>, ga, dim3(256), 0, s, V, X); break;
     case 6: hipLaunchKernelGGL(k_pme_gather<6>, ga, dim3(256), 0, s, V, X); break;

@@ -14,6 +14,11 @@ point (and per reference), so that a long grid can be run in pieces.
 
     python -m paper_2412_15073_amd.frontier --rs 5,7,9 --eps0 0.003,0.01,0.03,0.1 --seeds 7,8
 
+With --pme ALPHA,RC,GRID,ORDER,W the electrostatics are Ewald (damped real
+part to RC, particle-mesh reciprocal sum every step in JUMP's acceleration
+and BAOAB's kicks), e.g. the paper's settings for its 12 000-atom water:
+--pme 0.554,7,64,6,0.5 --rs 5,6.
+
 The reference runs (FP64 BAOAB at 1 fs, and at 0.5 fs as a check of the
 1 fs reference's own time-step error) are printed first. `--summarize`
 reads such JSON lines back (from any number of logs) and prints the table
@@ -81,13 +86,24 @@ def main():
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--ref-dt", default="1.0,0.5", help="time steps (fs) of the FP64 BAOAB references")
     ap.add_argument("--summarize", nargs="+", metavar="LOG", help="summarise logs of earlier runs and exit")
+    ap.add_argument("--pme", default="", metavar="ALPHA,RC,GRID,ORDER,W",
+                    help="Ewald electrostatics (particle-mesh reciprocal sum) instead of DSF to 10 A")
     a = ap.parse_args()
     if a.summarize:
         summarize(a.summarize)
         return
 
     seeds = [int(x) for x in a.seeds.split(",")]
-    split_eq = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=1.0, n_rings=a.rings)
+    pme = [float(x) for x in a.pme.split(",")] if a.pme else None
+
+    def make_split(rs, skin):
+        if not pme:
+            return S.water_split(r_s=rs, r_c=10.0, w=1.0, skin=skin, n_rings=a.rings)
+        sp = S.water_split(r_s=rs, r_c=pme[1], w=pme[4], skin=skin, alpha=pme[0], n_rings=a.rings)
+        sp.coulomb_kind, sp.pme_grid, sp.pme_order = S.COUL_SPME, (int(pme[2]),) * 3, int(pme[3])
+        return sp
+
+    split_eq = make_split(5.0, 1.0)
     starts = {s: equilibrated(a.n_mol, s, a.equil_ps, split_eq) for s in seeds}
     L = float(starts[seeds[0]].box[0])
     r_max, n_bins = min(0.5 * L, 12.0), 120
@@ -118,22 +134,23 @@ def main():
         return per, ms
 
     if not a.no_reference:
-        split_b = S.water_split(r_s=5.0, r_c=10.0, w=1.0, skin=1.0, n_rings=a.rings)
+        split_b = make_split(5.0, 1.0)
         for dt_fs in [float(x) for x in a.ref_dt.split(",")]:
             per, ms = measure(split_b, S.water_params(dt=dt_fs * 1e-3, jumps=False), "baoab")
-            print(json.dumps({"point": "baoab_fp64", "dt_fs": dt_fs, "ms_per_step": ms,
+            print(json.dumps({"point": "baoab_fp64", "dt_fs": dt_fs, "ms_per_step": ms, "pme": a.pme or None,
                               "ns_per_day": 86.4 * dt_fs / ms, "r_max": r_max,
                               "per_seed": [{"T": q["T"], "D": q["D"], "D_err": q["D_err"], "g": q["g"].tolist()}
                                            for q in per]}), flush=True)
 
     for rs in [float(x) for x in a.rs.split(",")]:
         for eps0 in [float(x) for x in a.eps0.split(",")]:
-            split = S.water_split(r_s=rs, r_c=10.0, w=1.0, skin=a.skin, n_rings=a.rings)
+            split = make_split(rs, a.skin)
             pa = S.water_params(eps0_per_kcal=eps0)
             pa.precision = S.FP32_MIXED
             t0 = time.perf_counter()
             per, ms = measure(split, pa, "jump")
             print(json.dumps({"point": "jump_fp32", "r_s": rs, "eps0": eps0, "dt_fs": 1.0, "ms_per_step": ms,
+                              "pme": a.pme or None,
                               "ns_per_day": 86.4 / ms, "wall_s": time.perf_counter() - t0,
                               "per_seed": [{"T": q["T"], "D": q["D"], "D_err": q["D_err"], "g": q["g"].tolist()}
                                            for q in per]}), flush=True)
@@ -162,6 +179,16 @@ def summarize(logs):
                 line = line.strip()
                 if line.startswith("{") and '"point"' in line:
                     pts.append(json.loads(line))
+    kinds = sorted({str(p.get("pme")) for p in pts})
+    if len(kinds) > 1:   # one table per electrostatics
+        for k in kinds:
+            print(f"electrostatics: {'DSF, r_c 10 A' if k == 'None' else 'Ewald ' + k}")
+            _table([p for p in pts if str(p.get("pme")) == k])
+        return
+    _table(pts)
+
+
+def _table(pts):
     refs = {p["dt_fs"]: p for p in pts if p["point"] == "baoab_fp64"}
     ref = refs.get(1.0)
     assert ref is not None, "no 1 fs BAOAB reference in the logs"

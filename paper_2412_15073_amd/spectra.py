@@ -150,7 +150,8 @@ def main():
                 "jump_respa": sim.step_jump_respa, "baoab_respa1": sim.step_baoab_respa1,
                 "jump_respa1": sim.step_jump_respa1}[name]
         try:
-            vs = _sample(sim, step, n // per_call, per_call, sysm.n_atoms, max(1, 1000 // per_call))
+            vs = _sample(sim, step, -(-n // per_call), per_call, sysm.n_atoms, max(1, 1000 // per_call))
+            vs = vs[:n] if vs is not None else None   # the same record count in every run
         except jumpmd.MDError as e:
             vs = None
             print(f"[spectra] {spec}: {e}", flush=True)
@@ -164,7 +165,17 @@ def main():
         spectra_[spec] = p
         c = vacf(vs, sysm.mass, n_lags=200)
         hi = nu >= BANDS["above_stretch"][0]
-        res[spec] = {"bands": band_summary(nu, p), "outer_step_fs": outer_fs,
+        # weight near the harmonics of the outer-step frequency (the impulse
+        # resonances of the multi-time-step schemes), +-300 cm^-1, below Nyquist
+        nu_out = CM_PER_PS / (outer_fs * 1e-3)
+        wins = {}
+        if per_call > 1:
+            for k in range(1, 5):
+                c0 = k * nu_out
+                if c0 + 300.0 < CM_PER_PS / (2 * dt):
+                    sel = (nu > c0 - 300.0) & (nu < c0 + 300.0)
+                    wins[f"{c0:.0f}"] = float(p[sel].sum())
+        res[spec] = {"bands": band_summary(nu, p), "outer_step_fs": outer_fs, "outer_harmonics": wins,
                      "nyquist_cm": float(CM_PER_PS / (2 * dt)),
                      "artifact_peak_cm": float(nu[hi][np.argmax(p[hi])]),
                      "vacf_zero_crossing_fs": int(np.argmax(c < 0))}
@@ -176,6 +187,8 @@ def main():
         for k, p in spectra_.items():
             if k != "baoab":
                 res[k]["l1_vs_baoab"] = float(np.abs(p - spectra_["baoab"]).sum())
+                print(f"[spectra] {k}: L1 vs BAOAB {res[k]['l1_vs_baoab']:.4f}, outer-step harmonics "
+                      + ", ".join(f"{c} cm^-1: {w:.4f}" for c, w in res[k]["outer_harmonics"].items()), flush=True)
     print(json.dumps({"workload": f"water_{a.n_mol}mol", "ps_each": a.ps, "resolution_cm": CM_PER_PS / a.ps,
                       "electrostatics": ({"kind": "SPME", "alpha": ew[0], "r_c": ew[1], "grid": int(pme[2]),
                                           "order": int(pme[3])} if pme else

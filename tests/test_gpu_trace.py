@@ -84,6 +84,37 @@ def test_trace_counts_and_unchanged_trajectory(jm, scheme, m, p):
     assert np.abs(v1 - v0).max() <= 1e-14 * np.abs(v0).max()
 
 
+@pytest.mark.parametrize("scheme", ["baoab_respa", "baoab_respa1"])
+def test_respa_records_are_the_last_inner_step_velocities(jm, scheme):
+    """The record of the last inner step of an outer step is the velocity
+    after its O update: the end-of-step velocity minus the kicks that follow
+    it (inner bonded half kick; BAOAB-RESPA: the full non-bonded outer half
+    kick; BAOAB-RESPA1: the short middle half kick and the reciprocal plus
+    long real-space outer half kick), all at the end positions. Every record
+    is a different inner step (the O noise makes consecutive records differ)."""
+    ew = scheme.endswith("respa1")
+    sy, sp = _ewald(seed=25) if ew else _water(seed=25)
+    pa = S.water_params(jumps=False)
+    m, p = (2, 3) if ew else (3, 1)
+    pa.respa_inner, pa.respa_outer = m, p
+    g = jm.Sim(sy, sp, pa)
+    g.trace_velocities(sy.n_atoms, 4 * m * p)
+    h = 0.5 * pa.dt
+    for call in range(4):
+        getattr(g, "step_" + scheme)(1)
+        _, v = g.state()
+        if ew:
+            want = v - h * g.accel(2) - m * h * g.accel(0) - p * m * h * (g.accel(4) + g.accel(3))
+        else:
+            want = v - h * g.accel(2) - m * h * g.accel(1)
+        rec, tn = g.trace()
+        assert tn == (call + 1) * m * p
+        assert np.abs(rec[-1] - want).max() < 1e-12 * np.abs(want).max()
+    flat = rec.reshape(len(rec), -1)
+    assert len(rec) == 4 * m * p
+    assert all(np.abs(flat[k] - flat[k + 1]).max() > 0.0 for k in range(len(rec) - 1))
+
+
 def test_ring_keeps_the_last_records(jm):
     sy, sp = _water(seed=23)
     pa = S.water_params(jumps=False)
