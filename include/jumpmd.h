@@ -58,6 +58,10 @@ extern "C" {
                                   bounces on the Coulomb long part in the (J) step together with the LJ
                                   ones (one chain over the whole long part, no acceleration between
                                   jumps); the (C) steps reduce to plain kicks */
+#define MD_JUMP_IN_C 5         /* jump_lj only: the LJ long part jumps in the (C) step together with the
+                                  Coulomb one, with jump_coul's kernel (one chain over the whole long
+                                  part, bounds summed; Sec. 2.2 with F_ij the whole long-part force),
+                                  no (J) step; needs jump_coul MRZ_CONST, MRZ_ADAPTIVE or BPS */
 
 /* arithmetic of the pair terms */
 #define MD_FP64 0
@@ -151,7 +155,7 @@ typedef struct {
   double kT;            /* energy */
   uint64_t seed;        /* counter-based Philox4x32-10 key: (low 32 bits of seed, high 32 bits of
                            seed xor replica index); counters (step, local atom, phase tag, draw) */
-  int32_t jump_lj;      /* MD_JUMP_NONE or MD_JUMP_BPS (J step, Alg. 5) */
+  int32_t jump_lj;      /* MD_JUMP_NONE, MD_JUMP_BPS (J step, Alg. 5) or MD_JUMP_IN_C */
   int32_t jump_coul;    /* MD_JUMP_NONE, MD_JUMP_MRZ_CONST or MD_JUMP_MRZ_ADAPTIVE (C step, Alg. 4),
                            or MD_JUMP_BPS: bounces of Sec. 3.2 in the C step (the eps -> infinity
                            end of the MRZ family, Sec. 2.2), or MD_JUMP_BOUNCE: bounces in the J step */

@@ -24,6 +24,8 @@ extern "C" {
 #define ORC_JUMP_MRZ_ADAPTIVE 3 /* same with eps(x) = eps0 |F_ij(x)| (Sec. 2.2, Sec. 3.1) */
 #define ORC_JUMP_BOUNCE 4       /* Coulomb: BPS bounces in the (J) step together with the LJ ones, no
                                    acceleration between jumps (the BOUNCE scheme B J A O A J B, Sec. 3) */
+#define ORC_JUMP_IN_C 5         /* LJ: the long part jumps in the (C) step with the Coulomb one, with the
+                                   Coulomb kernel (Sec. 2.2 with F_ij the whole long-part force) */
 
 /* random-stream phase tags (counter word 2, low byte) */
 #define ORC_PH_O 1

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libjumpmd_oracle.so")
 # tests load builds with a planted mistake this way)
 _LIB_ENV = "JUMPMD_ORACLE_LIBRARY"
 
-JUMP_NONE, JUMP_BPS, JUMP_MRZ_CONST, JUMP_MRZ_ADAPTIVE, JUMP_BOUNCE = 0, 1, 2, 3, 4
+JUMP_NONE, JUMP_BPS, JUMP_MRZ_CONST, JUMP_MRZ_ADAPTIVE, JUMP_BOUNCE, JUMP_IN_C = 0, 1, 2, 3, 4, 5
 PH_O, PH_J1, PH_J2, PH_C1, PH_C2 = 1, 2, 3, 4, 5
 F_SHORT, F_FULL, F_BONDED, F_LONG, F_RECIP = 0, 1, 2, 3, 4
 COUL_DSF, COUL_EWALD, COUL_SPME = 0, 1, 2

@@ -16,7 +16,10 @@ the RESPA schemes; n inner steps per outer step, default 3; eps0 in
 (kcal/mol/A)^-1; rs = split radius in A). coul= picks the
 Coulomb long part's treatment in JUMP: mrz (adaptive MRZ jumps, default),
 bps (BPS bounces in the C step), or none (the long part dropped: the
-negative control of Fig. 1b, whose structure must differ).
+negative control of Fig. 1b, whose structure must differ). lj= picks the
+Lennard-Jones long part's: bps (BPS bounces in the J step, default), inc
+(jumps in the C step together with the Coulomb part, with its kernel) or
+none (dropped).
 
 --ewald ALPHA,RC,KMAX[,W] switches every run (and the equilibration) to
 Ewald electrostatics: damped real part to RC with ALPHA, reciprocal sum over
@@ -132,6 +135,7 @@ def main():
         if jumps:
             pa.jump_coul = {"mrz": S.JUMP_MRZ_ADAPTIVE, "bps": S.JUMP_BPS,
                             "none": S.JUMP_NONE}[kv.get("coul", "mrz")]
+            pa.jump_lj = {"bps": S.JUMP_BPS, "none": S.JUMP_NONE, "inc": S.JUMP_IN_C}[kv.get("lj", "bps")]
         pa.respa_inner = n_in
         pa.respa_outer = n_out
         sim = jumpmd.Sim(sysm, sp, pa)

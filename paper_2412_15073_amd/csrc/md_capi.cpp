@@ -465,8 +465,11 @@ static int validate(const md_system *s, const md_split *sp, const md_params *p) 
     return fail(nullptr, MD_ERR_ARG, "bad split (need 0 < r_s - w, w > 0, r_s <= r_c, skin >= 0)");
   if (sp->n_rings > 1 && !(sp->ring_width > 0.0)) return fail(nullptr, MD_ERR_ARG, "ring_width must be > 0");
   if (!(p->dt > 0.0) || p->gamma < 0.0 || !(p->kT > 0.0)) return fail(nullptr, MD_ERR_ARG, "bad dt/gamma/kT");
-  if (p->jump_lj != MD_JUMP_NONE && p->jump_lj != MD_JUMP_BPS)
-    return fail(nullptr, MD_ERR_ARG, "jump_lj must be NONE or BPS");
+  if (p->jump_lj != MD_JUMP_NONE && p->jump_lj != MD_JUMP_BPS && p->jump_lj != MD_JUMP_IN_C)
+    return fail(nullptr, MD_ERR_ARG, "jump_lj must be NONE, BPS or IN_C");
+  if (p->jump_lj == MD_JUMP_IN_C && p->jump_coul != MD_JUMP_BPS && p->jump_coul != MD_JUMP_MRZ_CONST &&
+      p->jump_coul != MD_JUMP_MRZ_ADAPTIVE)
+    return fail(nullptr, MD_ERR_ARG, "jump_lj IN_C needs jump_coul BPS, MRZ_CONST or MRZ_ADAPTIVE");
   if (p->jump_coul != MD_JUMP_NONE && p->jump_coul != MD_JUMP_BPS && p->jump_coul != MD_JUMP_MRZ_CONST &&
       p->jump_coul != MD_JUMP_MRZ_ADAPTIVE && p->jump_coul != MD_JUMP_BOUNCE)
     return fail(nullptr, MD_ERR_ARG, "jump_coul must be NONE, BPS, MRZ_CONST, MRZ_ADAPTIVE or BOUNCE");

@@ -408,9 +408,9 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
   // the accepted proposals (about half) pay for it, in the window.
   constexpr bool kZPre = G >= 4;
   const bool isC = op.kind == OP_C;
-  // jump component: C the Coulomb long part; J the LJ long part, or both in
-  // the BOUNCE scheme
-  const int comp = isC ? 1 : (V.jc == MD_JUMP_BOUNCE ? 2 : 0);
+  // jump component: C the Coulomb long part (both parts when the LJ one
+  // jumps in C); J the LJ long part, or both in the BOUNCE scheme
+  const int comp = isC ? (V.jlj == MD_JUMP_IN_C ? 2 : 1) : (V.jc == MD_JUMP_BOUNCE ? 2 : 0);
   const int a = V.type[i];
   const bool cont = op.stream == MD_STREAM_CONTINUE;
   if (!(cont && rp.saved)) {
@@ -527,7 +527,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         long_grad<PREC>(V, xi, xb, a, (int)(((double)sb + 0.5) * inv_nr), comp, L, iL, img, eb, Fx, Fy, Fz);
         ring[RF_BX * M + sl] = (R)Fx; ring[RF_BY * M + sl] = (R)Fy; ring[RF_BZ * M + sl] = (R)Fz;
         if (adaptive) {
-          long_grad<PREC>(V, xi, xf, a, 0, 1, L, iL, img, ef, Fx, Fy, Fz);
+          long_grad<PREC>(V, xi, xf, a, (int)(((double)sf + 0.5) * inv_nr), comp, L, iL, img, ef, Fx, Fy, Fz);
           ring[RF_FX * M + sl] = (R)Fx; ring[RF_FY * M + sl] = (R)Fy; ring[RF_FZ * M + sl] = (R)Fz;
         }
         jring[sl] = make_int2(jb - i0, jf - i0);   // replica-local indices (event hash)

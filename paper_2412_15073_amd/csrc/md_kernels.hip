@@ -1042,6 +1042,44 @@ __global__ __launch_bounds__(256) void k_pme_spread(MDView V, const double4 *__r
   }
 }
 
+// Charge spreading by planes: block x owns mesh plane x (first index) in LDS,
+// adds the contributions of every atom whose support covers the plane (LDS
+// atomics), then writes the plane whole (real parts, zero imaginary parts):
+// no global atomics and no zeroing pass.
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_spread_planes(MDView V, const double4 *__restrict__ X) {
+  extern __shared__ double pl[];
+  const int px = blockIdx.x;
+  const int K0 = V.pk[0], K1 = V.pk[1], K2 = V.pk[2];
+  for (int e = threadIdx.x; e < K1 * K2; e += blockDim.x) pl[e] = 0.0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < V.n; i += blockDim.x) {
+    const double4 x = X[i];
+    if (x.w == 0.0) continue;
+    const double u0 = K0 * x.x / V.box[0], f0 = floor(u0);
+    const int d = wrap_index((int)f0 - px, K0);   // the atom's slice index j0 on this plane
+    if (d >= P) continue;
+    double T0[P], T1[P], T2[P];
+    bspline_weights<P>(u0 - f0, T0, nullptr);
+    const double u1 = K1 * x.y / V.box[1], f1 = floor(u1);
+    const double u2 = K2 * x.z / V.box[2], f2 = floor(u2);
+    bspline_weights<P>(u1 - f1, T1, nullptr);
+    bspline_weights<P>(u2 - f2, T2, nullptr);
+    double t0 = 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) t0 = j == d ? T0[j] : t0;
+    for (int j1 = 0; j1 < P; ++j1) {
+      const int r1 = wrap_index((int)f1 - j1, K1) * K2;
+      const double w01 = x.w * t0 * T1[j1];
+#pragma unroll
+      for (int j2 = 0; j2 < P; ++j2) atomicAdd(&pl[r1 + wrap_index((int)f2 - j2, K2)], w01 * T2[j2]);
+    }
+  }
+  __syncthreads();
+  double2 *g = V.pgrid + (size_t)px * K1 * K2;
+  for (int e = threadIdx.x; e < K1 * K2; e += blockDim.x) g[e] = make_double2(pl[e], 0.0);
+}
+
 // In-place transform F(m) = sum_k x_k exp(+2 pi i m k / N) along one axis of
 // the grid, N a power of two: each line of the axis is loaded into LDS in
 // bit-reversed order and combined in log2 N radix-2 stages (iterative
@@ -1444,12 +1482,22 @@ static hipError_t launch_fft3(const MDView &V, hipStream_t s) {
 // terms [NG] or NULL), and for forces the second transform and the gather
 static hipError_t pme_to_influence(const MDView &V, const double4 *X, double *e, hipStream_t s) {
   const int ng = V.pk[0] * V.pk[1] * V.pk[2];
-  CHK(launch_fill_u64((unsigned long long *)V.pgrid, 2 * ng, 0ull, s));
-  const dim3 ga((8 * V.n + 255) / 256);   // 8 lanes per atom
-  switch (V.porder) {
-    case 4: hipLaunchKernelGGL(k_pme_spread<4>, ga, dim3(256), 0, s, V, X); break;
-    case 6: hipLaunchKernelGGL(k_pme_spread<6>, ga, dim3(256), 0, s, V, X); break;
-    default: hipLaunchKernelGGL(k_pme_spread<8>, ga, dim3(256), 0, s, V, X); break;
+  const size_t plane = sizeof(double) * V.pk[1] * V.pk[2];
+  if (plane <= 64 * 1024) {   // one block per mesh plane, the plane in LDS
+    const dim3 gp(V.pk[0]);
+    switch (V.porder) {
+      case 4: hipLaunchKernelGGL(k_pme_spread_planes<4>, gp, dim3(256), plane, s, V, X); break;
+      case 6: hipLaunchKernelGGL(k_pme_spread_planes<6>, gp, dim3(256), plane, s, V, X); break;
+      default: hipLaunchKernelGGL(k_pme_spread_planes<8>, gp, dim3(256), plane, s, V, X); break;
+    }
+  } else {                    // larger planes: zeroed mesh and global atomics, 8 lanes per atom
+    CHK(launch_fill_u64((unsigned long long *)V.pgrid, 2 * ng, 0ull, s));
+    const dim3 ga((8 * V.n + 255) / 256);
+    switch (V.porder) {
+      case 4: hipLaunchKernelGGL(k_pme_spread<4>, ga, dim3(256), 0, s, V, X); break;
+      case 6: hipLaunchKernelGGL(k_pme_spread<6>, ga, dim3(256), 0, s, V, X); break;
+      default: hipLaunchKernelGGL(k_pme_spread<8>, ga, dim3(256), 0, s, V, X); break;
+    }
   }
   CHK(hipGetLastError());
   CHK(launch_fft3(V, s));

@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--ref-dt", default="1.0,0.5", help="time steps (fs) of the FP64 BAOAB references")
     ap.add_argument("--summarize", nargs="+", metavar="LOG", help="summarise logs of earlier runs and exit")
+    ap.add_argument("--lj", default="bps", choices=("bps", "inc"),
+                    help="LJ long part: BPS bounces in the J step, or jumps in the C step with the Coulomb part")
     ap.add_argument("--pme", default="", metavar="ALPHA,RC,GRID,ORDER,W",
                     help="Ewald electrostatics (particle-mesh reciprocal sum) instead of DSF to 10 A")
     a = ap.parse_args()
@@ -147,10 +149,12 @@ def main():
             split = make_split(rs, a.skin)
             pa = S.water_params(eps0_per_kcal=eps0)
             pa.precision = S.FP32_MIXED
+            if a.lj == "inc":
+                pa.jump_lj = S.JUMP_IN_C
             t0 = time.perf_counter()
             per, ms = measure(split, pa, "jump")
             print(json.dumps({"point": "jump_fp32", "r_s": rs, "eps0": eps0, "dt_fs": 1.0, "ms_per_step": ms,
-                              "pme": a.pme or None,
+                              "pme": a.pme or None, "lj": a.lj,
                               "ns_per_day": 86.4 / ms, "wall_s": time.perf_counter() - t0,
                               "per_seed": [{"T": q["T"], "D": q["D"], "D_err": q["D_err"], "g": q["g"].tolist()}
                                            for q in per]}), flush=True)
@@ -202,7 +206,7 @@ def _table(pts):
         dD = (D - D0) / D0
         ok = abs(dT) <= TARGETS["T_rel"] and l2 <= TARGETS["rdf_l2"] and abs(dD) <= TARGETS["D_rel"]
         name = (f"BAOAB FP64 {p['dt_fs']:g} fs" if p["point"] == "baoab_fp64"
-                else f"JUMP FP32 r_s {p['r_s']:g} eps0 {p['eps0']:g}")
+                else f"JUMP FP32 r_s {p['r_s']:g} eps0 {p['eps0']:g}" + (" LJ in C" if p.get("lj") == "inc" else ""))
         dT05 = (T - T05) / T05 if T05 else float("nan")
         rows.append((name, p["ms_per_step"], p["ns_per_day"], T, dT, l2, D, e, dD, ok, dT05))
     print(f"{'run':34s} {'ms/step':>8s} {'ns/day':>8s} {'T (K)':>8s} {'dT':>7s} {'dT.5fs':>7s} {'RDF L2':>7s} "

@@ -18,7 +18,7 @@ from typing import List, Optional
 import numpy as np
 
 # jump kinds (same numbering on both sides of the boundary)
-JUMP_NONE, JUMP_BPS, JUMP_MRZ_CONST, JUMP_MRZ_ADAPTIVE, JUMP_BOUNCE = 0, 1, 2, 3, 4
+JUMP_NONE, JUMP_BPS, JUMP_MRZ_CONST, JUMP_MRZ_ADAPTIVE, JUMP_BOUNCE, JUMP_IN_C = 0, 1, 2, 3, 4, 5
 COUL_DSF, COUL_EWALD, COUL_SPME = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 

@@ -36,6 +36,8 @@ PLANTS = {
         ["test_spme_converges_to_the_ewald_sum"]),
     9: ("SPME y force from the B-spline values instead of their derivative",
         ["test_spme_forces_are_minus_energy_gradient", "test_spme_converges_to_the_ewald_sum"]),
+    10: ("LJ in the C step jumping on the Coulomb gradient only",
+         ["test_c_step_with_lj_in_c_mean_kick_equals_whole_long_force"]),
 }
 
 

@@ -811,6 +811,28 @@ def test_j_step_mean_kick_equals_long_lj_force():
     assert st.chi2.sf(chi2, dof) > 1e-3, chi2
 
 
+@pytest.mark.parametrize("kind", [O.JUMP_MRZ_ADAPTIVE, O.JUMP_BPS])
+def test_c_step_with_lj_in_c_mean_kick_equals_whole_long_force(kind):
+    """LJ long part in the C step (jump_lj IN_C): one chain per atom over the
+    long part of the whole pair potential with the Coulomb kernel (bound
+    l_LJ + l_Coulomb, floor over every candidate with l > 0). Averaged over
+    Maxwell-Boltzmann velocities the C step changes v by -h grad U_long / m
+    of both parts, on charged LJ ions where either part alone would miss;
+    the Coulomb-only C step misses it."""
+    sy = S.ion_lattice(4, 3.7, q=1.0, lj_eps=5.0, lj_sigma=2.0, jitter=0.1)
+    sp = S.Split(r_s=3.5, r_c=6.0, switch_width=1.0, skin=0.3, coulomb_alpha=0.2, n_rings=3,
+                 ring_width=(6.3 - 2.2) / 3)
+    pa = S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_lj=O.JUMP_IN_C, jump_coul=kind, eps=0.3)
+    o = _oracle(sy, sp, pa)
+    chi2, signal, dof = _moment_check(o, lambda h: o.phase_c(O.PH_C1, h), 0.1, 10000, pa.kT)
+    assert signal > 4 * dof
+    assert st.chi2.sf(chi2, dof) > 1e-3, chi2
+    pa_c = S.Params(dt=0.01, gamma=0.0, kT=1.0, jump_coul=kind, eps=0.3)
+    o2 = _oracle(sy, sp, pa_c)
+    chi2_c, _, _ = _moment_check(o2, lambda h: o2.phase_c(O.PH_C1, h), 0.1, 10000, pa.kT)
+    assert st.chi2.sf(chi2_c, dof) < 1e-6
+
+
 def test_bounce_j_step_mean_kick_equals_whole_long_force():
     """BOUNCE (Sec. 3: bounces on the Coulomb part too, in the J step): one
     BPS chain per atom over the long part of the whole pair potential (LJ +
@@ -868,7 +890,7 @@ def _gibbs_reference(sy, sp, kT, edges):
     return p / p.sum()
 
 
-@pytest.mark.parametrize("scheme", ["jump", "jump_bps", "jump_respa", "baoab", "bounce"])
+@pytest.mark.parametrize("scheme", ["jump", "jump_bps", "jump_respa", "baoab", "bounce", "jump_lj_in_c"])
 def test_two_particle_gibbs_marginal(scheme):
     """Two charged LJ particles: the distance histogram (r < L/2) of a long run
     matches p(r) ~ r^2 exp(-beta U(r)) by quadrature, and <v^2> = kT/m.
@@ -878,9 +900,10 @@ def test_two_particle_gibbs_marginal(scheme):
     sy = S.two_charges()
     sp = S.Split(r_s=3.0, r_c=5.0, switch_width=0.5, skin=0.3, coulomb_alpha=0.2)
     pa = S.Params(dt=0.005, gamma=2.0, kT=0.722, seed=3,
-                  jump_lj=O.JUMP_BPS if scheme != "baoab" else 0,
+                  jump_lj={"baoab": 0, "jump_lj_in_c": O.JUMP_IN_C}.get(scheme, O.JUMP_BPS),
                   jump_coul={"jump": O.JUMP_MRZ_ADAPTIVE, "jump_bps": O.JUMP_BPS, "jump_respa": O.JUMP_MRZ_ADAPTIVE,
-                             "baoab": 0, "bounce": O.JUMP_BOUNCE}[scheme], eps=0.5)
+                             "baoab": 0, "bounce": O.JUMP_BOUNCE,
+                             "jump_lj_in_c": O.JUMP_MRZ_ADAPTIVE}[scheme], eps=0.5)
     pa.respa_inner = 3
     o = _oracle(sy, sp, pa)
     L = sy.box[0]
