@@ -27,6 +27,13 @@ comparator, kernel split and roofline:
                    mesh, order 6): JUMP-RESPA1 at 1:2:6 fs (bonded 1 fs, short
                    forces and jumps 2 fs, reciprocal forces 6 fs) FP32-mixed vs
                    FP64 BAOAB-RESPA1 at the same steps;
+  water4096_pme_matched  the 4096-water box at the same Ewald settings, plain
+                   JUMP (reciprocal forces every step in the C' acceleration)
+                   at the cheapest point of the accuracy frontier that keeps
+                   T within 1 %, the O-O RDF within 1e-2 and D within 5 % of
+                   FP64 BAOAB: r_s = 6 A, eps0 = 0.1, the LJ long part jumping
+                   in the C step with the Coulomb part; FP32-mixed JUMP vs
+                   FP64 BAOAB (full forces to 7 A + PME every step);
   lj864            864 LJ atoms (fcc, rho 0.8442, kT 0.722), B J A O A J B with
                    BPS jumps between r_s = 3 and r_c = 5 sigma, vs BAOAB, FP64
                    (reduced units: tau/day).
@@ -89,7 +96,8 @@ CHAIN_TRAFFIC = {}
 KERNELS = {0: "k_local (B/A/O updates)", 1: "k_force (pairs, with bonded when fused)", 2: "k_bonded (separate)",
            3: "row rebuild", 4: "k_chain (J/C jump chains)", 5: "reciprocal space (particle-mesh Ewald)"}
 METRIC = "ns/day & pair-interactions/s, JUMP vs full-force BAOAB, 1 MI355X, matched T/RDF/D"
-ALL_WORKLOADS = ("ensemble", "water4096", "water4096_fp32", "water32000_respa", "water4096_pme_respa1", "lj864")
+ALL_WORKLOADS = ("ensemble", "water4096", "water4096_fp32", "water32000_respa", "water4096_pme_respa1",
+                 "water4096_pme_matched", "lj864")
 PME = {"alpha": 0.554, "r_s": 5.0, "r_c": 7.0, "switch": 0.5, "grid": 64, "order": 6}
 
 
@@ -255,11 +263,14 @@ class Workload:
         self.name = name
         self.respa = name == "water32000_respa"
         self.respa1 = name == "water4096_pme_respa1"
+        self.matched = name == "water4096_pme_matched"
+        self.pme = self.respa1 or self.matched
         self.lj = name == "lj864"
         self.ensemble = name == "ensemble"
         self.jump_prec = {"ensemble": 1, "water4096": 0, "water4096_fp32": 1, "water32000_respa": 1,
-                          "water4096_pme_respa1": 1, "lj864": 0}[name]
-        self.rc = 12.0 if self.respa else (PME["r_c"] if self.respa1 else 10.0)
+                          "water4096_pme_respa1": 1, "water4096_pme_matched": 1, "lj864": 0}[name]
+        self.rc = 12.0 if self.respa else (PME["r_c"] if self.pme else 10.0)
+        self.rs = 6.0 if self.matched else (3.0 if self.lj else 5.0)
         self.inner = 3 if self.respa else (2 if self.respa1 else 1)
         self.outer = 3 if self.respa1 else 1
         self.graph = 0 if (self.respa or self.respa1) else a.graph_steps
@@ -280,8 +291,8 @@ class Workload:
     def split(self, skin):
         if self.lj:
             return self.S.lj_split(skin=0.3)
-        if self.respa1:
-            sp = self.S.water_split(r_s=PME["r_s"], r_c=self.rc, w=PME["switch"], skin=skin, alpha=PME["alpha"],
+        if self.pme:
+            sp = self.S.water_split(r_s=self.rs, r_c=self.rc, w=PME["switch"], skin=skin, alpha=PME["alpha"],
                                     n_rings=6)
             sp.coulomb_kind, sp.pme_grid, sp.pme_order = self.S.COUL_SPME, (PME["grid"],) * 3, PME["order"]
             return sp
@@ -296,6 +307,8 @@ class Workload:
             if self.respa or self.respa1:
                 p.respa_inner = self.inner
                 p.respa_outer = self.outer
+            if self.matched and jumps:
+                p.jump_lj = S.JUMP_IN_C
         p.chain_lanes = self.a.chain_lanes
         p.chain_order = self.a.chain_order
         p.graph_steps = graph
@@ -471,7 +484,7 @@ def run_workload(w, jumpmd, C, cache):
             print(f"[bench] {w.name} BAOAB FP64 {ms_b:.4f} ms/step, {base['rate']:.1f} {unit}, "
                   f"T = {obs_b['temperature']:.1f}, {pairs_full} pairs", flush=True)
 
-    pme_work = pme_flops(n_atoms, PME["grid"], PME["order"]) if w.respa1 else 0.0
+    pme_work = pme_flops(n_atoms, PME["grid"], PME["order"]) if w.pme else 0.0
     dom, roof = roofline(prof_j, a.profile_steps, props_prof, pairs_short, n_atoms, w.jump_prec, build_bytes, pme_work)
     tr = CHAIN_TRAFFIC.get(w.name)
     if dom == 4 and tr and chain_source_hash().startswith(tr["sha256"]):
@@ -493,17 +506,18 @@ def run_workload(w, jumpmd, C, cache):
         "kernel_ms_per_step": {KERNELS[k]: round(prof_j[k][0] / a.profile_steps, 5) for k in prof_j if prof_j[k][1]},
         "baoab_kernel_ms_per_step": base["kernel_ms_per_step"] if base else None,
         "roofline": roof,
-        "config": {"r_s": 3.0 if w.lj else 5.0, "r_c": 5.0 if w.lj else w.rc,
-                   "switch": 0.5 if (w.lj or w.respa1) else 1.0,
+        "config": {"r_s": w.rs, "r_c": 5.0 if w.lj else w.rc,
+                   "switch": 0.5 if (w.lj or w.pme) else 1.0,
                    "skin": 0.3 if w.lj else split_j.skin, "baoab_skin": base["skin"] if base else None,
                    "rings": 1 if w.lj else split_j.n_rings, "chain_lanes": pj.chain_lanes, "autotuned": tuned,
                    "respa_inner": w.inner if (w.respa or w.respa1) else None,
                    "respa_outer": w.outer if w.respa1 else None,
                    "electrostatics": (f"particle-mesh Ewald (alpha {PME['alpha']}, {PME['grid']}^3 mesh, order "
-                                      f"{PME['order']})" if w.respa1 else (None if w.lj else "DSF (alpha 0.2)")),
+                                      f"{PME['order']})" if w.pme else (None if w.lj else "DSF (alpha 0.2)")),
                    "dt": "0.005 tau" if w.lj else "1 fs", "graph_steps": pj.graph_steps,
                    "eps0_per_kcal_mol_A": None if w.lj else a.eps0,
-                   "jumps": "LJ BPS" if w.lj else "LJ BPS + Coulomb adaptive MRZ"},
+                   "jumps": "LJ BPS" if w.lj else ("LJ and Coulomb long parts, adaptive MRZ in the C step" if w.matched
+                                                   else "LJ BPS + Coulomb adaptive MRZ")},
     }
     cache[key] = {"state": (x, v, T_eq)}
     cache["baoab:" + w.name] = base

@@ -144,8 +144,8 @@ def main():
                               "per_seed": [{"T": q["T"], "D": q["D"], "D_err": q["D_err"], "g": q["g"].tolist()}
                                            for q in per]}), flush=True)
 
-    for rs in [float(x) for x in a.rs.split(",")]:
-        for eps0 in [float(x) for x in a.eps0.split(",")]:
+    for rs in [float(x) for x in a.rs.split(",") if x]:    # --rs "": the references only
+        for eps0 in [float(x) for x in a.eps0.split(",") if x]:
             split = make_split(rs, a.skin)
             pa = S.water_params(eps0_per_kcal=eps0)
             pa.precision = S.FP32_MIXED
