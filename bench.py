@@ -88,11 +88,16 @@ BYTES_PER_ATOM_LOCAL = 7 * 32   # x (read+write), v (read+write), f_nb, f_b, x_r
 # builder's own reads, about 200 B; plus 4 B per row entry and per segment start written
 BYTES_PER_ATOM_BUILD = 200
 BYTES_PER_ROW_ENTRY = 4
-# HBM bytes per launch of the chain kernel from FETCH_SIZE / WRITE_SIZE
-# counters, each scaled by the same counter on a plain 256 MiB copy (summaries
-# under profiles/), per workload, valid while the sha256 of the chain kernel's
-# sources (md_chain.hip, then md_device.h) starts with the given prefix.
-CHAIN_TRAFFIC = {}
+# HBM bytes of the chain kernel per proposal, from FETCH_SIZE / WRITE_SIZE
+# counters per launch (each scaled by the same counter on a plain 256 MiB
+# copy: fetch x 1.9998, write x 1.0) divided by that launch's proposals
+# (summaries under profiles/), per workload, valid while the sha256 of the
+# chain kernel's sources (md_chain.hip, then md_device.h) starts with the
+# given prefix. The line reports it times the proposals of its own launches.
+CHAIN_TRAFFIC = {
+    "ensemble": {"sha256": "a9b0c76df428baa9", "bytes_per_proposal": 252.2},
+    "water4096": {"sha256": "a9b0c76df428baa9", "bytes_per_proposal": 47.0},
+}
 KERNELS = {0: "k_local (B/A/O updates)", 1: "k_force (pairs, with bonded when fused)", 2: "k_bonded (separate)",
            3: "row rebuild", 4: "k_chain (J/C jump chains)", 5: "reciprocal space (particle-mesh Ewald)"}
 METRIC = "ns/day & pair-interactions/s, JUMP vs full-force BAOAB, 1 MI355X, matched T/RDF/D"
@@ -488,7 +493,7 @@ def run_workload(w, jumpmd, C, cache):
     dom, roof = roofline(prof_j, a.profile_steps, props_prof, pairs_short, n_atoms, w.jump_prec, build_bytes, pme_work)
     tr = CHAIN_TRAFFIC.get(w.name)
     if dom == 4 and tr and chain_source_hash().startswith(tr["sha256"]):
-        roof["traffic"] = tr["bytes"]
+        roof["traffic"] = tr["bytes_per_proposal"] * props_prof * a.profile_steps / max(roof["launches"], 1)
     steps_per_day = a.steps / dt_j * 86400.0
     res = {
         "workload": w.name, "n_atoms": n_atoms, "replicas": w.n_sys,
