@@ -48,6 +48,7 @@ struct md_ctx {
   bool frec_valid = false;     // frec holds the reciprocal-space forces at the current positions
   bool flong_valid = false;    // flong holds the long real-space forces at the current positions
   double2 *d_spart = nullptr, *d_sfac = nullptr;   // Ewald partial and total structure factors
+  double *d_pme_part = nullptr;                      // partial planes of the particle-mesh spreading
   double4 *d_fpart = nullptr;                       // Ewald partial forces per k-range
   double ew_ecoef = 0.0, ew_self = 0.0;            // Ewald energy prefactor (half space), self energy
   int rows_valid = 0;          // ROW_* bits valid for the current reference positions
@@ -426,7 +427,7 @@ static int eval_recip(md_ctx *c) {
   if (!c->ewald) return MD_OK;
   hipEvent_t e0{};
   prof_begin(c, MD_K_RECIP, &e0);
-  if (c->spme) HIPCHK(c, launch_pme_forces(c->V, Xcur(c), c->stream));
+  if (c->spme) HIPCHK(c, launch_pme_forces(c->V, Xcur(c), c->d_pme_part, c->stream));
   else HIPCHK(c, launch_recip(c->V, Xcur(c), c->d_spart, c->d_sfac, c->d_fpart, c->stream));
   prof_end(c, MD_K_RECIP, e0);
   c->frec_valid = true;
@@ -947,6 +948,20 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
           pinf[((size_t)m0 * K[1] + m1) * K[2] + m2] = V.ke / (2.0 * M_PI * vol) *
               std::exp(-M_PI * M_PI * mm / (V.alpha * V.alpha)) / mm * bm[0][m0] * bm[1][m1] * bm[2][m2];
         }
+    if (pme_fused(K)) {
+      // the four-launch path reads G at (p, y', z'): frequencies (rev p, rev y', rev z')
+      auto rev = [](int v, int Kd) {
+        int r = 0;
+        for (int b = 1; b < Kd; b <<= 1, v >>= 1) r = (r << 1) | (v & 1);
+        return r;
+      };
+      std::vector<double> nat(pinf);
+      for (int p0 = 0; p0 < K[0]; ++p0)
+        for (int y = 0; y < K[1]; ++y)
+          for (int z = 0; z < K[2]; ++z)
+            pinf[((size_t)p0 * K[1] + y) * K[2] + z] =
+                nat[((size_t)rev(p0, K[0]) * K[1] + rev(y, K[1])) * K[2] + rev(z, K[2])];
+    }
     const int tn = std::max(K[0], std::max(K[1], K[2]));
     ptw.resize(tn / 2);
     for (int k = 0; k < tn / 2; ++k) ptw[k] = make_double2(std::cos(2.0 * M_PI * k / tn), std::sin(2.0 * M_PI * k / tn));
@@ -955,6 +970,7 @@ extern "C" int md_create(const md_system *s, const md_split *sp, const md_params
     double2 *d_grid, *d_tw;
     double *d_inf;
     A(d_grid, pinf.size()); A(d_inf, pinf.size()); A(d_tw, ptw.size());
+    if (pme_fused(K)) A(c->d_pme_part, (size_t)MD_PME_PARTS * pinf.size());
     V.pgrid = d_grid; V.pinf = d_inf; V.ptw = d_tw;
     A(V.frec, n); A(V.flong, n);
     double q2 = 0.0;
@@ -1633,7 +1649,7 @@ extern "C" int md_observables(md_ctx *c, uint32_t flags, md_obs *o) {
     if (c->spme) {
       const size_t ng = (size_t)c->V.pk[0] * c->V.pk[1] * c->V.pk[2];
       std::vector<double> he(ng + (size_t)c->n);
-      HIPCHK(c, launch_pme_energy(c->V, X, c->d_scratch, c->stream));
+      HIPCHK(c, launch_pme_energy(c->V, X, c->d_pme_part, c->d_scratch, c->stream));
       HIPCHK(c, hipMemcpyAsync(he.data(), c->d_scratch, sizeof(double) * he.size(), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
       double ek = 0.0, ex = 0.0;

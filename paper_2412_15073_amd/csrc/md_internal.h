@@ -42,7 +42,15 @@ hipError_t launch_rdf_noalloc(const MDView &V, const double4 *X, const int *rep_
 hipError_t launch_recip(const MDView &V, const double4 *X, double2 *part, double2 *S, double4 *fpart,
                         hipStream_t s);
 void ewald_ranges(int n, int nk, int kmax, int &ranges, int &apb, int &ta, int &krange);
-hipError_t launch_pme_forces(const MDView &V, const double4 *X, hipStream_t s);
-hipError_t launch_pme_energy(const MDView &V, const double4 *X, double *e, hipStream_t s);
+// part: MD_PME_PARTS x K0 K1 K2 doubles of partial planes (four-launch path only)
+hipError_t launch_pme_forces(const MDView &V, const double4 *X, double *part, hipStream_t s);
+// the four-launch particle-mesh Ewald path applies (a complex FP64 (y, z)
+// plane fits 64 KiB of LDS); its influence table is then stored in the
+// bit-reversed order of that path (position p along x, then the plane
+// position (y', z'), each holding frequency bit-reverse of its index)
+inline bool pme_fused(const int *K) { return K[1] * K[2] <= 4096; }
+// atom ranges per mesh plane in the spreading of that path (partial planes summed after)
+#define MD_PME_PARTS 4
+hipError_t launch_pme_energy(const MDView &V, const double4 *X, double *part, double *e, hipStream_t s);
 hipError_t launch_ewald_energy(const MDView &V, const double4 *X, double2 *part, double2 *S, double *e,
                                hipStream_t s);

@@ -13,6 +13,9 @@
 //              atom, shuffle reduction (with the bonded forces appended when
 //              they fit the same round).
 //  k_bonded    bonds and angles, per atom over its incident terms.
+//  Ewald reciprocal space: the plain structure-factor sum (k_sfac,
+//              k_recip_force) and particle-mesh Ewald (spreading, transforms
+//              and influence function in LDS, gather).
 //  observables: kinetic energy, pair energies, pair histograms.
 #include <algorithm>
 #include <mutex>
@@ -1003,10 +1006,8 @@ __device__ __forceinline__ void bspline_weights(double w, double *T, double *dT)
   }
 }
 
-__device__ __forceinline__ int wrap_index(int k, int K) {
-  k %= K;
-  return k < 0 ? k + K : k;
-}
+// k mod K in [0, K) for a mesh edge K that is a power of two
+__device__ __forceinline__ int wrap_index(int k, int K) { return k & (K - 1); }
 
 // charge spreading: 8 lanes per atom, lane j0 < p the p^2 grid points of
 // the slice k0 - j0 along the first axis, atomic sums into the real parts of
@@ -1121,6 +1122,238 @@ __global__ __launch_bounds__(256) void k_fft_axis(double2 *__restrict__ g, const
   }
   if (ok)
     for (int e = t; e < Na; e += half) g[(size_t)base + (size_t)e * stride] = Lb[e];
+}
+
+// ---- particle-mesh Ewald in four launches, for meshes whose (y, z) plane
+// fits LDS as complex FP64 (K1 K2 <= 4096): spreading plus the y and z
+// transforms plane by plane; then one x-line kernel takes the x transform,
+// the influence function and the x part of the second transform; then the
+// y and z part of the second transform plane by plane; then the gather.
+// In between, a plane is stored with both of its indices bit-reversed (the
+// output order of the decimation-in-frequency passes), which the second
+// transform's decimation-in-time passes take as their input order.
+
+// element (y, z) of a K1 x K2 plane in LDS: rows of K2 with the z index
+// xor-ed by y, so that a column (fixed z) spreads over the LDS banks
+__device__ __forceinline__ int plane_at(int y, int z, int K2) { return y * K2 + (z ^ (y & (K2 - 1))); }
+
+// position of the n-th (from 0) set bit of m; n < popcount(m)
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int n) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w > 0; w >>= 1) {
+    const int c = __popcll(m & ((1ull << w) - 1ull));
+    if (n >= c) { n -= c; m >>= w; pos += w; }
+  }
+  return pos;
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 w) {
+  return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// Transforms F(m) = sum_k x_k exp(+2 pi i m k / N) of nl lines of length N
+// (a power of two) in LDS (element e of line l at addr(l, e)), all threads
+// of the block taking the work of a pass in turn. DIF: natural order in,
+// bit-reversed out; otherwise (DIT) bit-reversed in, natural out. Two
+// radix-2 stages per pass (four elements per thread in registers), one
+// single stage last when log2 N is odd. tw[j] = exp(+2 pi i j / twn).
+template <bool DIF, typename Addr>
+__device__ __forceinline__ void lds_fft_lines(double2 *buf, int nl, int N, const double2 *__restrict__ tw, int twn,
+                                              Addr addr) {
+  const int logN = 31 - __clz(N);
+  for (int s = 0; s < logN;) {
+    if (s + 1 < logN) {
+      // quads {e, e + q, e + 2q, e + 3q}: DIT spans 2q then 4q, DIF 4q then 2q
+      const int lq = DIF ? logN - s - 2 : s, q = 1 << lq;
+      const int lnq = logN - 2;   // log2 of the quads per line
+      const int nb = nl << lnq;
+      const int t2 = twn >> (lq + 1), t4 = twn >> (lq + 2);   // twiddle strides of spans 2q, 4q
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int l = b >> lnq, t = b & ((1 << lnq) - 1);
+        const int j = t & (q - 1);
+        const int e = ((t >> lq) << (lq + 2)) + j;
+        const int a0 = addr(l, e), a1 = addr(l, e + q), a2 = addr(l, e + 2 * q), a3 = addr(l, e + 3 * q);
+        double2 x0 = buf[a0], x1 = buf[a1], x2 = buf[a2], x3 = buf[a3];
+        const double2 w2 = tw[j * t2], w4 = tw[j * t4], w4q = tw[(j + q) * t4];
+        if (DIF) {
+          double2 y0 = cadd(x0, x2), y2 = cmul(csub(x0, x2), w4);
+          double2 y1 = cadd(x1, x3), y3 = cmul(csub(x1, x3), w4q);
+          x0 = cadd(y0, y1); x1 = cmul(csub(y0, y1), w2);
+          x2 = cadd(y2, y3); x3 = cmul(csub(y2, y3), w2);
+        } else {
+          const double2 v1 = cmul(x1, w2), v3 = cmul(x3, w2);
+          const double2 y0 = cadd(x0, v1), y1 = csub(x0, v1), y2 = cadd(x2, v3), y3 = csub(x2, v3);
+          const double2 u2 = cmul(y2, w4), u3 = cmul(y3, w4q);
+          x0 = cadd(y0, u2); x2 = csub(y0, u2);
+          x1 = cadd(y1, u3); x3 = csub(y1, u3);
+        }
+        buf[a0] = x0; buf[a1] = x1; buf[a2] = x2; buf[a3] = x3;
+      }
+      s += 2;
+    } else {
+      const int st = DIF ? logN - s : s + 1;   // span 2^st
+      const int hm = 1 << (st - 1), lh = logN - 1;
+      const int ts = twn >> st;
+      const int nb = nl << lh;
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int l = b >> lh, t = b & ((1 << lh) - 1);
+        const int j = t & (hm - 1);
+        const int e0 = ((t >> (st - 1)) << st) + j, e1 = e0 + hm;
+        const double2 w = tw[j * ts];
+        const int a0 = addr(l, e0), a1 = addr(l, e1);
+        const double2 u = buf[a0], v = buf[a1];
+        if (DIF) {
+          buf[a0] = cadd(u, v);
+          buf[a1] = cmul(csub(u, v), w);
+        } else {
+          const double2 vw = cmul(v, w);
+          buf[a0] = cadd(u, vw);
+          buf[a1] = csub(u, vw);
+        }
+      }
+      s += 1;
+    }
+    __syncthreads();
+  }
+}
+
+// Spreading, split over MD_PME_PARTS parts per plane so that K0 x parts
+// blocks fill the device: block (x, part) accumulates the charges of its
+// atoms with support on plane x in a real plane in LDS and writes it to its
+// partial plane. The atoms are dealt out in chunks of 64, chunk c to wave
+// c mod (parts x waves per block) over all blocks of a plane, so that atoms
+// stored in spatial order (those near a plane in a run of chunks) spread
+// over the plane's blocks and waves. Each wave tests 4 chunks at a time
+// (independent loads);
+// the ones with support (about p / K0 of them) are packed P lanes each (lane:
+// atom, y offset j1), with their mesh coordinates passed between lanes, so
+// that the LDS atomics run on full waves.
+template <int P>
+__global__ __launch_bounds__(256) void k_pme_spread_part(MDView V, const double4 *__restrict__ X,
+                                                         double *__restrict__ part) {
+  extern __shared__ double pr[];
+  const int px = blockIdx.x, pp = blockIdx.y;
+  const int K0 = V.pk[0], K1 = V.pk[1], K2 = V.pk[2];
+  for (int e = threadIdx.x; e < K1 * K2; e += blockDim.x) pr[e] = 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int slot = lane / P, j1 = lane - slot * P;
+  constexpr int APW = 64 / P;   // atoms per packed batch
+  constexpr int U = 4;          // chunks of 64 atoms per wave and iteration
+  const int nch = (V.n + 63) >> 6;
+  const int wpb = (int)blockDim.x >> 6;
+  const int cstride = (int)gridDim.y * wpb;               // chunks between two of this wave's
+  const int cw = pp * wpb + ((int)threadIdx.x >> 6);      // this wave's first chunk
+  for (int c0 = cw; c0 < nch; c0 += U * cstride) {
+    double4 xq[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int i = ((c0 + q * cstride) << 6) + lane;
+      xq[q] = i < V.n ? X[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      // mesh coordinates K x / L, as the gather and the reference form them
+      const double u0 = K0 * xq[q].x / V.box[0], f0 = floor(u0);
+      const bool on = xq[q].w != 0.0 && wrap_index((int)f0 - px, K0) < P;
+      const unsigned long long m = __ballot(on);
+      if (m == 0ull) continue;
+      double u1 = 0.0, u2 = 0.0;
+      if (on) { u1 = K1 * xq[q].y / V.box[1]; u2 = K2 * xq[q].z / V.box[2]; }
+      const int np = __popcll(m);
+      for (int b0 = 0; b0 < np; b0 += APW) {
+        const int src = nth_set_bit(m, min(b0 + slot, np - 1));
+        const double v0 = __shfl(u0, src), v1 = __shfl(u1, src), v2 = __shfl(u2, src);
+        const double qa = __shfl(xq[q].w, src);
+        if (slot < APW && b0 + slot < np) {
+          const double g0 = floor(v0), g1 = floor(v1), g2 = floor(v2);
+          double T0[P], T1[P], T2[P];
+          bspline_weights<P>(v0 - g0, T0, nullptr);
+          bspline_weights<P>(v1 - g1, T1, nullptr);
+          bspline_weights<P>(v2 - g2, T2, nullptr);
+          const int d = wrap_index((int)g0 - px, K0);
+          double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            t0 = j == d ? T0[j] : t0;
+            t1 = j == j1 ? T1[j] : t1;
+          }
+          const int r1 = wrap_index((int)g1 - j1, K1) * K2;
+          const double w01 = qa * t0 * t1;
+#pragma unroll
+          for (int j2 = 0; j2 < P; ++j2) atomicAdd(&pr[r1 + wrap_index((int)g2 - j2, K2)], w01 * T2[j2]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double *o = part + ((size_t)pp * K0 + px) * K1 * K2;
+  for (int e = threadIdx.x; e < K1 * K2; e += blockDim.x) o[e] = pr[e];
+}
+
+// plane x: the sum of its partial planes, then the z and y transforms (DIF)
+__global__ __launch_bounds__(512) void k_pme_yz_fwd(MDView V, const double *__restrict__ part, int nparts) {
+  extern __shared__ double2 pcx[];
+  const int px = blockIdx.x, K1 = V.pk[1], K2 = V.pk[2];
+  const size_t np = (size_t)K1 * K2, stride = (size_t)V.pk[0] * np;
+  const double *pin = part + (size_t)px * np;
+  for (int e = threadIdx.x; e < K1 * K2; e += blockDim.x) {
+    double q = 0.0;
+    for (int k = 0; k < nparts; ++k) q += pin[k * stride + e];
+    pcx[plane_at(e / K2, e % K2, K2)] = make_double2(q, 0.0);
+  }
+  __syncthreads();
+  lds_fft_lines<true>(pcx, K1, K2, V.ptw, V.ptw_n, [K2](int l, int k) { return plane_at(l, k, K2); });
+  lds_fft_lines<true>(pcx, K2, K1, V.ptw, V.ptw_n, [K2](int l, int k) { return plane_at(k, l, K2); });
+  double2 *g = V.pgrid + (size_t)px * np;
+  for (int e = threadIdx.x; e < K1 * K2; e += blockDim.x) g[e] = pcx[plane_at(e / K2, e % K2, K2)];
+}
+
+// x lines (lpb per block, adjacent in memory): the x transform (DIF), then
+// G conj(F) with G from the influence table in the same bit-reversed layout
+// (e: the energy terms G |F|^2 instead, and done), then the x part of the
+// second transform (DIT), back in natural x order.
+__global__ __launch_bounds__(256) void k_pme_xline(MDView V, int lpb, double *__restrict__ e) {
+  extern __shared__ double2 xbuf[];
+  const int K0 = V.pk[0], nyz = V.pk[1] * V.pk[2];
+  const int l0 = blockIdx.x * lpb, pitch = K0 + 1;   // one element of padding per line
+  for (int t = threadIdx.x; t < lpb * K0; t += blockDim.x) {
+    const int l = t % lpb, x = t / lpb;
+    xbuf[l * pitch + x] = V.pgrid[(size_t)x * nyz + l0 + l];
+  }
+  __syncthreads();
+  lds_fft_lines<true>(xbuf, lpb, K0, V.ptw, V.ptw_n, [pitch](int l, int k) { return l * pitch + k; });
+  for (int t = threadIdx.x; t < lpb * K0; t += blockDim.x) {
+    const int l = t % lpb, x = t / lpb;
+    const size_t m = (size_t)x * nyz + l0 + l;
+    const double G = V.pinf[m];
+    const double2 F = xbuf[l * pitch + x];
+    if (e) e[m] = G * (F.x * F.x + F.y * F.y);
+    else xbuf[l * pitch + x] = make_double2(G * F.x, -G * F.y);
+  }
+  if (e) return;
+  __syncthreads();
+  lds_fft_lines<false>(xbuf, lpb, K0, V.ptw, V.ptw_n, [pitch](int l, int k) { return l * pitch + k; });
+  for (int t = threadIdx.x; t < lpb * K0; t += blockDim.x) {
+    const int l = t % lpb, x = t / lpb;
+    V.pgrid[(size_t)x * nyz + l0 + l] = xbuf[l * pitch + x];
+  }
+}
+
+// the y and z part of the second transform, plane by plane: bit-reversed (y, z)
+// in, natural order out
+__global__ __launch_bounds__(512) void k_pme_yz_back(MDView V) {
+  extern __shared__ double2 pcy[];
+  const int K1 = V.pk[1], K2 = V.pk[2];
+  double2 *g = V.pgrid + (size_t)blockIdx.x * K1 * K2;
+  for (int e = threadIdx.x; e < K1 * K2; e += blockDim.x) pcy[plane_at(e / K2, e % K2, K2)] = g[e];
+  __syncthreads();
+  lds_fft_lines<false>(pcy, K1, K2, V.ptw, V.ptw_n, [K2](int l, int k) { return plane_at(l, k, K2); });
+  lds_fft_lines<false>(pcy, K2, K1, V.ptw, V.ptw_n, [K2](int l, int k) { return plane_at(k, l, K2); });
+  for (int e = threadIdx.x; e < K1 * K2; e += blockDim.x) g[e] = pcy[plane_at(e / K2, e % K2, K2)];
 }
 
 // grid <- G(m) conj(F(m)); e (if given) receives G(m) |F(m)|^2, the energy terms
@@ -1505,9 +1738,35 @@ static hipError_t pme_to_influence(const MDView &V, const double4 *X, double *e,
   return hipGetLastError();
 }
 
-hipError_t launch_pme_forces(const MDView &V, const double4 *X, hipStream_t s) {
-  CHK(pme_to_influence(V, X, nullptr, s));
-  CHK(launch_fft3(V, s));
+// fused path: spreading with the y, z transforms; the x line kernel (e:
+// energy terms only, and stop)
+static hipError_t pme_fused_forward(const MDView &V, const double4 *X, double *part, double *e, hipStream_t s) {
+  if (!part) return hipErrorInvalidValue;
+  const size_t plane = sizeof(double) * V.pk[1] * V.pk[2];
+  const dim3 gp(V.pk[0], MD_PME_PARTS);
+  switch (V.porder) {
+    case 4: hipLaunchKernelGGL(k_pme_spread_part<4>, gp, dim3(256), plane, s, V, X, part); break;
+    case 6: hipLaunchKernelGGL(k_pme_spread_part<6>, gp, dim3(256), plane, s, V, X, part); break;
+    default: hipLaunchKernelGGL(k_pme_spread_part<8>, gp, dim3(256), plane, s, V, X, part); break;
+  }
+  CHK(hipGetLastError());
+  hipLaunchKernelGGL(k_pme_yz_fwd, dim3(V.pk[0]), dim3(512), 2 * plane, s, V, part, MD_PME_PARTS);
+  CHK(hipGetLastError());
+  const int lpb = V.pk[0] >= 256 ? 8 : 16;   // K1 K2 >= 64 lines, a multiple of lpb
+  hipLaunchKernelGGL(k_pme_xline, dim3(V.pk[1] * V.pk[2] / lpb), dim3(256), sizeof(double2) * lpb * (V.pk[0] + 1), s,
+                     V, lpb, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_pme_forces(const MDView &V, const double4 *X, double *part, hipStream_t s) {
+  if (pme_fused(V.pk)) {
+    CHK(pme_fused_forward(V, X, part, nullptr, s));
+    hipLaunchKernelGGL(k_pme_yz_back, dim3(V.pk[0]), dim3(512), sizeof(double2) * V.pk[1] * V.pk[2], s, V);
+    CHK(hipGetLastError());
+  } else {
+    CHK(pme_to_influence(V, X, nullptr, s));
+    CHK(launch_fft3(V, s));
+  }
   const dim3 ga((8 * V.n + 255) / 256);   // 8 lanes per atom
   switch (V.porder) {
     case 4: hipLaunchKernelGGL(k_pme_gather<4>, ga, dim3(256), 0, s, V, X); break;
@@ -1518,9 +1777,10 @@ hipError_t launch_pme_forces(const MDView &V, const double4 *X, hipStream_t s) {
 }
 
 // energy terms: e[0, NG) = G |F|^2 per grid point, e[NG + i] = atom i's half of its excluded-pair correction
-hipError_t launch_pme_energy(const MDView &V, const double4 *X, double *e, hipStream_t s) {
+hipError_t launch_pme_energy(const MDView &V, const double4 *X, double *part, double *e, hipStream_t s) {
   const int ng = V.pk[0] * V.pk[1] * V.pk[2];
-  CHK(pme_to_influence(V, X, e, s));
+  if (pme_fused(V.pk)) CHK(pme_fused_forward(V, X, part, e, s));
+  else CHK(pme_to_influence(V, X, e, s));
   hipLaunchKernelGGL(k_excl_energy, dim3((V.n + 255) / 256), dim3(256), 0, s, V, X, e + ng);
   return hipGetLastError();
 }

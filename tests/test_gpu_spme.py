@@ -1,6 +1,8 @@
 """Smooth particle-mesh Ewald on the GPU (spreading, transforms, influence
 function, gather) against the oracle's plain SPME: reciprocal-space forces
-within 1e-12 for every B-spline order and a non-cubic grid, energies within
+within 1e-12 for every B-spline order and a non-cubic grid (the four-launch
+path), and for meshes with large (y, z) planes (the other two spreading
+paths), energies within
 1e-9, JUMP-RESPA1 and plain JUMP runs with identical jump events and FP64
 state within 1e-9, and the 4096-water box at the paper's 12 000-atom
 settings (alpha 0.554, 64^3 grid). Spreading sums with atomics, so two GPU
@@ -38,6 +40,20 @@ def test_spme_forces(jm, order):
     fo = o.accel(F_RECIP)
     assert np.abs(fo).max() > 0.0
     assert rel_err(g.accel(4), fo) < 1e-12
+
+
+@pytest.mark.parametrize("grid", [(8, 64, 128), (8, 128, 128), (256, 8, 16)])
+def test_spme_forces_other_paths(jm, grid):
+    """Meshes whose (y, z) plane does not fit LDS as complex FP64: spreading by
+    real planes in LDS (K1 K2 = 8192), and by global atomics (16384), each with
+    the six axis passes; and a 256-point first axis on the four-launch path
+    (8 x lines per block). Forces and energy against the oracle."""
+    from oracle.oracle import OracleSim, F_RECIP
+    sy, sp = _spme_water(seed=36, grid=grid, order=4)
+    g, o = jm.Sim(sy, sp, S.water_params(jumps=False)), OracleSim(sy, sp, S.water_params(jumps=False))
+    assert rel_err(g.accel(4), o.accel(F_RECIP)) < 1e-12
+    eg, eo = g.observables(pe=True)["pe_recip"], o.energies()["pe_recip"]
+    assert abs(eg - eo) <= TOL * abs(eo), (eg, eo)
 
 
 def test_spme_energy(jm):
