@@ -97,6 +97,13 @@ __device__ __forceinline__ double long_grad(const MDView &V, double4 xi, double4
   return long_grad_d(V, xi, xj, a, b, coul, L, iL, img, e, Fx, Fy, Fz);
 }
 
+// uniform in (0, 1) in the chain's real type: in FP64 (w + 1/2) 2^-32 (u01),
+// in the mixed path (w >> 9 + 1/2) 2^-23 from the top 23 bits, exact in float
+__device__ __forceinline__ double u01r(uint32_t w, double) { return u01(w); }
+__device__ __forceinline__ float u01r(uint32_t w, float) {
+  return ((float)(w >> 9) + 0.5f) * 1.1920928955078125e-07f;
+}
+
 // Theta in the chain's real type (float in the mixed path)
 __device__ __forceinline__ double theta_r(double eta) { return theta_fn(eta); }
 __device__ __forceinline__ float theta_r(float eta) { return theta_fn_f(eta); }
@@ -503,19 +510,19 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         int pb, pf, sb, sf;
         T.template pick2<seg_el_in_lds(G)>(V, u01(uw.w[2]), adaptive, pb, ellb, sb, pf, ellf, sf);
         const int eb = row[pb], ef = row[pf];
-        ring[RF_E * M + sl] = (R)(-log(u01(uw.w[0])));
+        ring[RF_E * M + sl] = -log(u01r(uw.w[0], R(0)));
         pwords[sl] = make_uint2(uw.w[1], uw.w[3]);
         ring[RF_BL * M + sl] = (R)ellb;
         if (adaptive) ring[RF_FL * M + sl] = (R)ellf;
         // the first Z iteration's uniforms, while the row entries are in flight
         if (mrz) {
           const u32x4 zw = draw4w(V.seed, rep, op.rstep, li, (uint64_t)(uint32_t)op.rphase | (1ull << 24), k);
-          const R zu2 = (R)u01(zw.w[2]);
+          const R zu2 = u01r(zw.w[2], R(0));
           if (kZPre) {
-            const ZPre<R> zp = z_pre<R>((R)u01(zw.w[0]), (R)u01(zw.w[1]), zu2);
+            const ZPre<R> zp = z_pre<R>(u01r(zw.w[0], R(0)), u01r(zw.w[1], R(0)), zu2);
             ring[RF_ZL0 * M + sl] = zp.l0; ring[RF_ZL1 * M + sl] = zp.l1; ring[RF_ZCP * M + sl] = zp.cp;
           } else {
-            ring[RF_ZL0 * M + sl] = (R)u01(zw.w[0]); ring[RF_ZL1 * M + sl] = (R)u01(zw.w[1]);
+            ring[RF_ZL0 * M + sl] = u01r(zw.w[0], R(0)); ring[RF_ZL1 * M + sl] = u01r(zw.w[1], R(0));
           }
           ring[RF_ZU2 * M + sl] = zu2;
           zwords[sl] = make_uint2(zw.w[0], zw.w[3]);
@@ -546,12 +553,12 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
       if (m == r) s = tot;
     }
     const uint2 pw = pwords[sl];
-    const bool use_f = adaptive && !((R)u01(pw.x) * Lam < Wb);
+    const bool use_f = adaptive && !(u01r(pw.x, R(0)) * Lam < Wb);
     const int fo = use_f ? (RF_FX - RF_BX) * M : 0;
     const R Fx = ring[fo + RF_BX * M + sl], Fy = ring[fo + RF_BY * M + sl], Fz = ring[fo + RF_BZ * M + sl];
     const R ell = ring[fo + RF_BL * M + sl];
     const R F2 = norm2_nc(Fx, Fy, Fz);
-    const R u3 = (R)u01(pw.y);
+    const R u3 = u01r(pw.y, R(0));
     // acceptance u3 <= lam / c and bound violation lam > c, tested without dividing
     bool out, acc = false, viol = false;
     R eta = R(0), tk = R(0);   // eta: MRZ argument of Theta, or v.F with BPS
@@ -606,7 +613,7 @@ __device__ void chain_op(const MDView &V, const double4 *__restrict__ X, int i, 
         const uint2 zz = zwords[sl];
         const ZPre<R> zp = kZPre ? ZPre<R>{ring[RF_ZL0 * M + sl], ring[RF_ZL1 * M + sl], ring[RF_ZCP * M + sl]}
                                  : z_pre<R>(ring[RF_ZL0 * M + sl], ring[RF_ZL1 * M + sl], ring[RF_ZU2 * M + sl]);
-        zok = z_accept<R>(eta, zp, (R)u01(zz.x), ring[RF_ZU2 * M + sl], (R)u01(zz.y), zown);
+        zok = z_accept<R>(eta, zp, u01r(zz.x, R(0)), ring[RF_ZU2 * M + sl], u01r(zz.y, R(0)), zown);
       }
     } else {
       out = s * iLam > h;
