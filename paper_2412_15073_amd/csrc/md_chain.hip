@@ -20,6 +20,19 @@ __device__ __forceinline__ double seg_ell(const MDView &V, int a, int sg, int co
   return coul == 1 ? cu : V.ell_lj[idx] + cu;
 }
 
+// Damped shifted-force Coulomb in float for the jump gradients of the mixed
+// path, with erfc(x) from the rational approximation of Abramowitz and Stegun
+// (Handbook of Mathematical Functions, 1964, eq. 7.1.26; absolute error below
+// 1.5e-7 for x >= 0), which reuses the Gaussian factor the force needs anyway.
+__device__ __forceinline__ void dsf_pair_fa(float r, float ir, float kqq, const MDView &V, float &U, float &dU) {
+  const float x = (float)V.alpha * r;
+  const float g = __expf(-x * x);
+  const float t = 1.0f / (1.0f + 0.3275911f * x);
+  const float e = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f)))) * g;
+  U = kqq * (e * ir - (float)V.dsf_erfc_rc_over_rc + (float)V.dsf_fc * (r - (float)V.rc));
+  dU = kqq * (-(e * ir * ir + (float)V.two_a_sqpi * g * ir) + (float)V.dsf_fc);
+}
+
 // long-range gradient in FP32 (mixed-precision path) for the candidate image
 // of row entry e: displacement in FP64,
 // pair arithmetic in float, gradient returned in FP64
@@ -43,7 +56,7 @@ __device__ __forceinline__ double long_grad_f(const MDView &V, double4 xi, doubl
       const float qq = (float)(xi.w * xj.w);
       if (qq != 0.0f) {
         float Uc, dUc;
-        dsf_pair_f(r, ir, (float)V.ke * qq, V, Uc, dUc);
+        dsf_pair_fa(r, ir, (float)V.ke * qq, V, Uc, dUc);
         U += Uc; dU += dUc;
       }
     }
@@ -106,7 +119,17 @@ __device__ __forceinline__ float u01r(uint32_t w, float) {
 
 // Theta in the chain's real type (float in the mixed path)
 __device__ __forceinline__ double theta_r(double eta) { return theta_fn(eta); }
-__device__ __forceinline__ float theta_r(float eta) { return theta_fn_f(eta); }
+// mixed path: Theta(eta) = eta Phi(eta) + phi(eta) with Phi from the same
+// erfc approximation (eq. 7.1.26) and the Gaussian factor shared with phi;
+// absolute error below 1e-7 (1 + |eta|)
+__device__ __forceinline__ float theta_r(float eta) {
+  const float x = fabsf(eta) * 0.70710678f;
+  const float g = __expf(-x * x);
+  const float t = 1.0f / (1.0f + 0.3275911f * x);
+  const float ec = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f)))) * g;
+  const float Phi = eta >= 0.0f ? 1.0f - 0.5f * ec : 0.5f * ec;
+  return eta * Phi + 0.39894228f * g;
+}
 
 // per-atom statistics of one launch: counts since its start (added to the
 // stored totals at its end) and the running event fingerprint
