@@ -95,8 +95,8 @@ BYTES_PER_ROW_ENTRY = 4
 # chain kernel's sources (md_chain.hip, then md_device.h) starts with the
 # given prefix. The line reports it times the proposals of its own launches.
 CHAIN_TRAFFIC = {
-    "ensemble": {"sha256": "a60c935dee456c89", "bytes_per_proposal": 242.5},
-    "water4096": {"sha256": "a60c935dee456c89", "bytes_per_proposal": 47.0},
+    "ensemble": {"sha256": "284d8ca1b862a64f", "bytes_per_proposal": 241.9},
+    "water4096": {"sha256": "284d8ca1b862a64f", "bytes_per_proposal": 46.9},
 }
 KERNELS = {0: "k_local (B/A/O updates)", 1: "k_force (pairs, with bonded when fused)", 2: "k_bonded (separate)",
            3: "row rebuild", 4: "k_chain (J/C jump chains)", 5: "reciprocal space (particle-mesh Ewald)"}
