@@ -552,12 +552,27 @@ __device__ __forceinline__ void bonded_atom(const MDView &V, const double4 *__re
 // separate instantiation: the bonded path's registers would cost the plain
 // pair kernel occupancy).
 // FP32 pair arithmetic with FP64 accumulation (mixed-precision path)
+// types whose LJ table the FP32 pair kernel keeps in LDS (more types read it from memory)
+#define MD_FORCE_LDS_TYPES 8
 template <int MODE, int SG, bool BONDED>
 __global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__restrict__ X, int nb_pair) {
   if (BONDED && (int)blockIdx.x >= nb_pair) {
     const int ib = ((int)blockIdx.x - nb_pair) * (int)blockDim.x + (int)threadIdx.x;
     if (ib < V.n) bonded_atom(V, X, ib);
     return;
+  }
+  // LJ coefficients of every type pair in LDS (up to MD_FORCE_LDS_TYPES types), so that a
+  // pair's coefficients follow its partner's type without another global load
+  __shared__ float s_lj[3 * MD_FORCE_LDS_TYPES * MD_FORCE_LDS_TYPES];
+  const int nt = V.nt;
+  const bool tab = nt <= MD_FORCE_LDS_TYPES;
+  if (tab) {
+    for (int t = threadIdx.x; t < nt * nt; t += blockDim.x) {
+      s_lj[3 * t] = (float)V.c12[t];
+      s_lj[3 * t + 1] = (float)V.c6[t];
+      s_lj[3 * t + 2] = (float)V.ljshift[t];
+    }
+    __syncthreads();
   }
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid / SG, lane = gid % SG;
@@ -573,9 +588,23 @@ __global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__rest
     const float cut = (float)(MODE == 0 ? V.rs : V.rc);
     const float cut2 = cut * cut;
     const float kq = (float)(V.ke * xi.w);
+    // software pipeline: the next row entry, its partner's position and type are loaded
+    // while the current pair is evaluated
+    int e = 0, tj = 0;
+    double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (lane < cnt) {
+      e = row[lane];
+      xj = X[row_j(e)];
+      tj = V.type[row_j(e)];
+    }
     for (int k = lane; k < cnt; k += SG) {
-      const int e = row[k], j = row_j(e);
-      const double4 xj = X[j];
+      int en = 0, tjn = 0;
+      double4 xjn = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (k + SG < cnt) {
+        en = row[k + SG];
+        xjn = X[row_j(en)];
+        tjn = V.type[row_j(en)];
+      }
       double ddx, ddy, ddz;
       row_disp(xi, xj, L, iL, img, e, ddx, ddy, ddz);
       const float dx = (float)ddx, dy = (float)ddy, dz = (float)ddz;
@@ -583,10 +612,12 @@ __global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__rest
       if (r2 < cut2) {
         const float rr = sqrtf(r2);
         const float ir = 1.0f / rr;
-        const int ab = a * V.nt + V.type[j];
+        const int ab = a * nt + tj;
         float U = 0.0f, dU = 0.0f;
-        const float c12 = (float)V.c12[ab], c6 = (float)V.c6[ab];
-        if (c12 != 0.0f || c6 != 0.0f) lj_pair_f(ir, c12, c6, (float)V.ljshift[ab], U, dU);
+        const float c12 = tab ? s_lj[3 * ab] : (float)V.c12[ab];
+        const float c6 = tab ? s_lj[3 * ab + 1] : (float)V.c6[ab];
+        if (c12 != 0.0f || c6 != 0.0f)
+          lj_pair_f(ir, c12, c6, tab ? s_lj[3 * ab + 2] : (float)V.ljshift[ab], U, dU);
         const float kqq = kq * (float)xj.w;
         if (kqq != 0.0f) {
           float Uc, dUc;
@@ -606,6 +637,7 @@ __global__ __launch_bounds__(256) void k_force_f(MDView V, const double4 *__rest
         const float sc = -g * ir;
         fx += (double)(sc * dx); fy += (double)(sc * dy); fz += (double)(sc * dz);
       }
+      e = en; xj = xjn; tj = tjn;
     }
   }
 #pragma unroll
