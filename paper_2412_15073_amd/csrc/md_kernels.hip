@@ -656,6 +656,18 @@ __global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restri
     if (ib < V.n) bonded_atom(V, X, ib);
     return;
   }
+  // LJ coefficients of every type pair in LDS (up to MD_FORCE_LDS_TYPES types)
+  __shared__ double s_lj[3 * MD_FORCE_LDS_TYPES * MD_FORCE_LDS_TYPES];
+  const int nt = V.nt;
+  const bool tab = nt <= MD_FORCE_LDS_TYPES;
+  if (tab) {
+    for (int t = threadIdx.x; t < nt * nt; t += blockDim.x) {
+      s_lj[3 * t] = V.c12[t];
+      s_lj[3 * t + 1] = V.c6[t];
+      s_lj[3 * t + 2] = V.ljshift[t];
+    }
+    __syncthreads();
+  }
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = gid / SG, lane = gid % SG;
   double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -669,19 +681,18 @@ __global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restri
     const int cnt = MODE == 0 ? V.scnt[i] : V.fcnt[i];
     const double cut = MODE == 0 ? V.rs : V.rc;
     const double cut2 = cut * cut;
-    for (int k = lane; k < cnt; k += SG) {
-      const int e = row[k], j = row_j(e);
-      const double4 xj = X[j];
+    // pair term of row entry e (partner j at xj, of type tj, or read here when tj < 0)
+    auto pair = [&](int e, int j, const double4 &xj, int tj) {
       double dx, dy, dz;
       row_disp(xi, xj, L, iL, img, e, dx, dy, dz);
       double r2 = dx * dx + dy * dy + dz * dz;
       if (r2 < cut2) {
         double rr = sqrt(r2);
         const double ir = 1.0 / rr;
-        int ab = a * V.nt + V.type[j];
+        const int ab = a * nt + (tj >= 0 ? tj : V.type[j]);
         double U = 0.0, dU = 0.0;
-        double c12 = V.c12[ab], c6 = V.c6[ab];
-        if (c12 != 0.0 || c6 != 0.0) lj_pair(ir, c12, c6, V.ljshift[ab], U, dU);
+        const double c12 = tab ? s_lj[3 * ab] : V.c12[ab], c6 = tab ? s_lj[3 * ab + 1] : V.c6[ab];
+        if (c12 != 0.0 || c6 != 0.0) lj_pair(ir, c12, c6, tab ? s_lj[3 * ab + 2] : V.ljshift[ab], U, dU);
         double qq = xi.w * xj.w;
         if (qq != 0.0) {
           double Uc, dUc;
@@ -698,8 +709,36 @@ __global__ __launch_bounds__(256) void k_force(MDView V, const double4 *__restri
           switch_fn(rr, V, chi, dchi);
           g = (1.0 - chi) * dU - dchi * U;
         }
-        double s = -g * ir;
-        fx += s * dx; fy += s * dy; fz += s * dz;
+        double sc = -g * ir;
+        fx += sc * dx; fy += sc * dy; fz += sc * dz;
+      }
+    };
+    if (MODE == 0) {
+      // short rows: the next row entry, its partner's position and type are loaded while
+      // the current pair is evaluated (the full-range sweeps are bound by their arithmetic
+      // and keep the plain loop, which measured faster there)
+      int e = 0, tj = 0;
+      double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (lane < cnt) {
+        e = row[lane];
+        xj = X[row_j(e)];
+        tj = V.type[row_j(e)];
+      }
+      for (int k = lane; k < cnt; k += SG) {
+        int en = 0, tjn = 0;
+        double4 xjn = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (k + SG < cnt) {
+          en = row[k + SG];
+          xjn = X[row_j(en)];
+          tjn = V.type[row_j(en)];
+        }
+        pair(e, row_j(e), xj, tj);
+        e = en; xj = xjn; tj = tjn;
+      }
+    } else {
+      for (int k = lane; k < cnt; k += SG) {
+        const int e = row[k], j = row_j(e);
+        pair(e, j, X[j], -1);
       }
     }
   }
