@@ -363,14 +363,25 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
   const float yiw = (float)(xi.y - L[1] * floor(xi.y / L[1]));
   const float ziw = (float)(xi.z - L[2] * floor(xi.z / L[2]));
   int nq = 0;
+  // the next chunk's cell index and position are loaded while this chunk is tested
+  int qn = 0;
+  float4 xn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (lane < total) {
+    while (s_pre[span + 1] <= lane) ++span;
+    qn = s_beg[span] + (lane - s_pre[span]);
+    xn = V.xcellf[qn];
+  }
   for (int base = 0; base < total; base += 64) {
     const int f = base + lane;
+    const int q = qn;
+    const float4 xj = xn;
+    if (f + 64 < total) {
+      while (s_pre[span + 1] <= f + 64) ++span;
+      qn = s_beg[span] + (f + 64 - s_pre[span]);
+      xn = V.xcellf[qn];
+    }
     bool keep = false;
-    int q = 0;
     if (f < total) {
-      while (s_pre[span + 1] <= f) ++span;
-      q = s_beg[span] + (f - s_pre[span]);
-      const float4 xj = V.xcellf[q];
       float dx = xiw - xj.x, dy = yiw - xj.y, dz = ziw - xj.z;
       const float rc_m = rcf + margin0 + 1e-6f * (fabsf(dx) + fabsf(dy) + fabsf(dz));
       dx -= Lf[0] * rintf(dx * iLf[0]);
@@ -396,16 +407,25 @@ __global__ __launch_bounds__(64) void k_build(MDView V, const double4 *__restric
   // the offset s from the nearest image orders the images of one j.
   // Otherwise keys are segment << 24 | j (candidates) or j.
   const int rep0 = V.rep_off[r];
+  // the next chunk's atom and position are loaded while this chunk is tested; keys
+  // overwrite only queue slots of chunks already read
+  int jn = -1;
+  double4 xjn = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (lane < nqq) {
+    const int q = (int)kq[lane];
+    jn = V.cell_atoms[q];
+    xjn = V.xcell[q];
+  }
   for (int base = 0; base < nqq; base += 64) {
-    int j = -1;
-    double4 xj = make_double4(0.0, 0.0, 0.0, 0.0);
+    int j = jn;
+    double4 xj = xjn;
     bool ok = base + lane < nqq;
-    if (ok) {
-      const int q = (int)kq[base + lane];
-      j = V.cell_atoms[q];
-      xj = V.xcell[q];
+    if (base + 64 + lane < nqq) {
+      const int q = (int)kq[base + 64 + lane];
+      jn = V.cell_atoms[q];
+      xjn = V.xcell[q];
     }
-    wave_lds_sync();   // every queue slot of this chunk is read before keys overwrite it
+    wave_lds_sync();   // the queue slots of this chunk and the next are read before keys overwrite them
     ok = ok && j != i && j != ex[0] && j != ex[1] && j != ex[2] && j != ex[3];
     if (ok && ex_more)
       for (int e = x0 + 4; ok && e < x1; ++e) ok = (V.xj[e] != j);
