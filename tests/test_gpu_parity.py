@@ -51,6 +51,38 @@ def test_forces_lj(jm):
     assert rel_err(g.accel(1), o.accel(F_FULL)) < 1e-12
 
 
+@pytest.mark.parametrize("n_types", [8, 10])
+def test_forces_lj_mixture_many_types(jm, n_types):
+    """A charged LJ mixture of n_types types: up to 8 the pair kernels read
+    the LJ table from LDS, above it from memory. Short, full and long
+    real-space forces (Ewald electrostatics, so that the long part has a
+    kernel of its own) against the oracle, in FP64 and (short forces)
+    FP32-mixed."""
+    from oracle.oracle import F_SHORT, F_FULL, F_LONG
+    sy = S.lj_fcc(4, seed=41, jitter=0.05)
+    rng = np.random.default_rng(42)
+    sy.n_types = n_types
+    sy.type = (np.arange(sy.n_atoms) % n_types).astype(np.int32)
+    e = rng.uniform(0.5, 1.5, n_types)
+    sg = rng.uniform(0.9, 1.1, n_types)
+    sy.lj_eps = np.sqrt(np.outer(e, e)).ravel()
+    sy.lj_sigma = (0.5 * (sg[:, None] + sg[None, :])).ravel()
+    q = rng.uniform(-0.3, 0.3, sy.n_atoms)
+    sy.charge = q - q.mean()
+    sy.coulomb_k = 1.0
+    sp = S.Split(r_s=2.0, r_c=3.0, switch_width=0.5, skin=0.3, coulomb_alpha=1.0)
+    sp.coulomb_kind, sp.ewald_kmax = S.COUL_EWALD, 6
+    g, o = _pair(jm, sy, sp, S.lj_params())
+    assert np.abs(o.accel(F_SHORT)).max() > 0.0
+    assert rel_err(g.accel(0), o.accel(F_SHORT)) < 1e-12
+    assert rel_err(g.accel(1), o.accel(F_FULL)) < 1e-12
+    assert rel_err(g.accel(3), o.accel(F_LONG)) < 1e-12
+    pa = S.lj_params()
+    pa.precision = S.FP32_MIXED
+    g32 = jm.Sim(sy, sp, pa)
+    assert rel_err(g32.accel(0), o.accel(F_SHORT)) < 2e-5
+
+
 def test_forces_water(jm):
     sy, sp = water_small()
     g, o = _pair(jm, sy, sp, S.water_params())
