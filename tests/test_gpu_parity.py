@@ -482,6 +482,38 @@ def test_jump_call_grouping_and_graph_chunks_change_nothing(jm):
     np.testing.assert_array_equal(g2.events(), o.events())
 
 
+@pytest.mark.parametrize("scheme", ["baoab", "jump", "jump_respa", "baoab_respa"])
+def test_zero_step_calls_change_nothing(jm, scheme):
+    """A call of zero steps leaves positions, velocities, counters, events and
+    the step count as they were (in the middle of a run, between the closing
+    and the next opening half step), and the run then continues exactly as
+    one without it; a negative count is refused."""
+    sy, sp = water_small()
+    pa = S.water_params(jumps=scheme.startswith("jump"))
+    pa.log_events = 1
+    pa.respa_inner = 2
+    step = lambda g, n: getattr(g, "step_" + scheme)(n)
+    g, ref = jm.Sim(sy, sp, pa), jm.Sim(sy, sp, pa)
+    step(g, 2)
+    before = g.state(), g.atom_stats(), g.events(), g.observables()["step"]
+    step(g, 0)
+    after = g.state(), g.atom_stats(), g.events(), g.observables()["step"]
+    for a, b in zip(before[0], after[0]):
+        assert np.array_equal(a, b)
+    for k in ("n_prop", "n_acc", "n_viol", "hash"):
+        np.testing.assert_array_equal(before[1][k], after[1][k])
+    np.testing.assert_array_equal(before[2], after[2])
+    assert before[3] == after[3]
+    step(g, 2)
+    step(ref, 4)
+    for a, b in zip(g.state(), ref.state()):
+        assert np.array_equal(a, b)
+    np.testing.assert_array_equal(g.events(), ref.events())
+    with pytest.raises(jm.MDError) as e:
+        step(g, -1)
+    assert e.value.code == jm.MD_ERR_ARG
+
+
 @pytest.mark.parametrize("precision_scheme", ["jump", "baoab"])
 def test_water_4096_full_size_in_bench_configuration(jm, precision_scheme):
     """The benchmark's 4096-molecule water box at full size, in the launch
